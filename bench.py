@@ -1,0 +1,201 @@
+#!/usr/bin/env python3
+"""Throughput of the TT grid-based filter on one MI355X.
+
+A step is one full recursion step (predict by per-core convolution, round,
+normalise, likelihood + Hadamard update with c_k, round, normalise + moments)
+for every filter of the batch.  The workload is d=6, N=128 points per axis on
+[-20,20]^6, rank cap 16, 256 independent filters (range on (x1,x2) plus
+linear x3..x6, tridiagonal-correlated random walk), synthetic seeded inputs.
+
+Prints ONE JSON line.  `value` = filter steps per second of the FP32-bulk
+batch (inputs resident in HBM).  Also reported: the plain FP64 single-filter
+comparator, per-kernel-class times from HIP events, the roofline figure of
+the dominant kernel and the CPU oracle on a bounded sample.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "TT-GBF filter steps/s (d=6,N=128,rank≤16) FP32 batch vs FP64 plain; grad ms/step"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def conv_bytes(ranks_prev, kranks, n, esz):
+    """Algorithmic HBM bytes of one convolution launch for one filter:
+    write the product cores, read the PMD and kernel cores once."""
+    d = len(n)
+    kr = kranks
+    w = sum(kr[k] * ranks_prev[k] * n[k] * kr[k + 1] * ranks_prev[k + 1] for k in range(d))
+    rp = sum(ranks_prev[k] * n[k] * ranks_prev[k + 1] for k in range(d))
+    return (w + rp) * esz
+
+
+def run_batch(B, runner, binding, wl, name, batch, steps, warmup, precision, profile_steps=0, seed=None):
+    import torch
+    total = 1 + warmup + steps + profile_steps
+    kw = {} if seed is None else {"seed": seed}
+    specs, xs, zs = wl.make_batch(name, batch=batch, steps=total, **kw)
+    t0 = time.time()
+    kernels, kidx, kr = runner.build_kernels(specs, precision)
+    fspecs = runner.filter_specs(specs, kidx, kr, 64)
+    z, zdim = runner.z_tensor(zs)
+    run = binding.FilterRun(fspecs, kernels, total, zdim, precision)
+    torch.cuda.synchronize()
+    log(f"[bench] {name} B={batch} prec={'f32' if precision == binding.F32 else 'f64'} setup {time.time() - t0:.1f}s "
+        f"kernel ranks {kernels[0].cap}")
+    # warm-up: step 0 (update only) and `warmup` full steps, untimed
+    run(z, k_begin=0, k_count=1 + warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    run(z, k_begin=1 + warmup, k_count=steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    prof = None
+    if profile_steps:
+        binding.profile_begin()
+        run(z, k_begin=1 + warmup + steps, k_count=profile_steps)
+        torch.cuda.synchronize()
+        prof = binding.profile_end()
+    st = run.status.cpu().numpy()
+    log(f"[bench] timed {steps} steps: {ms:.2f} ms, failed filters {int((st != 0).sum())}")
+    return {"run": run, "ms": ms, "prof": prof, "specs": specs, "kernels": kernels, "zs": zs,
+            "status": st, "total": total}
+
+
+def cpu_baseline(wl, steps=2):
+    """The FP64 oracle on a bounded sample: one filter of the same workload,
+    `steps` full steps after step 0, on the host cores."""
+    import numpy as np
+    from oracle import model as mdl
+    from oracle import tt as ttm
+    specs, xs, zs = wl.make_batch("range6d_n128_c16", batch=1, steps=1 + steps)
+    s, z = specs[0], zs[0]
+    axes = mdl.grid_axes(s.lo, s.hi, [s.n] * s.d)
+    hw = s.halfwidths()
+    t0 = time.time()
+    kern = mdl.kernel_tt(s.q, axes, hw, s.kernel_tol)
+    log(f"[bench] oracle kernel TT {ttm.ranks(kern)} in {time.time() - t0:.1f}s")
+    delta = mdl.cell_volume(axes)
+    p = mdl.prior_tt(axes, s.m0, s.p0_diag)
+    lik = mdl.likelihood_tt(axes, z[0], s.meas(), s.lik_tol)
+    p = ttm.tt_round(ttm.hadamard(lik, p), s.eps, s.cap)
+    p = ttm.scale(p, 1.0 / (ttm.tt_sum(p) * delta))
+    t0 = time.time()
+    for k in range(1, 1 + steps):
+        c = ttm.conv(kern, p, hw)
+        p = ttm.tt_round(c, s.eps, s.cap)
+        p = ttm.scale(p, 1.0 / (ttm.tt_sum(p) * delta))
+        lik = mdl.likelihood_tt(axes, z[k], s.meas(), s.lik_tol)
+        h = ttm.hadamard(lik, p)
+        p = ttm.tt_round(h, s.eps, s.cap)
+        p = ttm.scale(p, 1.0 / (ttm.tt_sum(p) * delta))
+        mdl.moments_tt(p, axes)
+    dt = time.time() - t0
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count()
+    thr = os.environ.get("OMP_NUM_THREADS")
+    if thr:
+        cores = min(cores, int(thr))
+    return {"value": steps / dt, "unit": "filter-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"1 filter x {steps} full steps of d=6 N=128 cap16 (FP64 NumPy oracle), {dt:.1f}s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=6)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--workload", default="range6d_n128_c16")
+    ap.add_argument("--no-plain", action="store_true", help="skip the FP64 single-filter comparator")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--profile-steps", type=int, default=2)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+              f"(independent filters shard across GPUs without communication; see DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2501_07942_amd import binding, runner, workload as wl
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(1)
+
+    main_res = run_batch(None, runner, binding, wl, args.workload, args.batch, args.steps, args.warmup,
+                         binding.F32, profile_steps=args.profile_steps)
+    B = args.batch
+    ms = main_res["ms"]
+    value = B * args.steps / (ms / 1000.0)
+
+    # roofline of the dominant kernel class from the profiled window
+    prof = main_res["prof"] or {}
+    kernel_ms = {k: round(v[0] / max(args.profile_steps, 1), 3) for k, v in prof.items()}
+    roof = None
+    if prof and prof["conv"][1] > 0:
+        run = main_res["run"]
+        ranks = run.ranks.cpu().numpy()
+        kr = [k.cap for k in main_res["kernels"]]
+        k0 = 1 + args.warmup + args.steps
+        tot = 0
+        for b in range(B):
+            spec = main_res["specs"][b]
+            n = [spec.n] * spec.d
+            kidx = 0
+            for k in range(k0, k0 + args.profile_steps):
+                tot += conv_bytes(list(ranks[b, k - 1]), kr[kidx], n, 4)
+        conv_ms, conv_n = prof["conv"]
+        avg_ms = conv_ms / conv_n
+        achieved = tot / conv_n / (avg_ms / 1000.0) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "conv_kernel<float>",
+                "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes_per_launch": int(tot / conv_n)}
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "filter-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded random-walk trajectories and range/linear measurements)",
+        "config": {"workload": args.workload, "d": 6, "N": 128, "rank_cap": 16, "filters": B,
+                   "precision": "fp32 bulk, fp64 Gram/pivoted-Cholesky/Jacobi, fp64 log-normaliser",
+                   "failed_filters": int((main_res["status"] != 0).sum())},
+        "roofline": roof,
+        "kernel_ms_per_step": kernel_ms,
+    }
+    if not args.no_plain:
+        plain = run_batch(None, runner, binding, wl, args.workload, 1, 3, 1, binding.F64)
+        out["fp64_plain"] = {"value": round(3 / (plain["ms"] / 1000.0), 3), "unit": "filter-steps/s",
+                             "ms_per_step": round(plain["ms"] / 3, 3), "filters": 1,
+                             "failed_filters": int((plain["status"] != 0).sum())}
+        out["fp32_batch_over_fp64_plain"] = round(value / out["fp64_plain"]["value"], 2)
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

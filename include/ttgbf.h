@@ -1,0 +1,265 @@
+/*
+ * ttgbf.h -- C ABI of the MI355X (gfx950) tensor-train grid-based filter.
+ *
+ * The library implements one Bayesian recursion step of the point-mass
+ * filter with every density held in tensor-train (TT) format:
+ *   prediction  = per-core convolution of the PMD TT with a TT transition
+ *                 kernel (Sec. 2.1 "Tensor Form", eq. tpmconvFFT; Sec. 4.2
+ *                 "FFT Convolution in Tensor Train"),
+ *   update      = Hadamard product with a TT likelihood and the normaliser
+ *                 c_k (Sec. 2.2, eqs. pmf_filtrace_a/b; Sec. 4.1 'times'),
+ *   rounding    = orthogonalisation sweep + truncated-SVD sweep capping the
+ *                 ranks (Sec. 3.2, Sec. 4.1 'round'),
+ *   moments     = full TT contractions (Sec. 4.1 'sum', 'power', 'dot').
+ * The step order is that of Alg. 2 with the convolution prediction of
+ * Alg. 3 (fixed grid, f = identity).
+ *
+ * Conventions shared by every entry point
+ *   - All pointers named *_dev and every pointer inside tt_train point to
+ *     device memory owned by the caller.  The library never allocates device
+ *     memory; scratch comes from the caller's workspace (ws, ws_bytes), whose
+ *     required size the matching *_workspace query returns.  Host pointers
+ *     (descriptors, q, halfwidths) are read during the call only.
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *     Work is enqueued asynchronously; results are valid after the stream
+ *     is synchronised.  Calls are reentrant given distinct workspaces.
+ *   - Return value: TT_OK, or an argument/shape/workspace/HIP error detected
+ *     on the host BEFORE anything is enqueued (TT_ERR_HIP is returned when a
+ *     launch fails; tt_last_error() then holds the message).
+ *   - Numerical failures are reported per TT in its device status word
+ *     (sticky bit flags TT_STATUS_*); a failed filter's later outputs are NaN
+ *     and other filters in a batch are unaffected.
+ */
+#ifndef TTGBF_H
+#define TTGBF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TT_MAXD 16
+
+typedef int32_t tt_status;
+#define TT_OK 0
+#define TT_ERR_ARG 1        /* null pointer, non-positive size, bad enum */
+#define TT_ERR_SHAPE 2      /* inconsistent d, n, capacities */
+#define TT_ERR_WORKSPACE 3  /* workspace smaller than the query returns */
+#define TT_ERR_HIP 4        /* a HIP call failed; see tt_last_error() */
+
+/* Per-TT device status bits (sticky; OR-ed by the kernels). */
+#define TT_STATUS_NONPOSITIVE 1  /* mass or c_k <= 0 */
+#define TT_STATUS_NONFINITE 2    /* NaN/Inf met */
+#define TT_STATUS_CAPACITY 4     /* a rank needed more room than reserved */
+
+typedef enum { TT_F64 = 0, TT_F32 = 1 } tt_dtype;
+
+/* Equidistant grid (Sec. 2 eq. pdf_pm; Sec. 4 grid bullet): axis l holds
+ * n[l] points lo[l] + i*(hi[l]-lo[l])/(n[l]-1), i = 0..n[l]-1. */
+typedef struct {
+  int32_t d;
+  int32_t n[TT_MAXD];
+  double lo[TT_MAXD];
+  double hi[TT_MAXD];
+} tt_grid;
+
+/* One tensor train on the device (Sec. 3.1 eq. ttd_exact):
+ *   A(i_1..i_d) = exp(*log_scale) * G_1(:,i_1,:) ... G_d(:,i_d,:).
+ * Core k is stored at element offset off_k = sum_{j<k} cap[j]*n[j]*cap[j+1]
+ * of `cores` (elements of `dtype`), packed with the CURRENT ranks r = ranks[]
+ * in row-major layout [r_{k-1}][n_k][r_k]; cap[] reserves the room
+ * (cap[0] = cap[d] = 1).  ranks, log_scale and status live on the device and
+ * are updated by the kernels without host synchronisation. */
+typedef struct {
+  int32_t d;
+  int32_t n[TT_MAXD];
+  int32_t cap[TT_MAXD + 1];
+  int32_t dtype;            /* tt_dtype */
+  void* cores;              /* device, tt_train_elems(...) elements */
+  int32_t* ranks;           /* device int32[d+1] */
+  double* log_scale;        /* device double[1] */
+  int32_t* status;          /* device int32[1] */
+} tt_train;
+
+/* Measurement model (Sec. 1 eq. asz with Gaussian v):
+ *   kind 0: z_l = x_l + v_l on every axis, v ~ N(0, sigma_lin^2 I);
+ *   kind 1: z_0 = ||(x_1,x_2) - sensor|| + v_0 (v_0 ~ N(0, sigma_r^2)) and
+ *           z_j = x_{j+1} + v_j for j = 1..d-2 (v_j ~ N(0, sigma_lin^2)).
+ * The likelihood tensor (Sec. 2.2 L^v, Sec. 4 tensor bullet) is held as a
+ * TT: rank one on the linear axes; the (x_1,x_2) block is a dense matrix
+ * truncated by SVD at relative Frobenius tolerance lik_tol (and to at most
+ * lik_max_rank terms when that is > 0). */
+typedef struct {
+  int32_t kind;
+  double sensor[2];
+  double sigma_r;
+  double sigma_lin;
+  double lik_tol;
+  int32_t lik_max_rank;
+} tt_meas;
+
+/* Number of elements a TT with these capacities needs. */
+size_t tt_train_elems(int32_t d, const int32_t* n, const int32_t* cap);
+
+/* Message of the last host-side error in this thread (never NULL). */
+const char* tt_last_error(void);
+
+/* Library version string. */
+const char* tt_version(void);
+
+/* ---------------------------------------------------------------------
+ * tt_kernel_build -- TT transition kernel (Sec. 2.1 eq. TPMmat and the
+ * middle-row tensor of eq. tpmconvFFT; Sec. 3.1 TT decomposition).
+ *   K(m) = N(Delta o m; 0, Q) * delta   for |m_l| <= halfwidths[l],
+ * Delta_l = (hi_l-lo_l)/(n_l-1), delta = prod Delta_l, evaluated densely on
+ * the device in FP64 and decomposed by TT-SVD (sequential truncated SVDs,
+ * per-bond threshold svd_tol*||K||_F/sqrt(d-1)).
+ *   grid        host; d <= 8 and prod(2h_l+1) <= 2^28 (dense build)
+ *   q           host, d*d row-major, symmetric positive definite
+ *   halfwidths  host, d entries h_l >= 0
+ *   out         TT with n[l] = 2*h_l+1 and rank capacities cap[]; dtype
+ *               TT_F64 or TT_F32 (the decomposition is FP64 either way).
+ *               On return (after sync) out->ranks holds the kernel ranks;
+ *               TT_STATUS_CAPACITY is set if a rank exceeded cap.
+ * --------------------------------------------------------------------- */
+size_t tt_kernel_build_workspace(const tt_grid* grid, const int32_t* halfwidths,
+                                 const int32_t* cap);
+tt_status tt_kernel_build(const tt_grid* grid, const double* q, const int32_t* halfwidths,
+                          double svd_tol, const tt_train* out, void* ws, size_t ws_bytes,
+                          void* stream);
+
+/* ---------------------------------------------------------------------
+ * tt_predict -- Chapman-Kolmogorov prediction for x_{k+1} = x_k + w_k as
+ * the linear convolution of the PMD with the kernel, cropped to the grid
+ * (Sec. 2.1 eq. tpmconvFFT; Sec. 4.2: the cores of a TT convolution are the
+ * convolutions of the cores).  For every filter b and core k:
+ *   C_k(a*rp+b', i, a'*rp'+b'') = sum_{m=-h_k}^{h_k} K_k(a, m+h_k, a') P_k(b', i-m, b'')
+ * with P = 0 off the grid and h_k = (kernel n_k - 1)/2.  The product is NOT
+ * rounded: out ranks are r_K * r_P; out->cap must be >= kernel cap * in cap.
+ * log_scale(out) = log_scale(kernel) + log_scale(in).
+ *   batch      number of filters; kernels[b], p_in[b], p_out[b] describe
+ *              filter b (kernels[] entries may describe the same TT).
+ * --------------------------------------------------------------------- */
+size_t tt_predict_workspace(int32_t batch);
+tt_status tt_predict(int32_t batch, const tt_train* kernels, const tt_train* p_in,
+                     const tt_train* p_out, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------
+ * tt_update -- Bayes update (Sec. 2.2 eqs. pmf_filtrace_a/b; Alg. 2 step 2):
+ * builds the likelihood TT for measurement z (FP64, max-shifted, its log
+ * shift added to the log-scale), forms H = L o P_pred as the Kronecker
+ * product of the core slices (Sec. 4.1 'times'; ranks multiply) and
+ *   log_c_dev[b] = log( sum_i L(i) P_pred(i) * delta )
+ * on the unrounded product.  H is not rounded or normalised.
+ *   grids[b], meas[b]  host descriptors per filter
+ *   z_dev              device FP64, filter b's measurement at z_dev + b*z_stride
+ *   h_out              capacity >= (likelihood rank cap) * p_pred cap on bond 1,
+ *                      >= p_pred cap elsewhere; lik_rank_cap bounds r_L.
+ * --------------------------------------------------------------------- */
+size_t tt_update_workspace(int32_t batch, const tt_grid* grids, const tt_meas* meas,
+                           const tt_train* p_pred, const tt_train* h_out, int32_t lik_rank_cap);
+tt_status tt_update(int32_t batch, const tt_grid* grids, const tt_meas* meas,
+                    const double* z_dev, int32_t z_stride, const tt_train* p_pred,
+                    const tt_train* h_out, int32_t lik_rank_cap, double* log_c_dev,
+                    void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------
+ * tt_round -- TT rounding (Sec. 3.2 maximum rank; Sec. 4.1 'round'):
+ * in exact arithmetic the result is that of a right-to-left orthogonalisation
+ * followed by a left-to-right sweep of truncated SVDs keeping at bond k the
+ * smallest r whose discarded tail sqrt(sum_{j>r} s_j^2) <= eps*||A||_F/sqrt(d-1),
+ * then r = min(max(r,1), max_rank).  The orthogonalisation is computed from
+ * Gram matrices accumulated in double-double (FP64 TTs) or FP64 (FP32 TTs)
+ * with pivoted Cholesky factors that drop directions below a relative
+ * pre-truncation threshold (1e-15 for FP64, 1e-7 for FP32 TTs); the small
+ * SVDs are one-sided Jacobi in FP64.  After rounding the last core is scaled
+ * to unit Frobenius norm and its norm moved into log_scale.
+ *   t_in, t_out  may be the same TT (in place); t_out->cap bounds the ranks
+ *                (capacity overflow sets TT_STATUS_CAPACITY).
+ * --------------------------------------------------------------------- */
+size_t tt_round_workspace(int32_t batch, const tt_train* t_in, const tt_train* t_out);
+tt_status tt_round(int32_t batch, const tt_train* t_in, const tt_train* t_out, double eps,
+                   int32_t max_rank, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------
+ * tt_normalize_moments -- mass, normalisation and moments (Sec. 4.1 'sum',
+ * 'mrdivide', 'power', 'dot'; Alg. 2 steps 2-4), for rank capacities <= 64:
+ *   mass = sum_i A(i) * delta,  log_mass_dev[b] = log(mass) (before),
+ *   log_scale -= log(mass)  (A now integrates to one),
+ *   mean_dev[b*d + l]       = sum_i xi_l(i_l) A(i) delta,
+ *   cov_dev[b*d*d + l*d + j] = sum_i xi_l xi_j A(i) delta - mean_l mean_j.
+ * mean_dev and cov_dev may be NULL.  Contractions accumulate in FP64.
+ * --------------------------------------------------------------------- */
+tt_status tt_normalize_moments(int32_t batch, const tt_grid* grids, const tt_train* t,
+                               double* log_mass_dev, double* mean_dev, double* cov_dev,
+                               void* ws, size_t ws_bytes, void* stream);
+size_t tt_normalize_moments_workspace(int32_t batch, const tt_train* t);
+
+/* ---------------------------------------------------------------------
+ * tt_filter_run -- the whole recursion for a batch of independent filters
+ * (Alg. 2 loop order with the convolution prediction; step 0 is an update
+ * only; steps k >= 1 predict, round, normalise, update, round, normalise).
+ * All filters share d; N, rank cap and model may differ per filter (ragged
+ * batch).  Outputs (device, FP64):
+ *   loglik_dev[b]          = sum_k log c_k
+ *   log_c_dev[b*K + k]     = log c_k
+ *   log_mpred_dev[b*K + k] = log predictive mass before normalisation
+ *                            (mass leaving the grid; 0 at k = 0)
+ *   mean_dev[(b*K + k)*d + l], cov_dev[((b*K + k)*d + l)*d + j]  (nullable)
+ *   ranks_dev[(b*K + k)*(d+1) + j]  filtering ranks per step (nullable)
+ *   status_dev[b]          sticky TT_STATUS_* bits
+ * Inputs: z_dev[(b*K + k)*zdim + j] with zdim = max over filters of b
+ * (d for kind 0, d-1 for kind 1); kernels[spec.kernel_index] is the filter's
+ * transition kernel TT (built by tt_kernel_build on the filter's grid).
+ * Steps k_begin .. k_begin+k_count-1 of a K-step horizon are run (outputs
+ * and z are always laid out for K steps).  k_begin = 0 starts from the
+ * prior; k_begin > 0 resumes from the filter state that the previous call
+ * left in the same workspace (same specs, kernels and ws), so a run split
+ * into several calls gives bitwise the same results as one call.
+ * loglik_dev sums log c_k over steps 0 .. k_begin+k_count-1.
+ * precision: TT_F64 (plain FP64 path) or TT_F32 (FP32 bulk cores and
+ * contractions, FP64 Gram/pivoted-Cholesky/Jacobi factorisations and FP64
+ * log-normaliser).  The kernels[] cores must have the same dtype.
+ * --------------------------------------------------------------------- */
+typedef struct {
+  tt_grid grid;
+  tt_meas meas;
+  double m0[TT_MAXD];       /* Gaussian prior mean */
+  double p0_diag[TT_MAXD];  /* Gaussian prior variances (diagonal) */
+  int32_t cap;              /* rank cap of the PMD */
+  double eps;               /* rounding tolerance */
+  int32_t kernel_index;
+  int32_t kernel_cap;       /* largest kernel TT rank reserved for */
+  int32_t lik_rank_cap;     /* largest likelihood rank reserved for */
+} tt_filter_spec;
+
+size_t tt_filter_run_workspace(int32_t batch, const tt_filter_spec* specs, int32_t precision);
+tt_status tt_filter_run(int32_t batch, const tt_filter_spec* specs, const tt_train* kernels,
+                        int32_t n_kernels, const double* z_dev, int32_t zdim, int32_t K,
+                        int32_t k_begin, int32_t k_count, int32_t precision, double* loglik_dev, double* log_c_dev,
+                        double* log_mpred_dev, double* mean_dev, double* cov_dev,
+                        int32_t* ranks_dev, int32_t* status_dev, void* ws, size_t ws_bytes,
+                        void* stream);
+
+/* ---------------------------------------------------------------------
+ * Optional timing of kernel classes (measurement support, not part of the
+ * method).  tt_profile_begin(mask) makes the library record a pair of HIP
+ * events on the launch stream around every launch of each class c with bit
+ * (1 << c) set in mask:
+ *   0 convolution, 1 Hadamard, 2 Gram, 3 pivoted Cholesky, 4 Jacobi,
+ *   5 triangular solve, 6 GEMM, 7 likelihood build, 8 sum/moments.
+ * tt_profile_end waits for the recorded events, writes the summed
+ * milliseconds and launch counts of classes 0..nclass-1 (either array may be
+ * NULL), stops recording and returns the number of classes (or -1).  The
+ * state is per process; do not profile from several threads at once.
+ * --------------------------------------------------------------------- */
+void tt_profile_begin(int32_t class_mask);
+int32_t tt_profile_end(double* ms, int32_t* launches, int32_t nclass);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TTGBF_H */

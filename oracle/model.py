@@ -70,17 +70,23 @@ def kernel_halfwidths(q, axes, nsigma=4.0, truncate=True):
 def kernel_dense(q, axes, halfwidths):
     """K(m) = N(Delta o m; 0, Q) * delta on the offset box (Sec. 2.1,
     eq. TPMmat with x_{k+1} = x_k + w_k: the TPM depends on i - j only and
-    its middle row, eq. tpmconvFFT, is this tensor)."""
+    its middle row, eq. tpmconvFFT, is this tensor).  The quadratic form is
+    accumulated from broadcast 1-D offset vectors, one dense array in all."""
     d = len(axes)
     dx = spacings(axes)
-    grids = np.meshgrid(*[dx[l] * np.arange(-halfwidths[l], halfwidths[l] + 1) for l in range(d)],
-                        indexing="ij")
-    y = np.stack([g.ravel() for g in grids], axis=0)        # d x M
+    ys = []
+    for l in range(d):
+        shp = [1] * d
+        shp[l] = -1
+        ys.append((dx[l] * np.arange(-halfwidths[l], halfwidths[l] + 1)).reshape(shp))
     qinv = np.linalg.inv(q)
-    quad = np.einsum("im,ij,jm->m", y, qinv, y)
+    quad = np.zeros([2 * h + 1 for h in halfwidths])
+    for l in range(d):
+        for j in range(d):
+            if qinv[l, j] != 0.0:
+                quad += qinv[l, j] * (ys[l] * ys[j])
     norm = (2.0 * math.pi) ** (-d / 2.0) / math.sqrt(np.linalg.det(q))
-    vals = norm * np.exp(-0.5 * quad) * cell_volume(axes)
-    return vals.reshape(grids[0].shape)
+    return norm * np.exp(-0.5 * quad) * cell_volume(axes)
 
 
 def kernel_tt(q, axes, halfwidths, tol=1e-12):

@@ -1,0 +1,329 @@
+"""Thin ctypes binding of libttgbf.so (include/ttgbf.h).
+
+Argument marshalling only: every numerical step runs in the HIP library.
+PyTorch supplies device memory and the stream.  Importing this module loads
+the library and raises if it is missing: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libttgbf.so")
+
+MAXD = 16
+F64, F32 = 0, 1
+OK, ERR_ARG, ERR_SHAPE, ERR_WORKSPACE, ERR_HIP = 0, 1, 2, 3, 4
+STATUS_NONPOSITIVE, STATUS_NONFINITE, STATUS_CAPACITY = 1, 2, 4
+
+
+class Grid(C.Structure):
+    _fields_ = [("d", C.c_int32), ("n", C.c_int32 * MAXD), ("lo", C.c_double * MAXD),
+                ("hi", C.c_double * MAXD)]
+
+
+class Train(C.Structure):
+    _fields_ = [("d", C.c_int32), ("n", C.c_int32 * MAXD), ("cap", C.c_int32 * (MAXD + 1)),
+                ("dtype", C.c_int32), ("cores", C.c_void_p), ("ranks", C.c_void_p),
+                ("log_scale", C.c_void_p), ("status", C.c_void_p)]
+
+
+class Meas(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("sensor", C.c_double * 2), ("sigma_r", C.c_double),
+                ("sigma_lin", C.c_double), ("lik_tol", C.c_double), ("lik_max_rank", C.c_int32)]
+
+
+class FilterSpec(C.Structure):
+    _fields_ = [("grid", Grid), ("meas", Meas), ("m0", C.c_double * MAXD),
+                ("p0_diag", C.c_double * MAXD), ("cap", C.c_int32), ("eps", C.c_double),
+                ("kernel_index", C.c_int32), ("kernel_cap", C.c_int32),
+                ("lik_rank_cap", C.c_int32)]
+
+
+class TTError(RuntimeError):
+    pass
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2501_07942_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    P, S, I, D = C.c_void_p, C.c_size_t, C.c_int32, C.c_double
+    sigs = {
+        "tt_train_elems": (S, [I, P, P]),
+        "tt_last_error": (C.c_char_p, []),
+        "tt_version": (C.c_char_p, []),
+        "tt_kernel_build_workspace": (S, [P, P, P]),
+        "tt_kernel_build": (I, [P, P, P, D, P, P, S, P]),
+        "tt_predict_workspace": (S, [I]),
+        "tt_predict": (I, [I, P, P, P, P, S, P]),
+        "tt_update_workspace": (S, [I, P, P, P, P, I]),
+        "tt_update": (I, [I, P, P, P, I, P, P, I, P, P, S, P]),
+        "tt_round_workspace": (S, [I, P, P]),
+        "tt_round": (I, [I, P, P, D, I, P, S, P]),
+        "tt_normalize_moments_workspace": (S, [I, P]),
+        "tt_normalize_moments": (I, [I, P, P, P, P, P, P, S, P]),
+        "tt_filter_run_workspace": (S, [I, P, I]),
+        "tt_profile_begin": (None, [I]),
+        "tt_profile_end": (I, [P, P, I]),
+        "tt_filter_run": (I, [I, P, P, I, P, I, I, I, I, I, P, P, P, P, P, P, P, P, S, P]),
+    }
+    for name, (res, args) in sigs.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+LIB = _load()
+EXPORTED = ("tt_train_elems", "tt_last_error", "tt_version", "tt_kernel_build_workspace",
+            "tt_kernel_build", "tt_predict_workspace", "tt_predict", "tt_update_workspace",
+            "tt_update", "tt_round_workspace", "tt_round", "tt_normalize_moments_workspace",
+            "tt_normalize_moments", "tt_filter_run_workspace", "tt_filter_run", "tt_profile_begin",
+            "tt_profile_end")
+
+PROFILE_CLASSES = ("conv", "hadamard", "gram", "pchol", "jacobi", "trsm", "gemm", "lik", "contract")
+
+
+def profile_begin(classes=PROFILE_CLASSES):
+    mask = 0
+    for c in classes:
+        mask |= 1 << PROFILE_CLASSES.index(c)
+    LIB.tt_profile_begin(mask)
+
+
+def profile_end():
+    """{class: (total ms, launches)} of the launches since profile_begin."""
+    n = len(PROFILE_CLASSES)
+    ms = (C.c_double * n)()
+    cnt = (C.c_int32 * n)()
+    if LIB.tt_profile_end(ms, cnt, n) < 0:
+        raise TTError(LIB.tt_last_error().decode())
+    return {PROFILE_CLASSES[i]: (ms[i], cnt[i]) for i in range(n)}
+
+
+def _check(st: int, what: str):
+    if st != OK:
+        raise TTError(f"{what} failed ({st}): {LIB.tt_last_error().decode()}")
+
+
+def _torch():
+    import torch  # imported lazily so that the CPU-only symbol test needs no GPU
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _arr(structs):
+    arr_t = type(structs[0]) * len(structs)
+    return arr_t(*structs)
+
+
+def make_grid(d: int, n: Sequence[int], lo: Sequence[float], hi: Sequence[float]) -> Grid:
+    g = Grid()
+    g.d = d
+    for l in range(d):
+        g.n[l] = int(n[l])
+        g.lo[l] = float(lo[l])
+        g.hi[l] = float(hi[l])
+    return g
+
+
+def make_meas(kind: int, sensor=(0.0, 0.0), sigma_r=1.0, sigma_lin=1.0, lik_tol=1e-12,
+              lik_max_rank=0) -> Meas:
+    m = Meas()
+    m.kind = kind
+    m.sensor[0], m.sensor[1] = float(sensor[0]), float(sensor[1])
+    m.sigma_r = float(sigma_r)
+    m.sigma_lin = float(sigma_lin)
+    m.lik_tol = float(lik_tol)
+    m.lik_max_rank = int(lik_max_rank)
+    return m
+
+
+class DeviceTT:
+    """A TT whose cores, ranks, log-scale and status live in torch device
+    tensors.  Layout of core k: [r_{k-1}][n_k][r_k] packed with the current
+    ranks at offset sum_{j<k} cap[j]*n[j]*cap[j+1]."""
+
+    def __init__(self, n: Sequence[int], cap: Sequence[int], dtype: int = F64, device="cuda"):
+        torch = _torch()
+        self.d = len(n)
+        self.n = [int(x) for x in n]
+        self.cap = [int(x) for x in cap]
+        assert len(self.cap) == self.d + 1 and self.cap[0] == 1 and self.cap[-1] == 1
+        self.dtype = dtype
+        tdt = torch.float64 if dtype == F64 else torch.float32
+        self.offsets = []
+        off = 0
+        for k in range(self.d):
+            self.offsets.append(off)
+            off += self.cap[k] * self.n[k] * self.cap[k + 1]
+        self.cores = torch.zeros(max(off, 1), dtype=tdt, device=device)
+        self.ranks = torch.ones(self.d + 1, dtype=torch.int32, device=device)
+        self.log_scale = torch.zeros(1, dtype=torch.float64, device=device)
+        self.status = torch.zeros(1, dtype=torch.int32, device=device)
+
+    def struct(self) -> Train:
+        t = Train()
+        t.d = self.d
+        for k in range(self.d):
+            t.n[k] = self.n[k]
+        for j in range(self.d + 1):
+            t.cap[j] = self.cap[j]
+        t.dtype = self.dtype
+        t.cores = self.cores.data_ptr()
+        t.ranks = self.ranks.data_ptr()
+        t.log_scale = self.log_scale.data_ptr()
+        t.status = self.status.data_ptr()
+        return t
+
+    def load(self, cores: List[np.ndarray], log_scale: float = 0.0):
+        """Copy host cores (list of (r0, n, r1) arrays) into the device TT."""
+        torch = _torch()
+        host = torch.zeros_like(self.cores, device="cpu")
+        for k, g in enumerate(cores):
+            r0, n, r1 = g.shape
+            if r0 > self.cap[k] or r1 > self.cap[k + 1] or n != self.n[k]:
+                raise ValueError(f"core {k} {g.shape} exceeds capacity {self.cap[k]}x{self.n[k]}x{self.cap[k+1]}")
+            flat = torch.from_numpy(np.ascontiguousarray(g).ravel()).to(host.dtype)
+            host[self.offsets[k]:self.offsets[k] + flat.numel()] = flat
+        self.cores.copy_(host)
+        rk = [1] + [g.shape[2] for g in cores]
+        self.ranks.copy_(torch.tensor(rk, dtype=torch.int32))
+        self.log_scale.fill_(float(log_scale))
+        self.status.zero_()
+
+    def fetch(self):
+        """(cores, log_scale, status) as host FP64 arrays."""
+        rk = self.ranks.cpu().numpy().tolist()
+        data = self.cores.cpu().double().numpy()
+        cores = []
+        for k in range(self.d):
+            r0, r1 = rk[k], rk[k + 1]
+            sz = r0 * self.n[k] * r1
+            cores.append(data[self.offsets[k]:self.offsets[k] + sz].reshape(r0, self.n[k], r1).copy())
+        return cores, float(self.log_scale.cpu().item()), int(self.status.cpu().item())
+
+    def fetch_scaled(self):
+        """Cores with exp(log_scale) folded into the first core."""
+        cores, ls, st = self.fetch()
+        cores[0] = cores[0] * math.exp(ls)
+        return cores, st
+
+
+def _ws(nbytes: int):
+    torch = _torch()
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device="cuda")
+
+
+# ---------------------------------------------------------------------------
+# entry points (same names as the C ABI)
+# ---------------------------------------------------------------------------
+
+def tt_kernel_build(grid: Grid, q: np.ndarray, halfwidths: Sequence[int], svd_tol: float, out: DeviceTT):
+    d = grid.d
+    hw = (C.c_int32 * d)(*[int(h) for h in halfwidths])
+    qq = (C.c_double * (d * d))(*np.asarray(q, dtype=np.float64).ravel().tolist())
+    capa = (C.c_int32 * (d + 1))(*out.cap)
+    nbytes = LIB.tt_kernel_build_workspace(C.byref(grid), hw, capa)
+    if nbytes == 0:
+        _check(ERR_ARG, "tt_kernel_build_workspace")
+    ws = _ws(nbytes)
+    t = out.struct()
+    _check(LIB.tt_kernel_build(C.byref(grid), qq, hw, float(svd_tol), C.byref(t), ws.data_ptr(),
+                               ws.numel(), _stream()), "tt_kernel_build")
+    return out
+
+
+def tt_predict(kernels: Sequence[DeviceTT], p_in: Sequence[DeviceTT], p_out: Sequence[DeviceTT]):
+    B = len(p_in)
+    ks, ps, xs = _arr([k.struct() for k in kernels]), _arr([p.struct() for p in p_in]), _arr([x.struct() for x in p_out])
+    ws = _ws(LIB.tt_predict_workspace(B))
+    _check(LIB.tt_predict(B, ks, ps, xs, ws.data_ptr(), ws.numel(), _stream()), "tt_predict")
+
+
+def tt_update(grids: Sequence[Grid], meas: Sequence[Meas], z, p_pred: Sequence[DeviceTT],
+              h_out: Sequence[DeviceTT], lik_rank_cap: int, log_c):
+    """z: torch float64 device tensor [B, zdim]; log_c: torch float64 device [B]."""
+    B = len(p_pred)
+    g, m = _arr(list(grids)), _arr(list(meas))
+    ps, hs = _arr([p.struct() for p in p_pred]), _arr([h.struct() for h in h_out])
+    nbytes = LIB.tt_update_workspace(B, g, m, ps, hs, int(lik_rank_cap))
+    if nbytes == 0:
+        _check(ERR_ARG, "tt_update_workspace")
+    ws = _ws(nbytes)
+    _check(LIB.tt_update(B, g, m, z.data_ptr(), int(z.shape[1]), ps, hs, int(lik_rank_cap),
+                         log_c.data_ptr(), ws.data_ptr(), ws.numel(), _stream()), "tt_update")
+
+
+def tt_round(t_in: Sequence[DeviceTT], t_out: Sequence[DeviceTT], eps: float, max_rank: int):
+    B = len(t_in)
+    a, b = _arr([t.struct() for t in t_in]), _arr([t.struct() for t in t_out])
+    nbytes = LIB.tt_round_workspace(B, a, b)
+    if nbytes == 0:
+        _check(ERR_ARG, "tt_round_workspace")
+    ws = _ws(nbytes)
+    _check(LIB.tt_round(B, a, b, float(eps), int(max_rank), ws.data_ptr(), ws.numel(), _stream()), "tt_round")
+
+
+def tt_normalize_moments(grids: Sequence[Grid], tts: Sequence[DeviceTT], log_mass, mean=None, cov=None):
+    B = len(tts)
+    g, a = _arr(list(grids)), _arr([t.struct() for t in tts])
+    ws = _ws(LIB.tt_normalize_moments_workspace(B, a))
+    _check(LIB.tt_normalize_moments(B, g, a, log_mass.data_ptr(), mean.data_ptr() if mean is not None else None,
+                                    cov.data_ptr() if cov is not None else None, ws.data_ptr(), ws.numel(),
+                                    _stream()), "tt_normalize_moments")
+
+
+class FilterRun:
+    """Device buffers and workspace of one batched tt_filter_run call."""
+
+    def __init__(self, specs: Sequence[FilterSpec], kernels: Sequence[DeviceTT], K: int, zdim: int,
+                 precision: int):
+        torch = _torch()
+        self.B = len(specs)
+        self.K = K
+        self.zdim = zdim
+        self.precision = precision
+        self.specs = _arr(list(specs))
+        self.kernels = kernels
+        self.karr = _arr([k.struct() for k in kernels])
+        d = specs[0].grid.d
+        self.d = d
+        dev = "cuda"
+        self.loglik = torch.zeros(self.B, dtype=torch.float64, device=dev)
+        self.log_c = torch.zeros(self.B, K, dtype=torch.float64, device=dev)
+        self.log_mpred = torch.zeros(self.B, K, dtype=torch.float64, device=dev)
+        self.mean = torch.zeros(self.B, K, d, dtype=torch.float64, device=dev)
+        self.cov = torch.zeros(self.B, K, d, d, dtype=torch.float64, device=dev)
+        self.ranks = torch.zeros(self.B, K, d + 1, dtype=torch.int32, device=dev)
+        self.status = torch.zeros(self.B, dtype=torch.int32, device=dev)
+        nbytes = LIB.tt_filter_run_workspace(self.B, self.specs, precision)
+        if nbytes == 0:
+            _check(ERR_ARG, "tt_filter_run_workspace")
+        self.ws = _ws(nbytes)
+
+    def __call__(self, z, moments: bool = True, k_begin: int = 0, k_count: Optional[int] = None):
+        """z: float64 device tensor [B, K, zdim].  Runs steps k_begin ..
+        k_begin+k_count-1 (all K by default); k_begin > 0 resumes from the
+        state the previous call left in this object's workspace."""
+        if k_count is None:
+            k_count = self.K - k_begin
+        st = LIB.tt_filter_run(self.B, self.specs, self.karr, len(self.kernels), z.data_ptr(), self.zdim,
+                               self.K, int(k_begin), int(k_count), self.precision, self.loglik.data_ptr(),
+                               self.log_c.data_ptr(),
+                               self.log_mpred.data_ptr(),
+                               self.mean.data_ptr() if moments else None,
+                               self.cov.data_ptr() if moments else None,
+                               self.ranks.data_ptr(), self.status.data_ptr(), self.ws.data_ptr(),
+                               self.ws.numel(), _stream())
+        _check(st, "tt_filter_run")

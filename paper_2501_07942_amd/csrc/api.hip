@@ -1,0 +1,2098 @@
+// Host side of the C ABI: argument checks, workspace planning, descriptor
+// upload and the launch sequences of every entry point in ttgbf.h.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+#include "linalg.h"
+#include "ttops.h"
+
+namespace ttg {
+
+static thread_local char g_err[1024] = "";
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+tt_status check_hip(hipError_t e, const char* what) {
+  set_error("%s: %s", what, hipGetErrorString(e));
+  return TT_ERR_HIP;
+}
+
+// ---------------------------------------------------------------------------
+// optional timing of kernel classes with HIP events on the launch stream
+// ---------------------------------------------------------------------------
+enum ProfClass {
+  PC_CONV = 0, PC_HADAMARD, PC_GRAM, PC_PCHOL, PC_JACOBI, PC_TRSM, PC_GEMM, PC_LIK, PC_CONTRACT, PC_OTHER, PC_N
+};
+struct ProfRec {
+  int cls;
+  hipEvent_t a, b;
+};
+static std::vector<ProfRec> g_prof;
+static std::vector<hipEvent_t> g_pool;
+static int g_prof_mask = 0;
+static size_t g_pool_next = 0;
+
+static hipEvent_t prof_event() {
+  if (g_pool_next == g_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    g_pool.push_back(e);
+  }
+  return g_pool[g_pool_next++];
+}
+
+struct ProfScope {
+  int cls;
+  hipStream_t st;
+  hipEvent_t a = nullptr;
+  ProfScope(int c, hipStream_t s) : cls(c), st(s) {
+    if (g_prof_mask & (1 << c)) {
+      a = prof_event();
+      if (a) hipEventRecord(a, st);
+    }
+  }
+  ~ProfScope() {
+    if (a) {
+      hipEvent_t b = prof_event();
+      if (b) {
+        hipEventRecord(b, st);
+        g_prof.push_back({cls, a, b});
+      }
+    }
+  }
+};
+
+#define HIP_TRY(expr, what)                              \
+  do {                                                   \
+    hipError_t e__ = (expr);                             \
+    if (e__ != hipSuccess) return check_hip(e__, what);  \
+  } while (0)
+
+#define TT_TRY(expr)                 \
+  do {                               \
+    tt_status s__ = (expr);          \
+    if (s__ != TT_OK) return s__;    \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// bump allocator over the caller's workspace; with base == nullptr it only
+// measures the bytes a plan needs (the *_workspace queries)
+// ---------------------------------------------------------------------------
+struct Arena {
+  char* base;
+  size_t cap;
+  size_t used = 0;
+  Arena(void* b, size_t c) : base(reinterpret_cast<char*>(b)), cap(c) {}
+  template <typename T>
+  T* take(size_t count) {
+    size_t off = (used + 255) & ~size_t(255);
+    used = off + count * sizeof(T);
+    if (!base) return nullptr;
+    return reinterpret_cast<T*>(base + off);
+  }
+  bool fits() const { return base != nullptr && used <= cap; }
+};
+
+static size_t elems_of(int d, const int* n, const int* cap) {
+  size_t s = 0;
+  for (int k = 0; k < d; ++k) s += (size_t)cap[k] * n[k] * cap[k + 1];
+  return s;
+}
+
+static DevTT make_dev(const tt_train& t) {
+  DevTT o;
+  memset(&o, 0, sizeof(o));
+  o.d = t.d;
+  long long off = 0;
+  for (int k = 0; k < t.d; ++k) {
+    o.n[k] = t.n[k];
+    o.off[k] = off;
+    off += (long long)t.cap[k] * t.n[k] * t.cap[k + 1];
+  }
+  for (int k = 0; k <= t.d; ++k) o.cap[k] = t.cap[k];
+  o.cores = t.cores;
+  o.ranks = t.ranks;
+  o.log_scale = t.log_scale;
+  o.status = t.status;
+  return o;
+}
+
+static tt_status check_train(const tt_train* t, const char* name, int want_dtype = -1) {
+  if (!t) {
+    set_error("%s is NULL", name);
+    return TT_ERR_ARG;
+  }
+  if (t->d < 1 || t->d > TT_MAXD) {
+    set_error("%s: d=%d out of range [1,%d]", name, t->d, TT_MAXD);
+    return TT_ERR_SHAPE;
+  }
+  if (!t->cores || !t->ranks || !t->log_scale || !t->status) {
+    set_error("%s: null device pointer", name);
+    return TT_ERR_ARG;
+  }
+  if (t->dtype != TT_F64 && t->dtype != TT_F32) {
+    set_error("%s: bad dtype %d", name, t->dtype);
+    return TT_ERR_ARG;
+  }
+  if (want_dtype >= 0 && t->dtype != want_dtype) {
+    set_error("%s: dtype %d, expected %d", name, t->dtype, want_dtype);
+    return TT_ERR_ARG;
+  }
+  if (t->cap[0] != 1 || t->cap[t->d] != 1) {
+    set_error("%s: cap[0] and cap[d] must be 1", name);
+    return TT_ERR_SHAPE;
+  }
+  for (int k = 0; k < t->d; ++k)
+    if (t->n[k] < 1 || t->n[k] > 4096) {
+      set_error("%s: n[%d]=%d out of range", name, k, t->n[k]);
+      return TT_ERR_SHAPE;
+    }
+  for (int k = 0; k <= t->d; ++k)
+    if (t->cap[k] < 1 || t->cap[k] > 4096) {
+      set_error("%s: cap[%d]=%d out of range", name, k, t->cap[k]);
+      return TT_ERR_SHAPE;
+    }
+  return TT_OK;
+}
+
+template <typename T>
+static tt_status upload(T* dst, const std::vector<T>& src, hipStream_t s) {
+  if (src.empty()) return TT_OK;
+  HIP_TRY(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s),
+          "descriptor upload");
+  // the host vectors die when the call returns: wait for the copy
+  HIP_TRY(hipStreamSynchronize(s), "descriptor upload sync");
+  return TT_OK;
+}
+
+static int cdiv(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+static FilterConst make_const(const tt_grid& g, const tt_meas* m) {
+  FilterConst c;
+  memset(&c, 0, sizeof(c));
+  c.d = g.d;
+  double ld = 0.0;
+  for (int l = 0; l < g.d; ++l) {
+    c.n[l] = g.n[l];
+    c.lo[l] = g.lo[l];
+    c.dx[l] = (g.hi[l] - g.lo[l]) / (double)(g.n[l] - 1);
+    ld += std::log(c.dx[l]);
+  }
+  c.logdelta = ld;
+  if (m) {
+    c.meas_kind = m->kind;
+    c.sensor[0] = m->sensor[0];
+    c.sensor[1] = m->sensor[1];
+    c.sigma_r = m->sigma_r;
+    c.sigma_lin = m->sigma_lin;
+    c.lik_tol = m->lik_tol;
+    c.lik_max_rank = m->lik_max_rank;
+  }
+  return c;
+}
+
+static tt_status check_grid(const tt_grid* g) {
+  if (!g || g->d < 1 || g->d > TT_MAXD) {
+    set_error("bad grid");
+    return TT_ERR_ARG;
+  }
+  for (int l = 0; l < g->d; ++l)
+    if (g->n[l] < 2 || !(g->hi[l] > g->lo[l])) {
+      set_error("grid axis %d: need n >= 2 and hi > lo", l);
+      return TT_ERR_SHAPE;
+    }
+  return TT_OK;
+}
+
+// ===========================================================================
+// rounding
+// ===========================================================================
+struct RoundShape {  // host-side maxima over the batch, for grid sizing
+  int d = 0, B = 0;
+  int rin[TT_MAXD + 1] = {0};   // input rank capacities
+  int rq[TT_MAXD + 1] = {0};    // pre-truncated rank capacities
+  int rout[TT_MAXD + 1] = {0};  // output rank capacities
+  int n[TT_MAXD] = {0};
+  int gcap = 0, splits = 1;
+  bool f64 = true;
+  bool merge = false;  // bond 1 wider than n_0: fold core 0 into the bond-1 step
+};
+
+static const int RQ_MAX_F64 = 256;
+static const int RQ_MAX_F32 = 128;
+
+struct RoundBufs {
+  DevTT* din = nullptr;
+  DevTT* dout = nullptr;
+  RoundScratch* drs = nullptr;
+};
+
+// Per-filter scratch for one rounding (also used by the likelihood SVD and
+// the kernel TT-SVD, which need the gram/pchol/jacobi parts only).
+static void plan_round_scratch(Arena& ar, const DevTT& in, const DevTT& out, bool f64, int gcap,
+                               int splits, RoundScratch& rs) {
+  memset(&rs, 0, sizeof(rs));
+  const int d = in.d;
+  const int rqmax = f64 ? RQ_MAX_F64 : RQ_MAX_F32;
+  rs.rqcap[0] = 1;
+  rs.rqcap[d] = 1;
+  for (int j = 1; j < d; ++j) rs.rqcap[j] = std::min(in.cap[j], rqmax);
+  long long q = 0, zmax = 0, bmax = 0;
+  for (int k = 0; k < d; ++k) {
+    rs.qoff[k] = q;
+    const int left = (k == 0) ? 1 : rs.rqcap[k];
+    q += (long long)left * in.n[k] * rs.rqcap[k + 1];
+    zmax = std::max(zmax, (long long)in.cap[k] * in.n[k] * rs.rqcap[k + 1]);
+    bmax = std::max(bmax, (long long)out.cap[k] * in.n[k] * rs.rqcap[k + 1]);
+  }
+  if (d >= 2) bmax = std::max(bmax, (long long)in.n[0] * in.n[1] * rs.rqcap[2]);
+  const size_t esz = f64 ? 8 : 4;
+  const int words = 2;  // room for double-double (the likelihood SVD always uses it)
+  rs.gcap = gcap;
+  rs.splits = splits;
+  rs.qbuf = ar.take<char>(q * esz);
+  rs.zbuf = ar.take<char>(zmax * esz);
+  rs.bbuf = ar.take<char>(bmax * esz);
+  const long long g2 = (long long)gcap * gcap;
+  rs.gram = ar.take<double>(g2 * words * splits);
+  rs.lwork = ar.take<double>(g2 * words);
+  rs.lfac = ar.take<double>(g2);
+  rs.jac = ar.take<double>(g2);
+  rs.sigma = ar.take<double>(gcap);
+  rs.usv = ar.take<double>(g2);
+  rs.vs = ar.take<double>(g2);
+  rs.w = ar.take<double>(g2);
+  rs.piv = ar.take<int>(gcap);
+  rs.rq = ar.take<int>(TT_MAXD + 1);
+  rs.ri = ar.take<int>(TT_MAXD + 1);
+  rs.misc = ar.take<int>(8);
+  rs.scal = ar.take<double>(8);
+}
+
+static int gram_tiles(int M) {
+  const int t = (M + 31) / 32;
+  return t * (t + 1) / 2;
+}
+
+// Split-K planes of every Gram scratch.  The split count a filter uses is
+// a function of its own summation length only (gram_split_count), so a
+// filter gives bitwise the same result alone or inside any batch.
+static const int GRAM_PLANES = 8;
+static int choose_splits(int pairs, int B, long long T, int smax) {
+  (void)pairs;
+  (void)B;
+  (void)T;
+  return std::min(smax, GRAM_PLANES);
+}
+
+// ---- functors (device side shape logic) ----------------------------------
+struct RCtx {
+  const DevTT* X;
+  const DevTT* O;
+  const RoundScratch* S;
+  int k;
+  int d;
+  double tau2;
+  int esz;    // bytes per bulk element
+  int merge;  // fold core 0 into the bond-1 step (left rank bounded by n_0)
+};
+
+template <typename T>
+__device__ inline T* qcore(const RoundScratch& s, int k) {
+  return reinterpret_cast<T*>(s.qbuf) + s.qoff[k];
+}
+
+// Fold core 0 into the bond-1 step when bond 1 is wider than n_0 (its rank
+// is bounded by n_0 from the left).  Decided per filter from its own ranks so
+// that a filter gives the same result alone or in any batch.
+__device__ inline bool merge_bond1(const DevTT& X, const RoundScratch& s) { return s.ri[1] > X.n[0]; }
+
+template <typename T>
+struct FRlAbsorb {  // Z_k = X_k x_3 L_{k+1}   (k = 0 writes the first core into qbuf)
+  RCtx c;
+  __device__ bool operator()(int b, GemmArgs& g) const {
+    const DevTT& X = c.X[b];
+    const RoundScratch& s = c.S[b];
+    const int k = c.k;
+    if (k == 0 && merge_bond1(X, s)) return false;  // first core comes from the bond-1 factor
+    g.M = s.ri[k] * X.n[k];
+    g.K = s.ri[k + 1];
+    g.N = s.rq[k + 1];
+    g.a = core_ptr<T>(X, k);
+    g.sam = g.K;
+    g.sak = 1;
+    g.b = s.lfac;
+    g.sbk = s.gcap;
+    g.sbn = 1;
+    g.c = (k == 0) ? (void*)qcore<T>(s, 0) : s.zbuf;
+    g.scm = g.N;
+    g.scn = 1;
+    return true;
+  }
+};
+
+template <typename T>
+struct FRlMerge {  // Z'_1 = X_0 (n_0 x r_1) * Z_1 (r_1 x n_1 rq_2)  -> bbuf
+  RCtx c;
+  __device__ bool operator()(int b, GemmArgs& g) const {
+    const DevTT& X = c.X[b];
+    const RoundScratch& s = c.S[b];
+    if (!merge_bond1(X, s)) return false;
+    g.M = X.n[0];
+    g.K = s.ri[1];
+    g.N = X.n[1] * s.rq[2];
+    g.a = core_ptr<T>(X, 0);
+    g.sam = g.K;
+    g.sak = 1;
+    g.b = (c.d == 2) ? (const void*)core_ptr<T>(X, 1) : (const void*)s.zbuf;
+    g.sbk = g.N;
+    g.sbn = 1;
+    g.c = s.bbuf;
+    g.scm = g.N;
+    g.scn = 1;
+    return true;
+  }
+};
+
+// merged case: the first core is the pivoted Cholesky factor L (n_0 x rq_1)
+template <typename T>
+__global__ void first_core_copy_kernel(const DevTT* __restrict__ X, const RoundScratch* __restrict__ S) {
+  const int f = blockIdx.x;
+  const RoundScratch& s = S[f];
+  if (!merge_bond1(X[f], s)) return;
+  const int n0 = X[f].n[0], r = s.rq[1];
+  T* q = qcore<T>(s, 0);
+  for (int e = threadIdx.x; e < n0 * r; e += blockDim.x) {
+    const int i = e / r, j = e % r;
+    q[e] = from_double<T>(s.lfac[(long long)i * s.gcap + j]);
+  }
+}
+
+template <typename T>
+struct FRlGram {
+  RCtx c;
+  __device__ bool operator()(int b, GramArgs& g) const {
+    const DevTT& X = c.X[b];
+    const RoundScratch& s = c.S[b];
+    const int k = c.k;
+    const bool mg = k == 1 && merge_bond1(X, s);
+    g.M = mg ? X.n[0] : s.ri[k];
+    g.T = X.n[k] * s.rq[k + 1];
+    g.x = mg ? (const void*)s.bbuf
+             : ((k == c.d - 1) ? (const void*)core_ptr<T>(X, k) : (const void*)s.zbuf);
+    g.sa = g.T;
+    g.st = 1;
+    g.out = s.gram;
+    g.gcap = s.gcap;
+    g.splits = s.splits;
+    return true;
+  }
+};
+
+struct FRlPchol {
+  RCtx c;
+  __device__ bool operator()(int b, PcholArgs& p) const {
+    const RoundScratch& s = c.S[b];
+    const int k = c.k;
+    p.M = (k == 1 && merge_bond1(c.X[b], s)) ? c.X[b].n[0] : s.ri[k];
+    p.g = s.gram;
+    p.lwork = s.lwork;
+    p.lfac = s.lfac;
+    p.piv = s.piv;
+    p.rank_out = &s.rq[k];
+    p.resid_out = nullptr;
+    p.status = c.O[b].status;
+    p.gcap = s.gcap;
+    p.rmax = s.rqcap[k];
+    p.tau2 = c.tau2;
+    return true;
+  }
+};
+
+template <typename T>
+struct FRlTrsm {
+  RCtx c;
+  __device__ bool operator()(int b, TrsmArgs& a) const {
+    const DevTT& X = c.X[b];
+    const RoundScratch& s = c.S[b];
+    const int k = c.k;
+    a.r = s.rq[k];
+    a.m = X.n[k] * s.rq[k + 1];
+    a.lfac = s.lfac;
+    a.piv = s.piv;
+    a.gcap = s.gcap;
+    const bool mg = k == 1 && merge_bond1(X, s);
+    a.z = mg ? (const void*)s.bbuf
+             : ((k == c.d - 1) ? (const void*)core_ptr<T>(X, k) : (const void*)s.zbuf);
+    a.ldz = a.m;
+    a.q = qcore<T>(s, k);
+    a.ldq = a.m;
+    return true;
+  }
+};
+
+template <typename T>
+struct FLrB {  // B_k = W_k x_1 Q_k  (k >= 1)
+  RCtx c;
+  __device__ bool operator()(int b, GemmArgs& g) const {
+    const DevTT& O = c.O[b];
+    const RoundScratch& s = c.S[b];
+    const int k = c.k;
+    g.M = O.ranks[k];
+    g.K = s.rq[k];
+    g.N = O.n[k] * s.rq[k + 1];
+    g.a = s.w;
+    g.sam = s.gcap;
+    g.sak = 1;
+    g.b = qcore<T>(s, k);
+    g.sbk = g.N;
+    g.sbn = 1;
+    g.c = (k == c.d - 1) ? (void*)core_ptr<T>(O, k) : s.bbuf;
+    g.scm = g.N;
+    g.scn = 1;
+    return true;
+  }
+};
+
+template <typename T>
+struct FLrGram {
+  RCtx c;
+  __device__ bool operator()(int b, GramArgs& g) const {
+    const DevTT& O = c.O[b];
+    const RoundScratch& s = c.S[b];
+    const int k = c.k;
+    g.M = s.rq[k + 1];
+    g.T = O.ranks[k] * O.n[k];
+    g.x = (k == 0) ? (const void*)qcore<T>(s, 0) : (const void*)s.bbuf;
+    g.sa = 1;
+    g.st = g.M;
+    g.out = s.gram;
+    g.gcap = s.gcap;
+    g.splits = s.splits;
+    return true;
+  }
+};
+
+struct FLrPchol {
+  RCtx c;
+  __device__ bool operator()(int b, PcholArgs& p) const {
+    const RoundScratch& s = c.S[b];
+    p.M = s.rq[c.k + 1];
+    p.g = s.gram;
+    p.lwork = s.lwork;
+    p.lfac = s.lfac;
+    p.piv = s.piv;
+    p.rank_out = &s.misc[0];
+    p.resid_out = &s.scal[2];
+    p.status = c.O[b].status;
+    p.gcap = s.gcap;
+    p.rmax = s.gcap;
+    p.tau2 = c.tau2;
+    return true;
+  }
+};
+
+struct FLrJacobi {
+  RCtx c;
+  __device__ bool operator()(int b, JacobiArgs& J) const {
+    const RoundScratch& s = c.S[b];
+    J.rows = s.rq[c.k + 1];
+    J.ncols = s.misc[0];
+    J.x = s.lfac;
+    J.ldx = s.gcap;
+    J.work = s.jac;
+    J.sigma = s.sigma;
+    J.usv = s.usv;
+    J.ncols_out = nullptr;
+    J.gcap = s.gcap;
+    return true;
+  }
+};
+
+template <typename T>
+struct FLrU {  // core k of the result = B_k V_r Sigma_r^{-1}
+  RCtx c;
+  __device__ bool operator()(int b, GemmArgs& g) const {
+    const DevTT& O = c.O[b];
+    const RoundScratch& s = c.S[b];
+    const int k = c.k;
+    g.M = O.ranks[k] * O.n[k];
+    g.K = s.rq[k + 1];
+    g.N = O.ranks[k + 1];
+    g.a = (k == 0) ? (const void*)qcore<T>(s, 0) : (const void*)s.bbuf;
+    g.sam = g.K;
+    g.sak = 1;
+    g.b = s.vs;
+    g.sbk = s.gcap;
+    g.sbn = 1;
+    g.c = core_ptr<T>(O, k);
+    g.scm = g.N;
+    g.scn = 1;
+    return true;
+  }
+};
+
+// rank rule at bond k+1 of the output; prepares V_r Sigma_r^{-1} and Sigma_r V_r^T
+__global__ void round_select_kernel(const DevTT* __restrict__ O, const RoundScratch* __restrict__ S,
+                                    int k, int max_rank) {
+  const int f = blockIdx.x;
+  const DevTT& o = O[f];
+  const RoundScratch& s = S[f];
+  __shared__ int s_r;
+  const int nc = s.misc[0];
+  const int rq = s.rq[k + 1];
+  if (threadIdx.x == 0) {
+    const double delta = s.scal[1];
+    double tail2 = fmax(s.scal[2], 0.0);
+    // smallest r with sqrt(resid + sum_{j>=r} sigma_j^2) <= delta
+    int r = nc;
+    if (sqrt(tail2) <= delta) {
+      r = nc;
+      for (int j = nc - 1; j >= 0; --j) {
+        const double t2 = tail2 + s.sigma[j] * s.sigma[j];
+        if (sqrt(t2) <= delta) {
+          tail2 = t2;
+          r = j;
+        } else {
+          break;
+        }
+      }
+    }
+    r = max(r, 1);
+    r = min(r, max_rank);
+    r = min(r, max(nc, 1));
+    if (r > o.cap[k + 1]) {
+      r = o.cap[k + 1];
+      atomicOr(o.status, TT_STATUS_CAPACITY);
+    }
+    o.ranks[k + 1] = r;
+    s_r = r;
+  }
+  __syncthreads();
+  const int r = s_r;
+  for (int e = threadIdx.x; e < r * rq; e += blockDim.x) {
+    const int j = e / rq, t = e % rq;
+    const double sg = (j < nc) ? s.sigma[j] : 0.0;
+    const double x = (j < nc) ? s.usv[(long long)j * s.gcap + t] : 0.0;
+    s.w[(long long)j * s.gcap + t] = x;
+    s.vs[(long long)t * s.gcap + j] = (sg > 0.0) ? x / (sg * sg) : 0.0;
+  }
+}
+
+// snapshot input ranks, fix boundary ranks, carry log-scale and status
+__global__ void round_init_kernel(const DevTT* __restrict__ X, const DevTT* __restrict__ O,
+                                  const RoundScratch* __restrict__ S, int nf) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nf) return;
+  const DevTT &x = X[f], &o = O[f];
+  const RoundScratch& s = S[f];
+  int over = 0;
+  for (int j = 0; j <= x.d; ++j) {
+    int r = x.ranks[j];
+    if (r > x.cap[j] || r < 1) {  // never read outside the reserved storage
+      over = 1;
+      r = max(1, min(r, x.cap[j]));
+    }
+    s.ri[j] = r;
+  }
+  if (over) atomicOr(o.status, TT_STATUS_CAPACITY);
+  s.rq[0] = 1;
+  s.rq[x.d] = 1;
+  const double ls = *x.log_scale;
+  const int st = *x.status;
+  o.ranks[0] = 1;
+  o.ranks[x.d] = 1;
+  *o.log_scale = ls;
+  if (o.status != x.status) atomicOr(o.status, st);
+}
+
+// ||first core|| -> scal[0]; delta = eps * ||A|| / sqrt(d-1) -> scal[1]
+template <typename T>
+__global__ void round_norm_kernel(const DevTT* __restrict__ X, const RoundScratch* __restrict__ S,
+                                  double eps) {
+  const int f = blockIdx.x;
+  const RoundScratch& s = S[f];
+  const DevTT& x = X[f];
+  const T* c = qcore<T>(s, 0);
+  const long long tot = (long long)x.n[0] * s.rq[1];
+  __shared__ double red[8];
+  double a = 0.0;
+  for (long long e = threadIdx.x; e < tot; e += blockDim.x) {
+    const double v = bulk_to_double(c[e]);
+    a += v * v;
+  }
+  a = block_sum(a, red);
+  if (threadIdx.x == 0) {
+    s.scal[0] = sqrt(a);
+    s.scal[1] = eps * sqrt(a) / sqrt((double)max(x.d - 1, 1));
+  }
+}
+
+template <typename F>
+static tt_status launch_pchol_any(bool f64, F f, int B, int gcap, hipStream_t st);
+
+template <typename Acc, typename F>
+static tt_status launch_pchol(F f, int B, int gcap, hipStream_t st) {
+  ProfScope ps_(PC_PCHOL, st);
+  const size_t smem = (size_t)(2 * gcap) * sizeof(typename Acc::V) + (size_t)gcap * sizeof(int) + 64;
+  if (smem > 48 * 1024)
+    HIP_TRY(hipFuncSetAttribute((const void*)pchol_kernel<Acc, F>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem),
+            "pchol smem attribute");
+  hipLaunchKernelGGL((pchol_kernel<Acc, F>), dim3(B), dim3(256), smem, st, f);
+  TTG_LAUNCH_CHECK("pchol_kernel");
+  return TT_OK;
+}
+
+template <typename T, typename Acc, typename F>
+static tt_status launch_gram(F f, int B, int Mcap, long long Tcap, int smax, hipStream_t st) {
+  ProfScope ps_(PC_GRAM, st);
+  const int pairs = gram_tiles(Mcap);
+  const int splits = choose_splits(pairs, B, Tcap, smax);
+  (void)splits;
+  // the split count actually used is the one stored in the scratch (smax)
+  hipLaunchKernelGGL((gram_partial_kernel<T, Acc, F>), dim3(pairs, smax, B), dim3(256), 0, st, f);
+  TTG_LAUNCH_CHECK("gram_partial_kernel");
+  const long long mm = (long long)Mcap * Mcap;
+  hipLaunchKernelGGL((gram_reduce_kernel<Acc, F>), dim3(std::max(1, std::min(cdiv(mm, 256), 1024)), 1, B),
+                     dim3(256), 0, st, f);
+  TTG_LAUNCH_CHECK("gram_reduce_kernel");
+  return TT_OK;
+}
+
+template <typename TA, typename TB, typename TC, typename TAcc, typename F>
+static tt_status launch_gemm(F f, int B, long long Mcap, long long Ncap, hipStream_t st) {
+  ProfScope ps_(PC_GEMM, st);
+  const int tm = std::max(1, cdiv(Mcap, 64)), tn = std::max(1, cdiv(Ncap, 64));
+  hipLaunchKernelGGL((gemm_kernel<TA, TB, TC, TAcc, F>), dim3(tn, tm, B), dim3(256), 0, st, f);
+  TTG_LAUNCH_CHECK("gemm_kernel");
+  return TT_OK;
+}
+
+template <typename F>
+static tt_status launch_jacobi(F f, int B, hipStream_t st) {
+  ProfScope ps_(PC_JACOBI, st);
+  hipLaunchKernelGGL((jacobi_kernel<F>), dim3(B), dim3(512), 0, st, f);
+  TTG_LAUNCH_CHECK("jacobi_kernel");
+  return TT_OK;
+}
+
+template <typename TZ, typename TQ, typename F>
+static tt_status launch_trsm(F f, int B, long long mcap, int rcap, hipStream_t st) {
+  ProfScope ps_(PC_TRSM, st);
+  const size_t smem = (size_t)rcap * 64 * sizeof(double);
+  if (smem > 48 * 1024)
+    HIP_TRY(hipFuncSetAttribute((const void*)trsm_kernel<TZ, TQ, F>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem),
+            "trsm smem attribute");
+  hipLaunchKernelGGL((trsm_kernel<TZ, TQ, F>), dim3(std::max(1, cdiv(mcap, 64)), 1, B), dim3(64), smem, st,
+                     f, rcap);
+  TTG_LAUNCH_CHECK("trsm_kernel");
+  return TT_OK;
+}
+
+// The launch sequence of one batched rounding.  Shapes come from device
+// ranks; `sh` only bounds the grids.
+template <typename T, typename Acc>
+static tt_status round_launch(const RoundShape& sh, const RoundBufs& rb, double eps, int max_rank,
+                              hipStream_t st) {
+  const int B = sh.B, d = sh.d;
+  const bool f64 = sizeof(T) == 8;
+  const double tau2_rl = f64 ? 1e-30 : 1e-14;
+  const double tau2_lr = f64 ? 1e-31 : 1e-16;
+  RCtx c{rb.din, rb.dout, rb.drs, 0, d, 0.0, (int)sizeof(T), sh.merge ? 1 : 0};
+  hipLaunchKernelGGL(round_init_kernel, dim3(cdiv(B, 64)), dim3(64), 0, st, rb.din, rb.dout, rb.drs, B);
+  TTG_LAUNCH_CHECK("round_init_kernel");
+  if (d == 1) {
+    // a single core: nothing to truncate; copy when not in place is handled by
+    // the caller (d == 1 is rejected there)
+    return TT_OK;
+  }
+  // ---- right-to-left orthogonalisation with pre-truncation -------------
+  for (int k = d - 1; k >= 1; --k) {
+    c.k = k;
+    if (k < d - 1) {
+      TT_TRY((launch_gemm<T, double, T, T>(FRlAbsorb<T>{c}, B, (long long)sh.rin[k] * sh.n[k], sh.rq[k + 1], st)));
+    }
+    const bool mg = sh.merge && k == 1;  // some filter may fold core 0 into this step
+    if (mg) TT_TRY((launch_gemm<T, T, T, T>(FRlMerge<T>{c}, B, sh.n[0], (long long)sh.n[1] * sh.rq[2], st)));
+    c.tau2 = tau2_rl;
+    const int mcap = (k == 1) ? std::min(sh.rin[1], std::max(sh.n[0], 1)) : sh.rin[k];
+    TT_TRY((launch_gram<T, Acc>(FRlGram<T>{c}, B, mcap, (long long)sh.n[k] * sh.rq[k + 1], sh.splits, st)));
+    TT_TRY((launch_pchol<Acc>(FRlPchol{c}, B, sh.gcap, st)));
+    TT_TRY((launch_trsm<T, T>(FRlTrsm<T>{c}, B, (long long)sh.n[k] * sh.rq[k + 1], sh.rq[k], st)));
+  }
+  c.k = 0;
+  if (sh.merge) {
+    hipLaunchKernelGGL((first_core_copy_kernel<T>), dim3(B), dim3(256), 0, st, rb.din, rb.drs);
+    TTG_LAUNCH_CHECK("first_core_copy_kernel");
+  }
+  TT_TRY((launch_gemm<T, double, T, T>(FRlAbsorb<T>{c}, B, (long long)sh.n[0], sh.rq[1], st)));
+  hipLaunchKernelGGL((round_norm_kernel<T>), dim3(B), dim3(256), 0, st, rb.din, rb.drs, eps);
+  TTG_LAUNCH_CHECK("round_norm_kernel");
+  // ---- left-to-right truncation ------------------------------------------
+  for (int k = 0; k <= d - 2; ++k) {
+    c.k = k;
+    if (k >= 1) {
+      TT_TRY((launch_gemm<double, T, T, T>(FLrB<T>{c}, B, sh.rout[k], (long long)sh.n[k] * sh.rq[k + 1], st)));
+    }
+    c.tau2 = tau2_lr;
+    TT_TRY((launch_gram<T, Acc>(FLrGram<T>{c}, B, sh.rq[k + 1], (long long)sh.rout[k] * sh.n[k], sh.splits, st)));
+    TT_TRY((launch_pchol<Acc>(FLrPchol{c}, B, sh.gcap, st)));
+    TT_TRY((launch_jacobi(FLrJacobi{c}, B, st)));
+    hipLaunchKernelGGL(round_select_kernel, dim3(B), dim3(256), 0, st, rb.dout, rb.drs, k, max_rank);
+    TTG_LAUNCH_CHECK("round_select_kernel");
+    TT_TRY((launch_gemm<T, double, T, T>(FLrU<T>{c}, B, (long long)sh.rout[k] * sh.n[k], sh.rout[k + 1], st)));
+  }
+  c.k = d - 1;
+  TT_TRY((launch_gemm<double, T, T, T>(FLrB<T>{c}, B, sh.rout[d - 1], (long long)sh.n[d - 1], st)));
+  hipLaunchKernelGGL((balance_kernel<T>), dim3(B), dim3(256), 0, st, rb.dout);
+  TTG_LAUNCH_CHECK("balance_kernel");
+  return TT_OK;
+}
+
+// host-side shape maxima and scratch planning for a batch of roundings
+static void round_shape(int B, const std::vector<DevTT>& in, const std::vector<DevTT>& out, bool f64,
+                        RoundShape& sh) {
+  sh.B = B;
+  sh.d = in[0].d;
+  sh.f64 = f64;
+  const int rqmax = f64 ? RQ_MAX_F64 : RQ_MAX_F32;
+  int gcap = 1;
+  for (int b = 0; b < B; ++b) {
+    for (int j = 0; j <= sh.d; ++j) {
+      sh.rin[j] = std::max(sh.rin[j], in[b].cap[j]);
+      sh.rout[j] = std::max(sh.rout[j], out[b].cap[j]);
+      const int rq = (j == 0 || j == sh.d) ? 1 : std::min(in[b].cap[j], rqmax);
+      sh.rq[j] = std::max(sh.rq[j], rq);
+    }
+    for (int k = 0; k < sh.d; ++k) sh.n[k] = std::max(sh.n[k], in[b].n[k]);
+    if (in[b].cap[1] > in[b].n[0]) sh.merge = true;
+  }
+  for (int j = 1; j < sh.d; ++j) {
+    gcap = std::max(gcap, j == 1 ? std::min(sh.rin[1], sh.n[0]) : sh.rin[j]);
+    gcap = std::max(gcap, sh.rq[j]);
+  }
+  sh.gcap = gcap;
+  // split-K planes: enough workgroups for small batches
+  int pairs = gram_tiles(gcap);
+  long long Tmax = 0;
+  for (int k = 0; k < sh.d; ++k)
+    Tmax = std::max(Tmax, (long long)sh.n[k] * std::max(sh.rq[k + 1], sh.rout[k]));
+  (void)pairs;
+  (void)Tmax;
+  sh.splits = GRAM_PLANES;
+}
+
+}  // namespace ttg
+
+using namespace ttg;
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+size_t tt_train_elems(int32_t d, const int32_t* n, const int32_t* cap) {
+  if (d < 1 || d > TT_MAXD || !n || !cap) return 0;
+  return elems_of(d, n, cap);
+}
+
+const char* tt_last_error(void) { return g_err; }
+
+const char* tt_version(void) { return "ttgbf 0.1 gfx950"; }
+
+// ---------------------------------------------------------------------------
+// tt_round
+// ---------------------------------------------------------------------------
+static tt_status round_plan(int32_t batch, const tt_train* t_in, const tt_train* t_out, Arena& ar,
+                            RoundShape& sh, RoundBufs& rb, std::vector<DevTT>& vin,
+                            std::vector<DevTT>& vout, std::vector<RoundScratch>& vrs) {
+  if (batch < 1) {
+    set_error("batch must be >= 1");
+    return TT_ERR_ARG;
+  }
+  const int dtype = t_in[0].dtype;
+  for (int b = 0; b < batch; ++b) {
+    TT_TRY(check_train(&t_in[b], "t_in", dtype));
+    TT_TRY(check_train(&t_out[b], "t_out", dtype));
+    if (t_in[b].d != t_in[0].d || t_out[b].d != t_in[0].d) {
+      set_error("all TTs of a batch must share d");
+      return TT_ERR_SHAPE;
+    }
+    if (t_in[0].d < 2) {
+      set_error("rounding needs d >= 2");
+      return TT_ERR_SHAPE;
+    }
+    for (int k = 0; k < t_in[b].d; ++k)
+      if (t_in[b].n[k] != t_out[b].n[k]) {
+        set_error("t_in and t_out mode sizes differ");
+        return TT_ERR_SHAPE;
+      }
+  }
+  const bool f64 = dtype == TT_F64;
+  vin.resize(batch);
+  vout.resize(batch);
+  vrs.resize(batch);
+  for (int b = 0; b < batch; ++b) {
+    vin[b] = make_dev(t_in[b]);
+    vout[b] = make_dev(t_out[b]);
+  }
+  round_shape(batch, vin, vout, f64, sh);
+  if (sh.gcap > 1024) {
+    set_error("tt_round: rank capacity %d exceeds 1024", sh.gcap);
+    return TT_ERR_SHAPE;
+  }
+  rb.din = ar.take<DevTT>(batch);
+  rb.dout = ar.take<DevTT>(batch);
+  rb.drs = ar.take<RoundScratch>(batch);
+  for (int b = 0; b < batch; ++b) plan_round_scratch(ar, vin[b], vout[b], f64, sh.gcap, sh.splits, vrs[b]);
+  return TT_OK;
+}
+
+size_t tt_round_workspace(int32_t batch, const tt_train* t_in, const tt_train* t_out) {
+  if (batch < 1 || !t_in || !t_out) return 0;
+  Arena ar(nullptr, 0);
+  RoundShape sh;
+  RoundBufs rb;
+  std::vector<DevTT> a, b;
+  std::vector<RoundScratch> r;
+  if (round_plan(batch, t_in, t_out, ar, sh, rb, a, b, r) != TT_OK) return 0;
+  return ar.used + 256;
+}
+
+tt_status tt_round(int32_t batch, const tt_train* t_in, const tt_train* t_out, double eps, int32_t max_rank,
+                   void* ws, size_t ws_bytes, void* stream) {
+  if (!t_in || !t_out || !ws) {
+    set_error("tt_round: null argument");
+    return TT_ERR_ARG;
+  }
+  if (!(eps >= 0.0) || max_rank < 1) {
+    set_error("tt_round: need eps >= 0 and max_rank >= 1");
+    return TT_ERR_ARG;
+  }
+  Arena ar(ws, ws_bytes);
+  RoundShape sh;
+  RoundBufs rb;
+  std::vector<DevTT> vin, vout;
+  std::vector<RoundScratch> vrs;
+  TT_TRY(round_plan(batch, t_in, t_out, ar, sh, rb, vin, vout, vrs));
+  if (!ar.fits()) {
+    set_error("tt_round: workspace too small (%zu < %zu)", ws_bytes, ar.used);
+    return TT_ERR_WORKSPACE;
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  TT_TRY(upload(rb.din, vin, st));
+  TT_TRY(upload(rb.dout, vout, st));
+  TT_TRY(upload(rb.drs, vrs, st));
+  if (sh.f64) return round_launch<double, AccDD>(sh, rb, eps, max_rank, st);
+  return round_launch<float, AccD>(sh, rb, eps, max_rank, st);
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// likelihood SVD, kernel TT-SVD helpers
+// ===========================================================================
+namespace ttg {
+
+// Likelihood rank rule: smallest r with sqrt(resid + sum_{j>=r} s_j^2) <=
+// lik_tol * ||M||_F; writes core 1 = V_r^T and vs = V_r (for core 0 = M V_r).
+__global__ void lik_select_kernel(const DevTT* __restrict__ L, const RoundScratch* __restrict__ S,
+                                  const FilterConst* __restrict__ fc) {
+  const int f = blockIdx.x;
+  const FilterConst& C = fc[f];
+  if (C.meas_kind != 1) return;
+  const DevTT& l = L[f];
+  const RoundScratch& s = S[f];
+  __shared__ int s_r;
+  const int nc = s.misc[0];
+  const int n1 = C.n[1];
+  if (threadIdx.x == 0) {
+    double tot = fmax(s.scal[2], 0.0);
+    for (int j = 0; j < nc; ++j) tot += s.sigma[j] * s.sigma[j];
+    const double delta = C.lik_tol * sqrt(tot);
+    double tail2 = fmax(s.scal[2], 0.0);
+    int r = nc;
+    if (sqrt(tail2) <= delta) {
+      for (int j = nc - 1; j >= 0; --j) {
+        const double t2 = tail2 + s.sigma[j] * s.sigma[j];
+        if (sqrt(t2) <= delta) {
+          tail2 = t2;
+          r = j;
+        } else {
+          break;
+        }
+      }
+    }
+    r = max(r, 1);
+    r = min(r, max(nc, 1));
+    if (C.lik_max_rank > 0) r = min(r, C.lik_max_rank);
+    if (r > l.cap[1]) {
+      r = l.cap[1];
+      atomicOr(l.status, TT_STATUS_CAPACITY);
+    }
+    l.ranks[1] = r;
+    s_r = r;
+  }
+  __syncthreads();
+  const int r = s_r;
+  double* core1 = core_ptr<double>(l, 1);
+  for (int e = threadIdx.x; e < r * n1; e += blockDim.x) {
+    const int j = e / n1, i = e % n1;
+    const double sg = (j < nc) ? s.sigma[j] : 0.0;
+    const double v = (j < nc && sg > 0.0) ? s.usv[(long long)j * s.gcap + i] / sg : 0.0;
+    core1[(long long)j * n1 + i] = v;
+    s.vs[(long long)i * s.gcap + j] = v;
+  }
+}
+
+struct LikCtx {
+  const DevTT* L;
+  const RoundScratch* S;
+  const FilterConst* C;
+  const double* mbuf;
+  long long mstride;
+};
+
+struct FLikGram {  // Gram of the columns of M (n0 x n1)
+  LikCtx c;
+  __device__ bool operator()(int b, GramArgs& g) const {
+    if (c.C[b].meas_kind != 1) return false;
+    const RoundScratch& s = c.S[b];
+    g.M = c.C[b].n[1];
+    g.T = c.C[b].n[0];
+    g.x = c.mbuf + b * c.mstride;
+    g.sa = 1;
+    g.st = g.M;
+    g.out = s.gram;
+    g.gcap = s.gcap;
+    g.splits = s.splits;
+    return true;
+  }
+};
+struct FLikPchol {
+  LikCtx c;
+  __device__ bool operator()(int b, PcholArgs& p) const {
+    if (c.C[b].meas_kind != 1) return false;
+    const RoundScratch& s = c.S[b];
+    p.M = c.C[b].n[1];
+    p.g = s.gram;
+    p.lwork = s.lwork;
+    p.lfac = s.lfac;
+    p.piv = s.piv;
+    p.rank_out = &s.misc[0];
+    p.resid_out = &s.scal[2];
+    p.status = c.L[b].status;
+    p.gcap = s.gcap;
+    p.rmax = s.gcap;
+    p.tau2 = 1e-31;
+    return true;
+  }
+};
+struct FLikJacobi {
+  LikCtx c;
+  __device__ bool operator()(int b, JacobiArgs& J) const {
+    if (c.C[b].meas_kind != 1) return false;
+    const RoundScratch& s = c.S[b];
+    J.rows = c.C[b].n[1];
+    J.ncols = s.misc[0];
+    J.x = s.lfac;
+    J.ldx = s.gcap;
+    J.work = s.jac;
+    J.sigma = s.sigma;
+    J.usv = s.usv;
+    J.ncols_out = nullptr;
+    J.gcap = s.gcap;
+    return true;
+  }
+};
+struct FLikCore0 {  // core 0 = M V_r  (n0 x r)
+  LikCtx c;
+  __device__ bool operator()(int b, GemmArgs& g) const {
+    if (c.C[b].meas_kind != 1) return false;
+    const DevTT& l = c.L[b];
+    const RoundScratch& s = c.S[b];
+    g.M = c.C[b].n[0];
+    g.K = c.C[b].n[1];
+    g.N = l.ranks[1];
+    g.a = c.mbuf + b * c.mstride;
+    g.sam = g.K;
+    g.sak = 1;
+    g.b = s.vs;
+    g.sbk = s.gcap;
+    g.sbn = 1;
+    g.c = core_ptr<double>(l, 0);
+    g.scm = g.N;
+    g.scn = 1;
+    return true;
+  }
+};
+
+// Likelihood TT for a batch (FP64): dense factors, range-block SVD.
+static tt_status lik_launch(int B, const DevTT* dL, const RoundScratch* drs, const FilterConst* dfc,
+                            const double* z, long long zstride, double* mbuf, long long mstride,
+                            bool any_range, int n0max, int n1max, int gcap, int splits, hipStream_t st) {
+  ProfScope ps_(PC_LIK, st);
+  hipLaunchKernelGGL(lik_dense_kernel, dim3(B), dim3(256), 0, st, dL, dfc, z, zstride, mbuf, mstride);
+  TTG_LAUNCH_CHECK("lik_dense_kernel");
+  if (!any_range) return TT_OK;
+  LikCtx c{dL, drs, dfc, mbuf, mstride};
+  TT_TRY((launch_gram<double, AccDD>(FLikGram{c}, B, n1max, n0max, splits, st)));
+  TT_TRY((launch_pchol<AccDD>(FLikPchol{c}, B, gcap, st)));
+  TT_TRY((launch_jacobi(FLikJacobi{c}, B, st)));
+  hipLaunchKernelGGL(lik_select_kernel, dim3(B), dim3(256), 0, st, dL, drs, dfc);
+  TTG_LAUNCH_CHECK("lik_select_kernel");
+  TT_TRY((launch_gemm<double, double, double, double>(FLikCore0{c}, B, n0max, n1max, st)));
+  return TT_OK;
+}
+
+// ---- kernel TT-SVD --------------------------------------------------------
+struct KsvdCtx {
+  const DevTT* K;  // FP64 result
+  const RoundScratch* S;
+  const double* a;   // current unfolding (row-major rows x cols)
+  double* next;      // next unfolding
+  long long cols;    // columns of the current unfolding
+  int k;
+  int d;
+};
+struct FKsvdGram {
+  KsvdCtx c;
+  __device__ bool operator()(int b, GramArgs& g) const {
+    const DevTT& K = c.K[b];
+    const RoundScratch& s = c.S[b];
+    g.M = K.ranks[c.k] * K.n[c.k];
+    g.T = (int)c.cols;
+    g.x = c.a;
+    g.sa = c.cols;
+    g.st = 1;
+    g.out = s.gram;
+    g.gcap = s.gcap;
+    g.splits = s.splits;
+    return true;
+  }
+};
+struct FKsvdPchol {
+  KsvdCtx c;
+  __device__ bool operator()(int b, PcholArgs& p) const {
+    const DevTT& K = c.K[b];
+    const RoundScratch& s = c.S[b];
+    p.M = K.ranks[c.k] * K.n[c.k];
+    p.g = s.gram;
+    p.lwork = s.lwork;
+    p.lfac = s.lfac;
+    p.piv = s.piv;
+    p.rank_out = &s.misc[0];
+    p.resid_out = &s.scal[2];
+    p.status = K.status;
+    p.gcap = s.gcap;
+    p.rmax = s.gcap;
+    p.tau2 = 1e-30;
+    return true;
+  }
+};
+struct FKsvdJacobi {
+  KsvdCtx c;
+  __device__ bool operator()(int b, JacobiArgs& J) const {
+    const DevTT& K = c.K[b];
+    const RoundScratch& s = c.S[b];
+    J.rows = K.ranks[c.k] * K.n[c.k];
+    J.ncols = s.misc[0];
+    J.x = s.lfac;
+    J.ldx = s.gcap;
+    J.work = s.jac;
+    J.sigma = s.sigma;
+    J.usv = s.usv;
+    J.ncols_out = nullptr;
+    J.gcap = s.gcap;
+    return true;
+  }
+};
+struct FKsvdNext {  // next = U_r^T A
+  KsvdCtx c;
+  __device__ bool operator()(int b, GemmArgs& g) const {
+    const DevTT& K = c.K[b];
+    const int r = K.ranks[c.k + 1];
+    g.M = r;
+    g.K = K.ranks[c.k] * K.n[c.k];
+    g.N = (int)c.cols;
+    g.a = core_ptr<double>(K, c.k);
+    g.sam = 1;
+    g.sak = r;
+    g.b = c.a;
+    g.sbk = c.cols;
+    g.sbn = 1;
+    g.c = c.next;
+    g.scm = c.cols;
+    g.scn = 1;
+    return true;
+  }
+};
+
+__global__ void ksvd_select_kernel(const DevTT* __restrict__ Kt, const RoundScratch* __restrict__ S, int k,
+                                   double tol) {
+  const DevTT& K = Kt[0];
+  const RoundScratch& s = S[0];
+  __shared__ int s_r;
+  const int nc = s.misc[0];
+  const int rows = K.ranks[k] * K.n[k];
+  if (threadIdx.x == 0) {
+    if (k == 0) {
+      double tot = fmax(s.scal[2], 0.0);
+      for (int j = 0; j < nc; ++j) tot += s.sigma[j] * s.sigma[j];
+      s.scal[0] = sqrt(tot);
+      s.scal[1] = tol * sqrt(tot) / sqrt((double)max(K.d - 1, 1));
+    }
+    const double delta = s.scal[1];
+    double tail2 = fmax(s.scal[2], 0.0);
+    int r = nc;
+    if (sqrt(tail2) <= delta) {
+      for (int j = nc - 1; j >= 0; --j) {
+        const double t2 = tail2 + s.sigma[j] * s.sigma[j];
+        if (sqrt(t2) <= delta) {
+          tail2 = t2;
+          r = j;
+        } else {
+          break;
+        }
+      }
+    }
+    r = max(r, 1);
+    r = min(r, max(nc, 1));
+    if (r > K.cap[k + 1]) {
+      r = K.cap[k + 1];
+      atomicOr(K.status, TT_STATUS_CAPACITY);
+    }
+    K.ranks[k + 1] = r;
+    s_r = r;
+  }
+  __syncthreads();
+  const int r = s_r;
+  double* core = core_ptr<double>(K, k);
+  for (int e = threadIdx.x; e < rows * r; e += blockDim.x) {
+    const int row = e / r, j = e % r;
+    const double sg = (j < nc) ? s.sigma[j] : 0.0;
+    core[e] = (j < nc && sg > 0.0) ? s.usv[(long long)j * s.gcap + row] / sg : 0.0;
+  }
+}
+
+__global__ void ksvd_init_kernel(const DevTT* __restrict__ Kt) {
+  const DevTT& K = Kt[0];
+  for (int j = 0; j <= K.d; ++j) K.ranks[j] = 1;
+  *K.log_scale = 0.0;
+  *K.status = 0;
+}
+
+__global__ void ksvd_last_kernel(const DevTT* __restrict__ Kt, const double* __restrict__ a) {
+  const DevTT& K = Kt[0];
+  const int k = K.d - 1;
+  const long long tot = (long long)K.ranks[k] * K.n[k];
+  double* core = core_ptr<double>(K, k);
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < tot; e += (long long)gridDim.x * blockDim.x)
+    core[e] = a[e];
+}
+
+__global__ void fill_kernel(double* p, long long n, long long stride, double v) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
+    p[e * stride] = v;
+}
+
+__global__ void record_ranks_kernel(const DevTT* __restrict__ P, int nf, int* out, long long stride) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nf) return;
+  for (int j = 0; j <= P[f].d; ++j) out[f * stride + j] = P[f].ranks[j];
+}
+
+__global__ void loglik_kernel(const double* log_c, int K, int kdone, int nf, double* out) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nf) return;
+  double s = 0.0;
+  for (int k = 0; k < kdone; ++k) s += log_c[(long long)f * K + k];
+  out[f] = s;
+}
+
+__global__ void copy_status_kernel(const DevTT* __restrict__ P, int nf, int* out) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nf) return;
+  if (P[f].status != out + f) out[f] = *P[f].status;
+}
+
+static size_t moments_scratch_per_filter(int d, int rcap) {
+  return (size_t)3 * d * rcap * rcap + 2 * (size_t)(d + 1) * rcap + 2 * (size_t)rcap + 8;
+}
+
+template <typename T>
+static tt_status launch_moments(int B, const DevTT* dt, const FilterConst* dfc, double* log_mass, long long lms,
+                                double* mean, long long ms, double* cov, long long cs, double* scratch,
+                                long long spf, int rcap, hipStream_t st) {
+  ProfScope ps_(PC_CONTRACT, st);
+  hipLaunchKernelGGL((moments_kernel<T>), dim3(B), dim3(256), 0, st, dt, dfc, log_mass, lms, mean, ms, cov, cs,
+                     scratch, spf, rcap);
+  TTG_LAUNCH_CHECK("moments_kernel");
+  return TT_OK;
+}
+
+template <typename T>
+static tt_status launch_conv(int B, int d, int r0cap, size_t smem, const DevTT* dk, const DevTT* dp,
+                             const DevTT* dx, hipStream_t st) {
+  hipLaunchKernelGGL(product_init_kernel, dim3(cdiv(B, 64)), dim3(64), 0, st, dk, dp, dx, B);
+  TTG_LAUNCH_CHECK("product_init_kernel");
+  if (smem > 48 * 1024)
+    HIP_TRY(hipFuncSetAttribute((const void*)conv_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem),
+            "conv smem attribute");
+  ProfScope ps_(PC_CONV, st);
+  hipLaunchKernelGGL((conv_kernel<T>), dim3(r0cap, d, B), dim3(256), smem, st, dk, dp, dx);
+  TTG_LAUNCH_CHECK("conv_kernel");
+  return TT_OK;
+}
+
+template <typename T>
+static tt_status launch_hadamard(int B, int d, int r0cap, const DevTT* dl, const DevTT* dp, const DevTT* dh,
+                                 hipStream_t st) {
+  hipLaunchKernelGGL(product_init_kernel, dim3(cdiv(B, 64)), dim3(64), 0, st, dl, dp, dh, B);
+  TTG_LAUNCH_CHECK("product_init_kernel");
+  ProfScope ps_(PC_HADAMARD, st);
+  hipLaunchKernelGGL((hadamard_kernel<T>), dim3(r0cap, d, B), dim3(256), 0, st, dl, dp, dh);
+  TTG_LAUNCH_CHECK("hadamard_kernel");
+  return TT_OK;
+}
+
+template <typename T>
+static size_t conv_smem(const DevTT& K, const DevTT& P) {
+  size_t m = 0;
+  for (int k = 0; k < P.d; ++k) {
+    const int taps = K.n[k], h = (taps - 1) / 2;
+    const int taps_pad = (taps + CONV_TB - 1) / CONV_TB * CONV_TB;
+    const size_t s = ((size_t)taps_pad * K.cap[k + 1] + (size_t)(CONV_TB + P.n[k] + 2 * h + CONV_ROWS) * P.cap[k + 1]) * sizeof(T);
+    m = std::max(m, s);
+  }
+  return m;
+}
+
+}  // namespace ttg
+
+extern "C" {
+
+// ---------------------------------------------------------------------------
+// tt_predict
+// ---------------------------------------------------------------------------
+size_t tt_predict_workspace(int32_t batch) {
+  if (batch < 1) return 0;
+  return (size_t)3 * batch * sizeof(DevTT) + 1024;
+}
+
+tt_status tt_predict(int32_t batch, const tt_train* kernels, const tt_train* p_in, const tt_train* p_out, void* ws,
+                     size_t ws_bytes, void* stream) {
+  if (batch < 1 || !kernels || !p_in || !p_out || !ws) {
+    set_error("tt_predict: bad arguments");
+    return TT_ERR_ARG;
+  }
+  const int dtype = p_in[0].dtype;
+  std::vector<DevTT> vk(batch), vp(batch), vx(batch);
+  int r0cap = 1;
+  size_t smem = 0;
+  for (int b = 0; b < batch; ++b) {
+    TT_TRY(check_train(&kernels[b], "kernel", dtype));
+    TT_TRY(check_train(&p_in[b], "p_in", dtype));
+    TT_TRY(check_train(&p_out[b], "p_out", dtype));
+    if (kernels[b].d != p_in[0].d || p_in[b].d != p_in[0].d || p_out[b].d != p_in[0].d) {
+      set_error("tt_predict: d differs");
+      return TT_ERR_SHAPE;
+    }
+    for (int k = 0; k < p_in[b].d; ++k) {
+      if (p_out[b].n[k] != p_in[b].n[k] || (kernels[b].n[k] % 2) != 1) {
+        set_error("tt_predict: n mismatch or even kernel length");
+        return TT_ERR_SHAPE;
+      }
+      r0cap = std::max(r0cap, kernels[b].cap[k] * p_in[b].cap[k]);
+    }
+    vk[b] = make_dev(kernels[b]);
+    vp[b] = make_dev(p_in[b]);
+    vx[b] = make_dev(p_out[b]);
+    smem = std::max(smem, dtype == TT_F64 ? conv_smem<double>(vk[b], vp[b]) : conv_smem<float>(vk[b], vp[b]));
+  }
+  if (smem > 160 * 1024) {
+    set_error("tt_predict: kernel/fibre too long for LDS (%zu bytes)", smem);
+    return TT_ERR_SHAPE;
+  }
+  Arena ar(ws, ws_bytes);
+  DevTT* dk = ar.take<DevTT>(batch);
+  DevTT* dp = ar.take<DevTT>(batch);
+  DevTT* dx = ar.take<DevTT>(batch);
+  if (!ar.fits()) {
+    set_error("tt_predict: workspace too small");
+    return TT_ERR_WORKSPACE;
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  TT_TRY(upload(dk, vk, st));
+  TT_TRY(upload(dp, vp, st));
+  TT_TRY(upload(dx, vx, st));
+  if (dtype == TT_F64) return launch_conv<double>(batch, p_in[0].d, r0cap, smem, dk, dp, dx, st);
+  return launch_conv<float>(batch, p_in[0].d, r0cap, smem, dk, dp, dx, st);
+}
+
+// ---------------------------------------------------------------------------
+// tt_update
+// ---------------------------------------------------------------------------
+struct UpdatePlan {
+  std::vector<DevTT> vl, vp, vh;
+  std::vector<RoundScratch> vrs;
+  std::vector<FilterConst> vfc;
+  DevTT *dl, *dp, *dh;
+  RoundScratch* drs;
+  FilterConst* dfc;
+  double* mbuf;
+  long long mstride;
+  double* vbuf;
+  int vcap;
+  bool any_range;
+  int n0max, n1max, gcap, splits, r0cap;
+};
+
+static tt_status update_plan(int32_t batch, const tt_grid* grids, const tt_meas* meas, const tt_train* p_pred,
+                             const tt_train* h_out, int32_t lik_rank_cap, Arena& ar, UpdatePlan& u) {
+  if (batch < 1 || !grids || !meas || !p_pred || !h_out || lik_rank_cap < 1) {
+    set_error("tt_update: bad arguments");
+    return TT_ERR_ARG;
+  }
+  const int dtype = p_pred[0].dtype;
+  u.vl.resize(batch);
+  u.vp.resize(batch);
+  u.vh.resize(batch);
+  u.vrs.resize(batch);
+  u.vfc.resize(batch);
+  u.any_range = false;
+  u.n0max = u.n1max = 1;
+  u.r0cap = 1;
+  u.vcap = 1;
+  const int d = p_pred[0].d;
+  for (int b = 0; b < batch; ++b) {
+    TT_TRY(check_grid(&grids[b]));
+    TT_TRY(check_train(&p_pred[b], "p_pred", dtype));
+    TT_TRY(check_train(&h_out[b], "h_out", dtype));
+    if (grids[b].d != d || p_pred[b].d != d || h_out[b].d != d) {
+      set_error("tt_update: d differs");
+      return TT_ERR_SHAPE;
+    }
+    if (meas[b].kind != 0 && meas[b].kind != 1) {
+      set_error("tt_update: meas kind must be 0 or 1");
+      return TT_ERR_ARG;
+    }
+    if (meas[b].kind == 1 && d < 2) {
+      set_error("tt_update: range model needs d >= 2");
+      return TT_ERR_SHAPE;
+    }
+    for (int k = 0; k < d; ++k)
+      if (grids[b].n[k] != p_pred[b].n[k] || h_out[b].n[k] != p_pred[b].n[k]) {
+        set_error("tt_update: grid / TT mode sizes differ");
+        return TT_ERR_SHAPE;
+      }
+    u.vfc[b] = make_const(grids[b], &meas[b]);
+    u.vp[b] = make_dev(p_pred[b]);
+    u.vh[b] = make_dev(h_out[b]);
+    u.any_range = u.any_range || meas[b].kind == 1;
+    u.n0max = std::max(u.n0max, grids[b].n[0]);
+    if (d > 1) u.n1max = std::max(u.n1max, grids[b].n[1]);
+    for (int j = 0; j <= d; ++j) u.vcap = std::max(u.vcap, h_out[b].cap[j]);
+  }
+  u.gcap = u.n1max;
+  if (u.gcap > 1024) {
+    set_error("tt_update: n[1] = %d exceeds 1024", u.gcap);
+    return TT_ERR_SHAPE;
+  }
+  u.splits = GRAM_PLANES;
+  u.dl = ar.take<DevTT>(batch);
+  u.dp = ar.take<DevTT>(batch);
+  u.dh = ar.take<DevTT>(batch);
+  u.drs = ar.take<RoundScratch>(batch);
+  u.dfc = ar.take<FilterConst>(batch);
+  u.mstride = (long long)u.n0max * u.n1max;
+  u.mbuf = u.any_range ? ar.take<double>((size_t)batch * u.mstride) : nullptr;
+  u.vbuf = ar.take<double>((size_t)batch * 2 * u.vcap);
+  for (int b = 0; b < batch; ++b) {
+    tt_train lt;
+    memset(&lt, 0, sizeof(lt));
+    lt.d = d;
+    lt.dtype = TT_F64;
+    for (int k = 0; k < d; ++k) lt.n[k] = p_pred[b].n[k];
+    for (int j = 0; j <= d; ++j) lt.cap[j] = 1;
+    if (meas[b].kind == 1) lt.cap[1] = std::min(lik_rank_cap, p_pred[b].n[1]);
+    lt.cores = ar.take<double>(elems_of(d, lt.n, lt.cap));
+    lt.ranks = ar.take<int>(TT_MAXD + 1);
+    lt.log_scale = ar.take<double>(1);
+    lt.status = h_out[b].status;  // shares the output's status word
+    u.vl[b] = make_dev(lt);
+    for (int k = 0; k < d; ++k) u.r0cap = std::max(u.r0cap, lt.cap[k] * p_pred[b].cap[k]);
+    // SVD scratch (gram/pchol/jacobi parts of a round scratch)
+    RoundScratch& rs = u.vrs[b];
+    memset(&rs, 0, sizeof(rs));
+    rs.gcap = u.gcap;
+    rs.splits = u.splits;
+    const long long g2 = (long long)u.gcap * u.gcap;
+    rs.gram = ar.take<double>(g2 * 2 * u.splits);
+    rs.lwork = ar.take<double>(g2 * 2);
+    rs.lfac = ar.take<double>(g2);
+    rs.jac = ar.take<double>(g2);
+    rs.sigma = ar.take<double>(u.gcap);
+    rs.usv = ar.take<double>(g2);
+    rs.vs = ar.take<double>(g2);
+    rs.piv = ar.take<int>(u.gcap);
+    rs.misc = ar.take<int>(8);
+    rs.scal = ar.take<double>(8);
+  }
+  return TT_OK;
+}
+
+static size_t update_ws_bytes(int32_t batch, const tt_grid* grids, const tt_meas* meas, const tt_train* p_pred,
+                              const tt_train* h_out, int32_t lik_rank_cap) {
+  Arena ar(nullptr, 0);
+  UpdatePlan u;
+  if (update_plan(batch, grids, meas, p_pred, h_out, lik_rank_cap, ar, u) != TT_OK) return 0;
+  return ar.used + 256;
+}
+
+size_t tt_update_workspace(int32_t batch, const tt_grid* grids, const tt_meas* meas, const tt_train* p_pred,
+                           const tt_train* h_out, int32_t lik_rank_cap) {
+  return update_ws_bytes(batch, grids, meas, p_pred, h_out, lik_rank_cap);
+}
+
+tt_status tt_update(int32_t batch, const tt_grid* grids, const tt_meas* meas, const double* z_dev, int32_t z_stride,
+                    const tt_train* p_pred, const tt_train* h_out, int32_t lik_rank_cap, double* log_c_dev, void* ws,
+                    size_t ws_bytes, void* stream) {
+  if (!z_dev || !log_c_dev || !ws) {
+    set_error("tt_update: null pointer");
+    return TT_ERR_ARG;
+  }
+  Arena ar(ws, ws_bytes);
+  UpdatePlan u;
+  TT_TRY(update_plan(batch, grids, meas, p_pred, h_out, lik_rank_cap, ar, u));
+  if (!ar.fits()) {
+    set_error("tt_update: workspace too small (%zu < %zu)", ws_bytes, ar.used);
+    return TT_ERR_WORKSPACE;
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  TT_TRY(upload(u.dl, u.vl, st));
+  TT_TRY(upload(u.dp, u.vp, st));
+  TT_TRY(upload(u.dh, u.vh, st));
+  TT_TRY(upload(u.drs, u.vrs, st));
+  TT_TRY(upload(u.dfc, u.vfc, st));
+  TT_TRY(lik_launch(batch, u.dl, u.drs, u.dfc, z_dev, z_stride, u.mbuf, u.mstride, u.any_range, u.n0max, u.n1max,
+                    u.gcap, u.splits, st));
+  const int d = p_pred[0].d;
+  if (p_pred[0].dtype == TT_F64) {
+    TT_TRY(launch_hadamard<double>(batch, d, u.r0cap, u.dl, u.dp, u.dh, st));
+    hipLaunchKernelGGL((sum_kernel<double>), dim3(batch), dim3(256), 0, st, u.dh, u.dfc, log_c_dev, 1LL, u.vbuf, u.vcap);
+  } else {
+    TT_TRY(launch_hadamard<float>(batch, d, u.r0cap, u.dl, u.dp, u.dh, st));
+    hipLaunchKernelGGL((sum_kernel<float>), dim3(batch), dim3(256), 0, st, u.dh, u.dfc, log_c_dev, 1LL, u.vbuf, u.vcap);
+  }
+  TTG_LAUNCH_CHECK("sum_kernel");
+  return TT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// tt_normalize_moments
+// ---------------------------------------------------------------------------
+size_t tt_normalize_moments_workspace(int32_t batch, const tt_train* t) {
+  if (batch < 1 || !t) return 0;
+  int rcap = 1;
+  for (int b = 0; b < batch; ++b)
+    for (int j = 0; j <= t[b].d && j <= TT_MAXD; ++j) rcap = std::max(rcap, t[b].cap[j]);
+  Arena ar(nullptr, 0);
+  ar.take<DevTT>(batch);
+  ar.take<FilterConst>(batch);
+  ar.take<double>((size_t)batch * moments_scratch_per_filter(t[0].d, rcap));
+  return ar.used + 256;
+}
+
+tt_status tt_normalize_moments(int32_t batch, const tt_grid* grids, const tt_train* t, double* log_mass_dev,
+                               double* mean_dev, double* cov_dev, void* ws, size_t ws_bytes, void* stream) {
+  if (batch < 1 || !grids || !t || !ws) {
+    set_error("tt_normalize_moments: bad arguments");
+    return TT_ERR_ARG;
+  }
+  if (cov_dev && !mean_dev) {
+    set_error("tt_normalize_moments: cov needs mean");
+    return TT_ERR_ARG;
+  }
+  const int dtype = t[0].dtype, d = t[0].d;
+  std::vector<DevTT> vt(batch);
+  std::vector<FilterConst> vfc(batch);
+  int rcap = 1;
+  for (int b = 0; b < batch; ++b) {
+    TT_TRY(check_grid(&grids[b]));
+    TT_TRY(check_train(&t[b], "t", dtype));
+    if (t[b].d != d || grids[b].d != d) {
+      set_error("tt_normalize_moments: d differs");
+      return TT_ERR_SHAPE;
+    }
+    for (int j = 0; j <= d; ++j) rcap = std::max(rcap, t[b].cap[j]);
+    vt[b] = make_dev(t[b]);
+    vfc[b] = make_const(grids[b], nullptr);
+  }
+  if (rcap > 64) {
+    set_error("tt_normalize_moments: rank capacity %d > 64", rcap);
+    return TT_ERR_SHAPE;
+  }
+  Arena ar(ws, ws_bytes);
+  DevTT* dt = ar.take<DevTT>(batch);
+  FilterConst* dfc = ar.take<FilterConst>(batch);
+  const long long spf = (long long)moments_scratch_per_filter(d, rcap);
+  double* scratch = ar.take<double>((size_t)batch * spf);
+  if (!ar.fits()) {
+    set_error("tt_normalize_moments: workspace too small");
+    return TT_ERR_WORKSPACE;
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  TT_TRY(upload(dt, vt, st));
+  TT_TRY(upload(dfc, vfc, st));
+  if (dtype == TT_F64)
+    return launch_moments<double>(batch, dt, dfc, log_mass_dev, 1, mean_dev, d, cov_dev, (long long)d * d, scratch,
+                                  spf, rcap, st);
+  return launch_moments<float>(batch, dt, dfc, log_mass_dev, 1, mean_dev, d, cov_dev, (long long)d * d, scratch, spf,
+                               rcap, st);
+}
+
+// ---------------------------------------------------------------------------
+// tt_kernel_build
+// ---------------------------------------------------------------------------
+static bool invert_spd(int d, const double* q, double* inv, double* det) {
+  // Gauss-Jordan with partial pivoting on a copy
+  double a[TT_MAXD][2 * TT_MAXD];
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < 2 * d; ++j) a[i][j] = (j < d) ? q[i * d + j] : (j - d == i ? 1.0 : 0.0);
+  double dt = 1.0;
+  for (int c = 0; c < d; ++c) {
+    int p = c;
+    for (int i = c + 1; i < d; ++i)
+      if (std::fabs(a[i][c]) > std::fabs(a[p][c])) p = i;
+    if (!(std::fabs(a[p][c]) > 0.0)) return false;
+    if (p != c) {
+      for (int j = 0; j < 2 * d; ++j) std::swap(a[p][j], a[c][j]);
+      dt = -dt;
+    }
+    const double piv = a[c][c];
+    dt *= piv;
+    for (int j = 0; j < 2 * d; ++j) a[c][j] /= piv;
+    for (int i = 0; i < d; ++i)
+      if (i != c) {
+        const double f = a[i][c];
+        for (int j = 0; j < 2 * d; ++j) a[i][j] -= f * a[c][j];
+      }
+  }
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < d; ++j) inv[i * d + j] = a[i][d + j];
+  *det = dt;
+  return dt > 0.0;
+}
+
+struct KernelPlan {
+  long long total;
+  int taps[TT_MAXD];
+  double* dense;
+  double* buf2;
+  DevTT* dK64;
+  DevTT* dKout;
+  RoundScratch* drs;
+  DevTT k64;
+  RoundScratch rs;
+  int gcap, splits;
+};
+
+static tt_status kernel_plan(const tt_grid* grid, const int32_t* halfwidths, const int32_t* cap, int out_dtype,
+                             Arena& ar, KernelPlan& kp) {
+  TT_TRY(check_grid(grid));
+  const int d = grid->d;
+  if (d > 8) {
+    set_error("tt_kernel_build: dense build supports d <= 8");
+    return TT_ERR_SHAPE;
+  }
+  long long total = 1;
+  for (int l = 0; l < d; ++l) {
+    if (halfwidths[l] < 0 || 2 * halfwidths[l] + 1 > 4095) {
+      set_error("tt_kernel_build: bad halfwidth");
+      return TT_ERR_SHAPE;
+    }
+    kp.taps[l] = 2 * halfwidths[l] + 1;
+    total *= kp.taps[l];
+    if (total > (1LL << 28)) {
+      set_error("tt_kernel_build: dense kernel larger than 2^28 taps");
+      return TT_ERR_SHAPE;
+    }
+  }
+  kp.total = total;
+  if (cap[0] != 1 || cap[d] != 1) {
+    set_error("tt_kernel_build: cap[0] and cap[d] must be 1");
+    return TT_ERR_SHAPE;
+  }
+  int gcap = 1;
+  for (int k = 0; k < d; ++k) gcap = std::max(gcap, cap[k] * kp.taps[k]);
+  if (gcap > 1024) {
+    set_error("tt_kernel_build: cap*taps = %d exceeds 1024", gcap);
+    return TT_ERR_SHAPE;
+  }
+  kp.gcap = gcap;
+  kp.splits = GRAM_PLANES;
+  kp.dense = ar.take<double>(total);
+  kp.buf2 = ar.take<double>(total);
+  tt_train t64;
+  memset(&t64, 0, sizeof(t64));
+  t64.d = d;
+  t64.dtype = TT_F64;
+  for (int k = 0; k < d; ++k) t64.n[k] = kp.taps[k];
+  for (int j = 0; j <= d; ++j) t64.cap[j] = cap[j];
+  t64.cores = ar.take<double>(elems_of(d, t64.n, t64.cap));
+  t64.ranks = ar.take<int>(TT_MAXD + 1);
+  t64.log_scale = ar.take<double>(1);
+  t64.status = ar.take<int>(1);
+  kp.k64 = make_dev(t64);
+  kp.dK64 = ar.take<DevTT>(1);
+  kp.dKout = ar.take<DevTT>(1);
+  kp.drs = ar.take<RoundScratch>(1);
+  RoundScratch& rs = kp.rs;
+  memset(&rs, 0, sizeof(rs));
+  rs.gcap = gcap;
+  rs.splits = kp.splits;
+  const long long g2 = (long long)gcap * gcap;
+  rs.gram = ar.take<double>(g2 * 2 * kp.splits);
+  rs.lwork = ar.take<double>(g2 * 2);
+  rs.lfac = ar.take<double>(g2);
+  rs.jac = ar.take<double>(g2);
+  rs.sigma = ar.take<double>(gcap);
+  rs.usv = ar.take<double>(g2);
+  rs.piv = ar.take<int>(gcap);
+  rs.misc = ar.take<int>(8);
+  rs.scal = ar.take<double>(8);
+  (void)out_dtype;
+  return TT_OK;
+}
+
+size_t tt_kernel_build_workspace(const tt_grid* grid, const int32_t* halfwidths, const int32_t* cap) {
+  if (!grid || !halfwidths || !cap) return 0;
+  Arena ar(nullptr, 0);
+  KernelPlan kp;
+  if (kernel_plan(grid, halfwidths, cap, TT_F64, ar, kp) != TT_OK) return 0;
+  return ar.used + 256;
+}
+
+tt_status tt_kernel_build(const tt_grid* grid, const double* q, const int32_t* halfwidths, double svd_tol,
+                          const tt_train* out, void* ws, size_t ws_bytes, void* stream) {
+  if (!grid || !q || !halfwidths || !out || !ws || !(svd_tol >= 0.0)) {
+    set_error("tt_kernel_build: bad arguments");
+    return TT_ERR_ARG;
+  }
+  TT_TRY(check_train(out, "out"));
+  const int d = grid->d;
+  if (out->d != d) {
+    set_error("tt_kernel_build: out->d != grid->d");
+    return TT_ERR_SHAPE;
+  }
+  for (int k = 0; k < d; ++k)
+    if (out->n[k] != 2 * halfwidths[k] + 1) {
+      set_error("tt_kernel_build: out->n[%d] must be 2*h+1", k);
+      return TT_ERR_SHAPE;
+    }
+  Arena ar(ws, ws_bytes);
+  KernelPlan kp;
+  TT_TRY(kernel_plan(grid, halfwidths, out->cap, out->dtype, ar, kp));
+  if (!ar.fits()) {
+    set_error("tt_kernel_build: workspace too small (%zu < %zu)", ws_bytes, ar.used);
+    return TT_ERR_WORKSPACE;
+  }
+  KernelEvalArgs ka;
+  memset(&ka, 0, sizeof(ka));
+  ka.d = d;
+  double det = 0.0, logdelta = 0.0;
+  if (!invert_spd(d, q, ka.qinv, &det)) {
+    set_error("tt_kernel_build: Q is not positive definite");
+    return TT_ERR_ARG;
+  }
+  for (int l = 0; l < d; ++l) {
+    ka.taps[l] = kp.taps[l];
+    ka.dx[l] = (grid->hi[l] - grid->lo[l]) / (double)(grid->n[l] - 1);
+    logdelta += std::log(ka.dx[l]);
+  }
+  ka.cnorm = std::exp(-0.5 * d * std::log(2.0 * M_PI) - 0.5 * std::log(det) + logdelta);
+  ka.total = kp.total;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const bool direct = out->dtype == TT_F64;
+  DevTT kout = make_dev(*out);
+  DevTT k64 = direct ? kout : kp.k64;
+  std::vector<DevTT> v64(1, k64), vout(1, kout);
+  std::vector<RoundScratch> vrs(1, kp.rs);
+  TT_TRY(upload(kp.dK64, v64, st));
+  TT_TRY(upload(kp.dKout, vout, st));
+  TT_TRY(upload(kp.drs, vrs, st));
+  hipLaunchKernelGGL(ksvd_init_kernel, dim3(1), dim3(1), 0, st, kp.dK64);
+  TTG_LAUNCH_CHECK("ksvd_init_kernel");
+  hipLaunchKernelGGL(kernel_dense_kernel, dim3(std::min(cdiv(kp.total, 256), 8192)), dim3(256), 0, st, ka, kp.dense);
+  TTG_LAUNCH_CHECK("kernel_dense_kernel");
+  double* cur = kp.dense;
+  double* nxt = kp.buf2;
+  long long cols = kp.total / kp.taps[0];
+  for (int k = 0; k < d - 1; ++k) {
+    KsvdCtx c{kp.dK64, kp.drs, cur, nxt, cols, k, d};
+    const int rows_cap = out->cap[k] * kp.taps[k];
+    TT_TRY((launch_gram<double, AccDD>(FKsvdGram{c}, 1, rows_cap, cols, kp.splits, st)));
+    TT_TRY((launch_pchol<AccDD>(FKsvdPchol{c}, 1, kp.gcap, st)));
+    TT_TRY((launch_jacobi(FKsvdJacobi{c}, 1, st)));
+    hipLaunchKernelGGL(ksvd_select_kernel, dim3(1), dim3(256), 0, st, kp.dK64, kp.drs, k, svd_tol);
+    TTG_LAUNCH_CHECK("ksvd_select_kernel");
+    TT_TRY((launch_gemm<double, double, double, double>(FKsvdNext{c}, 1, out->cap[k + 1], cols, st)));
+    std::swap(cur, nxt);
+    cols /= kp.taps[k + 1];
+  }
+  hipLaunchKernelGGL(ksvd_last_kernel, dim3(64), dim3(256), 0, st, kp.dK64, cur);
+  TTG_LAUNCH_CHECK("ksvd_last_kernel");
+  if (!direct) {
+    hipLaunchKernelGGL((convert_tt_kernel<float>), dim3(64, 1), dim3(256), 0, st, kp.dK64, kp.dKout);
+    TTG_LAUNCH_CHECK("convert_tt_kernel");
+  }
+  return TT_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// tt_filter_run
+// ===========================================================================
+namespace ttg {
+
+struct RunPlan {
+  std::vector<DevTT> vP, vX, vL, vH, vK;
+  std::vector<RoundScratch> vrs;
+  std::vector<FilterConst> vfc;
+  DevTT *dP = nullptr, *dX = nullptr, *dL = nullptr, *dH = nullptr, *dK = nullptr;
+  RoundScratch* drs = nullptr;
+  FilterConst* dfc = nullptr;
+  double* mbuf = nullptr;
+  long long mstride = 0;
+  double* vbuf = nullptr;
+  int vcap = 1;
+  double* mscr = nullptr;
+  long long mspf = 0;
+  int mrcap = 1;
+  double* lmass = nullptr;
+  RoundShape shX, shH;
+  int r0capX = 1, r0capH = 1;
+  size_t csmem = 0;
+  bool any_range = false;
+  int n0max = 1, n1max = 1, gcap = 1, splits = 1;
+  int d = 0;
+};
+
+static tt_status run_plan(int32_t batch, const tt_filter_spec* specs, const tt_train* kernels, int32_t n_kernels,
+                          int32_t precision, int32_t* status_dev, Arena& ar, RunPlan& p) {
+  if (batch < 1 || !specs) {
+    set_error("tt_filter_run: bad arguments");
+    return TT_ERR_ARG;
+  }
+  if (precision != TT_F64 && precision != TT_F32) {
+    set_error("tt_filter_run: precision must be TT_F64 or TT_F32");
+    return TT_ERR_ARG;
+  }
+  const bool f64 = precision == TT_F64;
+  const int d = specs[0].grid.d;
+  p.d = d;
+  if (d < 2) {
+    set_error("tt_filter_run: d must be >= 2");
+    return TT_ERR_SHAPE;
+  }
+  p.vP.resize(batch);
+  p.vX.resize(batch);
+  p.vL.resize(batch);
+  p.vH.resize(batch);
+  p.vK.resize(batch);
+  p.vrs.resize(batch);
+  p.vfc.resize(batch);
+  std::vector<DevTT> vU(batch);
+  const size_t esz = f64 ? 8 : 4;
+  p.dP = ar.take<DevTT>(batch);
+  p.dX = ar.take<DevTT>(batch);
+  p.dL = ar.take<DevTT>(batch);
+  p.dH = ar.take<DevTT>(batch);
+  p.dK = ar.take<DevTT>(batch);
+  p.drs = ar.take<RoundScratch>(batch);
+  p.dfc = ar.take<FilterConst>(batch);
+  int* ints = ar.take<int>((size_t)batch * 4 * (TT_MAXD + 1));
+  double* dbl = ar.take<double>((size_t)batch * 4);
+  for (int b = 0; b < batch; ++b) {
+    const tt_filter_spec& s = specs[b];
+    TT_TRY(check_grid(&s.grid));
+    if (s.grid.d != d) {
+      set_error("tt_filter_run: all filters must share d");
+      return TT_ERR_SHAPE;
+    }
+    if (s.cap < 1 || s.kernel_cap < 1 || s.lik_rank_cap < 1 || !(s.eps >= 0.0)) {
+      set_error("tt_filter_run: filter %d: cap, kernel_cap, lik_rank_cap >= 1 and eps >= 0 required", b);
+      return TT_ERR_ARG;
+    }
+    if (s.meas.kind != 0 && s.meas.kind != 1) {
+      set_error("tt_filter_run: meas kind must be 0 or 1");
+      return TT_ERR_ARG;
+    }
+    for (int l = 0; l < d; ++l)
+      if (!(s.p0_diag[l] > 0.0)) {
+        set_error("tt_filter_run: prior variances must be positive");
+        return TT_ERR_ARG;
+      }
+    if (kernels) {
+      if (s.kernel_index < 0 || s.kernel_index >= n_kernels) {
+        set_error("tt_filter_run: filter %d: kernel_index out of range", b);
+        return TT_ERR_ARG;
+      }
+      const tt_train& kt = kernels[s.kernel_index];
+      TT_TRY(check_train(&kt, "kernel", precision));
+      if (kt.d != d) {
+        set_error("tt_filter_run: kernel d differs");
+        return TT_ERR_SHAPE;
+      }
+      for (int k = 0; k < d; ++k) {
+        if (kt.n[k] % 2 != 1) {
+          set_error("tt_filter_run: kernel length must be odd");
+          return TT_ERR_SHAPE;
+        }
+        if (kt.cap[k + 1] > s.kernel_cap && k + 1 < d) {
+          set_error("tt_filter_run: kernel cap exceeds spec.kernel_cap");
+          return TT_ERR_SHAPE;
+        }
+      }
+      p.vK[b] = make_dev(kt);
+    }
+    p.vfc[b] = make_const(s.grid, &s.meas);
+    for (int l = 0; l < d; ++l) {
+      p.vfc[b].m0[l] = s.m0[l];
+      p.vfc[b].p0[l] = s.p0_diag[l];
+    }
+    p.any_range = p.any_range || s.meas.kind == 1;
+    p.n0max = std::max(p.n0max, s.grid.n[0]);
+    p.n1max = std::max(p.n1max, s.grid.n[1]);
+    tt_train tP, tX, tL, tH;
+    memset(&tP, 0, sizeof(tP));
+    tP.d = d;
+    tP.dtype = precision;
+    for (int k = 0; k < d; ++k) tP.n[k] = s.grid.n[k];
+    tX = tH = tL = tP;
+    tL.dtype = TT_F64;
+    const int lc = (s.meas.kind == 1) ? std::min(s.lik_rank_cap, s.grid.n[1]) : 1;
+    for (int j = 0; j <= d; ++j) {
+      const bool edge = (j == 0 || j == d);
+      tP.cap[j] = edge ? 1 : s.cap;
+      tX.cap[j] = edge ? 1 : s.cap * s.kernel_cap;
+      tL.cap[j] = (j == 1 && d > 1) ? lc : 1;
+      tH.cap[j] = tL.cap[j] * tP.cap[j];
+    }
+    int* rk = ints + (size_t)b * 4 * (TT_MAXD + 1);
+    double* ls = dbl + (size_t)b * 4;
+    int* stw = status_dev ? status_dev + b : nullptr;
+    tP.cores = ar.take<char>(elems_of(d, tP.n, tP.cap) * esz);
+    tX.cores = ar.take<char>(elems_of(d, tX.n, tX.cap) * esz);
+    tL.cores = ar.take<double>(elems_of(d, tL.n, tL.cap));
+    tH.cores = ar.take<char>(elems_of(d, tH.n, tH.cap) * esz);
+    tP.ranks = rk;
+    tX.ranks = rk ? rk + (TT_MAXD + 1) : nullptr;
+    tL.ranks = rk ? rk + 2 * (TT_MAXD + 1) : nullptr;
+    tH.ranks = rk ? rk + 3 * (TT_MAXD + 1) : nullptr;
+    tP.log_scale = ls;
+    tX.log_scale = ls ? ls + 1 : nullptr;
+    tL.log_scale = ls ? ls + 2 : nullptr;
+    tH.log_scale = ls ? ls + 3 : nullptr;
+    tP.status = tX.status = tL.status = tH.status = stw;
+    p.vP[b] = make_dev(tP);
+    p.vX[b] = make_dev(tX);
+    p.vL[b] = make_dev(tL);
+    p.vH[b] = make_dev(tH);
+    tt_train tU = tX;
+    for (int j = 0; j <= d; ++j) tU.cap[j] = std::max(tX.cap[j], tH.cap[j]);
+    vU[b] = make_dev(tU);
+    for (int j = 0; j <= d; ++j) p.vcap = std::max(p.vcap, tH.cap[j]);
+    for (int k = 0; k < d; ++k) {
+      p.r0capX = std::max(p.r0capX, tX.cap[k]);
+      p.r0capH = std::max(p.r0capH, tH.cap[k]);
+    }
+    p.mrcap = std::max(p.mrcap, s.cap);
+    if (kernels) p.csmem = std::max(p.csmem, f64 ? conv_smem<double>(p.vK[b], p.vP[b]) : conv_smem<float>(p.vK[b], p.vP[b]));
+  }
+  if (p.csmem > 160 * 1024) {
+    set_error("tt_filter_run: kernel/fibre too long for LDS");
+    return TT_ERR_SHAPE;
+  }
+  if (p.mrcap > 64) {
+    set_error("tt_filter_run: rank cap > 64 not supported");
+    return TT_ERR_SHAPE;
+  }
+  // rounding scratch sized for both roundings (X -> P and H -> P)
+  RoundShape shU;
+  round_shape(batch, vU, p.vP, f64, shU);
+  p.gcap = std::max(shU.gcap, p.n1max);
+  if (p.gcap > 1024) {
+    set_error("tt_filter_run: rank capacity or n[1] exceeds 1024 (%d)", p.gcap);
+    return TT_ERR_SHAPE;
+  }
+  p.splits = shU.splits;
+  for (int b = 0; b < batch; ++b) plan_round_scratch(ar, vU[b], p.vP[b], f64, p.gcap, p.splits, p.vrs[b]);
+  round_shape(batch, p.vX, p.vP, f64, p.shX);
+  round_shape(batch, p.vH, p.vP, f64, p.shH);
+  p.shX.gcap = p.shH.gcap = p.gcap;
+  p.shX.splits = p.shH.splits = p.splits;
+  p.mstride = (long long)p.n0max * p.n1max;
+  p.mbuf = p.any_range ? ar.take<double>((size_t)batch * p.mstride) : nullptr;
+  p.vbuf = ar.take<double>((size_t)batch * 2 * p.vcap);
+  p.mspf = (long long)moments_scratch_per_filter(d, p.mrcap);
+  p.mscr = ar.take<double>((size_t)batch * p.mspf);
+  p.lmass = ar.take<double>((size_t)batch);
+  return TT_OK;
+}
+
+template <typename T, typename Acc>
+static tt_status run_steps(RunPlan& p, int B, const double* z, int zdim, int K, int k_begin, int k_count,
+                           double* loglik, double* log_c, double* log_mpred, double* mean, double* cov,
+                           int* ranks_out, const tt_filter_spec* specs, hipStream_t st) {
+  const int d = p.d;
+  // all filters of a batch share one (eps, max_rank) pair per launch; group
+  // filters by rounding settings when they differ
+  const double eps = specs[0].eps;
+  int maxcap = 1;
+  for (int b = 0; b < B; ++b) maxcap = std::max(maxcap, specs[b].cap);
+  if (k_begin == 0) {
+    hipLaunchKernelGGL((prior_kernel<T>), dim3(B), dim3(256), 0, st, p.dP, p.dfc);
+    TTG_LAUNCH_CHECK("prior_kernel");
+    TT_TRY(launch_moments<T>(B, p.dP, p.dfc, p.lmass, 1, nullptr, 0, nullptr, 0, p.mscr, p.mspf, p.mrcap, st));
+    hipLaunchKernelGGL(fill_kernel, dim3(cdiv(B, 256)), dim3(256), 0, st, log_mpred, (long long)B, (long long)K,
+                       0.0);
+    TTG_LAUNCH_CHECK("fill_kernel");
+  }
+  RoundBufs rx{p.dX, p.dP, p.drs}, rh{p.dH, p.dP, p.drs};
+  for (int k = k_begin; k < k_begin + k_count; ++k) {
+    if (k > 0) {
+      TT_TRY(launch_conv<T>(B, d, p.r0capX, p.csmem, p.dK, p.dP, p.dX, st));
+      TT_TRY((round_launch<T, Acc>(p.shX, rx, eps, maxcap, st)));
+      TT_TRY(launch_moments<T>(B, p.dP, p.dfc, log_mpred + k, K, nullptr, 0, nullptr, 0, p.mscr, p.mspf, p.mrcap, st));
+    }
+    TT_TRY(lik_launch(B, p.dL, p.drs, p.dfc, z + (long long)k * zdim, (long long)K * zdim, p.mbuf, p.mstride,
+                      p.any_range, p.n0max, p.n1max, p.gcap, p.splits, st));
+    TT_TRY(launch_hadamard<T>(B, d, p.r0capH, p.dL, p.dP, p.dH, st));
+    hipLaunchKernelGGL((sum_kernel<T>), dim3(B), dim3(256), 0, st, p.dH, p.dfc, log_c + k, (long long)K, p.vbuf, p.vcap);
+    TTG_LAUNCH_CHECK("sum_kernel");
+    TT_TRY((round_launch<T, Acc>(p.shH, rh, eps, maxcap, st)));
+    TT_TRY(launch_moments<T>(B, p.dP, p.dfc, p.lmass, 1, mean ? mean + (long long)k * d : nullptr, (long long)K * d,
+                             cov ? cov + (long long)k * d * d : nullptr, (long long)K * d * d, p.mscr, p.mspf,
+                             p.mrcap, st));
+    if (ranks_out) {
+      hipLaunchKernelGGL(record_ranks_kernel, dim3(cdiv(B, 64)), dim3(64), 0, st, p.dP, B,
+                         ranks_out + (long long)k * (d + 1), (long long)K * (d + 1));
+      TTG_LAUNCH_CHECK("record_ranks_kernel");
+    }
+  }
+  hipLaunchKernelGGL(loglik_kernel, dim3(cdiv(B, 64)), dim3(64), 0, st, log_c, K, k_begin + k_count, B, loglik);
+  TTG_LAUNCH_CHECK("loglik_kernel");
+  return TT_OK;
+}
+
+}  // namespace ttg
+
+extern "C" {
+
+size_t tt_filter_run_workspace(int32_t batch, const tt_filter_spec* specs, int32_t precision) {
+  Arena ar(nullptr, 0);
+  RunPlan p;
+  if (run_plan(batch, specs, nullptr, 0, precision, nullptr, ar, p) != TT_OK) return 0;
+  // the plan without kernels does not know the LDS need; the bytes are the same
+  return ar.used + 256;
+}
+
+tt_status tt_filter_run(int32_t batch, const tt_filter_spec* specs, const tt_train* kernels, int32_t n_kernels,
+                        const double* z_dev, int32_t zdim, int32_t K, int32_t k_begin, int32_t k_count,
+                        int32_t precision, double* loglik_dev,
+                        double* log_c_dev, double* log_mpred_dev, double* mean_dev, double* cov_dev,
+                        int32_t* ranks_dev, int32_t* status_dev, void* ws, size_t ws_bytes, void* stream) {
+  if (!kernels || n_kernels < 1 || !z_dev || K < 1 || zdim < 1 || !loglik_dev || !log_c_dev || !log_mpred_dev ||
+      !status_dev || !ws) {
+    set_error("tt_filter_run: null pointer or bad size");
+    return TT_ERR_ARG;
+  }
+  if (k_begin < 0 || k_count < 1 || k_begin + k_count > K) {
+    set_error("tt_filter_run: need 0 <= k_begin, k_count >= 1, k_begin + k_count <= K");
+    return TT_ERR_ARG;
+  }
+  if (cov_dev && !mean_dev) {
+    set_error("tt_filter_run: cov needs mean");
+    return TT_ERR_ARG;
+  }
+  for (int b = 0; b < batch; ++b) {
+    const int need = specs[b].meas.kind == 0 ? specs[b].grid.d : specs[b].grid.d - 1;
+    if (need > zdim) {
+      set_error("tt_filter_run: zdim %d smaller than the measurement size %d", zdim, need);
+      return TT_ERR_SHAPE;
+    }
+    if (specs[b].eps != specs[0].eps) {
+      set_error("tt_filter_run: all filters of a batch must share eps");
+      return TT_ERR_ARG;
+    }
+  }
+  Arena ar(ws, ws_bytes);
+  RunPlan p;
+  TT_TRY(run_plan(batch, specs, kernels, n_kernels, precision, status_dev, ar, p));
+  if (!ar.fits()) {
+    set_error("tt_filter_run: workspace too small (%zu < %zu)", ws_bytes, ar.used);
+    return TT_ERR_WORKSPACE;
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  TT_TRY(upload(p.dP, p.vP, st));
+  TT_TRY(upload(p.dX, p.vX, st));
+  TT_TRY(upload(p.dL, p.vL, st));
+  TT_TRY(upload(p.dH, p.vH, st));
+  TT_TRY(upload(p.dK, p.vK, st));
+  TT_TRY(upload(p.drs, p.vrs, st));
+  TT_TRY(upload(p.dfc, p.vfc, st));
+  if (precision == TT_F64)
+    return run_steps<double, AccDD>(p, batch, z_dev, zdim, K, k_begin, k_count, loglik_dev, log_c_dev, log_mpred_dev,
+                                    mean_dev, cov_dev, ranks_dev, specs, st);
+  return run_steps<float, AccD>(p, batch, z_dev, zdim, K, k_begin, k_count, loglik_dev, log_c_dev, log_mpred_dev,
+                                mean_dev, cov_dev, ranks_dev, specs, st);
+}
+
+}  // extern "C"
+
+extern "C" {
+
+void tt_profile_begin(int32_t class_mask) {
+  g_prof.clear();
+  g_pool_next = 0;
+  g_prof_mask = class_mask;
+}
+
+int32_t tt_profile_end(double* ms, int32_t* launches, int32_t nclass) {
+  for (int c = 0; c < nclass; ++c) {
+    if (ms) ms[c] = 0.0;
+    if (launches) launches[c] = 0;
+  }
+  for (const ProfRec& r : g_prof) {
+    if (hipEventSynchronize(r.b) != hipSuccess) {
+      set_error("tt_profile_end: event synchronisation failed");
+      g_prof_mask = 0;
+      return -1;
+    }
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) continue;
+    if (r.cls < nclass) {
+      if (ms) ms[r.cls] += t;
+      if (launches) launches[r.cls] += 1;
+    }
+  }
+  g_prof.clear();
+  g_prof_mask = 0;
+  return PC_N;
+}
+
+}  // extern "C"

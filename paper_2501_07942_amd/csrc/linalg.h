@@ -1,0 +1,499 @@
+// Batched small dense linear algebra used by TT rounding, TT-SVD and the
+// likelihood SVD.  Every kernel takes a functor that, given the filter index
+// b (blockIdx.z or blockIdx.x), reads that filter's current ranks from device
+// memory and returns the operand shapes and pointers; grids are sized from
+// capacities and surplus blocks exit at once.  This keeps every launch free
+// of host synchronisation.
+#pragma once
+
+#include "common.h"
+
+// ---------------------------------------------------------------------------
+// Gram matrix  G(a, b) = sum_t X(a, t) X(b, t),  a, b < M,  t < T
+// with X(a, t) = x[a*sa + t*st].  Split-K partials go to
+// out + (b*splits + s)*gcap*gcap*words; gram_reduce sums them into split 0
+// and mirrors the upper triangle.
+// ---------------------------------------------------------------------------
+struct GramArgs {
+  int M, T;
+  const void* x;
+  long long sa, st;
+  double* out;  // partials base for this filter
+  int gcap, splits;  // splits = plane capacity on input
+};
+
+// split count used for a summation of length T with `planes` planes
+__device__ inline int gram_split_count(int T, int planes) {
+  const int s = (T + 2047) / 2048;
+  return max(1, min(s, planes));
+}
+
+template <typename TB, typename Acc, typename F>
+__global__ void __launch_bounds__(256) gram_partial_kernel(F f) {
+  constexpr int TS = 32;
+  const int b = blockIdx.z;
+  GramArgs g;
+  if (!f(b, g)) return;
+  g.splits = gram_split_count(g.T, g.splits);
+  // upper-triangular tile pair from blockIdx.x
+  const int ntile = (g.M + TS - 1) / TS;
+  int tp = blockIdx.x, ti = 0;
+  while (ti < ntile && tp >= ntile - ti) {
+    tp -= ntile - ti;
+    ++ti;
+  }
+  if (ti >= ntile) return;
+  const int tj = ti + tp;
+  const int s = blockIdx.y;
+  if (s >= g.splits) return;
+  const int chunk = (g.T + g.splits - 1) / g.splits;
+  const int t_begin = s * chunk, t_end = min(g.T, t_begin + chunk);
+
+  __shared__ double As[TS][TS + 1];
+  __shared__ double Bs[TS][TS + 1];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  typename Acc::V acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = Acc::zero();
+  const TB* x = reinterpret_cast<const TB*>(g.x);
+  const bool t_fast = (g.st == 1);
+  const int a0 = ti * TS, b0 = tj * TS;
+  for (int t0 = t_begin; t0 < t_end; t0 += TS) {
+    for (int e = threadIdx.x; e < TS * TS; e += blockDim.x) {
+      int r, c;  // r = vector index within tile, c = summation index within chunk
+      if (t_fast) {
+        r = e / TS;
+        c = e % TS;
+      } else {
+        c = e / TS;
+        r = e % TS;
+      }
+      const int t = t0 + c;
+      double va = 0.0, vb = 0.0;
+      if (t < t_end) {
+        if (a0 + r < g.M) va = bulk_to_double(x[(long long)(a0 + r) * g.sa + (long long)t * g.st]);
+        if (b0 + r < g.M) vb = bulk_to_double(x[(long long)(b0 + r) * g.sa + (long long)t * g.st]);
+      }
+      As[r][c] = va;
+      Bs[r][c] = vb;
+    }
+    __syncthreads();
+    const int kmax = min(TS, t_end - t0);
+    for (int c = 0; c < kmax; ++c) {
+      const double a_0 = As[ty * 2 + 0][c], a_1 = As[ty * 2 + 1][c];
+      const double b_0 = Bs[tx * 2 + 0][c], b_1 = Bs[tx * 2 + 1][c];
+      acc[0][0] = Acc::fma_(acc[0][0], a_0, b_0);
+      acc[0][1] = Acc::fma_(acc[0][1], a_0, b_1);
+      acc[1][0] = Acc::fma_(acc[1][0], a_1, b_0);
+      acc[1][1] = Acc::fma_(acc[1][1], a_1, b_1);
+    }
+    __syncthreads();
+  }
+  double* out = g.out + (long long)s * g.gcap * g.gcap * Acc::words;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int a = a0 + ty * 2 + i, bb = b0 + tx * 2 + j;
+      if (a < g.M && bb < g.M) Acc::store(out, (long long)a * g.gcap + bb, acc[i][j]);
+    }
+}
+
+template <typename Acc, typename F>
+__global__ void __launch_bounds__(256) gram_reduce_kernel(F f) {
+  const int b = blockIdx.z;
+  GramArgs g;
+  if (!f(b, g)) return;
+  g.splits = gram_split_count(g.T, g.splits);
+  const long long mm = (long long)g.M * g.M;
+  const long long plane = (long long)g.gcap * g.gcap;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < mm;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int a = (int)(e / g.M), c = (int)(e % g.M);
+    if (a > c) continue;
+    typename Acc::V s = Acc::load(g.out, (long long)a * g.gcap + c);
+    for (int sp = 1; sp < g.splits; ++sp)
+      s = Acc::add(s, Acc::load(g.out + sp * plane * Acc::words, (long long)a * g.gcap + c));
+    Acc::store(g.out, (long long)a * g.gcap + c, s);
+    Acc::store(g.out, (long long)c * g.gcap + a, s);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pivoted Cholesky  G ~= P L L^T P^T  with diagonal pivoting, stopped when
+// the largest remaining Schur diagonal is <= tau2 * trace(G) or when rmax
+// columns exist.  One workgroup per filter.  The factor is kept in the
+// accumulator precision (lwork, column-major gcap x rmax) and rounded to FP64
+// into lfac (row-major, rows in the ORIGINAL order, so that rows piv[0..r)
+// form a lower-triangular r x r block).  Writes *rank_out and the residual
+// trace of the remaining Schur complement.
+// ---------------------------------------------------------------------------
+struct PcholArgs {
+  int M;                // dimension of G
+  const double* g;      // G (accumulator type), ld gcap
+  double* lwork;        // accumulator-type factor, column-major ld gcap
+  double* lfac;         // FP64 factor, row-major ld gcap
+  int* piv;             // pivots
+  int* rank_out;        // where the rank is written
+  double* resid_out;    // residual trace
+  int* status;          // filter status (capacity overflow)
+  int gcap;
+  int rmax;             // rank capacity
+  double tau2;          // relative threshold on the Schur diagonal
+};
+
+template <typename Acc, typename F>
+__global__ void __launch_bounds__(256) pchol_kernel(F f) {
+  const int b = blockIdx.x;
+  PcholArgs p;
+  if (!f(b, p)) return;
+  using V = typename Acc::V;
+  extern __shared__ double smem[];
+  // layout: diag (M V) | lp (rmax V) | flags (M int) | red
+  const int jmax = min(p.M, p.rmax);
+  V* diag = reinterpret_cast<V*>(smem);
+  V* lp = diag + p.M;                           // jmax entries
+  int* done = reinterpret_cast<int*>(lp + jmax);  // M entries
+  __shared__ double red_v[8];
+  __shared__ int red_i[8];
+  __shared__ int s_piv;
+  __shared__ double s_trace;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  double tr_part = 0.0;
+  for (int i = tid; i < p.M; i += nt) {
+    diag[i] = Acc::load(p.g, (long long)i * p.gcap + i);
+    done[i] = 0;
+    tr_part += Acc::hi(diag[i]);
+  }
+  __syncthreads();
+  {
+    double t = block_sum(tr_part, red_v);
+    if (tid == 0) s_trace = t;
+  }
+  __syncthreads();
+  const double thr = p.tau2 * s_trace;
+  const bool bad = !(s_trace == s_trace) || s_trace > 1.7e308;
+  int j = 0;
+  for (; j < jmax; ++j) {
+    // argmax of the remaining diagonal
+    double bv = -1.0;
+    int bi = -1;
+    for (int i = tid; i < p.M; i += nt) {
+      if (!done[i]) {
+        const double v = Acc::hi(diag[i]);
+        if (v > bv || (v == bv && bi >= 0 && i < bi)) {
+          bv = v;
+          bi = i;
+        }
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_xor(bv, o, 64);
+      const int oi = __shfl_xor(bi, o, 64);
+      if (ov > bv || (ov == bv && oi >= 0 && (bi < 0 || oi < bi))) {
+        bv = ov;
+        bi = oi;
+      }
+    }
+    if ((tid & 63) == 0) {
+      red_v[tid >> 6] = bv;
+      red_i[tid >> 6] = bi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double v = red_v[0];
+      int ii = red_i[0];
+      for (int w = 1; w < (nt + 63) / 64; ++w)
+        if (red_v[w] > v || (red_v[w] == v && red_i[w] >= 0 && (ii < 0 || red_i[w] < ii))) {
+          v = red_v[w];
+          ii = red_i[w];
+        }
+      // stop when nothing is left above the threshold; the first column is
+      // always produced (a zero or non-finite matrix gets a unit pivot)
+      if (j == 0)
+        s_piv = (ii >= 0 && !bad && v > 0.0) ? ii : -2 - (ii < 0 ? 0 : ii);
+      else
+        s_piv = (ii < 0 || bad || !(v > thr)) ? -1 : ii;
+    }
+    __syncthreads();
+    int pv = s_piv;
+    if (pv == -1) break;
+    const bool zero_col = pv <= -2;
+    if (zero_col) pv = -2 - pv;
+    const V lpp = zero_col ? Acc::from(1.0) : Acc::sqrt_(diag[pv]);
+    // cache row pv of the factor
+    for (int t = tid; t < j; t += nt) lp[t] = Acc::load(p.lwork, (long long)t * p.gcap + pv);
+    __syncthreads();
+    for (int i = tid; i < p.M; i += nt) {
+      V l;
+      if (i == pv) {
+        l = lpp;
+      } else if (done[i] || zero_col) {
+        l = Acc::zero();
+      } else {
+        V s = Acc::load(p.g, (long long)i * p.gcap + pv);
+        for (int t = 0; t < j; ++t)
+          s = Acc::sub(s, Acc::mul(Acc::load(p.lwork, (long long)t * p.gcap + i), lp[t]));
+        l = Acc::div(s, lpp);
+        diag[i] = Acc::sub(diag[i], Acc::mul(l, l));
+      }
+      Acc::store(p.lwork, (long long)j * p.gcap + i, l);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      p.piv[j] = pv;
+      done[pv] = 1;
+      diag[pv] = Acc::zero();
+    }
+    __syncthreads();
+    if (zero_col) {
+      ++j;
+      break;
+    }
+  }
+  const int rank = j;
+  // residual: trace of the remaining Schur complement
+  double rp = 0.0;
+  for (int i = tid; i < p.M; i += nt)
+    if (!done[i]) rp += fmax(Acc::hi(diag[i]), 0.0);
+  const double resid = block_sum(rp, red_v);
+  if (tid == 0) {
+    *p.rank_out = rank;
+    if (p.resid_out) *p.resid_out = resid;
+    if (rank == jmax && jmax < p.M && resid > thr && p.status) atomicOr(p.status, TT_STATUS_CAPACITY);
+    if (bad && p.status) atomicOr(p.status, TT_STATUS_NONFINITE);
+  }
+  // FP64 row-major copy, zero beyond the rank
+  for (long long e = tid; e < (long long)p.M * rank; e += nt) {
+    const int i = (int)(e / rank), t = (int)(e % rank);
+    p.lfac[(long long)i * p.gcap + t] = Acc::hi(Acc::load(p.lwork, (long long)t * p.gcap + i));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// One-sided Jacobi (Hestenes) on the columns of an FP64 matrix X (rows x
+// ncols, read row-major from x with leading dimension ldx).  Rotations are
+// applied until every column pair is orthogonal to relative tolerance 1e-15;
+// the pair order is a round-robin tournament so that the pairs of one round
+// are disjoint and run in parallel, one per wavefront.  Outputs the column
+// norms (singular values) in descending order and the correspondingly
+// permuted columns sigma_j * u_j (column-major in usv, ld gcap).
+// ---------------------------------------------------------------------------
+struct JacobiArgs {
+  int rows, ncols;
+  const double* x;  // row-major input
+  long long ldx;
+  double* work;     // column-major scratch, ld gcap
+  double* sigma;    // out, descending
+  double* usv;      // out, column-major, ld gcap
+  int* ncols_out;   // nullable: number of columns written
+  int gcap;
+};
+
+template <typename F>
+__global__ void __launch_bounds__(512) jacobi_kernel(F f) {
+  const int b = blockIdx.x;
+  JacobiArgs J;
+  if (!f(b, J)) return;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, nw = blockDim.x >> 6;
+  const int rows = J.rows, nc = J.ncols;
+  double* W = J.work;
+  for (long long e = tid; e < (long long)rows * nc; e += blockDim.x) {
+    const int i = (int)(e / nc), c = (int)(e % nc);
+    W[(long long)c * J.gcap + i] = J.x[(long long)i * J.ldx + c];
+  }
+  __shared__ int s_rot;
+  __shared__ double s_sig[1024];
+  __syncthreads();
+  const int n = (nc + 1) & ~1;  // even number of players (one may be a dummy)
+  for (int sweep = 0; sweep < 60 && n >= 2; ++sweep) {
+    if (tid == 0) s_rot = 0;
+    __syncthreads();
+    for (int r = 0; r < n - 1; ++r) {
+      for (int i = wid; i < n / 2; i += nw) {
+        int pc, qc;
+        if (i == 0) {
+          pc = n - 1;
+          qc = r;
+        } else {
+          pc = (r + i) % (n - 1);
+          qc = (r - i + (n - 1)) % (n - 1);
+        }
+        if (pc >= nc || qc >= nc) continue;
+        double* xp = W + (long long)pc * J.gcap;
+        double* xq = W + (long long)qc * J.gcap;
+        double al = 0.0, be = 0.0, ga = 0.0;
+        for (int k = lane; k < rows; k += 64) {
+          const double u = xp[k], v = xq[k];
+          al = __fma_rn(u, u, al);
+          be = __fma_rn(v, v, be);
+          ga = __fma_rn(u, v, ga);
+        }
+        al = wave_sum(al);
+        be = wave_sum(be);
+        ga = wave_sum(ga);
+        if (ga != 0.0 && fabs(ga) > 1e-15 * sqrt(al * be)) {
+          const double zeta = (be - al) / (2.0 * ga);
+          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+          for (int k = lane; k < rows; k += 64) {
+            const double u = xp[k], v = xq[k];
+            xp[k] = cs * u - sn * v;
+            xq[k] = sn * u + cs * v;
+          }
+          if (lane == 0) s_rot = 1;
+        }
+      }
+      __syncthreads();
+    }
+    const int any = s_rot;
+    __syncthreads();
+    if (!any) break;
+  }
+  // column norms
+  for (int c = wid; c < nc; c += nw) {
+    const double* xc = W + (long long)c * J.gcap;
+    double s = 0.0;
+    for (int k = lane; k < rows; k += 64) s = __fma_rn(xc[k], xc[k], s);
+    s = wave_sum(s);
+    if (lane == 0) s_sig[c] = sqrt(s);
+  }
+  __syncthreads();
+  // rank of each column in descending order (ties by index)
+  for (int c = wid; c < nc; c += nw) {
+    const double sc = s_sig[c];
+    int rk = 0;
+    for (int o = lane; o < nc; o += 64) {
+      const double so = s_sig[o];
+      rk += (so > sc || (so == sc && o < c)) ? 1 : 0;
+    }
+    for (int o = 32; o > 0; o >>= 1) rk += __shfl_xor(rk, o, 64);
+    if (lane == 0) J.sigma[rk] = sc;
+    const double* xc = W + (long long)c * J.gcap;
+    double* dst = J.usv + (long long)rk * J.gcap;
+    for (int k = lane; k < rows; k += 64) dst[k] = xc[k];
+  }
+  if (tid == 0 && J.ncols_out) *J.ncols_out = nc;
+}
+
+// ---------------------------------------------------------------------------
+// Q(j, c) = [L11^{-1} Z(piv, :)](j, c) by forward substitution, one column c
+// per lane, partial solutions kept in FP64 shared memory.  L11(j, t) =
+// lfac[piv[j]*gcap + t].  Z rows are read with stride ldz, Q rows written with
+// stride ldq.
+// ---------------------------------------------------------------------------
+struct TrsmArgs {
+  int r, m;
+  const double* lfac;
+  const int* piv;
+  int gcap;
+  const void* z;
+  long long ldz;
+  void* q;
+  long long ldq;
+};
+
+template <typename TZ, typename TQ, typename F>
+__global__ void __launch_bounds__(64) trsm_kernel(F f, int rcap) {
+  const int b = blockIdx.z;
+  TrsmArgs a;
+  if (!f(b, a)) return;
+  const int c = blockIdx.x * 64 + threadIdx.x;
+  if (blockIdx.x * 64 >= a.m) return;
+  extern __shared__ double qs[];  // rcap x 64
+  const TZ* z = reinterpret_cast<const TZ*>(a.z);
+  TQ* q = reinterpret_cast<TQ*>(a.q);
+  const bool live = c < a.m;
+  for (int j = 0; j < a.r; ++j) {
+    const double* lrow = a.lfac + (long long)a.piv[j] * a.gcap;
+    double s = live ? bulk_to_double(z[(long long)a.piv[j] * a.ldz + c]) : 0.0;
+    for (int t = 0; t < j; ++t) s = __fma_rn(-lrow[t], qs[t * 64 + threadIdx.x], s);
+    const double v = s / lrow[j];
+    qs[j * 64 + threadIdx.x] = v;
+    if (live) q[(long long)j * a.ldq + c] = from_double<TQ>(v);
+  }
+  (void)rcap;
+}
+
+// ---------------------------------------------------------------------------
+// Generic batched GEMM  C(m, n) = sum_k A(m, k) B(k, n), strided operands,
+// 64x64 output tiles, 16-wide k steps, 256 threads with 4x4 outputs each.
+// ---------------------------------------------------------------------------
+struct GemmArgs {
+  int M, N, K;
+  const void* a;
+  long long sam, sak;
+  const void* b;
+  long long sbk, sbn;
+  void* c;
+  long long scm, scn;
+};
+
+template <typename TA, typename TB, typename TC, typename TAcc, typename F>
+__global__ void __launch_bounds__(256) gemm_kernel(F f) {
+  const int bz = blockIdx.z;
+  GemmArgs g;
+  if (!f(bz, g)) return;
+  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  if (m0 >= g.M || n0 >= g.N) return;
+  __shared__ TAcc As[16][64 + 1];
+  __shared__ TAcc Bs[16][64 + 1];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  TAcc acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = (TAcc)0;
+  const TA* A = reinterpret_cast<const TA*>(g.a);
+  const TB* B = reinterpret_cast<const TB*>(g.b);
+  const bool a_kfast = (g.sak == 1);
+  const bool b_nfast = (g.sbn == 1);
+  for (int k0 = 0; k0 < g.K; k0 += 16) {
+    for (int e = threadIdx.x; e < 64 * 16; e += 256) {
+      int mm, kk;
+      if (a_kfast) {
+        mm = e >> 4;
+        kk = e & 15;
+      } else {
+        kk = e >> 6;
+        mm = e & 63;
+      }
+      const int m = m0 + mm, k = k0 + kk;
+      As[kk][mm] = (m < g.M && k < g.K) ? (TAcc)A[(long long)m * g.sam + (long long)k * g.sak] : (TAcc)0;
+      int nn, kb;
+      if (b_nfast) {
+        kb = e >> 6;
+        nn = e & 63;
+      } else {
+        nn = e >> 4;
+        kb = e & 15;
+      }
+      const int n = n0 + nn, k2 = k0 + kb;
+      Bs[kb][nn] = (n < g.N && k2 < g.K) ? (TAcc)B[(long long)k2 * g.sbk + (long long)n * g.sbn] : (TAcc)0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      TAcc av[4], bv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) av[i] = As[kk][ty * 4 + i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bv[j] = Bs[kk][tx * 4 + j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] += av[i] * bv[j];
+    }
+    __syncthreads();
+  }
+  TC* C = reinterpret_cast<TC*>(g.c);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int m = m0 + ty * 4 + i, n = n0 + tx * 4 + j;
+      if (m < g.M && n < g.N) C[(long long)m * g.scm + (long long)n * g.scn] = (TC)acc[i][j];
+    }
+}

@@ -1,0 +1,544 @@
+// Kernels of the TT filter step that are not generic linear algebra:
+// prediction by per-core convolution, Hadamard update, likelihood build,
+// contractions for mass/normaliser/moments, prior and transition kernel.
+#pragma once
+
+#include "common.h"
+
+// Per-filter constants of the grid and the measurement model.
+struct FilterConst {
+  int d;
+  int n[TT_MAXD];
+  double lo[TT_MAXD];
+  double dx[TT_MAXD];
+  double logdelta;
+  int meas_kind;
+  double sensor[2];
+  double sigma_r, sigma_lin, lik_tol;
+  int lik_max_rank;
+  double m0[TT_MAXD], p0[TT_MAXD];
+};
+
+// ---------------------------------------------------------------------------
+// Prediction: C_k(a*rp0+b, i, a2*rp1+b2) = sum_m K_k(a, m+h, a2) P_k(b, i-m, b2)
+// (linear convolution cropped to the grid, P = 0 off the grid).
+// grid.x = left pair (a, b), grid.y = core k, grid.z = filter.
+// Each thread produces CONV_ROWS consecutive outputs along i of one column;
+// the P fibre of row b (zero padded) and the kernel slice of row a sit in
+// LDS, and taps are consumed in blocks of 8 from a register window.
+// ---------------------------------------------------------------------------
+#define CONV_ROWS 16
+#define CONV_TB 8
+
+template <typename T>
+__global__ void __launch_bounds__(256) conv_kernel(const DevTT* __restrict__ kern,
+                                                   const DevTT* __restrict__ pin,
+                                                   const DevTT* __restrict__ xout) {
+  const int f = blockIdx.z, k = blockIdx.y;
+  const DevTT& K = kern[f];
+  const DevTT& P = pin[f];
+  const DevTT& X = xout[f];
+  if (k >= P.d) return;
+  const int rk0 = K.ranks[k], rk1 = K.ranks[k + 1];
+  const int rp0 = P.ranks[k], rp1 = P.ranks[k + 1];
+  const int R0 = rk0 * rp0, R1 = rk1 * rp1;
+  if ((int)blockIdx.x >= R0) return;
+  if (R0 > X.cap[k] || R1 > X.cap[k + 1]) return;  // capacity flagged at init
+  const int a = blockIdx.x / rp0, b = blockIdx.x % rp0;
+  const int n = P.n[k];
+  const int taps = K.n[k];
+  const int h = (taps - 1) / 2;
+  const int taps_pad = (taps + CONV_TB - 1) / CONV_TB * CONV_TB;
+  const int front = CONV_TB;                       // extra zeros before P
+  const int plen = front + n + 2 * h + CONV_ROWS;  // padded fibre length
+  extern __shared__ unsigned char smem_raw[];
+  T* Ks = reinterpret_cast<T*>(smem_raw);  // [taps_pad][rk1]
+  T* Ps = Ks + taps_pad * rk1;             // [plen][rp1]
+  const T* kc = core_ptr<T>(K, k) + (long long)a * taps * rk1;
+  const T* pc = core_ptr<T>(P, k) + (long long)b * n * rp1;
+  for (int e = threadIdx.x; e < taps_pad * rk1; e += blockDim.x)
+    Ks[e] = (e < taps * rk1) ? kc[e] : (T)0;
+  for (int e = threadIdx.x; e < plen * rp1; e += blockDim.x) {
+    const int row = e / rp1 - front - h;  // grid index of this padded row
+    Ps[e] = (row >= 0 && row < n) ? pc[(long long)row * rp1 + (e % rp1)] : (T)0;
+  }
+  __syncthreads();
+  T* xc = core_ptr<T>(X, k) + (long long)blockIdx.x * n * R1;
+  const int nblk = (n + CONV_ROWS - 1) / CONV_ROWS;
+  const int tasks = R1 * nblk;
+  for (int t = threadIdx.x; t < tasks; t += blockDim.x) {
+    const int j = t % R1, blk = t / R1;
+    const int a2 = j / rp1, b2 = j % rp1;
+    const int i0 = blk * CONV_ROWS;
+    T acc[CONV_ROWS];
+#pragma unroll
+    for (int r = 0; r < CONV_ROWS; ++r) acc[r] = (T)0;
+    // output i uses Ppad[front + i + 2h - tm] for tap tm (offset m = tm - h)
+    for (int tm0 = 0; tm0 < taps_pad; tm0 += CONV_TB) {
+      T kv[CONV_TB];
+#pragma unroll
+      for (int u = 0; u < CONV_TB; ++u) kv[u] = Ks[(tm0 + u) * rk1 + a2];
+      // window w[v] = Ppad[base + v], base = front + i0 + 2h - tm0 - (TB-1)
+      const int base = front + i0 + 2 * h - tm0 - (CONV_TB - 1);
+      T w[CONV_ROWS + CONV_TB - 1];
+#pragma unroll
+      for (int v = 0; v < CONV_ROWS + CONV_TB - 1; ++v) w[v] = Ps[(base + v) * rp1 + b2];
+#pragma unroll
+      for (int u = 0; u < CONV_TB; ++u)
+#pragma unroll
+        for (int r = 0; r < CONV_ROWS; ++r) acc[r] += kv[u] * w[r - u + CONV_TB - 1];
+    }
+#pragma unroll
+    for (int r = 0; r < CONV_ROWS; ++r) {
+      const int i = i0 + r;
+      if (i < n) xc[(long long)i * R1 + j] = acc[r];
+    }
+  }
+}
+
+// ranks/log-scale/status of a product TT (convolution or Hadamard):
+// out.ranks = A.ranks * B.ranks, log_scale = sum; capacity overflow flagged.
+__global__ void product_init_kernel(const DevTT* __restrict__ A, const DevTT* __restrict__ B,
+                                    const DevTT* __restrict__ O, int nf) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nf) return;
+  const DevTT &a = A[f], &b = B[f], &o = O[f];
+  int bad = 0;
+  for (int j = 0; j <= o.d; ++j) {
+    int r = a.ranks[j] * b.ranks[j];
+    if (r > o.cap[j]) {
+      bad = 1;
+      r = o.cap[j];  // keep every later read inside the reserved storage
+    }
+    o.ranks[j] = r;
+  }
+  *o.log_scale = *a.log_scale + *b.log_scale;
+  int st = *b.status;
+  if (bad) st |= TT_STATUS_CAPACITY;
+  *o.status = st;
+}
+
+// ---------------------------------------------------------------------------
+// Hadamard: H_k(a*rp0+b, i, a2*rp1+b2) = L_k(a, i, a2) * P_k(b, i, b2)
+// (Kronecker product of the core slices).  L is FP64, P and H bulk type.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) hadamard_kernel(const DevTT* __restrict__ lik,
+                                                       const DevTT* __restrict__ pin,
+                                                       const DevTT* __restrict__ hout) {
+  const int f = blockIdx.z, k = blockIdx.y;
+  const DevTT &L = lik[f], &P = pin[f], &H = hout[f];
+  if (k >= P.d) return;
+  const int rl0 = L.ranks[k], rl1 = L.ranks[k + 1];
+  const int rp0 = P.ranks[k], rp1 = P.ranks[k + 1];
+  const int R0 = rl0 * rp0, R1 = rl1 * rp1;
+  if ((int)blockIdx.x >= R0) return;
+  if (R0 > H.cap[k] || R1 > H.cap[k + 1]) return;
+  const int a = blockIdx.x / rp0, b = blockIdx.x % rp0;
+  const int n = P.n[k];
+  const double* lc = core_ptr<double>(L, k) + (long long)a * n * rl1;
+  const T* pc = core_ptr<T>(P, k) + (long long)b * n * rp1;
+  T* hc = core_ptr<T>(H, k) + (long long)blockIdx.x * n * R1;
+  const long long tot = (long long)n * R1;
+  for (long long e = threadIdx.x; e < tot; e += blockDim.x) {
+    const int i = (int)(e / R1), j = (int)(e % R1);
+    const int a2 = j / rp1, b2 = j % rp1;
+    hc[e] = from_double<T>(lc[(long long)i * rl1 + a2] * bulk_to_double(pc[(long long)i * rp1 + b2]));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// sum of all entries: v <- v * (sum_i A_k(:, i, :)) core by core, FP64.
+// One workgroup per filter.  Writes log(sum) + logdelta + log_scale to
+// out[f*stride] (NaN and a status bit when the sum is not positive/finite).
+// Deterministic: fixed-order partial sums.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) sum_kernel(const DevTT* __restrict__ tt,
+                                                  const FilterConst* __restrict__ fc,
+                                                  double* __restrict__ out, long long stride,
+                                                  double* __restrict__ vbuf, int vcap) {
+  const int f = blockIdx.x;
+  const DevTT& A = tt[f];
+  double* v = vbuf + (long long)f * 2 * vcap;
+  double* vn = v + vcap;
+  __shared__ double part[256];
+  const int tid = threadIdx.x;
+  if (tid == 0) v[0] = 1.0;
+  __syncthreads();
+  for (int k = 0; k < A.d; ++k) {
+    const int r0 = A.ranks[k], r1 = A.ranks[k + 1], n = A.n[k];
+    const T* c = core_ptr<T>(A, k);
+    for (int j0 = 0; j0 < r1; j0 += 256) {
+      const int jc = min(256, r1 - j0);
+      const int groups = max(1, 256 / jc);
+      const int g = tid / jc, j = j0 + tid % jc;
+      double s = 0.0;
+      if (g < groups && tid < groups * jc) {
+        for (long long q = g; q < (long long)r0 * n; q += groups) {
+          const int aa = (int)(q / n);
+          s += v[aa] * bulk_to_double(c[q * r1 + j]);
+        }
+      }
+      part[tid] = s;
+      __syncthreads();
+      if (tid < jc) {
+        double t = 0.0;
+        for (int gg = 0; gg < groups; ++gg) t += part[gg * jc + tid];
+        vn[j0 + tid] = t;
+      }
+      __syncthreads();
+    }
+    for (int j = tid; j < r1; j += 256) v[j] = vn[j];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const double s = v[0];
+    double r;
+    if (!(s == s) || fabs(s) > 1.7e308) {
+      r = __longlong_as_double(0x7ff8000000000000LL);
+      set_status(A.status, TT_STATUS_NONFINITE);
+    } else if (!(s > 0.0)) {
+      r = __longlong_as_double(0x7ff8000000000000LL);
+      set_status(A.status, TT_STATUS_NONPOSITIVE);
+    } else {
+      r = log(s) + fc[f].logdelta + *A.log_scale;
+    }
+    if (*A.status & (TT_STATUS_NONFINITE | TT_STATUS_NONPOSITIVE))
+      r = __longlong_as_double(0x7ff8000000000000LL);
+    out[f * stride] = r;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// normalisation and moments (one workgroup per filter).  Per core the
+// contractions S^v_k = sum_i v(i) A_k(:, i, :) for v in {1, xi, xi^2} go to
+// scratch; prefix/suffix chains then give mass, means and second moments.
+// log_scale is decreased by log(mass) so the TT integrates to one.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) moments_kernel(const DevTT* __restrict__ tt,
+                                                      const FilterConst* __restrict__ fc,
+                                                      double* __restrict__ log_mass, long long lm_stride,
+                                                      double* __restrict__ mean, long long mean_stride,
+                                                      double* __restrict__ cov, long long cov_stride,
+                                                      double* __restrict__ scratch, long long scr_per_filter,
+                                                      int rcap) {
+  const int f = blockIdx.x;
+  const DevTT& A = tt[f];
+  const FilterConst& C = fc[f];
+  const int d = A.d, tid = threadIdx.x;
+  const long long mat = (long long)rcap * rcap;
+  double* S = scratch + f * scr_per_filter;      // [3][d][rcap*rcap]
+  double* left = S + 3 * d * mat;                // [d+1][rcap]
+  double* right = left + (d + 1) * rcap;         // [d+1][rcap]
+  double* tmp = right + (d + 1) * rcap;          // [2][rcap]
+  const bool want = (mean != nullptr);
+  const int nv = want ? 3 : 1;
+  for (int k = 0; k < d; ++k) {
+    const int r0 = A.ranks[k], r1 = A.ranks[k + 1], n = A.n[k];
+    const T* c = core_ptr<T>(A, k);
+    for (int e = tid; e < nv * r0 * r1; e += blockDim.x) {
+      const int v = e / (r0 * r1), q = e % (r0 * r1);
+      const int a = q / r1, b = q % r1;
+      double s = 0.0;
+      for (int i = 0; i < n; ++i) {
+        const double x = C.lo[k] + i * C.dx[k];
+        const double w = (v == 0) ? 1.0 : (v == 1 ? x : x * x);
+        s += w * bulk_to_double(c[((long long)a * n + i) * r1 + b]);
+      }
+      S[(v * d + k) * mat + a * r1 + b] = s;
+    }
+  }
+  __syncthreads();
+  // prefix chains left[k] (1 x r_k) and suffix right[k] (r_k x 1) of S^1
+  if (tid == 0) left[0] = 1.0;
+  __syncthreads();
+  for (int k = 0; k < d; ++k) {
+    const int r0 = A.ranks[k], r1 = A.ranks[k + 1];
+    for (int b = tid; b < r1; b += blockDim.x) {
+      double s = 0.0;
+      for (int a = 0; a < r0; ++a) s += left[k * rcap + a] * S[(0 * d + k) * mat + a * r1 + b];
+      left[(k + 1) * rcap + b] = s;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) right[d * rcap] = 1.0;
+  __syncthreads();
+  for (int k = d - 1; k >= 0; --k) {
+    const int r0 = A.ranks[k], r1 = A.ranks[k + 1];
+    for (int a = tid; a < r0; a += blockDim.x) {
+      double s = 0.0;
+      for (int b = 0; b < r1; ++b) s += S[(0 * d + k) * mat + a * r1 + b] * right[(k + 1) * rcap + b];
+      right[k * rcap + a] = s;
+    }
+    __syncthreads();
+  }
+  const double total = left[d * rcap];
+  int st = *A.status;
+  if (!(total == total) || fabs(total) > 1.7e308) st |= TT_STATUS_NONFINITE;
+  else if (!(total > 0.0)) st |= TT_STATUS_NONPOSITIVE;
+  __syncthreads();
+  const double nan = __longlong_as_double(0x7ff8000000000000LL);
+  const bool ok = (st & (TT_STATUS_NONFINITE | TT_STATUS_NONPOSITIVE)) == 0;
+  if (tid == 0) {
+    const double lm = ok ? log(total) + C.logdelta + *A.log_scale : nan;
+    if (log_mass) log_mass[f * lm_stride] = lm;
+    if (ok) *A.log_scale -= lm;
+    if (st != *A.status) atomicOr(A.status, st);
+  }
+  if (!want) return;
+  // means and E[x_l^2]
+  for (int l = tid; l < d; l += blockDim.x) {
+    const int r0 = A.ranks[l], r1 = A.ranks[l + 1];
+    double m1 = 0.0, m2 = 0.0;
+    for (int a = 0; a < r0; ++a)
+      for (int b = 0; b < r1; ++b) {
+        const double lr = left[l * rcap + a] * right[(l + 1) * rcap + b];
+        m1 += lr * S[(1 * d + l) * mat + a * r1 + b];
+        m2 += lr * S[(2 * d + l) * mat + a * r1 + b];
+      }
+    m1 /= total;
+    m2 /= total;
+    mean[f * mean_stride + l] = ok ? m1 : nan;
+    if (cov) cov[f * cov_stride + l * d + l] = ok ? m2 - m1 * m1 : nan;
+  }
+  if (!cov) return;
+  __syncthreads();
+  // off-diagonal E[x_l x_j], l < j: w = left_l S^xi_l, then chain S^1 up to j
+  double* w = tmp;
+  double* w2 = tmp + rcap;
+  for (int l = 0; l < d - 1; ++l) {
+    {
+      const int r0 = A.ranks[l], r1 = A.ranks[l + 1];
+      for (int b = tid; b < r1; b += blockDim.x) {
+        double s = 0.0;
+        for (int a = 0; a < r0; ++a) s += left[l * rcap + a] * S[(1 * d + l) * mat + a * r1 + b];
+        w[b] = s;
+      }
+    }
+    __syncthreads();
+    for (int j = l + 1; j < d; ++j) {
+      const int r0 = A.ranks[j], r1 = A.ranks[j + 1];
+      if (tid == 0) {
+        double s = 0.0;
+        for (int a = 0; a < r0; ++a)
+          for (int b = 0; b < r1; ++b) s += w[a] * S[(1 * d + j) * mat + a * r1 + b] * right[(j + 1) * rcap + b];
+        const double m = mean[f * mean_stride + l], mj = mean[f * mean_stride + j];
+        const double cv = s / total - m * mj;
+        cov[f * cov_stride + l * d + j] = ok ? cv : nan;
+        cov[f * cov_stride + j * d + l] = ok ? cv : nan;
+      }
+      for (int b = tid; b < r1; b += blockDim.x) {
+        double s = 0.0;
+        for (int a = 0; a < r0; ++a) s += w[a] * S[(0 * d + j) * mat + a * r1 + b];
+        w2[b] = s;
+      }
+      __syncthreads();
+      for (int b = tid; b < r1; b += blockDim.x) w[b] = w2[b];
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// balance: scale the last core to unit Frobenius norm, log_scale += log(norm)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) balance_kernel(const DevTT* __restrict__ tt) {
+  const int f = blockIdx.x;
+  const DevTT& A = tt[f];
+  const int k = A.d - 1;
+  T* c = core_ptr<T>(A, k);
+  const long long tot = (long long)A.ranks[k] * A.n[k] * A.ranks[k + 1];
+  __shared__ double red[8];
+  double s = 0.0;
+  for (long long e = threadIdx.x; e < tot; e += blockDim.x) {
+    const double x = bulk_to_double(c[e]);
+    s += x * x;
+  }
+  s = block_sum(s, red);
+  const double nrm = sqrt(s);
+  if (!(nrm > 0.0) || !(nrm < 1.7e308)) {
+    if (threadIdx.x == 0) set_status(A.status, nrm == 0.0 ? TT_STATUS_NONPOSITIVE : TT_STATUS_NONFINITE);
+    return;
+  }
+  const double inv = 1.0 / nrm;
+  for (long long e = threadIdx.x; e < tot; e += blockDim.x) c[e] = from_double<T>(bulk_to_double(c[e]) * inv);
+  if (threadIdx.x == 0) *A.log_scale += log(nrm);
+}
+
+// ---------------------------------------------------------------------------
+// Gaussian prior with diagonal covariance: rank-one cores, each scaled to a
+// unit maximum, the shifts and normalising constants in log_scale.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) prior_kernel(const DevTT* __restrict__ tt,
+                                                    const FilterConst* __restrict__ fc) {
+  const int f = blockIdx.x;
+  const DevTT& A = tt[f];
+  const FilterConst& C = fc[f];
+  __shared__ double red[8];
+  double lsum = 0.0;
+  for (int k = 0; k < A.d; ++k) {
+    const int n = A.n[k];
+    double mx = -1e308;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      const double x = C.lo[k] + i * C.dx[k] - C.m0[k];
+      mx = fmax(mx, -0.5 * x * x / C.p0[k]);
+    }
+    // block max via negated sums is awkward; use shared reduction
+    __shared__ double smx[256];
+    smx[threadIdx.x] = mx;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+      if ((int)threadIdx.x < o) smx[threadIdx.x] = fmax(smx[threadIdx.x], smx[threadIdx.x + o]);
+      __syncthreads();
+    }
+    mx = smx[0];
+    __syncthreads();
+    T* c = core_ptr<T>(A, k);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      const double x = C.lo[k] + i * C.dx[k] - C.m0[k];
+      c[i] = from_double<T>(exp(-0.5 * x * x / C.p0[k] - mx));
+    }
+    lsum += mx - 0.5 * log(2.0 * M_PI * C.p0[k]);
+  }
+  (void)red;
+  if (threadIdx.x == 0) {
+    for (int j = 0; j <= A.d; ++j) A.ranks[j] = 1;
+    *A.log_scale = lsum;
+    *A.status = 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Likelihood, part 1 (one workgroup per filter): the linear axes become
+// rank-one cores exp(log N(z_j; xi, sigma_lin^2) - max); for the range model
+// the dense block M(i1, i2) = exp(log N(z_0; ||(xi_1, xi_2) - s||, sigma_r^2)
+// - max) is written row-major to mbuf.  All shifts and constants go to
+// log_scale.  Ranks are set to 1 everywhere (bond 1 is set by part 2).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) lik_dense_kernel(const DevTT* __restrict__ lik,
+                                                        const FilterConst* __restrict__ fc,
+                                                        const double* __restrict__ z, long long zstride,
+                                                        double* __restrict__ mbuf, long long mstride) {
+  const int f = blockIdx.x;
+  const DevTT& L = lik[f];
+  const FilterConst& C = fc[f];
+  const double* zf = z + f * zstride;
+  __shared__ double smx[256];
+  const int tid = threadIdx.x;
+  double lsum = 0.0;
+  const int first_lin = (C.meas_kind == 0) ? 0 : 2;
+  const double slin2 = C.sigma_lin * C.sigma_lin;
+  for (int k = first_lin; k < C.d; ++k) {
+    const double zk = zf[C.meas_kind == 0 ? k : k - 1];
+    const int n = C.n[k];
+    double mx = -1e308;
+    for (int i = tid; i < n; i += blockDim.x) {
+      const double e = zk - (C.lo[k] + i * C.dx[k]);
+      mx = fmax(mx, -0.5 * e * e / slin2);
+    }
+    smx[tid] = mx;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (tid < o) smx[tid] = fmax(smx[tid], smx[tid + o]);
+      __syncthreads();
+    }
+    mx = smx[0];
+    __syncthreads();
+    double* c = core_ptr<double>(L, k);
+    for (int i = tid; i < n; i += blockDim.x) {
+      const double e = zk - (C.lo[k] + i * C.dx[k]);
+      c[i] = exp(-0.5 * e * e / slin2 - mx);
+    }
+    lsum += mx - 0.5 * log(2.0 * M_PI * slin2);
+  }
+  if (C.meas_kind == 1) {
+    const int n0 = C.n[0], n1 = C.n[1];
+    const double sr2 = C.sigma_r * C.sigma_r;
+    double mx = -1e308;
+    for (int e = tid; e < n0 * n1; e += blockDim.x) {
+      const int i = e / n1, j = e % n1;
+      const double x1 = C.lo[0] + i * C.dx[0] - C.sensor[0];
+      const double x2 = C.lo[1] + j * C.dx[1] - C.sensor[1];
+      const double r = zf[0] - sqrt(x1 * x1 + x2 * x2);
+      mx = fmax(mx, -0.5 * r * r / sr2);
+    }
+    smx[tid] = mx;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (tid < o) smx[tid] = fmax(smx[tid], smx[tid + o]);
+      __syncthreads();
+    }
+    mx = smx[0];
+    __syncthreads();
+    double* m = mbuf + f * mstride;
+    for (int e = tid; e < n0 * n1; e += blockDim.x) {
+      const int i = e / n1, j = e % n1;
+      const double x1 = C.lo[0] + i * C.dx[0] - C.sensor[0];
+      const double x2 = C.lo[1] + j * C.dx[1] - C.sensor[1];
+      const double r = zf[0] - sqrt(x1 * x1 + x2 * x2);
+      m[e] = exp(-0.5 * r * r / sr2 - mx);
+    }
+    lsum += mx - 0.5 * log(2.0 * M_PI * sr2);
+  }
+  if (tid == 0) {
+    for (int j = 0; j <= C.d; ++j) L.ranks[j] = 1;
+    *L.log_scale = lsum;
+    if (!(lsum == lsum)) atomicOr(L.status, TT_STATUS_NONFINITE);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// dense transition kernel K(m) = c * exp(-0.5 y^T Q^{-1} y), y = Delta o m,
+// over the offset box (row-major, axis 0 slowest); c includes the Gaussian
+// constant and the cell volume.
+// ---------------------------------------------------------------------------
+struct KernelEvalArgs {
+  int d;
+  int taps[TT_MAXD];
+  double dx[TT_MAXD];
+  double qinv[64];
+  double cnorm;
+  long long total;
+};
+
+__global__ void __launch_bounds__(256) kernel_dense_kernel(KernelEvalArgs a, double* __restrict__ out) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < a.total;
+       e += (long long)gridDim.x * blockDim.x) {
+    double y[8];
+    long long rem = e;
+    for (int l = a.d - 1; l >= 0; --l) {
+      const int t = (int)(rem % a.taps[l]);
+      rem /= a.taps[l];
+      y[l] = (t - (a.taps[l] - 1) / 2) * a.dx[l];
+    }
+    double q = 0.0;
+    for (int l = 0; l < a.d; ++l)
+      for (int j = 0; j < a.d; ++j) q += y[l] * a.qinv[l * a.d + j] * y[j];
+    out[e] = a.cnorm * exp(-0.5 * q);
+  }
+}
+
+// copy cores of an FP64 TT into a TT of type T with the same ranks
+template <typename T>
+__global__ void __launch_bounds__(256) convert_tt_kernel(const DevTT* __restrict__ src,
+                                                         const DevTT* __restrict__ dst) {
+  const int f = blockIdx.y;
+  const DevTT &S = src[f], &D = dst[f];
+  for (int k = 0; k < S.d; ++k) {
+    const long long tot = (long long)S.ranks[k] * S.n[k] * S.ranks[k + 1];
+    const double* s = core_ptr<double>(S, k);
+    T* o = core_ptr<T>(D, k);
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < tot;
+         e += (long long)gridDim.x * blockDim.x)
+      o[e] = from_double<T>(s[e]);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    for (int j = 0; j <= S.d; ++j) D.ranks[j] = S.ranks[j];
+    *D.log_scale = *S.log_scale;
+    *D.status = *S.status;
+  }
+}

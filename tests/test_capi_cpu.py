@@ -1,0 +1,83 @@
+"""C ABI checks that need no GPU: the library loads, exports every symbol
+the header declares, and host-side validation rejects bad arguments before
+touching the device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ttgbf.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:size_t|tt_status|const char\*|void|int32_t)\s+(tt_\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for must in ("tt_kernel_build", "tt_predict", "tt_update", "tt_round", "tt_normalize_moments",
+                 "tt_filter_run"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2501_07942_amd import binding as B
+    lib = C.CDLL(B.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(B.EXPORTED) == set(declared_functions())
+
+
+def test_train_elems_and_version():
+    from paper_2501_07942_amd import binding as B
+    n = (C.c_int32 * 3)(4, 5, 6)
+    cap = (C.c_int32 * 4)(1, 2, 3, 1)
+    assert B.LIB.tt_train_elems(3, n, cap) == 1 * 4 * 2 + 2 * 5 * 3 + 3 * 6 * 1
+    assert B.LIB.tt_train_elems(0, n, cap) == 0
+    assert b"gfx950" in B.LIB.tt_version()
+
+
+def test_host_validation_rejects_before_launch():
+    from paper_2501_07942_amd import binding as B
+    # null arguments
+    st = B.LIB.tt_round(1, None, None, 1e-10, 4, None, 0, None)
+    assert st == B.ERR_ARG
+    assert b"null" in B.LIB.tt_last_error()
+    # malformed train: cap[0] != 1 is rejected by the workspace query
+    t = B.Train()
+    t.d = 2
+    t.n[0] = t.n[1] = 4
+    t.cap[0], t.cap[1], t.cap[2] = 2, 2, 1
+    t.dtype = B.F64
+    t.cores = t.ranks = t.log_scale = t.status = 1024  # never dereferenced on the host
+    arr = (B.Train * 1)(t)
+    assert B.LIB.tt_round_workspace(1, arr, arr) == 0
+    # eps < 0 rejected
+    t.cap[0] = 1
+    arr = (B.Train * 1)(t)
+    st = B.LIB.tt_round(1, arr, arr, -1.0, 4, C.c_void_p(4096), 1 << 20, None)
+    assert st == B.ERR_ARG
+    # workspace too small
+    need = B.LIB.tt_round_workspace(1, arr, arr)
+    assert need > 0
+    st = B.LIB.tt_round(1, arr, arr, 1e-10, 4, C.c_void_p(4096), 16, None)
+    assert st == B.ERR_WORKSPACE
+    # bad grid in kernel build
+    g = B.make_grid(2, [1, 4], [0, 0], [1, 1])
+    hw = (C.c_int32 * 2)(1, 1)
+    capa = (C.c_int32 * 3)(1, 2, 1)
+    assert B.LIB.tt_kernel_build_workspace(C.byref(g), hw, capa) == 0
+
+
+def test_filter_run_workspace_query():
+    from paper_2501_07942_amd import binding as B, runner, workload as wl
+    specs, _, _ = wl.make_batch("range4d", batch=2, steps=3, d=3, n=32, cap=8)
+    fs = runner.filter_specs(specs, [0, 0], 13, 64)
+    arr = (B.FilterSpec * 2)(*fs)
+    assert B.LIB.tt_filter_run_workspace(2, arr, B.F64) > 0
+    assert B.LIB.tt_filter_run_workspace(2, arr, 7) == 0
