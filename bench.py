@@ -34,10 +34,12 @@ def conv_bytes(ranks_prev, kranks, n, esz):
     """Algorithmic HBM bytes of one convolution launch for one filter:
     write the product cores, read the PMD and kernel cores once."""
     d = len(n)
-    kr = kranks
-    w = sum(kr[k] * ranks_prev[k] * n[k] * kr[k + 1] * ranks_prev[k + 1] for k in range(d))
-    rp = sum(ranks_prev[k] * n[k] * ranks_prev[k + 1] for k in range(d))
-    return (w + rp) * esz
+    kr = [int(x) for x in kranks]
+    rp_ = [int(x) for x in ranks_prev]
+    w = sum(kr[k] * rp_[k] * n[k] * kr[k + 1] * rp_[k + 1] for k in range(d))
+    rp = sum(rp_[k] * n[k] * rp_[k + 1] for k in range(d))
+    kb = sum(kr[k] * (2 * 12 + 1) * kr[k + 1] for k in range(d))
+    return (w + rp + kb) * esz
 
 
 def run_batch(B, runner, binding, wl, name, batch, steps, warmup, precision, profile_steps=0, seed=None):
@@ -76,13 +78,14 @@ def run_batch(B, runner, binding, wl, name, batch, steps, warmup, precision, pro
             "status": st, "total": total}
 
 
-def cpu_baseline(wl, steps=2):
+def cpu_baseline(wl, steps=2, warm=3):
     """The FP64 oracle on a bounded sample: one filter of the same workload,
-    `steps` full steps after step 0, on the host cores."""
+    `warm` untimed full steps after step 0 (ranks reach the cap), then
+    `steps` timed full steps, on the host cores."""
     import numpy as np
     from oracle import model as mdl
     from oracle import tt as ttm
-    specs, xs, zs = wl.make_batch("range6d_n128_c16", batch=1, steps=1 + steps)
+    specs, xs, zs = wl.make_batch("range6d_n128_c16", batch=1, steps=1 + warm + steps)
     s, z = specs[0], zs[0]
     axes = mdl.grid_axes(s.lo, s.hi, [s.n] * s.d)
     hw = s.halfwidths()
@@ -95,7 +98,9 @@ def cpu_baseline(wl, steps=2):
     p = ttm.tt_round(ttm.hadamard(lik, p), s.eps, s.cap)
     p = ttm.scale(p, 1.0 / (ttm.tt_sum(p) * delta))
     t0 = time.time()
-    for k in range(1, 1 + steps):
+    for k in range(1, 1 + warm + steps):
+        if k == 1 + warm:
+            t0 = time.time()
         c = ttm.conv(kern, p, hw)
         p = ttm.tt_round(c, s.eps, s.cap)
         p = ttm.scale(p, 1.0 / (ttm.tt_sum(p) * delta))
@@ -113,14 +118,16 @@ def cpu_baseline(wl, steps=2):
     if thr:
         cores = min(cores, int(thr))
     return {"value": steps / dt, "unit": "filter-steps/s", "cores": cores, "kind": "oracle",
-            "sample": f"1 filter x {steps} full steps of d=6 N=128 cap16 (FP64 NumPy oracle), {dt:.1f}s"}
+            "sample": f"1 filter x {steps} full steps (steps {1 + warm}..{warm + steps}, ranks at the cap) of "
+                      f"d=6 N=128 cap16, FP64 NumPy oracle, {dt:.1f}s",
+            "ranks": [int(r) for r in ttm.ranks(p)]}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=6)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=6)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--workload", default="range6d_n128_c16")
     ap.add_argument("--no-plain", action="store_true", help="skip the FP64 single-filter comparator")
@@ -187,9 +194,9 @@ def main():
         "kernel_ms_per_step": kernel_ms,
     }
     if not args.no_plain:
-        plain = run_batch(None, runner, binding, wl, args.workload, 1, 3, 1, binding.F64)
-        out["fp64_plain"] = {"value": round(3 / (plain["ms"] / 1000.0), 3), "unit": "filter-steps/s",
-                             "ms_per_step": round(plain["ms"] / 3, 3), "filters": 1,
+        plain = run_batch(None, runner, binding, wl, args.workload, 1, args.steps, args.warmup, binding.F64)
+        out["fp64_plain"] = {"value": round(args.steps / (plain["ms"] / 1000.0), 3), "unit": "filter-steps/s",
+                             "ms_per_step": round(plain["ms"] / args.steps, 3), "filters": 1,
                              "failed_filters": int((plain["status"] != 0).sum())}
         out["fp32_batch_over_fp64_plain"] = round(value / out["fp64_plain"]["value"], 2)
     if not args.no_cpu:

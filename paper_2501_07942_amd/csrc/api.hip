@@ -656,11 +656,15 @@ static tt_status launch_pchol(F f, int B, int gcap, hipStream_t st) {
 template <typename T, typename Acc, typename F>
 static tt_status launch_gram(F f, int B, int Mcap, long long Tcap, int smax, hipStream_t st) {
   ProfScope ps_(PC_GRAM, st);
-  const int pairs = gram_tiles(Mcap);
-  const int splits = choose_splits(pairs, B, Tcap, smax);
-  (void)splits;
-  // the split count actually used is the one stored in the scratch (smax)
-  hipLaunchKernelGGL((gram_partial_kernel<T, Acc, F>), dim3(pairs, smax, B), dim3(256), 0, st, f);
+  (void)Tcap;
+  // the split count a filter uses is derived on the device from its own T
+  // (at most smax planes); wide Grams use 64x64 tiles with 4x4 blocking
+  if (Mcap > 32) {
+    const int t = (Mcap + 63) / 64;
+    hipLaunchKernelGGL((gram_partial_kernel<T, Acc, 64, F>), dim3(t * (t + 1) / 2, smax, B), dim3(256), 0, st, f);
+  } else {
+    hipLaunchKernelGGL((gram_partial_kernel<T, Acc, 32, F>), dim3(1, smax, B), dim3(256), 0, st, f);
+  }
   TTG_LAUNCH_CHECK("gram_partial_kernel");
   const long long mm = (long long)Mcap * Mcap;
   hipLaunchKernelGGL((gram_reduce_kernel<Acc, F>), dim3(std::max(1, std::min(cdiv(mm, 256), 1024)), 1, B),
@@ -678,10 +682,39 @@ static tt_status launch_gemm(F f, int B, long long Mcap, long long Ncap, hipStre
   return TT_OK;
 }
 
+// A (bulk) x B (FP64, N <= 128) for very tall A
+template <typename T, typename F>
+static tt_status launch_tall(F f, int B, long long Mcap, int Ncap, hipStream_t st) {
+  ProfScope ps_(PC_GEMM, st);
+  if (Ncap > 256) {
+    set_error("tall GEMM: N capacity %d > 256", Ncap);
+    return TT_ERR_SHAPE;
+  }
+  int G = 1;  // column groups of 32, a power of two so that 256 / G is exact
+  while (32 * G < Ncap) G *= 2;
+  const int RW = 256 / G;  // smallest row block any filter can use
+  // LDS for the largest row block (G = 1) or the widest B slice (G = Gmax)
+  const size_t smem = std::max((size_t)256 * (TSK_KC + 1) + (size_t)TSK_KC * 32,
+                               (size_t)RW * (TSK_KC + 1) + (size_t)TSK_KC * 32 * G) * sizeof(T);
+  if (smem > 48 * 1024)
+    HIP_TRY(hipFuncSetAttribute((const void*)tall_gemm_kernel<T, F>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)smem),
+            "tall gemm smem attribute");
+  hipLaunchKernelGGL((tall_gemm_kernel<T, F>), dim3(std::max(1, cdiv(Mcap, RW)), 1, B), dim3(256), smem, st, f, G);
+  TTG_LAUNCH_CHECK("tall_gemm_kernel");
+  return TT_OK;
+}
+
+// Jacobi columns in LDS up to rows*cols <= 16384 doubles (128 KB)
+static const int JAC_LDS_DOUBLES = 16384;
+
 template <typename F>
-static tt_status launch_jacobi(F f, int B, hipStream_t st) {
+static tt_status launch_jacobi(F f, int B, hipStream_t st, int lds_doubles = JAC_LDS_DOUBLES) {
   ProfScope ps_(PC_JACOBI, st);
-  hipLaunchKernelGGL((jacobi_kernel<F>), dim3(B), dim3(512), 0, st, f);
+  const size_t smem = (size_t)lds_doubles * sizeof(double);
+  HIP_TRY(hipFuncSetAttribute((const void*)jacobi_kernel<F>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem),
+          "jacobi smem attribute");
+  hipLaunchKernelGGL((jacobi_kernel<F>), dim3(B), dim3(512), smem, st, f, lds_doubles);
   TTG_LAUNCH_CHECK("jacobi_kernel");
   return TT_OK;
 }
@@ -689,13 +722,16 @@ static tt_status launch_jacobi(F f, int B, hipStream_t st) {
 template <typename TZ, typename TQ, typename F>
 static tt_status launch_trsm(F f, int B, long long mcap, int rcap, hipStream_t st) {
   ProfScope ps_(PC_TRSM, st);
-  const size_t smem = (size_t)rcap * 64 * sizeof(double);
+  const size_t qbytes = (size_t)rcap * 64 * sizeof(double);
+  const size_t lbytes = (size_t)rcap * rcap * sizeof(double);
+  const int l_in_lds = (qbytes + lbytes <= 150 * 1024) ? 1 : 0;
+  const size_t smem = qbytes + (l_in_lds ? lbytes : 0);
   if (smem > 48 * 1024)
     HIP_TRY(hipFuncSetAttribute((const void*)trsm_kernel<TZ, TQ, F>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem),
             "trsm smem attribute");
   hipLaunchKernelGGL((trsm_kernel<TZ, TQ, F>), dim3(std::max(1, cdiv(mcap, 64)), 1, B), dim3(64), smem, st,
-                     f, rcap);
+                     f, rcap, l_in_lds);
   TTG_LAUNCH_CHECK("trsm_kernel");
   return TT_OK;
 }
@@ -721,7 +757,7 @@ static tt_status round_launch(const RoundShape& sh, const RoundBufs& rb, double 
   for (int k = d - 1; k >= 1; --k) {
     c.k = k;
     if (k < d - 1) {
-      TT_TRY((launch_gemm<T, double, T, T>(FRlAbsorb<T>{c}, B, (long long)sh.rin[k] * sh.n[k], sh.rq[k + 1], st)));
+      TT_TRY((launch_tall<T>(FRlAbsorb<T>{c}, B, (long long)sh.rin[k] * sh.n[k], sh.rq[k + 1], st)));
     }
     const bool mg = sh.merge && k == 1;  // some filter may fold core 0 into this step
     if (mg) TT_TRY((launch_gemm<T, T, T, T>(FRlMerge<T>{c}, B, sh.n[0], (long long)sh.n[1] * sh.rq[2], st)));
@@ -736,7 +772,7 @@ static tt_status round_launch(const RoundShape& sh, const RoundBufs& rb, double 
     hipLaunchKernelGGL((first_core_copy_kernel<T>), dim3(B), dim3(256), 0, st, rb.din, rb.drs);
     TTG_LAUNCH_CHECK("first_core_copy_kernel");
   }
-  TT_TRY((launch_gemm<T, double, T, T>(FRlAbsorb<T>{c}, B, (long long)sh.n[0], sh.rq[1], st)));
+  TT_TRY((launch_tall<T>(FRlAbsorb<T>{c}, B, (long long)sh.n[0], sh.rq[1], st)));
   hipLaunchKernelGGL((round_norm_kernel<T>), dim3(B), dim3(256), 0, st, rb.din, rb.drs, eps);
   TTG_LAUNCH_CHECK("round_norm_kernel");
   // ---- left-to-right truncation ------------------------------------------
@@ -751,7 +787,7 @@ static tt_status round_launch(const RoundShape& sh, const RoundBufs& rb, double 
     TT_TRY((launch_jacobi(FLrJacobi{c}, B, st)));
     hipLaunchKernelGGL(round_select_kernel, dim3(B), dim3(256), 0, st, rb.dout, rb.drs, k, max_rank);
     TTG_LAUNCH_CHECK("round_select_kernel");
-    TT_TRY((launch_gemm<T, double, T, T>(FLrU<T>{c}, B, (long long)sh.rout[k] * sh.n[k], sh.rout[k + 1], st)));
+    TT_TRY((launch_tall<T>(FLrU<T>{c}, B, (long long)sh.rout[k] * sh.n[k], sh.rout[k + 1], st)));
   }
   c.k = d - 1;
   TT_TRY((launch_gemm<double, T, T, T>(FLrB<T>{c}, B, sh.rout[d - 1], (long long)sh.n[d - 1], st)));
@@ -1257,6 +1293,15 @@ static tt_status launch_conv(int B, int d, int r0cap, size_t smem, const DevTT* 
 }
 
 template <typename T>
+static tt_status launch_dot(int B, const DevTT* dl, const DevTT* dp, const FilterConst* dfc, double* out,
+                            long long stride, double* vbuf, long long vstride, long long tofs, hipStream_t st) {
+  ProfScope ps_(PC_CONTRACT, st);
+  hipLaunchKernelGGL((dot_kernel<T>), dim3(B), dim3(256), 0, st, dl, dp, dfc, out, stride, vbuf, vstride, tofs);
+  TTG_LAUNCH_CHECK("dot_kernel");
+  return TT_OK;
+}
+
+template <typename T>
 static tt_status launch_hadamard(int B, int d, int r0cap, const DevTT* dl, const DevTT* dp, const DevTT* dh,
                                  hipStream_t st) {
   hipLaunchKernelGGL(product_init_kernel, dim3(cdiv(B, 64)), dim3(64), 0, st, dl, dp, dh, B);
@@ -1355,6 +1400,7 @@ struct UpdatePlan {
   long long mstride;
   double* vbuf;
   int vcap;
+  long long vstride, tofs;
   bool any_range;
   int n0max, n1max, gcap, splits, r0cap;
 };
@@ -1418,7 +1464,17 @@ static tt_status update_plan(int32_t batch, const tt_grid* grids, const tt_meas*
   u.dfc = ar.take<FilterConst>(batch);
   u.mstride = (long long)u.n0max * u.n1max;
   u.mbuf = u.any_range ? ar.take<double>((size_t)batch * u.mstride) : nullptr;
-  u.vbuf = ar.take<double>((size_t)batch * 2 * u.vcap);
+  {
+    long long tmax = 1;
+    for (int b = 0; b < batch; ++b)
+      for (int k = 0; k < d; ++k) {
+        const int lc1 = (meas[b].kind == 1 && k == 0) ? std::min(lik_rank_cap, p_pred[b].n[1]) : 1;
+        tmax = std::max(tmax, (long long)lc1 * p_pred[b].cap[k] * p_pred[b].n[k]);
+      }
+    u.tofs = u.vcap;
+    u.vstride = u.vcap + tmax;
+  }
+  u.vbuf = ar.take<double>((size_t)batch * u.vstride);
   for (int b = 0; b < batch; ++b) {
     tt_train lt;
     memset(&lt, 0, sizeof(lt));
@@ -1490,13 +1546,12 @@ tt_status tt_update(int32_t batch, const tt_grid* grids, const tt_meas* meas, co
                     u.gcap, u.splits, st));
   const int d = p_pred[0].d;
   if (p_pred[0].dtype == TT_F64) {
+    TT_TRY(launch_dot<double>(batch, u.dl, u.dp, u.dfc, log_c_dev, 1LL, u.vbuf, u.vstride, u.tofs, st));
     TT_TRY(launch_hadamard<double>(batch, d, u.r0cap, u.dl, u.dp, u.dh, st));
-    hipLaunchKernelGGL((sum_kernel<double>), dim3(batch), dim3(256), 0, st, u.dh, u.dfc, log_c_dev, 1LL, u.vbuf, u.vcap);
   } else {
+    TT_TRY(launch_dot<float>(batch, u.dl, u.dp, u.dfc, log_c_dev, 1LL, u.vbuf, u.vstride, u.tofs, st));
     TT_TRY(launch_hadamard<float>(batch, d, u.r0cap, u.dl, u.dp, u.dh, st));
-    hipLaunchKernelGGL((sum_kernel<float>), dim3(batch), dim3(256), 0, st, u.dh, u.dfc, log_c_dev, 1LL, u.vbuf, u.vcap);
   }
-  TTG_LAUNCH_CHECK("sum_kernel");
   return TT_OK;
 }
 
@@ -1779,6 +1834,7 @@ struct RunPlan {
   long long mstride = 0;
   double* vbuf = nullptr;
   int vcap = 1;
+  long long vstride = 0, tofs = 0;
   double* mscr = nullptr;
   long long mspf = 0;
   int mrcap = 1;
@@ -1947,7 +2003,15 @@ static tt_status run_plan(int32_t batch, const tt_filter_spec* specs, const tt_t
   p.shX.splits = p.shH.splits = p.splits;
   p.mstride = (long long)p.n0max * p.n1max;
   p.mbuf = p.any_range ? ar.take<double>((size_t)batch * p.mstride) : nullptr;
-  p.vbuf = ar.take<double>((size_t)batch * 2 * p.vcap);
+  {
+    long long tmax = 1;
+    for (int b = 0; b < batch; ++b)
+      for (int k = 0; k < d; ++k)
+        tmax = std::max(tmax, (long long)p.vL[b].cap[k + 1] * p.vP[b].cap[k] * p.vP[b].n[k]);
+    p.tofs = p.vcap;
+    p.vstride = p.vcap + tmax;
+  }
+  p.vbuf = ar.take<double>((size_t)batch * p.vstride);
   p.mspf = (long long)moments_scratch_per_filter(d, p.mrcap);
   p.mscr = ar.take<double>((size_t)batch * p.mspf);
   p.lmass = ar.take<double>((size_t)batch);
@@ -1981,9 +2045,8 @@ static tt_status run_steps(RunPlan& p, int B, const double* z, int zdim, int K, 
     }
     TT_TRY(lik_launch(B, p.dL, p.drs, p.dfc, z + (long long)k * zdim, (long long)K * zdim, p.mbuf, p.mstride,
                       p.any_range, p.n0max, p.n1max, p.gcap, p.splits, st));
+    TT_TRY(launch_dot<T>(B, p.dL, p.dP, p.dfc, log_c + k, (long long)K, p.vbuf, p.vstride, p.tofs, st));
     TT_TRY(launch_hadamard<T>(B, d, p.r0capH, p.dL, p.dP, p.dH, st));
-    hipLaunchKernelGGL((sum_kernel<T>), dim3(B), dim3(256), 0, st, p.dH, p.dfc, log_c + k, (long long)K, p.vbuf, p.vcap);
-    TTG_LAUNCH_CHECK("sum_kernel");
     TT_TRY((round_launch<T, Acc>(p.shH, rh, eps, maxcap, st)));
     TT_TRY(launch_moments<T>(B, p.dP, p.dfc, p.lmass, 1, mean ? mean + (long long)k * d : nullptr, (long long)K * d,
                              cov ? cov + (long long)k * d * d : nullptr, (long long)K * d * d, p.mscr, p.mspf,

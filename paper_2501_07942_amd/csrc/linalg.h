@@ -24,13 +24,14 @@ struct GramArgs {
 
 // split count used for a summation of length T with `planes` planes
 __device__ inline int gram_split_count(int T, int planes) {
-  const int s = (T + 2047) / 2048;
+  const int s = (T + 511) / 512;
   return max(1, min(s, planes));
 }
 
-template <typename TB, typename Acc, typename F>
+template <typename TB, typename Acc, int TS, typename F>
 __global__ void __launch_bounds__(256) gram_partial_kernel(F f) {
-  constexpr int TS = 32;
+  constexpr int RB = TS / 16;  // outputs per thread along each side
+  constexpr int KC = 32;       // summation chunk
   const int b = blockIdx.z;
   GramArgs g;
   if (!f(b, g)) return;
@@ -49,23 +50,24 @@ __global__ void __launch_bounds__(256) gram_partial_kernel(F f) {
   const int chunk = (g.T + g.splits - 1) / g.splits;
   const int t_begin = s * chunk, t_end = min(g.T, t_begin + chunk);
 
-  __shared__ double As[TS][TS + 1];
-  __shared__ double Bs[TS][TS + 1];
+  __shared__ double As[TS][KC + 1];
+  __shared__ double Bs[TS][KC + 1];
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  typename Acc::V acc[2][2];
+  typename Acc::V acc[RB][RB];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < RB; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = Acc::zero();
+    for (int j = 0; j < RB; ++j) acc[i][j] = Acc::zero();
   const TB* x = reinterpret_cast<const TB*>(g.x);
   const bool t_fast = (g.st == 1);
   const int a0 = ti * TS, b0 = tj * TS;
-  for (int t0 = t_begin; t0 < t_end; t0 += TS) {
-    for (int e = threadIdx.x; e < TS * TS; e += blockDim.x) {
+  const bool diag_tile = (ti == tj);
+  for (int t0 = t_begin; t0 < t_end; t0 += KC) {
+    for (int e = threadIdx.x; e < TS * KC; e += blockDim.x) {
       int r, c;  // r = vector index within tile, c = summation index within chunk
       if (t_fast) {
-        r = e / TS;
-        c = e % TS;
+        r = e / KC;
+        c = e % KC;
       } else {
         c = e / TS;
         r = e % TS;
@@ -74,29 +76,32 @@ __global__ void __launch_bounds__(256) gram_partial_kernel(F f) {
       double va = 0.0, vb = 0.0;
       if (t < t_end) {
         if (a0 + r < g.M) va = bulk_to_double(x[(long long)(a0 + r) * g.sa + (long long)t * g.st]);
-        if (b0 + r < g.M) vb = bulk_to_double(x[(long long)(b0 + r) * g.sa + (long long)t * g.st]);
+        if (!diag_tile && b0 + r < g.M) vb = bulk_to_double(x[(long long)(b0 + r) * g.sa + (long long)t * g.st]);
       }
       As[r][c] = va;
-      Bs[r][c] = vb;
+      Bs[r][c] = diag_tile ? va : vb;
     }
     __syncthreads();
-    const int kmax = min(TS, t_end - t0);
+    const int kmax = min(KC, t_end - t0);
     for (int c = 0; c < kmax; ++c) {
-      const double a_0 = As[ty * 2 + 0][c], a_1 = As[ty * 2 + 1][c];
-      const double b_0 = Bs[tx * 2 + 0][c], b_1 = Bs[tx * 2 + 1][c];
-      acc[0][0] = Acc::fma_(acc[0][0], a_0, b_0);
-      acc[0][1] = Acc::fma_(acc[0][1], a_0, b_1);
-      acc[1][0] = Acc::fma_(acc[1][0], a_1, b_0);
-      acc[1][1] = Acc::fma_(acc[1][1], a_1, b_1);
+      double av[RB], bv[RB];
+#pragma unroll
+      for (int i = 0; i < RB; ++i) av[i] = As[ty * RB + i][c];
+#pragma unroll
+      for (int j = 0; j < RB; ++j) bv[j] = Bs[tx * RB + j][c];
+#pragma unroll
+      for (int i = 0; i < RB; ++i)
+#pragma unroll
+        for (int j = 0; j < RB; ++j) acc[i][j] = Acc::fma_(acc[i][j], av[i], bv[j]);
     }
     __syncthreads();
   }
   double* out = g.out + (long long)s * g.gcap * g.gcap * Acc::words;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < RB; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int a = a0 + ty * 2 + i, bb = b0 + tx * 2 + j;
+    for (int j = 0; j < RB; ++j) {
+      const int a = a0 + ty * RB + i, bb = b0 + tx * RB + j;
       if (a < g.M && bb < g.M) Acc::store(out, (long long)a * g.gcap + bb, acc[i][j]);
     }
 }
@@ -293,16 +298,21 @@ struct JacobiArgs {
 };
 
 template <typename F>
-__global__ void __launch_bounds__(512) jacobi_kernel(F f) {
+__global__ void __launch_bounds__(512) jacobi_kernel(F f, int lds_doubles) {
   const int b = blockIdx.x;
   JacobiArgs J;
   if (!f(b, J)) return;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, nw = blockDim.x >> 6;
   const int rows = J.rows, nc = J.ncols;
-  double* W = J.work;
+  // columns live in LDS when they fit (leading dimension = rows), else in
+  // the global scratch (leading dimension gcap)
+  extern __shared__ double jsm[];
+  const bool in_lds = (long long)rows * nc <= lds_doubles;
+  double* W = in_lds ? jsm : J.work;
+  const long long ldw = in_lds ? rows : J.gcap;
   for (long long e = tid; e < (long long)rows * nc; e += blockDim.x) {
     const int i = (int)(e / nc), c = (int)(e % nc);
-    W[(long long)c * J.gcap + i] = J.x[(long long)i * J.ldx + c];
+    W[(long long)c * ldw + i] = J.x[(long long)i * J.ldx + c];
   }
   __shared__ int s_rot;
   __shared__ double s_sig[1024];
@@ -322,8 +332,8 @@ __global__ void __launch_bounds__(512) jacobi_kernel(F f) {
           qc = (r - i + (n - 1)) % (n - 1);
         }
         if (pc >= nc || qc >= nc) continue;
-        double* xp = W + (long long)pc * J.gcap;
-        double* xq = W + (long long)qc * J.gcap;
+        double* xp = W + (long long)pc * ldw;
+        double* xq = W + (long long)qc * ldw;
         double al = 0.0, be = 0.0, ga = 0.0;
         for (int k = lane; k < rows; k += 64) {
           const double u = xp[k], v = xq[k];
@@ -354,7 +364,7 @@ __global__ void __launch_bounds__(512) jacobi_kernel(F f) {
   }
   // column norms
   for (int c = wid; c < nc; c += nw) {
-    const double* xc = W + (long long)c * J.gcap;
+    const double* xc = W + (long long)c * ldw;
     double s = 0.0;
     for (int k = lane; k < rows; k += 64) s = __fma_rn(xc[k], xc[k], s);
     s = wave_sum(s);
@@ -371,7 +381,7 @@ __global__ void __launch_bounds__(512) jacobi_kernel(F f) {
     }
     for (int o = 32; o > 0; o >>= 1) rk += __shfl_xor(rk, o, 64);
     if (lane == 0) J.sigma[rk] = sc;
-    const double* xc = W + (long long)c * J.gcap;
+    const double* xc = W + (long long)c * ldw;
     double* dst = J.usv + (long long)rk * J.gcap;
     for (int k = lane; k < rows; k += 64) dst[k] = xc[k];
   }
@@ -396,25 +406,33 @@ struct TrsmArgs {
 };
 
 template <typename TZ, typename TQ, typename F>
-__global__ void __launch_bounds__(64) trsm_kernel(F f, int rcap) {
+__global__ void __launch_bounds__(64) trsm_kernel(F f, int rcap, int l_in_lds) {
   const int b = blockIdx.z;
   TrsmArgs a;
   if (!f(b, a)) return;
   const int c = blockIdx.x * 64 + threadIdx.x;
   if (blockIdx.x * 64 >= a.m) return;
-  extern __shared__ double qs[];  // rcap x 64
+  extern __shared__ double qs[];  // rcap x 64 partial solutions, then r x r factor
+  double* ls = qs + (long long)rcap * 64;
   const TZ* z = reinterpret_cast<const TZ*>(a.z);
   TQ* q = reinterpret_cast<TQ*>(a.q);
   const bool live = c < a.m;
+  const bool lds_l = l_in_lds && a.r <= rcap;
+  if (lds_l) {
+    for (int e = threadIdx.x; e < a.r * a.r; e += 64) {
+      const int j = e / a.r, t = e % a.r;
+      ls[e] = (t <= j) ? a.lfac[(long long)a.piv[j] * a.gcap + t] : 0.0;
+    }
+    __syncthreads();
+  }
   for (int j = 0; j < a.r; ++j) {
-    const double* lrow = a.lfac + (long long)a.piv[j] * a.gcap;
+    const double* lrow = lds_l ? ls + (long long)j * a.r : a.lfac + (long long)a.piv[j] * a.gcap;
     double s = live ? bulk_to_double(z[(long long)a.piv[j] * a.ldz + c]) : 0.0;
     for (int t = 0; t < j; ++t) s = __fma_rn(-lrow[t], qs[t * 64 + threadIdx.x], s);
     const double v = s / lrow[j];
     qs[j * 64 + threadIdx.x] = v;
     if (live) q[(long long)j * a.ldq + c] = from_double<TQ>(v);
   }
-  (void)rcap;
 }
 
 // ---------------------------------------------------------------------------
@@ -496,4 +514,70 @@ __global__ void __launch_bounds__(256) gemm_kernel(F f) {
       const int m = m0 + ty * 4 + i, n = n0 + tx * 4 + j;
       if (m < g.M && n < g.N) C[(long long)m * g.scm + (long long)n * g.scn] = (TC)acc[i][j];
     }
+}
+
+// ---------------------------------------------------------------------------
+// Tall-skinny GEMM  C(m, n) = sum_k A(m, k) B(k, n)  for M >> K, N <= 128:
+// A and C row-major (bulk type), B row-major FP64 (ld sbk).  Each thread owns
+// one row and a group of 32 output columns (accumulators in registers); a
+// workgroup stages 256/G rows x 32 k of A and the matching 32 x N slice of B
+// in LDS (G = number of column groups), so A is read from HBM exactly once
+// with coalesced 128-byte row segments.
+// ---------------------------------------------------------------------------
+#define TSK_KC 32
+template <typename T, typename F>
+__global__ void __launch_bounds__(256) tall_gemm_kernel(F f, int Gmax) {
+  const int bz = blockIdx.z;
+  GemmArgs g;
+  if (!f(bz, g)) return;
+  // column groups for this filter's actual N (a power of two <= Gmax); the
+  // grid covers the smallest row block, surplus workgroups exit
+  int G = 1;
+  while (32 * G < g.N && G < Gmax) G *= 2;
+  if (g.N > 32 * G) return;
+  const int RW = 256 / G;  // rows per workgroup
+  const int m0 = blockIdx.x * RW;
+  if (m0 >= g.M) return;
+  extern __shared__ unsigned char smem_raw[];
+  T* Xs = reinterpret_cast<T*>(smem_raw);   // [RW][KC+1]
+  T* Ls = Xs + RW * (TSK_KC + 1);           // [KC][32*G]
+  const int tid = threadIdx.x;
+  const int cg = tid / RW, row = tid % RW;
+  const int NW = 32 * G;
+  const T* A = reinterpret_cast<const T*>(g.a);
+  const double* Bm = reinterpret_cast<const double*>(g.b);
+  T acc[32];
+#pragma unroll
+  for (int c = 0; c < 32; ++c) acc[c] = (T)0;
+  for (int k0 = 0; k0 < g.K; k0 += TSK_KC) {
+    // stage A rows m0..m0+RW, columns k0..k0+KC
+    for (int e = tid; e < RW * TSK_KC; e += 256) {
+      const int r = e / TSK_KC, kk = e % TSK_KC;
+      const int m = m0 + r, k = k0 + kk;
+      Xs[r * (TSK_KC + 1) + kk] = (m < g.M && k < g.K) ? A[(long long)m * g.sam + k] : (T)0;
+    }
+    for (int e = tid; e < TSK_KC * NW; e += 256) {
+      const int kk = e / NW, n = e % NW;
+      const int k = k0 + kk;
+      Ls[e] = (k < g.K && n < g.N) ? (T)Bm[(long long)k * g.sbk + n] : (T)0;
+    }
+    __syncthreads();
+    const int kmax = min(TSK_KC, g.K - k0);
+    for (int kk = 0; kk < kmax; ++kk) {
+      const T x = Xs[row * (TSK_KC + 1) + kk];
+      const T* lrow = Ls + kk * NW + cg * 32;
+#pragma unroll
+      for (int c = 0; c < 32; ++c) acc[c] += x * lrow[c];
+    }
+    __syncthreads();
+  }
+  const int m = m0 + row;
+  if (m < g.M) {
+    T* C = reinterpret_cast<T*>(g.c) + (long long)m * g.scm;
+#pragma unroll
+    for (int c = 0; c < 32; ++c) {
+      const int n = cg * 32 + c;
+      if (n < g.N) C[n] = acc[c];
+    }
+  }
 }

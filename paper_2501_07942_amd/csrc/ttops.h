@@ -542,3 +542,68 @@ __global__ void __launch_bounds__(256) convert_tt_kernel(const DevTT* __restrict
     *D.status = *S.status;
   }
 }
+
+// ---------------------------------------------------------------------------
+// Normaliser c_k = <L, P> * delta (Sec. 2.2 eq. pmf_filtrace_b; Sec. 4.1
+// 'dot') computed from the two factors, never from their Hadamard product:
+// per core, t(a', b, i) = sum_a v(a, b) L(a, i, a') and then
+// v'(a', b') = sum_{b, i} t(a', b, i) P(b, i, b').  One workgroup per
+// filter, one wavefront per output entry, fixed summation order.
+// Writes log(c) + logdelta + log_scale(L) + log_scale(P) to out[f*stride].
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) dot_kernel(const DevTT* __restrict__ lik, const DevTT* __restrict__ pin,
+                                                  const FilterConst* __restrict__ fc, double* __restrict__ out,
+                                                  long long stride, double* __restrict__ vbuf, long long vstride,
+                                                  long long tofs) {
+  const int f = blockIdx.x;
+  const DevTT &L = lik[f], &P = pin[f];
+  double* v = vbuf + f * vstride;
+  double* t = v + tofs;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  if (tid == 0) v[0] = 1.0;
+  __syncthreads();
+  for (int k = 0; k < P.d; ++k) {
+    const int l0 = L.ranks[k], l1 = L.ranks[k + 1], p0 = P.ranks[k], p1 = P.ranks[k + 1], n = P.n[k];
+    const double* lc = core_ptr<double>(L, k);
+    const T* pc = core_ptr<T>(P, k);
+    const long long nt = (long long)l1 * p0 * n;
+    for (long long e = tid; e < nt; e += blockDim.x) {
+      const int a2 = (int)(e / ((long long)p0 * n));
+      const int rem = (int)(e % ((long long)p0 * n));
+      const int b = rem / n, i = rem % n;
+      double s = 0.0;
+      for (int a = 0; a < l0; ++a) s += v[a * p0 + b] * lc[((long long)a * n + i) * l1 + a2];
+      t[e] = s;
+    }
+    __syncthreads();
+    const int nout = l1 * p1;
+    for (int o = wid; o < nout; o += 4) {
+      const int a2 = o / p1, b2 = o % p1;
+      double s = 0.0;
+      for (int q = lane; q < p0 * n; q += 64) {
+        const int b = q / n, i = q % n;
+        s += t[((long long)a2 * p0 + b) * n + i] * bulk_to_double(pc[((long long)b * n + i) * p1 + b2]);
+      }
+      s = wave_sum(s);
+      if (lane == 0) v[o] = s;  // v is consumed only through t, already complete
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const double s = v[0];
+    const double nan = __longlong_as_double(0x7ff8000000000000LL);
+    double r;
+    if (!(s == s) || fabs(s) > 1.7e308) {
+      r = nan;
+      set_status(P.status, TT_STATUS_NONFINITE);
+    } else if (!(s > 0.0)) {
+      r = nan;
+      set_status(P.status, TT_STATUS_NONPOSITIVE);
+    } else {
+      r = log(s) + fc[f].logdelta + *L.log_scale + *P.log_scale;
+    }
+    if (*P.status & (TT_STATUS_NONFINITE | TT_STATUS_NONPOSITIVE)) r = nan;
+    out[f * stride] = r;
+  }
+}
