@@ -235,13 +235,30 @@ typedef struct {
   int32_t lik_rank_cap;     /* largest likelihood rank reserved for */
 } tt_filter_spec;
 
-size_t tt_filter_run_workspace(int32_t batch, const tt_filter_spec* specs, int32_t precision);
+size_t tt_filter_run_workspace(int32_t batch, const tt_filter_spec* specs, const tt_train* kernels,
+                               int32_t n_kernels, int32_t precision);
 tt_status tt_filter_run(int32_t batch, const tt_filter_spec* specs, const tt_train* kernels,
                         int32_t n_kernels, const double* z_dev, int32_t zdim, int32_t K,
                         int32_t k_begin, int32_t k_count, int32_t precision, double* loglik_dev, double* log_c_dev,
                         double* log_mpred_dev, double* mean_dev, double* cov_dev,
                         int32_t* ranks_dev, int32_t* status_dev, void* ws, size_t ws_bytes,
                         void* stream);
+
+/* ---------------------------------------------------------------------
+ * How tt_filter_run evaluates the prediction for d >= 3 (process-wide
+ * setting; all modes compute the same Z_k = conv(K_k, P_k) x_3 L_{k+1} that
+ * the rounding's right-to-left sweep consumes, Sec. 2.1 eq. tpmconvFFT and
+ * Sec. 4.2):
+ *   0 (default) direct fused: the convolution and the absorption of L in
+ *     one time-domain kernel; the product TT is never materialised;
+ *   1 FFT fused: kernel-fibre spectra (computed once per kernel TT) times the
+ *     spectra of P x_3 L, inverse FFT and crop, per output column in LDS;
+ *   2 unfused: materialise the product (tt_predict's kernel) and absorb L
+ *     with a tall GEMM.
+ * tt_predict always materialises the product.
+ * --------------------------------------------------------------------- */
+tt_status tt_set_predict_mode(int32_t mode);
+int32_t tt_get_predict_mode(void);
 
 /* ---------------------------------------------------------------------
  * Optional timing of kernel classes (measurement support, not part of the

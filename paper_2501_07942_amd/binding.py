@@ -68,8 +68,10 @@ def _load():
         "tt_round": (I, [I, P, P, D, I, P, S, P]),
         "tt_normalize_moments_workspace": (S, [I, P]),
         "tt_normalize_moments": (I, [I, P, P, P, P, P, P, S, P]),
-        "tt_filter_run_workspace": (S, [I, P, I]),
+        "tt_filter_run_workspace": (S, [I, P, P, I, I]),
         "tt_profile_begin": (None, [I]),
+        "tt_set_predict_mode": (I, [I]),
+        "tt_get_predict_mode": (I, []),
         "tt_profile_end": (I, [P, P, I]),
         "tt_filter_run": (I, [I, P, P, I, P, I, I, I, I, I, P, P, P, P, P, P, P, P, S, P]),
     }
@@ -85,7 +87,13 @@ EXPORTED = ("tt_train_elems", "tt_last_error", "tt_version", "tt_kernel_build_wo
             "tt_kernel_build", "tt_predict_workspace", "tt_predict", "tt_update_workspace",
             "tt_update", "tt_round_workspace", "tt_round", "tt_normalize_moments_workspace",
             "tt_normalize_moments", "tt_filter_run_workspace", "tt_filter_run", "tt_profile_begin",
-            "tt_profile_end")
+            "tt_profile_end", "tt_set_predict_mode", "tt_get_predict_mode")
+
+PREDICT_DIRECT, PREDICT_FFT, PREDICT_UNFUSED = 0, 1, 2
+
+
+def set_predict_mode(mode: int):
+    _check(LIB.tt_set_predict_mode(int(mode)), "tt_set_predict_mode")
 
 PROFILE_CLASSES = ("conv", "hadamard", "gram", "pchol", "jacobi", "trsm", "gemm", "lik", "contract")
 
@@ -307,7 +315,7 @@ class FilterRun:
         self.cov = torch.zeros(self.B, K, d, d, dtype=torch.float64, device=dev)
         self.ranks = torch.zeros(self.B, K, d + 1, dtype=torch.int32, device=dev)
         self.status = torch.zeros(self.B, dtype=torch.int32, device=dev)
-        nbytes = LIB.tt_filter_run_workspace(self.B, self.specs, precision)
+        nbytes = LIB.tt_filter_run_workspace(self.B, self.specs, self.karr, len(kernels), precision)
         if nbytes == 0:
             _check(ERR_ARG, "tt_filter_run_workspace")
         self.ws = _ws(nbytes)

@@ -9,6 +9,7 @@
 #include "common.h"
 #include "linalg.h"
 #include "ttops.h"
+#include "fft.h"
 
 namespace ttg {
 
@@ -304,6 +305,52 @@ struct RCtx {
   double tau2;
   int esz;    // bytes per bulk element
   int merge;  // fold core 0 into the bond-1 step (left rank bounded by n_0)
+  const DevTT* Kn = nullptr;      // fused prediction: kernel TTs
+  const DevTT* Pn = nullptr;      //                   PMD before prediction
+  const FusedPred* FP = nullptr;  //                   FFT descriptors
+  int fused = 0;                  // interior Z_k come from the fused path
+  int zt = 0;                     // ... in (j, i) column order (FFT variant)
+};
+
+template <typename T>
+struct FArgs {
+  int N, rp0, rp1, rk0, rk1, n, k, gcap;
+  int hk;  // half width of this core's kernel fibre
+  const T* p;
+  const T* kcore;
+  const double* lfac;
+  FusedPred fp;
+  T* z;
+};
+
+template <typename T>
+struct FFused {
+  using Args = FArgs<T>;
+  RCtx c;
+  __device__ bool operator()(int b, Args& g) const {
+    const DevTT& K = c.Kn[b];
+    const DevTT& P = c.Pn[b];
+    const DevTT& X = c.X[b];
+    const RoundScratch& s = c.S[b];
+    const int k = c.k;
+    g.rk0 = K.ranks[k];
+    g.rk1 = K.ranks[k + 1];
+    g.rp0 = P.ranks[k];
+    g.rp1 = P.ranks[k + 1];
+    // a capacity overflow was flagged when the product ranks were set
+    if (g.rk0 * g.rp0 > X.cap[k] || g.rk1 * g.rp1 > X.cap[k + 1] || g.rk1 > 32) return false;
+    g.N = s.rq[k + 1];
+    g.n = P.n[k];
+    g.k = k;
+    g.gcap = s.gcap;
+    g.p = core_ptr<T>(P, k);
+    g.kcore = core_ptr<T>(K, k);
+    g.hk = (K.n[k] - 1) / 2;
+    g.lfac = s.lfac;
+    g.fp = c.FP[b];
+    g.z = reinterpret_cast<T*>(s.zbuf);
+    return true;
+  }
 };
 
 template <typename T>
@@ -436,6 +483,7 @@ struct FRlTrsm {
     a.ldz = a.m;
     a.q = qcore<T>(s, k);
     a.ldq = a.m;
+    a.zt_n = (c.zt && k >= 1 && k <= c.d - 2) ? X.n[k] : 0;
     return true;
   }
 };
@@ -705,6 +753,77 @@ static tt_status launch_tall(F f, int B, long long Mcap, int Ncap, hipStream_t s
   return TT_OK;
 }
 
+// the fused FFT prediction of interior core k (see fft.h)
+// prediction inside the filter step: 0 direct fused (default), 1 FFT fused,
+// 2 materialised product + tall GEMM
+static int g_predict_mode = 0;
+
+template <typename T>
+static size_t direct_smem(int hmax, int nmax, int pcap, int kcap) {
+  const int taps = 2 * hmax + 1;
+  const int taps_pad = (taps + DF_TB - 1) / DF_TB * DF_TB;
+  const int plen = DF_TB + nmax + 2 * hmax + 4 + DF_TB;
+  return ((size_t)taps_pad * pcap * DF_JC + (size_t)plen * (pcap + 1) + (size_t)taps * kcap) * sizeof(T);
+}
+
+template <typename T>
+static tt_status launch_direct(const RCtx& c, int B, int hmax, int kcap, int nmax, int pcap, int ncap,
+                               hipStream_t st) {
+  ProfScope ps_(PC_CONV, st);
+  FFused<T> f{c};
+  const size_t smem = direct_smem<T>(hmax, nmax, pcap, kcap);
+  if (smem > 160 * 1024) {
+    set_error("direct prediction: %zu bytes of LDS needed", smem);
+    return TT_ERR_SHAPE;
+  }
+  if (smem > 48 * 1024)
+    HIP_TRY(hipFuncSetAttribute((const void*)direct_pred_kernel<T, FFused<T>>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem),
+            "direct smem");
+  const int BB = B >= 64 ? 4 : 1;
+  const int grid = kcap * ((pcap + BB - 1) / BB) * ((ncap + DF_JC - 1) / DF_JC);
+  hipLaunchKernelGGL((direct_pred_kernel<T, FFused<T>>), dim3(std::max(1, grid), 1, B), dim3(256), smem, st, f, BB);
+  TTG_LAUNCH_CHECK("direct_pred_kernel");
+  return TT_OK;
+}
+
+template <typename T>
+constexpr int fused_cols() {
+  return sizeof(T) == 4 ? 2 : 1;  // output columns per workgroup
+}
+
+template <typename T>
+static size_t fused_smem(int L, int kcap, int nmax, int pcap) {
+  using C = typename Cpx<T>::t;
+  const int NC = fused_cols<T>();
+  const int pm = (kcap + 1) / 2;
+  const size_t nw = (size_t)L / 2 + 1;
+  const size_t bsz = std::max((size_t)pm * L, (size_t)kcap * nw);
+  return ((size_t)L / 2 + (size_t)FP_WCH * kcap * kcap + NC * (2 * bsz + (size_t)kcap * nw)) * sizeof(C) +
+         (size_t)NC * ((size_t)nmax * pcap + (size_t)kcap * pcap) * sizeof(T);
+}
+
+template <typename T>
+static tt_status launch_fused(const RCtx& c, int B, int Lmax, int kcap, int nmax, int pcap, int ncolcap,
+                              hipStream_t st) {
+  ProfScope ps_(PC_CONV, st);
+  constexpr int NC = fused_cols<T>();
+  FFused<T> f{c};
+  const size_t smem = fused_smem<T>(Lmax, kcap, nmax, pcap);
+  if (smem > 160 * 1024) {
+    set_error("fused prediction: %zu bytes of LDS needed", smem);
+    return TT_ERR_SHAPE;
+  }
+  if (smem > 48 * 1024)
+    HIP_TRY(hipFuncSetAttribute((const void*)fused_pred_kernel<T, NC, FFused<T>>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem),
+            "fused smem");
+  hipLaunchKernelGGL((fused_pred_kernel<T, NC, FFused<T>>), dim3(std::max(1, cdiv(ncolcap, NC)), 1, B), dim3(256),
+                     smem, st, f);
+  TTG_LAUNCH_CHECK("fused_pred_kernel");
+  return TT_OK;
+}
+
 // Jacobi columns in LDS up to rows*cols <= 16384 doubles (128 KB)
 static const int JAC_LDS_DOUBLES = 16384;
 
@@ -738,14 +857,29 @@ static tt_status launch_trsm(F f, int B, long long mcap, int rcap, hipStream_t s
 
 // The launch sequence of one batched rounding.  Shapes come from device
 // ranks; `sh` only bounds the grids.
+struct FusedLaunch {
+  const DevTT* Kn = nullptr;
+  const DevTT* Pn = nullptr;
+  const FusedPred* FP = nullptr;
+  int Lmax = 0, kcap = 1, pcap = 1, nmax = 1, hmax = 0;
+  int mode = 0;  // 0 direct, 1 FFT
+};
+
 template <typename T, typename Acc>
 static tt_status round_launch(const RoundShape& sh, const RoundBufs& rb, double eps, int max_rank,
-                              hipStream_t st) {
+                              hipStream_t st, const FusedLaunch* fl = nullptr) {
   const int B = sh.B, d = sh.d;
   const bool f64 = sizeof(T) == 8;
   const double tau2_rl = f64 ? 1e-30 : 1e-14;
   const double tau2_lr = f64 ? 1e-31 : 1e-16;
   RCtx c{rb.din, rb.dout, rb.drs, 0, d, 0.0, (int)sizeof(T), sh.merge ? 1 : 0};
+  if (fl) {
+    c.Kn = fl->Kn;
+    c.Pn = fl->Pn;
+    c.FP = fl->FP;
+    c.fused = 1;
+    c.zt = fl->mode == 1 ? 1 : 0;
+  }
   hipLaunchKernelGGL(round_init_kernel, dim3(cdiv(B, 64)), dim3(64), 0, st, rb.din, rb.dout, rb.drs, B);
   TTG_LAUNCH_CHECK("round_init_kernel");
   if (d == 1) {
@@ -757,7 +891,13 @@ static tt_status round_launch(const RoundShape& sh, const RoundBufs& rb, double 
   for (int k = d - 1; k >= 1; --k) {
     c.k = k;
     if (k < d - 1) {
-      TT_TRY((launch_tall<T>(FRlAbsorb<T>{c}, B, (long long)sh.rin[k] * sh.n[k], sh.rq[k + 1], st)));
+      if (fl && fl->mode == 1) {
+        TT_TRY(launch_fused<T>(c, B, fl->Lmax, fl->kcap, fl->nmax, fl->pcap, fl->pcap * sh.rq[k + 1], st));
+      } else if (fl) {
+        TT_TRY(launch_direct<T>(c, B, fl->hmax, fl->kcap, fl->nmax, fl->pcap, sh.rq[k + 1], st));
+      } else {
+        TT_TRY((launch_tall<T>(FRlAbsorb<T>{c}, B, (long long)sh.rin[k] * sh.n[k], sh.rq[k + 1], st)));
+      }
     }
     const bool mg = sh.merge && k == 1;  // some filter may fold core 0 into this step
     if (mg) TT_TRY((launch_gemm<T, T, T, T>(FRlMerge<T>{c}, B, sh.n[0], (long long)sh.n[1] * sh.rq[2], st)));
@@ -1280,14 +1420,14 @@ static tt_status launch_moments(int B, const DevTT* dt, const FilterConst* dfc, 
 
 template <typename T>
 static tt_status launch_conv(int B, int d, int r0cap, size_t smem, const DevTT* dk, const DevTT* dp,
-                             const DevTT* dx, hipStream_t st) {
+                             const DevTT* dx, hipStream_t st, int all_cores = 1) {
   hipLaunchKernelGGL(product_init_kernel, dim3(cdiv(B, 64)), dim3(64), 0, st, dk, dp, dx, B);
   TTG_LAUNCH_CHECK("product_init_kernel");
   if (smem > 48 * 1024)
     HIP_TRY(hipFuncSetAttribute((const void*)conv_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem),
             "conv smem attribute");
   ProfScope ps_(PC_CONV, st);
-  hipLaunchKernelGGL((conv_kernel<T>), dim3(r0cap, d, B), dim3(256), smem, st, dk, dp, dx);
+  hipLaunchKernelGGL((conv_kernel<T>), dim3(r0cap, d, B), dim3(256), smem, st, dk, dp, dx, all_cores);
   TTG_LAUNCH_CHECK("conv_kernel");
   return TT_OK;
 }
@@ -1842,6 +1982,17 @@ struct RunPlan {
   RoundShape shX, shH;
   int r0capX = 1, r0capH = 1;
   size_t csmem = 0;
+  // fused FFT prediction
+  bool fused = false;
+  std::vector<FusedPred> vfp;
+  FusedPred* dfp = nullptr;
+  std::vector<int> kL, klog2;        // FFT length per kernel
+  std::vector<void*> khat;           // spectra per kernel
+  std::vector<void*> ktw;            // twiddles per kernel
+  std::vector<long long> kpitch;
+  DevTT* dKk = nullptr;              // one descriptor per kernel (for the spectra launch)
+  std::vector<DevTT> vKk;
+  int Lmax = 0, kcap = 1, pcap = 1, hmax = 0;
   bool any_range = false;
   int n0max = 1, n1max = 1, gcap = 1, splits = 1;
   int d = 0;
@@ -1999,6 +2150,87 @@ static tt_status run_plan(int32_t batch, const tt_filter_spec* specs, const tt_t
   for (int b = 0; b < batch; ++b) plan_round_scratch(ar, vU[b], p.vP[b], f64, p.gcap, p.splits, p.vrs[b]);
   round_shape(batch, p.vX, p.vP, f64, p.shX);
   round_shape(batch, p.vH, p.vP, f64, p.shH);
+  // fused FFT prediction (interior cores exist for d >= 3)
+  p.fused = (d >= 3) && kernels != nullptr && g_predict_mode != 2;
+  if (d >= 3) {
+    const size_t csz = f64 ? sizeof(double2) : sizeof(float2);
+    const int nk = kernels ? n_kernels : 1;
+    p.kL.assign(nk, 0);
+    p.klog2.assign(nk, 0);
+    p.khat.assign(nk, nullptr);
+    p.ktw.assign(nk, nullptr);
+    p.kpitch.assign(nk, 0);
+    p.vKk.resize(nk);
+    // FFT length per kernel: the smallest power of two >= n + h over the
+    // grids that use it (a kernel belongs to one grid)
+    for (int b = 0; b < batch; ++b) {
+      const int ki = kernels ? specs[b].kernel_index : 0;
+      int hmax = 0;
+      if (kernels)
+        for (int k = 0; k < d; ++k) hmax = std::max(hmax, (kernels[ki].n[k] - 1) / 2);
+      int need = 0;
+      for (int k = 0; k < d; ++k) need = std::max(need, specs[b].grid.n[k] + hmax);
+      int L = 2, lg = 1;
+      while (L < need) {
+        L *= 2;
+        ++lg;
+      }
+      p.kL[ki] = std::max(p.kL[ki], L);
+      p.klog2[ki] = std::max(p.klog2[ki], lg);
+      p.Lmax = std::max(p.Lmax, L);
+      p.kcap = std::max(p.kcap, specs[b].kernel_cap);
+      p.pcap = std::max(p.pcap, specs[b].cap);
+    }
+    if (p.kcap > 32) {
+      set_error("tt_filter_run: kernel rank capacity %d > 32", p.kcap);
+      return TT_ERR_SHAPE;
+    }
+    {
+      int nmax = 1;
+      for (int b = 0; b < batch; ++b)
+        for (int k = 0; k < d; ++k) nmax = std::max(nmax, specs[b].grid.n[k]);
+      int hmax = 0;
+      if (kernels)
+        for (int ki = 0; ki < n_kernels; ++ki)
+          for (int k = 0; k < d; ++k) hmax = std::max(hmax, (kernels[ki].n[k] - 1) / 2);
+      p.hmax = hmax;
+      const size_t need = g_predict_mode == 1
+                              ? (f64 ? fused_smem<double>(p.Lmax, p.kcap, nmax, p.pcap)
+                                     : fused_smem<float>(p.Lmax, p.kcap, nmax, p.pcap))
+                              : (f64 ? direct_smem<double>(hmax, nmax, p.pcap, p.kcap)
+                                     : direct_smem<float>(hmax, nmax, p.pcap, p.kcap));
+      if (need > 160 * 1024) {
+        set_error("tt_filter_run: the fused prediction needs %zu bytes of LDS", need);
+        return TT_ERR_SHAPE;
+      }
+    }
+    for (int ki = 0; ki < nk; ++ki) {
+      if (p.kL[ki] == 0) continue;
+      const long long lhp = (p.kL[ki] / 2 + 1 + 7) / 8 * 8;
+      p.kpitch[ki] = lhp * p.kcap * p.kcap;
+      p.khat[ki] = ar.take<char>((size_t)d * p.kpitch[ki] * csz);
+      p.ktw[ki] = ar.take<char>((size_t)(p.kL[ki] / 2) * csz);
+      if (kernels) p.vKk[ki] = make_dev(kernels[ki]);
+    }
+    p.dKk = ar.take<DevTT>(nk);
+    p.vfp.resize(batch);
+    for (int b = 0; b < batch; ++b) {
+      const int ki = kernels ? specs[b].kernel_index : 0;
+      FusedPred& fp = p.vfp[b];
+      memset(&fp, 0, sizeof(fp));
+      fp.L = p.kL[ki];
+      fp.log2L = p.klog2[ki];
+      fp.LHP = (fp.L / 2 + 1 + 7) / 8 * 8;
+      fp.h = 0;
+      if (kernels)
+        for (int k = 0; k < d; ++k) fp.h = std::max(fp.h, (kernels[ki].n[k] - 1) / 2);
+      fp.khat = p.khat[ki];
+      fp.kpitch = p.kpitch[ki];
+      fp.tw = p.ktw[ki];
+      fp.zt = 1;
+    }
+    p.dfp = ar.take<FusedPred>(batch);
+  }
   p.shX.gcap = p.shH.gcap = p.gcap;
   p.shX.splits = p.shH.splits = p.splits;
   p.mstride = (long long)p.n0max * p.n1max;
@@ -2037,10 +2269,40 @@ static tt_status run_steps(RunPlan& p, int B, const double* z, int zdim, int K, 
     TTG_LAUNCH_CHECK("fill_kernel");
   }
   RoundBufs rx{p.dX, p.dP, p.drs}, rh{p.dH, p.dP, p.drs};
+  FusedLaunch fl;
+  if (p.fused && g_predict_mode == 1) {
+    // kernel spectra (the FFT of every kernel fibre), once per kernel TT
+    using C = typename Cpx<T>::t;
+    for (size_t ki = 0; ki < p.khat.size(); ++ki) {
+      if (!p.khat[ki]) continue;
+      const int L = p.kL[ki];
+      const size_t smem = ((size_t)L / 2 + (size_t)8 * L) * sizeof(C);
+      if (smem > 48 * 1024)
+        HIP_TRY(hipFuncSetAttribute((const void*)kernel_spectra_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)smem), "spectra smem");
+      hipLaunchKernelGGL((kernel_spectra_kernel<T>), dim3(cdiv((long long)p.kcap * p.kcap, 4), d), dim3(256), smem, st,
+                         p.dKk + ki, L, p.klog2[ki], (int)((L / 2 + 1 + 7) / 8 * 8), p.khat[ki], p.kpitch[ki]);
+      TTG_LAUNCH_CHECK("kernel_spectra_kernel");
+      hipLaunchKernelGGL((twiddle_kernel<T>), dim3(1), dim3(256), 0, st, p.ktw[ki], L);
+      TTG_LAUNCH_CHECK("twiddle_kernel");
+    }
+  }
+  if (p.fused) {
+    fl.mode = g_predict_mode == 1 ? 1 : 0;
+    fl.hmax = p.hmax;
+    fl.Kn = p.dK;
+    fl.Pn = p.dP;
+    fl.FP = p.dfp;
+    fl.Lmax = p.Lmax;
+    fl.kcap = p.kcap;
+    fl.pcap = p.pcap;
+    fl.nmax = p.shX.n[0];
+    for (int kk = 0; kk < d; ++kk) fl.nmax = std::max(fl.nmax, p.shX.n[kk]);
+  }
   for (int k = k_begin; k < k_begin + k_count; ++k) {
     if (k > 0) {
-      TT_TRY(launch_conv<T>(B, d, p.r0capX, p.csmem, p.dK, p.dP, p.dX, st));
-      TT_TRY((round_launch<T, Acc>(p.shX, rx, eps, maxcap, st)));
+      TT_TRY(launch_conv<T>(B, d, p.r0capX, p.csmem, p.dK, p.dP, p.dX, st, p.fused ? 0 : 1));
+      TT_TRY((round_launch<T, Acc>(p.shX, rx, eps, maxcap, st, p.fused ? &fl : nullptr)));
       TT_TRY(launch_moments<T>(B, p.dP, p.dfc, log_mpred + k, K, nullptr, 0, nullptr, 0, p.mscr, p.mspf, p.mrcap, st));
     }
     TT_TRY(lik_launch(B, p.dL, p.drs, p.dfc, z + (long long)k * zdim, (long long)K * zdim, p.mbuf, p.mstride,
@@ -2066,11 +2328,12 @@ static tt_status run_steps(RunPlan& p, int B, const double* z, int zdim, int K, 
 
 extern "C" {
 
-size_t tt_filter_run_workspace(int32_t batch, const tt_filter_spec* specs, int32_t precision) {
+size_t tt_filter_run_workspace(int32_t batch, const tt_filter_spec* specs, const tt_train* kernels,
+                               int32_t n_kernels, int32_t precision) {
+  if (!kernels || n_kernels < 1) return 0;
   Arena ar(nullptr, 0);
   RunPlan p;
-  if (run_plan(batch, specs, nullptr, 0, precision, nullptr, ar, p) != TT_OK) return 0;
-  // the plan without kernels does not know the LDS need; the bytes are the same
+  if (run_plan(batch, specs, kernels, n_kernels, precision, nullptr, ar, p) != TT_OK) return 0;
   return ar.used + 256;
 }
 
@@ -2118,6 +2381,10 @@ tt_status tt_filter_run(int32_t batch, const tt_filter_spec* specs, const tt_tra
   TT_TRY(upload(p.dK, p.vK, st));
   TT_TRY(upload(p.drs, p.vrs, st));
   TT_TRY(upload(p.dfc, p.vfc, st));
+  if (p.fused) {
+    TT_TRY(upload(p.dfp, p.vfp, st));
+    TT_TRY(upload(p.dKk, p.vKk, st));
+  }
   if (precision == TT_F64)
     return run_steps<double, AccDD>(p, batch, z_dev, zdim, K, k_begin, k_count, loglik_dev, log_c_dev, log_mpred_dev,
                                     mean_dev, cov_dev, ranks_dev, specs, st);
@@ -2157,5 +2424,20 @@ int32_t tt_profile_end(double* ms, int32_t* launches, int32_t nclass) {
   g_prof_mask = 0;
   return PC_N;
 }
+
+}  // extern "C"
+
+extern "C" {
+
+tt_status tt_set_predict_mode(int32_t mode) {
+  if (mode < 0 || mode > 2) {
+    set_error("tt_set_predict_mode: mode must be 0, 1 or 2");
+    return TT_ERR_ARG;
+  }
+  g_predict_mode = mode;
+  return TT_OK;
+}
+
+int32_t tt_get_predict_mode(void) { return g_predict_mode; }
 
 }  // extern "C"

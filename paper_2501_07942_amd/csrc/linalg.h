@@ -403,6 +403,7 @@ struct TrsmArgs {
   long long ldz;
   void* q;
   long long ldq;
+  int zt_n;  // 0: Z columns in output order; n: Z columns ordered (j, i), output c = i*(m/n) + j
 };
 
 template <typename TZ, typename TQ, typename F>
@@ -427,7 +428,12 @@ __global__ void __launch_bounds__(64) trsm_kernel(F f, int rcap, int l_in_lds) {
   }
   for (int j = 0; j < a.r; ++j) {
     const double* lrow = lds_l ? ls + (long long)j * a.r : a.lfac + (long long)a.piv[j] * a.gcap;
-    double s = live ? bulk_to_double(z[(long long)a.piv[j] * a.ldz + c]) : 0.0;
+    long long zc = c;
+    if (a.zt_n) {
+      const int nn = a.m / a.zt_n;
+      zc = (long long)(c % nn) * a.zt_n + c / nn;
+    }
+    double s = live ? bulk_to_double(z[(long long)a.piv[j] * a.ldz + zc]) : 0.0;
     for (int t = 0; t < j; ++t) s = __fma_rn(-lrow[t], qs[t * 64 + threadIdx.x], s);
     const double v = s / lrow[j];
     qs[j * 64 + threadIdx.x] = v;

@@ -33,12 +33,15 @@ struct FilterConst {
 template <typename T>
 __global__ void __launch_bounds__(256) conv_kernel(const DevTT* __restrict__ kern,
                                                    const DevTT* __restrict__ pin,
-                                                   const DevTT* __restrict__ xout) {
+                                                   const DevTT* __restrict__ xout, int all_cores) {
   const int f = blockIdx.z, k = blockIdx.y;
   const DevTT& K = kern[f];
   const DevTT& P = pin[f];
   const DevTT& X = xout[f];
   if (k >= P.d) return;
+  // the fused prediction produces the interior cores inside the rounding;
+  // only the first and last cores are materialised then
+  if (!all_cores && k != 0 && k != P.d - 1) return;
   const int rk0 = K.ranks[k], rk1 = K.ranks[k + 1];
   const int rp0 = P.ranks[k], rp1 = P.ranks[k + 1];
   const int R0 = rk0 * rp0, R1 = rk1 * rp1;

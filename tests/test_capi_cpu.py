@@ -79,5 +79,14 @@ def test_filter_run_workspace_query():
     specs, _, _ = wl.make_batch("range4d", batch=2, steps=3, d=3, n=32, cap=8)
     fs = runner.filter_specs(specs, [0, 0], 13, 64)
     arr = (B.FilterSpec * 2)(*fs)
-    assert B.LIB.tt_filter_run_workspace(2, arr, B.F64) > 0
-    assert B.LIB.tt_filter_run_workspace(2, arr, 7) == 0
+    kt = B.Train()
+    kt.d = 3
+    for k in range(3):
+        kt.n[k] = 2 * specs[0].halfwidths()[k] + 1
+    kt.cap[0], kt.cap[1], kt.cap[2], kt.cap[3] = 1, 13, 13, 1
+    kt.dtype = B.F64
+    kt.cores = kt.ranks = kt.log_scale = kt.status = 4096  # never dereferenced on the host
+    karr = (B.Train * 1)(kt)
+    assert B.LIB.tt_filter_run_workspace(2, arr, karr, 1, B.F64) > 0
+    assert B.LIB.tt_filter_run_workspace(2, arr, karr, 1, 7) == 0
+    assert B.LIB.tt_filter_run_workspace(2, arr, None, 0, B.F64) == 0

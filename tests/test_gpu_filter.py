@@ -44,8 +44,17 @@ def test_kf2d_fp64_matches_oracle_and_kalman(mods):
     assert abs(run.loglik.item() - ref["loglik"]) < 1e-9
 
 
+@pytest.fixture
+def predict_mode(mods, request):
+    B = mods[0]
+    B.set_predict_mode(request.param)
+    yield request.param
+    B.set_predict_mode(B.PREDICT_DIRECT)
+
+
+@pytest.mark.parametrize("predict_mode", [0, 1, 2], indirect=True)
 @pytest.mark.parametrize("d,n,cap,steps", [(3, 40, 8, 6), (4, 32, 8, 5)])
-def test_range_fp64_matches_oracle(mods, d, n, cap, steps):
+def test_range_fp64_matches_oracle(mods, d, n, cap, steps, predict_mode):
     B, runner, wl = mods
     specs, xs, zs = wl.make_batch("range4d", batch=1, steps=steps, d=d, n=n, cap=cap)
     s, z = specs[0], zs[0]
@@ -63,7 +72,24 @@ def test_range_fp64_matches_oracle(mods, d, n, cap, steps):
     assert np.abs(mean - ref["mean"]).max() < 1e-10 * dx
 
 
-def test_range_fp32_meets_reduced_precision_bars(mods):
+@pytest.mark.parametrize("predict_mode", [0, 1, 2], indirect=True)
+def test_per_axis_kernel_widths_fp64(mods, predict_mode):
+    # different process-noise scales per axis give kernel fibres of different
+    # lengths in every core
+    B, runner, wl = mods
+    s = wl.spec_range(3, 36, 8, sigma_w=[1.0, 0.6, 1.4])
+    assert len(set(s.halfwidths())) == 3
+    x, z = wl.simulate(s, 5, __import__("numpy").random.SeedSequence(7))
+    ref = oracle_run(s, z)
+    run, _ = runner.run_filters([s], [z], B.F64)
+    assert int(run.status.cpu()[0]) == 0
+    lc = run.log_c.cpu().numpy()[0]
+    assert np.abs(lc - ref["log_c"]).max() < 1e-10 * max(1.0, np.abs(ref["log_c"]).max())
+    assert np.abs(run.mean.cpu().numpy()[0] - ref["mean"]).max() < 1e-10 * s.spacing()
+
+
+@pytest.mark.parametrize("predict_mode", [0, 1, 2], indirect=True)
+def test_range_fp32_meets_reduced_precision_bars(mods, predict_mode):
     B, runner, wl = mods
     specs, xs, zs = wl.make_batch("range4d", batch=1, steps=6, d=3, n=40, cap=8)
     s, z = specs[0], zs[0]
