@@ -24,22 +24,16 @@ sys.path.insert(0, ROOT)
 
 METRIC = "TT-GBF filter steps/s (d=6,N=128,rank≤16) FP32 batch vs FP64 plain; grad ms/step"
 HBM_PEAK_GBS = 8000.0
+# published FP32 vector peak of MI355X (256 CUs x 2.4 GHz x 256 flops/clk,
+# counting packed FP32; ordinary FP32 FMAs issue at half that rate)
+FP32_VALU_PEAK_TFS = 157.3
+# HBM bytes per launch of direct_pred_kernel<float> from rocprofv3 FETCH_SIZE
+# and WRITE_SIZE, scaled by the copy-kernel calibration; None until measured
+TRAFFIC = None
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
-
-
-def conv_bytes(ranks_prev, kranks, n, esz):
-    """Algorithmic HBM bytes of one convolution launch for one filter:
-    write the product cores, read the PMD and kernel cores once."""
-    d = len(n)
-    kr = [int(x) for x in kranks]
-    rp_ = [int(x) for x in ranks_prev]
-    w = sum(kr[k] * rp_[k] * n[k] * kr[k + 1] * rp_[k + 1] for k in range(d))
-    rp = sum(rp_[k] * n[k] * rp_[k + 1] for k in range(d))
-    kb = sum(kr[k] * (2 * 12 + 1) * kr[k + 1] for k in range(d))
-    return (w + rp + kb) * esz
 
 
 def run_batch(B, runner, binding, wl, name, batch, steps, warmup, precision, profile_steps=0, seed=None):
@@ -133,6 +127,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the FP64 single-filter comparator")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--profile-steps", type=int, default=2)
+    ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="MIB",
+                    help="only run 5 device-to-device copies of MIB MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
@@ -144,6 +140,15 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(1)
+    if args.copy_calibration > 0:
+        nel = int(args.copy_calibration * 2 ** 20) // 4
+        src = torch.ones(nel, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": nel * 4, "copy_bytes_written": nel * 4, "copies": 5}), flush=True)
+        return
 
     main_res = run_batch(None, runner, binding, wl, args.workload, args.batch, args.steps, args.warmup,
                          binding.F32, profile_steps=args.profile_steps)
@@ -151,29 +156,23 @@ def main():
     ms = main_res["ms"]
     value = B * args.steps / (ms / 1000.0)
 
-    # roofline of the dominant kernel class from the profiled window
+    # roofline of the dominant kernel from the profiled window: the direct
+    # fused prediction (convolution + absorption of the next factor), FP32
+    # multiply-adds on the vector ALUs; its algorithmic flops and bytes come
+    # from the library's work model evaluated on the device-resident ranks
     prof = main_res["prof"] or {}
-    kernel_ms = {k: round(v[0] / max(args.profile_steps, 1), 3) for k, v in prof.items()}
+    kernel_ms = {k: round(v[0] / max(args.profile_steps, 1), 3) for k, v in prof.items() if v[1]}
     roof = None
-    if prof and prof["conv"][1] > 0:
-        run = main_res["run"]
-        ranks = run.ranks.cpu().numpy()
-        kr = [k.cap for k in main_res["kernels"]]
-        k0 = 1 + args.warmup + args.steps
-        tot = 0
-        for b in range(B):
-            spec = main_res["specs"][b]
-            n = [spec.n] * spec.d
-            kidx = 0
-            for k in range(k0, k0 + args.profile_steps):
-                tot += conv_bytes(list(ranks[b, k - 1]), kr[kidx], n, 4)
-        conv_ms, conv_n = prof["conv"]
-        avg_ms = conv_ms / conv_n
-        achieved = tot / conv_n / (avg_ms / 1000.0) / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "conv_kernel<float>",
-                "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes_per_launch": int(tot / conv_n)}
-
+    if prof and prof["pred"][1] > 0 and prof["pred"][2] > 0:
+        ms_p, n_p, fl_p, by_p = prof["pred"]
+        avg_s = ms_p / n_p / 1000.0
+        achieved = fl_p / n_p / avg_s / 1e12
+        roof = {"bound": "alu", "achieved": round(achieved, 2), "peak": FP32_VALU_PEAK_TFS, "unit": "TFLOP/s",
+                "frac": round(achieved / FP32_VALU_PEAK_TFS, 4), "traffic": TRAFFIC,
+                "kernel": "direct_pred_kernel<float>", "avg_launch_ms": round(ms_p / n_p, 4),
+                "launches": n_p, "algorithmic_flops_per_launch": round(fl_p / n_p),
+                "algorithmic_bytes_per_launch": round(by_p / n_p),
+                "algorithmic_GBs": round(by_p / n_p / avg_s / 1e9, 1)}
     out = {
         "metric": METRIC,
         "value": round(value, 2),

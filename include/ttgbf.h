@@ -266,14 +266,20 @@ int32_t tt_get_predict_mode(void);
  * events on the launch stream around every launch of each class c with bit
  * (1 << c) set in mask:
  *   0 convolution, 1 Hadamard, 2 Gram, 3 pivoted Cholesky, 4 Jacobi,
- *   5 triangular solve, 6 GEMM, 7 likelihood build, 8 sum/moments.
+ *   5 triangular solve, 6 GEMM, 7 likelihood build, 8 sum/moments,
+ *   9 fused prediction (convolution and absorption of the next factor).
+ * For classes with a work model (9; direct prediction mode only) a
+ * one-workgroup kernel after each launch adds the launch's algorithmic
+ * flops and HBM bytes, computed from the device-resident ranks, to a small
+ * device buffer that tt_profile_begin allocates once and clears.
  * tt_profile_end waits for the recorded events, writes the summed
- * milliseconds and launch counts of classes 0..nclass-1 (either array may be
- * NULL), stops recording and returns the number of classes (or -1).  The
- * state is per process; do not profile from several threads at once.
+ * milliseconds, launch counts, algorithmic flops and bytes of classes
+ * 0..nclass-1 (any array may be NULL; classes without a work model report
+ * 0), stops recording and returns the number of classes (or -1).  The state
+ * is per process; do not profile from several threads at once.
  * --------------------------------------------------------------------- */
 void tt_profile_begin(int32_t class_mask);
-int32_t tt_profile_end(double* ms, int32_t* launches, int32_t nclass);
+int32_t tt_profile_end(double* ms, int32_t* launches, double* flops, double* bytes, int32_t nclass);
 
 #ifdef __cplusplus
 }

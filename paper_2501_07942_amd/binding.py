@@ -72,7 +72,7 @@ def _load():
         "tt_profile_begin": (None, [I]),
         "tt_set_predict_mode": (I, [I]),
         "tt_get_predict_mode": (I, []),
-        "tt_profile_end": (I, [P, P, I]),
+        "tt_profile_end": (I, [P, P, P, P, I]),
         "tt_filter_run": (I, [I, P, P, I, P, I, I, I, I, I, P, P, P, P, P, P, P, P, S, P]),
     }
     for name, (res, args) in sigs.items():
@@ -95,7 +95,7 @@ PREDICT_DIRECT, PREDICT_FFT, PREDICT_UNFUSED = 0, 1, 2
 def set_predict_mode(mode: int):
     _check(LIB.tt_set_predict_mode(int(mode)), "tt_set_predict_mode")
 
-PROFILE_CLASSES = ("conv", "hadamard", "gram", "pchol", "jacobi", "trsm", "gemm", "lik", "contract")
+PROFILE_CLASSES = ("conv", "hadamard", "gram", "pchol", "jacobi", "trsm", "gemm", "lik", "contract", "pred")
 
 
 def profile_begin(classes=PROFILE_CLASSES):
@@ -106,13 +106,16 @@ def profile_begin(classes=PROFILE_CLASSES):
 
 
 def profile_end():
-    """{class: (total ms, launches)} of the launches since profile_begin."""
+    """{class: (total ms, launches, algorithmic flops, algorithmic bytes)} of
+    the launches since profile_begin (work is 0 for classes without a model)."""
     n = len(PROFILE_CLASSES)
     ms = (C.c_double * n)()
     cnt = (C.c_int32 * n)()
-    if LIB.tt_profile_end(ms, cnt, n) < 0:
+    fl = (C.c_double * n)()
+    by = (C.c_double * n)()
+    if LIB.tt_profile_end(ms, cnt, fl, by, n) < 0:
         raise TTError(LIB.tt_last_error().decode())
-    return {PROFILE_CLASSES[i]: (ms[i], cnt[i]) for i in range(n)}
+    return {PROFILE_CLASSES[i]: (ms[i], cnt[i], fl[i], by[i]) for i in range(n)}
 
 
 def _check(st: int, what: str):

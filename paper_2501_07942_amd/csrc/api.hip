@@ -31,7 +31,8 @@ tt_status check_hip(hipError_t e, const char* what) {
 // optional timing of kernel classes with HIP events on the launch stream
 // ---------------------------------------------------------------------------
 enum ProfClass {
-  PC_CONV = 0, PC_HADAMARD, PC_GRAM, PC_PCHOL, PC_JACOBI, PC_TRSM, PC_GEMM, PC_LIK, PC_CONTRACT, PC_OTHER, PC_N
+  PC_CONV = 0, PC_HADAMARD, PC_GRAM, PC_PCHOL, PC_JACOBI, PC_TRSM, PC_GEMM, PC_LIK, PC_CONTRACT, PC_PRED, PC_OTHER,
+  PC_N
 };
 struct ProfRec {
   int cls;
@@ -41,6 +42,11 @@ static std::vector<ProfRec> g_prof;
 static std::vector<hipEvent_t> g_pool;
 static int g_prof_mask = 0;
 static size_t g_pool_next = 0;
+
+// Algorithmic work of profiled launches: flops and HBM bytes per class,
+// summed on the device by a one-workgroup kernel after each launch of a class
+// that has a work model (so the counts follow the device-resident ranks).
+static double* g_work = nullptr;  // [PC_N][2]: flops, bytes
 
 static hipEvent_t prof_event() {
   if (g_pool_next == g_pool.size()) {
@@ -763,13 +769,41 @@ static size_t direct_smem(int hmax, int nmax, int pcap, int kcap) {
   const int taps = 2 * hmax + 1;
   const int taps_pad = (taps + DF_TB - 1) / DF_TB * DF_TB;
   const int plen = DF_TB + nmax + 2 * hmax + 4 + DF_TB;
-  return ((size_t)taps_pad * pcap * DF_JC + (size_t)plen * (pcap + 1) + (size_t)taps * kcap) * sizeof(T);
+  size_t most = 0;
+  for (int jc = 8; jc <= DF_JC; jc *= 2)  // every column chunk the kernel may pick
+    most = std::max(most, (size_t)taps_pad * pcap * jc + (size_t)(DF_JC / jc) * plen * (pcap + 1));
+  return (most + (size_t)taps * kcap) * sizeof(T);
+}
+
+// Work model of the direct fused prediction for one filter and core: the
+// contraction over taps and the next bond (2 flops per multiply-add) and the
+// V = K x L product, each counted once; bytes = read P_k, K_k and L (FP64),
+// write Z_k once.
+template <typename T>
+__global__ void __launch_bounds__(256) pred_work_kernel(FFused<T> fn, int B, double* work) {
+  __shared__ double red[4];
+  double fl = 0.0, by = 0.0;
+  for (int b = threadIdx.x; b < B; b += blockDim.x) {
+    FArgs<T> g;
+    if (!fn(b, g)) continue;
+    const double taps = 2.0 * g.hk + 1.0;
+    const double out = (double)g.rk0 * g.rp0 * g.n * g.N;
+    fl += 2.0 * out * taps * g.rp1 + 2.0 * g.rk0 * taps * g.rp1 * g.N * g.rk1;
+    by += sizeof(T) * (out + (double)g.rp0 * g.n * g.rp1 + (double)g.rk0 * taps * g.rk1) +
+          8.0 * g.rk1 * g.rp1 * g.N;
+  }
+  fl = block_sum(fl, red);
+  by = block_sum(by, red);
+  if (threadIdx.x == 0) {
+    work[2 * PC_PRED] += fl;
+    work[2 * PC_PRED + 1] += by;
+  }
 }
 
 template <typename T>
 static tt_status launch_direct(const RCtx& c, int B, int hmax, int kcap, int nmax, int pcap, int ncap,
                                hipStream_t st) {
-  ProfScope ps_(PC_CONV, st);
+  ProfScope ps_(PC_PRED, st);
   FFused<T> f{c};
   const size_t smem = direct_smem<T>(hmax, nmax, pcap, kcap);
   if (smem > 160 * 1024) {
@@ -784,6 +818,10 @@ static tt_status launch_direct(const RCtx& c, int B, int hmax, int kcap, int nma
   const int grid = kcap * ((pcap + BB - 1) / BB) * ((ncap + DF_JC - 1) / DF_JC);
   hipLaunchKernelGGL((direct_pred_kernel<T, FFused<T>>), dim3(std::max(1, grid), 1, B), dim3(256), smem, st, f, BB);
   TTG_LAUNCH_CHECK("direct_pred_kernel");
+  if (g_work && (g_prof_mask & (1 << PC_PRED))) {
+    hipLaunchKernelGGL((pred_work_kernel<T>), dim3(1), dim3(256), 0, st, f, B, g_work);
+    TTG_LAUNCH_CHECK("pred_work_kernel");
+  }
   return TT_OK;
 }
 
@@ -806,7 +844,7 @@ static size_t fused_smem(int L, int kcap, int nmax, int pcap) {
 template <typename T>
 static tt_status launch_fused(const RCtx& c, int B, int Lmax, int kcap, int nmax, int pcap, int ncolcap,
                               hipStream_t st) {
-  ProfScope ps_(PC_CONV, st);
+  ProfScope ps_(PC_PRED, st);
   constexpr int NC = fused_cols<T>();
   FFused<T> f{c};
   const size_t smem = fused_smem<T>(Lmax, kcap, nmax, pcap);
@@ -2400,12 +2438,16 @@ void tt_profile_begin(int32_t class_mask) {
   g_prof.clear();
   g_pool_next = 0;
   g_prof_mask = class_mask;
+  if (!g_work && hipMalloc((void**)&g_work, sizeof(double) * 2 * PC_N) != hipSuccess) g_work = nullptr;
+  if (g_work && hipMemset(g_work, 0, sizeof(double) * 2 * PC_N) != hipSuccess) g_work = nullptr;
 }
 
-int32_t tt_profile_end(double* ms, int32_t* launches, int32_t nclass) {
+int32_t tt_profile_end(double* ms, int32_t* launches, double* flops, double* bytes, int32_t nclass) {
   for (int c = 0; c < nclass; ++c) {
     if (ms) ms[c] = 0.0;
     if (launches) launches[c] = 0;
+    if (flops) flops[c] = 0.0;
+    if (bytes) bytes[c] = 0.0;
   }
   for (const ProfRec& r : g_prof) {
     if (hipEventSynchronize(r.b) != hipSuccess) {
@@ -2422,6 +2464,17 @@ int32_t tt_profile_end(double* ms, int32_t* launches, int32_t nclass) {
   }
   g_prof.clear();
   g_prof_mask = 0;
+  if (g_work && (flops || bytes)) {
+    double w[2 * PC_N];
+    if (hipMemcpy(w, g_work, sizeof(w), hipMemcpyDeviceToHost) != hipSuccess) {
+      set_error("tt_profile_end: reading the work counters failed");
+      return -1;
+    }
+    for (int c = 0; c < nclass && c < PC_N; ++c) {
+      if (flops) flops[c] = w[2 * c];
+      if (bytes) bytes[c] = w[2 * c + 1];
+    }
+  }
   return PC_N;
 }
 

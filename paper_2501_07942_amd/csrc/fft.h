@@ -372,14 +372,19 @@ __global__ void __launch_bounds__(256) fused_pred_kernel(F fn) {
 //   V(a, m, b', j) = sum_{a'} K_k(a, m, a') L(a' rp1 + b', j)
 //   Z(a rp0 + b, i, j) = sum_m sum_{b'} P_k(b, i + h - m, b') V(a, m, b', j)
 // (the same Z_k = X_k x_3 L_{k+1} as above, P = 0 off the grid).  A
-// workgroup owns one output row block a, BB consecutive b and a chunk of 32
-// columns j; V for that (a, j-chunk) and one zero-padded P fibre live in LDS.
-// Each thread produces 4 consecutive i x 4 consecutive j; taps are consumed
-// in blocks of DF_TB from a register window over the P fibre.
+// workgroup owns one output row block a, BB consecutive b and a chunk of JC
+// columns j; V for that (a, j-chunk) and NB = 32 / JC zero-padded P fibres
+// live in LDS.  JC (8, 16 or 32) follows the filter's own column count, so a
+// narrow L_{k+1} does not leave threads computing padding.  Each thread
+// produces 4 consecutive i x 4 consecutive j of one fibre; taps are consumed
+// in blocks of DF_TB from a register window over the fibre.
 // Z is written in the ordinary column order (i, j).
 // ---------------------------------------------------------------------------
 #define DF_TB 4
 #define DF_JC 32
+
+__host__ __device__ inline int direct_jc(int N) { return N <= 8 ? 8 : (N <= 16 ? 16 : DF_JC); }
+
 template <typename T, typename F>
 __global__ void __launch_bounds__(256) direct_pred_kernel(F fn, int BB) {
   const int bz = blockIdx.z;
@@ -388,6 +393,10 @@ __global__ void __launch_bounds__(256) direct_pred_kernel(F fn, int BB) {
   const int N = g.N, rp0 = g.rp0, rp1 = g.rp1, rk0 = g.rk0, rk1 = g.rk1, n = g.n;
   const int h = g.hk, taps = 2 * g.hk + 1;
   const int taps_pad = (taps + DF_TB - 1) / DF_TB * DF_TB;
+  const int JC = direct_jc(N);
+  const int NB = DF_JC / JC;  // fibres per pass
+  // blocks are laid out for 32-column chunks; narrower chunks leave the
+  // surplus chunk indices idle
   const int njc = (N + DF_JC - 1) / DF_JC;
   const int nbb = (rp0 + BB - 1) / BB;
   int blk = blockIdx.x;
@@ -396,44 +405,63 @@ __global__ void __launch_bounds__(256) direct_pred_kernel(F fn, int BB) {
   const int bb = blk % nbb;
   const int al = blk / nbb;
   if (al >= rk0) return;
-  const int j0 = jc * DF_JC;
+  const int j0 = jc * JC;
+  if (j0 >= N) return;
   // padded fibre rows: output i reads rows i + h - m + front, m in [0, taps_pad)
   const int front = DF_TB;
   const int plen = front + n + 2 * h + 4 + DF_TB;
   const int pp = rp1 + 1;  // odd pitch: the 8 rows a wavefront reads fall in distinct banks
   extern __shared__ unsigned char smem_raw[];
-  T* Vs = reinterpret_cast<T*>(smem_raw);  // [taps_pad][rp1][DF_JC]
-  T* Ps = Vs + taps_pad * rp1 * DF_JC;     // [plen][pp]
-  T* Ks = Ps + plen * pp;                  // [taps][rk1] of row a
+  T* Vs = reinterpret_cast<T*>(smem_raw);  // [taps_pad][rp1][JC]
+  T* Ps = Vs + taps_pad * rp1 * JC;        // [NB][plen][pp]
+  T* Ks = Ps + NB * plen * pp;             // [taps][rk1] of row a
   const int tid = threadIdx.x;
   const T* kc = g.kcore + (long long)al * taps * rk1;
   for (int e = tid; e < taps * rk1; e += blockDim.x) Ks[e] = kc[e];
   __syncthreads();
-  // V for this (a, j-chunk); zero beyond taps and beyond N
-  for (int e = tid; e < taps_pad * rp1 * DF_JC; e += blockDim.x) {
-    const int m = e / (rp1 * DF_JC), rem = e - m * rp1 * DF_JC;
-    const int q = rem / DF_JC, jj = rem - q * DF_JC;
+  // V for this (a, j-chunk); zero beyond taps and beyond N.  A thread owns
+  // one (b', j) fibre: its rk1 (<= 32) values of L are loaded together, then
+  // every tap is a short dot product with the kernel row held in LDS.
+  for (int e = tid; e < rp1 * JC; e += blockDim.x) {
+    const int q = e / JC, jj = e - q * JC;
     const int j = j0 + jj;
-    T v = (T)0;
-    if (m < taps && j < N) {
-      const double* lc = g.lfac + (long long)q * g.gcap + j;  // row a' rp1 + q
-      for (int a2 = 0; a2 < rk1; ++a2) v += Ks[m * rk1 + a2] * (T)lc[(long long)a2 * rp1 * g.gcap];
+    T lv[32];
+    const double* lc = g.lfac + (long long)q * g.gcap + j;  // row a' rp1 + q
+#pragma unroll
+    for (int a2 = 0; a2 < 32; ++a2)
+      lv[a2] = (a2 < rk1 && j < N) ? (T)lc[(long long)a2 * rp1 * g.gcap] : (T)0;
+    for (int m = 0; m < taps_pad; ++m) {
+      T v = (T)0;
+      if (m < taps) {
+        const T* kr = Ks + m * rk1;
+#pragma unroll
+        for (int a2 = 0; a2 < 32; ++a2)
+          if (a2 < rk1) v += kr[a2] * lv[a2];
+      }
+      Vs[(m * rp1 + q) * JC + jj] = v;
     }
-    Vs[e] = v;
   }
-  const int ti = tid >> 3, tj = tid & 7;  // 32 row groups x 8 column groups
+  const int tjn = JC / 4;
+  const int ti = tid >> 3, r8 = tid & 7;  // 32 row groups x 8 (fibre, column group) slots
+  const int fib = r8 / tjn, tj = r8 - fib * tjn;
   const int jj0 = tj * 4;
-  for (int bo = 0; bo < BB; ++bo) {
-    const int be = bb * BB + bo;
-    if (be >= rp0) break;
-    __syncthreads();  // Vs ready / previous fibre consumed
-    const T* pc = g.p + (long long)be * n * rp1;
-    for (int e = tid; e < plen * rp1; e += blockDim.x) {
-      const int pr = e / rp1, q = e % rp1;
+  const T* Pf = Ps + fib * plen * pp;
+  for (int bo = 0; bo < BB; bo += NB) {
+    const int bfirst = bb * BB + bo;
+    if (bfirst >= rp0) break;
+    __syncthreads();  // Vs ready / previous fibres consumed
+    for (int e = tid; e < NB * plen * rp1; e += blockDim.x) {
+      const int f = e / (plen * rp1), rem = e - f * plen * rp1;
+      const int pr = rem / rp1, q = rem - pr * rp1;
       const int row = pr - front - h;
-      Ps[pr * pp + q] = (row >= 0 && row < n) ? pc[(long long)row * rp1 + q] : (T)0;
+      const int bf = bfirst + f;
+      T v = (T)0;
+      if (bf < rp0 && bo + f < BB && row >= 0 && row < n) v = g.p[((long long)bf * n + row) * rp1 + q];
+      Ps[(f * plen + pr) * pp + q] = v;
     }
     __syncthreads();
+    const int be = bfirst + fib;
+    if (be >= rp0 || bo + fib >= BB) continue;
     for (int i0 = ti * 4; i0 < n; i0 += 128) {
       T acc[4][4];
 #pragma unroll
@@ -442,15 +470,14 @@ __global__ void __launch_bounds__(256) direct_pred_kernel(F fn, int BB) {
         for (int c = 0; c < 4; ++c) acc[r][c] = (T)0;
       for (int q = 0; q < rp1; ++q) {
         for (int m0 = 0; m0 < taps_pad; m0 += DF_TB) {
-          // output i uses padded row front + i + 2h - (m + h) ... offset m in [0,2h]
-          // row index of P(i - (m - h)) in the padded fibre: front + h + i - m + h
+          // row of P(i - (m - h)) in the padded fibre: front + 2h + i - m - ...
           const int base = front + 2 * h + i0 - m0 - (DF_TB - 1);
           T w[4 + DF_TB - 1];
 #pragma unroll
-          for (int v = 0; v < 4 + DF_TB - 1; ++v) w[v] = Ps[(base + v) * pp + q];
+          for (int v = 0; v < 4 + DF_TB - 1; ++v) w[v] = Pf[(base + v) * pp + q];
 #pragma unroll
           for (int u = 0; u < DF_TB; ++u) {
-            const T* vr = Vs + ((m0 + u) * rp1 + q) * DF_JC + jj0;
+            const T* vr = Vs + ((m0 + u) * rp1 + q) * JC + jj0;
             const T v0 = vr[0], v1 = vr[1], v2 = vr[2], v3 = vr[3];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
