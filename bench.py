@@ -24,10 +24,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "TT-GBF filter steps/s (d=6,N=128,rank≤16) FP32 batch vs FP64 plain; grad ms/step"
 HBM_PEAK_GBS = 8000.0
-# published FP32 vector peak of MI355X (256 CUs x 2.4 GHz x 256 flops/clk,
-# counting packed FP32; ordinary FP32 FMAs issue at half that rate)
-FP32_VALU_PEAK_TFS = 157.3
-# HBM bytes per launch of direct_pred_kernel<float> from rocprofv3 FETCH_SIZE
+# published dense FP32 matrix-core peak of MI355X (256 CUs x 2.4 GHz x 256
+# flops/clk)
+FP32_MFMA_PEAK_TFS = 157.3
+# HBM bytes per launch of mfma_pred_kernel from rocprofv3 FETCH_SIZE
 # and WRITE_SIZE, scaled by the copy-kernel calibration; None until measured
 TRAFFIC = None
 
@@ -156,9 +156,9 @@ def main():
     ms = main_res["ms"]
     value = B * args.steps / (ms / 1000.0)
 
-    # roofline of the dominant kernel from the profiled window: the direct
-    # fused prediction (convolution + absorption of the next factor), FP32
-    # multiply-adds on the vector ALUs; its algorithmic flops and bytes come
+    # roofline of the dominant kernel from the profiled window: the fused
+    # prediction (convolution + absorption of the next factor), a dense FP32
+    # contraction on the matrix cores; its algorithmic flops and bytes come
     # from the library's work model evaluated on the device-resident ranks
     prof = main_res["prof"] or {}
     kernel_ms = {k: round(v[0] / max(args.profile_steps, 1), 3) for k, v in prof.items() if v[1]}
@@ -167,9 +167,9 @@ def main():
         ms_p, n_p, fl_p, by_p = prof["pred"]
         avg_s = ms_p / n_p / 1000.0
         achieved = fl_p / n_p / avg_s / 1e12
-        roof = {"bound": "alu", "achieved": round(achieved, 2), "peak": FP32_VALU_PEAK_TFS, "unit": "TFLOP/s",
-                "frac": round(achieved / FP32_VALU_PEAK_TFS, 4), "traffic": TRAFFIC,
-                "kernel": "direct_pred_kernel<float>", "avg_launch_ms": round(ms_p / n_p, 4),
+        roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": FP32_MFMA_PEAK_TFS, "unit": "TFLOP/s",
+                "frac": round(achieved / FP32_MFMA_PEAK_TFS, 4), "traffic": TRAFFIC,
+                "kernel": "mfma_pred_kernel<FFused<float>>", "avg_launch_ms": round(ms_p / n_p, 4),
                 "launches": n_p, "algorithmic_flops_per_launch": round(fl_p / n_p),
                 "algorithmic_bytes_per_launch": round(by_p / n_p),
                 "algorithmic_GBs": round(by_p / n_p / avg_s / 1e9, 1)}

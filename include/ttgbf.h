@@ -250,11 +250,15 @@ tt_status tt_filter_run(int32_t batch, const tt_filter_spec* specs, const tt_tra
  * the rounding's right-to-left sweep consumes, Sec. 2.1 eq. tpmconvFFT and
  * Sec. 4.2):
  *   0 (default) direct fused: the convolution and the absorption of L in
- *     one time-domain kernel; the product TT is never materialised;
+ *     one time-domain kernel; the product TT is never materialised.  FP32
+ *     runs it on the matrix cores (v_mfma_f32_16x16x4f32) when its LDS
+ *     tiles fit, FP64 on the vector ALUs;
  *   1 FFT fused: kernel-fibre spectra (computed once per kernel TT) times the
  *     spectra of P x_3 L, inverse FFT and crop, per output column in LDS;
  *   2 unfused: materialise the product (tt_predict's kernel) and absorb L
- *     with a tall GEMM.
+ *     with a tall GEMM;
+ *   3 direct fused on the vector ALUs for both precisions (mode 0 without
+ *     the matrix cores).
  * tt_predict always materialises the product.
  * --------------------------------------------------------------------- */
 tt_status tt_set_predict_mode(int32_t mode);

@@ -89,7 +89,7 @@ EXPORTED = ("tt_train_elems", "tt_last_error", "tt_version", "tt_kernel_build_wo
             "tt_normalize_moments", "tt_filter_run_workspace", "tt_filter_run", "tt_profile_begin",
             "tt_profile_end", "tt_set_predict_mode", "tt_get_predict_mode")
 
-PREDICT_DIRECT, PREDICT_FFT, PREDICT_UNFUSED = 0, 1, 2
+PREDICT_DIRECT, PREDICT_FFT, PREDICT_UNFUSED, PREDICT_DIRECT_VALU = 0, 1, 2, 3
 
 
 def set_predict_mode(mode: int):

@@ -10,6 +10,7 @@
 #include "linalg.h"
 #include "ttops.h"
 #include "fft.h"
+#include "pred_mfma.h"
 
 namespace ttg {
 
@@ -800,11 +801,37 @@ __global__ void __launch_bounds__(256) pred_work_kernel(FFused<T> fn, int B, dou
   }
 }
 
+// the FP32 direct prediction runs on the matrix cores unless mode 3 asks for
+// the vector-ALU kernel or the MFMA kernel's LDS would not fit
+template <typename T>
+static bool use_mfma_pred(int hmax, int nmax, int pcap, int kcap) {
+  return sizeof(T) == 4 && g_predict_mode != 3 && mfma_pred_fits(hmax, nmax, pcap, kcap);
+}
+
 template <typename T>
 static tt_status launch_direct(const RCtx& c, int B, int hmax, int kcap, int nmax, int pcap, int ncap,
                                hipStream_t st) {
   ProfScope ps_(PC_PRED, st);
   FFused<T> f{c};
+  if constexpr (sizeof(T) == 4) {
+    if (use_mfma_pred<T>(hmax, nmax, pcap, kcap)) {
+      const size_t ms = mfma_pred_smem(hmax, nmax, pcap, kcap);
+      if (ms > 48 * 1024)
+        HIP_TRY(hipFuncSetAttribute((const void*)mfma_pred_kernel<FFused<float>>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)ms),
+                "mfma prediction smem");
+      const int BB = B >= 64 ? 8 : 2;
+      const int grid = kcap * ((pcap + BB - 1) / BB);
+      hipLaunchKernelGGL((mfma_pred_kernel<FFused<float>>), dim3(std::max(1, grid), 1, B), dim3(256), ms, st, f,
+                         BB);
+      TTG_LAUNCH_CHECK("mfma_pred_kernel");
+      if (g_work && (g_prof_mask & (1 << PC_PRED))) {
+        hipLaunchKernelGGL((pred_work_kernel<T>), dim3(1), dim3(256), 0, st, f, B, g_work);
+        TTG_LAUNCH_CHECK("pred_work_kernel");
+      }
+      return TT_OK;
+    }
+  }
   const size_t smem = direct_smem<T>(hmax, nmax, pcap, kcap);
   if (smem > 160 * 1024) {
     set_error("direct prediction: %zu bytes of LDS needed", smem);
@@ -2236,7 +2263,9 @@ static tt_status run_plan(int32_t batch, const tt_filter_spec* specs, const tt_t
                               ? (f64 ? fused_smem<double>(p.Lmax, p.kcap, nmax, p.pcap)
                                      : fused_smem<float>(p.Lmax, p.kcap, nmax, p.pcap))
                               : (f64 ? direct_smem<double>(hmax, nmax, p.pcap, p.kcap)
-                                     : direct_smem<float>(hmax, nmax, p.pcap, p.kcap));
+                                     : (use_mfma_pred<float>(hmax, nmax, p.pcap, p.kcap)
+                                            ? mfma_pred_smem(hmax, nmax, p.pcap, p.kcap)
+                                            : direct_smem<float>(hmax, nmax, p.pcap, p.kcap)));
       if (need > 160 * 1024) {
         set_error("tt_filter_run: the fused prediction needs %zu bytes of LDS", need);
         return TT_ERR_SHAPE;
@@ -2483,8 +2512,8 @@ int32_t tt_profile_end(double* ms, int32_t* launches, double* flops, double* byt
 extern "C" {
 
 tt_status tt_set_predict_mode(int32_t mode) {
-  if (mode < 0 || mode > 2) {
-    set_error("tt_set_predict_mode: mode must be 0, 1 or 2");
+  if (mode < 0 || mode > 3) {
+    set_error("tt_set_predict_mode: mode must be 0, 1, 2 or 3");
     return TT_ERR_ARG;
   }
   g_predict_mode = mode;

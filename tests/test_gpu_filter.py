@@ -88,7 +88,7 @@ def test_per_axis_kernel_widths_fp64(mods, predict_mode):
     assert np.abs(run.mean.cpu().numpy()[0] - ref["mean"]).max() < 1e-10 * s.spacing()
 
 
-@pytest.mark.parametrize("predict_mode", [0, 1, 2], indirect=True)
+@pytest.mark.parametrize("predict_mode", [0, 1, 2, 3], indirect=True)
 def test_range_fp32_meets_reduced_precision_bars(mods, predict_mode):
     B, runner, wl = mods
     specs, xs, zs = wl.make_batch("range4d", batch=1, steps=6, d=3, n=40, cap=8)
@@ -117,3 +117,50 @@ def test_ragged_batch_equals_single_runs(mods):
         assert np.array_equal(one.mean.cpu().numpy()[0], run.mean.cpu().numpy()[b])
         ref = oracle_run(specs[b], zs[b])
         assert np.abs(run.log_c.cpu().numpy()[b] - ref["log_c"]).max() < 1e-9
+
+
+def fp32_bars(run, b, s, ref):
+    assert int(run.status.cpu()[b]) == 0
+    mean = run.mean.cpu().numpy()[b]
+    lc = run.log_c.cpu().numpy()[b]
+    assert np.abs(mean - ref["mean"]).max() < 1e-3 * s.spacing()
+    assert np.abs(lc - ref["log_c"]).max() < 1e-4
+
+
+@pytest.mark.parametrize("predict_mode", [0, 3], indirect=True)
+def test_per_axis_kernel_widths_fp32(mods, predict_mode):
+    # kernel fibres of different lengths per core on the FP32 prediction
+    # kernels (matrix-core and vector-ALU); n = 36 leaves a ragged 16-row tile
+    B, runner, wl = mods
+    s = wl.spec_range(3, 36, 8, sigma_w=[1.0, 0.6, 1.4])
+    x, z = wl.simulate(s, 5, np.random.SeedSequence(7))
+    ref = oracle_run(s, z)
+    run, _ = runner.run_filters([s], [z], B.F32)
+    fp32_bars(run, 0, s, ref)
+
+
+@pytest.mark.parametrize("predict_mode", [0, 3], indirect=True)
+def test_wide_bond_fp32(mods, predict_mode):
+    # rank cap 24: bonds that are not a multiple of 4 and more than 32
+    # columns in the absorbed factor (two column passes of the MFMA kernel)
+    B, runner, wl = mods
+    specs, xs, zs = wl.make_batch("range4d", batch=1, steps=5, d=3, n=40, cap=24)
+    s, z = specs[0], zs[0]
+    ref = oracle_run(s, z)
+    run, _ = runner.run_filters(specs, zs, B.F32)
+    fp32_bars(run, 0, s, ref)
+
+
+def test_fp32_batch_of_64_equals_single_runs(mods):
+    # a batch large enough for the wide launch shapes gives every filter
+    # bit-for-bit the result it gets alone
+    B, runner, wl = mods
+    specs, xs, zs = wl.make_batch("range6d_ragged", batch=64, steps=3, d=3)
+    for i, s in enumerate(specs):
+        s.n = (24, 32, 40)[i % 3]
+        s.cap = (4, 8, 6)[i % 3]
+    run, _ = runner.run_filters(specs, zs, B.F32)
+    for b in (0, 1, 2, 37, 63):
+        one, _ = runner.run_filters([specs[b]], [zs[b]], B.F32)
+        assert np.array_equal(one.log_c.cpu().numpy()[0], run.log_c.cpu().numpy()[b])
+        assert np.array_equal(one.mean.cpu().numpy()[0], run.mean.cpu().numpy()[b])
