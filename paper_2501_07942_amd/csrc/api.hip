@@ -491,6 +491,7 @@ struct FRlTrsm {
     a.q = qcore<T>(s, k);
     a.ldq = a.m;
     a.zt_n = (c.zt && k >= 1 && k <= c.d - 2) ? X.n[k] : 0;
+    a.wbuf = s.jac;  // free during the right-to-left sweep
     return true;
   }
 };
@@ -692,6 +693,15 @@ __global__ void round_norm_kernel(const DevTT* __restrict__ X, const RoundScratc
   }
 }
 
+// Workgroups per filter for a grid-stride kernel: enough to fill the chip
+// for this batch (about 4096 workgroups in all), never more than the
+// capacity needs.  Idle workgroups are not free: sizing by capacity alone
+// can cost more than the work.
+static int stride_grid(long long cap_blocks, int B) {
+  const long long want = std::max<long long>(4, 4096 / std::max(1, B));
+  return (int)std::max<long long>(1, std::min(cap_blocks, want));
+}
+
 template <typename F>
 static tt_status launch_pchol_any(bool f64, F f, int B, int gcap, hipStream_t st);
 
@@ -716,14 +726,15 @@ static tt_status launch_gram(F f, int B, int Mcap, long long Tcap, int smax, hip
   // (at most smax planes); wide Grams use 64x64 tiles with 4x4 blocking
   if (Mcap > 32) {
     const int t = (Mcap + 63) / 64;
+    // one workgroup per (tile pair, split) work item of the largest shape:
+    // these items are long enough that launching idle ones costs little
     hipLaunchKernelGGL((gram_partial_kernel<T, Acc, 64, F>), dim3(t * (t + 1) / 2, smax, B), dim3(256), 0, st, f);
   } else {
     hipLaunchKernelGGL((gram_partial_kernel<T, Acc, 32, F>), dim3(1, smax, B), dim3(256), 0, st, f);
   }
   TTG_LAUNCH_CHECK("gram_partial_kernel");
   const long long mm = (long long)Mcap * Mcap;
-  hipLaunchKernelGGL((gram_reduce_kernel<Acc, F>), dim3(std::max(1, std::min(cdiv(mm, 256), 1024)), 1, B),
-                     dim3(256), 0, st, f);
+  hipLaunchKernelGGL((gram_reduce_kernel<Acc, F>), dim3(stride_grid(cdiv(mm, 256), B), 1, B), dim3(256), 0, st, f);
   TTG_LAUNCH_CHECK("gram_reduce_kernel");
   return TT_OK;
 }
@@ -755,7 +766,8 @@ static tt_status launch_tall(F f, int B, long long Mcap, int Ncap, hipStream_t s
     HIP_TRY(hipFuncSetAttribute((const void*)tall_gemm_kernel<T, F>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)smem),
             "tall gemm smem attribute");
-  hipLaunchKernelGGL((tall_gemm_kernel<T, F>), dim3(std::max(1, cdiv(Mcap, RW)), 1, B), dim3(256), smem, st, f, G);
+  hipLaunchKernelGGL((tall_gemm_kernel<T, F>), dim3(stride_grid(cdiv(Mcap, RW), B), 1, B), dim3(256), smem, st, f,
+                     G);
   TTG_LAUNCH_CHECK("tall_gemm_kernel");
   return TT_OK;
 }
@@ -906,6 +918,16 @@ static tt_status launch_jacobi(F f, int B, hipStream_t st, int lds_doubles = JAC
 template <typename TZ, typename TQ, typename F>
 static tt_status launch_trsm(F f, int B, long long mcap, int rcap, hipStream_t st) {
   ProfScope ps_(PC_TRSM, st);
+  if constexpr (sizeof(TQ) == 4) {
+    // FP32 bulk: explicit inverse of the pivot block, then one thread per column
+    hipLaunchKernelGGL((tri_inverse_kernel<F>), dim3(1, 1, B), dim3(256), 0, st, f);
+    TTG_LAUNCH_CHECK("tri_inverse_kernel");
+    hipLaunchKernelGGL((tri_apply_kernel<TZ, TQ, F>), dim3(stride_grid(cdiv(mcap, 256), B), 1, B), dim3(256), 0,
+                       st, f);
+    TTG_LAUNCH_CHECK("tri_apply_kernel");
+    (void)rcap;
+    return TT_OK;
+  }
   const size_t qbytes = (size_t)rcap * 64 * sizeof(double);
   const size_t lbytes = (size_t)rcap * rcap * sizeof(double);
   const int l_in_lds = (qbytes + lbytes <= 150 * 1024) ? 1 : 0;
@@ -1512,7 +1534,7 @@ static tt_status launch_hadamard(int B, int d, int r0cap, const DevTT* dl, const
   hipLaunchKernelGGL(product_init_kernel, dim3(cdiv(B, 64)), dim3(64), 0, st, dl, dp, dh, B);
   TTG_LAUNCH_CHECK("product_init_kernel");
   ProfScope ps_(PC_HADAMARD, st);
-  hipLaunchKernelGGL((hadamard_kernel<T>), dim3(r0cap, d, B), dim3(256), 0, st, dl, dp, dh);
+  hipLaunchKernelGGL((hadamard_kernel<T>), dim3(stride_grid(r0cap, B), d, B), dim3(256), 0, st, dl, dp, dh);
   TTG_LAUNCH_CHECK("hadamard_kernel");
   return TT_OK;
 }

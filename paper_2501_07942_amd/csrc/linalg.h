@@ -404,6 +404,7 @@ struct TrsmArgs {
   void* q;
   long long ldq;
   int zt_n;  // 0: Z columns in output order; n: Z columns ordered (j, i), output c = i*(m/n) + j
+  double* wbuf;  // gcap x gcap FP64 scratch for the explicit inverse (tri_* kernels)
 };
 
 template <typename TZ, typename TQ, typename F>
@@ -438,6 +439,85 @@ __global__ void __launch_bounds__(64) trsm_kernel(F f, int rcap, int l_in_lds) {
     const double v = s / lrow[j];
     qs[j * 64 + threadIdx.x] = v;
     if (live) q[(long long)j * a.ldq + c] = from_double<TQ>(v);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The same Q = L_pp^{-1} Z_p through an explicit inverse (FP32 bulk path,
+// where the factor's conditioning is bounded by the FP32 pre-truncation):
+// tri_inverse_kernel forms W = L_pp^{-1} (one filter per workgroup; thread c
+// solves L_pp w = e_c for its own column, so threads never wait for each
+// other) and stores column c of W contiguously, wt[c * gcap + j] = W(j, c),
+// zeros above the diagonal.  tri_apply_kernel gives each output column to
+// one thread, which accumulates 32 rows at a time in FP64 registers while W
+// is read with wave-uniform loads.
+// ---------------------------------------------------------------------------
+template <typename F>
+__global__ void __launch_bounds__(256) tri_inverse_kernel(F f) {
+  const int b = blockIdx.z;
+  TrsmArgs a;
+  if (!f(b, a)) return;
+  double* wt = a.wbuf;
+  for (int c = threadIdx.x; c < a.r; c += blockDim.x) {
+    double* w = wt + (long long)c * a.gcap;
+    for (int j = 0; j < c; ++j) w[j] = 0.0;
+    for (int j = c; j < a.r; ++j) {
+      const double* lrow = a.lfac + (long long)a.piv[j] * a.gcap;
+      double s = (j == c) ? 1.0 : 0.0;
+      for (int t = c; t < j; ++t) s = __fma_rn(-lrow[t], w[t], s);
+      w[j] = s / lrow[j];
+    }
+  }
+}
+
+#define TA_ROWS 32
+#define TA_TMAX 128  // largest pivot block (the FP32 pre-truncated rank capacity)
+template <typename TZ, typename TQ, typename F>
+__global__ void __launch_bounds__(256) tri_apply_kernel(F f) {
+  const int b = blockIdx.z;
+  TrsmArgs a;
+  if (!f(b, a)) return;
+  if (blockIdx.x * 256 >= a.m) return;
+  __shared__ double ws[TA_TMAX * TA_ROWS];  // W(j0 + u, t) at ws[t * 32 + u], zero past row r
+  const TZ* z = reinterpret_cast<const TZ*>(a.z);
+  TQ* q = reinterpret_cast<TQ*>(a.q);
+  const double* wt = a.wbuf;
+  const int r = min(a.r, TA_TMAX);
+  for (int j0 = 0; j0 < r; j0 += TA_ROWS) {
+    const int tend = min(r, j0 + TA_ROWS);  // W(j, t) = 0 for t > j
+    const int jn = min(TA_ROWS, r - j0);
+    __syncthreads();  // previous chunk consumed
+    for (int e = threadIdx.x; e < tend * TA_ROWS; e += blockDim.x) {
+      const int t = e / TA_ROWS, u = e - t * TA_ROWS;
+      ws[e] = u < jn ? wt[(long long)t * a.gcap + j0 + u] : 0.0;
+    }
+    __syncthreads();
+    // grid-stride over 256-column blocks: the grid is sized for the usual
+    // width, not the capacity, so few workgroups start with nothing to do
+    for (int cb = blockIdx.x; cb * 256 < a.m; cb += gridDim.x) {
+      const int c = cb * 256 + threadIdx.x;
+      const bool live = c < a.m;
+      long long zc = live ? c : 0;
+      if (a.zt_n) {
+        const int nn = a.m / a.zt_n;
+        zc = (long long)(zc % nn) * a.zt_n + zc / nn;
+      }
+      double acc[TA_ROWS];
+#pragma unroll
+      for (int u = 0; u < TA_ROWS; ++u) acc[u] = 0.0;
+#pragma unroll 2
+      for (int t = 0; t < tend; ++t) {
+        const double zv = bulk_to_double(z[(long long)a.piv[t] * a.ldz + zc]);
+        const double* wrow = ws + t * TA_ROWS;
+#pragma unroll
+        for (int u = 0; u < TA_ROWS; ++u) acc[u] = __fma_rn(wrow[u], zv, acc[u]);
+      }
+      if (live) {
+#pragma unroll
+        for (int u = 0; u < TA_ROWS; ++u)
+          if (u < jn) q[(long long)(j0 + u) * a.ldq + c] = from_double<TQ>(acc[u]);
+      }
+    }
   }
 }
 
@@ -542,8 +622,6 @@ __global__ void __launch_bounds__(256) tall_gemm_kernel(F f, int Gmax) {
   while (32 * G < g.N && G < Gmax) G *= 2;
   if (g.N > 32 * G) return;
   const int RW = 256 / G;  // rows per workgroup
-  const int m0 = blockIdx.x * RW;
-  if (m0 >= g.M) return;
   extern __shared__ unsigned char smem_raw[];
   T* Xs = reinterpret_cast<T*>(smem_raw);   // [RW][KC+1]
   T* Ls = Xs + RW * (TSK_KC + 1);           // [KC][32*G]
@@ -552,6 +630,7 @@ __global__ void __launch_bounds__(256) tall_gemm_kernel(F f, int Gmax) {
   const int NW = 32 * G;
   const T* A = reinterpret_cast<const T*>(g.a);
   const double* Bm = reinterpret_cast<const double*>(g.b);
+  for (int m0 = blockIdx.x * RW; m0 < g.M; m0 += gridDim.x * RW) {
   T acc[32];
 #pragma unroll
   for (int c = 0; c < 32; ++c) acc[c] = (T)0;
@@ -585,5 +664,6 @@ __global__ void __launch_bounds__(256) tall_gemm_kernel(F f, int Gmax) {
       const int n = cg * 32 + c;
       if (n < g.N) C[n] = acc[c];
     }
+  }
   }
 }

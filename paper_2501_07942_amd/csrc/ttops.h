@@ -135,18 +135,25 @@ __global__ void __launch_bounds__(256) hadamard_kernel(const DevTT* __restrict__
   const int rl0 = L.ranks[k], rl1 = L.ranks[k + 1];
   const int rp0 = P.ranks[k], rp1 = P.ranks[k + 1];
   const int R0 = rl0 * rp0, R1 = rl1 * rp1;
-  if ((int)blockIdx.x >= R0) return;
   if (R0 > H.cap[k] || R1 > H.cap[k + 1]) return;
-  const int a = blockIdx.x / rp0, b = blockIdx.x % rp0;
   const int n = P.n[k];
-  const double* lc = core_ptr<double>(L, k) + (long long)a * n * rl1;
-  const T* pc = core_ptr<T>(P, k) + (long long)b * n * rp1;
-  T* hc = core_ptr<T>(H, k) + (long long)blockIdx.x * n * R1;
-  const long long tot = (long long)n * R1;
-  for (long long e = threadIdx.x; e < tot; e += blockDim.x) {
-    const int i = (int)(e / R1), j = (int)(e % R1);
-    const int a2 = j / rp1, b2 = j % rp1;
-    hc[e] = from_double<T>(lc[(long long)i * rl1 + a2] * bulk_to_double(pc[(long long)i * rp1 + b2]));
+  // grid-stride over the rows (a, b) of the output core; within a row the
+  // threads take fixed columns j = (a', b') and step over the grid index i
+  const int lanes = max(1, (int)blockDim.x / R1);  // threads per column (R1 < 256)
+  const int jstep = lanes > 1 ? R1 : (int)blockDim.x;
+  const int j0 = lanes > 1 ? (int)threadIdx.x % R1 : (int)threadIdx.x;
+  const int i0 = lanes > 1 ? (int)threadIdx.x / R1 : 0;
+  if (i0 >= lanes) return;
+  for (int row = blockIdx.x; row < R0; row += gridDim.x) {
+    const int a = row / rp0, b = row % rp0;
+    const double* lc = core_ptr<double>(L, k) + (long long)a * n * rl1;
+    const T* pc = core_ptr<T>(P, k) + (long long)b * n * rp1;
+    T* hc = core_ptr<T>(H, k) + (long long)row * n * R1;
+    for (int j = j0; j < R1; j += jstep) {
+      const int a2 = j / rp1, b2 = j - (j / rp1) * rp1;
+      for (int i = i0; i < n; i += lanes)
+        hc[(long long)i * R1 + j] = from_double<T>(lc[(long long)i * rl1 + a2] * bulk_to_double(pc[(long long)i * rp1 + b2]));
+    }
   }
 }
 
