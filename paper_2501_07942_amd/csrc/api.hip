@@ -4,6 +4,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "common.h"
@@ -723,14 +724,18 @@ static tt_status launch_gram(F f, int B, int Mcap, long long Tcap, int smax, hip
   ProfScope ps_(PC_GRAM, st);
   (void)Tcap;
   // the split count a filter uses is derived on the device from its own T
-  // (at most smax planes); wide Grams use 64x64 tiles with 4x4 blocking
-  if (Mcap > 32) {
-    const int t = (Mcap + 63) / 64;
-    // one workgroup per (tile pair, split) work item of the largest shape:
-    // these items are long enough that launching idle ones costs little
-    hipLaunchKernelGGL((gram_partial_kernel<T, Acc, 64, F>), dim3(t * (t + 1) / 2, smax, B), dim3(256), 0, st, f);
+  // (at most smax planes).  FP64 accumulation runs on the matrix cores for
+  // every size, so that each element's summation order depends on the
+  // filter alone; double-double accumulation uses the vector ALUs with
+  // 32 x 32 or 64 x 64 tiles (both sum every element in the same order).
+  const int t = (Mcap + 63) / 64;
+  if constexpr (std::is_same<Acc, AccD>::value) {
+    hipLaunchKernelGGL((gram_mfma_kernel<T, F>), dim3(t * (t + 1) / 2, smax, B), dim3(256), 0, st, f);
   } else {
-    hipLaunchKernelGGL((gram_partial_kernel<T, Acc, 32, F>), dim3(1, smax, B), dim3(256), 0, st, f);
+    if (Mcap > 32)
+      hipLaunchKernelGGL((gram_partial_kernel<T, Acc, 64, F>), dim3(t * (t + 1) / 2, smax, B), dim3(256), 0, st, f);
+    else
+      hipLaunchKernelGGL((gram_partial_kernel<T, Acc, 32, F>), dim3(1, smax, B), dim3(256), 0, st, f);
   }
   TTG_LAUNCH_CHECK("gram_partial_kernel");
   const long long mm = (long long)Mcap * Mcap;

@@ -106,6 +106,111 @@ __global__ void __launch_bounds__(256) gram_partial_kernel(F f) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// The same Gram partials with FP64 accumulation on the matrix cores
+// (v_mfma_f64_16x16x4f64): one 64 x 64 upper-triangular tile pair and one
+// split per workgroup, each wavefront a 32 x 32 quadrant (2 x 2 MFMA tiles).
+// A chunk of 32 summation indices of both row blocks is staged in LDS as
+// FP64; within a chunk the k-lane lk of an MFMA step s takes index
+// lk * 8 + s, so a lane reads its eight operands as one contiguous run.
+// Products of FP32 inputs are exact in FP64.  Lane layout of the MFMA:
+// A(i, k) in lane i + 16 k, B(k, j) in lane j + 16 k, D(i, j) in lane
+// j + 16 (i % 4), register i / 4.
+// ---------------------------------------------------------------------------
+typedef double md4 __attribute__((ext_vector_type(4)));
+#define GM_KC 32
+#define GM_PITCH (GM_KC + 2)
+
+template <typename TB, typename F>
+__global__ void __launch_bounds__(256) gram_mfma_kernel(F f) {
+  const int b = blockIdx.z;
+  GramArgs g;
+  if (!f(b, g)) return;
+  g.splits = gram_split_count(g.T, g.splits);
+  const int ntile = (g.M + 63) / 64;
+  int tp = blockIdx.x, ti = 0;
+  while (ti < ntile && tp >= ntile - ti) {
+    tp -= ntile - ti;
+    ++ti;
+  }
+  if (ti >= ntile) return;
+  const int tj = ti + tp;
+  const int s = blockIdx.y;
+  if (s >= g.splits) return;
+  const int chunk = (g.T + g.splits - 1) / g.splits;
+  const int t_begin = s * chunk, t_end = min(g.T, t_begin + chunk);
+  __shared__ double As[64 * GM_PITCH];
+  __shared__ double Bs[64 * GM_PITCH];
+  const bool diag_tile = ti == tj;
+  const double* Bsrc = diag_tile ? As : Bs;
+  const TB* x = reinterpret_cast<const TB*>(g.x);
+  const bool t_fast = g.st == 1;
+  const int a0 = ti * 64, b0 = tj * 64;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int qa = wv >> 1, qb = wv & 1;
+  const int lr = lane & 15, lk = lane >> 4;
+  md4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = md4{0.0, 0.0, 0.0, 0.0};
+  for (int t0 = t_begin; t0 < t_end; t0 += GM_KC) {
+    __syncthreads();  // previous chunk consumed
+    for (int e = tid; e < 64 * GM_KC; e += blockDim.x) {
+      int r, c;
+      if (t_fast) {
+        r = e / GM_KC;
+        c = e - r * GM_KC;
+      } else {
+        c = e / 64;
+        r = e - c * 64;
+      }
+      const int t = t0 + c;
+      double va = 0.0, vb = 0.0;
+      if (t < t_end) {
+        if (a0 + r < g.M) va = bulk_to_double(x[(long long)(a0 + r) * g.sa + (long long)t * g.st]);
+        if (!diag_tile && b0 + r < g.M) vb = bulk_to_double(x[(long long)(b0 + r) * g.sa + (long long)t * g.st]);
+      }
+      As[r * GM_PITCH + c] = va;
+      if (!diag_tile) Bs[r * GM_PITCH + c] = vb;
+    }
+    __syncthreads();
+    double av[2][8], bv[2][8];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const double* pa = As + (qa * 32 + i * 16 + lr) * GM_PITCH + lk * 8;
+      const double* pb = Bsrc + (qb * 32 + i * 16 + lr) * GM_PITCH + lk * 8;
+#pragma unroll
+      for (int u = 0; u < 8; u += 2) {
+        const double2 ta = *reinterpret_cast<const double2*>(pa + u);
+        const double2 tb = *reinterpret_cast<const double2*>(pb + u);
+        av[i][u] = ta.x;
+        av[i][u + 1] = ta.y;
+        bv[i][u] = tb.x;
+        bv[i][u + 1] = tb.y;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][u], bv[j][u], acc[i][j], 0, 0, 0);
+  }
+  double* out = g.out + (long long)s * g.gcap * g.gcap;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int a = a0 + qa * 32 + i * 16 + lk + 4 * v;
+        const int c = b0 + qb * 32 + j * 16 + lr;
+        if (a < g.M && c < g.M) out[(long long)a * g.gcap + c] = acc[i][j][v];
+      }
+}
+
 template <typename Acc, typename F>
 __global__ void __launch_bounds__(256) gram_reduce_kernel(F f) {
   const int b = blockIdx.z;
