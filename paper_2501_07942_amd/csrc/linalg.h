@@ -402,6 +402,137 @@ struct JacobiArgs {
   int gcap;
 };
 
+// Rotation of one-sided Jacobi (Hestenes) for the column pair with squared
+// norms al, be and inner product ga (Rutishauser's formulas):
+//   zeta = (be - al) / (2 ga),  t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)),
+//   c = 1 / sqrt(1 + t^2),  s = c t.
+// Returns false when the pair is already orthogonal to relative tolerance
+// 1e-15 (ga^2 <= 1e-30 al be).  Reciprocals and reciprocal square roots start
+// from the hardware approximations and take two Newton steps each, which
+// reaches FP64 accuracy with a much shorter dependency chain than IEEE
+// division and square root.
+__device__ inline double jac_rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __fma_rn(-x, r, 1.0);
+  r = __fma_rn(r, e, r);
+  e = __fma_rn(-x, r, 1.0);
+  return __fma_rn(r, e, r);
+}
+__device__ inline double jac_rsq(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double h = 0.5 * x * y;
+  double e = __fma_rn(-h, y, 0.5);
+  y = __fma_rn(y, e, y);
+  h = 0.5 * x * y;
+  e = __fma_rn(-h, y, 0.5);
+  return __fma_rn(y, e, y);
+}
+__device__ inline bool jac_rotation(double al, double be, double ga, double& cs, double& sn) {
+  if (!(ga != 0.0 && ga * ga > 1e-30 * (al * be))) return false;
+  const double zeta = (be - al) * 0.5 * jac_rcp(ga);
+  const double s1 = __fma_rn(zeta, zeta, 1.0);
+  const double root = s1 * jac_rsq(s1);
+  const double t = (zeta >= 0.0 ? 1.0 : -1.0) * jac_rcp(fabs(zeta) + root);
+  cs = jac_rsq(__fma_rn(t, t, 1.0));
+  sn = cs * t;
+  return true;
+}
+
+// One-sided Jacobi for at most JW_NMAX columns, run by a single wavefront:
+// the n/2 column pairs of a round each get LP = 64 / (n/2) lanes (rounded
+// down to a power of two), which split the rows and reduce the three dot
+// products with log2(LP) lane exchanges.  Same round-robin pairing, rotation
+// and stopping rule as the workgroup version below.  Writes sigma (descending)
+// and the scaled left vectors like it.
+#define JW_NMAX 64
+__device__ inline double jw_group_sum(double v, int lp) {
+  for (int o = lp >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ inline void jacobi_wave(double* W, long long ldw, int rows, int nc, double* s_sig, const JacobiArgs& J) {
+  const int lane = threadIdx.x & 63;
+  const int n = (nc + 1) & ~1;
+  const int npair = n / 2;
+  int lp = 64;
+  while (lp > 1 && lp * npair > 64) lp >>= 1;
+  const int grp = lane / lp, lip = lane - grp * lp;
+  const int ngrp = 64 / lp;
+  for (int sweep = 0; sweep < 60 && n >= 2; ++sweep) {
+    int rot = 0;
+    for (int r = 0; r < n - 1; ++r) {
+      for (int i0 = 0; i0 < npair; i0 += ngrp) {
+        const int i = i0 + grp;
+        int pc = -1, qc = -1;
+        if (i < npair) {
+          if (i == 0) {
+            pc = n - 1;
+            qc = r;
+          } else {
+            pc = (r + i) % (n - 1);
+            qc = (r - i + (n - 1)) % (n - 1);
+          }
+        }
+        const bool live = i < npair && pc < nc && qc < nc;
+        double* xp = W + (long long)(live ? pc : 0) * ldw;
+        double* xq = W + (long long)(live ? qc : 0) * ldw;
+        double al = 0.0, be = 0.0, ga = 0.0;
+        if (live)
+          for (int k = lip; k < rows; k += lp) {
+            const double u = xp[k], v = xq[k];
+            al = __fma_rn(u, u, al);
+            be = __fma_rn(v, v, be);
+            ga = __fma_rn(u, v, ga);
+          }
+        al = jw_group_sum(al, lp);
+        be = jw_group_sum(be, lp);
+        ga = jw_group_sum(ga, lp);
+        double cs, sn;
+        if (live && jac_rotation(al, be, ga, cs, sn)) {
+          for (int k = lip; k < rows; k += lp) {
+            const double u = xp[k], v = xq[k];
+            xp[k] = cs * u - sn * v;
+            xq[k] = sn * u + cs * v;
+          }
+          rot = 1;
+        }
+        // the next round reads columns other lanes just rotated
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      }
+    }
+    // any lane rotated in this sweep?
+    const unsigned long long any = __ballot(rot);
+    if (!any) break;
+  }
+  // column norms
+  for (int c = lane; c < nc; c += 64) {
+    const double* xc = W + (long long)c * ldw;
+    double s = 0.0;
+    for (int k = 0; k < rows; ++k) s = __fma_rn(xc[k], xc[k], s);
+    s_sig[c] = sqrt(s);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  // rank of each column in descending order (ties by index)
+  for (int c = 0; c < nc; ++c) {
+    const double sc = s_sig[c];
+    int rk = 0;
+    for (int o = lane; o < nc; o += 64) {
+      const double so = s_sig[o];
+      rk += (so > sc || (so == sc && o < c)) ? 1 : 0;
+    }
+    for (int o = 32; o > 0; o >>= 1) rk += __shfl_xor(rk, o, 64);
+    if (lane == 0) J.sigma[rk] = sc;
+    const double* xc = W + (long long)c * ldw;
+    double* dst = J.usv + (long long)rk * J.gcap;
+    for (int k = lane; k < rows; k += 64) dst[k] = xc[k];
+  }
+  if (lane == 0 && J.ncols_out) *J.ncols_out = nc;
+}
+
 template <typename F>
 __global__ void __launch_bounds__(512) jacobi_kernel(F f, int lds_doubles) {
   const int b = blockIdx.x;
@@ -423,6 +554,12 @@ __global__ void __launch_bounds__(512) jacobi_kernel(F f, int lds_doubles) {
   __shared__ double s_sig[1024];
   __syncthreads();
   const int n = (nc + 1) & ~1;  // even number of players (one may be a dummy)
+  if (n <= JW_NMAX && rows <= 64) {
+    // small problem: wavefront 0 runs every sweep alone (no block barriers);
+    // decided per filter, so a filter's result does not depend on its batch
+    if (wid == 0) jacobi_wave(W, ldw, rows, nc, s_sig, J);
+    return;
+  }
   for (int sweep = 0; sweep < 60 && n >= 2; ++sweep) {
     if (tid == 0) s_rot = 0;
     __syncthreads();
@@ -449,10 +586,8 @@ __global__ void __launch_bounds__(512) jacobi_kernel(F f, int lds_doubles) {
         al = wave_sum(al);
         be = wave_sum(be);
         ga = wave_sum(ga);
-        if (ga != 0.0 && fabs(ga) > 1e-15 * sqrt(al * be)) {
-          const double zeta = (be - al) / (2.0 * ga);
-          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+        double cs, sn;
+        if (jac_rotation(al, be, ga, cs, sn)) {
           for (int k = lane; k < rows; k += 64) {
             const double u = xp[k], v = xq[k];
             xp[k] = cs * u - sn * v;
