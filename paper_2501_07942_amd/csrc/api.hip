@@ -698,8 +698,8 @@ __global__ void round_norm_kernel(const DevTT* __restrict__ X, const RoundScratc
 // for this batch (about 4096 workgroups in all), never more than the
 // capacity needs.  Idle workgroups are not free: sizing by capacity alone
 // can cost more than the work.
-static int stride_grid(long long cap_blocks, int B) {
-  const long long want = std::max<long long>(4, 4096 / std::max(1, B));
+static int stride_grid(long long cap_blocks, int B, int target = 4096) {
+  const long long want = std::max<long long>(4, target / std::max(1, B));
   return (int)std::max<long long>(1, std::min(cap_blocks, want));
 }
 
@@ -744,9 +744,28 @@ static tt_status launch_gram(F f, int B, int Mcap, long long Tcap, int smax, hip
   return TT_OK;
 }
 
+// FP32 products run on the matrix cores (for every shape, so a filter's
+// result does not depend on its batch); 128 x 32 tiles when no filter has
+// more than 32 columns
+template <typename TA, typename TB, typename F>
+static tt_status launch_gemm_mfma(F f, int B, long long Mcap, long long Ncap, hipStream_t st) {
+  if (Ncap <= 32) {
+    const long long tiles = std::max(1, cdiv(Mcap, 128));
+    hipLaunchKernelGGL((gemm_mfma_kernel<TA, TB, 32, F>), dim3(stride_grid(tiles, B, 16384), 1, B), dim3(256), 0, st,
+                       f);
+  } else {
+    const long long tiles = (long long)std::max(1, cdiv(Mcap, 64)) * std::max(1, cdiv(Ncap, 64));
+    hipLaunchKernelGGL((gemm_mfma_kernel<TA, TB, 64, F>), dim3(stride_grid(tiles, B, 16384), 1, B), dim3(256), 0, st,
+                       f);
+  }
+  TTG_LAUNCH_CHECK("gemm_mfma_kernel");
+  return TT_OK;
+}
+
 template <typename TA, typename TB, typename TC, typename TAcc, typename F>
 static tt_status launch_gemm(F f, int B, long long Mcap, long long Ncap, hipStream_t st) {
   ProfScope ps_(PC_GEMM, st);
+  if constexpr (std::is_same<TC, float>::value) return launch_gemm_mfma<TA, TB>(f, B, Mcap, Ncap, st);
   const int tm = std::max(1, cdiv(Mcap, 64)), tn = std::max(1, cdiv(Ncap, 64));
   hipLaunchKernelGGL((gemm_kernel<TA, TB, TC, TAcc, F>), dim3(tn, tm, B), dim3(256), 0, st, f);
   TTG_LAUNCH_CHECK("gemm_kernel");
@@ -757,6 +776,7 @@ static tt_status launch_gemm(F f, int B, long long Mcap, long long Ncap, hipStre
 template <typename T, typename F>
 static tt_status launch_tall(F f, int B, long long Mcap, int Ncap, hipStream_t st) {
   ProfScope ps_(PC_GEMM, st);
+  if constexpr (std::is_same<T, float>::value) return launch_gemm_mfma<float, double>(f, B, Mcap, Ncap, st);
   if (Ncap > 256) {
     set_error("tall GEMM: N capacity %d > 256", Ncap);
     return TT_ERR_SHAPE;

@@ -843,6 +843,101 @@ __global__ void __launch_bounds__(256) gemm_kernel(F f) {
 }
 
 // ---------------------------------------------------------------------------
+// FP32 GEMM on the matrix cores, C(m, n) = sum_k A(m, k) B(k, n), FP32 output
+// (A, B FP32 or FP64, rounded to FP32 as they are staged; FP32 accumulation
+// with v_mfma_f32_16x16x4f32).  Output tiles of TM x TN (64 x 64, or
+// 128 x 32 for tall-skinny products), a 32 x 32 quadrant per wavefront,
+// chunks of 16 k staged in LDS with each lane's four operands of a chunk
+// contiguous (k-lane lk takes k = 4 lk + s in step s).  The workgroups of a
+// filter stride over its tiles.  Every element sums its k in the same order
+// for any tile shape, so the result does not depend on the launch shape.
+// ---------------------------------------------------------------------------
+typedef float gf4 __attribute__((ext_vector_type(4)));
+#define GF_KC 16
+#define GF_PITCH (GF_KC + 4)
+template <typename TA, typename TB, int TN, typename F>
+__global__ void __launch_bounds__(256) gemm_mfma_kernel(F f) {
+  constexpr int TM = 8192 / (TN * 2);  // 64 x 64 or 128 x 32
+  constexpr int QN = TN / 32;          // quadrants across n
+  const int bz = blockIdx.z;
+  GemmArgs g;
+  if (!f(bz, g)) return;
+  __shared__ float As[TM * GF_PITCH];
+  __shared__ float Bs[TN * GF_PITCH];
+  const TA* A = reinterpret_cast<const TA*>(g.a);
+  const TB* Bm = reinterpret_cast<const TB*>(g.b);
+  float* C = reinterpret_cast<float*>(g.c);
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int qa = wv / QN, qb = wv - (wv / QN) * QN;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int tnn = (g.N + TN - 1) / TN;
+  const int ntiles = ((g.M + TM - 1) / TM) * tnn;
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int m0 = (tile / tnn) * TM, n0 = (tile - (tile / tnn) * tnn) * TN;
+    gf4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = gf4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < g.K; k0 += GF_KC) {
+      __syncthreads();  // previous chunk consumed
+      for (int e = tid; e < TM * GF_KC; e += 256) {
+        int m, kk;
+        if (g.sak == 1) {
+          m = e / GF_KC;
+          kk = e - m * GF_KC;
+        } else {
+          kk = e / TM;
+          m = e - kk * TM;
+        }
+        const int mg = m0 + m, k = k0 + kk;
+        As[m * GF_PITCH + kk] = (mg < g.M && k < g.K) ? (float)A[(long long)mg * g.sam + (long long)k * g.sak] : 0.f;
+      }
+      for (int e = tid; e < TN * GF_KC; e += 256) {
+        int n, kk;
+        if (g.sbn == 1) {
+          kk = e / TN;
+          n = e - kk * TN;
+        } else {
+          n = e / GF_KC;
+          kk = e - n * GF_KC;
+        }
+        const int ng = n0 + n, k = k0 + kk;
+        Bs[n * GF_PITCH + kk] = (ng < g.N && k < g.K) ? (float)Bm[(long long)k * g.sbk + (long long)ng * g.sbn] : 0.f;
+      }
+      __syncthreads();
+      float4 av[2], bv[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        av[i] = *reinterpret_cast<const float4*>(As + (qa * 32 + i * 16 + lr) * GF_PITCH + lk * 4);
+        bv[i] = *reinterpret_cast<const float4*>(Bs + (qb * 32 + i * 16 + lr) * GF_PITCH + lk * 4);
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].x, bv[j].x, acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].y, bv[j].y, acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].z, bv[j].z, acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].w, bv[j].w, acc[i][j], 0, 0, 0);
+        }
+    }
+    // D layout: lane (lr, lk), register v holds row 4 lk + v, column lr
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int m = m0 + qa * 32 + i * 16 + 4 * lk + v;
+          const int n = n0 + qb * 32 + j * 16 + lr;
+          if (m < g.M && n < g.N) C[(long long)m * g.scm + (long long)n * g.scn] = acc[i][j][v];
+        }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Tall-skinny GEMM  C(m, n) = sum_k A(m, k) B(k, n)  for M >> K, N <= 128:
 // A and C row-major (bulk type), B row-major FP64 (ld sbk).  Each thread owns
 // one row and a group of 32 output columns (accumulators in registers); a
