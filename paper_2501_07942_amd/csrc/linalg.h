@@ -155,9 +155,14 @@ __global__ void __launch_bounds__(256) gram_mfma_kernel(F f) {
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = md4{0.0, 0.0, 0.0, 0.0};
-  for (int t0 = t_begin; t0 < t_end; t0 += GM_KC) {
-    __syncthreads();  // previous chunk consumed
-    for (int e = tid; e < 64 * GM_KC; e += blockDim.x) {
+  // each thread stages GM_PER elements of both row blocks per chunk; the
+  // next chunk is loaded into registers while the current one is multiplied
+  constexpr int GM_PER = 64 * GM_KC / 256;
+  TB pa_[GM_PER], pb_[GM_PER];
+  auto fetch = [&](int t0) {
+#pragma unroll
+    for (int u = 0; u < GM_PER; ++u) {
+      const int e = tid + u * 256;
       int r, c;
       if (t_fast) {
         r = e / GM_KC;
@@ -167,15 +172,30 @@ __global__ void __launch_bounds__(256) gram_mfma_kernel(F f) {
         r = e - c * 64;
       }
       const int t = t0 + c;
-      double va = 0.0, vb = 0.0;
-      if (t < t_end) {
-        if (a0 + r < g.M) va = bulk_to_double(x[(long long)(a0 + r) * g.sa + (long long)t * g.st]);
-        if (!diag_tile && b0 + r < g.M) vb = bulk_to_double(x[(long long)(b0 + r) * g.sa + (long long)t * g.st]);
+      const bool tv = t < t_end;
+      pa_[u] = (tv && a0 + r < g.M) ? x[(long long)(a0 + r) * g.sa + (long long)t * g.st] : (TB)0;
+      pb_[u] = (!diag_tile && tv && b0 + r < g.M) ? x[(long long)(b0 + r) * g.sa + (long long)t * g.st] : (TB)0;
+    }
+  };
+  if (t_begin < t_end) fetch(t_begin);
+  for (int t0 = t_begin; t0 < t_end; t0 += GM_KC) {
+    __syncthreads();  // previous chunk consumed
+#pragma unroll
+    for (int u = 0; u < GM_PER; ++u) {
+      const int e = tid + u * 256;
+      int r, c;
+      if (t_fast) {
+        r = e / GM_KC;
+        c = e - r * GM_KC;
+      } else {
+        c = e / 64;
+        r = e - c * 64;
       }
-      As[r * GM_PITCH + c] = va;
-      if (!diag_tile) Bs[r * GM_PITCH + c] = vb;
+      As[r * GM_PITCH + c] = bulk_to_double(pa_[u]);
+      if (!diag_tile) Bs[r * GM_PITCH + c] = bulk_to_double(pb_[u]);
     }
     __syncthreads();
+    if (t0 + GM_KC < t_end) fetch(t0 + GM_KC);
     double av[2][8], bv[2][8];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
@@ -907,21 +927,30 @@ __global__ void __launch_bounds__(256) gemm_mfma_kernel(F f) {
         Bs[n * GF_PITCH + kk] = (ng < g.N && k < g.K) ? (float)Bm[(long long)k * g.sbk + (long long)ng * g.sbn] : 0.f;
       }
       __syncthreads();
-      float4 av[2], bv[2];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        av[i] = *reinterpret_cast<const float4*>(As + (qa * 32 + i * 16 + lr) * GF_PITCH + lk * 4);
-        bv[i] = *reinterpret_cast<const float4*>(Bs + (qb * 32 + i * 16 + lr) * GF_PITCH + lk * 4);
-      }
+      constexpr int KS = GF_KC / 4;  // MFMA steps per chunk; lane lk takes k = KS lk + s
+      float av[2][KS], bv[2][KS];
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].x, bv[j].x, acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].y, bv[j].y, acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].z, bv[j].z, acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].w, bv[j].w, acc[i][j], 0, 0, 0);
+        for (int u = 0; u < KS; u += 4) {
+          const float4 ta = *reinterpret_cast<const float4*>(As + (qa * 32 + i * 16 + lr) * GF_PITCH + lk * KS + u);
+          const float4 tb = *reinterpret_cast<const float4*>(Bs + (qb * 32 + i * 16 + lr) * GF_PITCH + lk * KS + u);
+          av[i][u] = ta.x;
+          av[i][u + 1] = ta.y;
+          av[i][u + 2] = ta.z;
+          av[i][u + 3] = ta.w;
+          bv[i][u] = tb.x;
+          bv[i][u + 1] = tb.y;
+          bv[i][u + 2] = tb.z;
+          bv[i][u + 3] = tb.w;
         }
+#pragma unroll
+      for (int u = 0; u < KS; ++u)
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i][u], bv[j][u], acc[i][j], 0, 0, 0);
     }
     // D layout: lane (lr, lk), register v holds row 4 lk + v, column lr
 #pragma unroll
