@@ -900,9 +900,14 @@ __global__ void __launch_bounds__(256) gemm_mfma_kernel(F f) {
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j) acc[i][j] = gf4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < g.K; k0 += GF_KC) {
-      __syncthreads();  // previous chunk consumed
-      for (int e = tid; e < TM * GF_KC; e += 256) {
+    // each thread stages PA elements of A and PB of B per chunk; the next
+    // chunk is loaded into registers while the current one is multiplied
+    constexpr int PA = TM * GF_KC / 256, PB = TN * GF_KC / 256;
+    float ra[PA], rb[PB];
+    auto fetch = [&](int k0) {
+#pragma unroll
+      for (int u = 0; u < PA; ++u) {
+        const int e = tid + u * 256;
         int m, kk;
         if (g.sak == 1) {
           m = e / GF_KC;
@@ -912,9 +917,11 @@ __global__ void __launch_bounds__(256) gemm_mfma_kernel(F f) {
           m = e - kk * TM;
         }
         const int mg = m0 + m, k = k0 + kk;
-        As[m * GF_PITCH + kk] = (mg < g.M && k < g.K) ? (float)A[(long long)mg * g.sam + (long long)k * g.sak] : 0.f;
+        ra[u] = (mg < g.M && k < g.K) ? (float)A[(long long)mg * g.sam + (long long)k * g.sak] : 0.f;
       }
-      for (int e = tid; e < TN * GF_KC; e += 256) {
+#pragma unroll
+      for (int u = 0; u < PB; ++u) {
+        const int e = tid + u * 256;
         int n, kk;
         if (g.sbn == 1) {
           kk = e / TN;
@@ -924,9 +931,40 @@ __global__ void __launch_bounds__(256) gemm_mfma_kernel(F f) {
           kk = e - n * GF_KC;
         }
         const int ng = n0 + n, k = k0 + kk;
-        Bs[n * GF_PITCH + kk] = (ng < g.N && k < g.K) ? (float)Bm[(long long)k * g.sbk + (long long)ng * g.sbn] : 0.f;
+        rb[u] = (ng < g.N && k < g.K) ? (float)Bm[(long long)k * g.sbk + (long long)ng * g.sbn] : 0.f;
+      }
+    };
+    fetch(0);
+    for (int k0 = 0; k0 < g.K; k0 += GF_KC) {
+      __syncthreads();  // previous chunk consumed
+#pragma unroll
+      for (int u = 0; u < PA; ++u) {
+        const int e = tid + u * 256;
+        int m, kk;
+        if (g.sak == 1) {
+          m = e / GF_KC;
+          kk = e - m * GF_KC;
+        } else {
+          kk = e / TM;
+          m = e - kk * TM;
+        }
+        As[m * GF_PITCH + kk] = ra[u];
+      }
+#pragma unroll
+      for (int u = 0; u < PB; ++u) {
+        const int e = tid + u * 256;
+        int n, kk;
+        if (g.sbn == 1) {
+          kk = e / TN;
+          n = e - kk * TN;
+        } else {
+          n = e / GF_KC;
+          kk = e - n * GF_KC;
+        }
+        Bs[n * GF_PITCH + kk] = rb[u];
       }
       __syncthreads();
+      if (k0 + GF_KC < g.K) fetch(k0 + GF_KC);
       constexpr int KS = GF_KC / 4;  // MFMA steps per chunk; lane lk takes k = KS lk + s
       float av[2][KS], bv[2][KS];
 #pragma unroll
