@@ -857,7 +857,7 @@ static tt_status launch_direct(const RCtx& c, int B, int hmax, int kcap, int nma
         HIP_TRY(hipFuncSetAttribute((const void*)mfma_pred_kernel<FFused<float>>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)ms),
                 "mfma prediction smem");
-      const int BB = B >= 64 ? 8 : 2;
+      const int BB = B >= 64 ? 16 : 2;
       const int grid = kcap * ((pcap + BB - 1) / BB);
       hipLaunchKernelGGL((mfma_pred_kernel<FFused<float>>), dim3(std::max(1, grid), 1, B), dim3(256), ms, st, f,
                          BB);

@@ -61,6 +61,17 @@ struct MpVec {
   }
 };
 
+// Position of bond b' of column jl in a V row block: the four S-float units
+// of a column are XOR-swizzled by the column index so that the 16 columns
+// an MFMA operand read touches spread over distinct LDS banks.
+template <int S>
+__device__ inline int mp_vswz(int jl, int q) {
+  constexpr int QP = 4 * S;
+  constexpr int per = 16 / S;  // columns whose rows would share banks
+  const int u = (q / S) ^ ((jl / per) & 3);
+  return jl * QP + u * S + (q % S);
+}
+
 // One pair of 16-row tiles times NJ 16-column tiles over all taps.
 template <int S, int NJ>
 __device__ inline void mp_tiles(const float* pa, const float* vb, int taps, int pp, int vstride, mf4* acc) {
@@ -138,7 +149,7 @@ __device__ inline void mp_body(const typename F::Args& g, int al, int bb, int BB
       float lv[32];
 #pragma unroll
       for (int a2 = 0; a2 < 32; ++a2) lv[a2] = (float)lc[(long long)min(a2, rk1 - 1) * rp1 * g.gcap];
-      float* vcol = Vs + (jj >> 4) * vstride + (jj & 15) * QP + q;
+      float* vcol = Vs + (jj >> 4) * vstride + mp_vswz<S>(jj & 15, q);
       for (int m = 0; m < taps; ++m) {
         const float* kr = Ks + m * 32;
         float v = 0.f;
@@ -190,9 +201,9 @@ __device__ inline void mp_body(const typename F::Args& g, int al, int bb, int BB
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[c] = mf4{0.f, 0.f, 0.f, 0.f};
         // lane (lr, lk): A rows it*16 + lr + 2h - m, bond lk S .. lk S + S - 1;
-        // B rows lr of column tile, same bond range
+        // B: column lr of the tile, the same bond unit (swizzled position)
         const float* pa = Pc + (it0 * 16 + lr + 2 * h) * pp + lk * S;
-        const float* vb = Vs + lr * QP + lk * S;
+        const float* vb = Vs + mp_vswz<S>(lr, lk * S);
         if (njt == 2)
           mp_tiles<S, 2>(pa, vb, taps, pp, vstride, acc);
         else
