@@ -27,9 +27,11 @@ HBM_PEAK_GBS = 8000.0
 # published dense FP32 matrix-core peak of MI355X (256 CUs x 2.4 GHz x 256
 # flops/clk)
 FP32_MFMA_PEAK_TFS = 157.3
-# HBM bytes per launch of mfma_pred_kernel from rocprofv3 FETCH_SIZE
-# and WRITE_SIZE, scaled by the copy-kernel calibration; None until measured
-TRAFFIC = None
+# HBM bytes per launch of mfma_pred_kernel over the timed steps, from
+# rocprofv3 FETCH_SIZE (x2.0) and WRITE_SIZE (x1.0), the factors measured on a
+# plain 256 MiB device copy (profiles/mfma_pred_kernel_traffic_*.txt); reset to
+# None whenever the kernel changes
+TRAFFIC = 856014667
 
 
 def log(msg):
@@ -72,7 +74,7 @@ def run_batch(B, runner, binding, wl, name, batch, steps, warmup, precision, pro
             "status": st, "total": total}
 
 
-def cpu_baseline(wl, steps=2, warm=3):
+def cpu_baseline(wl, steps=6, warm=3):
     """The FP64 oracle on a bounded sample: one filter of the same workload,
     `warm` untimed full steps after step 0 (ranks reach the cap), then
     `steps` timed full steps, on the host cores."""
@@ -188,7 +190,8 @@ def main():
         "data": "synthetic (seeded random-walk trajectories and range/linear measurements)",
         "config": {"workload": args.workload, "d": 6, "N": 128, "rank_cap": 16, "filters": B,
                    "precision": "fp32 bulk, fp64 Gram/pivoted-Cholesky/Jacobi, fp64 log-normaliser",
-                   "failed_filters": int((main_res["status"] != 0).sum())},
+                   "failed_filters": int((main_res["status"] != 0).sum()),
+                   "workspace_GB": round(main_res["run"].ws.numel() * main_res["run"].ws.element_size() / 1e9, 2)},
         "roofline": roof,
         "kernel_ms_per_step": kernel_ms,
     }
