@@ -42,10 +42,14 @@ def _marginal_min(p):
 
 def run_tt_filter(axes, q, halfwidths, meas, z, m0, p0_diag, cap, eps,
                   kernel_tol=1e-12, lik_tol=1e-12, lik_max_rank=None,
-                  kernel=None, record_density=False):
+                  kernel=None, record_density=False, replay=None):
     """TT point-mass filter in FP64 (Alg. 2 loop order, Alg. 3 step 4 FFT
     prediction with F = I).  z has shape [K, b].  Returns a dict of per-step
-    records and the final filtering TT."""
+    records and the final filtering TT.
+
+    ``replay`` = {"ranks_pred": [...], "ranks_filt": [...]} (as recorded by a
+    previous run) fixes the ranks of every rounding instead of the rank rule,
+    so that a perturbed run follows the same rank pattern."""
     delta = mdl.cell_volume(axes)
     if kernel is None:
         kernel = mdl.kernel_tt(q, axes, halfwidths, kernel_tol)
@@ -58,7 +62,8 @@ def run_tt_filter(axes, q, halfwidths, meas, z, m0, p0_diag, cap, eps,
         if k > 0:
             c = ttm.conv(kernel, p, halfwidths)
             rec["ranks_unrounded"].append(ttm.ranks(c))
-            pt, info = ttm.tt_round(c, eps, cap, return_info=True)
+            fr = None if replay is None else replay["ranks_pred"][k - 1]
+            pt, info = ttm.tt_round(c, eps, cap, return_info=True, forced_ranks=fr)
             mpred = ttm.tt_sum(pt) * delta
             rec["log_mpred"].append(math.log(mpred))
             p = ttm.scale(pt, 1.0 / mpred)
@@ -69,7 +74,8 @@ def run_tt_filter(axes, q, halfwidths, meas, z, m0, p0_diag, cap, eps,
         if not (ck > 0.0) or not math.isfinite(ck):
             raise FloatingPointError(f"non-positive or non-finite c_k at step {k}: {ck}")
         rec["log_c"].append(math.log(ck))
-        hr, info = ttm.tt_round(h, eps, cap, return_info=True)
+        fr = None if replay is None else replay["ranks_filt"][k]
+        hr, info = ttm.tt_round(h, eps, cap, return_info=True, forced_ranks=fr)
         rec["tails"].append(info["tails"])
         mass = ttm.tt_sum(hr) * delta
         p = ttm.scale(hr, 1.0 / mass)

@@ -126,11 +126,15 @@ def orthogonalize_rl(tt):
     return cores
 
 
-def tt_round(tt, eps, cap=None, return_info=False):
+def tt_round(tt, eps, cap=None, return_info=False, forced_ranks=None):
     """TT rounding (Sec. 4.1 'round'): right-to-left QR orthogonalisation,
     then a left-to-right sweep of truncated SVDs.  The threshold per bond is
     eps*||A||_F/sqrt(d-1); ||A||_F is read off the first core after the
-    orthogonalisation.  Ranks are capped at ``cap`` (Sec. 3.2)."""
+    orthogonalisation.  Ranks are capped at ``cap`` (Sec. 3.2).
+
+    ``forced_ranks`` (d+1 integers) replaces the rank rule by the given
+    ranks, clamped to the available singular values (rank replay: the
+    derivative of the rounding with its ranks held fixed)."""
     d = len(tt)
     cores = orthogonalize_rl(tt)
     nrm = float(np.linalg.norm(cores[0].ravel()))
@@ -141,6 +145,9 @@ def tt_round(tt, eps, cap=None, return_info=False):
         m = cores[k].reshape(r0 * n, r1)
         u, s, vt = np.linalg.svd(m, full_matrices=False)
         r, tail = choose_rank(s, delta, cap)
+        if forced_ranks is not None:
+            r = max(1, min(int(forced_ranks[k + 1]), len(s)))
+            tail = float(np.sqrt(np.sum(s[r:] ** 2)))
         info["tails"].append(tail)
         info["svals"].append(s.copy())
         info["gaps"].append(float(s[r - 1] - s[r]) if r < len(s) else float(s[r - 1]))
