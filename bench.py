@@ -3,7 +3,8 @@
 
 A step is one full recursion step (predict by per-core convolution, round,
 normalise, likelihood + Hadamard update with c_k, round, normalise + moments)
-for every filter of the batch.  The workload is d=6, N=128 points per axis on
+for every filter of the batch.  The "grad" entry times the FP64 gradient of
+sum_k log c_k on the differentiated workload (d=4, N=128, 32 filters).  The workload is d=6, N=128 points per axis on
 [-20,20]^6, rank cap 16, 256 independent filters (range on (x1,x2) plus
 linear x3..x6, tridiagonal-correlated random walk), synthetic seeded inputs.
 
@@ -119,6 +120,24 @@ def cpu_baseline(wl, steps=6, warm=3):
             "ranks": [int(r) for r in ttm.ranks(p)]}
 
 
+def grad_bench(G, wl, steps, batch):
+    """grad ms/step: the FP64 log-likelihood gradient of the differentiated
+    workload (d=4, N=128, cap 16, range + linear, 8 parameters) by batched
+    rank-replay central differences; one untimed call first (kernel builds,
+    first launches), then one timed call over `steps` steps."""
+    specs, xs, zs = wl.make_batch("range4d_grad", batch=batch, steps=steps)
+    G.loglik_grad(specs, zs)
+    ll, g, info = G.loglik_grad(specs, zs)
+    ms = info["ms_base"] + info["ms_perturbed"]
+    return {"value": round(ms / steps, 2), "unit": "ms per batched step (forward + gradient)",
+            "filter_steps_per_s": round(batch * steps / (ms / 1000.0), 1),
+            "workload": "range4d_grad", "d": 4, "N": 128, "rank_cap": 16, "filters": batch, "steps": steps,
+            "n_theta": int(g.shape[1]), "perturbed_filters": info["filters_perturbed"],
+            "precision": "fp64", "method": "rank-replay central differences, h = 1e-5 max(1,|theta|), "
+            "2 n_theta + 1 batched forward runs (not an adjoint)",
+            "ms_base": round(info["ms_base"], 1), "ms_perturbed": round(info["ms_perturbed"], 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -129,6 +148,9 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the FP64 single-filter comparator")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--profile-steps", type=int, default=2)
+    ap.add_argument("--no-grad", action="store_true", help="skip the gradient timing")
+    ap.add_argument("--grad-steps", type=int, default=8)
+    ap.add_argument("--grad-batch", type=int, default=32)
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -201,6 +223,12 @@ def main():
                              "ms_per_step": round(plain["ms"] / args.steps, 3), "filters": 1,
                              "failed_filters": int((plain["status"] != 0).sum())}
         out["fp32_batch_over_fp64_plain"] = round(value / out["fp64_plain"]["value"], 2)
+        plain.clear()
+    if not args.no_grad:
+        from paper_2501_07942_amd import grad as G
+        main_res.clear()  # release the batch's workspace before the gradient runs
+        torch.cuda.empty_cache()
+        out["grad"] = grad_bench(G, wl, args.grad_steps, args.grad_batch)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out), flush=True)

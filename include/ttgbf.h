@@ -210,6 +210,15 @@ size_t tt_normalize_moments_workspace(int32_t batch, const tt_train* t);
  *   mean_dev[(b*K + k)*d + l], cov_dev[((b*K + k)*d + l)*d + j]  (nullable)
  *   ranks_dev[(b*K + k)*(d+1) + j]  filtering ranks per step (nullable)
  *   status_dev[b]          sticky TT_STATUS_* bits
+ *   ranks_pred_dev[(b*K + k)*(d+1) + j]  ranks of the predictive after its
+ *                          rounding (the prior's at k = 0) (nullable)
+ * Rank replay (nullable inputs, same layout as ranks_pred_dev / ranks_dev):
+ * replay_pred_dev and replay_filt_dev give the ranks the prediction and the
+ * update rounding of every step must take instead of the rank rule (clamped
+ * to at least 1, the available singular values and the capacity).  A run
+ * replaying the ranks recorded by a base run computes the log-likelihood
+ * with its rank pattern frozen, whose central differences in the model
+ * parameters are the derivative of the computed sum of log c_k.
  * Inputs: z_dev[(b*K + k)*zdim + j] with zdim = max over filters of b
  * (d for kind 0, d-1 for kind 1); kernels[spec.kernel_index] is the filter's
  * transition kernel TT (built by tt_kernel_build on the filter's grid).
@@ -241,7 +250,8 @@ tt_status tt_filter_run(int32_t batch, const tt_filter_spec* specs, const tt_tra
                         int32_t n_kernels, const double* z_dev, int32_t zdim, int32_t K,
                         int32_t k_begin, int32_t k_count, int32_t precision, double* loglik_dev, double* log_c_dev,
                         double* log_mpred_dev, double* mean_dev, double* cov_dev,
-                        int32_t* ranks_dev, int32_t* status_dev, void* ws, size_t ws_bytes,
+                        int32_t* ranks_dev, int32_t* status_dev, int32_t* ranks_pred_dev,
+                        const int32_t* replay_pred_dev, const int32_t* replay_filt_dev, void* ws, size_t ws_bytes,
                         void* stream);
 
 /* ---------------------------------------------------------------------

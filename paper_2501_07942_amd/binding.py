@@ -73,7 +73,7 @@ def _load():
         "tt_set_predict_mode": (I, [I]),
         "tt_get_predict_mode": (I, []),
         "tt_profile_end": (I, [P, P, P, P, I]),
-        "tt_filter_run": (I, [I, P, P, I, P, I, I, I, I, I, P, P, P, P, P, P, P, P, S, P]),
+        "tt_filter_run": (I, [I, P, P, I, P, I, I, I, I, I, P, P, P, P, P, P, P, P, P, P, P, S, P]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -295,6 +295,15 @@ def tt_normalize_moments(grids: Sequence[Grid], tts: Sequence[DeviceTT], log_mas
                                     _stream()), "tt_normalize_moments")
 
 
+def workspace_bytes(specs: Sequence[FilterSpec], kernels: Sequence[DeviceTT], precision: int) -> int:
+    """tt_filter_run_workspace for a list of specs (no allocation)."""
+    n = LIB.tt_filter_run_workspace(len(specs), _arr(list(specs)), _arr([k.struct() for k in kernels]),
+                                    len(kernels), precision)
+    if n == 0:
+        _check(ERR_ARG, "tt_filter_run_workspace")
+    return int(n)
+
+
 class FilterRun:
     """Device buffers and workspace of one batched tt_filter_run call."""
 
@@ -317,24 +326,36 @@ class FilterRun:
         self.mean = torch.zeros(self.B, K, d, dtype=torch.float64, device=dev)
         self.cov = torch.zeros(self.B, K, d, d, dtype=torch.float64, device=dev)
         self.ranks = torch.zeros(self.B, K, d + 1, dtype=torch.int32, device=dev)
+        self.ranks_pred = torch.zeros(self.B, K, d + 1, dtype=torch.int32, device=dev)
         self.status = torch.zeros(self.B, dtype=torch.int32, device=dev)
         nbytes = LIB.tt_filter_run_workspace(self.B, self.specs, self.karr, len(kernels), precision)
         if nbytes == 0:
             _check(ERR_ARG, "tt_filter_run_workspace")
         self.ws = _ws(nbytes)
 
-    def __call__(self, z, moments: bool = True, k_begin: int = 0, k_count: Optional[int] = None):
+    def __call__(self, z, moments: bool = True, k_begin: int = 0, k_count: Optional[int] = None,
+                 replay=None):
         """z: float64 device tensor [B, K, zdim].  Runs steps k_begin ..
         k_begin+k_count-1 (all K by default); k_begin > 0 resumes from the
-        state the previous call left in this object's workspace."""
+        state the previous call left in this object's workspace.  replay =
+        (ranks_pred, ranks) int32 device tensors [B, K, d+1] fixes the ranks
+        of every rounding (rank replay)."""
         if k_count is None:
             k_count = self.K - k_begin
+        rp = rf = None
+        if replay is not None:
+            rp, rf = replay
+            for t in (rp, rf):
+                if tuple(t.shape) != (self.B, self.K, self.d + 1) or t.dtype != _torch().int32 or not t.is_contiguous():
+                    raise TTError("replay ranks must be contiguous int32 [B, K, d+1]")
         st = LIB.tt_filter_run(self.B, self.specs, self.karr, len(self.kernels), z.data_ptr(), self.zdim,
                                self.K, int(k_begin), int(k_count), self.precision, self.loglik.data_ptr(),
                                self.log_c.data_ptr(),
                                self.log_mpred.data_ptr(),
                                self.mean.data_ptr() if moments else None,
                                self.cov.data_ptr() if moments else None,
-                               self.ranks.data_ptr(), self.status.data_ptr(), self.ws.data_ptr(),
+                               self.ranks.data_ptr(), self.status.data_ptr(), self.ranks_pred.data_ptr(),
+                               rp.data_ptr() if rp is not None else None,
+                               rf.data_ptr() if rf is not None else None, self.ws.data_ptr(),
                                self.ws.numel(), _stream())
         _check(st, "tt_filter_run")

@@ -599,15 +599,26 @@ struct FLrU {  // core k of the result = B_k V_r Sigma_r^{-1}
 };
 
 // rank rule at bond k+1 of the output; prepares V_r Sigma_r^{-1} and Sigma_r V_r^T
+// (forced != nullptr: rank replay, the rank at bond k+1 is
+// forced[f * fstride + k + 1] instead of the rule, clamped like it)
 __global__ void round_select_kernel(const DevTT* __restrict__ O, const RoundScratch* __restrict__ S,
-                                    int k, int max_rank) {
+                                    int k, int max_rank, const int* __restrict__ forced, long long fstride) {
   const int f = blockIdx.x;
   const DevTT& o = O[f];
   const RoundScratch& s = S[f];
   __shared__ int s_r;
   const int nc = s.misc[0];
   const int rq = s.rq[k + 1];
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0 && forced) {
+    int r = forced[f * fstride + k + 1];
+    r = min(max(r, 1), max(nc, 1));
+    if (r > o.cap[k + 1]) {
+      r = o.cap[k + 1];
+      atomicOr(o.status, TT_STATUS_CAPACITY);
+    }
+    o.ranks[k + 1] = r;
+    s_r = r;
+  } else if (threadIdx.x == 0) {
     const double delta = s.scal[1];
     double tail2 = fmax(s.scal[2], 0.0);
     // smallest r with sqrt(resid + sum_{j>=r} sigma_j^2) <= delta
@@ -979,7 +990,8 @@ struct FusedLaunch {
 
 template <typename T, typename Acc>
 static tt_status round_launch(const RoundShape& sh, const RoundBufs& rb, double eps, int max_rank,
-                              hipStream_t st, const FusedLaunch* fl = nullptr) {
+                              hipStream_t st, const FusedLaunch* fl = nullptr, const int* forced = nullptr,
+                              long long fstride = 0) {
   const int B = sh.B, d = sh.d;
   const bool f64 = sizeof(T) == 8;
   const double tau2_rl = f64 ? 1e-30 : 1e-14;
@@ -1037,7 +1049,7 @@ static tt_status round_launch(const RoundShape& sh, const RoundBufs& rb, double 
     TT_TRY((launch_gram<T, Acc>(FLrGram<T>{c}, B, sh.rq[k + 1], (long long)sh.rout[k] * sh.n[k], sh.splits, st)));
     TT_TRY((launch_pchol<Acc>(FLrPchol{c}, B, sh.gcap, st)));
     TT_TRY((launch_jacobi(FLrJacobi{c}, B, st)));
-    hipLaunchKernelGGL(round_select_kernel, dim3(B), dim3(256), 0, st, rb.dout, rb.drs, k, max_rank);
+    hipLaunchKernelGGL(round_select_kernel, dim3(B), dim3(256), 0, st, rb.dout, rb.drs, k, max_rank, forced, fstride);
     TTG_LAUNCH_CHECK("round_select_kernel");
     TT_TRY((launch_tall<T>(FLrU<T>{c}, B, (long long)sh.rout[k] * sh.n[k], sh.rout[k + 1], st)));
   }
@@ -2367,7 +2379,8 @@ static tt_status run_plan(int32_t batch, const tt_filter_spec* specs, const tt_t
 template <typename T, typename Acc>
 static tt_status run_steps(RunPlan& p, int B, const double* z, int zdim, int K, int k_begin, int k_count,
                            double* loglik, double* log_c, double* log_mpred, double* mean, double* cov,
-                           int* ranks_out, const tt_filter_spec* specs, hipStream_t st) {
+                           int* ranks_out, int* ranks_pred_out, const int* replay_pred, const int* replay_filt,
+                           const tt_filter_spec* specs, hipStream_t st) {
   const int d = p.d;
   // all filters of a batch share one (eps, max_rank) pair per launch; group
   // filters by rounding settings when they differ
@@ -2413,23 +2426,31 @@ static tt_status run_steps(RunPlan& p, int B, const double* z, int zdim, int K, 
     fl.nmax = p.shX.n[0];
     for (int kk = 0; kk < d; ++kk) fl.nmax = std::max(fl.nmax, p.shX.n[kk]);
   }
+  const long long rstride = (long long)K * (d + 1);  // per filter, in the rank arrays
   for (int k = k_begin; k < k_begin + k_count; ++k) {
     if (k > 0) {
       TT_TRY(launch_conv<T>(B, d, p.r0capX, p.csmem, p.dK, p.dP, p.dX, st, p.fused ? 0 : 1));
-      TT_TRY((round_launch<T, Acc>(p.shX, rx, eps, maxcap, st, p.fused ? &fl : nullptr)));
+      TT_TRY((round_launch<T, Acc>(p.shX, rx, eps, maxcap, st, p.fused ? &fl : nullptr,
+                                   replay_pred ? replay_pred + (long long)k * (d + 1) : nullptr, rstride)));
       TT_TRY(launch_moments<T>(B, p.dP, p.dfc, log_mpred + k, K, nullptr, 0, nullptr, 0, p.mscr, p.mspf, p.mrcap, st));
+    }
+    if (ranks_pred_out) {  // ranks of the predictive (the prior's at k = 0)
+      hipLaunchKernelGGL(record_ranks_kernel, dim3(cdiv(B, 64)), dim3(64), 0, st, p.dP, B,
+                         ranks_pred_out + (long long)k * (d + 1), rstride);
+      TTG_LAUNCH_CHECK("record_ranks_kernel");
     }
     TT_TRY(lik_launch(B, p.dL, p.drs, p.dfc, z + (long long)k * zdim, (long long)K * zdim, p.mbuf, p.mstride,
                       p.any_range, p.n0max, p.n1max, p.gcap, p.splits, st));
     TT_TRY(launch_dot<T>(B, p.dL, p.dP, p.dfc, log_c + k, (long long)K, p.vbuf, p.vstride, p.tofs, st));
     TT_TRY(launch_hadamard<T>(B, d, p.r0capH, p.dL, p.dP, p.dH, st));
-    TT_TRY((round_launch<T, Acc>(p.shH, rh, eps, maxcap, st)));
+    TT_TRY((round_launch<T, Acc>(p.shH, rh, eps, maxcap, st, nullptr,
+                                 replay_filt ? replay_filt + (long long)k * (d + 1) : nullptr, rstride)));
     TT_TRY(launch_moments<T>(B, p.dP, p.dfc, p.lmass, 1, mean ? mean + (long long)k * d : nullptr, (long long)K * d,
                              cov ? cov + (long long)k * d * d : nullptr, (long long)K * d * d, p.mscr, p.mspf,
                              p.mrcap, st));
     if (ranks_out) {
       hipLaunchKernelGGL(record_ranks_kernel, dim3(cdiv(B, 64)), dim3(64), 0, st, p.dP, B,
-                         ranks_out + (long long)k * (d + 1), (long long)K * (d + 1));
+                         ranks_out + (long long)k * (d + 1), rstride);
       TTG_LAUNCH_CHECK("record_ranks_kernel");
     }
   }
@@ -2455,7 +2476,9 @@ tt_status tt_filter_run(int32_t batch, const tt_filter_spec* specs, const tt_tra
                         const double* z_dev, int32_t zdim, int32_t K, int32_t k_begin, int32_t k_count,
                         int32_t precision, double* loglik_dev,
                         double* log_c_dev, double* log_mpred_dev, double* mean_dev, double* cov_dev,
-                        int32_t* ranks_dev, int32_t* status_dev, void* ws, size_t ws_bytes, void* stream) {
+                        int32_t* ranks_dev, int32_t* status_dev, int32_t* ranks_pred_dev,
+                        const int32_t* replay_pred_dev, const int32_t* replay_filt_dev, void* ws,
+                        size_t ws_bytes, void* stream) {
   if (!kernels || n_kernels < 1 || !z_dev || K < 1 || zdim < 1 || !loglik_dev || !log_c_dev || !log_mpred_dev ||
       !status_dev || !ws) {
     set_error("tt_filter_run: null pointer or bad size");
@@ -2501,9 +2524,11 @@ tt_status tt_filter_run(int32_t batch, const tt_filter_spec* specs, const tt_tra
   }
   if (precision == TT_F64)
     return run_steps<double, AccDD>(p, batch, z_dev, zdim, K, k_begin, k_count, loglik_dev, log_c_dev, log_mpred_dev,
-                                    mean_dev, cov_dev, ranks_dev, specs, st);
+                                    mean_dev, cov_dev, ranks_dev, ranks_pred_dev, replay_pred_dev, replay_filt_dev,
+                                    specs, st);
   return run_steps<float, AccD>(p, batch, z_dev, zdim, K, k_begin, k_count, loglik_dev, log_c_dev, log_mpred_dev,
-                                mean_dev, cov_dev, ranks_dev, specs, st);
+                                mean_dev, cov_dev, ranks_dev, ranks_pred_dev, replay_pred_dev, replay_filt_dev,
+                                specs, st);
 }
 
 }  // extern "C"

@@ -57,6 +57,7 @@ class FilterSpec:
     kernel_tol: float = 1e-12
     lik_tol: float = 1e-12
     nsigma: float = 4.0
+    box: Optional[List[int]] = None    # fixed kernel half widths (overrides the rule)
 
     @property
     def b(self) -> int:
@@ -73,7 +74,10 @@ class FilterSpec:
 
     def halfwidths(self) -> List[int]:
         """Offsets of the kernel box per axis: floor(nsigma*sqrt(Q_ll)/Delta),
-        or N-1 (every grid offset) when the kernel is not truncated."""
+        or N-1 (every grid offset) when the kernel is not truncated; ``box``
+        when it is set."""
+        if self.box is not None:
+            return list(self.box)
         if not self.truncate_kernel:
             return [self.n - 1] * self.d
         dx = self.spacing()
