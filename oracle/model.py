@@ -89,6 +89,19 @@ def kernel_dense(q, axes, halfwidths):
     return norm * np.exp(-0.5 * quad) * cell_volume(axes)
 
 
+def kernel_at(q, axes, offsets):
+    """K(m) at integer offsets m (rows of ``offsets``): the transition density
+    p_w(Delta o m) = N(Delta o m; 0, Q) times the cell volume (Sec. 2.1,
+    eq. TPMmat with x_{k+1} = x_k + w_k), evaluated point by point."""
+    offsets = np.atleast_2d(np.asarray(offsets, dtype=np.float64))
+    d = len(axes)
+    y = offsets * spacings(axes)[None, :]
+    qinv = np.linalg.inv(q)
+    quad = np.einsum("pi,ij,pj->p", y, qinv, y)
+    norm = (2.0 * math.pi) ** (-d / 2.0) / math.sqrt(np.linalg.det(q))
+    return norm * np.exp(-0.5 * quad) * cell_volume(axes)
+
+
 def kernel_tt(q, axes, halfwidths, tol=1e-12):
     """TT transition kernel: TT-SVD of the dense offset kernel (Sec. 3.1)."""
     return ttm.tt_svd(kernel_dense(q, axes, halfwidths), tol)

@@ -135,3 +135,17 @@ def test_prediction_translation_equivariance():
     c2 = ttm.full(ttm.conv(k, p2, h))
     assert np.allclose(np.roll(np.roll(c1, 3, axis=0), -2, axis=1)[5:-5, 5:-5], c2[5:-5, 5:-5],
                        rtol=1e-10, atol=1e-14)
+
+
+def test_kernel_at_equals_dense_kernel_entries():
+    # the pointwise kernel (used at sizes where the dense box is too large)
+    # is the dense kernel's entry at every sampled offset
+    q = np.array([[1.0, 0.3, 0.0], [0.3, 0.7, 0.3], [0.0, 0.3, 1.2]])
+    axes = mdl.grid_axes(-6.0, 6.0, [25, 25, 25])
+    h = mdl.kernel_halfwidths(q, axes)
+    kd = mdl.kernel_dense(q, axes, h)
+    rng = np.random.default_rng(3)
+    offs = np.stack([rng.integers(-hh, hh + 1, 40) for hh in h], axis=1)
+    got = mdl.kernel_at(q, axes, offs)
+    ref = np.array([kd[tuple(o + np.array(h))] for o in offs])
+    assert np.allclose(got, ref, rtol=1e-14, atol=0)
