@@ -720,12 +720,17 @@ static tt_status launch_pchol_any(bool f64, F f, int B, int gcap, hipStream_t st
 template <typename Acc, typename F>
 static tt_status launch_pchol(F f, int B, int gcap, hipStream_t st) {
   ProfScope ps_(PC_PCHOL, st);
-  const size_t smem = (size_t)(2 * gcap) * sizeof(typename Acc::V) + (size_t)gcap * sizeof(int) + 64;
+  using V = typename Acc::V;
+  const size_t base = (size_t)(2 * gcap) * sizeof(V) + (size_t)gcap * sizeof(int) + 64;
+  int ncl = 0;  // factor columns mirrored in LDS (FP64 accumulation only)
+  if (sizeof(V) == sizeof(double) && base < 150 * 1024)
+    ncl = (int)std::min<size_t>(PC_LDS_COLS, (150 * 1024 - base) / ((size_t)gcap * sizeof(V)));
+  const size_t smem = base + (size_t)ncl * gcap * sizeof(V);
   if (smem > 48 * 1024)
     HIP_TRY(hipFuncSetAttribute((const void*)pchol_kernel<Acc, F>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem),
             "pchol smem attribute");
-  hipLaunchKernelGGL((pchol_kernel<Acc, F>), dim3(B), dim3(256), smem, st, f);
+  hipLaunchKernelGGL((pchol_kernel<Acc, F>), dim3(B), dim3(256), smem, st, f, ncl);
   TTG_LAUNCH_CHECK("pchol_kernel");
   return TT_OK;
 }
@@ -1262,6 +1267,7 @@ struct LikCtx {
   const FilterConst* C;
   const double* mbuf;
   long long mstride;
+  double tau2;  // relative pre-truncation of the pivoted Cholesky
 };
 
 struct FLikGram {  // Gram of the columns of M (n0 x n1)
@@ -1295,7 +1301,7 @@ struct FLikPchol {
     p.status = c.L[b].status;
     p.gcap = s.gcap;
     p.rmax = s.gcap;
-    p.tau2 = 1e-31;
+    p.tau2 = c.tau2;
     return true;
   }
 };
@@ -1339,16 +1345,27 @@ struct FLikCore0 {  // core 0 = M V_r  (n0 x r)
 };
 
 // Likelihood TT for a batch (FP64): dense factors, range-block SVD.
+// The range block's SVD: FP64 path with double-double Gram and pivoted
+// Cholesky (singular values resolved far below 1e-12 of the largest); the
+// FP32 bulk path with an FP64 Gram and a pre-truncation at the FP32 noise
+// level (the likelihood cores are FP32 there, so components below ~1e-7 of
+// the block's norm cannot be represented anyway).
 static tt_status lik_launch(int B, const DevTT* dL, const RoundScratch* drs, const FilterConst* dfc,
                             const double* z, long long zstride, double* mbuf, long long mstride,
-                            bool any_range, int n0max, int n1max, int gcap, int splits, hipStream_t st) {
+                            bool any_range, int n0max, int n1max, int gcap, int splits, hipStream_t st,
+                            bool f32 = false) {
   ProfScope ps_(PC_LIK, st);
   hipLaunchKernelGGL(lik_dense_kernel, dim3(B), dim3(256), 0, st, dL, dfc, z, zstride, mbuf, mstride);
   TTG_LAUNCH_CHECK("lik_dense_kernel");
   if (!any_range) return TT_OK;
-  LikCtx c{dL, drs, dfc, mbuf, mstride};
-  TT_TRY((launch_gram<double, AccDD>(FLikGram{c}, B, n1max, n0max, splits, st)));
-  TT_TRY((launch_pchol<AccDD>(FLikPchol{c}, B, gcap, st)));
+  LikCtx c{dL, drs, dfc, mbuf, mstride, f32 ? 1e-14 : 1e-31};
+  if (f32) {
+    TT_TRY((launch_gram<double, AccD>(FLikGram{c}, B, n1max, n0max, splits, st)));
+    TT_TRY((launch_pchol<AccD>(FLikPchol{c}, B, gcap, st)));
+  } else {
+    TT_TRY((launch_gram<double, AccDD>(FLikGram{c}, B, n1max, n0max, splits, st)));
+    TT_TRY((launch_pchol<AccDD>(FLikPchol{c}, B, gcap, st)));
+  }
   TT_TRY((launch_jacobi(FLikJacobi{c}, B, st)));
   hipLaunchKernelGGL(lik_select_kernel, dim3(B), dim3(256), 0, st, dL, drs, dfc);
   TTG_LAUNCH_CHECK("lik_select_kernel");
@@ -2440,7 +2457,7 @@ static tt_status run_steps(RunPlan& p, int B, const double* z, int zdim, int K, 
       TTG_LAUNCH_CHECK("record_ranks_kernel");
     }
     TT_TRY(lik_launch(B, p.dL, p.drs, p.dfc, z + (long long)k * zdim, (long long)K * zdim, p.mbuf, p.mstride,
-                      p.any_range, p.n0max, p.n1max, p.gcap, p.splits, st));
+                      p.any_range, p.n0max, p.n1max, p.gcap, p.splits, st, sizeof(T) == 4));
     TT_TRY(launch_dot<T>(B, p.dL, p.dP, p.dfc, log_c + k, (long long)K, p.vbuf, p.vstride, p.tofs, st));
     TT_TRY(launch_hadamard<T>(B, d, p.r0capH, p.dL, p.dP, p.dH, st));
     TT_TRY((round_launch<T, Acc>(p.shH, rh, eps, maxcap, st, nullptr,

@@ -260,6 +260,7 @@ __global__ void __launch_bounds__(256) gram_reduce_kernel(F f) {
 // form a lower-triangular r x r block).  Writes *rank_out and the residual
 // trace of the remaining Schur complement.
 // ---------------------------------------------------------------------------
+#define PC_LDS_COLS 48
 struct PcholArgs {
   int M;                // dimension of G
   const double* g;      // G (accumulator type), ld gcap
@@ -275,7 +276,7 @@ struct PcholArgs {
 };
 
 template <typename Acc, typename F>
-__global__ void __launch_bounds__(256) pchol_kernel(F f) {
+__global__ void __launch_bounds__(256) pchol_kernel(F f, int ncl) {
   const int b = blockIdx.x;
   PcholArgs p;
   if (!f(b, p)) return;
@@ -286,6 +287,12 @@ __global__ void __launch_bounds__(256) pchol_kernel(F f) {
   V* diag = reinterpret_cast<V*>(smem);
   V* lp = diag + p.M;                           // jmax entries
   int* done = reinterpret_cast<int*>(lp + jmax);  // M entries
+  // FP64 accumulation: the first ncl (<= PC_LDS_COLS, as many as the LDS
+  // holds) factor columns are also kept in LDS (column-major, pitch M), so
+  // each pivot step reads the thread's earlier entries from LDS instead of
+  // global memory
+  constexpr bool lds_cols = sizeof(V) == sizeof(double);
+  V* lc = reinterpret_cast<V*>(smem + (((size_t)(p.M + jmax) * sizeof(V) + (size_t)p.M * sizeof(int) + 7) / 8));
   __shared__ double red_v[8];
   __shared__ int red_i[8];
   __shared__ int s_piv;
@@ -354,7 +361,8 @@ __global__ void __launch_bounds__(256) pchol_kernel(F f) {
     if (zero_col) pv = -2 - pv;
     const V lpp = zero_col ? Acc::from(1.0) : Acc::sqrt_(diag[pv]);
     // cache row pv of the factor
-    for (int t = tid; t < j; t += nt) lp[t] = Acc::load(p.lwork, (long long)t * p.gcap + pv);
+    for (int t = tid; t < j; t += nt)
+      lp[t] = (lds_cols && t < ncl) ? lc[(long long)t * p.M + pv] : Acc::load(p.lwork, (long long)t * p.gcap + pv);
     __syncthreads();
     for (int i = tid; i < p.M; i += nt) {
       V l;
@@ -364,12 +372,20 @@ __global__ void __launch_bounds__(256) pchol_kernel(F f) {
         l = Acc::zero();
       } else {
         V s = Acc::load(p.g, (long long)i * p.gcap + pv);
-        for (int t = 0; t < j; ++t)
-          s = Acc::sub(s, Acc::mul(Acc::load(p.lwork, (long long)t * p.gcap + i), lp[t]));
+        if constexpr (lds_cols) {
+          const int tl = min(j, ncl);
+          for (int t = 0; t < tl; ++t) s = Acc::sub(s, Acc::mul(lc[(long long)t * p.M + i], lp[t]));
+          for (int t = tl; t < j; ++t)
+            s = Acc::sub(s, Acc::mul(Acc::load(p.lwork, (long long)t * p.gcap + i), lp[t]));
+        } else {
+          for (int t = 0; t < j; ++t)
+            s = Acc::sub(s, Acc::mul(Acc::load(p.lwork, (long long)t * p.gcap + i), lp[t]));
+        }
         l = Acc::div(s, lpp);
         diag[i] = Acc::sub(diag[i], Acc::mul(l, l));
       }
       Acc::store(p.lwork, (long long)j * p.gcap + i, l);
+      if (lds_cols && j < ncl) lc[(long long)j * p.M + i] = l;
     }
     __syncthreads();
     if (tid == 0) {
