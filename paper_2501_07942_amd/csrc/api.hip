@@ -570,6 +570,7 @@ struct FLrJacobi {
     J.sigma = s.sigma;
     J.usv = s.usv;
     J.ncols_out = nullptr;
+    J.tol2 = c.esz == 4 ? 1e-24 : 1e-30;  // FP32 bulk: 1e-12 relative orthogonality
     J.gcap = s.gcap;
     return true;
   }
@@ -1318,6 +1319,7 @@ struct FLikJacobi {
     J.sigma = s.sigma;
     J.usv = s.usv;
     J.ncols_out = nullptr;
+    J.tol2 = 1e-30;
     J.gcap = s.gcap;
     return true;
   }
@@ -1431,6 +1433,7 @@ struct FKsvdJacobi {
     J.sigma = s.sigma;
     J.usv = s.usv;
     J.ncols_out = nullptr;
+    J.tol2 = 1e-30;
     J.gcap = s.gcap;
     return true;
   }

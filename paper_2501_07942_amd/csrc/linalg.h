@@ -429,6 +429,7 @@ __global__ void __launch_bounds__(256) pchol_kernel(F f, int ncl) {
 // ---------------------------------------------------------------------------
 struct JacobiArgs {
   int rows, ncols;
+  double tol2;      // a pair is orthogonal when ga^2 <= tol2 * al * be
   const double* x;  // row-major input
   long long ldx;
   double* work;     // column-major scratch, ld gcap
@@ -442,8 +443,8 @@ struct JacobiArgs {
 // norms al, be and inner product ga (Rutishauser's formulas):
 //   zeta = (be - al) / (2 ga),  t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)),
 //   c = 1 / sqrt(1 + t^2),  s = c t.
-// Returns false when the pair is already orthogonal to relative tolerance
-// 1e-15 (ga^2 <= 1e-30 al be).  Reciprocals and reciprocal square roots start
+// Returns false when the pair is already orthogonal to the relative
+// tolerance sqrt(tol2) (ga^2 <= tol2 al be).  Reciprocals and reciprocal square roots start
 // from the hardware approximations and take two Newton steps each, which
 // reaches FP64 accuracy with a much shorter dependency chain than IEEE
 // division and square root.
@@ -463,8 +464,8 @@ __device__ inline double jac_rsq(double x) {
   e = __fma_rn(-h, y, 0.5);
   return __fma_rn(y, e, y);
 }
-__device__ inline bool jac_rotation(double al, double be, double ga, double& cs, double& sn) {
-  if (!(ga != 0.0 && ga * ga > 1e-30 * (al * be))) return false;
+__device__ inline bool jac_rotation(double al, double be, double ga, double& cs, double& sn, double tol2) {
+  if (!(ga != 0.0 && ga * ga > tol2 * (al * be))) return false;
   const double zeta = (be - al) * 0.5 * jac_rcp(ga);
   const double s1 = __fma_rn(zeta, zeta, 1.0);
   const double root = s1 * jac_rsq(s1);
@@ -474,7 +475,8 @@ __device__ inline bool jac_rotation(double al, double be, double ga, double& cs,
   return true;
 }
 
-// One-sided Jacobi for at most JW_NMAX columns, run by a single wavefront:
+// One-sided Jacobi for at most JW_NMAX columns and few rows per lane, run by
+// a single wavefront:
 // the n/2 column pairs of a round each get LP = 64 / (n/2) lanes (rounded
 // down to a power of two), which split the rows and reduce the three dot
 // products with log2(LP) lane exchanges.  Same round-robin pairing, rotation
@@ -486,7 +488,8 @@ __device__ inline double jw_group_sum(double v, int lp) {
   return v;
 }
 
-__device__ inline void jacobi_wave(double* W, long long ldw, int rows, int nc, double* s_sig, const JacobiArgs& J) {
+__device__ __forceinline__ void jacobi_wave(double* W, long long ldw, int rows, int nc, double* s_sig,
+                                            const JacobiArgs& J) {
   const int lane = threadIdx.x & 63;
   const int n = (nc + 1) & ~1;
   const int npair = n / 2;
@@ -524,7 +527,7 @@ __device__ inline void jacobi_wave(double* W, long long ldw, int rows, int nc, d
         be = jw_group_sum(be, lp);
         ga = jw_group_sum(ga, lp);
         double cs, sn;
-        if (live && jac_rotation(al, be, ga, cs, sn)) {
+        if (live && jac_rotation(al, be, ga, cs, sn, J.tol2)) {
           for (int k = lip; k < rows; k += lp) {
             const double u = xp[k], v = xq[k];
             xp[k] = cs * u - sn * v;
@@ -569,67 +572,75 @@ __device__ inline void jacobi_wave(double* W, long long ldw, int rows, int nc, d
   if (lane == 0 && J.ncols_out) *J.ncols_out = nc;
 }
 
-template <typename F>
-__global__ void __launch_bounds__(512) jacobi_kernel(F f, int lds_doubles) {
-  const int b = blockIdx.x;
-  JacobiArgs J;
-  if (!f(b, J)) return;
+// The sweep body, instantiated separately for columns in LDS and in global
+// memory so that the compiler knows the address space of every column
+// access (a pointer chosen at run time between the two would turn them all
+// into flat accesses with global-memory latency).
+__device__ __forceinline__ void jacobi_body(double* W, long long ldw, const JacobiArgs& J, double* s_sig,
+                                            int& s_rot) {
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, nw = blockDim.x >> 6;
   const int rows = J.rows, nc = J.ncols;
-  // columns live in LDS when they fit (leading dimension = rows), else in
-  // the global scratch (leading dimension gcap)
-  extern __shared__ double jsm[];
-  const bool in_lds = (long long)rows * nc <= lds_doubles;
-  double* W = in_lds ? jsm : J.work;
-  const long long ldw = in_lds ? rows : J.gcap;
   for (long long e = tid; e < (long long)rows * nc; e += blockDim.x) {
     const int i = (int)(e / nc), c = (int)(e % nc);
     W[(long long)c * ldw + i] = J.x[(long long)i * J.ldx + c];
   }
-  __shared__ int s_rot;
-  __shared__ double s_sig[1024];
   __syncthreads();
   const int n = (nc + 1) & ~1;  // even number of players (one may be a dummy)
-  if (n <= JW_NMAX && rows <= 64) {
+  int lpw = 1;  // lanes per pair the single-wavefront path would need for <= 8 rows per lane
+  while (lpw < 64 && 8 * lpw < rows) lpw *= 2;
+  if (n <= JW_NMAX && (n / 2) * lpw <= 64) {
     // small problem: wavefront 0 runs every sweep alone (no block barriers);
     // decided per filter, so a filter's result does not depend on its batch
     if (wid == 0) jacobi_wave(W, ldw, rows, nc, s_sig, J);
     return;
   }
+  const int npair = n / 2;
+  int lp = 1;
+  while (lp < 64 && 4 * 2 * lp <= rows) lp *= 2;      // about four rows per lane
+  while (lp > 1 && lp * npair > (int)blockDim.x) lp >>= 1;
+  const int grp = tid / lp, lip = tid - (tid / lp) * lp;
+  const int ngrp = blockDim.x / lp;
   for (int sweep = 0; sweep < 60 && n >= 2; ++sweep) {
     if (tid == 0) s_rot = 0;
     __syncthreads();
     for (int r = 0; r < n - 1; ++r) {
-      for (int i = wid; i < n / 2; i += nw) {
-        int pc, qc;
-        if (i == 0) {
-          pc = n - 1;
-          qc = r;
-        } else {
-          pc = (r + i) % (n - 1);
-          qc = (r - i + (n - 1)) % (n - 1);
+      // every pair of the round at once: pair i gets lp lanes (a power of
+      // two <= 64 sized to about four rows per lane), which split the rows
+      // and reduce the three dot products among themselves
+      for (int i0 = 0; i0 < npair; i0 += ngrp) {
+        const int i = i0 + grp;
+        int pc = -1, qc = -1;
+        if (i < npair) {
+          if (i == 0) {
+            pc = n - 1;
+            qc = r;
+          } else {
+            pc = (r + i) % (n - 1);
+            qc = (r - i + (n - 1)) % (n - 1);
+          }
         }
-        if (pc >= nc || qc >= nc) continue;
-        double* xp = W + (long long)pc * ldw;
-        double* xq = W + (long long)qc * ldw;
+        const bool live = i < npair && pc < nc && qc < nc;
+        double* xp = W + (long long)(live ? pc : 0) * ldw;
+        double* xq = W + (long long)(live ? qc : 0) * ldw;
         double al = 0.0, be = 0.0, ga = 0.0;
-        for (int k = lane; k < rows; k += 64) {
-          const double u = xp[k], v = xq[k];
-          al = __fma_rn(u, u, al);
-          be = __fma_rn(v, v, be);
-          ga = __fma_rn(u, v, ga);
-        }
-        al = wave_sum(al);
-        be = wave_sum(be);
-        ga = wave_sum(ga);
+        if (live)
+          for (int k = lip; k < rows; k += lp) {
+            const double u = xp[k], v = xq[k];
+            al = __fma_rn(u, u, al);
+            be = __fma_rn(v, v, be);
+            ga = __fma_rn(u, v, ga);
+          }
+        al = jw_group_sum(al, lp);
+        be = jw_group_sum(be, lp);
+        ga = jw_group_sum(ga, lp);
         double cs, sn;
-        if (jac_rotation(al, be, ga, cs, sn)) {
-          for (int k = lane; k < rows; k += 64) {
+        if (live && jac_rotation(al, be, ga, cs, sn, J.tol2)) {
+          for (int k = lip; k < rows; k += lp) {
             const double u = xp[k], v = xq[k];
             xp[k] = cs * u - sn * v;
             xq[k] = sn * u + cs * v;
           }
-          if (lane == 0) s_rot = 1;
+          if (lip == 0) s_rot = 1;
         }
       }
       __syncthreads();
@@ -662,6 +673,22 @@ __global__ void __launch_bounds__(512) jacobi_kernel(F f, int lds_doubles) {
     for (int k = lane; k < rows; k += 64) dst[k] = xc[k];
   }
   if (tid == 0 && J.ncols_out) *J.ncols_out = nc;
+}
+
+template <typename F>
+__global__ void __launch_bounds__(512) jacobi_kernel(F f, int lds_doubles) {
+  const int b = blockIdx.x;
+  JacobiArgs J;
+  if (!f(b, J)) return;
+  // columns live in LDS when they fit (leading dimension = rows), else in
+  // the global scratch (leading dimension gcap)
+  extern __shared__ double jsm[];
+  __shared__ int s_rot;
+  __shared__ double s_sig[1024];
+  if ((long long)J.rows * J.ncols <= lds_doubles)
+    jacobi_body(jsm, J.rows, J, s_sig, s_rot);
+  else
+    jacobi_body(J.work, J.gcap, J, s_sig, s_rot);
 }
 
 // ---------------------------------------------------------------------------
