@@ -962,12 +962,20 @@ static tt_status launch_trsm(F f, int B, long long mcap, int rcap, hipStream_t s
   ProfScope ps_(PC_TRSM, st);
   if constexpr (sizeof(TQ) == 4) {
     // FP32 bulk: explicit inverse of the pivot block, then one thread per column
-    hipLaunchKernelGGL((tri_inverse_kernel<F>), dim3(1, 1, B), dim3(256), 0, st, f);
+    const size_t lb = (size_t)rcap * rcap * sizeof(double);  // pivot block in LDS
+    if (lb > 160 * 1024) {
+      set_error("triangular inverse: pivot block of rank %d does not fit in LDS", rcap);
+      return TT_ERR_SHAPE;
+    }
+    if (lb > 48 * 1024)
+      HIP_TRY(hipFuncSetAttribute((const void*)tri_inverse_kernel<F>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lb),
+              "tri inverse smem");
+    hipLaunchKernelGGL((tri_inverse_kernel<F>), dim3(1, 1, B), dim3(256), lb, st, f);
     TTG_LAUNCH_CHECK("tri_inverse_kernel");
     hipLaunchKernelGGL((tri_apply_kernel<TZ, TQ, F>), dim3(stride_grid(cdiv(mcap, 256), B), 1, B), dim3(256), 0,
                        st, f);
     TTG_LAUNCH_CHECK("tri_apply_kernel");
-    (void)rcap;
     return TT_OK;
   }
   const size_t qbytes = (size_t)rcap * 64 * sizeof(double);
@@ -1548,7 +1556,7 @@ __global__ void copy_status_kernel(const DevTT* __restrict__ P, int nf, int* out
 }
 
 static size_t moments_scratch_per_filter(int d, int rcap) {
-  return (size_t)3 * d * rcap * rcap + 2 * (size_t)(d + 1) * rcap + 2 * (size_t)rcap + 8;
+  return (size_t)3 * d * rcap * rcap + 2 * (size_t)(d + 1) * rcap + 8 * (size_t)rcap + 8;  // chains: 2 rcap per wavefront
 }
 
 template <typename T>

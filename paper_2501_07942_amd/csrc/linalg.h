@@ -760,13 +760,22 @@ __global__ void __launch_bounds__(256) tri_inverse_kernel(F f) {
   const int b = blockIdx.z;
   TrsmArgs a;
   if (!f(b, a)) return;
+  // the pivot block L_pp (lower triangle, row j = lfac row piv[j]) in LDS
+  extern __shared__ double lpp[];  // [r][r]
+  const int r = a.r;
+  for (int e = threadIdx.x; e < r * r; e += blockDim.x) {
+    const int j = e / r, t = e - (e / r) * r;
+    lpp[e] = (t <= j) ? a.lfac[(long long)a.piv[j] * a.gcap + t] : 0.0;
+  }
+  __syncthreads();
   double* wt = a.wbuf;
-  for (int c = threadIdx.x; c < a.r; c += blockDim.x) {
+  for (int c = threadIdx.x; c < r; c += blockDim.x) {
     double* w = wt + (long long)c * a.gcap;
     for (int j = 0; j < c; ++j) w[j] = 0.0;
-    for (int j = c; j < a.r; ++j) {
-      const double* lrow = a.lfac + (long long)a.piv[j] * a.gcap;
+    for (int j = c; j < r; ++j) {
+      const double* lrow = lpp + (long long)j * r;
       double s = (j == c) ? 1.0 : 0.0;
+#pragma unroll 4
       for (int t = c; t < j; ++t) s = __fma_rn(-lrow[t], w[t], s);
       w[j] = s / lrow[j];
     }

@@ -238,115 +238,144 @@ __global__ void __launch_bounds__(256) moments_kernel(const DevTT* __restrict__ 
   const DevTT& A = tt[f];
   const FilterConst& C = fc[f];
   const int d = A.d, tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6, nwv = blockDim.x >> 6;
   const long long mat = (long long)rcap * rcap;
   double* S = scratch + f * scr_per_filter;      // [3][d][rcap*rcap]
   double* left = S + 3 * d * mat;                // [d+1][rcap]
   double* right = left + (d + 1) * rcap;         // [d+1][rcap]
-  double* tmp = right + (d + 1) * rcap;          // [2][rcap]
+  double* tmp = right + (d + 1) * rcap;          // [2][rcap] per wavefront (chains below)
   const bool want = (mean != nullptr);
-  const int nv = want ? 3 : 1;
+  __shared__ double s_mean[TT_MAXD];
+  __shared__ double s_total;
+  __shared__ int s_ok;
+  // per-core contractions with 1, xi and xi^2: one thread per (a, b) sums
+  // over the grid index (consecutive threads read consecutive b)
   for (int k = 0; k < d; ++k) {
     const int r0 = A.ranks[k], r1 = A.ranks[k + 1], n = A.n[k];
     const T* c = core_ptr<T>(A, k);
-    for (int e = tid; e < nv * r0 * r1; e += blockDim.x) {
-      const int v = e / (r0 * r1), q = e % (r0 * r1);
-      const int a = q / r1, b = q % r1;
-      double s = 0.0;
+    for (int q = tid; q < r0 * r1; q += blockDim.x) {
+      const int a = q / r1, bq = q - (q / r1) * r1;
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll 8
       for (int i = 0; i < n; ++i) {
         const double x = C.lo[k] + i * C.dx[k];
-        const double w = (v == 0) ? 1.0 : (v == 1 ? x : x * x);
-        s += w * bulk_to_double(c[((long long)a * n + i) * r1 + b]);
+        const double v = bulk_to_double(c[((long long)a * n + i) * r1 + bq]);
+        s0 += v;
+        if (want) {
+          s1 += x * v;
+          s2 += x * x * v;
+        }
       }
-      S[(v * d + k) * mat + a * r1 + b] = s;
+      S[(0 * d + k) * mat + a * r1 + bq] = s0;
+      if (want) {
+        S[(1 * d + k) * mat + a * r1 + bq] = s1;
+        S[(2 * d + k) * mat + a * r1 + bq] = s2;
+      }
     }
   }
   __syncthreads();
   // prefix chains left[k] (1 x r_k) and suffix right[k] (r_k x 1) of S^1
-  if (tid == 0) left[0] = 1.0;
+  if (tid == 0) {
+    left[0] = 1.0;
+    right[d * rcap] = 1.0;
+  }
   __syncthreads();
   for (int k = 0; k < d; ++k) {
     const int r0 = A.ranks[k], r1 = A.ranks[k + 1];
-    for (int b = tid; b < r1; b += blockDim.x) {
+    for (int bq = tid; bq < r1; bq += blockDim.x) {
       double s = 0.0;
-      for (int a = 0; a < r0; ++a) s += left[k * rcap + a] * S[(0 * d + k) * mat + a * r1 + b];
-      left[(k + 1) * rcap + b] = s;
+      for (int a = 0; a < r0; ++a) s += left[k * rcap + a] * S[(0 * d + k) * mat + a * r1 + bq];
+      left[(k + 1) * rcap + bq] = s;
+    }
+    const int kk = d - 1 - k;  // the suffix chain advances at the same time
+    const int q0 = A.ranks[kk], q1 = A.ranks[kk + 1];
+    for (int a = tid; a < q0; a += blockDim.x) {
+      double s = 0.0;
+      for (int bq = 0; bq < q1; ++bq) s += S[(0 * d + kk) * mat + a * q1 + bq] * right[(kk + 1) * rcap + bq];
+      right[kk * rcap + a] = s;
     }
     __syncthreads();
   }
-  if (tid == 0) right[d * rcap] = 1.0;
-  __syncthreads();
-  for (int k = d - 1; k >= 0; --k) {
-    const int r0 = A.ranks[k], r1 = A.ranks[k + 1];
-    for (int a = tid; a < r0; a += blockDim.x) {
-      double s = 0.0;
-      for (int b = 0; b < r1; ++b) s += S[(0 * d + k) * mat + a * r1 + b] * right[(k + 1) * rcap + b];
-      right[k * rcap + a] = s;
-    }
-    __syncthreads();
-  }
-  const double total = left[d * rcap];
-  int st = *A.status;
-  if (!(total == total) || fabs(total) > 1.7e308) st |= TT_STATUS_NONFINITE;
-  else if (!(total > 0.0)) st |= TT_STATUS_NONPOSITIVE;
-  __syncthreads();
-  const double nan = __longlong_as_double(0x7ff8000000000000LL);
-  const bool ok = (st & (TT_STATUS_NONFINITE | TT_STATUS_NONPOSITIVE)) == 0;
   if (tid == 0) {
+    const double total = left[d * rcap];
+    int st = *A.status;
+    if (!(total == total) || fabs(total) > 1.7e308) st |= TT_STATUS_NONFINITE;
+    else if (!(total > 0.0)) st |= TT_STATUS_NONPOSITIVE;
+    const bool ok = (st & (TT_STATUS_NONFINITE | TT_STATUS_NONPOSITIVE)) == 0;
+    const double nan = __longlong_as_double(0x7ff8000000000000LL);
     const double lm = ok ? log(total) + C.logdelta + *A.log_scale : nan;
     if (log_mass) log_mass[f * lm_stride] = lm;
     if (ok) *A.log_scale -= lm;
     if (st != *A.status) atomicOr(A.status, st);
+    s_total = total;
+    s_ok = ok ? 1 : 0;
   }
+  __syncthreads();
   if (!want) return;
-  // means and E[x_l^2]
-  for (int l = tid; l < d; l += blockDim.x) {
+  const double total = s_total;
+  const bool ok = s_ok != 0;
+  const double nan = __longlong_as_double(0x7ff8000000000000LL);
+  // means and E[x_l^2]: one wavefront per axis reduces left_l S_l right_{l+1}
+  for (int l = wv; l < d; l += nwv) {
     const int r0 = A.ranks[l], r1 = A.ranks[l + 1];
     double m1 = 0.0, m2 = 0.0;
-    for (int a = 0; a < r0; ++a)
-      for (int b = 0; b < r1; ++b) {
-        const double lr = left[l * rcap + a] * right[(l + 1) * rcap + b];
-        m1 += lr * S[(1 * d + l) * mat + a * r1 + b];
-        m2 += lr * S[(2 * d + l) * mat + a * r1 + b];
-      }
-    m1 /= total;
-    m2 /= total;
-    mean[f * mean_stride + l] = ok ? m1 : nan;
-    if (cov) cov[f * cov_stride + l * d + l] = ok ? m2 - m1 * m1 : nan;
+    for (int q = lane; q < r0 * r1; q += 64) {
+      const int a = q / r1, bq = q - (q / r1) * r1;
+      const double lr = left[l * rcap + a] * right[(l + 1) * rcap + bq];
+      m1 += lr * S[(1 * d + l) * mat + q];
+      m2 += lr * S[(2 * d + l) * mat + q];
+    }
+    m1 = wave_sum(m1) / total;
+    m2 = wave_sum(m2) / total;
+    if (lane == 0) {
+      s_mean[l] = m1;
+      mean[f * mean_stride + l] = ok ? m1 : nan;
+      if (cov) cov[f * cov_stride + l * d + l] = ok ? m2 - m1 * m1 : nan;
+    }
   }
   if (!cov) return;
   __syncthreads();
-  // off-diagonal E[x_l x_j], l < j: w = left_l S^xi_l, then chain S^1 up to j
-  double* w = tmp;
-  double* w2 = tmp + rcap;
-  for (int l = 0; l < d - 1; ++l) {
+  // off-diagonal E[x_l x_j], l < j: one wavefront per chain l carries
+  // w = left_l S^xi_l S^1_{l+1} ... and closes it with S^xi_j right_{j+1}
+  for (int l = wv; l < d - 1; l += nwv) {
+    double* w = tmp + (long long)wv * 2 * rcap;
+    double* w2 = w + rcap;
     {
       const int r0 = A.ranks[l], r1 = A.ranks[l + 1];
-      for (int b = tid; b < r1; b += blockDim.x) {
+      for (int bq = lane; bq < r1; bq += 64) {
         double s = 0.0;
-        for (int a = 0; a < r0; ++a) s += left[l * rcap + a] * S[(1 * d + l) * mat + a * r1 + b];
-        w[b] = s;
+        for (int a = 0; a < r0; ++a) s += left[l * rcap + a] * S[(1 * d + l) * mat + a * r1 + bq];
+        w[bq] = s;
       }
     }
-    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     for (int j = l + 1; j < d; ++j) {
       const int r0 = A.ranks[j], r1 = A.ranks[j + 1];
-      if (tid == 0) {
-        double s = 0.0;
-        for (int a = 0; a < r0; ++a)
-          for (int b = 0; b < r1; ++b) s += w[a] * S[(1 * d + j) * mat + a * r1 + b] * right[(j + 1) * rcap + b];
-        const double m = mean[f * mean_stride + l], mj = mean[f * mean_stride + j];
-        const double cv = s / total - m * mj;
+      double e = 0.0;
+      for (int bq = lane; bq < r1; bq += 64) {
+        double u = 0.0, nw = 0.0;
+        for (int a = 0; a < r0; ++a) {
+          const double wa = w[a];
+          u += wa * S[(1 * d + j) * mat + a * r1 + bq];
+          nw += wa * S[(0 * d + j) * mat + a * r1 + bq];
+        }
+        e += u * right[(j + 1) * rcap + bq];
+        w2[bq] = nw;
+      }
+      e = wave_sum(e);
+      if (lane == 0) {
+        const double cv = e / total - s_mean[l] * s_mean[j];
         cov[f * cov_stride + l * d + j] = ok ? cv : nan;
         cov[f * cov_stride + j * d + l] = ok ? cv : nan;
       }
-      for (int b = tid; b < r1; b += blockDim.x) {
-        double s = 0.0;
-        for (int a = 0; a < r0; ++a) s += w[a] * S[(0 * d + j) * mat + a * r1 + b];
-        w2[b] = s;
-      }
-      __syncthreads();
-      for (int b = tid; b < r1; b += blockDim.x) w[b] = w2[b];
-      __syncthreads();
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      double* t = w;
+      w = w2;
+      w2 = t;
     }
   }
 }
@@ -588,15 +617,28 @@ __global__ void __launch_bounds__(256) dot_kernel(const DevTT* __restrict__ lik,
     }
     __syncthreads();
     const int nout = l1 * p1;
-    for (int o = wid; o < nout; o += 4) {
-      const int a2 = o / p1, b2 = o % p1;
-      double s = 0.0;
-      for (int q = lane; q < p0 * n; q += 64) {
-        const int b = q / n, i = q % n;
-        s += t[((long long)a2 * p0 + b) * n + i] * bulk_to_double(pc[((long long)b * n + i) * p1 + b2]);
+    if (p0 * n <= 256 && nout >= 64) {
+      // many short sums: one thread per output (consecutive threads take
+      // consecutive b2, so the reads of P are coalesced)
+      for (int o = tid; o < nout; o += blockDim.x) {
+        const int a2 = o / p1, b2 = o % p1;
+        double s = 0.0;
+#pragma unroll 8
+        for (int q = 0; q < p0 * n; ++q)
+          s += t[(long long)a2 * p0 * n + q] * bulk_to_double(pc[(long long)q * p1 + b2]);
+        v[o] = s;  // v is consumed only through t, already complete
       }
-      s = wave_sum(s);
-      if (lane == 0) v[o] = s;  // v is consumed only through t, already complete
+    } else {
+      for (int o = wid; o < nout; o += 4) {
+        const int a2 = o / p1, b2 = o % p1;
+        double s = 0.0;
+        for (int q = lane; q < p0 * n; q += 64) {
+          const int b = q / n, i = q % n;
+          s += t[((long long)a2 * p0 + b) * n + i] * bulk_to_double(pc[((long long)b * n + i) * p1 + b2]);
+        }
+        s = wave_sum(s);
+        if (lane == 0) v[o] = s;  // v is consumed only through t, already complete
+      }
     }
     __syncthreads();
   }
