@@ -32,7 +32,7 @@ FP32_MFMA_PEAK_TFS = 157.3
 # rocprofv3 FETCH_SIZE (x2.0) and WRITE_SIZE (x1.0), the factors measured on a
 # plain 256 MiB device copy (profiles/mfma_pred_kernel_traffic_*.txt); reset to
 # None whenever the kernel changes
-TRAFFIC = 856014667
+TRAFFIC = None
 
 
 def log(msg):
@@ -193,7 +193,7 @@ def main():
         achieved = fl_p / n_p / avg_s / 1e12
         roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": FP32_MFMA_PEAK_TFS, "unit": "TFLOP/s",
                 "frac": round(achieved / FP32_MFMA_PEAK_TFS, 4), "traffic": TRAFFIC,
-                "kernel": "mfma_pred_kernel<FFused<float>>", "avg_launch_ms": round(ms_p / n_p, 4),
+                "kernel": "mfma_pred_kernel<float, FFused<float>>", "avg_launch_ms": round(ms_p / n_p, 4),
                 "launches": n_p, "algorithmic_flops_per_launch": round(fl_p / n_p),
                 "algorithmic_bytes_per_launch": round(by_p / n_p),
                 "algorithmic_GBs": round(by_p / n_p / avg_s / 1e9, 1)}

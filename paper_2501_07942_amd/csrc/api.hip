@@ -855,11 +855,12 @@ __global__ void __launch_bounds__(256) pred_work_kernel(FFused<T> fn, int B, dou
   }
 }
 
-// the FP32 direct prediction runs on the matrix cores unless mode 3 asks for
-// the vector-ALU kernel or the MFMA kernel's LDS would not fit
+// the direct prediction runs on the matrix cores unless mode 3 asks for the
+// vector-ALU kernel or the MFMA kernel's LDS would not fit.  The choice
+// depends on the launch's capacities only, never on the batch size.
 template <typename T>
 static bool use_mfma_pred(int hmax, int nmax, int pcap, int kcap) {
-  return sizeof(T) == 4 && g_predict_mode != 3 && mfma_pred_fits(hmax, nmax, pcap, kcap);
+  return g_predict_mode != 3 && mfma_pred_fits<T>(hmax, nmax, pcap, kcap);
 }
 
 template <typename T>
@@ -867,24 +868,22 @@ static tt_status launch_direct(const RCtx& c, int B, int hmax, int kcap, int nma
                                hipStream_t st) {
   ProfScope ps_(PC_PRED, st);
   FFused<T> f{c};
-  if constexpr (sizeof(T) == 4) {
-    if (use_mfma_pred<T>(hmax, nmax, pcap, kcap)) {
-      const size_t ms = mfma_pred_smem(hmax, nmax, pcap, kcap);
-      if (ms > 48 * 1024)
-        HIP_TRY(hipFuncSetAttribute((const void*)mfma_pred_kernel<FFused<float>>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)ms),
-                "mfma prediction smem");
-      const int BB = B >= 64 ? 16 : 2;
-      const int grid = kcap * ((pcap + BB - 1) / BB);
-      hipLaunchKernelGGL((mfma_pred_kernel<FFused<float>>), dim3(std::max(1, grid), 1, B), dim3(256), ms, st, f,
-                         BB);
-      TTG_LAUNCH_CHECK("mfma_pred_kernel");
-      if (g_work && (g_prof_mask & (1 << PC_PRED))) {
-        hipLaunchKernelGGL((pred_work_kernel<T>), dim3(1), dim3(256), 0, st, f, B, g_work);
-        TTG_LAUNCH_CHECK("pred_work_kernel");
-      }
-      return TT_OK;
+  if (use_mfma_pred<T>(hmax, nmax, pcap, kcap)) {
+    const size_t ms = mfma_pred_smem<T>(hmax, nmax, pcap, kcap);
+    if (ms > 48 * 1024)
+      HIP_TRY(hipFuncSetAttribute((const void*)mfma_pred_kernel<T, FFused<T>>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)ms),
+              "mfma prediction smem");
+    const int BB = B >= 64 ? 16 : 2;
+    const int grid = kcap * ((pcap + BB - 1) / BB);
+    hipLaunchKernelGGL((mfma_pred_kernel<T, FFused<T>>), dim3(std::max(1, grid), 1, B), dim3(256), ms, st, f,
+                       BB);
+    TTG_LAUNCH_CHECK("mfma_pred_kernel");
+    if (g_work && (g_prof_mask & (1 << PC_PRED))) {
+      hipLaunchKernelGGL((pred_work_kernel<T>), dim3(1), dim3(256), 0, st, f, B, g_work);
+      TTG_LAUNCH_CHECK("pred_work_kernel");
     }
+    return TT_OK;
   }
   const size_t smem = direct_smem<T>(hmax, nmax, pcap, kcap);
   if (smem > 160 * 1024) {
@@ -978,6 +977,11 @@ static tt_status launch_trsm(F f, int B, long long mcap, int rcap, hipStream_t s
     TTG_LAUNCH_CHECK("tri_apply_kernel");
     return TT_OK;
   }
+  if constexpr (sizeof(TQ) == 8) {
+    hipLaunchKernelGGL((trsm_f64_kernel<TZ, F>), dim3(stride_grid(cdiv(mcap, 256), B), 1, B), dim3(256), 0, st, f);
+    TTG_LAUNCH_CHECK("trsm_f64_kernel");
+    return TT_OK;
+  }
   const size_t qbytes = (size_t)rcap * 64 * sizeof(double);
   const size_t lbytes = (size_t)rcap * rcap * sizeof(double);
   const int l_in_lds = (qbytes + lbytes <= 150 * 1024) ? 1 : 0;
@@ -986,7 +990,7 @@ static tt_status launch_trsm(F f, int B, long long mcap, int rcap, hipStream_t s
     HIP_TRY(hipFuncSetAttribute((const void*)trsm_kernel<TZ, TQ, F>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem),
             "trsm smem attribute");
-  hipLaunchKernelGGL((trsm_kernel<TZ, TQ, F>), dim3(std::max(1, cdiv(mcap, 64)), 1, B), dim3(64), smem, st,
+  hipLaunchKernelGGL((trsm_kernel<TZ, TQ, F>), dim3(stride_grid(cdiv(mcap, 64), B), 1, B), dim3(64), smem, st,
                      f, rcap, l_in_lds);
   TTG_LAUNCH_CHECK("trsm_kernel");
   return TT_OK;
@@ -2349,9 +2353,11 @@ static tt_status run_plan(int32_t batch, const tt_filter_spec* specs, const tt_t
       const size_t need = g_predict_mode == 1
                               ? (f64 ? fused_smem<double>(p.Lmax, p.kcap, nmax, p.pcap)
                                      : fused_smem<float>(p.Lmax, p.kcap, nmax, p.pcap))
-                              : (f64 ? direct_smem<double>(hmax, nmax, p.pcap, p.kcap)
+                              : (f64 ? (use_mfma_pred<double>(hmax, nmax, p.pcap, p.kcap)
+                                            ? mfma_pred_smem<double>(hmax, nmax, p.pcap, p.kcap)
+                                            : direct_smem<double>(hmax, nmax, p.pcap, p.kcap))
                                      : (use_mfma_pred<float>(hmax, nmax, p.pcap, p.kcap)
-                                            ? mfma_pred_smem(hmax, nmax, p.pcap, p.kcap)
+                                            ? mfma_pred_smem<float>(hmax, nmax, p.pcap, p.kcap)
                                             : direct_smem<float>(hmax, nmax, p.pcap, p.kcap)));
       if (need > 160 * 1024) {
         set_error("tt_filter_run: the fused prediction needs %zu bytes of LDS", need);

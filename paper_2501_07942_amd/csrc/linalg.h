@@ -715,13 +715,11 @@ __global__ void __launch_bounds__(64) trsm_kernel(F f, int rcap, int l_in_lds) {
   const int b = blockIdx.z;
   TrsmArgs a;
   if (!f(b, a)) return;
-  const int c = blockIdx.x * 64 + threadIdx.x;
   if (blockIdx.x * 64 >= a.m) return;
   extern __shared__ double qs[];  // rcap x 64 partial solutions, then r x r factor
   double* ls = qs + (long long)rcap * 64;
   const TZ* z = reinterpret_cast<const TZ*>(a.z);
   TQ* q = reinterpret_cast<TQ*>(a.q);
-  const bool live = c < a.m;
   const bool lds_l = l_in_lds && a.r <= rcap;
   if (lds_l) {
     for (int e = threadIdx.x; e < a.r * a.r; e += 64) {
@@ -730,6 +728,10 @@ __global__ void __launch_bounds__(64) trsm_kernel(F f, int rcap, int l_in_lds) {
     }
     __syncthreads();
   }
+  // grid-stride over 64-column blocks (the grid is sized for the usual width)
+  for (int cb = blockIdx.x; cb * 64 < a.m; cb += gridDim.x) {
+  const int c = cb * 64 + threadIdx.x;
+  const bool live = c < a.m;
   for (int j = 0; j < a.r; ++j) {
     const double* lrow = lds_l ? ls + (long long)j * a.r : a.lfac + (long long)a.piv[j] * a.gcap;
     long long zc = c;
@@ -742,6 +744,55 @@ __global__ void __launch_bounds__(64) trsm_kernel(F f, int rcap, int l_in_lds) {
     const double v = s / lrow[j];
     qs[j * 64 + threadIdx.x] = v;
     if (live) q[(long long)j * a.ldq + c] = from_double<TQ>(v);
+  }
+  }
+}
+
+// FP64 outputs: the same forward substitution with the partial solutions
+// read back from the (exact, FP64) output rows instead of LDS, so a
+// workgroup needs no capacity-sized LDS and many run per CU; the pivot
+// block is staged in LDS when it is small.
+#define TS_LDS_R 64
+template <typename TZ, typename F>
+__global__ void __launch_bounds__(256) trsm_f64_kernel(F f) {
+  const int b = blockIdx.z;
+  TrsmArgs a;
+  if (!f(b, a)) return;
+  if (blockIdx.x * 256 >= a.m) return;
+  __shared__ double ls[TS_LDS_R * TS_LDS_R];
+  const int r = a.r;
+  const bool lds_l = r <= TS_LDS_R;
+  if (lds_l) {
+    for (int e = threadIdx.x; e < r * r; e += blockDim.x) {
+      const int j = e / r, t = e - (e / r) * r;
+      ls[e] = (t <= j) ? a.lfac[(long long)a.piv[j] * a.gcap + t] : 0.0;
+    }
+    __syncthreads();
+  }
+  const TZ* z = reinterpret_cast<const TZ*>(a.z);
+  double* q = reinterpret_cast<double*>(a.q);
+  for (int cb = blockIdx.x; cb * 256 < a.m; cb += gridDim.x) {
+    const int c = cb * 256 + threadIdx.x;
+    if (c >= a.m) continue;
+    long long zc = c;
+    if (a.zt_n) {
+      const int nn = a.m / a.zt_n;
+      zc = (long long)(c % nn) * a.zt_n + c / nn;
+    }
+    for (int j = 0; j < r; ++j) {
+      double s = bulk_to_double(z[(long long)a.piv[j] * a.ldz + zc]);
+      if (lds_l) {
+        const double* lrow = ls + (long long)j * r;
+#pragma unroll 4
+        for (int t = 0; t < j; ++t) s = __fma_rn(-lrow[t], q[(long long)t * a.ldq + c], s);
+        q[(long long)j * a.ldq + c] = s / lrow[j];
+      } else {
+        const double* lrow = a.lfac + (long long)a.piv[j] * a.gcap;
+#pragma unroll 4
+        for (int t = 0; t < j; ++t) s = __fma_rn(-lrow[t], q[(long long)t * a.ldq + c], s);
+        q[(long long)j * a.ldq + c] = s / lrow[j];
+      }
+    }
   }
 }
 
