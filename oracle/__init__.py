@@ -12,5 +12,7 @@ Contents
            Alg. 1 Einstein summation
   model    grid, prior, transition kernel, likelihood, moments
   filters  TT point-mass filter, dense point-mass filter, Kalman filter
+  grad     log-likelihood gradients: replayed-rank differences, complex step
+  adjoint  reverse-mode log-likelihood gradient at fixed ranks
 """
 from . import tt, model, filters  # noqa: F401
