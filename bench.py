@@ -39,7 +39,8 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def run_batch(B, runner, binding, wl, name, batch, steps, warmup, precision, profile_steps=0, seed=None):
+def run_batch(B, runner, binding, wl, name, batch, steps, warmup, precision, profile_steps=0, seed=None,
+              graph_replays=0):
     import torch
     total = 1 + warmup + steps + profile_steps
     kw = {} if seed is None else {"seed": seed}
@@ -71,8 +72,25 @@ def run_batch(B, runner, binding, wl, name, batch, steps, warmup, precision, pro
         prof = binding.profile_end()
     st = run.status.cpu().numpy()
     log(f"[bench] timed {steps} steps: {ms:.2f} ms, failed filters {int((st != 0).sum())}")
+    graph = None
+    if graph_replays:
+        # the last step recorded once as a HIP graph, replayed as a streaming
+        # filter fed the same measurement (timing only; the results are
+        # checked against eager steps in the GPU tests)
+        g = run.graph(z, k_begin=total - 1, k_count=1)
+        g.launch()
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(graph_replays):
+            g.launch()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        graph = {"ms_per_step": round(ev0.elapsed_time(ev1) / graph_replays, 3), "replays": graph_replays,
+                 "eager_ms_per_step": round(ms / steps, 3)}
+        g.destroy()
+        log(f"[bench] graph replay: {graph}")
     return {"run": run, "ms": ms, "prof": prof, "specs": specs, "kernels": kernels, "zs": zs,
-            "status": st, "total": total}
+            "status": st, "total": total, "graph": graph}
 
 
 def cpu_baseline(wl, steps=6, warm=3):
@@ -151,6 +169,8 @@ def main():
     ap.add_argument("--no-grad", action="store_true", help="skip the gradient timing")
     ap.add_argument("--grad-steps", type=int, default=8)
     ap.add_argument("--grad-batch", type=int, default=32)
+    ap.add_argument("--graph-replays", type=int, default=3,
+                    help="replays of one step recorded as a HIP graph (0: skip)")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -175,7 +195,7 @@ def main():
         return
 
     main_res = run_batch(None, runner, binding, wl, args.workload, args.batch, args.steps, args.warmup,
-                         binding.F32, profile_steps=args.profile_steps)
+                         binding.F32, profile_steps=args.profile_steps, graph_replays=args.graph_replays)
     B = args.batch
     ms = main_res["ms"]
     value = B * args.steps / (ms / 1000.0)
@@ -216,6 +236,7 @@ def main():
                    "workspace_GB": round(main_res["run"].ws.numel() * main_res["run"].ws.element_size() / 1e9, 2)},
         "roofline": roof,
         "kernel_ms_per_step": kernel_ms,
+        "graph_step": main_res["graph"],
     }
     if not args.no_plain:
         plain = run_batch(None, runner, binding, wl, args.workload, 1, args.steps, args.warmup, binding.F64)

@@ -255,6 +255,40 @@ tt_status tt_filter_run(int32_t batch, const tt_filter_spec* specs, const tt_tra
                         void* stream);
 
 /* ---------------------------------------------------------------------
+ * tt_filter_graph_* -- the steps of tt_filter_run recorded once as a HIP
+ * graph and replayed (one graph per time step when k_count = 1; the
+ * recursion of Alg. 2 repeated without host launch work).
+ *
+ * tt_filter_graph_create takes exactly the arguments of tt_filter_run.  It
+ * validates them, uploads the batch descriptors into ws (synchronously, on
+ * stream), records the launches of steps k_begin .. k_begin+k_count-1 on a
+ * capture stream of its own and instantiates the graph; nothing runs.
+ * k_begin must be >= 1: step 0 starts from the prior and is run once with
+ * tt_filter_run.  Every tt_filter_graph_launch then executes those steps on
+ * stream, continuing from whatever filter state the workspace holds, reading
+ * z_dev at the rows of those steps and writing the outputs of those steps
+ * (a streaming filter: write the next measurement into z_dev's row k_begin,
+ * launch, read log_c / mean at k_begin).  Every pointer is baked into the
+ * graph: z_dev, the outputs and ws must stay allocated and unchanged in
+ * layout until tt_filter_graph_destroy, and the specs/kernels arrays are not
+ * read again.  Results are bitwise those of tt_filter_run on the same state.
+ * Errors: as tt_filter_run; TT_ERR_ARG for k_begin < 1, a null handle or
+ * active profiling (tt_profile_begin); TT_ERR_HIP when capture or
+ * instantiation fails.  The handle is owned by the caller.
+ * --------------------------------------------------------------------- */
+typedef struct tt_graph_s tt_graph;
+
+tt_status tt_filter_graph_create(int32_t batch, const tt_filter_spec* specs, const tt_train* kernels,
+                                 int32_t n_kernels, const double* z_dev, int32_t zdim, int32_t K, int32_t k_begin,
+                                 int32_t k_count, int32_t precision, double* loglik_dev, double* log_c_dev,
+                                 double* log_mpred_dev, double* mean_dev, double* cov_dev, int32_t* ranks_dev,
+                                 int32_t* status_dev, int32_t* ranks_pred_dev, const int32_t* replay_pred_dev,
+                                 const int32_t* replay_filt_dev, void* ws, size_t ws_bytes, void* stream,
+                                 tt_graph** out);
+tt_status tt_filter_graph_launch(tt_graph* graph, void* stream);
+void tt_filter_graph_destroy(tt_graph* graph);
+
+/* ---------------------------------------------------------------------
  * How tt_filter_run evaluates the prediction for d >= 3 (process-wide
  * setting; all modes compute the same Z_k = conv(K_k, P_k) x_3 L_{k+1} that
  * the rounding's right-to-left sweep consumes, Sec. 2.1 eq. tpmconvFFT and

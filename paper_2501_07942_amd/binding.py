@@ -74,6 +74,10 @@ def _load():
         "tt_get_predict_mode": (I, []),
         "tt_profile_end": (I, [P, P, P, P, I]),
         "tt_filter_run": (I, [I, P, P, I, P, I, I, I, I, I, P, P, P, P, P, P, P, P, P, P, P, S, P]),
+        "tt_filter_graph_create": (I, [I, P, P, I, P, I, I, I, I, I, P, P, P, P, P, P, P, P, P, P, P, S, P,
+                                       C.POINTER(C.c_void_p)]),
+        "tt_filter_graph_launch": (I, [P, P]),
+        "tt_filter_graph_destroy": (None, [P]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -87,7 +91,8 @@ EXPORTED = ("tt_train_elems", "tt_last_error", "tt_version", "tt_kernel_build_wo
             "tt_kernel_build", "tt_predict_workspace", "tt_predict", "tt_update_workspace",
             "tt_update", "tt_round_workspace", "tt_round", "tt_normalize_moments_workspace",
             "tt_normalize_moments", "tt_filter_run_workspace", "tt_filter_run", "tt_profile_begin",
-            "tt_profile_end", "tt_set_predict_mode", "tt_get_predict_mode")
+            "tt_profile_end", "tt_set_predict_mode", "tt_get_predict_mode", "tt_filter_graph_create",
+            "tt_filter_graph_launch", "tt_filter_graph_destroy")
 
 PREDICT_DIRECT, PREDICT_FFT, PREDICT_UNFUSED, PREDICT_DIRECT_VALU = 0, 1, 2, 3
 
@@ -359,3 +364,46 @@ class FilterRun:
                                rf.data_ptr() if rf is not None else None, self.ws.data_ptr(),
                                self.ws.numel(), _stream())
         _check(st, "tt_filter_run")
+
+    def graph(self, z, k_begin: int, k_count: int = 1, moments: bool = True) -> "FilterGraph":
+        """Record steps k_begin .. k_begin+k_count-1 (k_begin >= 1) as a HIP
+        graph over this object's buffers (tt_filter_graph_create).  Each
+        launch() continues from the current workspace state; ``z`` must stay
+        alive and may be rewritten in place between launches."""
+        if self.precision not in (F32, F64):
+            raise TTError("bad precision")
+        h = C.c_void_p()
+        st = LIB.tt_filter_graph_create(self.B, self.specs, self.karr, len(self.kernels), z.data_ptr(), self.zdim,
+                                        self.K, int(k_begin), int(k_count), self.precision,
+                                        self.loglik.data_ptr(), self.log_c.data_ptr(), self.log_mpred.data_ptr(),
+                                        self.mean.data_ptr() if moments else None,
+                                        self.cov.data_ptr() if moments else None,
+                                        self.ranks.data_ptr(), self.status.data_ptr(), self.ranks_pred.data_ptr(),
+                                        None, None, self.ws.data_ptr(), self.ws.numel(), _stream(), C.byref(h))
+        _check(st, "tt_filter_graph_create")
+        return FilterGraph(h, (self, z))
+
+
+class FilterGraph:
+    """A recorded HIP graph of filter steps (tt_filter_graph_*); keeps the
+    buffers it was recorded over alive."""
+
+    def __init__(self, handle, keep):
+        self._h = handle
+        self._keep = keep
+
+    def launch(self):
+        if self._h is None:
+            raise TTError("graph destroyed")
+        _check(LIB.tt_filter_graph_launch(self._h, _stream()), "tt_filter_graph_launch")
+
+    def destroy(self):
+        if self._h is not None:
+            LIB.tt_filter_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

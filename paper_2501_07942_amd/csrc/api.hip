@@ -4,6 +4,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <new>
 #include <type_traits>
 #include <vector>
 
@@ -2506,13 +2507,19 @@ size_t tt_filter_run_workspace(int32_t batch, const tt_filter_spec* specs, const
   return ar.used + 256;
 }
 
-tt_status tt_filter_run(int32_t batch, const tt_filter_spec* specs, const tt_train* kernels, int32_t n_kernels,
-                        const double* z_dev, int32_t zdim, int32_t K, int32_t k_begin, int32_t k_count,
-                        int32_t precision, double* loglik_dev,
-                        double* log_c_dev, double* log_mpred_dev, double* mean_dev, double* cov_dev,
-                        int32_t* ranks_dev, int32_t* status_dev, int32_t* ranks_pred_dev,
-                        const int32_t* replay_pred_dev, const int32_t* replay_filt_dev, void* ws,
-                        size_t ws_bytes, void* stream) {
+}  // extern "C"
+
+namespace ttg {
+
+// Validation, planning and the descriptor upload of tt_filter_run; then the
+// steps, launched on st, or recorded into *graph when graph is non-null.
+static tt_status filter_run_impl(int32_t batch, const tt_filter_spec* specs, const tt_train* kernels,
+                                 int32_t n_kernels, const double* z_dev, int32_t zdim, int32_t K, int32_t k_begin,
+                                 int32_t k_count, int32_t precision, double* loglik_dev, double* log_c_dev,
+                                 double* log_mpred_dev, double* mean_dev, double* cov_dev, int32_t* ranks_dev,
+                                 int32_t* status_dev, int32_t* ranks_pred_dev, const int32_t* replay_pred_dev,
+                                 const int32_t* replay_filt_dev, void* ws, size_t ws_bytes, hipStream_t st,
+                                 hipGraph_t* graph) {
   if (!kernels || n_kernels < 1 || !z_dev || K < 1 || zdim < 1 || !loglik_dev || !log_c_dev || !log_mpred_dev ||
       !status_dev || !ws) {
     set_error("tt_filter_run: null pointer or bad size");
@@ -2544,7 +2551,6 @@ tt_status tt_filter_run(int32_t batch, const tt_filter_spec* specs, const tt_tra
     set_error("tt_filter_run: workspace too small (%zu < %zu)", ws_bytes, ar.used);
     return TT_ERR_WORKSPACE;
   }
-  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   TT_TRY(upload(p.dP, p.vP, st));
   TT_TRY(upload(p.dX, p.vX, st));
   TT_TRY(upload(p.dL, p.vL, st));
@@ -2556,13 +2562,120 @@ tt_status tt_filter_run(int32_t batch, const tt_filter_spec* specs, const tt_tra
     TT_TRY(upload(p.dfp, p.vfp, st));
     TT_TRY(upload(p.dKk, p.vKk, st));
   }
-  if (precision == TT_F64)
-    return run_steps<double, AccDD>(p, batch, z_dev, zdim, K, k_begin, k_count, loglik_dev, log_c_dev, log_mpred_dev,
-                                    mean_dev, cov_dev, ranks_dev, ranks_pred_dev, replay_pred_dev, replay_filt_dev,
-                                    specs, st);
-  return run_steps<float, AccD>(p, batch, z_dev, zdim, K, k_begin, k_count, loglik_dev, log_c_dev, log_mpred_dev,
-                                mean_dev, cov_dev, ranks_dev, ranks_pred_dev, replay_pred_dev, replay_filt_dev,
-                                specs, st);
+  hipStream_t run_st = st;
+  if (graph) {
+    // capture on a stream of our own (the caller's may be the null stream);
+    // the descriptors are already on the device, so nothing in the recorded
+    // steps reads host memory
+    HIP_TRY(hipStreamCreateWithFlags(&run_st, hipStreamNonBlocking), "capture stream");
+    const hipError_t e = hipStreamBeginCapture(run_st, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) {
+      hipStreamDestroy(run_st);
+      return check_hip(e, "hipStreamBeginCapture");
+    }
+  }
+  tt_status rs = precision == TT_F64
+                     ? run_steps<double, AccDD>(p, batch, z_dev, zdim, K, k_begin, k_count, loglik_dev, log_c_dev,
+                                                log_mpred_dev, mean_dev, cov_dev, ranks_dev, ranks_pred_dev,
+                                                replay_pred_dev, replay_filt_dev, specs, run_st)
+                     : run_steps<float, AccD>(p, batch, z_dev, zdim, K, k_begin, k_count, loglik_dev, log_c_dev,
+                                              log_mpred_dev, mean_dev, cov_dev, ranks_dev, ranks_pred_dev,
+                                              replay_pred_dev, replay_filt_dev, specs, run_st);
+  if (graph) {
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(run_st, &g);
+    hipStreamDestroy(run_st);
+    if (rs != TT_OK) {
+      if (g) hipGraphDestroy(g);
+      return rs;
+    }
+    if (e != hipSuccess) {
+      if (g) hipGraphDestroy(g);
+      return check_hip(e, "hipStreamEndCapture");
+    }
+    *graph = g;
+  }
+  return rs;
+}
+
+}  // namespace ttg
+
+struct tt_graph_s {
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
+extern "C" {
+
+tt_status tt_filter_run(int32_t batch, const tt_filter_spec* specs, const tt_train* kernels, int32_t n_kernels,
+                        const double* z_dev, int32_t zdim, int32_t K, int32_t k_begin, int32_t k_count,
+                        int32_t precision, double* loglik_dev,
+                        double* log_c_dev, double* log_mpred_dev, double* mean_dev, double* cov_dev,
+                        int32_t* ranks_dev, int32_t* status_dev, int32_t* ranks_pred_dev,
+                        const int32_t* replay_pred_dev, const int32_t* replay_filt_dev, void* ws,
+                        size_t ws_bytes, void* stream) {
+  return filter_run_impl(batch, specs, kernels, n_kernels, z_dev, zdim, K, k_begin, k_count, precision, loglik_dev,
+                         log_c_dev, log_mpred_dev, mean_dev, cov_dev, ranks_dev, status_dev, ranks_pred_dev,
+                         replay_pred_dev, replay_filt_dev, ws, ws_bytes, reinterpret_cast<hipStream_t>(stream),
+                         nullptr);
+}
+
+tt_status tt_filter_graph_create(int32_t batch, const tt_filter_spec* specs, const tt_train* kernels,
+                                 int32_t n_kernels, const double* z_dev, int32_t zdim, int32_t K, int32_t k_begin,
+                                 int32_t k_count, int32_t precision, double* loglik_dev, double* log_c_dev,
+                                 double* log_mpred_dev, double* mean_dev, double* cov_dev, int32_t* ranks_dev,
+                                 int32_t* status_dev, int32_t* ranks_pred_dev, const int32_t* replay_pred_dev,
+                                 const int32_t* replay_filt_dev, void* ws, size_t ws_bytes, void* stream,
+                                 tt_graph** out) {
+  if (!out) {
+    set_error("tt_filter_graph_create: null output handle");
+    return TT_ERR_ARG;
+  }
+  *out = nullptr;
+  if (k_begin < 1) {
+    set_error("tt_filter_graph_create: k_begin must be >= 1 (step 0 starts from the prior: run it eagerly)");
+    return TT_ERR_ARG;
+  }
+  if (g_prof_mask) {
+    set_error("tt_filter_graph_create: profiling is active");
+    return TT_ERR_ARG;
+  }
+  hipGraph_t g = nullptr;
+  TT_TRY(filter_run_impl(batch, specs, kernels, n_kernels, z_dev, zdim, K, k_begin, k_count, precision, loglik_dev,
+                         log_c_dev, log_mpred_dev, mean_dev, cov_dev, ranks_dev, status_dev, ranks_pred_dev,
+                         replay_pred_dev, replay_filt_dev, ws, ws_bytes, reinterpret_cast<hipStream_t>(stream),
+                         &g));
+  hipGraphExec_t ex = nullptr;
+  const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    hipGraphDestroy(g);
+    return check_hip(e, "hipGraphInstantiate");
+  }
+  tt_graph* h = new (std::nothrow) tt_graph_s{g, ex};
+  if (!h) {
+    hipGraphExecDestroy(ex);
+    hipGraphDestroy(g);
+    set_error("tt_filter_graph_create: out of host memory");
+    return TT_ERR_ARG;
+  }
+  *out = h;
+  return TT_OK;
+}
+
+tt_status tt_filter_graph_launch(tt_graph* g, void* stream) {
+  if (!g) {
+    set_error("tt_filter_graph_launch: null handle");
+    return TT_ERR_ARG;
+  }
+  HIP_TRY(hipGraphLaunch(g->exec, reinterpret_cast<hipStream_t>(stream)), "hipGraphLaunch");
+  return TT_OK;
+}
+
+void tt_filter_graph_destroy(tt_graph* g) {
+  if (!g) return;
+  hipGraphExecDestroy(g->exec);
+  hipGraphDestroy(g->graph);
+  delete g;
 }
 
 }  // extern "C"

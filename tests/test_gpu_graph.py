@@ -1,0 +1,58 @@
+"""A filter step recorded as a HIP graph (tt_filter_graph_*) and replayed
+as a streaming filter: every replay must equal the eager recursion bit for
+bit, with eager work and synchronisations between the replays."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mods():
+    import torch
+    from paper_2501_07942_amd import binding, runner, workload
+    assert torch.cuda.is_available()
+    return binding, runner, workload
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_graph_replays_equal_the_eager_recursion(mods, precision):
+    B, runner, wl = mods
+    import torch
+    prec = B.F64 if precision == "f64" else B.F32
+    K = 6
+    specs, xs, zs = wl.make_batch("range4d", batch=3, steps=K, d=3, n=32, cap=6)
+    print(f"graph replay: {precision}, B=3, d=3, N=32, cap 6, K={K}", flush=True)
+    ref, z = runner.run_filters(specs, zs, prec)
+    kernels, kidx, kr = runner.build_kernels(specs, prec)
+    fspecs = runner.filter_specs(specs, kidx, kr, 64)
+    # streaming run over a two-row measurement buffer: row 0 for the prior
+    # update, row 1 rewritten before every replay of the steady step
+    zs2 = z[:, :2, :].clone()
+    run = B.FilterRun(fspecs, kernels, 2, z.shape[2], prec)
+    run(zs2, k_begin=0, k_count=1)
+    g = run.graph(zs2, k_begin=1, k_count=1)
+    lc_ref = ref.log_c.cpu().numpy()
+    mean_ref = ref.mean.cpu().numpy()
+    ranks_ref = ref.ranks.cpu().numpy()
+    for k in range(1, K):
+        zs2[:, 1, :].copy_(z[:, k, :])
+        g.launch()
+        torch.cuda.synchronize()
+        assert np.array_equal(run.log_c[:, 1].cpu().numpy(), lc_ref[:, k]), k
+        assert np.array_equal(run.mean[:, 1].cpu().numpy(), mean_ref[:, k]), k
+        assert np.array_equal(run.ranks[:, 1].cpu().numpy(), ranks_ref[:, k]), k
+        # unrelated eager work between replays
+        torch.ones(1000, device="cuda").sum().item()
+    assert int(run.status.abs().sum().item()) == 0
+    g.destroy()
+
+
+def test_graph_create_rejects_step_zero(mods):
+    B, runner, wl = mods
+    specs, xs, zs = wl.make_batch("range4d", batch=1, steps=3, d=3, n=24, cap=4)
+    kernels, kidx, kr = runner.build_kernels(specs, B.F64)
+    z, zdim = runner.z_tensor(zs)
+    run = B.FilterRun(runner.filter_specs(specs, kidx, kr, 64), kernels, 3, zdim, B.F64)
+    with pytest.raises(B.TTError):
+        run.graph(z, k_begin=0)
