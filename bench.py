@@ -40,7 +40,7 @@ def log(msg):
 
 
 def run_batch(B, runner, binding, wl, name, batch, steps, warmup, precision, profile_steps=0, seed=None,
-              graph_replays=0):
+              graph_replays=0, autotune=False):
     import torch
     total = 1 + warmup + steps + profile_steps
     kw = {} if seed is None else {"seed": seed}
@@ -53,6 +53,12 @@ def run_batch(B, runner, binding, wl, name, batch, steps, warmup, precision, pro
     torch.cuda.synchronize()
     log(f"[bench] {name} B={batch} prec={'f32' if precision == binding.F32 else 'f64'} setup {time.time() - t0:.1f}s "
         f"kernel ranks {kernels[0].cap}")
+    tune = None
+    if autotune and total >= 9:
+        # pick the prediction's launch shape on this batch; the recursion then
+        # restarts from the prior
+        tune = run.autotune(z, warmup_steps=min(4, total - 9), rounds=2)
+        log(f"[bench] autotune: {tune}")
     # warm-up: step 0 (update only) and `warmup` full steps, untimed
     run(z, k_begin=0, k_count=1 + warmup)
     torch.cuda.synchronize()
@@ -90,7 +96,7 @@ def run_batch(B, runner, binding, wl, name, batch, steps, warmup, precision, pro
         g.destroy()
         log(f"[bench] graph replay: {graph}")
     return {"run": run, "ms": ms, "prof": prof, "specs": specs, "kernels": kernels, "zs": zs,
-            "status": st, "total": total, "graph": graph}
+            "status": st, "total": total, "graph": graph, "autotune": tune}
 
 
 def cpu_baseline(wl, steps=6, warm=3):
@@ -169,6 +175,7 @@ def main():
     ap.add_argument("--no-grad", action="store_true", help="skip the gradient timing")
     ap.add_argument("--grad-steps", type=int, default=8)
     ap.add_argument("--grad-batch", type=int, default=32)
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default prediction launch shape")
     ap.add_argument("--graph-replays", type=int, default=3,
                     help="replays of one step recorded as a HIP graph (0: skip)")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="MIB",
@@ -195,7 +202,8 @@ def main():
         return
 
     main_res = run_batch(None, runner, binding, wl, args.workload, args.batch, args.steps, args.warmup,
-                         binding.F32, profile_steps=args.profile_steps, graph_replays=args.graph_replays)
+                         binding.F32, profile_steps=args.profile_steps, graph_replays=args.graph_replays,
+                         autotune=not args.no_autotune)
     B = args.batch
     ms = main_res["ms"]
     value = B * args.steps / (ms / 1000.0)
@@ -237,6 +245,7 @@ def main():
         "roofline": roof,
         "kernel_ms_per_step": kernel_ms,
         "graph_step": main_res["graph"],
+        "autotune": main_res["autotune"],
     }
     if not args.no_plain:
         plain = run_batch(None, runner, binding, wl, args.workload, 1, args.steps, args.warmup, binding.F64)

@@ -289,6 +289,35 @@ tt_status tt_filter_graph_launch(tt_graph* graph, void* stream);
 void tt_filter_graph_destroy(tt_graph* graph);
 
 /* ---------------------------------------------------------------------
+ * tt_autotune_prediction -- time the launch shapes of the matrix-core
+ * prediction on the caller's own batch and keep the fastest.
+ *
+ * The prediction (the per-core convolution of Sec. 4.2, fused with the
+ * first rounding sweep) gives each workgroup one kernel row block and BB
+ * density fibres; BB trades LDS reuse of the kernel block against the
+ * number of workgroups.  The tuner runs step 0 and warmup_steps steps, then
+ * `rounds` rounds of one step per candidate BB in {2, 4, 8, 16}, continuing
+ * the recursion in ws and timing every step with HIP events on stream (it
+ * synchronises).  Each candidate keeps its fastest step; the fastest
+ * candidate is recorded for this launch shape (precision, batch size,
+ * largest kernel half-width, grid size, PMD and kernel rank capacities) and
+ * used by later tt_filter_run calls with the same shape.  BB does not change
+ * any result bit.  Arguments are those of tt_filter_run (moments and rank
+ * records are not written); K >= 1 + warmup_steps + 4 * rounds.  Outputs:
+ * *best_bb (0 when the batch does not use the matrix-core prediction) and
+ * ms_per_candidate[4] (ms of the candidate's fastest step).  The filter
+ * state and outputs left in ws are those of the tuning steps: start the
+ * real run at k_begin = 0.  Errors: TT_ERR_ARG for bad sizes, null outputs
+ * or active profiling; as tt_filter_run otherwise.
+ * --------------------------------------------------------------------- */
+#define TT_TUNE_CANDIDATES 4
+tt_status tt_autotune_prediction(int32_t batch, const tt_filter_spec* specs, const tt_train* kernels,
+                                 int32_t n_kernels, const double* z_dev, int32_t zdim, int32_t K,
+                                 int32_t precision, double* loglik_dev, double* log_c_dev, double* log_mpred_dev,
+                                 int32_t* status_dev, void* ws, size_t ws_bytes, void* stream,
+                                 int32_t warmup_steps, int32_t rounds, int32_t* best_bb, float* ms_per_candidate);
+
+/* ---------------------------------------------------------------------
  * How tt_filter_run evaluates the prediction for d >= 3 (process-wide
  * setting; all modes compute the same Z_k = conv(K_k, P_k) x_3 L_{k+1} that
  * the rounding's right-to-left sweep consumes, Sec. 2.1 eq. tpmconvFFT and

@@ -77,6 +77,8 @@ def _load():
         "tt_filter_graph_create": (I, [I, P, P, I, P, I, I, I, I, I, P, P, P, P, P, P, P, P, P, P, P, S, P,
                                        C.POINTER(C.c_void_p)]),
         "tt_filter_graph_launch": (I, [P, P]),
+        "tt_autotune_prediction": (I, [I, P, P, I, P, I, I, I, P, P, P, P, P, S, P, I, I, C.POINTER(C.c_int32),
+                                       C.POINTER(C.c_float)]),
         "tt_filter_graph_destroy": (None, [P]),
     }
     for name, (res, args) in sigs.items():
@@ -92,7 +94,7 @@ EXPORTED = ("tt_train_elems", "tt_last_error", "tt_version", "tt_kernel_build_wo
             "tt_update", "tt_round_workspace", "tt_round", "tt_normalize_moments_workspace",
             "tt_normalize_moments", "tt_filter_run_workspace", "tt_filter_run", "tt_profile_begin",
             "tt_profile_end", "tt_set_predict_mode", "tt_get_predict_mode", "tt_filter_graph_create",
-            "tt_filter_graph_launch", "tt_filter_graph_destroy")
+            "tt_filter_graph_launch", "tt_filter_graph_destroy", "tt_autotune_prediction")
 
 PREDICT_DIRECT, PREDICT_FFT, PREDICT_UNFUSED, PREDICT_DIRECT_VALU = 0, 1, 2, 3
 
@@ -364,6 +366,21 @@ class FilterRun:
                                rf.data_ptr() if rf is not None else None, self.ws.data_ptr(),
                                self.ws.numel(), _stream())
         _check(st, "tt_filter_run")
+
+    def autotune(self, z, warmup_steps: int = 3, rounds: int = 2) -> dict:
+        """tt_autotune_prediction on this batch: times each prediction launch
+        shape (one step per candidate per round after the warm-up) and keeps
+        the fastest for later runs of the same shape.  The workspace state
+        afterwards is the tuner's: rerun from k_begin = 0."""
+        best = C.c_int32(0)
+        ms = (C.c_float * 4)()
+        st = LIB.tt_autotune_prediction(self.B, self.specs, self.karr, len(self.kernels), z.data_ptr(), self.zdim,
+                                        self.K, self.precision, self.loglik.data_ptr(), self.log_c.data_ptr(),
+                                        self.log_mpred.data_ptr(), self.status.data_ptr(), self.ws.data_ptr(),
+                                        self.ws.numel(), _stream(), int(warmup_steps), int(rounds), C.byref(best),
+                                        ms)
+        _check(st, "tt_autotune_prediction")
+        return {"best_bb": int(best.value), "ms_per_step": {bb: round(float(m), 3) for bb, m in zip((2, 4, 8, 16), ms)}}
 
     def graph(self, z, k_begin: int, k_count: int = 1, moments: bool = True) -> "FilterGraph":
         """Record steps k_begin .. k_begin+k_count-1 (k_begin >= 1) as a HIP

@@ -820,6 +820,29 @@ static tt_status launch_tall(F f, int B, long long Mcap, int Ncap, hipStream_t s
 // 2 materialised product + tall GEMM
 static int g_predict_mode = 0;
 
+// Fibres per workgroup of the MFMA prediction (BB), picked by
+// tt_autotune_prediction per launch shape; BB only regroups work, every
+// output element sums the same terms in the same order whatever BB is.
+struct TuneKey {
+  int f64, B, hmax, nmax, pcap, kcap;
+  bool operator==(const TuneKey& o) const {
+    return f64 == o.f64 && B == o.B && hmax == o.hmax && nmax == o.nmax && pcap == o.pcap && kcap == o.kcap;
+  }
+};
+static std::vector<std::pair<TuneKey, int>> g_tuned_bb;
+static int g_force_bb = 0;       // candidate under test (0: none)
+static TuneKey g_last_key{};     // shape of the last MFMA prediction launch
+static bool g_have_key = false;
+
+static int pred_bb(const TuneKey& key, int B) {
+  g_last_key = key;
+  g_have_key = true;
+  if (g_force_bb) return g_force_bb;
+  for (const auto& e : g_tuned_bb)
+    if (e.first == key) return e.second;
+  return B >= 64 ? 16 : 2;
+}
+
 template <typename T>
 static size_t direct_smem(int hmax, int nmax, int pcap, int kcap) {
   const int taps = 2 * hmax + 1;
@@ -875,7 +898,7 @@ static tt_status launch_direct(const RCtx& c, int B, int hmax, int kcap, int nma
       HIP_TRY(hipFuncSetAttribute((const void*)mfma_pred_kernel<T, FFused<T>>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)ms),
               "mfma prediction smem");
-    const int BB = B >= 64 ? 16 : 2;
+    const int BB = pred_bb(TuneKey{sizeof(T) == 8 ? 1 : 0, B, hmax, nmax, pcap, kcap}, B);
     const int grid = kcap * ((pcap + BB - 1) / BB);
     hipLaunchKernelGGL((mfma_pred_kernel<T, FFused<T>>), dim3(std::max(1, grid), 1, B), dim3(256), ms, st, f,
                        BB);
@@ -2740,5 +2763,78 @@ tt_status tt_set_predict_mode(int32_t mode) {
 }
 
 int32_t tt_get_predict_mode(void) { return g_predict_mode; }
+
+tt_status tt_autotune_prediction(int32_t batch, const tt_filter_spec* specs, const tt_train* kernels,
+                                 int32_t n_kernels, const double* z_dev, int32_t zdim, int32_t K,
+                                 int32_t precision, double* loglik_dev, double* log_c_dev, double* log_mpred_dev,
+                                 int32_t* status_dev, void* ws, size_t ws_bytes, void* stream,
+                                 int32_t warmup_steps, int32_t rounds, int32_t* best_bb, float* ms_per_candidate) {
+  static const int cand[TT_TUNE_CANDIDATES] = {2, 4, 8, 16};
+  if (!best_bb || !ms_per_candidate || warmup_steps < 0 || rounds < 1 ||
+      K < 1 + warmup_steps + TT_TUNE_CANDIDATES * rounds) {
+    set_error("tt_autotune_prediction: need outputs, rounds >= 1 and K >= 1 + warmup_steps + %d * rounds",
+              TT_TUNE_CANDIDATES);
+    return TT_ERR_ARG;
+  }
+  if (g_prof_mask) {
+    set_error("tt_autotune_prediction: profiling is active");
+    return TT_ERR_ARG;
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  auto run = [&](int kb, int kc) {
+    return filter_run_impl(batch, specs, kernels, n_kernels, z_dev, zdim, K, kb, kc, precision, loglik_dev,
+                           log_c_dev, log_mpred_dev, nullptr, nullptr, nullptr, status_dev, nullptr, nullptr,
+                           nullptr, ws, ws_bytes, st, nullptr);
+  };
+  // step 0 and the warm-up steps bring the ranks to their working size
+  TT_TRY(run(0, 1 + warmup_steps));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0), "tune event");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    set_error("tt_autotune_prediction: event creation failed");
+    return TT_ERR_HIP;
+  }
+  for (int c = 0; c < TT_TUNE_CANDIDATES; ++c) ms_per_candidate[c] = 3.4e38f;
+  g_have_key = false;
+  tt_status rs = TT_OK;
+  int k = 1 + warmup_steps;
+  // one step per candidate per round, candidates in turn, so that a slow
+  // drift of the ranks affects all of them alike; each keeps its fastest step
+  for (int r = 0; r < rounds && rs == TT_OK; ++r)
+    for (int c = 0; c < TT_TUNE_CANDIDATES && rs == TT_OK; ++c, ++k) {
+      g_force_bb = cand[c];
+      hipEventRecord(e0, st);
+      rs = run(k, 1);
+      hipEventRecord(e1, st);
+      if (rs != TT_OK) break;
+      if (hipEventSynchronize(e1) != hipSuccess) {
+        set_error("tt_autotune_prediction: event synchronisation failed");
+        rs = TT_ERR_HIP;
+        break;
+      }
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, e0, e1);
+      ms_per_candidate[c] = std::min(ms_per_candidate[c], ms);
+    }
+  g_force_bb = 0;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rs != TT_OK) return rs;
+  int best = 0;
+  for (int c = 1; c < TT_TUNE_CANDIDATES; ++c)
+    if (ms_per_candidate[c] < ms_per_candidate[best]) best = c;
+  *best_bb = g_have_key ? cand[best] : 0;  // 0: the matrix-core prediction was not used by this batch
+  if (g_have_key) {
+    bool found = false;
+    for (auto& e : g_tuned_bb)
+      if (e.first == g_last_key) {
+        e.second = cand[best];
+        found = true;
+      }
+    if (!found) g_tuned_bb.push_back({g_last_key, cand[best]});
+  }
+  return TT_OK;
+}
 
 }  // extern "C"

@@ -56,3 +56,24 @@ def test_graph_create_rejects_step_zero(mods):
     run = B.FilterRun(runner.filter_specs(specs, kidx, kr, 64), kernels, 3, zdim, B.F64)
     with pytest.raises(B.TTError):
         run.graph(z, k_begin=0)
+
+
+def test_autotuned_prediction_shape_changes_no_result_bit(mods):
+    # the tuner picks the fibres per workgroup of the matrix-core prediction;
+    # a run after tuning equals the run before it bit for bit
+    B, runner, wl = mods
+    import torch
+    K = 9
+    specs, xs, zs = wl.make_batch("range4d", batch=4, steps=K, d=4, n=48, cap=8)
+    print("autotune: FP32, B=4, d=4, N=48, cap 8", flush=True)
+    before, z = runner.run_filters(specs, zs, B.F32)
+    kernels, kidx, kr = runner.build_kernels(specs, B.F32)
+    run = B.FilterRun(runner.filter_specs(specs, kidx, kr, 64), kernels, K, z.shape[2], B.F32)
+    res = run.autotune(z, warmup_steps=0, rounds=2)
+    torch.cuda.synchronize()
+    assert res["best_bb"] in (2, 4, 8, 16)
+    assert all(v > 0 for v in res["ms_per_step"].values())
+    run(z)
+    torch.cuda.synchronize()
+    assert np.array_equal(run.log_c.cpu().numpy(), before.log_c.cpu().numpy())
+    assert np.array_equal(run.mean.cpu().numpy(), before.mean.cpu().numpy())
