@@ -198,6 +198,57 @@ tt_status tt_normalize_moments(int32_t batch, const tt_grid* grids, const tt_tra
 size_t tt_normalize_moments_workspace(int32_t batch, const tt_train* t);
 
 /* ---------------------------------------------------------------------
+ * Adjoints (reverse-mode derivatives) of the linear steps.
+ *
+ * Convention: a TT is its stored cores times exp(log_scale).  An adjoint
+ * train has its primal's modes and ranks (the library sets its ranks from
+ * the primal); its cores hold the derivative of the caller's scalar with
+ * respect to the primal's stored cores and its log_scale field holds the
+ * derivative with respect to the primal's log-scale.  Its status word is
+ * set to TT_STATUS_CAPACITY when a rank does not fit its capacity or the
+ * incoming adjoint's ranks do not match (the cores are then not written),
+ * else 0.  All sums are FP64 in a fixed order.  Workspace:
+ * tt_adjoint_workspace(batch, d, largest rank capacity) bytes, used for the
+ * uploaded descriptors (and the sum environments of tt_normalize_adjoint);
+ * the calls are asynchronous on stream after a synchronous descriptor
+ * upload, like the forward calls.
+ *
+ * tt_predict_adjoint: for the prediction C = K (*) P of tt_predict (Sec.
+ * 4.2: C_k(a rp0 + c, i, b rp1 + e) = sum_m K_k(a, m+h, b) P_k(c, i-m, e),
+ * P = 0 off the grid; log_scale(C) = log_scale(K) + log_scale(P)), given
+ * c_bar (ranks must be the product ranks), writes
+ *   p_bar_k(c, j, e) = sum_{m,a,b} K_k(a, m+h, b) c_bar_k(a rp0 + c, j+m, b rp1 + e)
+ *   k_bar_k(a, m+h, b) = sum_{c,i,e} c_bar_k(a rp0 + c, i, b rp1 + e) P_k(c, i-m, e)
+ * and copies c_bar's log_scale into both.
+ *
+ * tt_hadamard_adjoint: for H = A o B (Sec. 4.1 'times': H_k(a rb0 + c, i,
+ * b rb1 + e) = A_k(a,i,b) B_k(c,i,e)), A in FP64 (the likelihood of
+ * tt_update), given h_bar writes
+ *   a_bar_k(a,i,b) = sum_{c,e} h_bar_k(a rb0 + c, i, b rb1 + e) B_k(c,i,e)
+ *   b_bar_k(c,i,e) = sum_{a,b} h_bar_k(a rb0 + c, i, b rb1 + e) A_k(a,i,b)
+ * (either output may be null) and copies h_bar's log_scale into both.
+ *
+ * tt_normalize_adjoint: the normalisation of tt_normalize_moments (Alg. 2
+ * step 4, the normaliser of eq. pmf_filtrace_b) keeps the cores of X and
+ * sets log_scale(P) = -log(S delta), S = sum of the stored entries of X,
+ * with log-mass log m = log_scale(X) + log(S delta).  Given p_bar (its
+ * log_scale = the derivative with respect to log_scale(P)) and the
+ * derivative mbar of log m (log_mass_bar_dev[b], nullable: 0), writes
+ *   x_bar cores = p_bar cores + (mbar - p_bar.log_scale) / S * dS/dX,
+ *   x_bar.log_scale = mbar.
+ * --------------------------------------------------------------------- */
+size_t tt_adjoint_workspace(int32_t batch, int32_t d, int32_t rank_cap);
+tt_status tt_predict_adjoint(int32_t batch, const tt_train* kernels, const tt_train* p_in, const tt_train* c_bar,
+                             const tt_train* p_bar, const tt_train* k_bar, void* ws, size_t ws_bytes,
+                             void* stream);
+tt_status tt_hadamard_adjoint(int32_t batch, const tt_train* a, const tt_train* b, const tt_train* h_bar,
+                              const tt_train* a_bar, const tt_train* b_bar, void* ws, size_t ws_bytes,
+                              void* stream);
+tt_status tt_normalize_adjoint(int32_t batch, const tt_train* x, const tt_train* p_bar,
+                               const double* log_mass_bar_dev, const tt_train* x_bar, void* ws, size_t ws_bytes,
+                               void* stream);
+
+/* ---------------------------------------------------------------------
  * tt_filter_run -- the whole recursion for a batch of independent filters
  * (Alg. 2 loop order with the convolution prediction; step 0 is an update
  * only; steps k >= 1 predict, round, normalise, update, round, normalise).

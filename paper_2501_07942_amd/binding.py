@@ -77,6 +77,10 @@ def _load():
         "tt_filter_graph_create": (I, [I, P, P, I, P, I, I, I, I, I, P, P, P, P, P, P, P, P, P, P, P, S, P,
                                        C.POINTER(C.c_void_p)]),
         "tt_filter_graph_launch": (I, [P, P]),
+        "tt_adjoint_workspace": (S, [I, I, I]),
+        "tt_predict_adjoint": (I, [I, P, P, P, P, P, P, S, P]),
+        "tt_hadamard_adjoint": (I, [I, P, P, P, P, P, P, S, P]),
+        "tt_normalize_adjoint": (I, [I, P, P, P, P, P, S, P]),
         "tt_autotune_prediction": (I, [I, P, P, I, P, I, I, I, P, P, P, P, P, S, P, I, I, C.POINTER(C.c_int32),
                                        C.POINTER(C.c_float)]),
         "tt_filter_graph_destroy": (None, [P]),
@@ -94,7 +98,8 @@ EXPORTED = ("tt_train_elems", "tt_last_error", "tt_version", "tt_kernel_build_wo
             "tt_update", "tt_round_workspace", "tt_round", "tt_normalize_moments_workspace",
             "tt_normalize_moments", "tt_filter_run_workspace", "tt_filter_run", "tt_profile_begin",
             "tt_profile_end", "tt_set_predict_mode", "tt_get_predict_mode", "tt_filter_graph_create",
-            "tt_filter_graph_launch", "tt_filter_graph_destroy", "tt_autotune_prediction")
+            "tt_filter_graph_launch", "tt_filter_graph_destroy", "tt_autotune_prediction",
+            "tt_adjoint_workspace", "tt_predict_adjoint", "tt_hadamard_adjoint", "tt_normalize_adjoint")
 
 PREDICT_DIRECT, PREDICT_FFT, PREDICT_UNFUSED, PREDICT_DIRECT_VALU = 0, 1, 2, 3
 
@@ -300,6 +305,44 @@ def tt_normalize_moments(grids: Sequence[Grid], tts: Sequence[DeviceTT], log_mas
     _check(LIB.tt_normalize_moments(B, g, a, log_mass.data_ptr(), mean.data_ptr() if mean is not None else None,
                                     cov.data_ptr() if cov is not None else None, ws.data_ptr(), ws.numel(),
                                     _stream()), "tt_normalize_moments")
+
+
+def _adj_ws(tts):
+    B = len(tts)
+    d = tts[0].d
+    rcap = max(max(t.cap) for t in tts)
+    return _ws(LIB.tt_adjoint_workspace(B, d, rcap))
+
+
+def tt_predict_adjoint(kernels: Sequence[DeviceTT], p_in: Sequence[DeviceTT], c_bar: Sequence[DeviceTT],
+                       p_bar: Sequence[DeviceTT], k_bar: Sequence[DeviceTT]):
+    B = len(p_in)
+    ws = _adj_ws(list(p_in) + list(c_bar) + list(kernels))
+    _check(LIB.tt_predict_adjoint(B, _arr([k.struct() for k in kernels]), _arr([p.struct() for p in p_in]),
+                                  _arr([c.struct() for c in c_bar]), _arr([p.struct() for p in p_bar]),
+                                  _arr([k.struct() for k in k_bar]), ws.data_ptr(), ws.numel(), _stream()),
+           "tt_predict_adjoint")
+
+
+def tt_hadamard_adjoint(a: Sequence[DeviceTT], b: Sequence[DeviceTT], h_bar: Sequence[DeviceTT],
+                        a_bar: Optional[Sequence[DeviceTT]], b_bar: Optional[Sequence[DeviceTT]]):
+    B = len(b)
+    ws = _adj_ws(list(a) + list(b) + list(h_bar))
+    _check(LIB.tt_hadamard_adjoint(B, _arr([t.struct() for t in a]), _arr([t.struct() for t in b]),
+                                   _arr([t.struct() for t in h_bar]),
+                                   _arr([t.struct() for t in a_bar]) if a_bar else None,
+                                   _arr([t.struct() for t in b_bar]) if b_bar else None,
+                                   ws.data_ptr(), ws.numel(), _stream()), "tt_hadamard_adjoint")
+
+
+def tt_normalize_adjoint(x: Sequence[DeviceTT], p_bar: Sequence[DeviceTT], log_mass_bar, x_bar: Sequence[DeviceTT]):
+    """log_mass_bar: torch float64 device tensor [B] or None."""
+    B = len(x)
+    ws = _adj_ws(list(x))
+    _check(LIB.tt_normalize_adjoint(B, _arr([t.struct() for t in x]), _arr([t.struct() for t in p_bar]),
+                                    log_mass_bar.data_ptr() if log_mass_bar is not None else None,
+                                    _arr([t.struct() for t in x_bar]), ws.data_ptr(), ws.numel(), _stream()),
+           "tt_normalize_adjoint")
 
 
 def workspace_bytes(specs: Sequence[FilterSpec], kernels: Sequence[DeviceTT], precision: int) -> int:

@@ -12,6 +12,7 @@
 #include "linalg.h"
 #include "ttops.h"
 #include "fft.h"
+#include "adjoint.h"
 #include "pred_mfma.h"
 
 namespace ttg {
@@ -1704,6 +1705,234 @@ tt_status tt_predict(int32_t batch, const tt_train* kernels, const tt_train* p_i
   TT_TRY(upload(dx, vx, st));
   if (dtype == TT_F64) return launch_conv<double>(batch, p_in[0].d, r0cap, smem, dk, dp, dx, st);
   return launch_conv<float>(batch, p_in[0].d, r0cap, smem, dk, dp, dx, st);
+}
+
+// ---------------------------------------------------------------------------
+// adjoints of the linear steps
+// ---------------------------------------------------------------------------
+static tt_status check_like(const tt_train& a, const tt_train& b, const char* what) {
+  if (a.d != b.d) {
+    set_error("%s: d differs", what);
+    return TT_ERR_SHAPE;
+  }
+  for (int k = 0; k < a.d; ++k)
+    if (a.n[k] != b.n[k]) {
+      set_error("%s: mode sizes differ", what);
+      return TT_ERR_SHAPE;
+    }
+  return TT_OK;
+}
+
+size_t tt_adjoint_workspace(int32_t batch, int32_t d, int32_t rcap) {
+  if (batch < 1 || d < 1 || rcap < 1) return 0;
+  return (size_t)5 * batch * sizeof(DevTT) + (size_t)batch * (2 * (d + 1) * rcap + 1) * sizeof(double) + 2048;
+}
+
+tt_status tt_predict_adjoint(int32_t batch, const tt_train* kernels, const tt_train* p_in, const tt_train* c_bar,
+                             const tt_train* p_bar, const tt_train* k_bar, void* ws, size_t ws_bytes,
+                             void* stream) {
+  if (batch < 1 || !kernels || !p_in || !c_bar || !p_bar || !k_bar || !ws) {
+    set_error("tt_predict_adjoint: bad arguments");
+    return TT_ERR_ARG;
+  }
+  const int dtype = p_in[0].dtype, d = p_in[0].d;
+  std::vector<DevTT> vk(batch), vp(batch), vc(batch), vpb(batch), vkb(batch);
+  int r0cap = 1, rkcap = 1, tapmax = 1;
+  for (int b = 0; b < batch; ++b) {
+    TT_TRY(check_train(&kernels[b], "kernel", dtype));
+    TT_TRY(check_train(&p_in[b], "p_in", dtype));
+    TT_TRY(check_train(&c_bar[b], "c_bar", dtype));
+    TT_TRY(check_train(&p_bar[b], "p_bar", dtype));
+    TT_TRY(check_train(&k_bar[b], "k_bar", dtype));
+    if (p_in[b].d != d || kernels[b].d != d) {
+      set_error("tt_predict_adjoint: d differs");
+      return TT_ERR_SHAPE;
+    }
+    TT_TRY(check_like(p_in[b], c_bar[b], "tt_predict_adjoint c_bar"));
+    TT_TRY(check_like(p_in[b], p_bar[b], "tt_predict_adjoint p_bar"));
+    TT_TRY(check_like(kernels[b], k_bar[b], "tt_predict_adjoint k_bar"));
+    for (int k = 0; k < d; ++k) {
+      if ((kernels[b].n[k] % 2) != 1) {
+        set_error("tt_predict_adjoint: even kernel length");
+        return TT_ERR_SHAPE;
+      }
+      r0cap = std::max(r0cap, p_in[b].cap[k]);
+      rkcap = std::max(rkcap, kernels[b].cap[k] * kernels[b].n[k] * kernels[b].cap[k + 1]);
+      tapmax = std::max(tapmax, kernels[b].n[k]);
+    }
+    vk[b] = make_dev(kernels[b]);
+    vp[b] = make_dev(p_in[b]);
+    vc[b] = make_dev(c_bar[b]);
+    vpb[b] = make_dev(p_bar[b]);
+    vkb[b] = make_dev(k_bar[b]);
+  }
+  Arena ar(ws, ws_bytes);
+  DevTT* dk = ar.take<DevTT>(batch);
+  DevTT* dp = ar.take<DevTT>(batch);
+  DevTT* dc = ar.take<DevTT>(batch);
+  DevTT* dpb = ar.take<DevTT>(batch);
+  DevTT* dkb = ar.take<DevTT>(batch);
+  if (!ar.fits()) {
+    set_error("tt_predict_adjoint: workspace too small");
+    return TT_ERR_WORKSPACE;
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  TT_TRY(upload(dk, vk, st));
+  TT_TRY(upload(dp, vp, st));
+  TT_TRY(upload(dc, vc, st));
+  TT_TRY(upload(dpb, vpb, st));
+  TT_TRY(upload(dkb, vkb, st));
+  hipLaunchKernelGGL(adj_init_kernel, dim3(cdiv(batch, 64)), dim3(64), 0, st, dp, dpb, dc, dk, dp, batch);
+  TTG_LAUNCH_CHECK("adj_init_kernel");
+  hipLaunchKernelGGL(adj_init_kernel, dim3(cdiv(batch, 64)), dim3(64), 0, st, dk, dkb, dc, dk, dp, batch);
+  TTG_LAUNCH_CHECK("adj_init_kernel");
+  int pel = 1;
+  for (int b = 0; b < batch; ++b)
+    for (int k = 0; k < d; ++k) pel = std::max(pel, p_in[b].cap[k] * p_in[b].n[k] * p_in[b].cap[k + 1]);
+  if (dtype == TT_F64) {
+    hipLaunchKernelGGL((pred_adj_p_kernel<double>), dim3(stride_grid(cdiv(pel, 256), batch), d, batch), dim3(256), 0,
+                       st, dk, dp, dc, dpb);
+    TTG_LAUNCH_CHECK("pred_adj_p_kernel");
+    hipLaunchKernelGGL((pred_adj_k_kernel<double>), dim3(std::min(rkcap, 65535), d, batch), dim3(256), 0, st, dk, dp,
+                       dc, dkb);
+    TTG_LAUNCH_CHECK("pred_adj_k_kernel");
+  } else {
+    hipLaunchKernelGGL((pred_adj_p_kernel<float>), dim3(stride_grid(cdiv(pel, 256), batch), d, batch), dim3(256), 0,
+                       st, dk, dp, dc, dpb);
+    TTG_LAUNCH_CHECK("pred_adj_p_kernel");
+    hipLaunchKernelGGL((pred_adj_k_kernel<float>), dim3(std::min(rkcap, 65535), d, batch), dim3(256), 0, st, dk, dp,
+                       dc, dkb);
+    TTG_LAUNCH_CHECK("pred_adj_k_kernel");
+  }
+  (void)r0cap;
+  (void)tapmax;
+  return TT_OK;
+}
+
+tt_status tt_hadamard_adjoint(int32_t batch, const tt_train* a, const tt_train* b, const tt_train* h_bar,
+                              const tt_train* a_bar, const tt_train* b_bar, void* ws, size_t ws_bytes,
+                              void* stream) {
+  if (batch < 1 || !a || !b || !h_bar || (!a_bar && !b_bar) || !ws) {
+    set_error("tt_hadamard_adjoint: bad arguments");
+    return TT_ERR_ARG;
+  }
+  const int dtype = b[0].dtype, d = b[0].d;
+  std::vector<DevTT> va(batch), vb(batch), vh(batch), vab(batch), vbb(batch);
+  int pel = 1;
+  for (int f = 0; f < batch; ++f) {
+    TT_TRY(check_train(&a[f], "a", TT_F64));
+    TT_TRY(check_train(&b[f], "b", dtype));
+    TT_TRY(check_train(&h_bar[f], "h_bar", dtype));
+    if (a_bar) TT_TRY(check_train(&a_bar[f], "a_bar", TT_F64));
+    if (b_bar) TT_TRY(check_train(&b_bar[f], "b_bar", dtype));
+    if (b[f].d != d) {
+      set_error("tt_hadamard_adjoint: d differs");
+      return TT_ERR_SHAPE;
+    }
+    TT_TRY(check_like(b[f], a[f], "tt_hadamard_adjoint a"));
+    TT_TRY(check_like(b[f], h_bar[f], "tt_hadamard_adjoint h_bar"));
+    if (a_bar) TT_TRY(check_like(b[f], a_bar[f], "tt_hadamard_adjoint a_bar"));
+    if (b_bar) TT_TRY(check_like(b[f], b_bar[f], "tt_hadamard_adjoint b_bar"));
+    for (int k = 0; k < d; ++k)
+      pel = std::max(pel, std::max(a[f].cap[k] * a[f].n[k] * a[f].cap[k + 1], b[f].cap[k] * b[f].n[k] * b[f].cap[k + 1]));
+    va[f] = make_dev(a[f]);
+    vb[f] = make_dev(b[f]);
+    vh[f] = make_dev(h_bar[f]);
+    if (a_bar) vab[f] = make_dev(a_bar[f]);
+    if (b_bar) vbb[f] = make_dev(b_bar[f]);
+  }
+  Arena ar(ws, ws_bytes);
+  DevTT* da = ar.take<DevTT>(batch);
+  DevTT* db = ar.take<DevTT>(batch);
+  DevTT* dh = ar.take<DevTT>(batch);
+  DevTT* dab = ar.take<DevTT>(batch);
+  DevTT* dbb = ar.take<DevTT>(batch);
+  if (!ar.fits()) {
+    set_error("tt_hadamard_adjoint: workspace too small");
+    return TT_ERR_WORKSPACE;
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  TT_TRY(upload(da, va, st));
+  TT_TRY(upload(db, vb, st));
+  TT_TRY(upload(dh, vh, st));
+  if (a_bar) {
+    TT_TRY(upload(dab, vab, st));
+    hipLaunchKernelGGL(adj_init_kernel, dim3(cdiv(batch, 64)), dim3(64), 0, st, da, dab, dh, da, db, batch);
+    TTG_LAUNCH_CHECK("adj_init_kernel");
+  }
+  if (b_bar) {
+    TT_TRY(upload(dbb, vbb, st));
+    hipLaunchKernelGGL(adj_init_kernel, dim3(cdiv(batch, 64)), dim3(64), 0, st, db, dbb, dh, da, db, batch);
+    TTG_LAUNCH_CHECK("adj_init_kernel");
+  }
+  const dim3 grid(stride_grid(cdiv(pel, 256), batch), d, batch);
+  if (dtype == TT_F64)
+    hipLaunchKernelGGL((hadamard_adj_kernel<double>), grid, dim3(256), 0, st, da, db, dh, a_bar ? dab : nullptr,
+                       b_bar ? dbb : nullptr);
+  else
+    hipLaunchKernelGGL((hadamard_adj_kernel<float>), grid, dim3(256), 0, st, da, db, dh, a_bar ? dab : nullptr,
+                       b_bar ? dbb : nullptr);
+  TTG_LAUNCH_CHECK("hadamard_adj_kernel");
+  return TT_OK;
+}
+
+tt_status tt_normalize_adjoint(int32_t batch, const tt_train* x, const tt_train* p_bar,
+                               const double* log_mass_bar_dev, const tt_train* x_bar, void* ws, size_t ws_bytes,
+                               void* stream) {
+  if (batch < 1 || !x || !p_bar || !x_bar || !ws) {
+    set_error("tt_normalize_adjoint: bad arguments");
+    return TT_ERR_ARG;
+  }
+  const int dtype = x[0].dtype, d = x[0].d;
+  std::vector<DevTT> vx(batch), vpb(batch), vxb(batch);
+  int rcap = 1, pel = 1;
+  for (int f = 0; f < batch; ++f) {
+    TT_TRY(check_train(&x[f], "x", dtype));
+    TT_TRY(check_train(&p_bar[f], "p_bar", dtype));
+    TT_TRY(check_train(&x_bar[f], "x_bar", dtype));
+    if (x[f].d != d) {
+      set_error("tt_normalize_adjoint: d differs");
+      return TT_ERR_SHAPE;
+    }
+    TT_TRY(check_like(x[f], p_bar[f], "tt_normalize_adjoint p_bar"));
+    TT_TRY(check_like(x[f], x_bar[f], "tt_normalize_adjoint x_bar"));
+    for (int k = 0; k <= d; ++k) rcap = std::max(rcap, x[f].cap[k]);
+    for (int k = 0; k < d; ++k) pel = std::max(pel, x[f].cap[k] * x[f].n[k] * x[f].cap[k + 1]);
+    vx[f] = make_dev(x[f]);
+    vpb[f] = make_dev(p_bar[f]);
+    vxb[f] = make_dev(x_bar[f]);
+  }
+  Arena ar(ws, ws_bytes);
+  DevTT* dx = ar.take<DevTT>(batch);
+  DevTT* dpb = ar.take<DevTT>(batch);
+  DevTT* dxb = ar.take<DevTT>(batch);
+  double* env = ar.take<double>((size_t)batch * 2 * (d + 1) * rcap);
+  double* ssum = ar.take<double>(batch);
+  if (!ar.fits()) {
+    set_error("tt_normalize_adjoint: workspace too small (%zu < %zu)", ws_bytes, ar.used);
+    return TT_ERR_WORKSPACE;
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  TT_TRY(upload(dx, vx, st));
+  TT_TRY(upload(dpb, vpb, st));
+  TT_TRY(upload(dxb, vxb, st));
+  hipLaunchKernelGGL(normalize_adj_init_kernel, dim3(cdiv(batch, 64)), dim3(64), 0, st, dx, dpb, dxb,
+                     log_mass_bar_dev, batch);
+  TTG_LAUNCH_CHECK("normalize_adj_init_kernel");
+  const dim3 grid(stride_grid(cdiv(pel, 256), batch), d, batch);
+  if (dtype == TT_F64) {
+    hipLaunchKernelGGL((sum_env_kernel<double>), dim3(batch), dim3(256), 0, st, dx, env, rcap, ssum);
+    TTG_LAUNCH_CHECK("sum_env_kernel");
+    hipLaunchKernelGGL((normalize_adj_kernel<double>), grid, dim3(256), 0, st, dx, dpb, dxb, log_mass_bar_dev, env,
+                       rcap, ssum);
+  } else {
+    hipLaunchKernelGGL((sum_env_kernel<float>), dim3(batch), dim3(256), 0, st, dx, env, rcap, ssum);
+    TTG_LAUNCH_CHECK("sum_env_kernel");
+    hipLaunchKernelGGL((normalize_adj_kernel<float>), grid, dim3(256), 0, st, dx, dpb, dxb, log_mass_bar_dev, env,
+                       rcap, ssum);
+  }
+  TTG_LAUNCH_CHECK("normalize_adj_kernel");
+  return TT_OK;
 }
 
 // ---------------------------------------------------------------------------

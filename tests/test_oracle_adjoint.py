@@ -15,6 +15,10 @@ from oracle import model as mdl
 from oracle import tt as ttm
 from paper_2501_07942_amd import workload as wl
 
+import os, sys  # noqa: E401
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+from adjoint_helpers import full_vjp  # noqa: E402
+
 
 def rand_tt(rng, n, r, decay=1.0):
     rk = [1] + list(r) + [1]
@@ -25,24 +29,6 @@ def rand_tt(rng, n, r, decay=1.0):
         g *= decay ** np.arange(rk[k + 1])[None, None, :]
         cores.append(g)
     return cores
-
-
-def full_vjp(cores, t):
-    """Core adjoints of f = <full(cores), t> by brute-force contraction."""
-    d = len(cores)
-    out = []
-    for k in range(d):
-        left = np.ones((1, 1))
-        for j in range(k):
-            left = np.einsum("xa,aib->xib", left, cores[j]).reshape(-1, cores[j].shape[2])
-        right = np.ones((1, 1))
-        for j in range(d - 1, k, -1):
-            right = np.einsum("aib,bx->aix", cores[j], right).reshape(cores[j].shape[0], -1)
-        nl = left.shape[0]
-        nr = right.shape[1]
-        tk = t.reshape(nl, cores[k].shape[1], nr)
-        out.append(np.einsum("la,lir,br->aib", left, tk, right))
-    return out
 
 
 def inner(a, b):
