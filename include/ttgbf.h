@@ -237,6 +237,32 @@ size_t tt_normalize_moments_workspace(int32_t batch, const tt_train* t);
  *   x_bar cores = p_bar cores + (mbar - p_bar.log_scale) / S * dS/dX,
  *   x_bar.log_scale = mbar.
  * --------------------------------------------------------------------- */
+/* ---------------------------------------------------------------------
+ * tt_round_adjoint: adjoint of the rounding of Sec. 4.1 'round' (the
+ * right-to-left orthogonalisation and the left-to-right truncated SVDs of
+ * tt_round) at the ranks it produced, FP64.
+ *
+ * a: the input train of tt_round; y: its output (the output's cores define
+ * the basis in which y_bar is expressed); y_bar: adjoint of y (same
+ * capacities and ranks); a_bar: written with a's ranks, the derivative with
+ * respect to a's stored cores, log_scale = y_bar's log_scale.  The rounding
+ * is differentiated as a function of the input cores with every output rank
+ * held fixed: Gram matrices of the right parts, leading eigenvectors of the
+ * projected unfoldings (their adjoint couples kept and discarded singular
+ * directions, whose singular values come from a Jacobi SVD), then both
+ * sweeps backwards.  Kept singular values below 6e-6 of the largest at a
+ * bond are left out of the eigenvector adjoint (rounding noise there
+ * exceeds their signal).  The call reads the ranks to the host once and is
+ * synchronous (it returns after the work is done).  Workspace:
+ * tt_round_adjoint_workspace(batch, a, y) bytes (from the capacities).
+ * Errors: TT_ERR_ARG (null, non-FP64), TT_ERR_SHAPE (modes, capacities or
+ * ranks inconsistent, y_bar ranks differ from y, a rank above 1024),
+ * TT_ERR_WORKSPACE, TT_ERR_HIP.
+ * --------------------------------------------------------------------- */
+size_t tt_round_adjoint_workspace(int32_t batch, const tt_train* a, const tt_train* y);
+tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, const tt_train* y_bar,
+                           const tt_train* a_bar, void* ws, size_t ws_bytes, void* stream);
+
 size_t tt_adjoint_workspace(int32_t batch, int32_t d, int32_t rank_cap);
 tt_status tt_predict_adjoint(int32_t batch, const tt_train* kernels, const tt_train* p_in, const tt_train* c_bar,
                              const tt_train* p_bar, const tt_train* k_bar, void* ws, size_t ws_bytes,

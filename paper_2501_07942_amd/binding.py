@@ -78,6 +78,8 @@ def _load():
                                        C.POINTER(C.c_void_p)]),
         "tt_filter_graph_launch": (I, [P, P]),
         "tt_adjoint_workspace": (S, [I, I, I]),
+        "tt_round_adjoint_workspace": (S, [I, P, P]),
+        "tt_round_adjoint": (I, [I, P, P, P, P, P, S, P]),
         "tt_predict_adjoint": (I, [I, P, P, P, P, P, P, S, P]),
         "tt_hadamard_adjoint": (I, [I, P, P, P, P, P, P, S, P]),
         "tt_normalize_adjoint": (I, [I, P, P, P, P, P, S, P]),
@@ -99,7 +101,8 @@ EXPORTED = ("tt_train_elems", "tt_last_error", "tt_version", "tt_kernel_build_wo
             "tt_normalize_moments", "tt_filter_run_workspace", "tt_filter_run", "tt_profile_begin",
             "tt_profile_end", "tt_set_predict_mode", "tt_get_predict_mode", "tt_filter_graph_create",
             "tt_filter_graph_launch", "tt_filter_graph_destroy", "tt_autotune_prediction",
-            "tt_adjoint_workspace", "tt_predict_adjoint", "tt_hadamard_adjoint", "tt_normalize_adjoint")
+            "tt_adjoint_workspace", "tt_predict_adjoint", "tt_hadamard_adjoint", "tt_normalize_adjoint",
+            "tt_round_adjoint_workspace", "tt_round_adjoint")
 
 PREDICT_DIRECT, PREDICT_FFT, PREDICT_UNFUSED, PREDICT_DIRECT_VALU = 0, 1, 2, 3
 
@@ -343,6 +346,18 @@ def tt_normalize_adjoint(x: Sequence[DeviceTT], p_bar: Sequence[DeviceTT], log_m
                                     log_mass_bar.data_ptr() if log_mass_bar is not None else None,
                                     _arr([t.struct() for t in x_bar]), ws.data_ptr(), ws.numel(), _stream()),
            "tt_normalize_adjoint")
+
+
+def tt_round_adjoint(a: Sequence[DeviceTT], y: Sequence[DeviceTT], y_bar: Sequence[DeviceTT],
+                     a_bar: Sequence[DeviceTT]):
+    B = len(a)
+    aa, yy = _arr([t.struct() for t in a]), _arr([t.struct() for t in y])
+    nbytes = LIB.tt_round_adjoint_workspace(B, aa, yy)
+    if nbytes == 0:
+        _check(ERR_ARG, "tt_round_adjoint_workspace")
+    ws = _ws(nbytes)
+    _check(LIB.tt_round_adjoint(B, aa, yy, _arr([t.struct() for t in y_bar]), _arr([t.struct() for t in a_bar]),
+                                ws.data_ptr(), ws.numel(), _stream()), "tt_round_adjoint")
 
 
 def workspace_bytes(specs: Sequence[FilterSpec], kernels: Sequence[DeviceTT], precision: int) -> int:

@@ -13,6 +13,7 @@
 #include "ttops.h"
 #include "fft.h"
 #include "adjoint.h"
+#include "round_adj.h"
 #include "pred_mfma.h"
 
 namespace ttg {
@@ -1239,6 +1240,611 @@ tt_status tt_round(int32_t batch, const tt_train* t_in, const tt_train* t_out, d
   TT_TRY(upload(rb.drs, vrs, st));
   if (sh.f64) return round_launch<double, AccDD>(sh, rb, eps, max_rank, st);
   return round_launch<float, AccD>(sh, rb, eps, max_rank, st);
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// adjoint of the rounding (FP64): host orchestration of the phases described
+// in round_adj.h; every shape is known on the host after one read of the
+// ranks, so every product is a job of a grouped GEMM launch
+// ===========================================================================
+namespace ttg {
+
+struct RadjCore {  // per filter and core k (0-based)
+  double *G, *T, *W, *U, *c, *N, *lfac, *lwork, *M, *jw, *sig, *usv, *Ud, *Fm, *Gbar;
+  int* piv;
+  int* prank;
+};
+
+struct RadjFilter {
+  int d, n[TT_MAXD], Ra[TT_MAXD + 1], ry[TT_MAXD + 1];
+  RadjCore c[TT_MAXD];
+  double *L, *kappa, *Lbar, *Wb0, *Wb1, *Nbar, *Ubar, *P1, *P2, *WG, *XtN, *XtNG, *Gs, *T2, *Tg;
+};
+
+// lays out the buffers of every filter in the arena (sizes from ranks Ra, ry)
+static void radj_layout(Arena& ar, RadjFilter& F) {
+  const int d = F.d;
+  long long tmax = 1, pmax = 1, rmax = 1, Rmax = 1, prmax = 1, pRmax = 1, rRmax = 1;
+  for (int k = 0; k < d; ++k) {
+    const long long Rk = F.Ra[k], Rk1 = F.Ra[k + 1], rk = F.ry[k], rk1 = F.ry[k + 1], n = F.n[k];
+    RadjCore& C = F.c[k];
+    C.G = ar.take<double>(Rk1 * Rk1);
+    C.Gbar = ar.take<double>(Rk1 * Rk1);
+    C.W = ar.take<double>(std::max(1LL, rk * Rk));
+    tmax = std::max(tmax, Rk * n * Rk1);
+    rmax = std::max(rmax, std::max(rk, rk1));
+    Rmax = std::max(Rmax, std::max(Rk, Rk1));
+    if (k < d - 1) {
+      const long long p = rk * n;
+      pmax = std::max(pmax, p);
+      prmax = std::max(prmax, p * rk1);
+      pRmax = std::max(pRmax, p * Rk1);
+      rRmax = std::max(rRmax, std::max(rk * Rk, rk1 * Rk1));
+      const long long nd = std::max(0LL, Rk1 - rk1);
+      C.U = ar.take<double>(p * rk1);
+      C.c = ar.take<double>(1);
+      C.N = ar.take<double>(p * Rk1);
+      C.lfac = ar.take<double>(Rk1 * Rk1);
+      C.lwork = ar.take<double>(Rk1 * Rk1);
+      C.piv = ar.take<int>(Rk1);
+      C.prank = ar.take<int>(1);
+      C.M = ar.take<double>(p * Rk1);
+      C.jw = ar.take<double>(p * Rk1);
+      C.sig = ar.take<double>(Rk1);
+      C.usv = ar.take<double>(p * Rk1);
+      C.Ud = ar.take<double>(std::max(1LL, p * nd));
+      C.Fm = ar.take<double>(nd * rk1 + rk1);
+    }
+  }
+  const int rl = F.ry[d - 1], nl = F.n[d - 1];
+  F.L = ar.take<double>((long long)rl * nl);
+  F.Lbar = ar.take<double>((long long)rl * nl);
+  F.kappa = ar.take<double>(1);
+  F.Wb0 = ar.take<double>(rRmax);
+  F.Wb1 = ar.take<double>(rRmax);
+  F.Nbar = ar.take<double>(pRmax);
+  F.Ubar = ar.take<double>(prmax);
+  F.P1 = ar.take<double>(rmax * rmax);
+  F.P2 = ar.take<double>(Rmax * rmax);
+  F.WG = ar.take<double>(rmax * Rmax);
+  F.XtN = ar.take<double>(rmax * Rmax);
+  F.XtNG = ar.take<double>(rmax * Rmax);
+  F.Gs = ar.take<double>(Rmax * Rmax);
+  F.T2 = ar.take<double>(tmax);
+  F.Tg = ar.take<double>(tmax);
+}
+
+struct RadjRun {
+  hipStream_t st;
+  GJob* dg;
+  EJob* de;
+  PcholArgs* dp;
+  JacobiArgs* dj;
+  int jcap;
+  std::vector<GJob> g;
+  std::vector<EJob> e;
+  // device regions a job may touch (workspace, the trains' core buffers):
+  // every job's extent is checked on the host before anything is launched
+  std::vector<std::pair<const double*, long long>> regions;
+  bool inside(const void* p, long long last) const {
+    if (last < 0) return true;
+    const double* q = reinterpret_cast<const double*>(p);
+    for (const auto& r : regions)
+      if (q >= r.first && q + last < r.first + r.second) return true;
+    return false;
+  }
+  tt_status check(bool ok, const char* what) const {
+    if (ok) return TT_OK;
+    set_error("tt_round_adjoint: internal extent check failed (%s)", what);
+    return TT_ERR_ARG;
+  }
+  tt_status gemm() {  // launch the queued products
+    if (g.empty()) return TT_OK;
+    if ((int)g.size() > jcap) {
+      set_error("tt_round_adjoint: job table overflow");
+      return TT_ERR_ARG;
+    }
+    for (const auto& j : g) {
+      TT_TRY(check(j.K == 0 || inside(j.a, (long long)(j.M - 1) * j.sam + (long long)(j.K - 1) * j.sak), "gemm a"));
+      TT_TRY(check(j.K == 0 || inside(j.b, (long long)(j.K - 1) * j.sbk + (long long)(j.N - 1) * j.sbn), "gemm b"));
+      TT_TRY(check(inside(j.c, (long long)(j.M - 1) * j.scm + (long long)(j.N - 1) * j.scn), "gemm c"));
+    }
+    int tiles = 0;
+    for (auto& j : g) {
+      j.tn = std::max(1, (j.N + 63) / 64);
+      j.tile0 = tiles;
+      tiles += std::max(1, (j.M + 63) / 64) * j.tn;
+    }
+    TT_TRY(upload(dg, g, st));
+    hipLaunchKernelGGL(gjob_gemm_kernel, dim3(tiles), dim3(256), 0, st, dg, (int)g.size());
+    TTG_LAUNCH_CHECK("gjob_gemm_kernel");
+    g.clear();
+    return TT_OK;
+  }
+  tt_status elem() {
+    if (e.empty()) return TT_OK;
+    if ((int)e.size() > jcap) {
+      set_error("tt_round_adjoint: job table overflow");
+      return TT_ERR_ARG;
+    }
+    for (const auto& j : e) {
+      const long long n = j.op == EJ_SYM ? (long long)j.r * j.r : j.cnt;
+      TT_TRY(check(inside(j.out, n - 1), "elementwise out"));
+      if (j.op == EJ_SCALE || j.op == EJ_SYM) TT_TRY(check(inside(j.x, n - 1), "elementwise x"));
+      if (j.op == EJ_SCALE) TT_TRY(check(inside(j.s, 0), "elementwise s"));
+    }
+    long long mx = 1;
+    for (auto& j : e) mx = std::max(mx, j.cnt);
+    TT_TRY(upload(de, e, st));
+    hipLaunchKernelGGL(ejob_kernel, dim3(std::min(cdiv(mx, 256), 1024), (int)e.size()), dim3(256), 0, st, de);
+    TTG_LAUNCH_CHECK("ejob_kernel");
+    e.clear();
+    return TT_OK;
+  }
+  void mm(int M, int N, int K, const double* a, long long sam, long long sak, const double* b, long long sbk,
+          long long sbn, double* c, long long scm, double alpha, double beta) {
+    if (M <= 0 || N <= 0) return;
+    GJob j;
+    memset(&j, 0, sizeof(j));
+    j.M = M;
+    j.N = N;
+    j.K = K;
+    j.a = a;
+    j.sam = sam;
+    j.sak = sak;
+    j.b = b;
+    j.sbk = sbk;
+    j.sbn = sbn;
+    j.c = c;
+    j.scm = scm;
+    j.scn = 1;
+    j.alpha = alpha;
+    j.beta = beta;
+    g.push_back(j);
+  }
+  void ej(int op, long long cnt, const double* x, const double* y, double* out, double* out2, const double* sc,
+          int r = 0, int p = 0, int R = 0, int ld = 0) {
+    EJob j;
+    memset(&j, 0, sizeof(j));
+    j.op = op;
+    j.cnt = cnt;
+    j.x = x;
+    j.y = y;
+    j.out = out;
+    j.out2 = out2;
+    j.s = sc;
+    j.r = r;
+    j.p = p;
+    j.R = R;
+    j.ld = ld;
+    e.push_back(j);
+  }
+};
+
+static long long radj_bytes(const RadjFilter& proto) {
+  RadjFilter F = proto;
+  Arena ar(nullptr, 0);
+  radj_layout(ar, F);
+  return (long long)ar.used;
+}
+
+}  // namespace ttg
+
+extern "C" {
+
+size_t tt_round_adjoint_workspace(int32_t batch, const tt_train* a, const tt_train* y) {
+  if (batch < 1 || !a || !y) return 0;
+  const int dd = a[0].d;
+  size_t total = (size_t)batch * (3 * dd + 8) * (sizeof(GJob) + sizeof(EJob) + sizeof(PcholArgs) + sizeof(JacobiArgs)) +
+                 8192;
+  for (int b = 0; b < batch; ++b) {
+    RadjFilter F;
+    memset(&F, 0, sizeof(F));
+    F.d = a[b].d;
+    for (int k = 0; k < F.d; ++k) F.n[k] = a[b].n[k];
+    for (int k = 0; k <= F.d; ++k) {
+      F.Ra[k] = a[b].cap[k];
+      F.ry[k] = y[b].cap[k];
+    }
+    total += (size_t)radj_bytes(F) + 256 * 64;
+  }
+  return total;
+}
+
+tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, const tt_train* y_bar,
+                           const tt_train* a_bar, void* ws, size_t ws_bytes, void* stream) {
+  if (batch < 1 || !a || !y || !y_bar || !a_bar || !ws) {
+    set_error("tt_round_adjoint: bad arguments");
+    return TT_ERR_ARG;
+  }
+  const int d = a[0].d;
+  for (int b = 0; b < batch; ++b) {
+    TT_TRY(check_train(&a[b], "a", TT_F64));
+    TT_TRY(check_train(&y[b], "y", TT_F64));
+    TT_TRY(check_train(&y_bar[b], "y_bar", TT_F64));
+    TT_TRY(check_train(&a_bar[b], "a_bar", TT_F64));
+    if (a[b].d != d || y[b].d != d || y_bar[b].d != d || a_bar[b].d != d) {
+      set_error("tt_round_adjoint: d differs");
+      return TT_ERR_SHAPE;
+    }
+    for (int k = 0; k < d; ++k)
+      if (y[b].n[k] != a[b].n[k] || y_bar[b].n[k] != a[b].n[k] || a_bar[b].n[k] != a[b].n[k]) {
+        set_error("tt_round_adjoint: mode sizes differ");
+        return TT_ERR_SHAPE;
+      }
+    for (int k = 0; k <= d; ++k)
+      if (y_bar[b].cap[k] != y[b].cap[k] || a_bar[b].cap[k] != a[b].cap[k]) {
+        set_error("tt_round_adjoint: adjoint capacities differ from their primals");
+        return TT_ERR_SHAPE;
+      }
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  // the ranks, once, to the host
+  std::vector<int> hr((size_t)batch * 3 * (d + 1));
+  for (int b = 0; b < batch; ++b) {
+    HIP_TRY(hipMemcpyAsync(&hr[(size_t)(3 * b) * (d + 1)], a[b].ranks, sizeof(int) * (d + 1), hipMemcpyDeviceToHost,
+                           st), "ranks");
+    HIP_TRY(hipMemcpyAsync(&hr[(size_t)(3 * b + 1) * (d + 1)], y[b].ranks, sizeof(int) * (d + 1),
+                           hipMemcpyDeviceToHost, st), "ranks");
+    HIP_TRY(hipMemcpyAsync(&hr[(size_t)(3 * b + 2) * (d + 1)], y_bar[b].ranks, sizeof(int) * (d + 1),
+                           hipMemcpyDeviceToHost, st), "ranks");
+  }
+  HIP_TRY(hipStreamSynchronize(st), "ranks sync");
+  std::vector<RadjFilter> F(batch);
+  Arena ar(ws, ws_bytes);
+  RadjRun R;
+  R.st = st;
+  R.jcap = batch * (3 * d + 8);
+  R.dg = ar.take<GJob>(R.jcap);
+  R.de = ar.take<EJob>(R.jcap);
+  R.dp = ar.take<PcholArgs>((size_t)batch * d);
+  R.dj = ar.take<JacobiArgs>((size_t)batch * d);
+  int Rmax = 1;
+  for (int b = 0; b < batch; ++b) {
+    RadjFilter& f = F[b];
+    memset(&f, 0, sizeof(f));
+    f.d = d;
+    for (int k = 0; k < d; ++k) f.n[k] = a[b].n[k];
+    const int* ra = &hr[(size_t)(3 * b) * (d + 1)];
+    const int* ry = &hr[(size_t)(3 * b + 1) * (d + 1)];
+    const int* rb = &hr[(size_t)(3 * b + 2) * (d + 1)];
+    for (int k = 0; k <= d; ++k) {
+      if (ra[k] < 1 || ra[k] > a[b].cap[k] || ry[k] < 1 || ry[k] > y[b].cap[k] || rb[k] != ry[k]) {
+        set_error("tt_round_adjoint: ranks out of range or y_bar ranks differ from y (filter %d)", b);
+        return TT_ERR_SHAPE;
+      }
+      if (k > 0 && k < d && ry[k] > ra[k]) {
+        set_error("tt_round_adjoint: output rank above the input rank (filter %d)", b);
+        return TT_ERR_SHAPE;
+      }
+      f.Ra[k] = ra[k];
+      f.ry[k] = ry[k];
+      Rmax = std::max(Rmax, ra[k]);
+    }
+    radj_layout(ar, f);
+  }
+  if (!ar.fits()) {
+    set_error("tt_round_adjoint: workspace too small (%zu < %zu)", ws_bytes, ar.used);
+    return TT_ERR_WORKSPACE;
+  }
+  R.regions.push_back({reinterpret_cast<const double*>(ws), (long long)(ar.used / sizeof(double))});
+  for (int b = 0; b < batch; ++b)
+    for (const tt_train* t : {&a[b], &y[b], &y_bar[b], &a_bar[b]})
+      R.regions.push_back({reinterpret_cast<const double*>(t->cores), (long long)elems_of(t->d, t->n, t->cap)});
+  auto check_scalar_jobs = [&](int kind) -> tt_status {
+    for (const auto& j : R.e) {
+      if (kind == 0) {  // radj_scalar_kernel
+        TT_TRY(R.check(R.inside(j.x, j.cnt - 1) && R.inside(j.out2, 0), "scalar x"));
+        TT_TRY(R.check(j.op == 0 ? R.inside(j.out, j.cnt - 1) : R.inside(j.y, j.cnt - 1), "scalar out"));
+      } else if (kind == 1) {  // eigprep
+        const long long nd = j.R - j.r;
+        TT_TRY(R.check(j.R >= j.r && R.inside(j.x, j.R - 1) && R.inside(j.y, (long long)j.R * j.ld - 1) &&
+                           j.ld >= j.p && R.inside(j.out, (long long)j.p * nd - 1) &&
+                           R.inside(j.out2, nd * j.r + j.r - 1),
+                       "eigprep"));
+      } else {  // eigapply
+        const long long nd = j.R - j.r;
+        TT_TRY(R.check(R.inside(j.out, (long long)j.p * j.r - 1) && R.inside(j.out2, nd * j.r - 1) &&
+                           R.inside(j.y, nd * j.r - 1) && R.inside(j.s, j.r - 1),
+                       "eigapply"));
+      }
+    }
+    return TT_OK;
+  };
+  auto acore = [&](int b, int k) { return reinterpret_cast<const double*>(a[b].cores) + make_dev(a[b]).off[k]; };
+  auto ycore = [&](int b, int k) { return reinterpret_cast<const double*>(y[b].cores) + make_dev(y[b]).off[k]; };
+  auto ybcore = [&](int b, int k) {
+    return reinterpret_cast<const double*>(y_bar[b].cores) + make_dev(y_bar[b]).off[k];
+  };
+  auto abcore = [&](int b, int k) { return reinterpret_cast<double*>(a_bar[b].cores) + make_dev(a_bar[b]).off[k]; };
+  // zero accumulators and factors; G_{d-1} = 1, W_0 = 1
+  for (int b = 0; b < batch; ++b) {
+    RadjFilter& f = F[b];
+    for (int k = 0; k < d; ++k) {
+      const long long asz = (long long)f.Ra[k] * f.n[k] * f.Ra[k + 1];
+      R.ej(EJ_FILL, asz, nullptr, nullptr, abcore(b, k), nullptr, nullptr);
+      R.ej(EJ_FILL, (long long)f.Ra[k + 1] * f.Ra[k + 1], nullptr, nullptr, f.c[k].Gbar, nullptr, nullptr);
+      if (k < d - 1)
+        R.ej(EJ_FILL, (long long)f.Ra[k + 1] * f.Ra[k + 1], nullptr, nullptr, f.c[k].lfac, nullptr, nullptr);
+    }
+    R.ej(EJ_ONE, 1, nullptr, nullptr, f.c[d - 1].G, nullptr, nullptr);
+    R.ej(EJ_ONE, 1, nullptr, nullptr, f.c[0].W, nullptr, nullptr);
+    TT_TRY(R.elem());
+  }
+  // phase 1: right-part Grams, G_{k-1} = sum_i A_k(:,i,:) G_k A_k(:,i,:)^T
+  for (int k = d - 1; k >= 1; --k) {
+    for (int b = 0; b < batch; ++b) {
+      RadjFilter& f = F[b];
+      const int R0 = f.Ra[k], R1 = f.Ra[k + 1], n = f.n[k];
+      R.mm(R0 * n, R1, R1, acore(b, k), R1, 1, f.c[k].G, R1, 1, f.Tg, R1, 1.0, 0.0);
+    }
+    TT_TRY(R.gemm());
+    for (int b = 0; b < batch; ++b) {
+      RadjFilter& f = F[b];
+      const int R0 = f.Ra[k], R1 = f.Ra[k + 1], n = f.n[k];
+      R.mm(R0, R0, n * R1, f.Tg, (long long)n * R1, 1, acore(b, k), 1, (long long)n * R1, f.c[k - 1].G, R0, 1.0, 0.0);
+    }
+    TT_TRY(R.gemm());
+  }
+  // phase 2: U_k = Y_k / c_k, N_k = W_k x_1 A_k, W_{k+1} = U_k^T N_k, L = W_{d-1} x_1 A_{d-1}
+  for (int b = 0; b < batch; ++b) {
+    RadjFilter& f = F[b];
+    for (int k = 0; k < d - 1; ++k)
+      R.ej(0, (long long)f.ry[k] * f.n[k] * f.ry[k + 1], ycore(b, k), nullptr, f.c[k].U, f.c[k].c, nullptr,
+           f.ry[k + 1]);
+  }
+  if (!R.e.empty()) {
+    TT_TRY(check_scalar_jobs(0));
+    TT_TRY(upload(R.de, R.e, st));
+    hipLaunchKernelGGL(radj_scalar_kernel, dim3((int)R.e.size()), dim3(256), 0, st, R.de);
+    TTG_LAUNCH_CHECK("radj_scalar_kernel");
+    R.e.clear();
+  }
+  for (int k = 0; k < d - 1; ++k) {
+    for (int b = 0; b < batch; ++b) {
+      RadjFilter& f = F[b];
+      const int R0 = f.Ra[k], R1 = f.Ra[k + 1], n = f.n[k], r0 = f.ry[k];
+      R.mm(r0, n * R1, R0, f.c[k].W, R0, 1, acore(b, k), (long long)n * R1, 1, f.c[k].N, (long long)n * R1, 1.0, 0.0);
+    }
+    TT_TRY(R.gemm());
+    for (int b = 0; b < batch; ++b) {
+      RadjFilter& f = F[b];
+      const int R1 = f.Ra[k + 1], n = f.n[k], r0 = f.ry[k], r1 = f.ry[k + 1];
+      const int p = r0 * n;
+      R.mm(r1, R1, p, f.c[k].U, 1, r1, f.c[k].N, R1, 1, f.c[k + 1].W, R1, 1.0, 0.0);
+    }
+    TT_TRY(R.gemm());
+  }
+  for (int b = 0; b < batch; ++b) {
+    RadjFilter& f = F[b];
+    const int R0 = f.Ra[d - 1], n = f.n[d - 1], r0 = f.ry[d - 1];
+    R.mm(r0, n, R0, f.c[d - 1].W, R0, 1, acore(b, d - 1), n, 1, f.L, n, 1.0, 0.0);
+  }
+  TT_TRY(R.gemm());
+  for (int b = 0; b < batch; ++b) {
+    RadjFilter& f = F[b];
+    R.ej(1, (long long)f.ry[d - 1] * f.n[d - 1], ycore(b, d - 1), f.L, nullptr, f.kappa, nullptr);
+  }
+  TT_TRY(check_scalar_jobs(0));
+  TT_TRY(upload(R.de, R.e, st));
+  hipLaunchKernelGGL(radj_scalar_kernel, dim3((int)R.e.size()), dim3(256), 0, st, R.de);
+  TTG_LAUNCH_CHECK("radj_scalar_kernel");
+  R.e.clear();
+  // phase 3: F_k (pivoted Cholesky of G_k), M_k = N_k F_k, Jacobi SVD of M_k
+  if (d > 1) {
+    std::vector<PcholArgs> pj;
+    std::vector<JacobiArgs> jj;
+    int gmax = 1, pmax = 1;
+    for (int b = 0; b < batch; ++b) {
+      RadjFilter& f = F[b];
+      for (int k = 0; k < d - 1; ++k) {
+        const int R1 = f.Ra[k + 1];
+        PcholArgs pa;
+        memset(&pa, 0, sizeof(pa));
+        pa.M = R1;
+        pa.g = f.c[k].G;
+        pa.lwork = f.c[k].lwork;
+        pa.lfac = f.c[k].lfac;
+        pa.piv = f.c[k].piv;
+        pa.rank_out = f.c[k].prank;
+        pa.gcap = R1;
+        pa.rmax = R1;
+        pa.tau2 = 1e-24;
+        pj.push_back(pa);
+        gmax = std::max(gmax, R1);
+        const int p = f.ry[k] * f.n[k];
+        pmax = std::max(pmax, p);
+        JacobiArgs ja;
+        memset(&ja, 0, sizeof(ja));
+        ja.rows = p;
+        ja.ncols = R1;
+        ja.tol2 = 1e-30;
+        ja.x = f.c[k].M;
+        ja.ldx = R1;
+        ja.work = f.c[k].jw;
+        ja.sigma = f.c[k].sig;
+        ja.usv = f.c[k].usv;
+        ja.gcap = p;
+        jj.push_back(ja);
+      }
+    }
+    if (gmax > 1024 || (int)pj.size() > batch * d) {
+      set_error("tt_round_adjoint: rank above 1024");
+      return TT_ERR_SHAPE;
+    }
+    for (const auto& pa : pj)
+      TT_TRY(R.check(R.inside(pa.g, (long long)pa.M * pa.gcap - 1) && R.inside(pa.lwork, (long long)pa.M * pa.gcap - 1) &&
+                         R.inside(pa.lfac, (long long)pa.M * pa.gcap - 1),
+                     "pchol"));
+    for (const auto& ja : jj)
+      TT_TRY(R.check(R.inside(ja.x, (long long)(ja.rows - 1) * ja.ldx + ja.ncols - 1) &&
+                         R.inside(ja.work, (long long)ja.ncols * ja.gcap - 1) &&
+                         R.inside(ja.usv, (long long)ja.ncols * ja.gcap - 1) && R.inside(ja.sigma, ja.ncols - 1) &&
+                         ja.rows <= ja.gcap,
+                     "jacobi"));
+    TT_TRY(upload(R.dp, pj, st));
+    TT_TRY((launch_pchol<AccD, FAdjPchol>(FAdjPchol{R.dp}, (int)pj.size(), gmax, st)));
+    for (int b = 0; b < batch; ++b) {
+      RadjFilter& f = F[b];
+      for (int k = 0; k < d - 1; ++k) {
+        const int R1 = f.Ra[k + 1], p = f.ry[k] * f.n[k];
+        R.mm(p, R1, R1, f.c[k].N, R1, 1, f.c[k].lfac, R1, 1, f.c[k].M, R1, 1.0, 0.0);
+      }
+    }
+    TT_TRY(R.gemm());
+    TT_TRY(upload(R.dj, jj, st));
+    TT_TRY(launch_jacobi(FAdjJacobi{R.dj}, (int)jj.size(), st));
+    for (int b = 0; b < batch; ++b) {
+      RadjFilter& f = F[b];
+      for (int k = 0; k < d - 1; ++k) {
+        const int R1 = f.Ra[k + 1], r1 = f.ry[k + 1], p = f.ry[k] * f.n[k];
+        R.ej(0, 0, f.c[k].sig, f.c[k].usv, f.c[k].Ud, f.c[k].Fm, nullptr, r1, p, R1, p);
+      }
+    }
+    TT_TRY(check_scalar_jobs(1));
+    TT_TRY(upload(R.de, R.e, st));
+    hipLaunchKernelGGL(radj_eigprep_kernel, dim3((int)R.e.size()), dim3(256), 0, st, R.de);
+    TTG_LAUNCH_CHECK("radj_eigprep_kernel");
+    R.e.clear();
+  }
+  // phase 4: the left-to-right sweep backwards
+  for (int b = 0; b < batch; ++b) {
+    RadjFilter& f = F[b];
+    R.ej(EJ_SCALE, (long long)f.ry[d - 1] * f.n[d - 1], ybcore(b, d - 1), nullptr, f.Lbar, nullptr, f.kappa);
+  }
+  TT_TRY(R.elem());
+  for (int b = 0; b < batch; ++b) {
+    RadjFilter& f = F[b];
+    const int R0 = f.Ra[d - 1], n = f.n[d - 1], r0 = f.ry[d - 1];
+    // Wbar_{d-1} = Lbar A_{d-1}^T, Abar_{d-1} += W_{d-1}^T Lbar
+    R.mm(r0, R0, n, f.Lbar, n, 1, acore(b, d - 1), 1, n, f.Wb0, R0, 1.0, 0.0);
+    R.mm(R0, n, r0, f.c[d - 1].W, 1, R0, f.Lbar, n, 1, abcore(b, d - 1), n, 1.0, 1.0);
+  }
+  TT_TRY(R.gemm());
+  bool cur0 = true;  // Wbar_{k+1} lives in Wb0 when true
+  for (int k = d - 2; k >= 0; --k) {
+    auto wb_in = [&](RadjFilter& f) { return cur0 ? f.Wb0 : f.Wb1; };
+    auto wb_out = [&](RadjFilter& f) { return cur0 ? f.Wb1 : f.Wb0; };
+    for (int b = 0; b < batch; ++b) {
+      RadjFilter& f = F[b];
+      const int R1 = f.Ra[k + 1], r1 = f.ry[k + 1], p = f.ry[k] * f.n[k];
+      R.mm(p, R1, r1, f.c[k].U, r1, 1, wb_in(f), R1, 1, f.Nbar, R1, 1.0, 0.0);
+      R.ej(EJ_SCALE, (long long)p * r1, ybcore(b, k), nullptr, f.Ubar, nullptr, f.c[k].c);
+    }
+    TT_TRY(R.gemm());
+    TT_TRY(R.elem());
+    for (int b = 0; b < batch; ++b) {  // Ubar += N W_bar^T
+      RadjFilter& f = F[b];
+      const int R1 = f.Ra[k + 1], r1 = f.ry[k + 1], p = f.ry[k] * f.n[k];
+      R.mm(p, r1, R1, f.c[k].N, R1, 1, wb_in(f), 1, R1, f.Ubar, r1, 1.0, 1.0);
+    }
+    TT_TRY(R.gemm());
+    for (int b = 0; b < batch; ++b) {  // P1 = U^T Ubar, P2 = Ud^T Ubar
+      RadjFilter& f = F[b];
+      const int R1 = f.Ra[k + 1], r1 = f.ry[k + 1], p = f.ry[k] * f.n[k], nd = R1 - r1;
+      R.mm(r1, r1, p, f.c[k].U, 1, r1, f.Ubar, r1, 1, f.P1, r1, 1.0, 0.0);
+      R.mm(nd, r1, p, f.c[k].Ud, 1, nd, f.Ubar, r1, 1, f.P2, r1, 1.0, 0.0);
+    }
+    TT_TRY(R.gemm());
+    for (int b = 0; b < batch; ++b) {  // Ubar -= U P1
+      RadjFilter& f = F[b];
+      const int r1 = f.ry[k + 1], p = f.ry[k] * f.n[k];
+      R.mm(p, r1, r1, f.c[k].U, r1, 1, f.P1, r1, 1, f.Ubar, r1, -1.0, 1.0);
+    }
+    TT_TRY(R.gemm());
+    for (int b = 0; b < batch; ++b) {  // Ubar -= Ud P2
+      RadjFilter& f = F[b];
+      const int R1 = f.Ra[k + 1], r1 = f.ry[k + 1], p = f.ry[k] * f.n[k], nd = R1 - r1;
+      R.mm(p, r1, nd, f.c[k].Ud, nd, 1, f.P2, r1, 1, f.Ubar, r1, -1.0, 1.0);
+    }
+    TT_TRY(R.gemm());
+    for (int b = 0; b < batch; ++b) {  // X = Ubar diag(linv), P2 = P2 o Fm
+      RadjFilter& f = F[b];
+      const int R1 = f.Ra[k + 1], r1 = f.ry[k + 1], p = f.ry[k] * f.n[k], nd = R1 - r1;
+      R.ej(0, 0, nullptr, f.c[k].Fm, f.Ubar, f.P2, f.c[k].Fm + (long long)nd * r1, r1, p, R1, 0);
+    }
+    {
+      long long mx = 1;
+      for (auto& j : R.e) mx = std::max(mx, (long long)j.p * j.r + (long long)(j.R - j.r) * j.r);
+      TT_TRY(check_scalar_jobs(2));
+      TT_TRY(upload(R.de, R.e, st));
+      hipLaunchKernelGGL(radj_eigapply_kernel, dim3(std::min(cdiv(mx, 256), 1024), (int)R.e.size()), dim3(256), 0, st,
+                         R.de);
+      TTG_LAUNCH_CHECK("radj_eigapply_kernel");
+      R.e.clear();
+    }
+    for (int b = 0; b < batch; ++b) {  // X += Ud P2
+      RadjFilter& f = F[b];
+      const int R1 = f.Ra[k + 1], r1 = f.ry[k + 1], p = f.ry[k] * f.n[k], nd = R1 - r1;
+      R.mm(p, r1, nd, f.c[k].Ud, nd, 1, f.P2, r1, 1, f.Ubar, r1, 1.0, 1.0);
+    }
+    TT_TRY(R.gemm());
+    for (int b = 0; b < batch; ++b) {  // WG = W_{k+1} G_k, XtN = X^T N
+      RadjFilter& f = F[b];
+      const int R1 = f.Ra[k + 1], r1 = f.ry[k + 1], p = f.ry[k] * f.n[k];
+      R.mm(r1, R1, R1, f.c[k + 1].W, R1, 1, f.c[k].G, R1, 1, f.WG, R1, 1.0, 0.0);
+      R.mm(r1, R1, p, f.Ubar, 1, r1, f.c[k].N, R1, 1, f.XtN, R1, 1.0, 0.0);
+    }
+    TT_TRY(R.gemm());
+    for (int b = 0; b < batch; ++b) {  // XtNG = XtN G, Nbar += X WG, Gbar_k += XtN^T W_{k+1}
+      RadjFilter& f = F[b];
+      const int R1 = f.Ra[k + 1], r1 = f.ry[k + 1], p = f.ry[k] * f.n[k];
+      R.mm(r1, R1, R1, f.XtN, R1, 1, f.c[k].G, R1, 1, f.XtNG, R1, 1.0, 0.0);
+      R.mm(p, R1, r1, f.Ubar, r1, 1, f.WG, R1, 1, f.Nbar, R1, 1.0, 1.0);
+      R.mm(R1, R1, r1, f.XtN, 1, R1, f.c[k + 1].W, R1, 1, f.c[k].Gbar, R1, 1.0, 1.0);
+    }
+    TT_TRY(R.gemm());
+    for (int b = 0; b < batch; ++b) {  // Nbar += U XtNG
+      RadjFilter& f = F[b];
+      const int R1 = f.Ra[k + 1], r1 = f.ry[k + 1], p = f.ry[k] * f.n[k];
+      R.mm(p, R1, r1, f.c[k].U, r1, 1, f.XtNG, R1, 1, f.Nbar, R1, 1.0, 1.0);
+    }
+    TT_TRY(R.gemm());
+    for (int b = 0; b < batch; ++b) {  // Wbar_k = Nbar A_k^T, Abar_k += W_k^T Nbar
+      RadjFilter& f = F[b];
+      const int R0 = f.Ra[k], R1 = f.Ra[k + 1], n = f.n[k], r0 = f.ry[k];
+      R.mm(r0, R0, n * R1, f.Nbar, (long long)n * R1, 1, acore(b, k), 1, (long long)n * R1, wb_out(f), R0, 1.0, 0.0);
+      R.mm(R0, n * R1, r0, f.c[k].W, 1, R0, f.Nbar, (long long)n * R1, 1, abcore(b, k), (long long)n * R1, 1.0, 1.0);
+    }
+    TT_TRY(R.gemm());
+    cur0 = !cur0;
+  }
+  // phase 5: the Gram recursion backwards, from the left
+  for (int k = 1; k < d; ++k) {
+    for (int b = 0; b < batch; ++b) {
+      RadjFilter& f = F[b];
+      const int R0 = f.Ra[k];
+      R.ej(EJ_SYM, (long long)R0 * R0, f.c[k - 1].Gbar, nullptr, f.Gs, nullptr, nullptr, R0);
+    }
+    TT_TRY(R.elem());
+    for (int b = 0; b < batch; ++b) {
+      RadjFilter& f = F[b];
+      const int R0 = f.Ra[k], R1 = f.Ra[k + 1], n = f.n[k];
+      R.mm(R0, n * R1, R0, f.Gs, R0, 1, acore(b, k), (long long)n * R1, 1, f.Tg, (long long)n * R1, 1.0, 0.0);
+      R.mm(R0, n * R1, R0, f.c[k - 1].Gbar, R0, 1, acore(b, k), (long long)n * R1, 1, f.T2, (long long)n * R1, 1.0,
+           0.0);
+    }
+    TT_TRY(R.gemm());
+    for (int b = 0; b < batch; ++b) {
+      RadjFilter& f = F[b];
+      const int R0 = f.Ra[k], R1 = f.Ra[k + 1], n = f.n[k];
+      R.mm(R0 * n, R1, R1, f.Tg, R1, 1, f.c[k].G, R1, 1, abcore(b, k), R1, 1.0, 1.0);
+      R.mm(R1, R1, R0 * n, acore(b, k), 1, R1, f.T2, R1, 1, f.c[k].Gbar, R1, 1.0, 1.0);
+    }
+    TT_TRY(R.gemm());
+  }
+  // the adjoint train: ranks of a, log-scale adjoint of y_bar, status 0
+  for (int b = 0; b < batch; ++b) {
+    HIP_TRY(hipMemcpyAsync(a_bar[b].ranks, &hr[(size_t)(3 * b) * (d + 1)], sizeof(int) * (d + 1),
+                           hipMemcpyHostToDevice, st), "a_bar ranks");
+    HIP_TRY(hipMemcpyAsync(a_bar[b].log_scale, y_bar[b].log_scale, sizeof(double), hipMemcpyDeviceToDevice, st),
+            "a_bar log_scale");
+    HIP_TRY(hipMemsetAsync(a_bar[b].status, 0, sizeof(int), st), "a_bar status");
+  }
+  HIP_TRY(hipStreamSynchronize(st), "tt_round_adjoint");
+  return TT_OK;
 }
 
 }  // extern "C"

@@ -467,9 +467,16 @@ __device__ inline double jac_rsq(double x) {
 __device__ inline bool jac_rotation(double al, double be, double ga, double& cs, double& sn, double tol2) {
   if (!(ga != 0.0 && ga * ga > tol2 * (al * be))) return false;
   const double zeta = (be - al) * 0.5 * jac_rcp(ga);
-  const double s1 = __fma_rn(zeta, zeta, 1.0);
-  const double root = s1 * jac_rsq(s1);
-  const double t = (zeta >= 0.0 ? 1.0 : -1.0) * jac_rcp(fabs(zeta) + root);
+  double t;
+  if (fabs(zeta) > 1.3e154) {
+    // zeta^2 would overflow (a column many orders below its partner, as
+    // rank-deficient inputs produce): t = 1 / (2 zeta) to working precision
+    t = 0.5 * jac_rcp(zeta);
+  } else {
+    const double s1 = __fma_rn(zeta, zeta, 1.0);
+    const double root = s1 * jac_rsq(s1);
+    t = (zeta >= 0.0 ? 1.0 : -1.0) * jac_rcp(fabs(zeta) + root);
+  }
   cs = jac_rsq(__fma_rn(t, t, 1.0));
   sn = cs * t;
   return true;

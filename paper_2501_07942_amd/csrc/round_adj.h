@@ -1,0 +1,246 @@
+// Adjoint of the TT rounding of Sec. 4.1 'round' at fixed ranks (FP64).
+//
+// The rounding is written as a function of the input cores A_k alone (its
+// value as a full tensor does not depend on the orthogonalisation used):
+//
+//   right-part Grams   G_{d-1} = 1,  G_{k-1} = sum_i A_k(:,i,:) G_k A_k(:,i,:)^T
+//   left to right      N_k = W_k x_1 A_k  ((r_k n_k) x R_{k+1}),  W_0 = 1
+//                      U_k = leading r_{k+1} eigenvectors of S_k = N_k G_k N_k^T
+//                      W_{k+1} = U_k^T N_k
+//   output             core k = U_k (k < d-1),  last core = W_{d-1} x_1 A_{d-1}
+//
+// The library's forward rounding returns exactly these cores up to scalar
+// factors moved into the log-scale; the adjoint takes the kept U_k from
+// the forward's output (its gauge) and the eigenvalues and discarded
+// directions of S_k from a one-sided Jacobi SVD of M_k = N_k F_k with
+// F_k F_k^T = G_k (pivoted Cholesky).  For the leading eigenvectors,
+// dU_j = sum_{i != j} u_i (u_i^T dS u_j) / (lam_j - lam_i); its adjoint is
+// Sbar = X U^T with
+//   X_j = (I - U_all U_all^T) Ubar_j / lam_j + sum_{i discarded} u_i (u_i^T Ubar_j) / (lam_j - lam_i)
+// (couplings among kept vectors cancel because everything downstream
+// depends on the rounded tensor only).  Kept directions below TAU of the
+// largest singular value are left out: their terms carry rounding noise of
+// order eps sigma_1^2 / sigma_j^2.  Then, per core from the right,
+//   Nbar = U Wbar_{k+1} + X (W_{k+1} G_k) + U ((X^T N_k) G_k)
+//   Gbar_k += (X^T N_k)^T W_{k+1}
+//   Wbar_k = Nbar x A_k^T,  Abar_k += W_k^T Nbar
+// and finally the Gram recursion from the left:
+//   Abar_k(:,i,:) += (Gbar_{k-1} + Gbar_{k-1}^T) A_k(:,i,:) G_k
+//   Gbar_k += sum_i A_k(:,i,:)^T Gbar_{k-1} A_k(:,i,:).
+//
+// Every step is a small dense product (one grouped GEMM launch per phase,
+// described by a job table built on the host) or an elementwise pass.
+#pragma once
+
+#include "common.h"
+#include "linalg.h"
+
+namespace ttg {
+
+#define RADJ_TAU 6e-6     // kept singular values below TAU * sigma_1 are left out
+#define RADJ_DISC 1e-9    // discarded singular values below this (relative) count as null space
+
+// C = alpha * A B + beta * C (beta = 0 overwrites), one 64 x 64 tile of one
+// job per workgroup; FP64, every element sums its k in increasing order.
+struct GJob {
+  int M, N, K;
+  const double* a;
+  long long sam, sak;
+  const double* b;
+  long long sbk, sbn;
+  double* c;
+  long long scm, scn;
+  double alpha, beta;
+  int tile0;  // first global tile of this job
+  int tn;     // tiles along N
+};
+
+__global__ void __launch_bounds__(256) gjob_gemm_kernel(const GJob* __restrict__ jobs, int njobs) {
+  const int t = blockIdx.x;
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].tile0 <= t)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const GJob g = jobs[lo];
+  const int lt = t - g.tile0;
+  const int m0 = (lt / g.tn) * 64, n0 = (lt - (lt / g.tn) * g.tn) * 64;
+  if (m0 >= g.M || n0 >= g.N) return;
+  __shared__ double As[16][64 + 1];
+  __shared__ double Bs[16][64 + 1];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  for (int k0 = 0; k0 < g.K; k0 += 16) {
+    for (int e = threadIdx.x; e < 64 * 16; e += 256) {
+      const int mm = e >> 4, kk = e & 15;
+      const int m = m0 + mm, k = k0 + kk;
+      As[kk][mm] = (m < g.M && k < g.K) ? g.a[(long long)m * g.sam + (long long)k * g.sak] : 0.0;
+      const int kb = e >> 6, nn = e & 63;
+      const int n = n0 + nn, k2 = k0 + kb;
+      Bs[kb][nn] = (n < g.N && k2 < g.K) ? g.b[(long long)k2 * g.sbk + (long long)n * g.sbn] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) av[i] = As[kk][ty * 4 + i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bv[j] = Bs[kk][tx * 4 + j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __fma_rn(av[i], bv[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int m = m0 + ty * 4 + i, n = n0 + tx * 4 + j;
+      if (m < g.M && n < g.N) {
+        double* cp = g.c + (long long)m * g.scm + (long long)n * g.scn;
+        *cp = g.beta == 0.0 ? g.alpha * acc[i][j] : __fma_rn(g.alpha, acc[i][j], g.beta * *cp);
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// elementwise passes; blockIdx.y selects the job
+// ---------------------------------------------------------------------------
+struct EJob {
+  int op;
+  long long cnt;
+  const double* x;
+  const double* y;
+  double* out;
+  double* out2;
+  const double* s;  // device scalar
+  int r, p, R;      // shapes for the eigen passes
+  int ld;
+};
+
+enum {
+  EJ_FILL = 0,      // out[e] = 0
+  EJ_SCALE = 1,     // out[e] = s[0] * x[e]
+  EJ_SYM = 2,       // out = x + x^T (r x r)
+  EJ_ONE = 3,       // out[0] = 1
+};
+
+__global__ void __launch_bounds__(256) ejob_kernel(const EJob* __restrict__ jobs) {
+  const EJob j = jobs[blockIdx.y];
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < j.cnt; e += stride) {
+    switch (j.op) {
+      case EJ_FILL: j.out[e] = 0.0; break;
+      case EJ_SCALE: j.out[e] = j.s[0] * j.x[e]; break;
+      case EJ_SYM: {
+        const int a = (int)(e / j.r), b = (int)(e - (long long)a * j.r);
+        j.out[e] = j.x[e] + j.x[(long long)b * j.r + a];
+        break;
+      }
+      default: if (e == 0) j.out[0] = 1.0; break;
+    }
+  }
+}
+
+// Norm factor c of a core Y_k = c U_k with orthonormal columns (r of them):
+// c = sqrt(||Y||^2 / r); writes c and U = Y / c.  One workgroup per job.
+// With op = 1 instead: kappa = <x, y> / ||y||^2 (the last core Y = kappa L).
+__global__ void __launch_bounds__(256) radj_scalar_kernel(const EJob* __restrict__ jobs) {
+  const EJob j = jobs[blockIdx.x];
+  __shared__ double red[4];
+  double s = 0.0, t = 0.0;
+  for (long long e = threadIdx.x; e < j.cnt; e += blockDim.x) {
+    const double v = j.x[e];
+    if (j.op == 0) {
+      s = __fma_rn(v, v, s);
+    } else {
+      s = __fma_rn(v, j.y[e], s);
+      t = __fma_rn(j.y[e], j.y[e], t);
+    }
+  }
+  s = block_sum(s, red);
+  t = block_sum(t, red);
+  if (j.op == 0) {
+    const double c = sqrt(s / (double)j.r);
+    if (threadIdx.x == 0) j.out2[0] = c;
+    const double ic = c > 0.0 ? 1.0 / c : 0.0;
+    for (long long e = threadIdx.x; e < j.cnt; e += blockDim.x) j.out[e] = j.x[e] * ic;
+  } else if (threadIdx.x == 0) {
+    j.out2[0] = t > 0.0 ? s / t : 0.0;
+  }
+}
+
+// From the Jacobi SVD of M (sigma descending, usv column c = sigma_c u_c,
+// column-major ld p) and the kept count r: the discarded left vectors
+// Ud (p x (R - r), row-major) = u_i for sigma_i > DISC sigma_1 (zero
+// otherwise), the coupling matrix Fm ((R - r) x r) = 1 / (lam_j - lam_i) for
+// those i and live j, and linv (r) = 1 / lam_j for live j (sigma_j >= TAU
+// sigma_1), zero for left-out j.  x = sigma, y = usv, out = Ud, out2 = Fm,
+// s -> linv (written through out2 + (R - r) r).  One workgroup per job.
+__global__ void __launch_bounds__(256) radj_eigprep_kernel(const EJob* __restrict__ jobs) {
+  const EJob j = jobs[blockIdx.x];
+  const int p = j.p, R = j.R, r = j.r, nd = R - r;
+  const double* sig = j.x;
+  const double s1 = sig[0];
+  double* linv = j.out2 + (long long)nd * r;
+  for (int c = threadIdx.x; c < r; c += blockDim.x) {
+    const double sj = sig[c];
+    linv[c] = (s1 > 0.0 && sj >= RADJ_TAU * s1) ? 1.0 / (sj * sj) : 0.0;
+  }
+  for (long long e = threadIdx.x; e < (long long)nd * r; e += blockDim.x) {
+    const int i = (int)(e / r), c = (int)(e - (long long)i * r);
+    const double si = sig[r + i], sj = sig[c];
+    const bool ok = s1 > 0.0 && si > RADJ_DISC * s1 && sj >= RADJ_TAU * s1 && sj > si;
+    j.out2[e] = ok ? 1.0 / ((sj - si) * (sj + si)) : 0.0;
+  }
+  for (long long e = threadIdx.x; e < (long long)p * nd; e += blockDim.x) {
+    const int row = (int)(e / nd), i = (int)(e - (long long)row * nd);
+    const double si = sig[r + i];
+    j.out[e] = (s1 > 0.0 && si > RADJ_DISC * s1) ? j.y[(long long)(r + i) * j.ld + row] / si : 0.0;
+  }
+}
+
+// X = Z diag(linv) in place (Z p x r) and P2 = P2 o Fm in place ((R - r) x r).
+// x unused; out = Z, out2 = P2, y = Fm, s = linv.
+__global__ void __launch_bounds__(256) radj_eigapply_kernel(const EJob* __restrict__ jobs) {
+  const EJob j = jobs[blockIdx.y];
+  const int r = j.r, nd = j.R - j.r;
+  const long long nz = (long long)j.p * r, np = (long long)nd * r;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nz + np; e += stride) {
+    if (e < nz) {
+      j.out[e] *= j.s[e % r];
+    } else {
+      const long long f = e - nz;
+      j.out2[f] *= j.y[f];
+    }
+  }
+}
+
+// pivoted Cholesky and Jacobi SVD over job tables
+struct FAdjPchol {
+  const PcholArgs* a;
+  __device__ bool operator()(int b, PcholArgs& p) const {
+    p = a[b];
+    return p.M > 0;
+  }
+};
+struct FAdjJacobi {
+  const JacobiArgs* a;
+  __device__ bool operator()(int b, JacobiArgs& J) const {
+    J = a[b];
+    return J.rows > 0 && J.ncols > 0;
+  }
+};
+
+}  // namespace ttg
