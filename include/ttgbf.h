@@ -263,6 +263,70 @@ size_t tt_round_adjoint_workspace(int32_t batch, const tt_train* a, const tt_tra
 tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, const tt_train* y_bar,
                            const tt_train* a_bar, void* ws, size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------------
+ * Pieces for a composed reverse-mode gradient (all FP64 trains):
+ *
+ * tt_prior: the rank-one Gaussian prior of Sec. 2 (eq. pdf_pm with a
+ * diagonal Gaussian p(x_0)), per axis exp(-(xi - m0)^2 / (2 p0)) shifted by
+ * its maximum, the shifts and Gaussian constants in log_scale (the density
+ * is not normalised here).  m0, p0_diag: host arrays [batch*d].
+ *
+ * tt_likelihood: the likelihood TT that tt_update multiplies with (Sec.
+ * 2.2; the range block by truncated SVD at meas.lik_tol, linear axes rank
+ * one, each factor max-shifted into log_scale), written to l_out (FP64;
+ * capacities 1 except cap[1] = min(lik_rank_cap, n[1]) for the range
+ * model).  Workspace: tt_update_workspace with p_pred = h_out = l_out.
+ *
+ * tt_likelihood_dense: the likelihood before the range block's truncation
+ * (p_out, FP64): core 0 = the max-shifted (x_1, x_2) block M (n[0] x n[1]),
+ * core 1 = the identity (capacities 1 except cap[1] = n[1] for the range
+ * model), linear-axis factors and log_scale as tt_likelihood writes them.
+ * Workspace: tt_update_workspace(batch, grids, meas, p_out, p_out, 1).
+ *
+ * tt_likelihood_adjoint: adjoint of the build l = tt_likelihood(...) with
+ * respect to its dense input p = tt_likelihood_dense(...) of the same
+ * measurement: given l_bar (the adjoint of l, l's capacities and ranks),
+ * writes p_bar (p's capacities): core 0 = the adjoint of M through the
+ * truncated SVD at l's rank (Sec. 3.1 truncation, differentiated as the
+ * rounding adjoint of the two-core train (M^T, I), tt_round_adjoint), core 1
+ * zero, linear factors and the log-scale adjoint copied from l_bar.  For
+ * the linear model p_bar = l_bar.  <p_bar, dp> is then the derivative of the
+ * scalar l_bar belongs to along a parameter tangent dp of the dense
+ * likelihood.  TT_STATUS_CAPACITY on p_bar if l_bar's ranks differ from l's.
+ * Workspace: tt_likelihood_adjoint_workspace(batch, meas, p, l).
+ *
+ * tt_adjoint_axpy: y += alpha x (cores and log_scale) for adjoint trains of
+ * equal ranks (TT_STATUS_CAPACITY on y otherwise).
+ *
+ * tt_adjoint_inner: out_dev[b] = sum of the stored core entries of a_bar
+ * times those of b over the ranks both share, plus the product of their
+ * log_scale fields: the derivative <a_bar, db> of the scalar that a_bar is
+ * the adjoint of, for a tangent db of the train b.
+ *
+ * tt_align_signs: flips the sign of each bond index of t (in both adjacent
+ * cores, so the tensor is unchanged) to correlate positively with ref,
+ * bond by bond from the left: puts a truncated-SVD build at perturbed
+ * parameters into the basis of the build at the base parameters.
+ * Workspace for the last three: tt_adjoint_workspace.
+ * --------------------------------------------------------------------- */
+tt_status tt_prior(int32_t batch, const tt_grid* grids, const double* m0, const double* p0_diag, const tt_train* out,
+                   void* ws, size_t ws_bytes, void* stream);
+tt_status tt_likelihood(int32_t batch, const tt_grid* grids, const tt_meas* meas, const double* z_dev,
+                        int32_t z_stride, const tt_train* l_out, int32_t lik_rank_cap, void* ws, size_t ws_bytes,
+                        void* stream);
+tt_status tt_likelihood_dense(int32_t batch, const tt_grid* grids, const tt_meas* meas, const double* z_dev,
+                              int32_t z_stride, const tt_train* p_out, void* ws, size_t ws_bytes, void* stream);
+size_t tt_likelihood_adjoint_workspace(int32_t batch, const tt_meas* meas, const tt_train* p, const tt_train* l);
+tt_status tt_likelihood_adjoint(int32_t batch, const tt_meas* meas, const tt_train* p, const tt_train* l,
+                                const tt_train* l_bar, const tt_train* p_bar, void* ws, size_t ws_bytes,
+                                void* stream);
+tt_status tt_adjoint_axpy(int32_t batch, double alpha, const tt_train* x, const tt_train* y, void* ws,
+                          size_t ws_bytes, void* stream);
+tt_status tt_adjoint_inner(int32_t batch, const tt_train* a_bar, const tt_train* b, double* out_dev, void* ws,
+                           size_t ws_bytes, void* stream);
+tt_status tt_align_signs(int32_t batch, const tt_train* ref, const tt_train* t, void* ws, size_t ws_bytes,
+                         void* stream);
+
 size_t tt_adjoint_workspace(int32_t batch, int32_t d, int32_t rank_cap);
 tt_status tt_predict_adjoint(int32_t batch, const tt_train* kernels, const tt_train* p_in, const tt_train* c_bar,
                              const tt_train* p_bar, const tt_train* k_bar, void* ws, size_t ws_bytes,

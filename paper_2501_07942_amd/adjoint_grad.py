@@ -1,0 +1,238 @@
+"""Reverse-mode gradient of the log marginal likelihood sum_k log c_k (Sec.
+2.2, eq. pmf_filtrace_b) for a batch of FP64 filters, composed from the
+library's forward and adjoint entry points.  Marshalling and sequencing
+only: every arithmetic step runs in libttgbf.so.
+
+Forward (Alg. 2 order, the prediction of Sec. 4.2 materialised):
+  k = 0: P = normalise(prior)
+  k >= 1: X = K (*) P;  Pt = round(X);  P_pred = normalise(Pt)
+  every k: L_k = likelihood(z_k);  H = L_k o P_pred,  log c_k = log(sum(H) delta);
+           HR = round(H);  P = normalise(HR)
+Only the filtering densities P are kept (a checkpoint per step); the
+reverse sweep recomputes each step from its checkpoint and runs the
+adjoints backwards (tt_normalize_adjoint, tt_round_adjoint,
+tt_hadamard_adjoint, tt_predict_adjoint), collecting the adjoints of the
+kernel train and of every likelihood train.
+
+Parameters enter through the kernel TT (sigma_w) and the likelihood TTs
+(sigma_r, sigma_lin, sensor).  The likelihood adjoints are carried through
+the range block's truncated SVD (tt_likelihood_adjoint) onto the dense
+likelihood P_k, whose parameter tangent is smooth; the kernel contribution
+<Kbar, dK/dtheta> uses the tangent of the kernel's TT-SVD as the central
+difference of the builds at theta +- h aligned to the base build's bond
+bases (tt_align_signs).  Both tangents are central differences of
+dense-in-theta quantities; the recursion itself is differentiated exactly.
+Ranks of every rounding are those of the forward run (the same
+deterministic calls reproduce them).
+"""
+from __future__ import annotations
+
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+from . import binding as B
+from . import grad as G
+from . import runner
+
+
+def _tt_like(t: B.DeviceTT) -> B.DeviceTT:
+    return B.DeviceTT(t.n, t.cap, t.dtype)
+
+
+def _zero_adj(t: B.DeviceTT) -> B.DeviceTT:
+    """Adjoint train of t's layout holding zeros, with t's ranks."""
+    z = _tt_like(t)
+    z.ranks.copy_(t.ranks)
+    return z
+
+
+def _prod_caps(a: B.DeviceTT, b: B.DeviceTT) -> List[int]:
+    return [x * y for x, y in zip(a.cap, b.cap)]
+
+
+def _lik_caps(spec, lik_rank_cap: int) -> List[int]:
+    caps = [1] * (spec.d + 1)
+    if spec.meas_kind == "range":
+        caps[1] = min(lik_rank_cap, spec.n)
+    return caps
+
+
+class _Step:
+    pass
+
+
+class ComposedGradient:
+    """Forward run with checkpoints and the reverse sweep for one batch."""
+
+    def __init__(self, specs: Sequence, zs: Sequence[np.ndarray], lik_rank_cap: int = 64):
+        import torch
+        self.torch = torch
+        self.specs = list(specs)
+        self.Bn = len(specs)
+        self.K = zs[0].shape[0]
+        self.lik_rank_cap = lik_rank_cap
+        self.z, self.zdim = runner.z_tensor(zs)
+        self.grids = [runner.grid_of(s) for s in self.specs]
+        self.meas = [runner.meas_of(s) for s in self.specs]
+        self.delta = [float(np.prod([(s.hi - s.lo) / (s.n - 1)] * s.d)) for s in self.specs]
+        self.kern = []
+        for s in self.specs:
+            ks, _, _ = runner.build_kernels([s], B.F64)
+            self.kern.append(ks[0])
+        self.pcaps = [[1] + [s.cap] * (s.d - 1) + [1] for s in self.specs]
+
+    # ---- forward pieces -------------------------------------------------
+    def _zk(self, k):
+        return self.z[:, k, :].contiguous()
+
+    def _normalise(self, tts):
+        lm = self.torch.zeros(self.Bn, dtype=self.torch.float64, device="cuda")
+        B.tt_normalize_moments(self.grids, tts, lm)
+        return lm
+
+    def _round(self, xs):
+        outs = [B.DeviceTT(x.n, pc, B.F64) for x, pc in zip(xs, self.pcaps)]
+        for s, x, o in zip(self.specs, xs, outs):
+            B.tt_round([x], [o], s.eps, s.cap)
+        return outs
+
+    def _likelihood(self, k, meas=None):
+        ls = [B.DeviceTT([s.n] * s.d, _lik_caps(s, self.lik_rank_cap), B.F64) for s in self.specs]
+        B.tt_likelihood(self.grids, meas or self.meas, self._zk(k), ls, self.lik_rank_cap)
+        return ls
+
+    def _dense_likelihood(self, k, meas=None):
+        ps = [B.DeviceTT([s.n] * s.d, _lik_caps(s, s.n), B.F64) for s in self.specs]
+        B.tt_likelihood_dense(self.grids, meas or self.meas, self._zk(k), ps)
+        return ps
+
+    def _step(self, k, p_prev):
+        """Recompute step k from the filtering density p_prev (None at k = 0)."""
+        st = _Step()
+        if k == 0:
+            pt = [B.DeviceTT([s.n] * s.d, pc, B.F64) for s, pc in zip(self.specs, self.pcaps)]
+            B.tt_prior(self.grids, np.array([s.m0 for s in self.specs]), np.array([s.p0_diag for s in self.specs]), pt)
+            st.x = None
+        else:
+            st.x = [B.DeviceTT(p.n, _prod_caps(kk, p), B.F64) for kk, p in zip(self.kern, p_prev)]
+            B.tt_predict(self.kern, p_prev, st.x)
+            pt = self._round(st.x)
+        st.pt = pt
+        self._normalise(pt)            # pt now holds P_pred (same cores)
+        st.lik = self._likelihood(k)
+        st.h = [B.DeviceTT(p.n, _prod_caps(l, p), B.F64) for l, p in zip(st.lik, pt)]
+        log_c = self.torch.zeros(self.Bn, dtype=self.torch.float64, device="cuda")
+        B.tt_update(self.grids, self.meas, self._zk(k), pt, st.h, self.lik_rank_cap, log_c)
+        st.log_c = log_c
+        st.hr = self._round(st.h)
+        self._normalise(st.hr)         # hr now holds P_k
+        return st
+
+    def forward(self):
+        """Log-likelihoods [B] and the checkpoints P_0 .. P_{K-1}."""
+        self.ckpt = []
+        ll = self.torch.zeros(self.Bn, dtype=self.torch.float64, device="cuda")
+        p = None
+        for k in range(self.K):
+            st = self._step(k, p)
+            ll += st.log_c
+            p = st.hr
+            self.ckpt.append(p)
+        self.torch.cuda.synchronize()
+        self.ll = ll.cpu().numpy()
+        return self.ll
+
+    # ---- reverse sweep --------------------------------------------------
+    def reverse(self):
+        """Adjoints of the kernel trains and of every likelihood train."""
+        kbar = [_zero_adj(kk) for kk in self.kern]
+        self.lbar = [None] * self.K
+        pbar = None
+        for k in range(self.K - 1, -1, -1):
+            st = self._step(k, self.ckpt[k - 1] if k > 0 else None)
+            if pbar is None:
+                pbar = [_zero_adj(h) for h in st.hr]
+            # P_k = normalise(HR)
+            hrbar = [_tt_like(h) for h in st.hr]
+            B.tt_normalize_adjoint(st.hr, pbar, None, hrbar)
+            # HR = round(H)
+            hbar = [_tt_like(h) for h in st.h]
+            B.tt_round_adjoint(st.h, st.hr, hrbar, hbar)
+            # log c_k = log(sum(H) delta): the log-mass adjoint of H with weight one
+            cbar = [_tt_like(h) for h in st.h]
+            one = self.torch.ones(self.Bn, dtype=self.torch.float64, device="cuda")
+            B.tt_normalize_adjoint(st.h, [_zero_adj(h) for h in st.h], one, cbar)
+            B.tt_adjoint_axpy(1.0, cbar, hbar)
+            # H = L o P_pred
+            lbar = [_tt_like(l) for l in st.lik]
+            ppbar = [_tt_like(p) for p in st.pt]
+            B.tt_hadamard_adjoint(st.lik, st.pt, hbar, lbar, ppbar)
+            # L = build(P): the adjoint onto the dense likelihood
+            pd = self._dense_likelihood(k)
+            pdbar = [_tt_like(p) for p in pd]
+            B.tt_likelihood_adjoint(self.meas, pd, st.lik, lbar, pdbar)
+            self.lbar[k] = pdbar
+            if k == 0:
+                break
+            # P_pred = normalise(Pt), Pt = round(X), X = K (*) P_{k-1}
+            ptbar = [_tt_like(p) for p in st.pt]
+            B.tt_normalize_adjoint(st.pt, ppbar, None, ptbar)
+            xbar = [_tt_like(x) for x in st.x]
+            B.tt_round_adjoint(st.x, st.pt, ptbar, xbar)
+            pprev = self.ckpt[k - 1]
+            pbar = [_tt_like(p) for p in pprev]
+            kb = [_tt_like(kk) for kk in self.kern]
+            B.tt_predict_adjoint(self.kern, pprev, xbar, pbar, kb)
+            B.tt_adjoint_axpy(1.0, kb, kbar)
+        self.kbar = kbar
+        self.torch.cuda.synchronize()
+
+    # ---- parameter tangents -----------------------------------------------
+    def _inner(self, abar, b):
+        out = self.torch.zeros(self.Bn, dtype=self.torch.float64, device="cuda")
+        B.tt_adjoint_inner(abar, b, out)
+        return out
+
+    def theta_grad(self, thetas: np.ndarray, h_rel: float = 1e-5) -> np.ndarray:
+        nt = thetas.shape[1]
+        d = self.specs[0].d
+        g = np.zeros((self.Bn, nt))
+        boxes = [s.halfwidths() for s in self.specs]
+        for j in range(nt):
+            hs = h_rel * np.maximum(1.0, np.abs(thetas[:, j]))
+            vals = []
+            for sgn in (1.0, -1.0):
+                th = thetas.copy()
+                th[:, j] += sgn * hs
+                sp = [G.spec_at(s, t, bx) for s, t, bx in zip(self.specs, th, boxes)]
+                acc = self.torch.zeros(self.Bn, dtype=self.torch.float64, device="cuda")
+                if j < d:
+                    kp = []
+                    for s in sp:
+                        ks, _, _ = runner.build_kernels([s], B.F64)
+                        kp.append(ks[0])
+                    B.tt_align_signs(self.kern, kp)
+                    acc += self._inner(self.kbar, kp)
+                else:
+                    meas = [runner.meas_of(s) for s in sp]
+                    for k in range(self.K):
+                        acc += self._inner(self.lbar[k], self._dense_likelihood(k, meas))
+                vals.append(acc)
+            g[:, j] = ((vals[0] - vals[1]).cpu().numpy()) / (2.0 * hs)
+        return g
+
+
+def loglik_grad_adjoint(specs: Sequence, zs: Sequence[np.ndarray], thetas: Optional[np.ndarray] = None,
+                        h_rel: float = 1e-5, lik_rank_cap: int = 64):
+    """LL [B] and dLL/dtheta [B, n_theta] by the composed reverse sweep
+    (FP64).  thetas: [B, n_theta] (None: each spec's own parameters)."""
+    specs = list(specs)
+    if thetas is None:
+        thetas = np.array([G.theta_of(s) for s in specs])
+    boxes = [s.halfwidths() for s in specs]
+    sp = [G.spec_at(s, t, bx) for s, t, bx in zip(specs, thetas, boxes)]
+    cg = ComposedGradient(sp, zs, lik_rank_cap)
+    ll = cg.forward()
+    cg.reverse()
+    return ll, cg.theta_grad(np.asarray(thetas, dtype=np.float64), h_rel), cg

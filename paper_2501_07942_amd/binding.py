@@ -80,6 +80,14 @@ def _load():
         "tt_adjoint_workspace": (S, [I, I, I]),
         "tt_round_adjoint_workspace": (S, [I, P, P]),
         "tt_round_adjoint": (I, [I, P, P, P, P, P, S, P]),
+        "tt_prior": (I, [I, P, P, P, P, P, S, P]),
+        "tt_likelihood": (I, [I, P, P, P, I, P, I, P, S, P]),
+        "tt_likelihood_dense": (I, [I, P, P, P, I, P, P, S, P]),
+        "tt_likelihood_adjoint_workspace": (S, [I, P, P, P]),
+        "tt_likelihood_adjoint": (I, [I, P, P, P, P, P, P, S, P]),
+        "tt_adjoint_axpy": (I, [I, D, P, P, P, S, P]),
+        "tt_adjoint_inner": (I, [I, P, P, P, P, S, P]),
+        "tt_align_signs": (I, [I, P, P, P, S, P]),
         "tt_predict_adjoint": (I, [I, P, P, P, P, P, P, S, P]),
         "tt_hadamard_adjoint": (I, [I, P, P, P, P, P, P, S, P]),
         "tt_normalize_adjoint": (I, [I, P, P, P, P, P, S, P]),
@@ -102,7 +110,9 @@ EXPORTED = ("tt_train_elems", "tt_last_error", "tt_version", "tt_kernel_build_wo
             "tt_profile_end", "tt_set_predict_mode", "tt_get_predict_mode", "tt_filter_graph_create",
             "tt_filter_graph_launch", "tt_filter_graph_destroy", "tt_autotune_prediction",
             "tt_adjoint_workspace", "tt_predict_adjoint", "tt_hadamard_adjoint", "tt_normalize_adjoint",
-            "tt_round_adjoint_workspace", "tt_round_adjoint")
+            "tt_round_adjoint_workspace", "tt_round_adjoint", "tt_prior", "tt_likelihood", "tt_likelihood_dense",
+            "tt_likelihood_adjoint_workspace", "tt_likelihood_adjoint", "tt_adjoint_axpy",
+            "tt_adjoint_inner", "tt_align_signs")
 
 PREDICT_DIRECT, PREDICT_FFT, PREDICT_UNFUSED, PREDICT_DIRECT_VALU = 0, 1, 2, 3
 
@@ -358,6 +368,76 @@ def tt_round_adjoint(a: Sequence[DeviceTT], y: Sequence[DeviceTT], y_bar: Sequen
     ws = _ws(nbytes)
     _check(LIB.tt_round_adjoint(B, aa, yy, _arr([t.struct() for t in y_bar]), _arr([t.struct() for t in a_bar]),
                                 ws.data_ptr(), ws.numel(), _stream()), "tt_round_adjoint")
+
+
+def tt_prior(grids: Sequence[Grid], m0: np.ndarray, p0_diag: np.ndarray, out: Sequence[DeviceTT]):
+    B = len(out)
+    d = out[0].d
+    m = np.ascontiguousarray(np.asarray(m0, dtype=np.float64).reshape(B * d))
+    p = np.ascontiguousarray(np.asarray(p0_diag, dtype=np.float64).reshape(B * d))
+    ws = _ws(2 * B * 4096 + 4096)
+    _check(LIB.tt_prior(B, _arr(list(grids)), m.ctypes.data_as(C.c_void_p), p.ctypes.data_as(C.c_void_p),
+                        _arr([t.struct() for t in out]), ws.data_ptr(), ws.numel(), _stream()), "tt_prior")
+
+
+def tt_likelihood(grids: Sequence[Grid], meas: Sequence[Meas], z, l_out: Sequence[DeviceTT], lik_rank_cap: int):
+    """z: float64 device tensor [B, zdim]."""
+    B = len(l_out)
+    g, m = _arr(list(grids)), _arr(list(meas))
+    ls = _arr([t.struct() for t in l_out])
+    nbytes = LIB.tt_update_workspace(B, g, m, ls, ls, int(lik_rank_cap))
+    if nbytes == 0:
+        _check(ERR_ARG, "tt_update_workspace")
+    ws = _ws(nbytes)
+    _check(LIB.tt_likelihood(B, g, m, z.data_ptr(), int(z.shape[1]), ls, int(lik_rank_cap), ws.data_ptr(),
+                             ws.numel(), _stream()), "tt_likelihood")
+
+
+def tt_likelihood_dense(grids: Sequence[Grid], meas: Sequence[Meas], z, p_out: Sequence[DeviceTT]):
+    """The likelihood before the range block's SVD (bond 1 of full rank n[1]
+    for the range model).  z: float64 device tensor [B, zdim]."""
+    B = len(p_out)
+    g, m = _arr(list(grids)), _arr(list(meas))
+    ps = _arr([t.struct() for t in p_out])
+    nbytes = LIB.tt_update_workspace(B, g, m, ps, ps, 1)
+    if nbytes == 0:
+        _check(ERR_ARG, "tt_update_workspace")
+    ws = _ws(nbytes)
+    _check(LIB.tt_likelihood_dense(B, g, m, z.data_ptr(), int(z.shape[1]), ps, ws.data_ptr(), ws.numel(),
+                                   _stream()), "tt_likelihood_dense")
+
+
+def tt_likelihood_adjoint(meas: Sequence[Meas], p: Sequence[DeviceTT], l: Sequence[DeviceTT],
+                          l_bar: Sequence[DeviceTT], p_bar: Sequence[DeviceTT]):
+    B = len(p)
+    m = _arr(list(meas))
+    pp, ll = _arr([t.struct() for t in p]), _arr([t.struct() for t in l])
+    nbytes = LIB.tt_likelihood_adjoint_workspace(B, m, pp, ll)
+    if nbytes == 0:
+        _check(ERR_ARG, "tt_likelihood_adjoint_workspace")
+    ws = _ws(nbytes)
+    _check(LIB.tt_likelihood_adjoint(B, m, pp, ll, _arr([t.struct() for t in l_bar]),
+                                     _arr([t.struct() for t in p_bar]), ws.data_ptr(), ws.numel(), _stream()),
+           "tt_likelihood_adjoint")
+
+
+def tt_adjoint_axpy(alpha: float, x: Sequence[DeviceTT], y: Sequence[DeviceTT]):
+    ws = _adj_ws(list(x))
+    _check(LIB.tt_adjoint_axpy(len(x), float(alpha), _arr([t.struct() for t in x]), _arr([t.struct() for t in y]),
+                               ws.data_ptr(), ws.numel(), _stream()), "tt_adjoint_axpy")
+
+
+def tt_adjoint_inner(a_bar: Sequence[DeviceTT], b: Sequence[DeviceTT], out):
+    """out: float64 device tensor [B]."""
+    ws = _adj_ws(list(a_bar))
+    _check(LIB.tt_adjoint_inner(len(b), _arr([t.struct() for t in a_bar]), _arr([t.struct() for t in b]),
+                                out.data_ptr(), ws.data_ptr(), ws.numel(), _stream()), "tt_adjoint_inner")
+
+
+def tt_align_signs(ref: Sequence[DeviceTT], t: Sequence[DeviceTT]):
+    ws = _adj_ws(list(ref))
+    _check(LIB.tt_align_signs(len(t), _arr([x.struct() for x in ref]), _arr([x.struct() for x in t]),
+                              ws.data_ptr(), ws.numel(), _stream()), "tt_align_signs")
 
 
 def workspace_bytes(specs: Sequence[FilterSpec], kernels: Sequence[DeviceTT], precision: int) -> int:

@@ -12,6 +12,7 @@
 #pragma once
 
 #include "common.h"
+#include "linalg.h"
 
 namespace ttg {
 
@@ -278,6 +279,301 @@ __global__ void normalize_adj_init_kernel(const DevTT* __restrict__ xt, const De
   }
   *Xb.log_scale = log_mass_bar ? log_mass_bar[f] : 0.0;
   *Xb.status = bad ? TT_STATUS_CAPACITY : 0;
+}
+
+// y += alpha x for adjoint trains of the same layout and ranks (cores and
+// the log-scale adjoint)
+__global__ void __launch_bounds__(256) adj_axpy_kernel(const DevTT* __restrict__ xs, const DevTT* __restrict__ ys,
+                                                       double alpha) {
+  const int f = blockIdx.z, k = blockIdx.y;
+  const DevTT &X = xs[f], &Y = ys[f];
+  if (k >= X.d) return;
+  bool same = true;
+  for (int j = 0; j <= X.d; ++j) same = same && X.ranks[j] == Y.ranks[j];
+  if (!same) {
+    if (blockIdx.x == 0 && threadIdx.x == 0 && k == 0) set_status(Y.status, TT_STATUS_CAPACITY);
+    return;
+  }
+  const long long tot = (long long)X.ranks[k] * X.n[k] * X.ranks[k + 1];
+  const double* xc = core_ptr<double>(X, k);
+  double* yc = core_ptr<double>(Y, k);
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < tot; e += (long long)gridDim.x * blockDim.x)
+    yc[e] += alpha * xc[e];
+  if (k == 0 && blockIdx.x == 0 && threadIdx.x == 0) *Y.log_scale += alpha * *X.log_scale;
+}
+
+// <Abar, B> = sum over cores of the stored entries + log-scale product, over
+// the ranks the two trains share (index ranges beyond the smaller rank at a
+// bond are skipped).  One workgroup per filter, fixed summation order.
+__global__ void __launch_bounds__(256) adj_inner_kernel(const DevTT* __restrict__ as, const DevTT* __restrict__ bs,
+                                                        double* __restrict__ out) {
+  const int f = blockIdx.x;
+  const DevTT &A = as[f], &Bt = bs[f];
+  __shared__ double red[4];
+  double acc = 0.0;
+  for (int k = 0; k < A.d; ++k) {
+    const int ra0 = A.ranks[k], ra1 = A.ranks[k + 1], rb0 = Bt.ranks[k], rb1 = Bt.ranks[k + 1], n = A.n[k];
+    const int r0 = min(ra0, rb0), r1 = min(ra1, rb1);
+    const double* ac = core_ptr<double>(A, k);
+    const double* bc = core_ptr<double>(Bt, k);
+    const long long tot = (long long)r0 * n * r1;
+    for (long long e = threadIdx.x; e < tot; e += blockDim.x) {
+      const int a = (int)(e / ((long long)n * r1));
+      const int rem = (int)(e - (long long)a * n * r1);
+      const int i = rem / r1, b = rem - (rem / r1) * r1;
+      acc += ac[((long long)a * n + i) * ra1 + b] * bc[((long long)a * n + i) * rb1 + b];
+    }
+  }
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) out[f] = acc + *A.log_scale * *Bt.log_scale;
+}
+
+// Alignment of a train T to a reference R of the same construction (a
+// truncated-SVD build at nearby parameters), bond by bond from the left: the
+// bond basis of T is rotated by the orthogonal polar factor O of the cosine
+// matrix M(c, c') = <r_c, t_c'> / (|r_c| |t_c'|) between the columns of the
+// left unfoldings of core k (T_k <- T_k O^T, T_{k+1} <- O T_{k+1}; the tensor
+// is unchanged).  This removes sign flips and rotations among nearly equal
+// singular values, which are choices of the build, not changes of the
+// tensor.  The polar factor comes from a Jacobi SVD of the stacked matrix
+// [M; I] (its lower block accumulates V): O = U V^T.  A bond whose cosine
+// matrix has a singular value below 1e-6 (no counterpart) is left as is.
+#define ALIGN_RMAX 64
+
+// stacked [M; I] (2r x r, row-major) for bond k; r = the common bond rank
+__global__ void __launch_bounds__(256) align_cos_kernel(const DevTT* __restrict__ refs, const DevTT* __restrict__ ts,
+                                                        int k, double* __restrict__ buf, int* __restrict__ rbuf) {
+  const int f = blockIdx.x;
+  const DevTT &R = refs[f], &T = ts[f];
+  double* X = buf + (long long)f * 2 * ALIGN_RMAX * ALIGN_RMAX;
+  __shared__ double nr[ALIGN_RMAX], nt[ALIGN_RMAX];
+  __shared__ double red[4];
+  const int rr0 = R.ranks[k], rr1 = R.ranks[k + 1], rt0 = T.ranks[k], rt1 = T.ranks[k + 1], n = T.n[k];
+  const int r = min(min(rr1, rt1), ALIGN_RMAX), r0 = min(rr0, rt0);
+  const long long rows = (long long)r0 * n;
+  const double* rc = core_ptr<double>(R, k);
+  const double* tc = core_ptr<double>(T, k);
+  for (int c = 0; c < r; ++c) {
+    double a = 0.0, b = 0.0;
+    for (long long e = threadIdx.x; e < rows; e += blockDim.x) {
+      a += rc[e * rr1 + c] * rc[e * rr1 + c];
+      b += tc[e * rt1 + c] * tc[e * rt1 + c];
+    }
+    a = block_sum(a, red);
+    b = block_sum(b, red);
+    if (threadIdx.x == 0) {
+      nr[c] = a > 0.0 ? 1.0 / sqrt(a) : 0.0;
+      nt[c] = b > 0.0 ? 1.0 / sqrt(b) : 0.0;
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < r * r; e += blockDim.x) {
+    const int c = e / r, c2 = e - (e / r) * r;
+    double s = 0.0;
+    for (long long w = 0; w < rows; ++w) s += rc[w * rr1 + c] * tc[w * rt1 + c2];
+    X[(long long)c * r + c2] = s * nr[c] * nt[c2];
+    X[(long long)(r + c) * r + c2] = c == c2 ? 1.0 : 0.0;
+  }
+  if (threadIdx.x == 0) rbuf[f] = r;
+}
+
+struct FAlignJacobi {
+  double* buf;
+  const int* rbuf;
+  double* work;
+  double* sigma;
+  double* usv;
+  __device__ bool operator()(int f, JacobiArgs& J) const {
+    const int r = rbuf[f];
+    J.rows = 2 * r;
+    J.ncols = r;
+    J.tol2 = 1e-30;
+    J.x = buf + (long long)f * 2 * ALIGN_RMAX * ALIGN_RMAX;
+    J.ldx = r;
+    J.work = work + (long long)f * 2 * ALIGN_RMAX * ALIGN_RMAX;
+    J.sigma = sigma + (long long)f * ALIGN_RMAX;
+    J.usv = usv + (long long)f * 2 * ALIGN_RMAX * ALIGN_RMAX;
+    J.ncols_out = nullptr;
+    J.gcap = 2 * r;
+    return r > 0;
+  }
+};
+
+// O = U V^T from the Jacobi output (usv column c = [sigma_c u_c; v_c],
+// column-major ld 2r); T_k <- T_k O^T, T_{k+1} <- O T_{k+1}
+__global__ void __launch_bounds__(256) align_apply_kernel(const DevTT* __restrict__ ts, int k,
+                                                          const double* __restrict__ sigma,
+                                                          const double* __restrict__ usv,
+                                                          const int* __restrict__ rbuf) {
+  const int f = blockIdx.x;
+  const DevTT& T = ts[f];
+  const int r = rbuf[f];
+  if (r <= 0) return;
+  (void)sigma;
+  const double* U = usv + (long long)f * 2 * ALIGN_RMAX * ALIGN_RMAX;
+  __shared__ double O[ALIGN_RMAX * ALIGN_RMAX];
+  __shared__ double tmp[256 / 64 * ALIGN_RMAX];
+  __shared__ double sg[ALIGN_RMAX];
+  // the upper block of column c is sigma_c u_c (sigma_c a singular value of M)
+  for (int c = threadIdx.x; c < r; c += blockDim.x) {
+    double s = 0.0;
+    for (int a = 0; a < r; ++a) s += U[(long long)c * 2 * r + a] * U[(long long)c * 2 * r + a];
+    sg[c] = sqrt(s);
+  }
+  __syncthreads();
+  for (int c = 0; c < r; ++c)
+    if (!(sg[c] > 1e-6)) return;  // same decision in every thread
+  for (int e = threadIdx.x; e < r * r; e += blockDim.x) {
+    const int a = e / r, b = e - (e / r) * r;
+    double s = 0.0;
+    for (int c = 0; c < r; ++c) s += (U[(long long)c * 2 * r + a] / sg[c]) * U[(long long)c * 2 * r + r + b];
+    O[e] = s;  // O(a, b) = sum_c u_c(a) v_c(b)
+  }
+  __syncthreads();
+  const int rt0 = T.ranks[k], rt1 = T.ranks[k + 1], n = T.n[k];
+  double* tc = core_ptr<double>(T, k);
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  double* tw = tmp + wid * ALIGN_RMAX;
+  // columns of core k: each row (a, i) of the left unfolding, one wavefront per row
+  for (long long row = wid; row < (long long)rt0 * n; row += nw) {
+    double* tr = tc + row * rt1;
+    if (lane < r) tw[lane] = tr[lane];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    double s = 0.0;
+    if (lane < r)
+      for (int c = 0; c < r; ++c) s += tw[c] * O[lane * r + c];  // (T O^T)(row, lane)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    if (lane < r) tr[lane] = s;
+  }
+  // rows of core k+1: each column (i, b) of its right unfolding
+  const int n1 = T.n[k + 1], rt2 = T.ranks[k + 2];
+  double* tn = core_ptr<double>(T, k + 1);
+  const long long ncol = (long long)n1 * rt2;
+  for (long long col = wid; col < ncol; col += nw) {
+    if (lane < r) tw[lane] = tn[(long long)lane * ncol + col];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    double s = 0.0;
+    if (lane < r)
+      for (int c = 0; c < r; ++c) s += O[lane * r + c] * tw[c];  // (O T)(lane, col)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    if (lane < r) tn[(long long)lane * ncol + col] = s;
+  }
+}
+
+}  // namespace ttg
+
+namespace ttg {
+
+// ---------------------------------------------------------------------------
+// Adjoint of the likelihood build (Sec. 2.2 likelihood as a TT).  The
+// (x_1, x_2) range block M (n0 x n1, max-shifted) is truncated by SVD into
+// core 0 = M V_r and core 1 = V_r^T (V_r: leading right singular vectors).
+// Rounding the two-core train A = (M^T, I_{n0}) to rank r yields exactly
+// Y = (V_r, V_r^T M^T), the build's cores transposed and swapped, so the
+// adjoint of the build is the rounding adjoint on A.  The dense train P
+// holds the build's input: core 0 = M (bond 1 of full rank n1), core 1 =
+// the identity, the linear-axis factors and the log-scale as in the build.
+// ---------------------------------------------------------------------------
+struct LikAdjJob {
+  DevTT p, l, lbar, pbar;  // caller's trains
+  DevTT a, y, ybar, abar;  // two-core trains in the workspace (range block only)
+  int range;
+};
+
+// A, Y, Ybar of every range filter (one workgroup per filter)
+__global__ void __launch_bounds__(256) lik_adj_pack_kernel(const LikAdjJob* __restrict__ jobs) {
+  const LikAdjJob& J = jobs[blockIdx.x];
+  if (!J.range) return;
+  const int n0 = J.p.n[0], n1 = J.p.n[1], r = J.l.ranks[1];
+  const double* m = core_ptr<double>(J.p, 0);
+  double* a0 = core_ptr<double>(J.a, 0);
+  double* a1 = core_ptr<double>(J.a, 1);
+  for (int e = threadIdx.x; e < n0 * n1; e += blockDim.x) {
+    const int i = e / n1, j = e - (e / n1) * n1;
+    a0[(long long)j * n0 + i] = m[e];
+  }
+  for (int e = threadIdx.x; e < n0 * n0; e += blockDim.x) a1[e] = (e / n0 == e - (e / n0) * n0) ? 1.0 : 0.0;
+  const double *l0 = core_ptr<double>(J.l, 0), *l1 = core_ptr<double>(J.l, 1);
+  const double *b0 = core_ptr<double>(J.lbar, 0), *b1 = core_ptr<double>(J.lbar, 1);
+  double *y0 = core_ptr<double>(J.y, 0), *y1 = core_ptr<double>(J.y, 1);
+  double *yb0 = core_ptr<double>(J.ybar, 0), *yb1 = core_ptr<double>(J.ybar, 1);
+  for (int e = threadIdx.x; e < n1 * r; e += blockDim.x) {  // Y_0(j, c) = L_1(c, j)
+    const int j = e / r, c = e - (e / r) * r;
+    y0[e] = l1[(long long)c * n1 + j];
+    yb0[e] = b1[(long long)c * n1 + j];
+  }
+  for (int e = threadIdx.x; e < r * n0; e += blockDim.x) {  // Y_1(c, i) = L_0(i, c)
+    const int c = e / n0, i = e - (e / n0) * n0;
+    y1[e] = l0[(long long)i * r + c];
+    yb1[e] = b0[(long long)i * r + c];
+  }
+  if (threadIdx.x == 0) {
+    const int ra[3] = {1, n0, 1}, ry[3] = {1, r, 1};
+    for (int j = 0; j < 3; ++j) {
+      J.a.ranks[j] = ra[j];
+      J.abar.ranks[j] = ra[j];
+      J.y.ranks[j] = ry[j];
+      J.ybar.ranks[j] = ry[j];
+    }
+    *J.a.log_scale = *J.y.log_scale = *J.ybar.log_scale = *J.abar.log_scale = 0.0;
+    *J.a.status = *J.y.status = *J.ybar.status = *J.abar.status = 0;
+  }
+}
+
+// Pbar: core 0 = Abar_0 transposed (range) or Lbar_0, core 1 zero (the build
+// reads the identity core of P not at all) or Lbar_1, linear factors and the
+// log-scale adjoint passed through (the build copies them).
+__global__ void __launch_bounds__(256) lik_adj_unpack_kernel(const LikAdjJob* __restrict__ jobs) {
+  const LikAdjJob& J = jobs[blockIdx.x];
+  const int d = J.p.d;
+  bool ok = true;
+  for (int j = 0; j <= d; ++j) ok = ok && J.lbar.ranks[j] == J.l.ranks[j];
+  for (int k = 0; k < d; ++k) {
+    const int n = J.p.n[k];
+    double* o = core_ptr<double>(J.pbar, k);
+    if (J.range && k == 0) {
+      const int n1 = J.p.n[1];
+      const double* ab = core_ptr<double>(J.abar, 0);
+      for (int e = threadIdx.x; e < n * n1; e += blockDim.x) {
+        const int i = e / n1, j = e - (e / n1) * n1;
+        o[e] = ab[(long long)j * n + i];
+      }
+    } else if (J.range && k == 1) {
+      for (int e = threadIdx.x; e < n * n; e += blockDim.x) o[e] = 0.0;
+    } else {
+      const double* lb = core_ptr<double>(J.lbar, k);
+      for (int e = threadIdx.x; e < n; e += blockDim.x) o[e] = lb[e];
+    }
+  }
+  if (threadIdx.x == 0) {
+    for (int j = 0; j <= d; ++j) J.pbar.ranks[j] = J.p.ranks[j];
+    *J.pbar.log_scale = *J.lbar.log_scale;
+    *J.pbar.status = ok ? 0 : TT_STATUS_CAPACITY;
+  }
+}
+
+// the dense train P of every range filter: core 0 = the block, core 1 = I
+__global__ void __launch_bounds__(256) lik_dense_pack_kernel(const DevTT* __restrict__ ps,
+                                                             const FilterConst* __restrict__ fc,
+                                                             const double* __restrict__ mbuf, long long mstride) {
+  const int f = blockIdx.x;
+  if (fc[f].meas_kind != 1) return;
+  const DevTT& P = ps[f];
+  const int n0 = P.n[0], n1 = P.n[1];
+  const double* m = mbuf + f * mstride;
+  double* c0 = core_ptr<double>(P, 0);
+  double* c1 = core_ptr<double>(P, 1);
+  for (int e = threadIdx.x; e < n0 * n1; e += blockDim.x) c0[e] = m[e];
+  for (int e = threadIdx.x; e < n1 * n1; e += blockDim.x) c1[e] = (e / n1 == e - (e / n1) * n1) ? 1.0 : 0.0;
+  if (threadIdx.x == 0) P.ranks[1] = n1;
 }
 
 }  // namespace ttg

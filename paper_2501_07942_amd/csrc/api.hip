@@ -1251,8 +1251,9 @@ tt_status tt_round(int32_t batch, const tt_train* t_in, const tt_train* t_out, d
 // ===========================================================================
 namespace ttg {
 
+#define RADJ_PLANES 4
 struct RadjCore {  // per filter and core k (0-based)
-  double *G, *T, *W, *U, *c, *N, *lfac, *lwork, *M, *jw, *sig, *usv, *Ud, *Fm, *Gbar;
+  double *G, *T, *W, *U, *c, *N, *lfac, *lwork, *gdd, *M, *jw, *sig, *usv, *Ud, *Fm, *Gbar, *D, *YBt;
   int* piv;
   int* prank;
 };
@@ -1260,7 +1261,7 @@ struct RadjCore {  // per filter and core k (0-based)
 struct RadjFilter {
   int d, n[TT_MAXD], Ra[TT_MAXD + 1], ry[TT_MAXD + 1];
   RadjCore c[TT_MAXD];
-  double *L, *kappa, *Lbar, *Wb0, *Wb1, *Nbar, *Ubar, *P1, *P2, *WG, *XtN, *XtNG, *Gs, *T2, *Tg;
+  double *L, *kappa, *Lbar, *Wb0, *Wb1, *Nbar, *Ubar, *P1, *P2, *WG, *XtN, *XtNG, *Gs, *T2, *Tg, *one;
 };
 
 // lays out the buffers of every filter in the arena (sizes from ranks Ra, ry)
@@ -1272,6 +1273,11 @@ static void radj_layout(Arena& ar, RadjFilter& F) {
     RadjCore& C = F.c[k];
     C.G = ar.take<double>(Rk1 * Rk1);
     C.Gbar = ar.take<double>(Rk1 * Rk1);
+    C.lfac = ar.take<double>(Rk1 * Rk1);
+    C.lwork = ar.take<double>(2 * Rk1 * Rk1);
+    C.piv = ar.take<int>(Rk1);
+    C.prank = ar.take<int>(1);
+    C.gdd = ar.take<double>(2 * RADJ_PLANES * Rk * Rk);  // double-double Gram planes of G_{k-1}
     C.W = ar.take<double>(std::max(1LL, rk * Rk));
     tmax = std::max(tmax, Rk * n * Rk1);
     rmax = std::max(rmax, std::max(rk, rk1));
@@ -1286,11 +1292,9 @@ static void radj_layout(Arena& ar, RadjFilter& F) {
       C.U = ar.take<double>(p * rk1);
       C.c = ar.take<double>(1);
       C.N = ar.take<double>(p * Rk1);
-      C.lfac = ar.take<double>(Rk1 * Rk1);
-      C.lwork = ar.take<double>(Rk1 * Rk1);
-      C.piv = ar.take<int>(Rk1);
-      C.prank = ar.take<int>(1);
       C.M = ar.take<double>(p * Rk1);
+      C.D = ar.take<double>(rk1);
+      C.YBt = ar.take<double>(p * rk1);
       C.jw = ar.take<double>(p * Rk1);
       C.sig = ar.take<double>(Rk1);
       C.usv = ar.take<double>(p * Rk1);
@@ -1314,6 +1318,7 @@ static void radj_layout(Arena& ar, RadjFilter& F) {
   F.Gs = ar.take<double>(Rmax * Rmax);
   F.T2 = ar.take<double>(tmax);
   F.Tg = ar.take<double>(tmax);
+  F.one = ar.take<double>(1);
 }
 
 struct RadjRun {
@@ -1322,6 +1327,8 @@ struct RadjRun {
   EJob* de;
   PcholArgs* dp;
   JacobiArgs* dj;
+  GramArgs* dga;
+  AJob* daj;
   int jcap;
   std::vector<GJob> g;
   std::vector<EJob> e;
@@ -1373,6 +1380,9 @@ struct RadjRun {
       const long long n = j.op == EJ_SYM ? (long long)j.r * j.r : j.cnt;
       TT_TRY(check(inside(j.out, n - 1), "elementwise out"));
       if (j.op == EJ_SCALE || j.op == EJ_SYM) TT_TRY(check(inside(j.x, n - 1), "elementwise x"));
+      if (j.op == EJ_DDHI) TT_TRY(check(inside(j.x, 2 * n - 1), "elementwise x"));
+      if (j.op == EJ_COPY || j.op == EJ_ROWFLIP) TT_TRY(check(inside(j.x, n - 1), "elementwise x"));
+      if (j.op == EJ_ROWFLIP) TT_TRY(check(j.ld > 0 && inside(j.y, (n - 1) / j.ld), "elementwise y"));
       if (j.op == EJ_SCALE) TT_TRY(check(inside(j.s, 0), "elementwise s"));
     }
     long long mx = 1;
@@ -1423,6 +1433,14 @@ struct RadjRun {
   }
 };
 
+struct FAdjGram {
+  const GramArgs* a;
+  __device__ bool operator()(int b, GramArgs& g) const {
+    g = a[b];
+    return g.M > 0;
+  }
+};
+
 static long long radj_bytes(const RadjFilter& proto) {
   RadjFilter F = proto;
   Arena ar(nullptr, 0);
@@ -1437,7 +1455,9 @@ extern "C" {
 size_t tt_round_adjoint_workspace(int32_t batch, const tt_train* a, const tt_train* y) {
   if (batch < 1 || !a || !y) return 0;
   const int dd = a[0].d;
-  size_t total = (size_t)batch * (3 * dd + 8) * (sizeof(GJob) + sizeof(EJob) + sizeof(PcholArgs) + sizeof(JacobiArgs)) +
+  size_t total = (size_t)batch * (3 * dd + 8) *
+                     (sizeof(GJob) + sizeof(EJob) + sizeof(PcholArgs) + sizeof(JacobiArgs) + sizeof(GramArgs) +
+                      sizeof(AJob)) +
                  8192;
   for (int b = 0; b < batch; ++b) {
     RadjFilter F;
@@ -1501,6 +1521,8 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
   R.de = ar.take<EJob>(R.jcap);
   R.dp = ar.take<PcholArgs>((size_t)batch * d);
   R.dj = ar.take<JacobiArgs>((size_t)batch * d);
+  R.dga = ar.take<GramArgs>((size_t)batch);
+  R.daj = ar.take<AJob>((size_t)batch);
   int Rmax = 1;
   for (int b = 0; b < batch; ++b) {
     RadjFilter& f = F[b];
@@ -1566,29 +1588,74 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
       const long long asz = (long long)f.Ra[k] * f.n[k] * f.Ra[k + 1];
       R.ej(EJ_FILL, asz, nullptr, nullptr, abcore(b, k), nullptr, nullptr);
       R.ej(EJ_FILL, (long long)f.Ra[k + 1] * f.Ra[k + 1], nullptr, nullptr, f.c[k].Gbar, nullptr, nullptr);
-      if (k < d - 1)
-        R.ej(EJ_FILL, (long long)f.Ra[k + 1] * f.Ra[k + 1], nullptr, nullptr, f.c[k].lfac, nullptr, nullptr);
+      R.ej(EJ_FILL, (long long)f.Ra[k + 1] * f.Ra[k + 1], nullptr, nullptr, f.c[k].lfac, nullptr, nullptr);
     }
     R.ej(EJ_ONE, 1, nullptr, nullptr, f.c[d - 1].G, nullptr, nullptr);
     R.ej(EJ_ONE, 1, nullptr, nullptr, f.c[0].W, nullptr, nullptr);
+    R.ej(EJ_ONE, 1, nullptr, nullptr, f.one, nullptr, nullptr);
     TT_TRY(R.elem());
   }
-  // phase 1: right-part Grams, G_{k-1} = sum_i A_k(:,i,:) G_k A_k(:,i,:)^T
-  for (int k = d - 1; k >= 1; --k) {
-    for (int b = 0; b < batch; ++b) {
-      RadjFilter& f = F[b];
-      const int R0 = f.Ra[k], R1 = f.Ra[k + 1], n = f.n[k];
-      R.mm(R0 * n, R1, R1, acore(b, k), R1, 1, f.c[k].G, R1, 1, f.Tg, R1, 1.0, 0.0);
-    }
-    TT_TRY(R.gemm());
-    for (int b = 0; b < batch; ++b) {
-      RadjFilter& f = F[b];
-      const int R0 = f.Ra[k], R1 = f.Ra[k + 1], n = f.n[k];
-      R.mm(R0, R0, n * R1, f.Tg, (long long)n * R1, 1, acore(b, k), 1, (long long)n * R1, f.c[k - 1].G, R0, 1.0, 0.0);
-    }
-    TT_TRY(R.gemm());
+  // phase 1: right-part Grams and their factors, from the right: with
+  // G_k = F_k F_k^T, Z_k = A_k x_3 F_k and G_{k-1} = Z_k Z_k^T accumulated in
+  // double-double (the forward rounding's accuracy), F_{k-1} by pivoted
+  // Cholesky of G_{k-1}; G_{k-1} in FP64 for the products below
+  for (int b = 0; b < batch; ++b) {
+    RadjFilter& f = F[b];
+    R.ej(EJ_ONE, 1, nullptr, nullptr, f.c[d - 1].lfac, nullptr, nullptr);
   }
-  // phase 2: U_k = Y_k / c_k, N_k = W_k x_1 A_k, W_{k+1} = U_k^T N_k, L = W_{d-1} x_1 A_{d-1}
+  TT_TRY(R.elem());
+  for (int k = d - 1; k >= 1; --k) {
+    int mcap = 1;
+    long long tcap = 1;
+    std::vector<GramArgs> gj;
+    std::vector<PcholArgs> pj;
+    for (int b = 0; b < batch; ++b) {
+      RadjFilter& f = F[b];
+      const int R0 = f.Ra[k], R1 = f.Ra[k + 1], n = f.n[k];
+      R.mm(R0 * n, R1, R1, acore(b, k), R1, 1, f.c[k].lfac, R1, 1, f.Tg, R1, 1.0, 0.0);
+      GramArgs ga;
+      memset(&ga, 0, sizeof(ga));
+      ga.M = R0;
+      ga.T = n * R1;
+      ga.x = f.Tg;
+      ga.sa = (long long)n * R1;
+      ga.st = 1;
+      ga.out = f.c[k].gdd;
+      ga.gcap = R0;
+      ga.splits = RADJ_PLANES;
+      gj.push_back(ga);
+      TT_TRY(R.check(R.inside(f.c[k].gdd, 2LL * RADJ_PLANES * R0 * R0 - 1) &&
+                         R.inside(f.Tg, (long long)R0 * n * R1 - 1),
+                     "gram"));
+      PcholArgs pa;
+      memset(&pa, 0, sizeof(pa));
+      pa.M = R0;
+      pa.g = f.c[k].gdd;
+      pa.lwork = f.c[k - 1].lwork;
+      pa.lfac = f.c[k - 1].lfac;
+      pa.piv = f.c[k - 1].piv;
+      pa.rank_out = f.c[k - 1].prank;
+      pa.gcap = R0;
+      pa.rmax = R0;
+      pa.tau2 = 1e-30;
+      pj.push_back(pa);
+      mcap = std::max(mcap, R0);
+      tcap = std::max(tcap, (long long)n * R1);
+    }
+    TT_TRY(R.gemm());
+    TT_TRY(upload(R.dga, gj, st));
+    TT_TRY((launch_gram<double, AccDD>(FAdjGram{R.dga}, batch, mcap, tcap, RADJ_PLANES, st)));
+    TT_TRY(upload(R.dp, pj, st));
+    TT_TRY((launch_pchol<AccDD, FAdjPchol>(FAdjPchol{R.dp}, batch, mcap, st)));
+    for (int b = 0; b < batch; ++b) {
+      RadjFilter& f = F[b];
+      const int R0 = f.Ra[k];
+      R.ej(EJ_DDHI, (long long)R0 * R0, f.c[k].gdd, nullptr, f.c[k - 1].G, nullptr, nullptr);
+    }
+    TT_TRY(R.elem());
+  }
+  // the forward's scaled kept vectors U_fwd = Y_k / c_k (compared with the
+  // adjoint's own below)
   for (int b = 0; b < batch; ++b) {
     RadjFilter& f = F[b];
     for (int k = 0; k < d - 1; ++k)
@@ -1602,6 +1669,16 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
     TTG_LAUNCH_CHECK("radj_scalar_kernel");
     R.e.clear();
   }
+  // phase 2/3, core by core: N_k = W_k x_1 A_k, M_k = N_k F_k and its
+  // Jacobi SVD; the kept vectors of that SVD (signs matched to the forward's
+  // output) become U_k, and W_{k+1} = U_k^T N_k
+  int gmax = 1;
+  for (int b = 0; b < batch; ++b)
+    for (int k = 0; k < d; ++k) gmax = std::max(gmax, F[b].Ra[k + 1]);
+  if (gmax > 1024) {
+    set_error("tt_round_adjoint: rank above 1024");
+    return TT_ERR_SHAPE;
+  }
   for (int k = 0; k < d - 1; ++k) {
     for (int b = 0; b < batch; ++b) {
       RadjFilter& f = F[b];
@@ -1611,12 +1688,64 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
     TT_TRY(R.gemm());
     for (int b = 0; b < batch; ++b) {
       RadjFilter& f = F[b];
-      const int R1 = f.Ra[k + 1], n = f.n[k], r0 = f.ry[k], r1 = f.ry[k + 1];
-      const int p = r0 * n;
+      const int R1 = f.Ra[k + 1], p = f.ry[k] * f.n[k];
+      R.mm(p, R1, R1, f.c[k].N, R1, 1, f.c[k].lfac, R1, 1, f.c[k].M, R1, 1.0, 0.0);
+    }
+    TT_TRY(R.gemm());
+    std::vector<JacobiArgs> jj;
+    std::vector<AJob> aj;
+    for (int b = 0; b < batch; ++b) {
+      RadjFilter& f = F[b];
+      const int R1 = f.Ra[k + 1], r1 = f.ry[k + 1], p = f.ry[k] * f.n[k];
+      JacobiArgs ja;
+      memset(&ja, 0, sizeof(ja));
+      ja.rows = p;
+      ja.ncols = R1;
+      ja.tol2 = 1e-30;
+      ja.x = f.c[k].M;
+      ja.ldx = R1;
+      ja.work = f.c[k].jw;
+      ja.sigma = f.c[k].sig;
+      ja.usv = f.c[k].usv;
+      ja.gcap = p;
+      TT_TRY(R.check(R.inside(ja.x, (long long)(ja.rows - 1) * ja.ldx + ja.ncols - 1) &&
+                         R.inside(ja.work, (long long)ja.ncols * ja.gcap - 1) &&
+                         R.inside(ja.usv, (long long)ja.ncols * ja.gcap - 1) && R.inside(ja.sigma, ja.ncols - 1),
+                     "jacobi"));
+      jj.push_back(ja);
+      AJob a1;
+      memset(&a1, 0, sizeof(a1));
+      a1.usv = f.c[k].usv;
+      a1.sig = f.c[k].sig;
+      a1.U = f.c[k].U;
+      a1.ybt = f.c[k].YBt;
+      a1.ybar = ybcore(b, k);
+      a1.c = f.c[k].c;
+      a1.dprev = k == 0 ? f.one : f.c[k - 1].D;
+      a1.dk = f.c[k].D;
+      a1.p = p;
+      a1.r = r1;
+      a1.n = f.n[k];
+      a1.ldu = p;
+      TT_TRY(R.check(r1 <= R1 && R.inside(a1.U, (long long)p * r1 - 1) && R.inside(a1.ybt, (long long)p * r1 - 1) &&
+                         R.inside(a1.ybar, (long long)p * r1 - 1) && R.inside(a1.dk, r1 - 1) &&
+                         R.inside(a1.dprev, f.ry[k] - 1),
+                     "adopt"));
+      aj.push_back(a1);
+    }
+    TT_TRY(upload(R.dj, jj, st));
+    TT_TRY(launch_jacobi(FAdjJacobi{R.dj}, batch, st));
+    TT_TRY(upload(R.daj, aj, st));
+    hipLaunchKernelGGL(radj_adopt_kernel, dim3(batch), dim3(256), 0, st, R.daj);
+    TTG_LAUNCH_CHECK("radj_adopt_kernel");
+    for (int b = 0; b < batch; ++b) {
+      RadjFilter& f = F[b];
+      const int R1 = f.Ra[k + 1], r1 = f.ry[k + 1], p = f.ry[k] * f.n[k];
       R.mm(r1, R1, p, f.c[k].U, 1, r1, f.c[k].N, R1, 1, f.c[k + 1].W, R1, 1.0, 0.0);
     }
     TT_TRY(R.gemm());
   }
+  // last core: L = W_{d-1} x_1 A_{d-1}; Y_{d-1} (left signs matched) = kappa L
   for (int b = 0; b < batch; ++b) {
     RadjFilter& f = F[b];
     const int R0 = f.Ra[d - 1], n = f.n[d - 1], r0 = f.ry[d - 1];
@@ -1625,77 +1754,34 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
   TT_TRY(R.gemm());
   for (int b = 0; b < batch; ++b) {
     RadjFilter& f = F[b];
-    R.ej(1, (long long)f.ry[d - 1] * f.n[d - 1], ycore(b, d - 1), f.L, nullptr, f.kappa, nullptr);
+    const int n = f.n[d - 1], r0 = f.ry[d - 1];
+    R.ej(EJ_ROWFLIP, (long long)r0 * n, ycore(b, d - 1), d > 1 ? f.c[d - 2].D : f.one, f.Lbar, nullptr, nullptr,
+         0, 0, 0, n);
+  }
+  TT_TRY(R.elem());
+  for (int b = 0; b < batch; ++b) {
+    RadjFilter& f = F[b];
+    R.ej(1, (long long)f.ry[d - 1] * f.n[d - 1], f.Lbar, f.L, nullptr, f.kappa, nullptr);
   }
   TT_TRY(check_scalar_jobs(0));
   TT_TRY(upload(R.de, R.e, st));
   hipLaunchKernelGGL(radj_scalar_kernel, dim3((int)R.e.size()), dim3(256), 0, st, R.de);
   TTG_LAUNCH_CHECK("radj_scalar_kernel");
   R.e.clear();
-  // phase 3: F_k (pivoted Cholesky of G_k), M_k = N_k F_k, Jacobi SVD of M_k
+  for (int b = 0; b < batch; ++b) {
+    RadjFilter& f = F[b];
+    const int n = f.n[d - 1], r0 = f.ry[d - 1];
+    R.ej(EJ_ROWFLIP, (long long)r0 * n, ybcore(b, d - 1), d > 1 ? f.c[d - 2].D : f.one, f.Lbar, nullptr, nullptr,
+         0, 0, 0, n);
+  }
+  TT_TRY(R.elem());
+  for (int b = 0; b < batch; ++b) {
+    RadjFilter& f = F[b];
+    R.ej(EJ_SCALE, (long long)f.ry[d - 1] * f.n[d - 1], f.Lbar, nullptr, f.Lbar, nullptr, f.kappa);
+  }
+  TT_TRY(R.elem());
+  // eigen data of every core for the backward sweep
   if (d > 1) {
-    std::vector<PcholArgs> pj;
-    std::vector<JacobiArgs> jj;
-    int gmax = 1, pmax = 1;
-    for (int b = 0; b < batch; ++b) {
-      RadjFilter& f = F[b];
-      for (int k = 0; k < d - 1; ++k) {
-        const int R1 = f.Ra[k + 1];
-        PcholArgs pa;
-        memset(&pa, 0, sizeof(pa));
-        pa.M = R1;
-        pa.g = f.c[k].G;
-        pa.lwork = f.c[k].lwork;
-        pa.lfac = f.c[k].lfac;
-        pa.piv = f.c[k].piv;
-        pa.rank_out = f.c[k].prank;
-        pa.gcap = R1;
-        pa.rmax = R1;
-        pa.tau2 = 1e-24;
-        pj.push_back(pa);
-        gmax = std::max(gmax, R1);
-        const int p = f.ry[k] * f.n[k];
-        pmax = std::max(pmax, p);
-        JacobiArgs ja;
-        memset(&ja, 0, sizeof(ja));
-        ja.rows = p;
-        ja.ncols = R1;
-        ja.tol2 = 1e-30;
-        ja.x = f.c[k].M;
-        ja.ldx = R1;
-        ja.work = f.c[k].jw;
-        ja.sigma = f.c[k].sig;
-        ja.usv = f.c[k].usv;
-        ja.gcap = p;
-        jj.push_back(ja);
-      }
-    }
-    if (gmax > 1024 || (int)pj.size() > batch * d) {
-      set_error("tt_round_adjoint: rank above 1024");
-      return TT_ERR_SHAPE;
-    }
-    for (const auto& pa : pj)
-      TT_TRY(R.check(R.inside(pa.g, (long long)pa.M * pa.gcap - 1) && R.inside(pa.lwork, (long long)pa.M * pa.gcap - 1) &&
-                         R.inside(pa.lfac, (long long)pa.M * pa.gcap - 1),
-                     "pchol"));
-    for (const auto& ja : jj)
-      TT_TRY(R.check(R.inside(ja.x, (long long)(ja.rows - 1) * ja.ldx + ja.ncols - 1) &&
-                         R.inside(ja.work, (long long)ja.ncols * ja.gcap - 1) &&
-                         R.inside(ja.usv, (long long)ja.ncols * ja.gcap - 1) && R.inside(ja.sigma, ja.ncols - 1) &&
-                         ja.rows <= ja.gcap,
-                     "jacobi"));
-    TT_TRY(upload(R.dp, pj, st));
-    TT_TRY((launch_pchol<AccD, FAdjPchol>(FAdjPchol{R.dp}, (int)pj.size(), gmax, st)));
-    for (int b = 0; b < batch; ++b) {
-      RadjFilter& f = F[b];
-      for (int k = 0; k < d - 1; ++k) {
-        const int R1 = f.Ra[k + 1], p = f.ry[k] * f.n[k];
-        R.mm(p, R1, R1, f.c[k].N, R1, 1, f.c[k].lfac, R1, 1, f.c[k].M, R1, 1.0, 0.0);
-      }
-    }
-    TT_TRY(R.gemm());
-    TT_TRY(upload(R.dj, jj, st));
-    TT_TRY(launch_jacobi(FAdjJacobi{R.dj}, (int)jj.size(), st));
     for (int b = 0; b < batch; ++b) {
       RadjFilter& f = F[b];
       for (int k = 0; k < d - 1; ++k) {
@@ -1712,11 +1798,6 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
   // phase 4: the left-to-right sweep backwards
   for (int b = 0; b < batch; ++b) {
     RadjFilter& f = F[b];
-    R.ej(EJ_SCALE, (long long)f.ry[d - 1] * f.n[d - 1], ybcore(b, d - 1), nullptr, f.Lbar, nullptr, f.kappa);
-  }
-  TT_TRY(R.elem());
-  for (int b = 0; b < batch; ++b) {
-    RadjFilter& f = F[b];
     const int R0 = f.Ra[d - 1], n = f.n[d - 1], r0 = f.ry[d - 1];
     // Wbar_{d-1} = Lbar A_{d-1}^T, Abar_{d-1} += W_{d-1}^T Lbar
     R.mm(r0, R0, n, f.Lbar, n, 1, acore(b, d - 1), 1, n, f.Wb0, R0, 1.0, 0.0);
@@ -1731,7 +1812,7 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
       RadjFilter& f = F[b];
       const int R1 = f.Ra[k + 1], r1 = f.ry[k + 1], p = f.ry[k] * f.n[k];
       R.mm(p, R1, r1, f.c[k].U, r1, 1, wb_in(f), R1, 1, f.Nbar, R1, 1.0, 0.0);
-      R.ej(EJ_SCALE, (long long)p * r1, ybcore(b, k), nullptr, f.Ubar, nullptr, f.c[k].c);
+      R.ej(EJ_COPY, (long long)p * r1, f.c[k].YBt, nullptr, f.Ubar, nullptr, nullptr);
     }
     TT_TRY(R.gemm());
     TT_TRY(R.elem());
@@ -1752,12 +1833,6 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
       RadjFilter& f = F[b];
       const int r1 = f.ry[k + 1], p = f.ry[k] * f.n[k];
       R.mm(p, r1, r1, f.c[k].U, r1, 1, f.P1, r1, 1, f.Ubar, r1, -1.0, 1.0);
-    }
-    TT_TRY(R.gemm());
-    for (int b = 0; b < batch; ++b) {  // Ubar -= Ud P2
-      RadjFilter& f = F[b];
-      const int R1 = f.Ra[k + 1], r1 = f.ry[k + 1], p = f.ry[k] * f.n[k], nd = R1 - r1;
-      R.mm(p, r1, nd, f.c[k].Ud, nd, 1, f.P2, r1, 1, f.Ubar, r1, -1.0, 1.0);
     }
     TT_TRY(R.gemm());
     for (int b = 0; b < batch; ++b) {  // X = Ubar diag(linv), P2 = P2 o Fm
@@ -2331,7 +2406,9 @@ static tt_status check_like(const tt_train& a, const tt_train& b, const char* wh
 
 size_t tt_adjoint_workspace(int32_t batch, int32_t d, int32_t rcap) {
   if (batch < 1 || d < 1 || rcap < 1) return 0;
-  return (size_t)5 * batch * sizeof(DevTT) + (size_t)batch * (2 * (d + 1) * rcap + 1) * sizeof(double) + 2048;
+  const size_t align = (size_t)batch * (3 * 2 * ALIGN_RMAX * ALIGN_RMAX + ALIGN_RMAX + 1) * sizeof(double);
+  return (size_t)5 * batch * sizeof(DevTT) +
+         std::max((size_t)batch * (2 * (d + 1) * rcap + 1) * sizeof(double), align) + 4096;
 }
 
 tt_status tt_predict_adjoint(int32_t batch, const tt_train* kernels, const tt_train* p_in, const tt_train* c_bar,
@@ -2670,6 +2747,369 @@ static size_t update_ws_bytes(int32_t batch, const tt_grid* grids, const tt_meas
   UpdatePlan u;
   if (update_plan(batch, grids, meas, p_pred, h_out, lik_rank_cap, ar, u) != TT_OK) return 0;
   return ar.used + 256;
+}
+
+tt_status tt_likelihood(int32_t batch, const tt_grid* grids, const tt_meas* meas, const double* z_dev,
+                        int32_t z_stride, const tt_train* l_out, int32_t lik_rank_cap, void* ws, size_t ws_bytes,
+                        void* stream) {
+  if (!z_dev || !ws || !l_out || batch < 1) {
+    set_error("tt_likelihood: bad arguments");
+    return TT_ERR_ARG;
+  }
+  for (int b = 0; b < batch; ++b) {
+    TT_TRY(check_train(&l_out[b], "l_out", TT_F64));
+    for (int j = 0; j <= l_out[b].d; ++j) {
+      const int want = (meas[b].kind == 1 && j == 1) ? std::min(lik_rank_cap, l_out[b].n[1]) : 1;
+      if (l_out[b].cap[j] != want) {
+        set_error("tt_likelihood: l_out capacities must be 1 except cap[1] = min(lik_rank_cap, n[1]) (range)");
+        return TT_ERR_SHAPE;
+      }
+    }
+  }
+  Arena ar(ws, ws_bytes);
+  UpdatePlan u;
+  TT_TRY(update_plan(batch, grids, meas, l_out, l_out, lik_rank_cap, ar, u));
+  if (!ar.fits()) {
+    set_error("tt_likelihood: workspace too small (%zu < %zu)", ws_bytes, ar.used);
+    return TT_ERR_WORKSPACE;
+  }
+  for (int b = 0; b < batch; ++b) u.vl[b] = make_dev(l_out[b]);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  TT_TRY(upload(u.dl, u.vl, st));
+  TT_TRY(upload(u.drs, u.vrs, st));
+  TT_TRY(upload(u.dfc, u.vfc, st));
+  return lik_launch(batch, u.dl, u.drs, u.dfc, z_dev, z_stride, u.mbuf, u.mstride, u.any_range, u.n0max, u.n1max,
+                    u.gcap, u.splits, st);
+}
+
+tt_status tt_likelihood_dense(int32_t batch, const tt_grid* grids, const tt_meas* meas, const double* z_dev,
+                              int32_t z_stride, const tt_train* p_out, void* ws, size_t ws_bytes, void* stream) {
+  if (!z_dev || !ws || !p_out || !meas || batch < 1) {
+    set_error("tt_likelihood_dense: bad arguments");
+    return TT_ERR_ARG;
+  }
+  for (int b = 0; b < batch; ++b) {
+    TT_TRY(check_train(&p_out[b], "p_out", TT_F64));
+    for (int j = 0; j <= p_out[b].d; ++j) {
+      const int want = (meas[b].kind == 1 && j == 1) ? p_out[b].n[1] : 1;
+      if (p_out[b].cap[j] != want) {
+        set_error("tt_likelihood_dense: p_out capacities must be 1 except cap[1] = n[1] (range)");
+        return TT_ERR_SHAPE;
+      }
+    }
+  }
+  Arena ar(ws, ws_bytes);
+  UpdatePlan u;
+  TT_TRY(update_plan(batch, grids, meas, p_out, p_out, 1, ar, u));
+  if (!ar.fits()) {
+    set_error("tt_likelihood_dense: workspace too small (%zu < %zu)", ws_bytes, ar.used);
+    return TT_ERR_WORKSPACE;
+  }
+  for (int b = 0; b < batch; ++b) u.vl[b] = make_dev(p_out[b]);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  TT_TRY(upload(u.dl, u.vl, st));
+  TT_TRY(upload(u.dfc, u.vfc, st));
+  hipLaunchKernelGGL(lik_dense_kernel, dim3(batch), dim3(256), 0, st, u.dl, u.dfc, z_dev, (long long)z_stride, u.mbuf,
+                     u.mstride);
+  TTG_LAUNCH_CHECK("lik_dense_kernel");
+  if (u.any_range) {
+    hipLaunchKernelGGL(lik_dense_pack_kernel, dim3(batch), dim3(256), 0, st, u.dl, u.dfc, u.mbuf, u.mstride);
+    TTG_LAUNCH_CHECK("lik_dense_pack_kernel");
+  }
+  return TT_OK;
+}
+
+}  // extern "C"
+
+namespace ttg {
+
+// host descriptors of the two-core trains of the likelihood-build adjoint
+struct LikAdjPlan {
+  std::vector<tt_train> a, y, ybar, abar;
+  std::vector<int> idx;  // range filters
+};
+
+static tt_status lik_adj_plan(int32_t batch, const tt_meas* meas, const tt_train* p, const tt_train* l,
+                              const tt_train* l_bar, const tt_train* p_bar, Arena* ar, LikAdjPlan& pl) {
+  for (int b = 0; b < batch; ++b) {
+    for (const tt_train* t : {&p[b], &l[b]}) TT_TRY(check_train(t, "tt_likelihood_adjoint", TT_F64));
+    if (l_bar) TT_TRY(check_train(&l_bar[b], "l_bar", TT_F64));
+    if (p_bar) TT_TRY(check_train(&p_bar[b], "p_bar", TT_F64));
+    const int d = p[b].d;
+    const bool range = meas[b].kind == 1;
+    if (meas[b].kind != 0 && meas[b].kind != 1) {
+      set_error("tt_likelihood_adjoint: meas kind must be 0 or 1");
+      return TT_ERR_ARG;
+    }
+    if (l[b].d != d || (range && d < 2)) {
+      set_error("tt_likelihood_adjoint: d differs or range model with d < 2");
+      return TT_ERR_SHAPE;
+    }
+    for (int k = 0; k < d; ++k)
+      if (l[b].n[k] != p[b].n[k]) {
+        set_error("tt_likelihood_adjoint: mode sizes differ");
+        return TT_ERR_SHAPE;
+      }
+    for (int j = 0; j <= d; ++j) {
+      const int pw = (range && j == 1) ? p[b].n[1] : 1;
+      if (p[b].cap[j] != pw || (j != 1 || !range ? l[b].cap[j] != 1 : l[b].cap[1] > p[b].n[1])) {
+        set_error("tt_likelihood_adjoint: capacities of p or l do not match the likelihood layout");
+        return TT_ERR_SHAPE;
+      }
+      if ((l_bar && l_bar[b].cap[j] != l[b].cap[j]) || (p_bar && p_bar[b].cap[j] != p[b].cap[j])) {
+        set_error("tt_likelihood_adjoint: adjoint capacities differ from their primals");
+        return TT_ERR_SHAPE;
+      }
+    }
+    if (l_bar && p_bar)
+      for (int k = 0; k < d; ++k)
+        if (l_bar[b].n[k] != p[b].n[k] || p_bar[b].n[k] != p[b].n[k]) {
+          set_error("tt_likelihood_adjoint: mode sizes differ");
+          return TT_ERR_SHAPE;
+        }
+    if (!range) continue;
+    pl.idx.push_back(b);
+    // the build's rank is at most min(n0, n1), below the capacity
+    const int n0 = p[b].n[0], n1 = p[b].n[1], rc = std::min(l[b].cap[1], n0);
+    auto mk = [&](int cap1) {
+      tt_train t;
+      memset(&t, 0, sizeof(t));
+      t.d = 2;
+      t.n[0] = n1;
+      t.n[1] = n0;
+      t.cap[0] = t.cap[2] = 1;
+      t.cap[1] = cap1;
+      t.dtype = TT_F64;
+      if (ar) {
+        t.cores = ar->take<double>(elems_of(2, t.n, t.cap));
+        t.ranks = ar->take<int>(TT_MAXD + 1);
+        t.log_scale = ar->take<double>(1);
+        t.status = ar->take<int>(1);
+      }
+      return t;
+    };
+    pl.a.push_back(mk(n0));
+    pl.y.push_back(mk(rc));
+    pl.ybar.push_back(mk(rc));
+    pl.abar.push_back(mk(n0));
+  }
+  return TT_OK;
+}
+
+}  // namespace ttg
+
+extern "C" {
+
+size_t tt_likelihood_adjoint_workspace(int32_t batch, const tt_meas* meas, const tt_train* p, const tt_train* l) {
+  if (batch < 1 || !meas || !p || !l) return 0;
+  Arena ar(nullptr, 0);
+  LikAdjPlan pl;
+  ar.take<LikAdjJob>(batch);
+  if (lik_adj_plan(batch, meas, p, l, nullptr, nullptr, &ar, pl) != TT_OK) return 0;
+  size_t total = ar.used + 1024;
+  if (!pl.idx.empty())
+    total += tt_round_adjoint_workspace((int32_t)pl.idx.size(), pl.a.data(), pl.y.data()) + 256;
+  return total;
+}
+
+tt_status tt_likelihood_adjoint(int32_t batch, const tt_meas* meas, const tt_train* p, const tt_train* l,
+                                const tt_train* l_bar, const tt_train* p_bar, void* ws, size_t ws_bytes,
+                                void* stream) {
+  if (batch < 1 || !meas || !p || !l || !l_bar || !p_bar || !ws) {
+    set_error("tt_likelihood_adjoint: bad arguments");
+    return TT_ERR_ARG;
+  }
+  Arena ar(ws, ws_bytes);
+  LikAdjPlan pl;
+  LikAdjJob* dj = ar.take<LikAdjJob>(batch);
+  TT_TRY(lik_adj_plan(batch, meas, p, l, l_bar, p_bar, &ar, pl));
+  const int nr = (int)pl.idx.size();
+  size_t rbytes = 0;
+  void* rws = nullptr;
+  if (nr > 0) {
+    rbytes = tt_round_adjoint_workspace(nr, pl.a.data(), pl.y.data());
+    rws = ar.take<char>(rbytes);
+  }
+  if (!ar.fits()) {
+    set_error("tt_likelihood_adjoint: workspace too small (%zu < %zu)", ws_bytes, ar.used);
+    return TT_ERR_WORKSPACE;
+  }
+  std::vector<LikAdjJob> jobs(batch);
+  for (int b = 0, q = 0; b < batch; ++b) {
+    LikAdjJob& J = jobs[b];
+    memset(&J, 0, sizeof(J));
+    J.p = make_dev(p[b]);
+    J.l = make_dev(l[b]);
+    J.lbar = make_dev(l_bar[b]);
+    J.pbar = make_dev(p_bar[b]);
+    J.range = meas[b].kind == 1;
+    if (J.range) {
+      J.a = make_dev(pl.a[q]);
+      J.y = make_dev(pl.y[q]);
+      J.ybar = make_dev(pl.ybar[q]);
+      J.abar = make_dev(pl.abar[q]);
+      ++q;
+    }
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  TT_TRY(upload(dj, jobs, st));
+  if (nr > 0) {
+    hipLaunchKernelGGL(lik_adj_pack_kernel, dim3(batch), dim3(256), 0, st, dj);
+    TTG_LAUNCH_CHECK("lik_adj_pack_kernel");
+    TT_TRY(tt_round_adjoint(nr, pl.a.data(), pl.y.data(), pl.ybar.data(), pl.abar.data(), rws, rbytes, stream));
+  }
+  hipLaunchKernelGGL(lik_adj_unpack_kernel, dim3(batch), dim3(256), 0, st, dj);
+  TTG_LAUNCH_CHECK("lik_adj_unpack_kernel");
+  return TT_OK;
+}
+
+tt_status tt_prior(int32_t batch, const tt_grid* grids, const double* m0, const double* p0_diag, const tt_train* out,
+                   void* ws, size_t ws_bytes, void* stream) {
+  if (batch < 1 || !grids || !m0 || !p0_diag || !out || !ws) {
+    set_error("tt_prior: bad arguments");
+    return TT_ERR_ARG;
+  }
+  const int dtype = out[0].dtype, d = out[0].d;
+  std::vector<DevTT> vt(batch);
+  std::vector<FilterConst> vfc(batch);
+  for (int b = 0; b < batch; ++b) {
+    TT_TRY(check_grid(&grids[b]));
+    TT_TRY(check_train(&out[b], "out", dtype));
+    if (grids[b].d != d || out[b].d != d) {
+      set_error("tt_prior: d differs");
+      return TT_ERR_SHAPE;
+    }
+    for (int k = 0; k < d; ++k) {
+      if (grids[b].n[k] != out[b].n[k]) {
+        set_error("tt_prior: grid and train mode sizes differ");
+        return TT_ERR_SHAPE;
+      }
+      if (!(p0_diag[b * d + k] > 0.0)) {
+        set_error("tt_prior: prior variances must be positive");
+        return TT_ERR_ARG;
+      }
+    }
+    vt[b] = make_dev(out[b]);
+    vfc[b] = make_const(grids[b], nullptr);
+    for (int k = 0; k < d; ++k) {
+      vfc[b].m0[k] = m0[b * d + k];
+      vfc[b].p0[k] = p0_diag[b * d + k];
+    }
+  }
+  Arena ar(ws, ws_bytes);
+  DevTT* dt = ar.take<DevTT>(batch);
+  FilterConst* dfc = ar.take<FilterConst>(batch);
+  if (!ar.fits()) {
+    set_error("tt_prior: workspace too small");
+    return TT_ERR_WORKSPACE;
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  TT_TRY(upload(dt, vt, st));
+  TT_TRY(upload(dfc, vfc, st));
+  if (dtype == TT_F64)
+    hipLaunchKernelGGL((prior_kernel<double>), dim3(batch), dim3(256), 0, st, dt, dfc);
+  else
+    hipLaunchKernelGGL((prior_kernel<float>), dim3(batch), dim3(256), 0, st, dt, dfc);
+  TTG_LAUNCH_CHECK("prior_kernel");
+  return TT_OK;
+}
+
+static tt_status adj_pair(int32_t batch, const tt_train* x, const tt_train* y, const char* what, DevTT** dx,
+                          DevTT** dy, void* ws, size_t ws_bytes, hipStream_t st) {
+  std::vector<DevTT> vx(batch), vy(batch);
+  for (int b = 0; b < batch; ++b) {
+    TT_TRY(check_train(&x[b], what, TT_F64));
+    TT_TRY(check_train(&y[b], what, TT_F64));
+    TT_TRY(check_like(x[b], y[b], what));
+    vx[b] = make_dev(x[b]);
+    vy[b] = make_dev(y[b]);
+  }
+  Arena ar(ws, ws_bytes);
+  *dx = ar.take<DevTT>(batch);
+  *dy = ar.take<DevTT>(batch);
+  if (!ar.fits()) {
+    set_error("%s: workspace too small", what);
+    return TT_ERR_WORKSPACE;
+  }
+  TT_TRY(upload(*dx, vx, st));
+  TT_TRY(upload(*dy, vy, st));
+  return TT_OK;
+}
+
+tt_status tt_adjoint_axpy(int32_t batch, double alpha, const tt_train* x, const tt_train* y, void* ws,
+                          size_t ws_bytes, void* stream) {
+  if (batch < 1 || !x || !y || !ws) {
+    set_error("tt_adjoint_axpy: bad arguments");
+    return TT_ERR_ARG;
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  DevTT *dx, *dy;
+  TT_TRY(adj_pair(batch, x, y, "tt_adjoint_axpy", &dx, &dy, ws, ws_bytes, st));
+  int pel = 1;
+  for (int b = 0; b < batch; ++b)
+    for (int k = 0; k < x[b].d; ++k) pel = std::max(pel, x[b].cap[k] * x[b].n[k] * x[b].cap[k + 1]);
+  hipLaunchKernelGGL(adj_axpy_kernel, dim3(stride_grid(cdiv(pel, 256), batch), x[0].d, batch), dim3(256), 0, st, dx,
+                     dy, alpha);
+  TTG_LAUNCH_CHECK("adj_axpy_kernel");
+  return TT_OK;
+}
+
+tt_status tt_adjoint_inner(int32_t batch, const tt_train* a_bar, const tt_train* b, double* out_dev, void* ws,
+                           size_t ws_bytes, void* stream) {
+  if (batch < 1 || !a_bar || !b || !out_dev || !ws) {
+    set_error("tt_adjoint_inner: bad arguments");
+    return TT_ERR_ARG;
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  DevTT *da, *db;
+  TT_TRY(adj_pair(batch, a_bar, b, "tt_adjoint_inner", &da, &db, ws, ws_bytes, st));
+  hipLaunchKernelGGL(adj_inner_kernel, dim3(batch), dim3(256), 0, st, da, db, out_dev);
+  TTG_LAUNCH_CHECK("adj_inner_kernel");
+  return TT_OK;
+}
+
+tt_status tt_align_signs(int32_t batch, const tt_train* ref, const tt_train* t, void* ws, size_t ws_bytes,
+                         void* stream) {
+  if (batch < 1 || !ref || !t || !ws) {
+    set_error("tt_align_signs: bad arguments");
+    return TT_ERR_ARG;
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  std::vector<DevTT> vr(batch), vt(batch);
+  for (int b = 0; b < batch; ++b) {
+    TT_TRY(check_train(&ref[b], "tt_align_signs", TT_F64));
+    TT_TRY(check_train(&t[b], "tt_align_signs", TT_F64));
+    TT_TRY(check_like(ref[b], t[b], "tt_align_signs"));
+    if (t[b].d != t[0].d) {
+      set_error("tt_align_signs: d differs");
+      return TT_ERR_SHAPE;
+    }
+    vr[b] = make_dev(ref[b]);
+    vt[b] = make_dev(t[b]);
+  }
+  const size_t m2 = (size_t)2 * ALIGN_RMAX * ALIGN_RMAX;
+  Arena ar(ws, ws_bytes);
+  DevTT* dr = ar.take<DevTT>(batch);
+  DevTT* dt = ar.take<DevTT>(batch);
+  double* buf = ar.take<double>(batch * m2);
+  double* work = ar.take<double>(batch * m2);
+  double* usv = ar.take<double>(batch * m2);
+  double* sigma = ar.take<double>((size_t)batch * ALIGN_RMAX);
+  int* rbuf = ar.take<int>(batch);
+  if (!ar.fits()) {
+    set_error("tt_align_signs: workspace too small (%zu < %zu)", ws_bytes, ar.used);
+    return TT_ERR_WORKSPACE;
+  }
+  TT_TRY(upload(dr, vr, st));
+  TT_TRY(upload(dt, vt, st));
+  for (int k = 0; k + 1 < t[0].d; ++k) {
+    hipLaunchKernelGGL(align_cos_kernel, dim3(batch), dim3(256), 0, st, dr, dt, k, buf, rbuf);
+    TTG_LAUNCH_CHECK("align_cos_kernel");
+    TT_TRY(launch_jacobi(FAlignJacobi{buf, rbuf, work, sigma, usv}, batch, st));
+    hipLaunchKernelGGL(align_apply_kernel, dim3(batch), dim3(256), 0, st, dt, k, sigma, usv, rbuf);
+    TTG_LAUNCH_CHECK("align_apply_kernel");
+  }
+  return TT_OK;
 }
 
 size_t tt_update_workspace(int32_t batch, const tt_grid* grids, const tt_meas* meas, const tt_train* p_pred,

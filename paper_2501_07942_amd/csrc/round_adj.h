@@ -13,10 +13,12 @@
 // factors moved into the log-scale; the adjoint takes the kept U_k from
 // the forward's output (its gauge) and the eigenvalues and discarded
 // directions of S_k from a one-sided Jacobi SVD of M_k = N_k F_k with
-// F_k F_k^T = G_k (pivoted Cholesky).  For the leading eigenvectors,
+// F_k F_k^T = G_k (pivoted Cholesky of G_k accumulated in double-double, as
+// the forward rounding does, so that small singular values are resolved).  For the leading eigenvectors,
 // dU_j = sum_{i != j} u_i (u_i^T dS u_j) / (lam_j - lam_i); its adjoint is
 // Sbar = X U^T with
 //   X_j = (I - U_all U_all^T) Ubar_j / lam_j + sum_{i discarded} u_i (u_i^T Ubar_j) / (lam_j - lam_i)
+//       = (I - U U^T) Ubar_j / lam_j + sum_{i discarded} u_i (u_i^T Ubar_j) lam_i / (lam_j (lam_j - lam_i))
 // (couplings among kept vectors cancel because everything downstream
 // depends on the rounded tensor only).  Kept directions below TAU of the
 // largest singular value are left out: their terms carry rounding noise of
@@ -133,6 +135,9 @@ enum {
   EJ_SCALE = 1,     // out[e] = s[0] * x[e]
   EJ_SYM = 2,       // out = x + x^T (r x r)
   EJ_ONE = 3,       // out[0] = 1
+  EJ_DDHI = 4,      // out[e] = high word of the double-double x[e]
+  EJ_COPY = 5,      // out[e] = x[e]
+  EJ_ROWFLIP = 6,   // out[e] = x[e] * y[e / ld] (signs of the left bond index)
 };
 
 __global__ void __launch_bounds__(256) ejob_kernel(const EJob* __restrict__ jobs) {
@@ -147,6 +152,9 @@ __global__ void __launch_bounds__(256) ejob_kernel(const EJob* __restrict__ jobs
         j.out[e] = j.x[e] + j.x[(long long)b * j.r + a];
         break;
       }
+      case EJ_DDHI: j.out[e] = j.x[2 * e]; break;
+      case EJ_COPY: j.out[e] = j.x[e]; break;
+      case EJ_ROWFLIP: j.out[e] = j.x[e] * j.y[e / j.ld]; break;
       default: if (e == 0) j.out[0] = 1.0; break;
     }
   }
@@ -183,9 +191,14 @@ __global__ void __launch_bounds__(256) radj_scalar_kernel(const EJob* __restrict
 // From the Jacobi SVD of M (sigma descending, usv column c = sigma_c u_c,
 // column-major ld p) and the kept count r: the discarded left vectors
 // Ud (p x (R - r), row-major) = u_i for sigma_i > DISC sigma_1 (zero
-// otherwise), the coupling matrix Fm ((R - r) x r) = 1 / (lam_j - lam_i) for
-// those i and live j, and linv (r) = 1 / lam_j for live j (sigma_j >= TAU
-// sigma_1), zero for left-out j.  x = sigma, y = usv, out = Ud, out2 = Fm,
+// otherwise), the coupling corrections Fm ((R - r) x r) =
+// 1 / (lam_j - lam_i) - 1 / lam_j for those i and live j, and linv (r) =
+// 1 / lam_j for live j (sigma_j >= TAU sigma_1), zero for left-out j.  The
+// eigenvector adjoint is then X = (I - U U^T) Ubar diag(linv) +
+// Ud ((Ud^T Ubar) o Fm): the complement of the kept vectors U (taken from
+// the forward's output) enters through U alone, and each discarded
+// direction only through a correction weighted by its own lam_i, so
+// rounding noise in small discarded directions stays small.  x = sigma, y = usv, out = Ud, out2 = Fm,
 // s -> linv (written through out2 + (R - r) r).  One workgroup per job.
 __global__ void __launch_bounds__(256) radj_eigprep_kernel(const EJob* __restrict__ jobs) {
   const EJob j = jobs[blockIdx.x];
@@ -201,7 +214,8 @@ __global__ void __launch_bounds__(256) radj_eigprep_kernel(const EJob* __restric
     const int i = (int)(e / r), c = (int)(e - (long long)i * r);
     const double si = sig[r + i], sj = sig[c];
     const bool ok = s1 > 0.0 && si > RADJ_DISC * s1 && sj >= RADJ_TAU * s1 && sj > si;
-    j.out2[e] = ok ? 1.0 / ((sj - si) * (sj + si)) : 0.0;
+    // 1 / (lam_j - lam_i) - 1 / lam_j = lam_i / (lam_j (lam_j - lam_i))
+    j.out2[e] = ok ? (si * si) / ((sj * sj) * ((sj - si) * (sj + si))) : 0.0;
   }
   for (long long e = threadIdx.x; e < (long long)p * nd; e += blockDim.x) {
     const int row = (int)(e / nd), i = (int)(e - (long long)row * nd);
@@ -224,6 +238,47 @@ __global__ void __launch_bounds__(256) radj_eigapply_kernel(const EJob* __restri
       const long long f = e - nz;
       j.out2[f] *= j.y[f];
     }
+  }
+}
+
+// The adjoint works in the basis of its own SVD of M_k (so that the kept
+// vectors, their complement and the eigenvalues are mutually consistent to
+// working precision); the forward's output core Y_k = c_k U_fwd differs from
+// it by the signs of the bond indices.  Per job (filter, core k): with the
+// previous bond's signs dprev (on the left index a of a row (a, i)), the
+// sign of each kept column c is that of <dprev o U_fwd(:, c), u_c>; then
+// U <- u_c (overwriting U_fwd) and ybt = c_k (dprev o Ybar_k) diag(dk),
+// the output adjoint expressed in the adjoint's basis.  One workgroup per
+// job.
+struct AJob {
+  const double* usv;
+  const double* sig;
+  double* U;
+  double* ybt;
+  const double* ybar;
+  const double* c;
+  const double* dprev;
+  double* dk;
+  int p, r, n, ldu;
+};
+
+__global__ void __launch_bounds__(256) radj_adopt_kernel(const AJob* __restrict__ jobs) {
+  const AJob j = jobs[blockIdx.x];
+  __shared__ double red[4];
+  for (int c = 0; c < j.r; ++c) {
+    double s = 0.0;
+    for (int row = threadIdx.x; row < j.p; row += blockDim.x)
+      s += j.dprev[row / j.n] * j.U[(long long)row * j.r + c] * j.usv[(long long)c * j.ldu + row];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) j.dk[c] = s >= 0.0 ? 1.0 : -1.0;
+  }
+  __syncthreads();
+  const double c0 = j.c[0];
+  for (long long e = threadIdx.x; e < (long long)j.p * j.r; e += blockDim.x) {
+    const int row = (int)(e / j.r), c = (int)(e - (long long)row * j.r);
+    const double sc = j.sig[c];
+    j.U[e] = sc > 0.0 ? j.usv[(long long)c * j.ldu + row] / sc : 0.0;
+    j.ybt[e] = c0 * j.dprev[row / j.n] * j.ybar[e] * j.dk[c];
   }
 }
 

@@ -40,6 +40,8 @@ CASES = [
     ([4, 7, 5, 6], [4, 8, 7], 3, 0.6),
 ]
 CASES_D3 = [([6, 7, 5], [8, 9], 3, 0.6)]
+# a wide first bond over rank-one bonds (the update rounding of the first step)
+CASES_R1 = [([40, 6, 5, 4], [9, 1, 1], 8, 0.6)]
 
 
 def run_case(B, cases, seed):
@@ -77,7 +79,7 @@ def run_case(B, cases, seed):
     return outs, AB
 
 
-@pytest.mark.parametrize("cases", [CASES, CASES_D3], ids=["d4_batch2", "d3"])
+@pytest.mark.parametrize("cases", [CASES, CASES_D3, CASES_R1], ids=["d4_batch2", "d3", "rank_one_bonds"])
 def test_round_adjoint_matches_oracle_reverse_mode(B, cases):
     print(f"round adjoint: {len(cases)} filter(s), d={len(cases[0][0])}, binding caps", flush=True)
     outs, AB = run_case(B, cases, 21)
