@@ -93,8 +93,11 @@ class ComposedGradient:
 
     def _round(self, xs):
         outs = [B.DeviceTT(x.n, pc, B.F64) for x, pc in zip(xs, self.pcaps)]
-        for s, x, o in zip(self.specs, xs, outs):
-            B.tt_round([x], [o], s.eps, s.cap)
+        groups = {}
+        for i, s in enumerate(self.specs):
+            groups.setdefault((s.eps, s.cap), []).append(i)
+        for (eps, cap), idx in groups.items():    # one batched call per tolerance and cap
+            B.tt_round([xs[i] for i in idx], [outs[i] for i in idx], eps, cap)
         return outs
 
     def _likelihood(self, k, meas=None):

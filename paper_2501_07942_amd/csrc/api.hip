@@ -1253,7 +1253,8 @@ namespace ttg {
 
 #define RADJ_PLANES 4
 struct RadjCore {  // per filter and core k (0-based)
-  double *G, *T, *W, *U, *c, *N, *lfac, *lwork, *gdd, *M, *jw, *sig, *usv, *Ud, *Fm, *Gbar, *D, *YBt;
+  double *G, *T, *W, *U, *c, *N, *lfac, *lwork, *gdd, *M, *jw, *sig, *usv, *Ud, *Fm, *Gbar, *D, *YBt, *vs, *js;
+  int* flag;
   int* piv;
   int* prank;
 };
@@ -1262,6 +1263,11 @@ struct RadjFilter {
   int d, n[TT_MAXD], Ra[TT_MAXD + 1], ry[TT_MAXD + 1];
   RadjCore c[TT_MAXD];
   double *L, *kappa, *Lbar, *Wb0, *Wb1, *Nbar, *Ubar, *P1, *P2, *WG, *XtN, *XtNG, *Gs, *T2, *Tg, *one;
+  // first core wider than its rows (Ra[1] > n[0], d >= 2): the SVD of M_0
+  // from S_0 = M'_0 M'_0^T, M'_0 = A_0 x_3 Z_1 (n[0] x n[1] Ra[2])
+  bool wide0;
+  double *Mw, *sdd, *slw, *slf;
+  int *spiv, *srank;
 };
 
 // lays out the buffers of every filter in the arena (sizes from ranks Ra, ry)
@@ -1300,7 +1306,20 @@ static void radj_layout(Arena& ar, RadjFilter& F) {
       C.usv = ar.take<double>(p * Rk1);
       C.Ud = ar.take<double>(std::max(1LL, p * nd));
       C.Fm = ar.take<double>(nd * rk1 + rk1);
+      C.vs = ar.take<double>(Rk1 * Rk1);
+      C.js = ar.take<double>(Rk1 * Rk1);
+      C.flag = ar.take<int>(1);
     }
+  }
+  F.wide0 = d >= 2 && F.Ra[1] > F.n[0];
+  if (F.wide0) {
+    const long long n0 = F.n[0];
+    F.Mw = ar.take<double>(n0 * F.n[1] * F.Ra[2]);
+    F.sdd = ar.take<double>(2 * RADJ_PLANES * n0 * n0);
+    F.slw = ar.take<double>(2 * n0 * n0);
+    F.slf = ar.take<double>(n0 * n0);
+    F.spiv = ar.take<int>(n0);
+    F.srank = ar.take<int>(1);
   }
   const int rl = F.ry[d - 1], nl = F.n[d - 1];
   F.L = ar.take<double>((long long)rl * nl);
@@ -1329,6 +1348,9 @@ struct RadjRun {
   JacobiArgs* dj;
   GramArgs* dga;
   AJob* daj;
+  RkJacobi* drj;
+  CondJacobi* dcj;
+  RefJob* drf;
   int jcap;
   std::vector<GJob> g;
   std::vector<EJob> e;
@@ -1381,8 +1403,9 @@ struct RadjRun {
       TT_TRY(check(inside(j.out, n - 1), "elementwise out"));
       if (j.op == EJ_SCALE || j.op == EJ_SYM) TT_TRY(check(inside(j.x, n - 1), "elementwise x"));
       if (j.op == EJ_DDHI) TT_TRY(check(inside(j.x, 2 * n - 1), "elementwise x"));
-      if (j.op == EJ_COPY || j.op == EJ_ROWFLIP) TT_TRY(check(inside(j.x, n - 1), "elementwise x"));
-      if (j.op == EJ_ROWFLIP) TT_TRY(check(j.ld > 0 && inside(j.y, (n - 1) / j.ld), "elementwise y"));
+      if (j.op == EJ_COPY || j.op == EJ_ROWFLIP || j.op == EJ_COLDIV) TT_TRY(check(inside(j.x, n - 1), "elementwise x"));
+      if (j.op == EJ_ROWFLIP || j.op == EJ_COLDIV)
+        TT_TRY(check(j.ld > 0 && inside(j.y, (n - 1) / j.ld), "elementwise y"));
       if (j.op == EJ_SCALE) TT_TRY(check(inside(j.s, 0), "elementwise s"));
     }
     long long mx = 1;
@@ -1457,7 +1480,7 @@ size_t tt_round_adjoint_workspace(int32_t batch, const tt_train* a, const tt_tra
   const int dd = a[0].d;
   size_t total = (size_t)batch * (3 * dd + 8) *
                      (sizeof(GJob) + sizeof(EJob) + sizeof(PcholArgs) + sizeof(JacobiArgs) + sizeof(GramArgs) +
-                      sizeof(AJob)) +
+                      sizeof(AJob) + sizeof(RkJacobi) + sizeof(CondJacobi) + sizeof(RefJob)) +
                  8192;
   for (int b = 0; b < batch; ++b) {
     RadjFilter F;
@@ -1523,6 +1546,9 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
   R.dj = ar.take<JacobiArgs>((size_t)batch * d);
   R.dga = ar.take<GramArgs>((size_t)batch);
   R.daj = ar.take<AJob>((size_t)batch);
+  R.drj = ar.take<RkJacobi>((size_t)batch);
+  R.dcj = ar.take<CondJacobi>((size_t)batch);
+  R.drf = ar.take<RefJob>((size_t)batch);
   int Rmax = 1;
   for (int b = 0; b < batch; ++b) {
     RadjFilter& f = F[b];
@@ -1637,7 +1663,8 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
       pa.rank_out = f.c[k - 1].prank;
       pa.gcap = R0;
       pa.rmax = R0;
-      pa.tau2 = 1e-30;
+      pa.tau2 = RADJ_PCHOL_TAU2;
+      if (k == 1 && f.wide0) pa.M = 0;  // F_0 is not needed: M_0's SVD comes from S_0
       pj.push_back(pa);
       mcap = std::max(mcap, R0);
       tcap = std::max(tcap, (long long)n * R1);
@@ -1689,30 +1716,142 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
     for (int b = 0; b < batch; ++b) {
       RadjFilter& f = F[b];
       const int R1 = f.Ra[k + 1], p = f.ry[k] * f.n[k];
+      if (k == 0 && f.wide0) {
+        // M'_0 = A_0 Z_1 (Z_1 = A_1 x_3 F_1 is left in Tg by the right sweep)
+        const long long T = (long long)f.n[1] * f.Ra[2];
+        R.mm(f.n[0], (int)T, f.Ra[1], acore(b, 0), f.Ra[1], 1, f.Tg, T, 1, f.Mw, T, 1.0, 0.0);
+        continue;
+      }
       R.mm(p, R1, R1, f.c[k].N, R1, 1, f.c[k].lfac, R1, 1, f.c[k].M, R1, 1.0, 0.0);
     }
     TT_TRY(R.gemm());
-    std::vector<JacobiArgs> jj;
+    // The SVD of M_k from a double-double Gram, its pivoted Cholesky factor C
+    // (pre-truncated far below the singular values the adjoint resolves) and
+    // the one-sided Jacobi SVD of C.  Tall M_k (p >= R1): Gram M_k^T M_k, the
+    // Jacobi vectors are the right singular vectors v_c and the columns
+    // sigma_c u_c = M_k v_c follow by one product.  Wide first core: Gram
+    // S_0 = M'_0 M'_0^T, the Jacobi vectors are the left singular vectors.
+    {
+      int mcap = 1;
+      long long tcap = 1;
+      std::vector<GramArgs> gj(batch);
+      std::vector<PcholArgs> pj(batch);
+      std::vector<RkJacobi> rj(batch);
+      for (int b = 0; b < batch; ++b) {
+        RadjFilter& f = F[b];
+        memset(&gj[b], 0, sizeof(GramArgs));
+        memset(&pj[b], 0, sizeof(PcholArgs));
+        memset(&rj[b], 0, sizeof(RkJacobi));
+        const int R1 = f.Ra[k + 1], p = f.ry[k] * f.n[k];
+        const bool wide = k == 0 && f.wide0;
+        const int gm = wide ? f.n[0] : R1;                       // Gram dimension
+        const long long T = wide ? (long long)f.n[1] * f.Ra[2] : p;  // summation length
+        double* gout = wide ? f.sdd : f.c[k + 1].gdd;
+        double* lw = wide ? f.slw : f.c[k].lwork;
+        double* lf = wide ? f.slf : f.c[k].lfac;
+        int* pv = wide ? f.spiv : f.c[k].piv;
+        int* rk = wide ? f.srank : f.c[k].prank;
+        double* jv = wide ? f.c[0].usv : f.c[k].vs;
+        double* jwk = wide ? f.c[0].jw : f.c[k].js;
+        R.ej(EJ_FILL, R1, nullptr, nullptr, f.c[k].sig, nullptr, nullptr);
+        R.ej(EJ_FILL, (long long)gm * gm, nullptr, nullptr, jv, nullptr, nullptr);
+        GramArgs& ga = gj[b];
+        ga.M = gm;
+        ga.T = (int)T;
+        ga.x = wide ? f.Mw : f.c[k].M;
+        ga.sa = wide ? T : 1;
+        ga.st = wide ? 1 : R1;
+        ga.out = gout;
+        ga.gcap = gm;
+        ga.splits = RADJ_PLANES;
+        PcholArgs& pa = pj[b];
+        pa.M = gm;
+        pa.g = gout;
+        pa.lwork = lw;
+        pa.lfac = lf;
+        pa.piv = pv;
+        pa.rank_out = rk;
+        pa.gcap = gm;
+        pa.rmax = gm;
+        pa.tau2 = RADJ_PCHOL_TAU2;
+        JacobiArgs& ja = rj[b].ja;
+        ja.rows = gm;
+        ja.ncols = gm;
+        ja.tol2 = 1e-30;
+        ja.x = lf;
+        ja.ldx = gm;
+        ja.work = jwk;
+        ja.sigma = f.c[k].sig;
+        ja.usv = jv;
+        ja.gcap = gm;
+        rj[b].ncols = rk;
+        TT_TRY(R.check((wide ? (f.ry[0] == 1 && R1 > f.n[0]) : p >= 1) &&
+                           R.inside(ga.x, wide ? (long long)gm * T - 1 : (long long)p * R1 - 1) &&
+                           R.inside(gout, 2LL * RADJ_PLANES * gm * gm - 1) && R.inside(lw, 2LL * gm * gm - 1) &&
+                           R.inside(lf, (long long)gm * gm - 1) && R.inside(jwk, (long long)gm * gm - 1) &&
+                           R.inside(jv, (long long)gm * gm - 1) && R.inside(f.c[k].sig, R1 - 1) && gm <= R1,
+                       "svd of M_k"));
+        mcap = std::max(mcap, gm);
+        tcap = std::max(tcap, T);
+      }
+      TT_TRY(R.elem());
+      TT_TRY(upload(R.dga, gj, st));
+      TT_TRY((launch_gram<double, AccDD>(FAdjGram{R.dga}, batch, mcap, tcap, RADJ_PLANES, st)));
+      TT_TRY(upload(R.dp, pj, st));
+      TT_TRY((launch_pchol<AccDD, FAdjPchol>(FAdjPchol{R.dp}, batch, mcap, st)));
+      TT_TRY(upload(R.drj, rj, st));
+      TT_TRY(launch_jacobi(FAdjJacobiRk{R.drj}, batch, st));
+      for (int b = 0; b < batch; ++b) {  // sigma_c u_c = M_k v_c (tall cores)
+        RadjFilter& f = F[b];
+        if (k == 0 && f.wide0) continue;
+        const int R1 = f.Ra[k + 1], p = f.ry[k] * f.n[k];
+        R.mm(R1, p, R1, f.c[k].vs, R1, 1, f.c[k].M, 1, R1, f.c[k].usv, p, 1.0, 0.0);
+      }
+      TT_TRY(R.gemm());
+      for (int b = 0; b < batch; ++b) {
+        RadjFilter& f = F[b];
+        if (k == 0 && f.wide0) continue;
+        const int R1 = f.Ra[k + 1], p = f.ry[k] * f.n[k];
+        R.ej(EJ_COLDIV, (long long)p * R1, f.c[k].usv, f.c[k].sig, f.c[k].usv, nullptr, nullptr, 0, 0, 0, p);
+      }
+      TT_TRY(R.elem());
+      // tall cores that kept a very small singular value: Jacobi on M_k
+      std::vector<RefJob> rf(batch);
+      std::vector<CondJacobi> cj(batch);
+      for (int b = 0; b < batch; ++b) {
+        RadjFilter& f = F[b];
+        memset(&rf[b], 0, sizeof(RefJob));
+        memset(&cj[b], 0, sizeof(CondJacobi));
+        if (k == 0 && f.wide0) continue;
+        const int R1 = f.Ra[k + 1], p = f.ry[k] * f.n[k];
+        rf[b].sig = f.c[k].sig;
+        rf[b].r = f.ry[k + 1];
+        rf[b].flag = f.c[k].flag;
+        JacobiArgs& ja = cj[b].ja;
+        ja.rows = p;
+        ja.ncols = R1;
+        ja.tol2 = 1e-30;
+        ja.x = f.c[k].M;
+        ja.ldx = R1;
+        ja.work = f.c[k].jw;
+        ja.sigma = f.c[k].sig;
+        ja.usv = f.c[k].usv;
+        ja.gcap = p;
+        cj[b].flag = f.c[k].flag;
+        TT_TRY(R.check(f.ry[k + 1] <= R1 && R.inside(ja.x, (long long)p * R1 - 1) &&
+                           R.inside(ja.work, (long long)R1 * p - 1) && R.inside(ja.usv, (long long)R1 * p - 1),
+                       "jacobi on M_k"));
+      }
+      TT_TRY(upload(R.drf, rf, st));
+      hipLaunchKernelGGL(radj_refine_flag_kernel, dim3(cdiv(batch, 64)), dim3(64), 0, st, R.drf, batch);
+      TTG_LAUNCH_CHECK("radj_refine_flag_kernel");
+      TT_TRY(upload(R.dcj, cj, st));
+      TT_TRY(launch_jacobi(FAdjJacobiIf{R.dcj}, batch, st));
+    }
     std::vector<AJob> aj;
     for (int b = 0; b < batch; ++b) {
       RadjFilter& f = F[b];
       const int R1 = f.Ra[k + 1], r1 = f.ry[k + 1], p = f.ry[k] * f.n[k];
-      JacobiArgs ja;
-      memset(&ja, 0, sizeof(ja));
-      ja.rows = p;
-      ja.ncols = R1;
-      ja.tol2 = 1e-30;
-      ja.x = f.c[k].M;
-      ja.ldx = R1;
-      ja.work = f.c[k].jw;
-      ja.sigma = f.c[k].sig;
-      ja.usv = f.c[k].usv;
-      ja.gcap = p;
-      TT_TRY(R.check(R.inside(ja.x, (long long)(ja.rows - 1) * ja.ldx + ja.ncols - 1) &&
-                         R.inside(ja.work, (long long)ja.ncols * ja.gcap - 1) &&
-                         R.inside(ja.usv, (long long)ja.ncols * ja.gcap - 1) && R.inside(ja.sigma, ja.ncols - 1),
-                     "jacobi"));
-      jj.push_back(ja);
       AJob a1;
       memset(&a1, 0, sizeof(a1));
       a1.usv = f.c[k].usv;
@@ -1733,8 +1872,6 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
                      "adopt"));
       aj.push_back(a1);
     }
-    TT_TRY(upload(R.dj, jj, st));
-    TT_TRY(launch_jacobi(FAdjJacobi{R.dj}, batch, st));
     TT_TRY(upload(R.daj, aj, st));
     hipLaunchKernelGGL(radj_adopt_kernel, dim3(batch), dim3(256), 0, st, R.daj);
     TTG_LAUNCH_CHECK("radj_adopt_kernel");

@@ -41,6 +41,10 @@ namespace ttg {
 
 #define RADJ_TAU 6e-6     // kept singular values below TAU * sigma_1 are left out
 #define RADJ_DISC 1e-9    // discarded singular values below this (relative) count as null space
+// pivoted-Cholesky stop of the adjoint's double-double Grams, relative to
+// the trace (singular values down to about 1e-15 of the largest are kept: a
+// rounding may keep directions that small, and each kept one needs its vector)
+#define RADJ_PCHOL_TAU2 1e-30
 
 // C = alpha * A B + beta * C (beta = 0 overwrites), one 64 x 64 tile of one
 // job per workgroup; FP64, every element sums its k in increasing order.
@@ -138,6 +142,7 @@ enum {
   EJ_DDHI = 4,      // out[e] = high word of the double-double x[e]
   EJ_COPY = 5,      // out[e] = x[e]
   EJ_ROWFLIP = 6,   // out[e] = x[e] * y[e / ld] (signs of the left bond index)
+  EJ_COLDIV = 7,    // out[e] = x[e] / y[e / ld] where y > 0, else 0 (column-major columns)
 };
 
 __global__ void __launch_bounds__(256) ejob_kernel(const EJob* __restrict__ jobs) {
@@ -155,6 +160,11 @@ __global__ void __launch_bounds__(256) ejob_kernel(const EJob* __restrict__ jobs
       case EJ_DDHI: j.out[e] = j.x[2 * e]; break;
       case EJ_COPY: j.out[e] = j.x[e]; break;
       case EJ_ROWFLIP: j.out[e] = j.x[e] * j.y[e / j.ld]; break;
+      case EJ_COLDIV: {
+        const double v = j.y[e / j.ld];
+        j.out[e] = v > 0.0 ? j.x[e] / v : 0.0;
+        break;
+      }
       default: if (e == 0) j.out[0] = 1.0; break;
     }
   }
@@ -295,6 +305,52 @@ struct FAdjJacobi {
   __device__ bool operator()(int b, JacobiArgs& J) const {
     J = a[b];
     return J.rows > 0 && J.ncols > 0;
+  }
+};
+
+// Jacobi over a job table whose column count is capped by a device value
+// (the rank a pivoted Cholesky factor reached)
+struct RkJacobi {
+  JacobiArgs ja;
+  const int* ncols;
+};
+struct FAdjJacobiRk {
+  const RkJacobi* a;
+  __device__ bool operator()(int b, JacobiArgs& J) const {
+    J = a[b].ja;
+    if (J.rows <= 0) return false;
+    J.ncols = min(J.ncols, *a[b].ncols);
+    return J.ncols > 0;
+  }
+};
+
+// The SVD of a tall M_k from its Gram gives u_c = M_k v_c / sigma_c, whose
+// error grows like eps * sigma_1 / sigma_c.  When a rounding kept a singular
+// value below RADJ_REFINE * sigma_1 the vectors are recomputed by one-sided
+// Jacobi on M_k itself (accurate for every column, slower): flag per job.
+#define RADJ_REFINE 1e-8
+struct RefJob {
+  const double* sig;
+  int r;
+  int* flag;
+};
+__global__ void radj_refine_flag_kernel(const RefJob* __restrict__ jobs, int njobs) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= njobs) return;
+  const RefJob j = jobs[i];
+  if (!j.flag) return;
+  const double s1 = j.sig[0], sr = j.r >= 1 ? j.sig[j.r - 1] : s1;
+  j.flag[0] = (s1 > 0.0 && !(sr >= RADJ_REFINE * s1)) ? 1 : 0;
+}
+struct CondJacobi {
+  JacobiArgs ja;
+  const int* flag;
+};
+struct FAdjJacobiIf {
+  const CondJacobi* a;
+  __device__ bool operator()(int b, JacobiArgs& J) const {
+    J = a[b].ja;
+    return J.rows > 0 && J.ncols > 0 && a[b].flag && *a[b].flag != 0;
   }
 };
 
