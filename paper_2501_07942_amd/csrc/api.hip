@@ -1349,6 +1349,7 @@ struct RadjRun {
   GramArgs* dga;
   AJob* daj;
   RkJacobi* drj;
+  DJob* ddj;
   CondJacobi* dcj;
   RefJob* drf;
   int jcap;
@@ -1480,7 +1481,7 @@ size_t tt_round_adjoint_workspace(int32_t batch, const tt_train* a, const tt_tra
   const int dd = a[0].d;
   size_t total = (size_t)batch * (3 * dd + 8) *
                      (sizeof(GJob) + sizeof(EJob) + sizeof(PcholArgs) + sizeof(JacobiArgs) + sizeof(GramArgs) +
-                      sizeof(AJob) + sizeof(RkJacobi) + sizeof(CondJacobi) + sizeof(RefJob)) +
+                      sizeof(AJob) + sizeof(RkJacobi) + sizeof(DJob) + sizeof(CondJacobi) + sizeof(RefJob)) +
                  8192;
   for (int b = 0; b < batch; ++b) {
     RadjFilter F;
@@ -1547,6 +1548,7 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
   R.dga = ar.take<GramArgs>((size_t)batch);
   R.daj = ar.take<AJob>((size_t)batch);
   R.drj = ar.take<RkJacobi>((size_t)batch);
+  R.ddj = ar.take<DJob>((size_t)batch);
   R.dcj = ar.take<CondJacobi>((size_t)batch);
   R.drf = ar.take<RefJob>((size_t)batch);
   int Rmax = 1;
@@ -1815,36 +1817,56 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
         R.ej(EJ_COLDIV, (long long)p * R1, f.c[k].usv, f.c[k].sig, f.c[k].usv, nullptr, nullptr, 0, 0, 0, p);
       }
       TT_TRY(R.elem());
-      // tall cores that kept a very small singular value: Jacobi on M_k
+      // tall cores that kept a very small singular value: Mt = M_k V in
+      // double-double (into jw), then one-sided Jacobi on Mt (M_k's buffer as
+      // its scratch)
       std::vector<RefJob> rf(batch);
+      std::vector<DJob> dj(batch);
       std::vector<CondJacobi> cj(batch);
+      long long dmax = 1;
       for (int b = 0; b < batch; ++b) {
         RadjFilter& f = F[b];
         memset(&rf[b], 0, sizeof(RefJob));
+        memset(&dj[b], 0, sizeof(DJob));
         memset(&cj[b], 0, sizeof(CondJacobi));
         if (k == 0 && f.wide0) continue;
         const int R1 = f.Ra[k + 1], p = f.ry[k] * f.n[k];
         rf[b].sig = f.c[k].sig;
         rf[b].r = f.ry[k + 1];
         rf[b].flag = f.c[k].flag;
+        DJob& q = dj[b];
+        q.vs = f.c[k].vs;
+        q.M = f.c[k].M;
+        q.sig = f.c[k].sig;
+        q.usv = f.c[k].jw;
+        q.flag = f.c[k].flag;
+        q.p = p;
+        q.R1 = R1;
         JacobiArgs& ja = cj[b].ja;
         ja.rows = p;
         ja.ncols = R1;
         ja.tol2 = 1e-30;
-        ja.x = f.c[k].M;
+        ja.x = f.c[k].jw;
         ja.ldx = R1;
-        ja.work = f.c[k].jw;
+        ja.work = f.c[k].M;
         ja.sigma = f.c[k].sig;
         ja.usv = f.c[k].usv;
         ja.gcap = p;
         cj[b].flag = f.c[k].flag;
-        TT_TRY(R.check(f.ry[k + 1] <= R1 && R.inside(ja.x, (long long)p * R1 - 1) &&
-                           R.inside(ja.work, (long long)R1 * p - 1) && R.inside(ja.usv, (long long)R1 * p - 1),
-                       "jacobi on M_k"));
+        TT_TRY(R.check(f.ry[k + 1] <= R1 && R.inside(q.M, (long long)p * R1 - 1) &&
+                           R.inside(q.vs, (long long)R1 * R1 - 1) && R.inside(q.usv, (long long)R1 * p - 1) &&
+                           R.inside(q.sig, R1 - 1) && R.inside(ja.work, (long long)R1 * p - 1) &&
+                           R.inside(ja.usv, (long long)R1 * p - 1),
+                       "refinement"));
+        dmax = std::max(dmax, (long long)p * R1);
       }
       TT_TRY(upload(R.drf, rf, st));
       hipLaunchKernelGGL(radj_refine_flag_kernel, dim3(cdiv(batch, 64)), dim3(64), 0, st, R.drf, batch);
       TTG_LAUNCH_CHECK("radj_refine_flag_kernel");
+      TT_TRY(upload(R.ddj, dj, st));
+      hipLaunchKernelGGL(radj_ddprod_kernel, dim3((int)std::min<long long>(cdiv(dmax, 256), 4096), batch), dim3(256),
+                         0, st, R.ddj);
+      TTG_LAUNCH_CHECK("radj_ddprod_kernel");
       TT_TRY(upload(R.dcj, cj, st));
       TT_TRY(launch_jacobi(FAdjJacobiIf{R.dcj}, batch, st));
     }

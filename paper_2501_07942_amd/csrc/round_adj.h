@@ -324,10 +324,14 @@ struct FAdjJacobiRk {
   }
 };
 
-// The SVD of a tall M_k from its Gram gives u_c = M_k v_c / sigma_c, whose
-// error grows like eps * sigma_1 / sigma_c.  When a rounding kept a singular
-// value below RADJ_REFINE * sigma_1 the vectors are recomputed by one-sided
-// Jacobi on M_k itself (accurate for every column, slower): flag per job.
+// The SVD of a tall M_k from its Gram gives sigma_c u_c = M_k v_c with v_c
+// from the Jacobi SVD of the FP64 Cholesky factor; a singular vector u_c of
+// a very small sigma_c then carries errors of order eps * sigma_1 / sigma_c.
+// When a rounding kept a singular value below RADJ_REFINE * sigma_1 the SVD
+// is refined: Mt = M_k V (the product summed in double-double, so each
+// column is exact to its own size) has nearly orthogonal columns graded by
+// sigma_c, and one-sided Jacobi on Mt removes what is left in a sweep or
+// two, with accuracy relative to each column.  Flag per job.
 #define RADJ_REFINE 1e-8
 struct RefJob {
   const double* sig;
@@ -353,5 +357,36 @@ struct FAdjJacobiIf {
     return J.rows > 0 && J.ncols > 0 && a[b].flag && *a[b].flag != 0;
   }
 };
+
+// Mt(:, c) = M vs(:, c) / sigma_c summed in double-double, for flagged jobs
+// (columns with sigma_c = 0 are zero).  M: p x R1 row-major; vs: column-major
+// R1 x R1 (column c = sigma_c v_c); Mt: p x R1 row-major.  Grid: (blocks, jobs).
+struct DJob {
+  const double* vs;
+  const double* M;
+  const double* sig;
+  double* usv;  // Mt
+  const int* flag;
+  int p, R1;
+};
+__global__ void __launch_bounds__(256) radj_ddprod_kernel(const DJob* __restrict__ jobs) {
+  const DJob j = jobs[blockIdx.y];
+  if (!j.flag || *j.flag == 0) return;
+  const long long tot = (long long)j.p * j.R1;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < tot; e += stride) {
+    const int row = (int)(e / j.R1), c = (int)(e - (long long)row * j.R1);
+    const double sc = j.sig[c];
+    if (!(sc > 0.0)) {
+      j.usv[e] = 0.0;
+      continue;
+    }
+    const double* vc = j.vs + (long long)c * j.R1;
+    const double* mr = j.M + (long long)row * j.R1;
+    dd acc = AccDD::zero();
+    for (int q = 0; q < j.R1; ++q) acc = AccDD::fma_(acc, vc[q], mr[q]);
+    j.usv[e] = dd_div(acc, AccDD::from(sc)).hi;
+  }
+}
 
 }  // namespace ttg
