@@ -1388,8 +1388,8 @@ struct RadjRun {
       tiles += std::max(1, (j.M + 63) / 64) * j.tn;
     }
     TT_TRY(upload(dg, g, st));
-    hipLaunchKernelGGL(gjob_gemm_kernel, dim3(tiles), dim3(256), 0, st, dg, (int)g.size());
-    TTG_LAUNCH_CHECK("gjob_gemm_kernel");
+    hipLaunchKernelGGL(gjob_mfma_kernel, dim3(tiles), dim3(256), 0, st, dg, (int)g.size());
+    TTG_LAUNCH_CHECK("gjob_mfma_kernel");
     g.clear();
     return TT_OK;
   }

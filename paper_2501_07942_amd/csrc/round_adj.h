@@ -119,6 +119,65 @@ __global__ void __launch_bounds__(256) gjob_gemm_kernel(const GJob* __restrict__
     }
 }
 
+// The same job table on the matrix cores: one 64 x 64 tile per workgroup,
+// wavefront w owns rows 16 w .. 16 w + 15 and the four 16-column tiles, each
+// 16 x 16 x 4 FP64 MFMA step reads A(i, k) in lane i + 16 k and B(k, j) in
+// lane j + 16 k from the LDS stage; D(i, j) sits in lane j + 16 (i % 4),
+// register i / 4.  Every element sums its k in MFMA chunks of four in
+// increasing order, independent of the other jobs.
+typedef double gj_d4 __attribute__((ext_vector_type(4)));
+__global__ void __launch_bounds__(256) gjob_mfma_kernel(const GJob* __restrict__ jobs, int njobs) {
+  const int t = blockIdx.x;
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].tile0 <= t)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const GJob g = jobs[lo];
+  const int lt = t - g.tile0;
+  const int m0 = (lt / g.tn) * 64, n0 = (lt - (lt / g.tn) * g.tn) * 64;
+  if (m0 >= g.M || n0 >= g.N) return;
+  __shared__ double As[16][64 + 1];
+  __shared__ double Bs[16][64 + 1];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  gj_d4 acc[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) acc[j] = gj_d4{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < g.K; k0 += 16) {
+    for (int e = threadIdx.x; e < 64 * 16; e += 256) {
+      const int mm = e >> 4, kk = e & 15;
+      const int m = m0 + mm, k = k0 + kk;
+      As[kk][mm] = (m < g.M && k < g.K) ? g.a[(long long)m * g.sam + (long long)k * g.sak] : 0.0;
+      const int kb = e >> 6, nn = e & 63;
+      const int n = n0 + nn, k2 = k0 + kb;
+      Bs[kb][nn] = (n < g.N && k2 < g.K) ? g.b[(long long)k2 * g.sbk + (long long)n * g.sbn] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 4) {
+      const double av = As[kk + lk][16 * w + li];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Bs[kk + lk][16 * j + li], acc[j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int m = m0 + 16 * w + 4 * v + lk, n = n0 + 16 * j + li;
+      if (m < g.M && n < g.N) {
+        double* cp = g.c + (long long)m * g.scm + (long long)n * g.scn;
+        *cp = g.beta == 0.0 ? g.alpha * acc[j][v] : __fma_rn(g.alpha, acc[j][v], g.beta * *cp);
+      }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // elementwise passes; blockIdx.y selects the job
 // ---------------------------------------------------------------------------
