@@ -126,11 +126,17 @@ def loglik_grad(specs: Sequence, zs: Sequence[np.ndarray], thetas=None, h_rel: f
 class TTFilterLogLik:
     """torch.autograd.Function-style wrapper: apply(theta, specs, zs) returns
     LL[B] as a float64 tensor whose backward gives dLL/dtheta.  theta is
-    [n_theta] (shared by the batch) or [B, n_theta]."""
+    [n_theta] (shared by the batch) or [B, n_theta].  method "adjoint" (the
+    default) takes the gradient from the reverse sweep of
+    adjoint_grad.loglik_grad_adjoint (forward with checkpoints, adjoints of
+    every step); "differences" from the batched rank-replay central
+    differences of loglik_grad."""
 
     @staticmethod
-    def apply(theta, specs, zs, h_rel: float = 1e-5):
+    def apply(theta, specs, zs, h_rel: float = 1e-5, method: str = "adjoint"):
         import torch
+        if method not in ("adjoint", "differences"):
+            raise ValueError(f"unknown gradient method {method!r}")
 
         class _Fn(torch.autograd.Function):
             @staticmethod
@@ -138,7 +144,11 @@ class TTFilterLogLik:
                 tcpu = th.detach().cpu().numpy().astype(np.float64)
                 shared = tcpu.ndim == 1
                 thetas = np.tile(tcpu, (len(specs), 1)) if shared else tcpu
-                ll, g, _ = loglik_grad(specs, zs, thetas, h_rel)
+                if method == "adjoint":
+                    from . import adjoint_grad
+                    ll, g, _ = adjoint_grad.loglik_grad_adjoint(specs, zs, thetas, h_rel)
+                else:
+                    ll, g, _ = loglik_grad(specs, zs, thetas, h_rel)
                 ctx.shared = shared
                 ctx.save_for_backward(torch.as_tensor(g, dtype=th.dtype, device=th.device))
                 return torch.as_tensor(ll, dtype=th.dtype, device=th.device)

@@ -85,9 +85,23 @@ def test_autograd_wrapper(mods):
     specs, xs, zs = wl.make_batch("range4d", batch=2, steps=4, d=3, n=24, cap=5)
     th0 = G.theta_of(specs[0])
     theta = torch.tensor(th0, dtype=torch.float64, requires_grad=True)
-    ll = G.TTFilterLogLik.apply(theta, specs, zs)
     w = torch.tensor([0.25, -1.5], dtype=torch.float64)
+    # rank-replay differences behind the wrapper
+    ll = G.TTFilterLogLik.apply(theta, specs, zs, method="differences")
     (ll * w).sum().backward()
     ll_ref, g_ref, _ = G.loglik_grad(specs, zs, np.tile(th0, (2, 1)))
     assert np.allclose(ll.detach().numpy(), ll_ref, rtol=0, atol=0)
     assert np.allclose(theta.grad.numpy(), 0.25 * g_ref[0] - 1.5 * g_ref[1], rtol=1e-12, atol=0)
+    # the reverse sweep (default): same value as the composed adjoint, and
+    # the same gradient as the differences to their accuracy
+    from paper_2501_07942_amd import adjoint_grad as AG
+    theta.grad = None
+    ll = G.TTFilterLogLik.apply(theta, specs, zs)
+    (ll * w).sum().backward()
+    ll_a, g_a, _ = AG.loglik_grad_adjoint(specs, zs, np.tile(th0, (2, 1)))
+    assert np.array_equal(ll.detach().numpy(), ll_a)
+    assert np.allclose(theta.grad.numpy(), 0.25 * g_a[0] - 1.5 * g_a[1], rtol=1e-12, atol=0)
+    gw = 0.25 * g_ref[0] - 1.5 * g_ref[1]
+    assert np.abs(theta.grad.numpy() - gw).max() < 1e-5 * np.abs(gw).max()
+    with pytest.raises(ValueError):
+        G.TTFilterLogLik.apply(theta, specs, zs, method="fd")
