@@ -202,6 +202,7 @@ class ComposedGradient:
         d = self.specs[0].d
         g = np.zeros((self.Bn, nt))
         boxes = [s.halfwidths() for s in self.specs]
+        built = []
         for j in range(nt):
             hs = h_rel * np.maximum(1.0, np.abs(thetas[:, j]))
             vals = []
@@ -211,18 +212,26 @@ class ComposedGradient:
                 sp = [G.spec_at(s, t, bx) for s, t, bx in zip(self.specs, th, boxes)]
                 acc = self.torch.zeros(self.Bn, dtype=self.torch.float64, device="cuda")
                 if j < d:
+                    # built straight into the base kernels' capacities (their
+                    # ranks): no host round trip; statuses checked at the end
                     kp = []
-                    for s in sp:
-                        ks, _, _ = runner.build_kernels([s], B.F64)
-                        kp.append(ks[0])
+                    for s, kb in zip(sp, self.kern):
+                        kt = B.DeviceTT(kb.n, kb.cap, B.F64)
+                        B.tt_kernel_build(runner.grid_of(s), s.q, s.halfwidths(), s.kernel_tol, kt)
+                        kp.append(kt)
                     B.tt_align_signs(self.kern, kp)
                     acc += self._inner(self.kbar, kp)
+                    built.extend(kp)
                 else:
                     meas = [runner.meas_of(s) for s in sp]
                     for k in range(self.K):
                         acc += self._inner(self.lbar[k], self._dense_likelihood(k, meas))
                 vals.append(acc)
             g[:, j] = ((vals[0] - vals[1]).cpu().numpy()) / (2.0 * hs)
+        if built:
+            st = self.torch.stack([t.status for t in built]).cpu().numpy()
+            if np.any(st != 0):
+                raise B.TTError(f"perturbed kernel builds set status bits {np.unique(st)} (a rank moved)")
         return g
 
 

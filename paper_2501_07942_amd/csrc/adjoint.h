@@ -205,31 +205,46 @@ __global__ void __launch_bounds__(256) sum_env_kernel(const DevTT* __restrict__ 
     right[(long long)d * rcap] = 1.0;
   }
   __syncthreads();
+  __shared__ double part[256];
+  // left[k+1](b) = sum over rows (a, i) of left[k](a) X_k(a, i, b): groups of
+  // nb threads own the columns, the groups split the rows, an LDS pass sums
+  // the groups (blockDim.x = 256)
   for (int k = 0; k < d; ++k) {
     const int r0 = X.ranks[k], r1 = X.ranks[k + 1], n = X.n[k];
     const T* xc = core_ptr<T>(X, k);
-    for (int b = threadIdx.x; b < r1; b += blockDim.x) {
+    const double* lk = left + (long long)k * rcap;
+    const int nb = min(r1, 256), G = 256 / nb;
+    const int g = threadIdx.x / nb, tb = threadIdx.x - (threadIdx.x / nb) * nb;
+    const long long rows = (long long)r0 * n;
+    for (int b0 = 0; b0 < r1; b0 += nb) {
+      const int b = b0 + tb;
       double acc = 0.0;
-      for (int a = 0; a < r0; ++a) {
-        double s = 0.0;
-        for (int i = 0; i < n; ++i) s += bulk_to_double(xc[((long long)a * n + i) * r1 + b]);
-        acc += left[(long long)k * rcap + a] * s;
+      if (g < G && b < r1)
+        for (long long row = g; row < rows; row += G) acc += lk[row / n] * bulk_to_double(xc[row * r1 + b]);
+      part[threadIdx.x] = acc;
+      __syncthreads();
+      if (threadIdx.x < nb && b < r1) {
+        double t = 0.0;
+        for (int q = 0; q < G; ++q) t += part[q * nb + tb];
+        left[(long long)(k + 1) * rcap + b] = t;
       }
-      left[(long long)(k + 1) * rcap + b] = acc;
+      __syncthreads();
     }
-    __syncthreads();
   }
+  // right[k](a) = sum over (i, b) of X_k(a, i, b) right[k+1](b): one
+  // wavefront per row a, lanes over the contiguous (i, b) block
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
   for (int k = d - 1; k >= 0; --k) {
     const int r0 = X.ranks[k], r1 = X.ranks[k + 1], n = X.n[k];
     const T* xc = core_ptr<T>(X, k);
-    for (int a = threadIdx.x; a < r0; a += blockDim.x) {
+    const double* rk1 = right + (long long)(k + 1) * rcap;
+    const long long len = (long long)n * r1;
+    for (int a = wv; a < r0; a += nw) {
+      const T* row = xc + (long long)a * len;
       double acc = 0.0;
-      for (int b = 0; b < r1; ++b) {
-        double s = 0.0;
-        for (int i = 0; i < n; ++i) s += bulk_to_double(xc[((long long)a * n + i) * r1 + b]);
-        acc += s * right[(long long)(k + 1) * rcap + b];
-      }
-      right[(long long)k * rcap + a] = acc;
+      for (long long e = lane; e < len; e += 64) acc += bulk_to_double(row[e]) * rk1[e % r1];
+      for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+      if (lane == 0) right[(long long)k * rcap + a] = acc;
     }
     __syncthreads();
   }
