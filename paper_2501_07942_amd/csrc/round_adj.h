@@ -140,25 +140,41 @@ __global__ void __launch_bounds__(256) gjob_mfma_kernel(const GJob* __restrict__
   const int lt = t - g.tile0;
   const int m0 = (lt / g.tn) * 64, n0 = (lt - (lt / g.tn) * g.tn) * 64;
   if (m0 >= g.M || n0 >= g.N) return;
-  __shared__ double As[16][64 + 1];
-  __shared__ double Bs[16][64 + 1];
+  // K blocks of 32; the next block is fetched into registers while the
+  // current one is multiplied out of the LDS
+  constexpr int KB = 32;
+  __shared__ double As[KB][64 + 1];
+  __shared__ double Bs[KB][64 + 1];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   gj_d4 acc[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) acc[j] = gj_d4{0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < g.K; k0 += 16) {
-    for (int e = threadIdx.x; e < 64 * 16; e += 256) {
-      const int mm = e >> 4, kk = e & 15;
+  double ra[8], rb[8];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      const int mm = e >> 5, kk = e & 31;  // A: 64 rows x 32 k
       const int m = m0 + mm, k = k0 + kk;
-      As[kk][mm] = (m < g.M && k < g.K) ? g.a[(long long)m * g.sam + (long long)k * g.sak] : 0.0;
-      const int kb = e >> 6, nn = e & 63;
+      ra[u] = (m < g.M && k < g.K) ? g.a[(long long)m * g.sam + (long long)k * g.sak] : 0.0;
+      const int kb = e >> 6, nn = e & 63;  // B: 32 k x 64 columns
       const int n = n0 + nn, k2 = k0 + kb;
-      Bs[kb][nn] = (n < g.N && k2 < g.K) ? g.b[(long long)k2 * g.sbk + (long long)n * g.sbn] : 0.0;
+      rb[u] = (n < g.N && k2 < g.K) ? g.b[(long long)k2 * g.sbk + (long long)n * g.sbn] : 0.0;
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < g.K; k0 += KB) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      As[e & 31][e >> 5] = ra[u];
+      Bs[e >> 6][e & 63] = rb[u];
     }
     __syncthreads();
+    if (k0 + KB < g.K) fetch(k0 + KB);
 #pragma unroll
-    for (int kk = 0; kk < 16; kk += 4) {
+    for (int kk = 0; kk < KB; kk += 4) {
       const double av = As[kk + lk][16 * w + li];
 #pragma unroll
       for (int j = 0; j < 4; ++j)
