@@ -20,8 +20,9 @@ the range block's truncated SVD (tt_likelihood_adjoint) onto the dense
 likelihood P_k, whose parameter tangent is smooth; the kernel contribution
 <Kbar, dK/dtheta> uses the tangent of the kernel's TT-SVD as the central
 difference of the builds at theta +- h aligned to the base build's bond
-bases (tt_align_signs).  Both tangents are central differences of
-dense-in-theta quantities; the recursion itself is differentiated exactly.
+bases (tt_align_signs).  Both tangents are central differences (or, optionally,
+forward differences from the base builds) of dense-in-theta quantities; the
+recursion itself is differentiated exactly.
 Ranks of every rounding are those of the forward run (the same
 deterministic calls reproduce them).
 """
@@ -197,16 +198,33 @@ class ComposedGradient:
         B.tt_adjoint_inner(abar, b, out)
         return out
 
-    def theta_grad(self, thetas: np.ndarray, h_rel: float = 1e-5) -> np.ndarray:
+    def theta_grad(self, thetas: np.ndarray, h_rel: Optional[float] = None, scheme: str = "central") -> np.ndarray:
+        """dLL/dtheta from the adjoints: the tangents of the kernel builds and
+        of the dense likelihoods by central differences (scheme "central",
+        h = 1e-5 max(1,|theta|) by default) or by forward differences from
+        the base builds ("forward", 1e-7: one perturbed build per parameter
+        instead of two, but the kernel TT-SVD's truncation noise, about 1e-12
+        of the kernel, divided by h limits it to about 1e-4 relative)."""
+        if scheme not in ("forward", "central"):
+            raise ValueError(f"unknown difference scheme {scheme!r}")
+        if h_rel is None:
+            h_rel = 1e-7 if scheme == "forward" else 1e-5
         nt = thetas.shape[1]
         d = self.specs[0].d
         g = np.zeros((self.Bn, nt))
         boxes = [s.halfwidths() for s in self.specs]
         built = []
+        signs = (1.0,) if scheme == "forward" else (1.0, -1.0)
+        base_k = base_l = None
+        if scheme == "forward":
+            base_k = self._inner(self.kbar, self.kern)
+            base_l = self.torch.zeros(self.Bn, dtype=self.torch.float64, device="cuda")
+            for k in range(self.K):
+                base_l += self._inner(self.lbar[k], self._dense_likelihood(k))
         for j in range(nt):
             hs = h_rel * np.maximum(1.0, np.abs(thetas[:, j]))
             vals = []
-            for sgn in (1.0, -1.0):
+            for sgn in signs:
                 th = thetas.copy()
                 th[:, j] += sgn * hs
                 sp = [G.spec_at(s, t, bx) for s, t, bx in zip(self.specs, th, boxes)]
@@ -227,7 +245,11 @@ class ComposedGradient:
                     for k in range(self.K):
                         acc += self._inner(self.lbar[k], self._dense_likelihood(k, meas))
                 vals.append(acc)
-            g[:, j] = ((vals[0] - vals[1]).cpu().numpy()) / (2.0 * hs)
+            if scheme == "forward":
+                base = base_k if j < d else base_l
+                g[:, j] = ((vals[0] - base).cpu().numpy()) / hs
+            else:
+                g[:, j] = ((vals[0] - vals[1]).cpu().numpy()) / (2.0 * hs)
         if built:
             st = self.torch.stack([t.status for t in built]).cpu().numpy()
             if np.any(st != 0):
@@ -236,9 +258,10 @@ class ComposedGradient:
 
 
 def loglik_grad_adjoint(specs: Sequence, zs: Sequence[np.ndarray], thetas: Optional[np.ndarray] = None,
-                        h_rel: float = 1e-5, lik_rank_cap: int = 64):
+                        h_rel: Optional[float] = None, lik_rank_cap: int = 64, scheme: str = "central"):
     """LL [B] and dLL/dtheta [B, n_theta] by the composed reverse sweep
-    (FP64).  thetas: [B, n_theta] (None: each spec's own parameters)."""
+    (FP64).  thetas: [B, n_theta] (None: each spec's own parameters);
+    h_rel, scheme: the differences of the parameter tangents (theta_grad)."""
     specs = list(specs)
     if thetas is None:
         thetas = np.array([G.theta_of(s) for s in specs])
@@ -247,4 +270,4 @@ def loglik_grad_adjoint(specs: Sequence, zs: Sequence[np.ndarray], thetas: Optio
     cg = ComposedGradient(sp, zs, lik_rank_cap)
     ll = cg.forward()
     cg.reverse()
-    return ll, cg.theta_grad(np.asarray(thetas, dtype=np.float64), h_rel), cg
+    return ll, cg.theta_grad(np.asarray(thetas, dtype=np.float64), h_rel, scheme), cg

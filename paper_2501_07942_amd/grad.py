@@ -130,7 +130,7 @@ class TTFilterLogLik:
     default) takes the gradient from the reverse sweep of
     adjoint_grad.loglik_grad_adjoint (forward with checkpoints, adjoints of
     every step); "differences" from the batched rank-replay central
-    differences of loglik_grad."""
+    differences of loglik_grad (step h_rel)."""
 
     @staticmethod
     def apply(theta, specs, zs, h_rel: float = 1e-5, method: str = "adjoint"):
@@ -146,7 +146,7 @@ class TTFilterLogLik:
                 thetas = np.tile(tcpu, (len(specs), 1)) if shared else tcpu
                 if method == "adjoint":
                     from . import adjoint_grad
-                    ll, g, _ = adjoint_grad.loglik_grad_adjoint(specs, zs, thetas, h_rel)
+                    ll, g, _ = adjoint_grad.loglik_grad_adjoint(specs, zs, thetas)
                 else:
                     ll, g, _ = loglik_grad(specs, zs, thetas, h_rel)
                 ctx.shared = shared

@@ -37,7 +37,13 @@ def test_adjoint_gradient_binding_cap_batch(mods):
     print("composed adjoint: 2 filters, d=3, N=32, cap 6, 5 steps", flush=True)
     ll, g, _ = AG.loglik_grad_adjoint(specs, zs)
     ll_fd, g_fd, _ = G.loglik_grad(specs, zs)
+    # the parameter tangents by forward instead of central differences
+    _, g_f, _ = AG.loglik_grad_adjoint(specs, zs, scheme="forward")
+    with pytest.raises(ValueError):
+        AG.loglik_grad_adjoint(specs, zs, scheme="backward")
     for b in range(2):
+        print(f"  filter {b}: forward vs central tangents {rel(g_f[b], g[b]):.1e}", flush=True)
+        assert rel(g_f[b], g[b]) < 1e-5
         ctx = ctx_of(specs[b], zs[b])
         base = og.loglik_tt(G.theta_of(specs[b]), ctx)
         # same log-likelihood as the oracle and the fused forward
@@ -56,11 +62,17 @@ def test_adjoint_gradient_linear_gaussian(mods):
     AG, G, wl = mods
     s = wl.spec_kf2d()
     x, z = wl.simulate(s, 12, np.random.SeedSequence(11))
+    # tangents by central differences (O(h^2), h = 1e-5, the default)
     ll, g, _ = AG.loglik_grad_adjoint([s], [z])
     ctx, th = ctx_of(s, z), G.theta_of(s)
-    print(f"  linear Gaussian: vs dense {rel(g[0], og.grad_complex_step(og.loglik_dense_cs, th, ctx)):.1e}", flush=True)
-    assert rel(g[0], og.grad_complex_step(og.loglik_dense_cs, th, ctx)) < 1e-8
+    g_dense = og.grad_complex_step(og.loglik_dense_cs, th, ctx)
+    print(f"  linear Gaussian: vs dense {rel(g[0], g_dense):.1e}", flush=True)
+    assert rel(g[0], g_dense) < 1e-8
     assert rel(g[0], og.grad_complex_step(og.loglik_kalman_cs, th, ctx)) < 1e-7
+    # forward differences (O(h), h = 1e-7)
+    _, g_f, _ = AG.loglik_grad_adjoint([s], [z], scheme="forward")
+    print(f"  linear Gaussian, forward tangents: vs dense {rel(g_f[0], g_dense):.1e}", flush=True)
+    assert rel(g_f[0], g_dense) < 1e-6
 
 
 def test_adjoint_gradient_loose_cap_matches_dense_complex_step(mods):
