@@ -129,6 +129,17 @@ size_t tt_kernel_build_workspace(const tt_grid* grid, const int32_t* halfwidths,
 tt_status tt_kernel_build(const tt_grid* grid, const double* q, const int32_t* halfwidths,
                           double svd_tol, const tt_train* out, void* ws, size_t ws_bytes,
                           void* stream);
+/* tt_kernel_build_batch -- the same build for `batch` kernels at once (one
+ * launch per step for all of them).  grids[batch] and q[batch*d*d] may
+ * differ per kernel; d and the offset box (halfwidths, d entries) are
+ * shared; out[batch] may have different capacities but one dtype.
+ * Workspace: tt_kernel_build_batch_workspace(batch, grids, halfwidths,
+ * caps) with caps[b*(d+1) + j] = out[b].cap[j]; it holds two dense kernels
+ * per filter (batch * prod(2h_l+1) doubles each). */
+size_t tt_kernel_build_batch_workspace(int32_t batch, const tt_grid* grids, const int32_t* halfwidths,
+                                       const int32_t* caps);
+tt_status tt_kernel_build_batch(int32_t batch, const tt_grid* grids, const double* q, const int32_t* halfwidths,
+                                double svd_tol, const tt_train* out, void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------
  * tt_predict -- Chapman-Kolmogorov prediction for x_{k+1} = x_k + w_k as

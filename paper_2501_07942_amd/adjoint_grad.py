@@ -231,12 +231,15 @@ class ComposedGradient:
                 acc = self.torch.zeros(self.Bn, dtype=self.torch.float64, device="cuda")
                 if j < d:
                     # built straight into the base kernels' capacities (their
-                    # ranks): no host round trip; statuses checked at the end
-                    kp = []
-                    for s, kb in zip(sp, self.kern):
-                        kt = B.DeviceTT(kb.n, kb.cap, B.F64)
-                        B.tt_kernel_build(runner.grid_of(s), s.q, s.halfwidths(), s.kernel_tol, kt)
-                        kp.append(kt)
+                    # ranks), one batched build per offset box and tolerance;
+                    # statuses checked at the end
+                    kp = [B.DeviceTT(kb.n, kb.cap, B.F64) for kb in self.kern]
+                    groups = {}
+                    for i, s in enumerate(sp):
+                        groups.setdefault((tuple(int(h) for h in s.halfwidths()), s.kernel_tol), []).append(i)
+                    for (hw, tol), idx in groups.items():
+                        B.tt_kernel_build_batch([runner.grid_of(sp[i]) for i in idx], [sp[i].q for i in idx], hw, tol,
+                                                [kp[i] for i in idx])
                     B.tt_align_signs(self.kern, kp)
                     acc += self._inner(self.kbar, kp)
                     built.extend(kp)

@@ -82,6 +82,8 @@ def _load():
         "tt_round_adjoint": (I, [I, P, P, P, P, P, S, P]),
         "tt_prior": (I, [I, P, P, P, P, P, S, P]),
         "tt_likelihood": (I, [I, P, P, P, I, P, I, P, S, P]),
+        "tt_kernel_build_batch_workspace": (S, [I, P, P, P]),
+        "tt_kernel_build_batch": (I, [I, P, P, P, D, P, P, S, P]),
         "tt_likelihood_dense": (I, [I, P, P, P, I, P, P, S, P]),
         "tt_likelihood_adjoint_workspace": (S, [I, P, P, P]),
         "tt_likelihood_adjoint": (I, [I, P, P, P, P, P, P, S, P]),
@@ -111,6 +113,7 @@ EXPORTED = ("tt_train_elems", "tt_last_error", "tt_version", "tt_kernel_build_wo
             "tt_filter_graph_launch", "tt_filter_graph_destroy", "tt_autotune_prediction",
             "tt_adjoint_workspace", "tt_predict_adjoint", "tt_hadamard_adjoint", "tt_normalize_adjoint",
             "tt_round_adjoint_workspace", "tt_round_adjoint", "tt_prior", "tt_likelihood", "tt_likelihood_dense",
+            "tt_kernel_build_batch_workspace", "tt_kernel_build_batch",
             "tt_likelihood_adjoint_workspace", "tt_likelihood_adjoint", "tt_adjoint_axpy",
             "tt_adjoint_inner", "tt_align_signs")
 
@@ -278,6 +281,25 @@ def tt_kernel_build(grid: Grid, q: np.ndarray, halfwidths: Sequence[int], svd_to
     _check(LIB.tt_kernel_build(C.byref(grid), qq, hw, float(svd_tol), C.byref(t), ws.data_ptr(),
                                ws.numel(), _stream()), "tt_kernel_build")
     return out
+
+
+def tt_kernel_build_batch(grids: Sequence[Grid], qs: Sequence[np.ndarray], halfwidths: Sequence[int],
+                          svd_tol: float, outs: Sequence[DeviceTT]):
+    """tt_kernel_build for several kernels sharing d and the offset box."""
+    B = len(outs)
+    d = grids[0].d
+    hw = (C.c_int32 * d)(*[int(h) for h in halfwidths])
+    qq = np.ascontiguousarray(np.stack([np.asarray(q, dtype=np.float64).reshape(d, d) for q in qs]))
+    caps = (C.c_int32 * (B * (d + 1)))(*[int(c) for o in outs for c in o.cap])
+    g = _arr(list(grids))
+    nbytes = LIB.tt_kernel_build_batch_workspace(B, g, hw, caps)
+    if nbytes == 0:
+        _check(ERR_ARG, "tt_kernel_build_batch_workspace")
+    ws = _ws(nbytes)
+    _check(LIB.tt_kernel_build_batch(B, g, qq.ctypes.data_as(C.c_void_p), hw, float(svd_tol),
+                                     _arr([o.struct() for o in outs]), ws.data_ptr(), ws.numel(), _stream()),
+           "tt_kernel_build_batch")
+    return outs
 
 
 def tt_predict(kernels: Sequence[DeviceTT], p_in: Sequence[DeviceTT], p_out: Sequence[DeviceTT]):

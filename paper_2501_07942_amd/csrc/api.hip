@@ -2256,11 +2256,12 @@ static tt_status lik_launch(int B, const DevTT* dL, const RoundScratch* drs, con
 struct KsvdCtx {
   const DevTT* K;  // FP64 result
   const RoundScratch* S;
-  const double* a;   // current unfolding (row-major rows x cols)
+  const double* a;   // current unfolding (row-major rows x cols), filter b at a + b * bstride
   double* next;      // next unfolding
   long long cols;    // columns of the current unfolding
   int k;
   int d;
+  long long bstride;  // elements between the unfoldings of consecutive filters
 };
 struct FKsvdGram {
   KsvdCtx c;
@@ -2269,7 +2270,7 @@ struct FKsvdGram {
     const RoundScratch& s = c.S[b];
     g.M = K.ranks[c.k] * K.n[c.k];
     g.T = (int)c.cols;
-    g.x = c.a;
+    g.x = c.a + b * c.bstride;
     g.sa = c.cols;
     g.st = 1;
     g.out = s.gram;
@@ -2326,10 +2327,10 @@ struct FKsvdNext {  // next = U_r^T A
     g.a = core_ptr<double>(K, c.k);
     g.sam = 1;
     g.sak = r;
-    g.b = c.a;
+    g.b = c.a + b * c.bstride;
     g.sbk = c.cols;
     g.sbn = 1;
-    g.c = c.next;
+    g.c = c.next + b * c.bstride;
     g.scm = c.cols;
     g.scn = 1;
     return true;
@@ -2338,8 +2339,8 @@ struct FKsvdNext {  // next = U_r^T A
 
 __global__ void ksvd_select_kernel(const DevTT* __restrict__ Kt, const RoundScratch* __restrict__ S, int k,
                                    double tol) {
-  const DevTT& K = Kt[0];
-  const RoundScratch& s = S[0];
+  const DevTT& K = Kt[blockIdx.x];
+  const RoundScratch& s = S[blockIdx.x];
   __shared__ int s_r;
   const int nc = s.misc[0];
   const int rows = K.ranks[k] * K.n[k];
@@ -2384,14 +2385,15 @@ __global__ void ksvd_select_kernel(const DevTT* __restrict__ Kt, const RoundScra
 }
 
 __global__ void ksvd_init_kernel(const DevTT* __restrict__ Kt) {
-  const DevTT& K = Kt[0];
+  const DevTT& K = Kt[blockIdx.x];
   for (int j = 0; j <= K.d; ++j) K.ranks[j] = 1;
   *K.log_scale = 0.0;
   *K.status = 0;
 }
 
-__global__ void ksvd_last_kernel(const DevTT* __restrict__ Kt, const double* __restrict__ a) {
-  const DevTT& K = Kt[0];
+__global__ void ksvd_last_kernel(const DevTT* __restrict__ Kt, const double* __restrict__ ab, long long bstride) {
+  const DevTT& K = Kt[blockIdx.y];
+  const double* a = ab + blockIdx.y * bstride;
   const int k = K.d - 1;
   const long long tot = (long long)K.ranks[k] * K.n[k];
   double* core = core_ptr<double>(K, k);
@@ -3408,20 +3410,23 @@ static bool invert_spd(int d, const double* q, double* inv, double* det) {
 struct KernelPlan {
   long long total;
   int taps[TT_MAXD];
-  double* dense;
-  double* buf2;
+  double* dense;  // batch x total
+  double* buf2;   // batch x total
   DevTT* dK64;
   DevTT* dKout;
   RoundScratch* drs;
-  DevTT k64;
-  RoundScratch rs;
+  KernelEvalArgs* dka;
+  std::vector<DevTT> k64;  // FP64 result per filter (the output itself when it is FP64)
+  std::vector<RoundScratch> rs;
   int gcap, splits;
 };
 
-static tt_status kernel_plan(const tt_grid* grid, const int32_t* halfwidths, const int32_t* cap, int out_dtype,
-                             Arena& ar, KernelPlan& kp) {
-  TT_TRY(check_grid(grid));
-  const int d = grid->d;
+// Buffers of a batched kernel build: every filter shares d and the offset
+// box (taps); grids, Q and rank capacities may differ.  outs == nullptr
+// sizes the FP64 staging TTs for FP32 outputs of the given capacities.
+static tt_status kernel_plan(int batch, const tt_grid* grids, const int32_t* halfwidths, const int32_t* caps,
+                             const int* out_dtypes, Arena& ar, KernelPlan& kp) {
+  const int d = grids[0].d;
   if (d > 8) {
     set_error("tt_kernel_build: dense build supports d <= 8");
     return TT_ERR_SHAPE;
@@ -3440,134 +3445,196 @@ static tt_status kernel_plan(const tt_grid* grid, const int32_t* halfwidths, con
     }
   }
   kp.total = total;
-  if (cap[0] != 1 || cap[d] != 1) {
-    set_error("tt_kernel_build: cap[0] and cap[d] must be 1");
-    return TT_ERR_SHAPE;
-  }
   int gcap = 1;
-  for (int k = 0; k < d; ++k) gcap = std::max(gcap, cap[k] * kp.taps[k]);
+  for (int b = 0; b < batch; ++b) {
+    TT_TRY(check_grid(&grids[b]));
+    if (grids[b].d != d) {
+      set_error("tt_kernel_build: d differs within the batch");
+      return TT_ERR_SHAPE;
+    }
+    const int32_t* cap = caps + (long long)b * (d + 1);
+    if (cap[0] != 1 || cap[d] != 1) {
+      set_error("tt_kernel_build: cap[0] and cap[d] must be 1");
+      return TT_ERR_SHAPE;
+    }
+    for (int k = 0; k < d; ++k) gcap = std::max(gcap, cap[k] * kp.taps[k]);
+  }
   if (gcap > 1024) {
     set_error("tt_kernel_build: cap*taps = %d exceeds 1024", gcap);
     return TT_ERR_SHAPE;
   }
+  if ((double)batch * (double)total > 4.0e9) {
+    set_error("tt_kernel_build: batch x dense kernel too large");
+    return TT_ERR_SHAPE;
+  }
   kp.gcap = gcap;
   kp.splits = GRAM_PLANES;
-  kp.dense = ar.take<double>(total);
-  kp.buf2 = ar.take<double>(total);
-  tt_train t64;
-  memset(&t64, 0, sizeof(t64));
-  t64.d = d;
-  t64.dtype = TT_F64;
-  for (int k = 0; k < d; ++k) t64.n[k] = kp.taps[k];
-  for (int j = 0; j <= d; ++j) t64.cap[j] = cap[j];
-  t64.cores = ar.take<double>(elems_of(d, t64.n, t64.cap));
-  t64.ranks = ar.take<int>(TT_MAXD + 1);
-  t64.log_scale = ar.take<double>(1);
-  t64.status = ar.take<int>(1);
-  kp.k64 = make_dev(t64);
-  kp.dK64 = ar.take<DevTT>(1);
-  kp.dKout = ar.take<DevTT>(1);
-  kp.drs = ar.take<RoundScratch>(1);
-  RoundScratch& rs = kp.rs;
-  memset(&rs, 0, sizeof(rs));
-  rs.gcap = gcap;
-  rs.splits = kp.splits;
-  const long long g2 = (long long)gcap * gcap;
-  rs.gram = ar.take<double>(g2 * 2 * kp.splits);
-  rs.lwork = ar.take<double>(g2 * 2);
-  rs.lfac = ar.take<double>(g2);
-  rs.jac = ar.take<double>(g2);
-  rs.sigma = ar.take<double>(gcap);
-  rs.usv = ar.take<double>(g2);
-  rs.piv = ar.take<int>(gcap);
-  rs.misc = ar.take<int>(8);
-  rs.scal = ar.take<double>(8);
-  (void)out_dtype;
+  kp.dense = ar.take<double>((size_t)batch * total);
+  kp.buf2 = ar.take<double>((size_t)batch * total);
+  kp.k64.assign(batch, DevTT{});
+  kp.rs.assign(batch, RoundScratch{});
+  for (int b = 0; b < batch; ++b) {
+    const int32_t* cap = caps + (long long)b * (d + 1);
+    if (!out_dtypes || out_dtypes[b] != TT_F64) {  // FP64 staging for an FP32 output
+      tt_train t64;
+      memset(&t64, 0, sizeof(t64));
+      t64.d = d;
+      t64.dtype = TT_F64;
+      for (int k = 0; k < d; ++k) t64.n[k] = kp.taps[k];
+      for (int j = 0; j <= d; ++j) t64.cap[j] = cap[j];
+      t64.cores = ar.take<double>(elems_of(d, t64.n, t64.cap));
+      t64.ranks = ar.take<int>(TT_MAXD + 1);
+      t64.log_scale = ar.take<double>(1);
+      t64.status = ar.take<int>(1);
+      kp.k64[b] = make_dev(t64);
+    }
+    RoundScratch& rs = kp.rs[b];
+    memset(&rs, 0, sizeof(rs));
+    rs.gcap = gcap;
+    rs.splits = kp.splits;
+    const long long g2 = (long long)gcap * gcap;
+    rs.gram = ar.take<double>(g2 * 2 * kp.splits);
+    rs.lwork = ar.take<double>(g2 * 2);
+    rs.lfac = ar.take<double>(g2);
+    rs.jac = ar.take<double>(g2);
+    rs.sigma = ar.take<double>(gcap);
+    rs.usv = ar.take<double>(g2);
+    rs.piv = ar.take<int>(gcap);
+    rs.misc = ar.take<int>(8);
+    rs.scal = ar.take<double>(8);
+  }
+  kp.dK64 = ar.take<DevTT>(batch);
+  kp.dKout = ar.take<DevTT>(batch);
+  kp.drs = ar.take<RoundScratch>(batch);
+  kp.dka = ar.take<KernelEvalArgs>(batch);
   return TT_OK;
 }
+
+static tt_status kernel_build_run(int batch, const tt_grid* grids, const double* q, const int32_t* halfwidths,
+                                  double svd_tol, const tt_train* out, void* ws, size_t ws_bytes, void* stream) {
+  if (batch < 1 || !grids || !q || !halfwidths || !out || !ws || !(svd_tol >= 0.0)) {
+    set_error("tt_kernel_build: bad arguments");
+    return TT_ERR_ARG;
+  }
+  const int d = grids[0].d;
+  std::vector<int32_t> caps((size_t)batch * (d + 1));
+  std::vector<int> dtypes(batch);
+  for (int b = 0; b < batch; ++b) {
+    TT_TRY(check_train(&out[b], "out"));
+    if (out[b].d != d) {
+      set_error("tt_kernel_build: out->d != grid->d");
+      return TT_ERR_SHAPE;
+    }
+    for (int k = 0; k < d; ++k)
+      if (out[b].n[k] != 2 * halfwidths[k] + 1) {
+        set_error("tt_kernel_build: out->n[%d] must be 2*h+1", k);
+        return TT_ERR_SHAPE;
+      }
+    for (int j = 0; j <= d; ++j) caps[(size_t)b * (d + 1) + j] = out[b].cap[j];
+    dtypes[b] = out[b].dtype;
+    if (dtypes[b] != dtypes[0]) {
+      set_error("tt_kernel_build: output dtypes differ within the batch");
+      return TT_ERR_ARG;
+    }
+  }
+  Arena ar(ws, ws_bytes);
+  KernelPlan kp;
+  TT_TRY(kernel_plan(batch, grids, halfwidths, caps.data(), dtypes.data(), ar, kp));
+  if (!ar.fits()) {
+    set_error("tt_kernel_build: workspace too small (%zu < %zu)", ws_bytes, ar.used);
+    return TT_ERR_WORKSPACE;
+  }
+  std::vector<KernelEvalArgs> vka(batch);
+  std::vector<DevTT> vout(batch);
+  bool any_f32 = false;
+  for (int b = 0; b < batch; ++b) {
+    KernelEvalArgs& ka = vka[b];
+    memset(&ka, 0, sizeof(ka));
+    ka.d = d;
+    double det = 0.0, logdelta = 0.0;
+    if (!invert_spd(d, q + (size_t)b * d * d, ka.qinv, &det)) {
+      set_error("tt_kernel_build: Q is not positive definite (filter %d)", b);
+      return TT_ERR_ARG;
+    }
+    for (int l = 0; l < d; ++l) {
+      ka.taps[l] = kp.taps[l];
+      ka.dx[l] = (grids[b].hi[l] - grids[b].lo[l]) / (double)(grids[b].n[l] - 1);
+      logdelta += std::log(ka.dx[l]);
+    }
+    ka.cnorm = std::exp(-0.5 * d * std::log(2.0 * M_PI) - 0.5 * std::log(det) + logdelta);
+    ka.total = kp.total;
+    vout[b] = make_dev(out[b]);
+    if (out[b].dtype == TT_F64)
+      kp.k64[b] = vout[b];
+    else
+      any_f32 = true;
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  TT_TRY(upload(kp.dK64, kp.k64, st));
+  TT_TRY(upload(kp.dKout, vout, st));
+  TT_TRY(upload(kp.drs, kp.rs, st));
+  TT_TRY(upload(kp.dka, vka, st));
+  hipLaunchKernelGGL(ksvd_init_kernel, dim3(batch), dim3(1), 0, st, kp.dK64);
+  TTG_LAUNCH_CHECK("ksvd_init_kernel");
+  hipLaunchKernelGGL(kernel_dense_kernel, dim3(std::min(cdiv(kp.total, 256), 8192), batch), dim3(256), 0, st, kp.dka,
+                     kp.dense, kp.total);
+  TTG_LAUNCH_CHECK("kernel_dense_kernel");
+  double* cur = kp.dense;
+  double* nxt = kp.buf2;
+  long long cols = kp.total / kp.taps[0];
+  int capmax[TT_MAXD + 1] = {0};
+  for (int b = 0; b < batch; ++b)
+    for (int j = 0; j <= d; ++j) capmax[j] = std::max(capmax[j], out[b].cap[j]);
+  for (int k = 0; k < d - 1; ++k) {
+    KsvdCtx c{kp.dK64, kp.drs, cur, nxt, cols, k, d, kp.total};
+    const int rows_cap = capmax[k] * kp.taps[k];
+    TT_TRY((launch_gram<double, AccDD>(FKsvdGram{c}, batch, rows_cap, cols, kp.splits, st)));
+    TT_TRY((launch_pchol<AccDD>(FKsvdPchol{c}, batch, kp.gcap, st)));
+    TT_TRY((launch_jacobi(FKsvdJacobi{c}, batch, st)));
+    hipLaunchKernelGGL(ksvd_select_kernel, dim3(batch), dim3(256), 0, st, kp.dK64, kp.drs, k, svd_tol);
+    TTG_LAUNCH_CHECK("ksvd_select_kernel");
+    TT_TRY((launch_gemm<double, double, double, double>(FKsvdNext{c}, batch, capmax[k + 1], cols, st)));
+    std::swap(cur, nxt);
+    cols /= kp.taps[k + 1];
+  }
+  hipLaunchKernelGGL(ksvd_last_kernel, dim3(64, batch), dim3(256), 0, st, kp.dK64, cur, kp.total);
+  TTG_LAUNCH_CHECK("ksvd_last_kernel");
+  if (any_f32) {  // every output is FP32 (one dtype per batch)
+    hipLaunchKernelGGL((convert_tt_kernel<float>), dim3(64, batch), dim3(256), 0, st, kp.dK64, kp.dKout);
+    TTG_LAUNCH_CHECK("convert_tt_kernel");
+  }
+  return TT_OK;
+}
+
+}  // namespace ttg
+
+extern "C" {
 
 size_t tt_kernel_build_workspace(const tt_grid* grid, const int32_t* halfwidths, const int32_t* cap) {
   if (!grid || !halfwidths || !cap) return 0;
   Arena ar(nullptr, 0);
   KernelPlan kp;
-  if (kernel_plan(grid, halfwidths, cap, TT_F64, ar, kp) != TT_OK) return 0;
+  if (kernel_plan(1, grid, halfwidths, cap, nullptr, ar, kp) != TT_OK) return 0;
+  return ar.used + 256;
+}
+
+size_t tt_kernel_build_batch_workspace(int32_t batch, const tt_grid* grids, const int32_t* halfwidths,
+                                       const int32_t* caps) {
+  if (batch < 1 || !grids || !halfwidths || !caps) return 0;
+  Arena ar(nullptr, 0);
+  KernelPlan kp;
+  if (kernel_plan(batch, grids, halfwidths, caps, nullptr, ar, kp) != TT_OK) return 0;
   return ar.used + 256;
 }
 
 tt_status tt_kernel_build(const tt_grid* grid, const double* q, const int32_t* halfwidths, double svd_tol,
                           const tt_train* out, void* ws, size_t ws_bytes, void* stream) {
-  if (!grid || !q || !halfwidths || !out || !ws || !(svd_tol >= 0.0)) {
-    set_error("tt_kernel_build: bad arguments");
-    return TT_ERR_ARG;
-  }
-  TT_TRY(check_train(out, "out"));
-  const int d = grid->d;
-  if (out->d != d) {
-    set_error("tt_kernel_build: out->d != grid->d");
-    return TT_ERR_SHAPE;
-  }
-  for (int k = 0; k < d; ++k)
-    if (out->n[k] != 2 * halfwidths[k] + 1) {
-      set_error("tt_kernel_build: out->n[%d] must be 2*h+1", k);
-      return TT_ERR_SHAPE;
-    }
-  Arena ar(ws, ws_bytes);
-  KernelPlan kp;
-  TT_TRY(kernel_plan(grid, halfwidths, out->cap, out->dtype, ar, kp));
-  if (!ar.fits()) {
-    set_error("tt_kernel_build: workspace too small (%zu < %zu)", ws_bytes, ar.used);
-    return TT_ERR_WORKSPACE;
-  }
-  KernelEvalArgs ka;
-  memset(&ka, 0, sizeof(ka));
-  ka.d = d;
-  double det = 0.0, logdelta = 0.0;
-  if (!invert_spd(d, q, ka.qinv, &det)) {
-    set_error("tt_kernel_build: Q is not positive definite");
-    return TT_ERR_ARG;
-  }
-  for (int l = 0; l < d; ++l) {
-    ka.taps[l] = kp.taps[l];
-    ka.dx[l] = (grid->hi[l] - grid->lo[l]) / (double)(grid->n[l] - 1);
-    logdelta += std::log(ka.dx[l]);
-  }
-  ka.cnorm = std::exp(-0.5 * d * std::log(2.0 * M_PI) - 0.5 * std::log(det) + logdelta);
-  ka.total = kp.total;
-  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  const bool direct = out->dtype == TT_F64;
-  DevTT kout = make_dev(*out);
-  DevTT k64 = direct ? kout : kp.k64;
-  std::vector<DevTT> v64(1, k64), vout(1, kout);
-  std::vector<RoundScratch> vrs(1, kp.rs);
-  TT_TRY(upload(kp.dK64, v64, st));
-  TT_TRY(upload(kp.dKout, vout, st));
-  TT_TRY(upload(kp.drs, vrs, st));
-  hipLaunchKernelGGL(ksvd_init_kernel, dim3(1), dim3(1), 0, st, kp.dK64);
-  TTG_LAUNCH_CHECK("ksvd_init_kernel");
-  hipLaunchKernelGGL(kernel_dense_kernel, dim3(std::min(cdiv(kp.total, 256), 8192)), dim3(256), 0, st, ka, kp.dense);
-  TTG_LAUNCH_CHECK("kernel_dense_kernel");
-  double* cur = kp.dense;
-  double* nxt = kp.buf2;
-  long long cols = kp.total / kp.taps[0];
-  for (int k = 0; k < d - 1; ++k) {
-    KsvdCtx c{kp.dK64, kp.drs, cur, nxt, cols, k, d};
-    const int rows_cap = out->cap[k] * kp.taps[k];
-    TT_TRY((launch_gram<double, AccDD>(FKsvdGram{c}, 1, rows_cap, cols, kp.splits, st)));
-    TT_TRY((launch_pchol<AccDD>(FKsvdPchol{c}, 1, kp.gcap, st)));
-    TT_TRY((launch_jacobi(FKsvdJacobi{c}, 1, st)));
-    hipLaunchKernelGGL(ksvd_select_kernel, dim3(1), dim3(256), 0, st, kp.dK64, kp.drs, k, svd_tol);
-    TTG_LAUNCH_CHECK("ksvd_select_kernel");
-    TT_TRY((launch_gemm<double, double, double, double>(FKsvdNext{c}, 1, out->cap[k + 1], cols, st)));
-    std::swap(cur, nxt);
-    cols /= kp.taps[k + 1];
-  }
-  hipLaunchKernelGGL(ksvd_last_kernel, dim3(64), dim3(256), 0, st, kp.dK64, cur);
-  TTG_LAUNCH_CHECK("ksvd_last_kernel");
-  if (!direct) {
-    hipLaunchKernelGGL((convert_tt_kernel<float>), dim3(64, 1), dim3(256), 0, st, kp.dK64, kp.dKout);
-    TTG_LAUNCH_CHECK("convert_tt_kernel");
-  }
-  return TT_OK;
+  return kernel_build_run(1, grid, q, halfwidths, svd_tol, out, ws, ws_bytes, stream);
+}
+
+tt_status tt_kernel_build_batch(int32_t batch, const tt_grid* grids, const double* q, const int32_t* halfwidths,
+                                double svd_tol, const tt_train* out, void* ws, size_t ws_bytes, void* stream) {
+  return kernel_build_run(batch, grids, q, halfwidths, svd_tol, out, ws, ws_bytes, stream);
 }
 
 }  // extern "C"

@@ -544,7 +544,11 @@ struct KernelEvalArgs {
   long long total;
 };
 
-__global__ void __launch_bounds__(256) kernel_dense_kernel(KernelEvalArgs a, double* __restrict__ out) {
+// one filter per blockIdx.y; filter f writes out + f * ostride
+__global__ void __launch_bounds__(256) kernel_dense_kernel(const KernelEvalArgs* __restrict__ args,
+                                                           double* __restrict__ outb, long long ostride) {
+  const KernelEvalArgs& a = args[blockIdx.y];
+  double* out = outb + blockIdx.y * ostride;
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < a.total;
        e += (long long)gridDim.x * blockDim.x) {
     double y[8];

@@ -40,6 +40,35 @@ def test_kernel_build_matches_oracle(B):
             assert ttm.ranks(cores) == ttm.ranks(ref)
 
 
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_kernel_build_batch_equals_single_builds(B, dt):
+    # three kernels with different Q, grids and capacities in one batched
+    # build: each equal bit for bit to its own single build, and to the
+    # dense kernel of its own Q
+    prec = B.F64 if dt == "f64" else B.F32
+    base = np.array([[1.0, 0.3, 0.0], [0.3, 1.0, 0.3], [0.0, 0.3, 1.0]])
+    qs = [base, base * np.array([1.1, 0.9, 1.0])[:, None] * np.array([1.1, 0.9, 1.0])[None, :],
+          np.diag([0.8, 1.2, 1.0])]
+    grids_ax = [(-20.0, 20.0, 64), (-18.0, 18.0, 64), (-20.0, 20.0, 48)]
+    h = [10, 10, 10]
+    caps = [[1, 24, 24, 1], [1, 20, 22, 1], [1, 24, 24, 1]]
+    print(f"batched kernel build: {dt}, 3 kernels, taps 21^3", flush=True)
+    grids = [B.make_grid(3, [n] * 3, [lo] * 3, [hi] * 3) for lo, hi, n in grids_ax]
+    outs = [B.DeviceTT([21] * 3, c, prec) for c in caps]
+    B.tt_kernel_build_batch(grids, qs, h, 1e-12, outs)
+    for g, q, c, o, (lo, hi, n) in zip(grids, qs, caps, outs, grids_ax):
+        one = B.DeviceTT([21] * 3, c, prec)
+        B.tt_kernel_build(g, q, h, 1e-12, one)
+        fa, ca, sa = fetch_full(o)
+        fb, cb, sb = fetch_full(one)
+        assert sa == 0 and sb == 0
+        assert [x.shape for x in ca] == [x.shape for x in cb]
+        for x, y in zip(ca, cb):
+            assert np.array_equal(x, y)
+        kd = mdl.kernel_dense(q, mdl.grid_axes(lo, hi, [n] * 3), h)
+        assert np.linalg.norm(fa - kd) <= (2e-12 if dt == "f64" else 1e-6) * np.linalg.norm(kd)
+
+
 def test_kernel_build_4d_config_kernel(B):
     from paper_2501_07942_amd import workload as wl
     s = wl.spec_range(4, 128, 16)
