@@ -37,15 +37,21 @@ from . import grad as G
 from . import runner
 
 
-def _tt_like(t: B.DeviceTT) -> B.DeviceTT:
-    return B.DeviceTT(t.n, t.cap, t.dtype)
+def _like(ts: Sequence[B.DeviceTT]) -> List[B.DeviceTT]:
+    """Trains of the layouts of ts (one allocation for the batch)."""
+    return B.DeviceTT.batch([t.n for t in ts], [t.cap for t in ts], ts[0].dtype)
 
 
-def _zero_adj(t: B.DeviceTT) -> B.DeviceTT:
-    """Adjoint train of t's layout holding zeros, with t's ranks."""
-    z = _tt_like(t)
-    z.ranks.copy_(t.ranks)
-    return z
+def _zero_adj(ts: Sequence[B.DeviceTT]) -> List[B.DeviceTT]:
+    """Adjoint trains of ts's layouts holding zeros, with ts's ranks."""
+    zs = _like(ts)
+    for z, t in zip(zs, ts):
+        z.ranks.copy_(t.ranks)
+    return zs
+
+
+def _new(ns: Sequence[Sequence[int]], caps: Sequence[Sequence[int]]) -> List[B.DeviceTT]:
+    return B.DeviceTT.batch(ns, caps, B.F64)
 
 
 def _prod_caps(a: B.DeviceTT, b: B.DeviceTT) -> List[int]:
@@ -93,7 +99,7 @@ class ComposedGradient:
         return lm
 
     def _round(self, xs):
-        outs = [B.DeviceTT(x.n, pc, B.F64) for x, pc in zip(xs, self.pcaps)]
+        outs = _new([x.n for x in xs], self.pcaps)
         groups = {}
         for i, s in enumerate(self.specs):
             groups.setdefault((s.eps, s.cap), []).append(i)
@@ -102,12 +108,12 @@ class ComposedGradient:
         return outs
 
     def _likelihood(self, k, meas=None):
-        ls = [B.DeviceTT([s.n] * s.d, _lik_caps(s, self.lik_rank_cap), B.F64) for s in self.specs]
+        ls = _new([[s.n] * s.d for s in self.specs], [_lik_caps(s, self.lik_rank_cap) for s in self.specs])
         B.tt_likelihood(self.grids, meas or self.meas, self._zk(k), ls, self.lik_rank_cap)
         return ls
 
     def _dense_likelihood(self, k, meas=None):
-        ps = [B.DeviceTT([s.n] * s.d, _lik_caps(s, s.n), B.F64) for s in self.specs]
+        ps = _new([[s.n] * s.d for s in self.specs], [_lik_caps(s, s.n) for s in self.specs])
         B.tt_likelihood_dense(self.grids, meas or self.meas, self._zk(k), ps)
         return ps
 
@@ -115,17 +121,17 @@ class ComposedGradient:
         """Recompute step k from the filtering density p_prev (None at k = 0)."""
         st = _Step()
         if k == 0:
-            pt = [B.DeviceTT([s.n] * s.d, pc, B.F64) for s, pc in zip(self.specs, self.pcaps)]
+            pt = _new([[s.n] * s.d for s in self.specs], self.pcaps)
             B.tt_prior(self.grids, np.array([s.m0 for s in self.specs]), np.array([s.p0_diag for s in self.specs]), pt)
             st.x = None
         else:
-            st.x = [B.DeviceTT(p.n, _prod_caps(kk, p), B.F64) for kk, p in zip(self.kern, p_prev)]
+            st.x = _new([p.n for p in p_prev], [_prod_caps(kk, p) for kk, p in zip(self.kern, p_prev)])
             B.tt_predict(self.kern, p_prev, st.x)
             pt = self._round(st.x)
         st.pt = pt
         self._normalise(pt)            # pt now holds P_pred (same cores)
         st.lik = self._likelihood(k)
-        st.h = [B.DeviceTT(p.n, _prod_caps(l, p), B.F64) for l, p in zip(st.lik, pt)]
+        st.h = _new([p.n for p in pt], [_prod_caps(l, p) for l, p in zip(st.lik, pt)])
         log_c = self.torch.zeros(self.Bn, dtype=self.torch.float64, device="cuda")
         B.tt_update(self.grids, self.meas, self._zk(k), pt, st.h, self.lik_rank_cap, log_c)
         st.log_c = log_c
@@ -150,43 +156,43 @@ class ComposedGradient:
     # ---- reverse sweep --------------------------------------------------
     def reverse(self):
         """Adjoints of the kernel trains and of every likelihood train."""
-        kbar = [_zero_adj(kk) for kk in self.kern]
+        kbar = _zero_adj(self.kern)
         self.lbar = [None] * self.K
         pbar = None
         for k in range(self.K - 1, -1, -1):
             st = self._step(k, self.ckpt[k - 1] if k > 0 else None)
             if pbar is None:
-                pbar = [_zero_adj(h) for h in st.hr]
+                pbar = _zero_adj(st.hr)
             # P_k = normalise(HR)
-            hrbar = [_tt_like(h) for h in st.hr]
+            hrbar = _like(st.hr)
             B.tt_normalize_adjoint(st.hr, pbar, None, hrbar)
             # HR = round(H)
-            hbar = [_tt_like(h) for h in st.h]
+            hbar = _like(st.h)
             B.tt_round_adjoint(st.h, st.hr, hrbar, hbar)
             # log c_k = log(sum(H) delta): the log-mass adjoint of H with weight one
-            cbar = [_tt_like(h) for h in st.h]
+            cbar = _like(st.h)
             one = self.torch.ones(self.Bn, dtype=self.torch.float64, device="cuda")
-            B.tt_normalize_adjoint(st.h, [_zero_adj(h) for h in st.h], one, cbar)
+            B.tt_normalize_adjoint(st.h, _zero_adj(st.h), one, cbar)
             B.tt_adjoint_axpy(1.0, cbar, hbar)
             # H = L o P_pred
-            lbar = [_tt_like(l) for l in st.lik]
-            ppbar = [_tt_like(p) for p in st.pt]
+            lbar = _like(st.lik)
+            ppbar = _like(st.pt)
             B.tt_hadamard_adjoint(st.lik, st.pt, hbar, lbar, ppbar)
             # L = build(P): the adjoint onto the dense likelihood
             pd = self._dense_likelihood(k)
-            pdbar = [_tt_like(p) for p in pd]
+            pdbar = _like(pd)
             B.tt_likelihood_adjoint(self.meas, pd, st.lik, lbar, pdbar)
             self.lbar[k] = pdbar
             if k == 0:
                 break
             # P_pred = normalise(Pt), Pt = round(X), X = K (*) P_{k-1}
-            ptbar = [_tt_like(p) for p in st.pt]
+            ptbar = _like(st.pt)
             B.tt_normalize_adjoint(st.pt, ppbar, None, ptbar)
-            xbar = [_tt_like(x) for x in st.x]
+            xbar = _like(st.x)
             B.tt_round_adjoint(st.x, st.pt, ptbar, xbar)
             pprev = self.ckpt[k - 1]
-            pbar = [_tt_like(p) for p in pprev]
-            kb = [_tt_like(kk) for kk in self.kern]
+            pbar = _like(pprev)
+            kb = _like(self.kern)
             B.tt_predict_adjoint(self.kern, pprev, xbar, pbar, kb)
             B.tt_adjoint_axpy(1.0, kb, kbar)
         self.kbar = kbar
@@ -233,7 +239,7 @@ class ComposedGradient:
                     # built straight into the base kernels' capacities (their
                     # ranks), one batched build per offset box and tolerance;
                     # statuses checked at the end
-                    kp = [B.DeviceTT(kb.n, kb.cap, B.F64) for kb in self.kern]
+                    kp = _like(self.kern)
                     groups = {}
                     for i, s in enumerate(sp):
                         groups.setdefault((tuple(int(h) for h in s.halfwidths()), s.kernel_tol), []).append(i)

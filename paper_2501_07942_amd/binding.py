@@ -195,21 +195,50 @@ class DeviceTT:
 
     def __init__(self, n: Sequence[int], cap: Sequence[int], dtype: int = F64, device="cuda"):
         torch = _torch()
+        total = self._layout(n, cap, dtype)
+        tdt = torch.float64 if dtype == F64 else torch.float32
+        self.cores = torch.zeros(total, dtype=tdt, device=device)
+        self.ranks = torch.ones(self.d + 1, dtype=torch.int32, device=device)
+        self.log_scale = torch.zeros(1, dtype=torch.float64, device=device)
+        self.status = torch.zeros(1, dtype=torch.int32, device=device)
+
+    def _layout(self, n: Sequence[int], cap: Sequence[int], dtype: int) -> int:
         self.d = len(n)
         self.n = [int(x) for x in n]
         self.cap = [int(x) for x in cap]
         assert len(self.cap) == self.d + 1 and self.cap[0] == 1 and self.cap[-1] == 1
         self.dtype = dtype
-        tdt = torch.float64 if dtype == F64 else torch.float32
         self.offsets = []
         off = 0
         for k in range(self.d):
             self.offsets.append(off)
             off += self.cap[k] * self.n[k] * self.cap[k + 1]
-        self.cores = torch.zeros(max(off, 1), dtype=tdt, device=device)
-        self.ranks = torch.ones(self.d + 1, dtype=torch.int32, device=device)
-        self.log_scale = torch.zeros(1, dtype=torch.float64, device=device)
-        self.status = torch.zeros(1, dtype=torch.int32, device=device)
+        return max(off, 1)
+
+    @classmethod
+    def batch(cls, ns: Sequence[Sequence[int]], caps: Sequence[Sequence[int]], dtype: int = F64,
+              device="cuda") -> List["DeviceTT"]:
+        """Several TTs whose cores, ranks, log-scales and statuses are views of
+        four shared allocations (each core buffer starts 512-byte aligned)."""
+        torch = _torch()
+        objs = [cls.__new__(cls) for _ in ns]
+        totals = [o._layout(n, c, dtype) for o, n, c in zip(objs, ns, caps)]
+        starts, pos = [], 0
+        for t in totals:
+            starts.append(pos)
+            pos += (t + 127) // 128 * 128
+        tdt = torch.float64 if dtype == F64 else torch.float32
+        cores = torch.zeros(max(pos, 1), dtype=tdt, device=device)
+        dmax = max(o.d for o in objs) + 1
+        ranks = torch.ones((len(objs), dmax), dtype=torch.int32, device=device)
+        logs = torch.zeros(len(objs), dtype=torch.float64, device=device)
+        status = torch.zeros(len(objs), dtype=torch.int32, device=device)
+        for b, (o, st, t) in enumerate(zip(objs, starts, totals)):
+            o.cores = cores[st:st + t]
+            o.ranks = ranks[b, :o.d + 1]
+            o.log_scale = logs[b:b + 1]
+            o.status = status[b:b + 1]
+        return objs
 
     def struct(self) -> Train:
         t = Train()
