@@ -1308,7 +1308,7 @@ static void radj_layout(Arena& ar, RadjFilter& F) {
       C.Fm = ar.take<double>(nd * rk1 + rk1);
       C.vs = ar.take<double>(Rk1 * Rk1);
       C.js = ar.take<double>(Rk1 * Rk1);
-      C.flag = ar.take<int>(1);
+      C.flag = ar.take<int>(2);
     }
   }
   F.wide0 = d >= 2 && F.Ra[1] > F.n[0];
@@ -1833,6 +1833,7 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
         const int R1 = f.Ra[k + 1], p = f.ry[k] * f.n[k];
         rf[b].sig = f.c[k].sig;
         rf[b].r = f.ry[k + 1];
+        rf[b].R = R1;
         rf[b].flag = f.c[k].flag;
         DJob& q = dj[b];
         q.vs = f.c[k].vs;
@@ -1869,6 +1870,8 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
       TTG_LAUNCH_CHECK("radj_ddprod_kernel");
       TT_TRY(upload(R.dcj, cj, st));
       TT_TRY(launch_jacobi(FAdjJacobiIf{R.dcj}, batch, st));
+      hipLaunchKernelGGL(radj_refine_tail_kernel, dim3(batch), dim3(64), 0, st, R.drf, batch);
+      TTG_LAUNCH_CHECK("radj_refine_tail_kernel");
     }
     std::vector<AJob> aj;
     for (int b = 0; b < batch; ++b) {

@@ -408,10 +408,13 @@ struct FAdjJacobiRk {
 // sigma_c, and one-sided Jacobi on Mt removes what is left in a sweep or
 // two, with accuracy relative to each column.  Flag per job.
 #define RADJ_REFINE 1e-8
+// The refinement keeps the columns that the adjoint resolves: the kept
+// ones and the discarded ones above RADJ_DISC * sigma_1 (the rest count as
+// null space anyway); flag[1] holds their number.
 struct RefJob {
   const double* sig;
-  int r;
-  int* flag;
+  int r, R;
+  int* flag;  // [0]: refine, [1]: columns kept for it
 };
 __global__ void radj_refine_flag_kernel(const RefJob* __restrict__ jobs, int njobs) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -420,6 +423,9 @@ __global__ void radj_refine_flag_kernel(const RefJob* __restrict__ jobs, int njo
   if (!j.flag) return;
   const double s1 = j.sig[0], sr = j.r >= 1 ? j.sig[j.r - 1] : s1;
   j.flag[0] = (s1 > 0.0 && !(sr >= RADJ_REFINE * s1)) ? 1 : 0;
+  int m = j.r;
+  while (m < j.R && j.sig[m] > RADJ_DISC * s1) ++m;
+  j.flag[1] = m;
 }
 struct CondJacobi {
   JacobiArgs ja;
@@ -429,9 +435,18 @@ struct FAdjJacobiIf {
   const CondJacobi* a;
   __device__ bool operator()(int b, JacobiArgs& J) const {
     J = a[b].ja;
-    return J.rows > 0 && J.ncols > 0 && a[b].flag && *a[b].flag != 0;
+    if (!a[b].flag || a[b].flag[0] == 0) return false;
+    J.ncols = min(J.ncols, a[b].flag[1]);
+    return J.rows > 0 && J.ncols > 0;
   }
 };
+// after the refinement: singular values beyond the refined columns are zero
+__global__ void radj_refine_tail_kernel(const RefJob* __restrict__ jobs, int njobs) {
+  const RefJob j = jobs[blockIdx.x];
+  if (!j.flag || j.flag[0] == 0) return;
+  double* sig = const_cast<double*>(j.sig);
+  for (int c = j.flag[1] + threadIdx.x; c < j.R; c += blockDim.x) sig[c] = 0.0;
+}
 
 // Mt(:, c) = M vs(:, c) / sigma_c summed in double-double, for flagged jobs
 // (columns with sigma_c = 0 are zero).  M: p x R1 row-major; vs: column-major
@@ -452,7 +467,7 @@ __global__ void __launch_bounds__(256) radj_ddprod_kernel(const DJob* __restrict
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < tot; e += stride) {
     const int row = (int)(e / j.R1), c = (int)(e - (long long)row * j.R1);
     const double sc = j.sig[c];
-    if (!(sc > 0.0)) {
+    if (!(sc > 0.0) || c >= j.flag[1]) {
       j.usv[e] = 0.0;
       continue;
     }
