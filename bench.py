@@ -33,7 +33,7 @@ FP32_MFMA_PEAK_TFS = 157.3
 # rocprofv3 FETCH_SIZE (x2.0) and WRITE_SIZE (x1.0), the factors measured on a
 # plain 256 MiB device copy (profiles/mfma_pred_kernel_traffic_*.txt); reset to
 # None whenever the kernel changes
-TRAFFIC = 856901491
+TRAFFIC = 902968638
 
 
 def log(msg):
@@ -196,6 +196,8 @@ def main():
     ap.add_argument("--no-grad", action="store_true", help="skip the gradient timing")
     ap.add_argument("--grad-steps", type=int, default=8)
     ap.add_argument("--grad-batch", type=int, default=32)
+    ap.add_argument("--grad-only", action="store_true",
+                    help="only time the gradient (prints {\"grad\": ...}; for profiling the reverse sweep)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default prediction launch shape")
     ap.add_argument("--graph-replays", type=int, default=3,
                     help="replays of one step recorded as a HIP graph (0: skip)")
@@ -220,6 +222,11 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": nel * 4, "copy_bytes_written": nel * 4, "copies": 5}), flush=True)
+        return
+
+    if args.grad_only:
+        from paper_2501_07942_amd import grad as G
+        print(json.dumps({"grad": grad_bench(G, wl, args.grad_steps, args.grad_batch)}), flush=True)
         return
 
     main_res = run_batch(None, runner, binding, wl, args.workload, args.batch, args.steps, args.warmup,
