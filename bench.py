@@ -164,10 +164,13 @@ def grad_bench(G, wl, steps, batch):
     AG.loglik_grad_adjoint(specs, warm)
     G.loglik_grad(specs, warm)
     torch.cuda.synchronize()
+    torch.cuda.reset_peak_memory_stats()
+    base_mem = torch.cuda.memory_allocated()
     t0 = time.perf_counter()
     ll_a, g_a, _ = AG.loglik_grad_adjoint(specs, zs)
     torch.cuda.synchronize()
     ms_adj = (time.perf_counter() - t0) * 1e3
+    peak_gb = (torch.cuda.max_memory_allocated() - base_mem) / 1e9
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ll, g, info = G.loglik_grad(specs, zs)
@@ -182,6 +185,7 @@ def grad_bench(G, wl, steps, batch):
             "method": "reverse sweep: forward with a checkpoint per step, adjoints of prediction, rounding "
                       "(fixed ranks), Hadamard update, normalisation and likelihood build; parameter tangents "
                       "of the kernel and likelihood builds by central differences",
+            "checkpoint_every": 1, "peak_hbm_GB": round(peak_gb, 2),
             "max_rel_diff_vs_differences": agree, "max_abs_dll": float(np.abs(ll_a - ll).max()),
             "differences": {"value": round(ms_fd_wall / steps, 2), "unit": "ms per batched step (forward + gradient)",
                             "runs_only_ms_per_step": round(ms_fd / steps, 2),

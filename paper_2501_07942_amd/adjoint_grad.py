@@ -8,10 +8,11 @@ Forward (Alg. 2 order, the prediction of Sec. 4.2 materialised):
   k >= 1: X = K (*) P;  Pt = round(X);  P_pred = normalise(Pt)
   every k: L_k = likelihood(z_k);  H = L_k o P_pred,  log c_k = log(sum(H) delta);
            HR = round(H);  P = normalise(HR)
-Only the filtering densities P are kept (a checkpoint per step); the
-reverse sweep recomputes each step from its checkpoint and runs the
-adjoints backwards (tt_normalize_adjoint, tt_round_adjoint,
-tt_hadamard_adjoint, tt_predict_adjoint), collecting the adjoints of the
+Only the filtering densities P that start segments of ckpt_every steps
+are kept (every one by default); the reverse sweep recomputes each segment
+from its checkpoint, then each step of it, and runs the adjoints backwards
+(tt_normalize_adjoint, tt_round_adjoint, tt_hadamard_adjoint,
+tt_likelihood_adjoint, tt_predict_adjoint), collecting the adjoints of the
 kernel train and of every likelihood train.
 
 Parameters enter through the kernel TT (sigma_w) and the likelihood TTs
@@ -72,8 +73,11 @@ class _Step:
 class ComposedGradient:
     """Forward run with checkpoints and the reverse sweep for one batch."""
 
-    def __init__(self, specs: Sequence, zs: Sequence[np.ndarray], lik_rank_cap: int = 64):
+    def __init__(self, specs: Sequence, zs: Sequence[np.ndarray], lik_rank_cap: int = 64, ckpt_every: int = 1):
         import torch
+        if ckpt_every < 1:
+            raise ValueError("ckpt_every must be >= 1")
+        self.C = int(ckpt_every)
         self.torch = torch
         self.specs = list(specs)
         self.Bn = len(specs)
@@ -140,63 +144,84 @@ class ComposedGradient:
         return st
 
     def forward(self):
-        """Log-likelihoods [B] and the checkpoints P_0 .. P_{K-1}."""
-        self.ckpt = []
+        """Log-likelihoods [B]; keeps the filtering TT that starts each segment
+        of ckpt_every steps (P_{s-1} for s = C, 2C, ...)."""
+        self.ckpt = {}
         ll = self.torch.zeros(self.Bn, dtype=self.torch.float64, device="cuda")
         p = None
         for k in range(self.K):
             st = self._step(k, p)
             ll += st.log_c
             p = st.hr
-            self.ckpt.append(p)
+            if (k + 1) % self.C == 0 and k + 1 < self.K:
+                self.ckpt[k] = p
         self.torch.cuda.synchronize()
         self.ll = ll.cpu().numpy()
         return self.ll
 
     # ---- reverse sweep --------------------------------------------------
     def reverse(self):
-        """Adjoints of the kernel trains and of every likelihood train."""
+        """Adjoints of the kernel trains and of every likelihood train.  The
+        segments of ckpt_every steps are taken from the last: each is
+        recomputed from its checkpoint (the filtering TTs inside it kept),
+        then every step of it is recomputed once more and run backwards."""
         kbar = _zero_adj(self.kern)
         self.lbar = [None] * self.K
         pbar = None
-        for k in range(self.K - 1, -1, -1):
-            st = self._step(k, self.ckpt[k - 1] if k > 0 else None)
-            if pbar is None:
-                pbar = _zero_adj(st.hr)
-            # P_k = normalise(HR)
-            hrbar = _like(st.hr)
-            B.tt_normalize_adjoint(st.hr, pbar, None, hrbar)
-            # HR = round(H)
-            hbar = _like(st.h)
-            B.tt_round_adjoint(st.h, st.hr, hrbar, hbar)
-            # log c_k = log(sum(H) delta): the log-mass adjoint of H with weight one
-            cbar = _like(st.h)
-            one = self.torch.ones(self.Bn, dtype=self.torch.float64, device="cuda")
-            B.tt_normalize_adjoint(st.h, _zero_adj(st.h), one, cbar)
-            B.tt_adjoint_axpy(1.0, cbar, hbar)
-            # H = L o P_pred
-            lbar = _like(st.lik)
-            ppbar = _like(st.pt)
-            B.tt_hadamard_adjoint(st.lik, st.pt, hbar, lbar, ppbar)
-            # L = build(P): the adjoint onto the dense likelihood
-            pd = self._dense_likelihood(k)
-            pdbar = _like(pd)
-            B.tt_likelihood_adjoint(self.meas, pd, st.lik, lbar, pdbar)
-            self.lbar[k] = pdbar
-            if k == 0:
-                break
-            # P_pred = normalise(Pt), Pt = round(X), X = K (*) P_{k-1}
-            ptbar = _like(st.pt)
-            B.tt_normalize_adjoint(st.pt, ppbar, None, ptbar)
-            xbar = _like(st.x)
-            B.tt_round_adjoint(st.x, st.pt, ptbar, xbar)
-            pprev = self.ckpt[k - 1]
-            pbar = _like(pprev)
-            kb = _like(self.kern)
-            B.tt_predict_adjoint(self.kern, pprev, xbar, pbar, kb)
-            B.tt_adjoint_axpy(1.0, kb, kbar)
+        for s0 in reversed(range(0, self.K, self.C)):
+            s1 = min(s0 + self.C, self.K)
+            seg = {}
+            p = self.ckpt[s0 - 1] if s0 > 0 else None
+            for k in range(s0, s1 - 1):
+                p = self._step(k, p).hr
+                seg[k] = p
+
+            def prev(k):
+                return None if k == 0 else (seg[k - 1] if (k - 1) in seg else self.ckpt[k - 1])
+
+            for k in range(s1 - 1, s0 - 1, -1):
+                pbar = self._reverse_step(k, prev(k), pbar, kbar)
         self.kbar = kbar
         self.torch.cuda.synchronize()
+
+    def _reverse_step(self, k, pprev, pbar, kbar):
+        """Recompute step k from P_{k-1} = pprev and run its adjoints; returns
+        the adjoint of P_{k-1} (None at k = 0)."""
+        st = self._step(k, pprev)
+        if pbar is None:
+            pbar = _zero_adj(st.hr)
+        # P_k = normalise(HR)
+        hrbar = _like(st.hr)
+        B.tt_normalize_adjoint(st.hr, pbar, None, hrbar)
+        # HR = round(H)
+        hbar = _like(st.h)
+        B.tt_round_adjoint(st.h, st.hr, hrbar, hbar)
+        # log c_k = log(sum(H) delta): the log-mass adjoint of H with weight one
+        cbar = _like(st.h)
+        one = self.torch.ones(self.Bn, dtype=self.torch.float64, device="cuda")
+        B.tt_normalize_adjoint(st.h, _zero_adj(st.h), one, cbar)
+        B.tt_adjoint_axpy(1.0, cbar, hbar)
+        # H = L o P_pred
+        lbar = _like(st.lik)
+        ppbar = _like(st.pt)
+        B.tt_hadamard_adjoint(st.lik, st.pt, hbar, lbar, ppbar)
+        # L = build(P): the adjoint onto the dense likelihood
+        pd = self._dense_likelihood(k)
+        pdbar = _like(pd)
+        B.tt_likelihood_adjoint(self.meas, pd, st.lik, lbar, pdbar)
+        self.lbar[k] = pdbar
+        if k == 0:
+            return None
+        # P_pred = normalise(Pt), Pt = round(X), X = K (*) P_{k-1}
+        ptbar = _like(st.pt)
+        B.tt_normalize_adjoint(st.pt, ppbar, None, ptbar)
+        xbar = _like(st.x)
+        B.tt_round_adjoint(st.x, st.pt, ptbar, xbar)
+        pbar = _like(pprev)
+        kb = _like(self.kern)
+        B.tt_predict_adjoint(self.kern, pprev, xbar, pbar, kb)
+        B.tt_adjoint_axpy(1.0, kb, kbar)
+        return pbar
 
     # ---- parameter tangents -----------------------------------------------
     def _inner(self, abar, b):
@@ -267,16 +292,18 @@ class ComposedGradient:
 
 
 def loglik_grad_adjoint(specs: Sequence, zs: Sequence[np.ndarray], thetas: Optional[np.ndarray] = None,
-                        h_rel: Optional[float] = None, lik_rank_cap: int = 64, scheme: str = "central"):
+                        h_rel: Optional[float] = None, lik_rank_cap: int = 64, scheme: str = "central",
+                        ckpt_every: int = 1):
     """LL [B] and dLL/dtheta [B, n_theta] by the composed reverse sweep
     (FP64).  thetas: [B, n_theta] (None: each spec's own parameters);
-    h_rel, scheme: the differences of the parameter tangents (theta_grad)."""
+    h_rel, scheme: the differences of the parameter tangents (theta_grad);
+    ckpt_every: steps per checkpoint segment (1: every filtering TT kept)."""
     specs = list(specs)
     if thetas is None:
         thetas = np.array([G.theta_of(s) for s in specs])
     boxes = [s.halfwidths() for s in specs]
     sp = [G.spec_at(s, t, bx) for s, t, bx in zip(specs, thetas, boxes)]
-    cg = ComposedGradient(sp, zs, lik_rank_cap)
+    cg = ComposedGradient(sp, zs, lik_rank_cap, ckpt_every)
     ll = cg.forward()
     cg.reverse()
     return ll, cg.theta_grad(np.asarray(thetas, dtype=np.float64), h_rel, scheme), cg
