@@ -73,11 +73,17 @@ class _Step:
 class ComposedGradient:
     """Forward run with checkpoints and the reverse sweep for one batch."""
 
-    def __init__(self, specs: Sequence, zs: Sequence[np.ndarray], lik_rank_cap: int = 64, ckpt_every: int = 1):
+    def __init__(self, specs: Sequence, zs: Sequence[np.ndarray], lik_rank_cap: int = 64, ckpt_every: int = 1,
+                 tape: bool = True):
         import torch
         if ckpt_every < 1:
             raise ValueError("ckpt_every must be >= 1")
         self.C = int(ckpt_every)
+        # with a checkpoint per step the forward also keeps each step's
+        # rounded and normalised predictive, likelihood and update product
+        # (a few MB per filter and step), so the reverse sweep recomputes only
+        # the prediction product, not the two roundings
+        self.tape = bool(tape) and self.C == 1
         self.torch = torch
         self.specs = list(specs)
         self.Bn = len(specs)
@@ -147,6 +153,7 @@ class ComposedGradient:
         """Log-likelihoods [B]; keeps the filtering TT that starts each segment
         of ckpt_every steps (P_{s-1} for s = C, 2C, ...)."""
         self.ckpt = {}
+        self.tapes = {}
         ll = self.torch.zeros(self.Bn, dtype=self.torch.float64, device="cuda")
         p = None
         for k in range(self.K):
@@ -155,6 +162,9 @@ class ComposedGradient:
             p = st.hr
             if (k + 1) % self.C == 0 and k + 1 < self.K:
                 self.ckpt[k] = p
+            if self.tape:
+                st.x = None
+                self.tapes[k] = st
         self.torch.cuda.synchronize()
         self.ll = ll.cpu().numpy()
         return self.ll
@@ -185,9 +195,15 @@ class ComposedGradient:
         self.torch.cuda.synchronize()
 
     def _reverse_step(self, k, pprev, pbar, kbar):
-        """Recompute step k from P_{k-1} = pprev and run its adjoints; returns
+        """Recompute step k from P_{k-1} = pprev (or take its tape and
+        recompute only the prediction product) and run its adjoints; returns
         the adjoint of P_{k-1} (None at k = 0)."""
-        st = self._step(k, pprev)
+        st = self.tapes.pop(k, None) if self.tape else None
+        if st is None:
+            st = self._step(k, pprev)
+        elif k > 0:
+            st.x = _new([p.n for p in pprev], [_prod_caps(kk, p) for kk, p in zip(self.kern, pprev)])
+            B.tt_predict(self.kern, pprev, st.x)
         if pbar is None:
             pbar = _zero_adj(st.hr)
         # P_k = normalise(HR)
@@ -293,17 +309,19 @@ class ComposedGradient:
 
 def loglik_grad_adjoint(specs: Sequence, zs: Sequence[np.ndarray], thetas: Optional[np.ndarray] = None,
                         h_rel: Optional[float] = None, lik_rank_cap: int = 64, scheme: str = "central",
-                        ckpt_every: int = 1):
+                        ckpt_every: int = 1, tape: bool = True):
     """LL [B] and dLL/dtheta [B, n_theta] by the composed reverse sweep
     (FP64).  thetas: [B, n_theta] (None: each spec's own parameters);
     h_rel, scheme: the differences of the parameter tangents (theta_grad);
-    ckpt_every: steps per checkpoint segment (1: every filtering TT kept)."""
+    ckpt_every: steps per checkpoint segment (1: every filtering TT kept);
+    tape: with ckpt_every = 1, keep each step's intermediates except the
+    prediction product (no recomputed roundings)."""
     specs = list(specs)
     if thetas is None:
         thetas = np.array([G.theta_of(s) for s in specs])
     boxes = [s.halfwidths() for s in specs]
     sp = [G.spec_at(s, t, bx) for s, t, bx in zip(specs, thetas, boxes)]
-    cg = ComposedGradient(sp, zs, lik_rank_cap, ckpt_every)
+    cg = ComposedGradient(sp, zs, lik_rank_cap, ckpt_every, tape)
     ll = cg.forward()
     cg.reverse()
     return ll, cg.theta_grad(np.asarray(thetas, dtype=np.float64), h_rel, scheme), cg

@@ -37,9 +37,12 @@ def test_adjoint_gradient_binding_cap_batch(mods):
     print("composed adjoint: 2 filters, d=3, N=32, cap 6, 5 steps", flush=True)
     ll, g, _ = AG.loglik_grad_adjoint(specs, zs)
     ll_fd, g_fd, _ = G.loglik_grad(specs, zs)
-    # checkpoint segments of two steps: the same computations, bit for bit
+    # checkpoint segments of two steps, and a checkpoint per step without
+    # the tape: the same computations, bit for bit
     ll2, g2, _ = AG.loglik_grad_adjoint(specs, zs, ckpt_every=2)
     assert np.array_equal(ll2, ll) and np.array_equal(g2, g)
+    ll1, g1, _ = AG.loglik_grad_adjoint(specs, zs, tape=False)
+    assert np.array_equal(ll1, ll) and np.array_equal(g1, g)
     # the parameter tangents by forward instead of central differences
     _, g_f, _ = AG.loglik_grad_adjoint(specs, zs, scheme="forward")
     with pytest.raises(ValueError):
