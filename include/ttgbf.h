@@ -260,10 +260,12 @@ size_t tt_normalize_moments_workspace(int32_t batch, const tt_train* t);
  * is differentiated as a function of the input cores with every output rank
  * held fixed: Gram matrices of the right parts, leading eigenvectors of the
  * projected unfoldings (their adjoint couples kept and discarded singular
- * directions, whose singular values come from a Jacobi SVD), then both
- * sweeps backwards.  Kept singular values below 6e-6 of the largest at a
- * bond are left out of the eigenvector adjoint (rounding noise there
- * exceeds their signal).  The call reads the ranks to the host once and is
+ * directions; the vectors and singular values come from the adjoint's own
+ * SVD of each projected unfolding, and y and y_bar are sign-matched to it
+ * bond by bond), then both sweeps backwards.  Kept singular values below
+ * 6e-6 of the largest at a bond are left out of the eigenvector adjoint
+ * (rounding noise there exceeds their signal) and discarded ones below 1e-9
+ * count as null space.  The call reads the ranks to the host once and is
  * synchronous (it returns after the work is done).  Workspace:
  * tt_round_adjoint_workspace(batch, a, y) bytes (from the capacities).
  * Errors: TT_ERR_ARG (null, non-FP64), TT_ERR_SHAPE (modes, capacities or

@@ -1345,7 +1345,6 @@ struct RadjRun {
   GJob* dg;
   EJob* de;
   PcholArgs* dp;
-  JacobiArgs* dj;
   GramArgs* dga;
   AJob* daj;
   RkJacobi* drj;
@@ -1480,7 +1479,7 @@ size_t tt_round_adjoint_workspace(int32_t batch, const tt_train* a, const tt_tra
   if (batch < 1 || !a || !y) return 0;
   const int dd = a[0].d;
   size_t total = (size_t)batch * (3 * dd + 8) *
-                     (sizeof(GJob) + sizeof(EJob) + sizeof(PcholArgs) + sizeof(JacobiArgs) + sizeof(GramArgs) +
+                     (sizeof(GJob) + sizeof(EJob) + sizeof(PcholArgs) + sizeof(GramArgs) +
                       sizeof(AJob) + sizeof(RkJacobi) + sizeof(DJob) + sizeof(CondJacobi) + sizeof(RefJob)) +
                  8192;
   for (int b = 0; b < batch; ++b) {
@@ -1544,7 +1543,6 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
   R.dg = ar.take<GJob>(R.jcap);
   R.de = ar.take<EJob>(R.jcap);
   R.dp = ar.take<PcholArgs>((size_t)batch * d);
-  R.dj = ar.take<JacobiArgs>((size_t)batch * d);
   R.dga = ar.take<GramArgs>((size_t)batch);
   R.daj = ar.take<AJob>((size_t)batch);
   R.drj = ar.take<RkJacobi>((size_t)batch);

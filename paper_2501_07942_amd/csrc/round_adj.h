@@ -9,12 +9,17 @@
 //                      W_{k+1} = U_k^T N_k
 //   output             core k = U_k (k < d-1),  last core = W_{d-1} x_1 A_{d-1}
 //
-// The library's forward rounding returns exactly these cores up to scalar
-// factors moved into the log-scale; the adjoint takes the kept U_k from
-// the forward's output (its gauge) and the eigenvalues and discarded
-// directions of S_k from a one-sided Jacobi SVD of M_k = N_k F_k with
-// F_k F_k^T = G_k (pivoted Cholesky of G_k accumulated in double-double, as
-// the forward rounding does, so that small singular values are resolved).  For the leading eigenvectors,
+// The library's forward rounding returns these cores up to scalar factors
+// moved into the log-scale and the signs of the bond indices.  The adjoint
+// takes all eigen-data of S_k (kept and discarded vectors, eigenvalues) from
+// its own SVD of M_k = N_k F_k, with F_k F_k^T = G_k a pivoted Cholesky
+// factor of G_k accumulated in double-double (as the forward rounding does,
+// so that small singular values are resolved); the SVD comes from a
+// double-double Gram of M_k, its pivoted Cholesky factor and a one-sided
+// Jacobi SVD of that factor, refined where tiny singular values were kept.
+// The forward output and its adjoint are sign-matched to that basis bond by
+// bond, so every quantity of the adjoint belongs to one decomposition.  For
+// the leading eigenvectors,
 // dU_j = sum_{i != j} u_i (u_i^T dS u_j) / (lam_j - lam_i); its adjoint is
 // Sbar = X U^T with
 //   X_j = (I - U_all U_all^T) Ubar_j / lam_j + sum_{i discarded} u_i (u_i^T Ubar_j) / (lam_j - lam_i)
@@ -46,8 +51,8 @@ namespace ttg {
 // rounding may keep directions that small, and each kept one needs its vector)
 #define RADJ_PCHOL_TAU2 1e-30
 
-// C = alpha * A B + beta * C (beta = 0 overwrites), one 64 x 64 tile of one
-// job per workgroup; FP64, every element sums its k in increasing order.
+// C = alpha * A B + beta * C (beta = 0 overwrites) for a table of FP64
+// products with arbitrary strides, one 64 x 64 tile of one job per workgroup.
 struct GJob {
   int M, N, K;
   const double* a;
@@ -61,66 +66,8 @@ struct GJob {
   int tn;     // tiles along N
 };
 
-__global__ void __launch_bounds__(256) gjob_gemm_kernel(const GJob* __restrict__ jobs, int njobs) {
-  const int t = blockIdx.x;
-  int lo = 0, hi = njobs - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (jobs[mid].tile0 <= t)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  const GJob g = jobs[lo];
-  const int lt = t - g.tile0;
-  const int m0 = (lt / g.tn) * 64, n0 = (lt - (lt / g.tn) * g.tn) * 64;
-  if (m0 >= g.M || n0 >= g.N) return;
-  __shared__ double As[16][64 + 1];
-  __shared__ double Bs[16][64 + 1];
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  double acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-  for (int k0 = 0; k0 < g.K; k0 += 16) {
-    for (int e = threadIdx.x; e < 64 * 16; e += 256) {
-      const int mm = e >> 4, kk = e & 15;
-      const int m = m0 + mm, k = k0 + kk;
-      As[kk][mm] = (m < g.M && k < g.K) ? g.a[(long long)m * g.sam + (long long)k * g.sak] : 0.0;
-      const int kb = e >> 6, nn = e & 63;
-      const int n = n0 + nn, k2 = k0 + kb;
-      Bs[kb][nn] = (n < g.N && k2 < g.K) ? g.b[(long long)k2 * g.sbk + (long long)n * g.sbn] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      double av[4], bv[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) av[i] = As[kk][ty * 4 + i];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) bv[j] = Bs[kk][tx * 4 + j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = __fma_rn(av[i], bv[j], acc[i][j]);
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int m = m0 + ty * 4 + i, n = n0 + tx * 4 + j;
-      if (m < g.M && n < g.N) {
-        double* cp = g.c + (long long)m * g.scm + (long long)n * g.scn;
-        *cp = g.beta == 0.0 ? g.alpha * acc[i][j] : __fma_rn(g.alpha, acc[i][j], g.beta * *cp);
-      }
-    }
-}
-
-// The same job table on the matrix cores: one 64 x 64 tile per workgroup,
-// wavefront w owns rows 16 w .. 16 w + 15 and the four 16-column tiles, each
+// The job table on the FP64 matrix cores: wavefront w of a tile owns rows
+// 16 w .. 16 w + 15 and the four 16-column tiles, each
 // 16 x 16 x 4 FP64 MFMA step reads A(i, k) in lane i + 16 k and B(k, j) in
 // lane j + 16 k from the LDS stage; D(i, j) sits in lane j + 16 (i % 4),
 // register i / 4.  Every element sums its k in MFMA chunks of four in
@@ -375,13 +322,6 @@ struct FAdjPchol {
     return p.M > 0;
   }
 };
-struct FAdjJacobi {
-  const JacobiArgs* a;
-  __device__ bool operator()(int b, JacobiArgs& J) const {
-    J = a[b];
-    return J.rows > 0 && J.ncols > 0;
-  }
-};
 
 // Jacobi over a job table whose column count is capped by a device value
 // (the rank a pivoted Cholesky factor reached)
@@ -412,7 +352,7 @@ struct FAdjJacobiRk {
 // ones and the discarded ones above RADJ_DISC * sigma_1 (the rest count as
 // null space anyway); flag[1] holds their number.
 struct RefJob {
-  const double* sig;
+  double* sig;
   int r, R;
   int* flag;  // [0]: refine, [1]: columns kept for it
 };
@@ -444,8 +384,7 @@ struct FAdjJacobiIf {
 __global__ void radj_refine_tail_kernel(const RefJob* __restrict__ jobs, int njobs) {
   const RefJob j = jobs[blockIdx.x];
   if (!j.flag || j.flag[0] == 0) return;
-  double* sig = const_cast<double*>(j.sig);
-  for (int c = j.flag[1] + threadIdx.x; c < j.R; c += blockDim.x) sig[c] = 0.0;
+  for (int c = j.flag[1] + threadIdx.x; c < j.R; c += blockDim.x) j.sig[c] = 0.0;
 }
 
 // Mt(:, c) = M vs(:, c) / sigma_c summed in double-double, for flagged jobs
