@@ -265,6 +265,15 @@ def main():
                 "launches": n_p, "algorithmic_flops_per_launch": round(fl_p / n_p),
                 "algorithmic_bytes_per_launch": round(by_p / n_p),
                 "algorithmic_GBs": round(by_p / n_p / avg_s / 1e9, 1)}
+    # the HBM-bound update product: algorithmic bytes (write H, read L and P)
+    # per launch over its HIP-event time
+    hbm = None
+    if prof and prof["hadamard"][1] > 0 and prof["hadamard"][3] > 0:
+        ms_h, n_h, _, by_h = prof["hadamard"]
+        gbs = by_h / n_h / (ms_h / n_h / 1000.0) / 1e9
+        hbm = {"kernel": "hadamard_kernel<float>", "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+               "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "avg_launch_ms": round(ms_h / n_h, 4),
+               "algorithmic_bytes_per_launch": round(by_h / n_h)}
     out = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -284,6 +293,7 @@ def main():
                    "workspace_GB": round(main_res["run"].ws.numel() * main_res["run"].ws.element_size() / 1e9, 2)},
         "roofline": roof,
         "kernel_ms_per_step": kernel_ms,
+        "hadamard_hbm": hbm,
         "graph_step": main_res["graph"],
         "autotune": main_res["autotune"],
     }

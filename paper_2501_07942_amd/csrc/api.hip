@@ -2465,14 +2465,40 @@ static tt_status launch_dot(int B, const DevTT* dl, const DevTT* dp, const Filte
   return TT_OK;
 }
 
+// Work model of the Hadamard product: no flops counted (one multiply per
+// output element), bytes = write H once, read the likelihood (FP64) and the
+// density cores once, with the device ranks of the launch.
+template <typename T>
+__global__ void __launch_bounds__(256) hadamard_work_kernel(const DevTT* __restrict__ dl,
+                                                            const DevTT* __restrict__ dp, int B, double* work) {
+  __shared__ double red[4];
+  double by = 0.0;
+  for (int b = threadIdx.x; b < B; b += blockDim.x) {
+    const DevTT &L = dl[b], &P = dp[b];
+    for (int k = 0; k < P.d; ++k) {
+      const double n = P.n[k];
+      const double rl = (double)L.ranks[k] * L.ranks[k + 1], rp = (double)P.ranks[k] * P.ranks[k + 1];
+      by += sizeof(T) * rl * rp * n + 8.0 * rl * n + sizeof(T) * rp * n;
+    }
+  }
+  by = block_sum(by, red);
+  if (threadIdx.x == 0) work[2 * PC_HADAMARD + 1] += by;
+}
+
 template <typename T>
 static tt_status launch_hadamard(int B, int d, int r0cap, const DevTT* dl, const DevTT* dp, const DevTT* dh,
                                  hipStream_t st) {
   hipLaunchKernelGGL(product_init_kernel, dim3(cdiv(B, 64)), dim3(64), 0, st, dl, dp, dh, B);
   TTG_LAUNCH_CHECK("product_init_kernel");
-  ProfScope ps_(PC_HADAMARD, st);
-  hipLaunchKernelGGL((hadamard_kernel<T>), dim3(stride_grid(r0cap, B), d, B), dim3(256), 0, st, dl, dp, dh);
-  TTG_LAUNCH_CHECK("hadamard_kernel");
+  {
+    ProfScope ps_(PC_HADAMARD, st);
+    hipLaunchKernelGGL((hadamard_kernel<T>), dim3(stride_grid(r0cap, B, 8192), 1, B), dim3(256), 0, st, dl, dp, dh);
+    TTG_LAUNCH_CHECK("hadamard_kernel");
+  }
+  if (g_work && (g_prof_mask & (1 << PC_HADAMARD))) {
+    hipLaunchKernelGGL((hadamard_work_kernel<T>), dim3(1), dim3(256), 0, st, dl, dp, B, g_work);
+    TTG_LAUNCH_CHECK("hadamard_work_kernel");
+  }
   return TT_OK;
 }
 

@@ -129,30 +129,83 @@ template <typename T>
 __global__ void __launch_bounds__(256) hadamard_kernel(const DevTT* __restrict__ lik,
                                                        const DevTT* __restrict__ pin,
                                                        const DevTT* __restrict__ hout) {
-  const int f = blockIdx.z, k = blockIdx.y;
+  // one filter per blockIdx.z; the workgroups of a filter walk all its cores
+  // (few workgroups: the chip starts them at a bounded rate), each core as a
+  // grid-stride loop over its output elements e = (row (a, b), i, column
+  // (a', b')), every element written once, in order
+  const int f = blockIdx.z;
   const DevTT &L = lik[f], &P = pin[f], &H = hout[f];
-  if (k >= P.d) return;
-  const int rl0 = L.ranks[k], rl1 = L.ranks[k + 1];
-  const int rp0 = P.ranks[k], rp1 = P.ranks[k + 1];
-  const int R0 = rl0 * rp0, R1 = rl1 * rp1;
-  if (R0 > H.cap[k] || R1 > H.cap[k + 1]) return;
-  const int n = P.n[k];
-  // grid-stride over the rows (a, b) of the output core; within a row the
-  // threads take fixed columns j = (a', b') and step over the grid index i
-  const int lanes = max(1, (int)blockDim.x / R1);  // threads per column (R1 < 256)
-  const int jstep = lanes > 1 ? R1 : (int)blockDim.x;
-  const int j0 = lanes > 1 ? (int)threadIdx.x % R1 : (int)threadIdx.x;
-  const int i0 = lanes > 1 ? (int)threadIdx.x / R1 : 0;
-  if (i0 >= lanes) return;
-  for (int row = blockIdx.x; row < R0; row += gridDim.x) {
-    const int a = row / rp0, b = row % rp0;
-    const double* lc = core_ptr<double>(L, k) + (long long)a * n * rl1;
-    const T* pc = core_ptr<T>(P, k) + (long long)b * n * rp1;
-    T* hc = core_ptr<T>(H, k) + (long long)row * n * R1;
-    for (int j = j0; j < R1; j += jstep) {
-      const int a2 = j / rp1, b2 = j - (j / rp1) * rp1;
-      for (int i = i0; i < n; i += lanes)
-        hc[(long long)i * R1 + j] = from_double<T>(lc[(long long)i * rl1 + a2] * bulk_to_double(pc[(long long)i * rp1 + b2]));
+  const int stride = gridDim.x * blockDim.x;
+  const int t0 = blockIdx.x * blockDim.x + threadIdx.x;
+  for (int k = 0; k < P.d; ++k) {
+    const int rl1 = L.ranks[k + 1];
+    const int rp0 = P.ranks[k], rp1 = P.ranks[k + 1];
+    const int R0 = L.ranks[k] * rp0, R1 = rl1 * rp1;
+    if (R0 > H.cap[k] || R1 > H.cap[k + 1]) continue;
+    const int n = P.n[k];
+    if ((long long)R0 * n * R1 > 0x7fffffffLL) {  // 32-bit element indices below
+      if (t0 == 0) set_status(H.status, TT_STATUS_CAPACITY);
+      continue;
+    }
+    const double* lc = core_ptr<double>(L, k);
+    const T* pc = core_ptr<T>(P, k);
+    T* hc = core_ptr<T>(H, k);
+    const int nR1 = n * R1;
+    const int tot = R0 * nR1;
+    const bool vec = sizeof(T) == 4 && (R1 & 3) == 0 && (rp1 & 3) == 0 &&
+                     ((reinterpret_cast<uintptr_t>(hc) | reinterpret_cast<uintptr_t>(pc)) & 15) == 0;
+    if (vec && stride % (R1 >> 2) == 0) {
+      // a thread keeps one quad of columns (a', b'..b'+3) and steps over the
+      // positions (row, i); one 16-byte load of P and one 16-byte store of H
+      const int Q = R1 >> 2, qj = t0 % Q, pstep = stride / Q;
+      const int j = qj << 2, a2 = j / rp1, b2 = j - a2 * rp1;
+      const int npos = R0 * n;
+      const int drow = pstep / n, di = pstep - drow * n;
+      int p = t0 / Q;
+      int row = p / n, i = p - row * n;
+      for (; p < npos; p += pstep) {
+        const int a = row / rp0, b = row - a * rp0;
+        const double lv = lc[(a * n + i) * rl1 + a2];
+        const float4 pv = *reinterpret_cast<const float4*>(pc + (b * n + i) * rp1 + b2);
+        typedef float had_f4 __attribute__((ext_vector_type(4)));
+        const had_f4 o = {from_double<float>(lv * (double)pv.x), from_double<float>(lv * (double)pv.y),
+                          from_double<float>(lv * (double)pv.z), from_double<float>(lv * (double)pv.w)};
+        __builtin_nontemporal_store(o, reinterpret_cast<had_f4*>(hc + (row * n + i) * R1 + j));
+        row += drow;
+        i += di;
+        if (i >= n) {
+          i -= n;
+          ++row;
+        }
+      }
+      continue;
+    }
+    if (vec) {
+      // four consecutive columns share a' and read four consecutive b' of P:
+      // one 16-byte load of P and one 16-byte store of H
+      for (int q = t0; q < (tot >> 2); q += stride) {
+        const int e = q << 2;
+        const int row = e / nR1, rem = e - row * nR1;
+        const int i = rem / R1, j = rem - i * R1;
+        const int a = row / rp0, b = row - a * rp0;
+        const int a2 = j / rp1, b2 = j - a2 * rp1;
+        const double lv = lc[(a * n + i) * rl1 + a2];
+        const float4 pv = *reinterpret_cast<const float4*>(pc + (b * n + i) * rp1 + b2);
+        float4 o;
+        o.x = from_double<float>(lv * (double)pv.x);
+        o.y = from_double<float>(lv * (double)pv.y);
+        o.z = from_double<float>(lv * (double)pv.z);
+        o.w = from_double<float>(lv * (double)pv.w);
+        *reinterpret_cast<float4*>(hc + e) = o;
+      }
+      continue;
+    }
+    for (int e = t0; e < tot; e += stride) {
+      const int row = e / nR1, rem = e - row * nR1;
+      const int i = rem / R1, j = rem - i * R1;
+      const int a = row / rp0, b = row - a * rp0;
+      const int a2 = j / rp1, b2 = j - a2 * rp1;
+      hc[e] = from_double<T>(lc[(a * n + i) * rl1 + a2] * bulk_to_double(pc[(b * n + i) * rp1 + b2]));
     }
   }
 }
