@@ -87,7 +87,75 @@ __global__ void __launch_bounds__(256) pred_adj_p_kernel(const DevTT* __restrict
   }
 }
 
-// one workgroup per kernel-core element, a block reduction over (c, i, e)
+// Pbar with the adjoint cores staged in LDS: one workgroup per density row
+// c and block of PADJ_JB grid points j; for each kernel row a it stages the
+// kernel slice K(a, :, :) and the rows i = j - h .. j + PADJ_JB - 1 + h of
+// Cbar(a rp0 + c, :, :) (zero off the grid), so every Cbar element is read
+// from memory about (PADJ_JB + 2h) / PADJ_JB times instead of once per tap.
+// Each thread owns up to four outputs (j, e); sums run over a, then taps,
+// then b, in a fixed order.  LDS: (taps rk1 + (PADJ_JB + 2h) rk1 rp1) T.
+#define PADJ_JB 16
+template <typename T>
+__global__ void __launch_bounds__(256) pred_adj_p_lds_kernel(const DevTT* __restrict__ kern,
+                                                             const DevTT* __restrict__ pin,
+                                                             const DevTT* __restrict__ cbar,
+                                                             const DevTT* __restrict__ pbar) {
+  const int f = blockIdx.z, k = blockIdx.y;
+  const DevTT &K = kern[f], &P = pin[f], &C = cbar[f], &Q = pbar[f];
+  if (k >= P.d || !adj_shapes_ok(K, P, C, k) || P.ranks[k] > Q.cap[k] || P.ranks[k + 1] > Q.cap[k + 1]) return;
+  const int rk0 = K.ranks[k], rk1 = K.ranks[k + 1], rp0 = P.ranks[k], rp1 = P.ranks[k + 1];
+  const int R1 = rk1 * rp1;
+  const int n = P.n[k], taps = K.n[k], h = (taps - 1) / 2;
+  const int nblk = (n + PADJ_JB - 1) / PADJ_JB, rows = PADJ_JB + 2 * h, nout = PADJ_JB * rp1;
+  if (nout > 4 * (int)blockDim.x) return;  // excluded by the host (rp1 <= 64)
+  extern __shared__ unsigned char padj_smem[];
+  T* Ks = reinterpret_cast<T*>(padj_smem);
+  T* Cs = Ks + taps * rk1;
+  const T* kc = core_ptr<T>(K, k);
+  const T* cc = core_ptr<T>(C, k);
+  T* qc = core_ptr<T>(Q, k);
+  for (int blk = blockIdx.x; blk < rp0 * nblk; blk += gridDim.x) {
+    const int c = blk / nblk, j0 = (blk - (blk / nblk) * nblk) * PADJ_JB, i_lo = j0 - h;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int a = 0; a < rk0; ++a) {
+      __syncthreads();
+      for (int e = threadIdx.x; e < taps * rk1; e += blockDim.x) Ks[e] = kc[(long long)a * taps * rk1 + e];
+      const T* crow = cc + (long long)(a * rp0 + c) * n * R1;
+      for (int e = threadIdx.x; e < rows * R1; e += blockDim.x) {
+        const int r = e / R1, col = e - (e / R1) * R1, i = i_lo + r;
+        Cs[e] = (i >= 0 && i < n) ? crow[(long long)i * R1 + col] : (T)0;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int o = threadIdx.x + q * blockDim.x;
+        if (o >= nout) break;
+        const int jl = o / rp1, e = o - (o / rp1) * rp1;
+        double s = acc[q];
+        // i = j0 + jl + m with m = tm - h sits in row jl + tm of the stage
+        for (int tm = 0; tm < taps; ++tm) {
+          const T* kr = Ks + tm * rk1;
+          const T* cr = Cs + (jl + tm) * R1 + e;
+          for (int b = 0; b < rk1; ++b) s += bulk_to_double(kr[b]) * bulk_to_double(cr[b * rp1]);
+        }
+        acc[q] = s;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int o = threadIdx.x + q * blockDim.x;
+      if (o >= nout) break;
+      const int jl = o / rp1, e = o - (o / rp1) * rp1, j = j0 + jl;
+      if (j < n) qc[((long long)c * n + j) * rp1 + e] = from_double<T>(acc[q]);
+    }
+  }
+}
+
+// One workgroup per kernel bond pair (a, b): one pass over its slice of
+// Cbar (read once per PADJ_TAPS taps) accumulates every tap of that pair at
+// once (the density values it needs are PADJ_TAPS shifted reads of one
+// fibre), then a fixed-order block reduction per tap.
+#define PADJ_TAPS 32
 template <typename T>
 __global__ void __launch_bounds__(256) pred_adj_k_kernel(const DevTT* __restrict__ kern,
                                                          const DevTT* __restrict__ pin,
@@ -100,28 +168,35 @@ __global__ void __launch_bounds__(256) pred_adj_k_kernel(const DevTT* __restrict
   const int rk0 = K.ranks[k], rk1 = K.ranks[k + 1], rp0 = P.ranks[k], rp1 = P.ranks[k + 1];
   const int R1 = rk1 * rp1;
   const int n = P.n[k], taps = K.n[k], h = (taps - 1) / 2;
-  const long long nel = (long long)rk0 * taps * rk1;
   const long long nt = (long long)rp0 * n * rp1;
   const T* cc = core_ptr<T>(C, k);
   const T* pc = core_ptr<T>(P, k);
   T* qc = core_ptr<T>(Q, k);
-  for (long long el = blockIdx.x; el < nel; el += gridDim.x) {
-    const int a = (int)(el / ((long long)taps * rk1));
-    const int rem = (int)(el - (long long)a * taps * rk1);
-    const int tm = rem / rk1, b = rem - (rem / rk1) * rk1;
-    const int m = tm - h;
-    double acc = 0.0;
-    for (long long t = threadIdx.x; t < nt; t += blockDim.x) {
-      const int c = (int)(t / ((long long)n * rp1));
-      const int r2 = (int)(t - (long long)c * n * rp1);
-      const int i = r2 / rp1, ee = r2 - (r2 / rp1) * rp1;
-      const int ip = i - m;
-      if (ip < 0 || ip >= n) continue;
-      acc += bulk_to_double(cc[((long long)(a * rp0 + c) * n + i) * R1 + (long long)b * rp1 + ee]) *
-             bulk_to_double(pc[((long long)c * n + ip) * rp1 + ee]);
+  for (int pair = blockIdx.x; pair < rk0 * rk1; pair += gridDim.x) {
+    const int a = pair / rk1, b = pair - (pair / rk1) * rk1;
+    for (int m0 = 0; m0 < taps; m0 += PADJ_TAPS) {
+      const int mc = min(PADJ_TAPS, taps - m0);
+      double acc[PADJ_TAPS];
+#pragma unroll
+      for (int u = 0; u < PADJ_TAPS; ++u) acc[u] = 0.0;
+      for (long long t = threadIdx.x; t < nt; t += blockDim.x) {
+        const int c = (int)(t / ((long long)n * rp1));
+        const int r2 = (int)(t - (long long)c * n * rp1);
+        const int i = r2 / rp1, ee = r2 - (r2 / rp1) * rp1;
+        const double cv = bulk_to_double(cc[((long long)(a * rp0 + c) * n + i) * R1 + (long long)b * rp1 + ee]);
+        const T* prow = pc + (long long)c * n * rp1 + ee;
+        // tap tm = m0 + u has offset m = tm - h and reads P(c, i - m, e)
+#pragma unroll
+        for (int u = 0; u < PADJ_TAPS; ++u) {
+          const int ip = i - (m0 + u - h);
+          if (u < mc && ip >= 0 && ip < n) acc[u] += cv * bulk_to_double(prow[(long long)ip * rp1]);
+        }
+      }
+      for (int u = 0; u < mc; ++u) {
+        const double sum = block_sum(acc[u], red);
+        if (threadIdx.x == 0) qc[((long long)a * taps + m0 + u) * rk1 + b] = from_double<T>(sum);
+      }
     }
-    acc = block_sum(acc, red);
-    if (threadIdx.x == 0) qc[el] = from_double<T>(acc);
   }
 }
 
