@@ -152,10 +152,14 @@ __global__ void __launch_bounds__(256) pred_adj_p_lds_kernel(const DevTT* __rest
 }
 
 // One workgroup per kernel bond pair (a, b): one pass over its slice of
-// Cbar (read once per PADJ_TAPS taps) accumulates every tap of that pair at
-// once (the density values it needs are PADJ_TAPS shifted reads of one
-// fibre), then a fixed-order block reduction per tap.
+// Cbar per PADJ_TAPS taps accumulates every tap of that pair at once.  A
+// work item is one density pair (c, e) and PADJ_ROWS consecutive grid points
+// i: it holds their Cbar values and the window of density values
+// P(c, i - m, e) those rows need for the chunk's taps in registers, so each
+// load feeds several multiply-adds.  A fixed-order block reduction per tap
+// follows.
 #define PADJ_TAPS 32
+#define PADJ_ROWS 8
 template <typename T>
 __global__ void __launch_bounds__(256) pred_adj_k_kernel(const DevTT* __restrict__ kern,
                                                          const DevTT* __restrict__ pin,
@@ -168,7 +172,9 @@ __global__ void __launch_bounds__(256) pred_adj_k_kernel(const DevTT* __restrict
   const int rk0 = K.ranks[k], rk1 = K.ranks[k + 1], rp0 = P.ranks[k], rp1 = P.ranks[k + 1];
   const int R1 = rk1 * rp1;
   const int n = P.n[k], taps = K.n[k], h = (taps - 1) / 2;
-  const long long nt = (long long)rp0 * n * rp1;
+  const int nib = (n + PADJ_ROWS - 1) / PADJ_ROWS;
+  const long long items = (long long)rp0 * rp1 * nib;
+  constexpr int W = PADJ_ROWS + PADJ_TAPS - 1;
   const T* cc = core_ptr<T>(C, k);
   const T* pc = core_ptr<T>(P, k);
   T* qc = core_ptr<T>(Q, k);
@@ -179,18 +185,27 @@ __global__ void __launch_bounds__(256) pred_adj_k_kernel(const DevTT* __restrict
       double acc[PADJ_TAPS];
 #pragma unroll
       for (int u = 0; u < PADJ_TAPS; ++u) acc[u] = 0.0;
-      for (long long t = threadIdx.x; t < nt; t += blockDim.x) {
-        const int c = (int)(t / ((long long)n * rp1));
-        const int r2 = (int)(t - (long long)c * n * rp1);
-        const int i = r2 / rp1, ee = r2 - (r2 / rp1) * rp1;
-        const double cv = bulk_to_double(cc[((long long)(a * rp0 + c) * n + i) * R1 + (long long)b * rp1 + ee]);
-        const T* prow = pc + (long long)c * n * rp1 + ee;
-        // tap tm = m0 + u has offset m = tm - h and reads P(c, i - m, e)
+      for (long long t = threadIdx.x; t < items; t += blockDim.x) {
+        const int e = (int)(t % rp1);
+        const long long rest = t / rp1;
+        const int c = (int)(rest % rp0), i0 = (int)(rest / rp0) * PADJ_ROWS;
+        const T* crow = cc + ((long long)(a * rp0 + c) * n) * R1 + (long long)b * rp1 + e;
+        const T* prow = pc + (long long)c * n * rp1 + e;
+        double cv[PADJ_ROWS], w[W];
 #pragma unroll
-        for (int u = 0; u < PADJ_TAPS; ++u) {
-          const int ip = i - (m0 + u - h);
-          if (u < mc && ip >= 0 && ip < n) acc[u] += cv * bulk_to_double(prow[(long long)ip * rp1]);
+        for (int r = 0; r < PADJ_ROWS; ++r)
+          cv[r] = (i0 + r < n) ? bulk_to_double(crow[(long long)(i0 + r) * R1]) : 0.0;
+        // tap tm = m0 + u (offset m = tm - h) reads P(c, i0 + r - m, e) = w[PADJ_TAPS - 1 + r - u]
+        const int base = i0 - m0 - (PADJ_TAPS - 1) + h;
+#pragma unroll
+        for (int v = 0; v < W; ++v) {
+          const int ip = base + v;
+          w[v] = (ip >= 0 && ip < n) ? bulk_to_double(prow[(long long)ip * rp1]) : 0.0;
         }
+#pragma unroll
+        for (int u = 0; u < PADJ_TAPS; ++u)
+#pragma unroll
+          for (int r = 0; r < PADJ_ROWS; ++r) acc[u] += cv[r] * w[PADJ_TAPS - 1 + r - u];
       }
       for (int u = 0; u < mc; ++u) {
         const double sum = block_sum(acc[u], red);
