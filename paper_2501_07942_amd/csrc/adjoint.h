@@ -87,16 +87,15 @@ __global__ void __launch_bounds__(256) pred_adj_p_kernel(const DevTT* __restrict
   }
 }
 
-// Pbar with the adjoint cores staged in LDS: one workgroup per density row
-// c and block of PADJ_JB grid points j; for each kernel row a it stages the
-// kernel slice K(a, :, :) and the rows i = j - h .. j + PADJ_JB - 1 + h of
-// Cbar(a rp0 + c, :, :) (zero off the grid), so every Cbar element is read
-// from memory about (PADJ_JB + 2h) / PADJ_JB times instead of once per tap.
-// Each thread owns up to four outputs (j, e); sums run over a, then taps,
-// then b, in a fixed order.  LDS: (taps rk1 + (PADJ_JB + 2h) rk1 rp1) T.
-#define PADJ_JB 16
+// Pbar with register windows: a work item is one density pair (c, e) and
+// PADJ_JROWS consecutive grid points j; for every kernel pair (a, b) it loads
+// the window of Cbar(a rp0 + c, i, b rp1 + e) over i = j + m that its rows
+// and a chunk of PADJ_TAPS taps need, and multiplies it with the kernel
+// values of that pair (staged once per workgroup in LDS).  Sums run over a,
+// b, tap chunks and taps in a fixed order.  LDS: rk0 taps rk1 elements.
+#define PADJ_JROWS 16
 template <typename T>
-__global__ void __launch_bounds__(256) pred_adj_p_lds_kernel(const DevTT* __restrict__ kern,
+__global__ void __launch_bounds__(256) pred_adj_p_reg_kernel(const DevTT* __restrict__ kern,
                                                              const DevTT* __restrict__ pin,
                                                              const DevTT* __restrict__ cbar,
                                                              const DevTT* __restrict__ pbar) {
@@ -106,47 +105,53 @@ __global__ void __launch_bounds__(256) pred_adj_p_lds_kernel(const DevTT* __rest
   const int rk0 = K.ranks[k], rk1 = K.ranks[k + 1], rp0 = P.ranks[k], rp1 = P.ranks[k + 1];
   const int R1 = rk1 * rp1;
   const int n = P.n[k], taps = K.n[k], h = (taps - 1) / 2;
-  const int nblk = (n + PADJ_JB - 1) / PADJ_JB, rows = PADJ_JB + 2 * h, nout = PADJ_JB * rp1;
-  if (nout > 4 * (int)blockDim.x) return;  // excluded by the host (rp1 <= 64)
+  const int njb = (n + PADJ_JROWS - 1) / PADJ_JROWS;
+  const long long items = (long long)rp0 * rp1 * njb;
+  constexpr int TC = 32, W = PADJ_JROWS + TC - 1;
   extern __shared__ unsigned char padj_smem[];
-  T* Ks = reinterpret_cast<T*>(padj_smem);
-  T* Cs = Ks + taps * rk1;
+  T* Ks = reinterpret_cast<T*>(padj_smem);  // K_k(a, tm, b) as stored
   const T* kc = core_ptr<T>(K, k);
+  for (int e = threadIdx.x; e < rk0 * taps * rk1; e += blockDim.x) Ks[e] = kc[e];
+  __syncthreads();
   const T* cc = core_ptr<T>(C, k);
   T* qc = core_ptr<T>(Q, k);
-  for (int blk = blockIdx.x; blk < rp0 * nblk; blk += gridDim.x) {
-    const int c = blk / nblk, j0 = (blk - (blk / nblk) * nblk) * PADJ_JB, i_lo = j0 - h;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int a = 0; a < rk0; ++a) {
-      __syncthreads();
-      for (int e = threadIdx.x; e < taps * rk1; e += blockDim.x) Ks[e] = kc[(long long)a * taps * rk1 + e];
-      const T* crow = cc + (long long)(a * rp0 + c) * n * R1;
-      for (int e = threadIdx.x; e < rows * R1; e += blockDim.x) {
-        const int r = e / R1, col = e - (e / R1) * R1, i = i_lo + r;
-        Cs[e] = (i >= 0 && i < n) ? crow[(long long)i * R1 + col] : (T)0;
-      }
-      __syncthreads();
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < items;
+       t += (long long)gridDim.x * blockDim.x) {
+    const int e = (int)(t % rp1);
+    const long long rest = t / rp1;
+    const int c = (int)(rest % rp0), j0 = (int)(rest / rp0) * PADJ_JROWS;
+    double acc[PADJ_JROWS];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int o = threadIdx.x + q * blockDim.x;
-        if (o >= nout) break;
-        const int jl = o / rp1, e = o - (o / rp1) * rp1;
-        double s = acc[q];
-        // i = j0 + jl + m with m = tm - h sits in row jl + tm of the stage
-        for (int tm = 0; tm < taps; ++tm) {
-          const T* kr = Ks + tm * rk1;
-          const T* cr = Cs + (jl + tm) * R1 + e;
-          for (int b = 0; b < rk1; ++b) s += bulk_to_double(kr[b]) * bulk_to_double(cr[b * rp1]);
+    for (int r = 0; r < PADJ_JROWS; ++r) acc[r] = 0.0;
+    for (int a = 0; a < rk0; ++a)
+      for (int b = 0; b < rk1; ++b) {
+        const T* crow = cc + ((long long)(a * rp0 + c) * n) * R1 + (long long)b * rp1 + e;
+        const T* kr = Ks + (long long)a * taps * rk1 + b;
+        for (int m0 = 0; m0 < taps; m0 += TC) {
+          // output j = j0 + r and tap tm = m0 + u (offset m = tm - h) read
+          // Cbar at i = j + m = base + r + u
+          const int base = j0 + m0 - h;
+          double w[W];
+#pragma unroll
+          for (int v = 0; v < W; ++v) {
+            const int i = base + v;
+            w[v] = (i >= 0 && i < n) ? bulk_to_double(crow[(long long)i * R1]) : 0.0;
+          }
+          const int mc = min(TC, taps - m0);
+#pragma unroll
+          for (int u = 0; u < TC; ++u) {
+            if (u < mc) {
+              const double kv = bulk_to_double(kr[(long long)(m0 + u) * rk1]);
+#pragma unroll
+              for (int r = 0; r < PADJ_JROWS; ++r) acc[r] += kv * w[r + u];
+            }
+          }
         }
-        acc[q] = s;
       }
-    }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int o = threadIdx.x + q * blockDim.x;
-      if (o >= nout) break;
-      const int jl = o / rp1, e = o - (o / rp1) * rp1, j = j0 + jl;
-      if (j < n) qc[((long long)c * n + j) * rp1 + e] = from_double<T>(acc[q]);
+    for (int r = 0; r < PADJ_JROWS; ++r) {
+      const int j = j0 + r;
+      if (j < n) qc[((long long)c * n + j) * rp1 + e] = from_double<T>(acc[r]);
     }
   }
 }

@@ -2660,30 +2660,28 @@ tt_status tt_predict_adjoint(int32_t batch, const tt_train* kernels, const tt_tr
   int pel = 1;
   for (int b = 0; b < batch; ++b)
     for (int k = 0; k < d; ++k) pel = std::max(pel, p_in[b].cap[k] * p_in[b].n[k] * p_in[b].cap[k + 1]);
-  // the staged Pbar kernel when its LDS fits and a workgroup's outputs fit
-  // four per thread (decided from capacities only)
-  int rk1cap = 1, rp1cap = 1, r1cap = 1, rp0cap = 1, nmax = 1;
+  // the register-window Pbar kernel when the kernel core fits the LDS
+  // (decided from capacities only)
+  int kelcap = 1, rp0cap = 1, rp1cap = 1, nmax = 1;
   for (int b = 0; b < batch; ++b)
     for (int k = 0; k < d; ++k) {
-      rk1cap = std::max(rk1cap, kernels[b].cap[k + 1]);
-      rp1cap = std::max(rp1cap, p_in[b].cap[k + 1]);
-      r1cap = std::max(r1cap, kernels[b].cap[k + 1] * p_in[b].cap[k + 1]);
+      kelcap = std::max(kelcap, kernels[b].cap[k] * kernels[b].n[k] * kernels[b].cap[k + 1]);
       rp0cap = std::max(rp0cap, p_in[b].cap[k]);
+      rp1cap = std::max(rp1cap, p_in[b].cap[k + 1]);
       nmax = std::max(nmax, p_in[b].n[k]);
     }
-  const size_t esz = dtype == TT_F64 ? 8 : 4;
-  const size_t padj_lds = esz * ((size_t)tapmax * rk1cap + (size_t)(PADJ_JB + tapmax - 1) * r1cap);
-  const bool staged = padj_lds <= 160 * 1024 && PADJ_JB * rp1cap <= 4 * 256;
-  const int padj_grid = (int)std::min<long long>((long long)rp0cap * cdiv(nmax, PADJ_JB), 65535);
-  if (staged) {
-    const void* fn = dtype == TT_F64 ? (const void*)pred_adj_p_lds_kernel<double>
-                                     : (const void*)pred_adj_p_lds_kernel<float>;
-    if (padj_lds > 48 * 1024)
-      HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)padj_lds), "padj smem");
+  const size_t padj_lds = (size_t)kelcap * (dtype == TT_F64 ? 8 : 4);
+  const bool staged = padj_lds <= 64 * 1024;
+  const long long padj_items = (long long)rp0cap * rp1cap * cdiv(nmax, PADJ_JROWS);
+  const int padj_grid = stride_grid(cdiv(padj_items, 256), batch * d);
+  if (staged && padj_lds > 48 * 1024) {
+    const void* fn = dtype == TT_F64 ? (const void*)pred_adj_p_reg_kernel<double>
+                                     : (const void*)pred_adj_p_reg_kernel<float>;
+    HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)padj_lds), "padj smem");
   }
   if (dtype == TT_F64) {
     if (staged)
-      hipLaunchKernelGGL((pred_adj_p_lds_kernel<double>), dim3(padj_grid, d, batch), dim3(256), padj_lds, st, dk, dp,
+      hipLaunchKernelGGL((pred_adj_p_reg_kernel<double>), dim3(padj_grid, d, batch), dim3(256), padj_lds, st, dk, dp,
                          dc, dpb);
     else
       hipLaunchKernelGGL((pred_adj_p_kernel<double>), dim3(stride_grid(cdiv(pel, 256), batch), d, batch), dim3(256),
@@ -2694,7 +2692,7 @@ tt_status tt_predict_adjoint(int32_t batch, const tt_train* kernels, const tt_tr
     TTG_LAUNCH_CHECK("pred_adj_k_kernel");
   } else {
     if (staged)
-      hipLaunchKernelGGL((pred_adj_p_lds_kernel<float>), dim3(padj_grid, d, batch), dim3(256), padj_lds, st, dk, dp,
+      hipLaunchKernelGGL((pred_adj_p_reg_kernel<float>), dim3(padj_grid, d, batch), dim3(256), padj_lds, st, dk, dp,
                          dc, dpb);
     else
       hipLaunchKernelGGL((pred_adj_p_kernel<float>), dim3(stride_grid(cdiv(pel, 256), batch), d, batch), dim3(256),
