@@ -194,6 +194,23 @@ size_t tt_round_workspace(int32_t batch, const tt_train* t_in, const tt_train* t
 tt_status tt_round(int32_t batch, const tt_train* t_in, const tt_train* t_out, double eps,
                    int32_t max_rank, void* ws, size_t ws_bytes, void* stream);
 
+/* tt_round_taped -- tt_round (FP64 trains only) that also records, per
+ * filter, the products of its right-to-left sweep that tt_round_adjoint
+ * needs: for every bond j = 1..d-1 the Gram matrix G of the right part of
+ * the input at bond j (r_j x r_j, r_j = the input's rank there, row-major,
+ * leading dimension r_j) and its pivoted Cholesky factor F (G ~ F F^T, rows
+ * in the original order, r_j x r_j, columns beyond its rank zero).  Bond 1
+ * is not recorded when it is wider than n[0] (the sweep folds core 0 into
+ * it); valid[j] says which bonds were.  Caller-owned device buffers:
+ * g[j], f[j] of in->cap[j]^2 doubles, valid of d+1 int32. */
+typedef struct {
+  double* g[TT_MAXD];
+  double* f[TT_MAXD];
+  int32_t* valid;
+} tt_round_tape;
+tt_status tt_round_taped(int32_t batch, const tt_train* t_in, const tt_train* t_out, double eps,
+                         int32_t max_rank, const tt_round_tape* tape, void* ws, size_t ws_bytes, void* stream);
+
 /* ---------------------------------------------------------------------
  * tt_normalize_moments -- mass, normalisation and moments (Sec. 4.1 'sum',
  * 'mrdivide', 'power', 'dot'; Alg. 2 steps 2-4), for rank capacities <= 64:
@@ -266,15 +283,19 @@ size_t tt_normalize_moments_workspace(int32_t batch, const tt_train* t);
  * 6e-6 of the largest at a bond are left out of the eigenvector adjoint
  * (rounding noise there exceeds their signal) and discarded ones below 1e-9
  * count as null space.  The call reads the ranks to the host once and is
- * synchronous (it returns after the work is done).  Workspace:
+ * synchronous (it returns after the work is done).  tape (nullable): the
+ * record tt_round_taped wrote for this rounding; its Grams and factors are
+ * used instead of being recomputed.  Workspace:
  * tt_round_adjoint_workspace(batch, a, y) bytes (from the capacities).
- * Errors: TT_ERR_ARG (null, non-FP64), TT_ERR_SHAPE (modes, capacities or
- * ranks inconsistent, y_bar ranks differ from y, a rank above 1024),
+ * Errors: TT_ERR_ARG (null, non-FP64, a recorded bond whose buffers are
+ * null), TT_ERR_SHAPE (modes, capacities or ranks inconsistent, y_bar ranks
+ * differ from y, a rank above 1024),
  * TT_ERR_WORKSPACE, TT_ERR_HIP.
  * --------------------------------------------------------------------- */
 size_t tt_round_adjoint_workspace(int32_t batch, const tt_train* a, const tt_train* y);
 tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, const tt_train* y_bar,
-                           const tt_train* a_bar, void* ws, size_t ws_bytes, void* stream);
+                           const tt_train* a_bar, const tt_round_tape* tape, void* ws, size_t ws_bytes,
+                           void* stream);
 
 /* ---------------------------------------------------------------------
  * Pieces for a composed reverse-mode gradient (all FP64 trains):

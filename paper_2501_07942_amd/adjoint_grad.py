@@ -82,7 +82,9 @@ class ComposedGradient:
         # with a checkpoint per step the forward also keeps each step's
         # rounded and normalised predictive, likelihood and update product
         # (a few MB per filter and step), so the reverse sweep recomputes only
-        # the prediction product, not the two roundings
+        # the prediction product, not the two roundings; the prediction
+        # rounding also records its right-part Grams and factors, which its
+        # adjoint would otherwise recompute
         self.tape = bool(tape) and self.C == 1
         self.torch = torch
         self.specs = list(specs)
@@ -108,13 +110,14 @@ class ComposedGradient:
         B.tt_normalize_moments(self.grids, tts, lm)
         return lm
 
-    def _round(self, xs):
+    def _round(self, xs, tape=None):
         outs = _new([x.n for x in xs], self.pcaps)
         groups = {}
         for i, s in enumerate(self.specs):
             groups.setdefault((s.eps, s.cap), []).append(i)
         for (eps, cap), idx in groups.items():    # one batched call per tolerance and cap
-            B.tt_round([xs[i] for i in idx], [outs[i] for i in idx], eps, cap)
+            B.tt_round([xs[i] for i in idx], [outs[i] for i in idx], eps, cap,
+                       tape=tape.select(idx) if tape is not None else None)
         return outs
 
     def _likelihood(self, k, meas=None):
@@ -127,9 +130,12 @@ class ComposedGradient:
         B.tt_likelihood_dense(self.grids, meas or self.meas, self._zk(k), ps)
         return ps
 
-    def _step(self, k, p_prev):
-        """Recompute step k from the filtering density p_prev (None at k = 0)."""
+    def _step(self, k, p_prev, record=False):
+        """Recompute step k from the filtering density p_prev (None at k = 0).
+        record: keep the prediction rounding's right-to-left Grams and factors
+        (st.xtape) for its adjoint."""
         st = _Step()
+        st.xtape = None
         if k == 0:
             pt = _new([[s.n] * s.d for s in self.specs], self.pcaps)
             B.tt_prior(self.grids, np.array([s.m0 for s in self.specs]), np.array([s.p0_diag for s in self.specs]), pt)
@@ -137,7 +143,9 @@ class ComposedGradient:
         else:
             st.x = _new([p.n for p in p_prev], [_prod_caps(kk, p) for kk, p in zip(self.kern, p_prev)])
             B.tt_predict(self.kern, p_prev, st.x)
-            pt = self._round(st.x)
+            if record:
+                st.xtape = B.RoundTape(st.x)
+            pt = self._round(st.x, st.xtape)
         st.pt = pt
         self._normalise(pt)            # pt now holds P_pred (same cores)
         st.lik = self._likelihood(k)
@@ -157,7 +165,7 @@ class ComposedGradient:
         ll = self.torch.zeros(self.Bn, dtype=self.torch.float64, device="cuda")
         p = None
         for k in range(self.K):
-            st = self._step(k, p)
+            st = self._step(k, p, record=self.tape)
             ll += st.log_c
             p = st.hr
             if (k + 1) % self.C == 0 and k + 1 < self.K:
@@ -232,7 +240,7 @@ class ComposedGradient:
         ptbar = _like(st.pt)
         B.tt_normalize_adjoint(st.pt, ppbar, None, ptbar)
         xbar = _like(st.x)
-        B.tt_round_adjoint(st.x, st.pt, ptbar, xbar)
+        B.tt_round_adjoint(st.x, st.pt, ptbar, xbar, tape=st.xtape.structs if st.xtape is not None else None)
         pbar = _like(pprev)
         kb = _like(self.kern)
         B.tt_predict_adjoint(self.kern, pprev, xbar, pbar, kb)

@@ -45,6 +45,10 @@ class FilterSpec(C.Structure):
                 ("lik_rank_cap", C.c_int32)]
 
 
+class RoundTapeStruct(C.Structure):
+    _fields_ = [("g", C.c_void_p * MAXD), ("f", C.c_void_p * MAXD), ("valid", C.c_void_p)]
+
+
 class TTError(RuntimeError):
     pass
 
@@ -79,7 +83,8 @@ def _load():
         "tt_filter_graph_launch": (I, [P, P]),
         "tt_adjoint_workspace": (S, [I, I, I]),
         "tt_round_adjoint_workspace": (S, [I, P, P]),
-        "tt_round_adjoint": (I, [I, P, P, P, P, P, S, P]),
+        "tt_round_adjoint": (I, [I, P, P, P, P, P, P, S, P]),
+        "tt_round_taped": (I, [I, P, P, D, I, P, P, S, P]),
         "tt_prior": (I, [I, P, P, P, P, P, S, P]),
         "tt_likelihood": (I, [I, P, P, P, I, P, I, P, S, P]),
         "tt_kernel_build_batch_workspace": (S, [I, P, P, P]),
@@ -115,7 +120,7 @@ EXPORTED = ("tt_train_elems", "tt_last_error", "tt_version", "tt_kernel_build_wo
             "tt_round_adjoint_workspace", "tt_round_adjoint", "tt_prior", "tt_likelihood", "tt_likelihood_dense",
             "tt_kernel_build_batch_workspace", "tt_kernel_build_batch",
             "tt_likelihood_adjoint_workspace", "tt_likelihood_adjoint", "tt_adjoint_axpy",
-            "tt_adjoint_inner", "tt_align_signs")
+            "tt_adjoint_inner", "tt_align_signs", "tt_round_taped")
 
 PREDICT_DIRECT, PREDICT_FFT, PREDICT_UNFUSED, PREDICT_DIRECT_VALU = 0, 1, 2, 3
 
@@ -352,14 +357,50 @@ def tt_update(grids: Sequence[Grid], meas: Sequence[Meas], z, p_pred: Sequence[D
                          log_c.data_ptr(), ws.data_ptr(), ws.numel(), _stream()), "tt_update")
 
 
-def tt_round(t_in: Sequence[DeviceTT], t_out: Sequence[DeviceTT], eps: float, max_rank: int):
+class RoundTape:
+    """Record of an FP64 rounding's right-to-left sweep, one per filter: for
+    each bond j the right-part Gram and its pivoted Cholesky factor
+    (cap[j] x cap[j] doubles each, cap of the rounding's input) and a flag
+    per bond, all in one device allocation."""
+
+    def __init__(self, t_in: Sequence[DeviceTT]):
+        torch = _torch()
+        self.d = t_in[0].d
+        self.sizes = [[t.cap[j] * t.cap[j] if 1 <= j < self.d else 0 for j in range(self.d)] for t in t_in]
+        per = [2 * sum(sz) for sz in self.sizes]
+        self.buf = torch.zeros(max(sum(per), 1), dtype=torch.float64, device="cuda")
+        self.valid = torch.zeros((len(t_in), self.d + 1), dtype=torch.int32, device="cuda")
+        self.structs = []
+        off = 0
+        for b, sz in enumerate(self.sizes):
+            st = RoundTapeStruct()
+            for j in range(1, self.d):
+                st.g[j] = self.buf.data_ptr() + 8 * off
+                off += sz[j]
+                st.f[j] = self.buf.data_ptr() + 8 * off
+                off += sz[j]
+            st.valid = self.valid.data_ptr() + 4 * b * (self.d + 1)
+            self.structs.append(st)
+
+    def select(self, idx: Sequence[int]):
+        return [self.structs[i] for i in idx]
+
+
+def tt_round(t_in: Sequence[DeviceTT], t_out: Sequence[DeviceTT], eps: float, max_rank: int, tape=None):
+    """tape: None, or a list of RoundTapeStruct (one per filter, FP64 only)
+    that receives the right-to-left record for tt_round_adjoint."""
     B = len(t_in)
     a, b = _arr([t.struct() for t in t_in]), _arr([t.struct() for t in t_out])
     nbytes = LIB.tt_round_workspace(B, a, b)
     if nbytes == 0:
         _check(ERR_ARG, "tt_round_workspace")
     ws = _ws(nbytes)
-    _check(LIB.tt_round(B, a, b, float(eps), int(max_rank), ws.data_ptr(), ws.numel(), _stream()), "tt_round")
+    if tape is None:
+        _check(LIB.tt_round(B, a, b, float(eps), int(max_rank), ws.data_ptr(), ws.numel(), _stream()), "tt_round")
+    else:
+        assert len(tape) == B
+        _check(LIB.tt_round_taped(B, a, b, float(eps), int(max_rank), _arr(list(tape)), ws.data_ptr(), ws.numel(),
+                                  _stream()), "tt_round_taped")
 
 
 def tt_normalize_moments(grids: Sequence[Grid], tts: Sequence[DeviceTT], log_mass, mean=None, cov=None):
@@ -410,7 +451,8 @@ def tt_normalize_adjoint(x: Sequence[DeviceTT], p_bar: Sequence[DeviceTT], log_m
 
 
 def tt_round_adjoint(a: Sequence[DeviceTT], y: Sequence[DeviceTT], y_bar: Sequence[DeviceTT],
-                     a_bar: Sequence[DeviceTT]):
+                     a_bar: Sequence[DeviceTT], tape=None):
+    """tape: None, or the RoundTapeStruct list tt_round filled for this rounding."""
     B = len(a)
     aa, yy = _arr([t.struct() for t in a]), _arr([t.struct() for t in y])
     nbytes = LIB.tt_round_adjoint_workspace(B, aa, yy)
@@ -418,7 +460,8 @@ def tt_round_adjoint(a: Sequence[DeviceTT], y: Sequence[DeviceTT], y_bar: Sequen
         _check(ERR_ARG, "tt_round_adjoint_workspace")
     ws = _ws(nbytes)
     _check(LIB.tt_round_adjoint(B, aa, yy, _arr([t.struct() for t in y_bar]), _arr([t.struct() for t in a_bar]),
-                                ws.data_ptr(), ws.numel(), _stream()), "tt_round_adjoint")
+                                _arr(list(tape)) if tape is not None else None, ws.data_ptr(), ws.numel(),
+                                _stream()), "tt_round_adjoint")
 
 
 def tt_prior(grids: Sequence[Grid], m0: np.ndarray, p0_diag: np.ndarray, out: Sequence[DeviceTT]):

@@ -1032,10 +1032,35 @@ struct FusedLaunch {
   int mode = 0;  // 0 direct, 1 FFT
 };
 
+// Record of the right-to-left sweep for the rounding adjoint (FP64 path,
+// double-double Gram planes): at step k the Gram of the right part at bond k
+// (plane 0, high words) and its pivoted Cholesky factor, both compacted to
+// leading dimension r_k, the factor's columns beyond its rank zeroed.  A
+// bond 1 folded with core 0 is not recorded.  One workgroup per filter.
+__global__ void __launch_bounds__(256) round_tape_kernel(const DevTT* __restrict__ din,
+                                                         const RoundScratch* __restrict__ drs, int k,
+                                                         const tt_round_tape* __restrict__ tapes) {
+  const int f = blockIdx.x;
+  const DevTT& X = din[f];
+  const RoundScratch& s = drs[f];
+  const tt_round_tape& t = tapes[f];
+  if (k == 1 && merge_bond1(X, s)) {
+    if (threadIdx.x == 0) t.valid[1] = 0;
+    return;
+  }
+  const int R = s.ri[k], rank = s.rq[k], gc = s.gcap;
+  for (int e = threadIdx.x; e < R * R; e += blockDim.x) {
+    const int i = e / R, j = e - (e / R) * R;
+    t.g[k][e] = s.gram[2LL * ((long long)i * gc + j)];
+    t.f[k][e] = j < rank ? s.lfac[(long long)i * gc + j] : 0.0;
+  }
+  if (threadIdx.x == 0) t.valid[k] = 1;
+}
+
 template <typename T, typename Acc>
 static tt_status round_launch(const RoundShape& sh, const RoundBufs& rb, double eps, int max_rank,
                               hipStream_t st, const FusedLaunch* fl = nullptr, const int* forced = nullptr,
-                              long long fstride = 0) {
+                              long long fstride = 0, const tt_round_tape* dtape = nullptr) {
   const int B = sh.B, d = sh.d;
   const bool f64 = sizeof(T) == 8;
   const double tau2_rl = f64 ? 1e-30 : 1e-14;
@@ -1073,6 +1098,10 @@ static tt_status round_launch(const RoundShape& sh, const RoundBufs& rb, double 
     const int mcap = (k == 1) ? std::min(sh.rin[1], std::max(sh.n[0], 1)) : sh.rin[k];
     TT_TRY((launch_gram<T, Acc>(FRlGram<T>{c}, B, mcap, (long long)sh.n[k] * sh.rq[k + 1], sh.splits, st)));
     TT_TRY((launch_pchol<Acc>(FRlPchol{c}, B, sh.gcap, st)));
+    if (dtape) {
+      hipLaunchKernelGGL(round_tape_kernel, dim3(B), dim3(256), 0, st, rb.din, rb.drs, k, dtape);
+      TTG_LAUNCH_CHECK("round_tape_kernel");
+    }
     TT_TRY((launch_trsm<T, T>(FRlTrsm<T>{c}, B, (long long)sh.n[k] * sh.rq[k + 1], sh.rq[k], st)));
   }
   c.k = 0;
@@ -1211,7 +1240,53 @@ size_t tt_round_workspace(int32_t batch, const tt_train* t_in, const tt_train* t
   std::vector<DevTT> a, b;
   std::vector<RoundScratch> r;
   if (round_plan(batch, t_in, t_out, ar, sh, rb, a, b, r) != TT_OK) return 0;
+  ar.take<tt_round_tape>(batch);  // the record table of tt_round_taped
   return ar.used + 256;
+}
+
+tt_status tt_round_taped(int32_t batch, const tt_train* t_in, const tt_train* t_out, double eps, int32_t max_rank,
+                         const tt_round_tape* tape, void* ws, size_t ws_bytes, void* stream) {
+  if (!t_in || !t_out || !ws || !tape) {
+    set_error("tt_round_taped: null argument");
+    return TT_ERR_ARG;
+  }
+  if (!(eps >= 0.0) || max_rank < 1) {
+    set_error("tt_round_taped: need eps >= 0 and max_rank >= 1");
+    return TT_ERR_ARG;
+  }
+  for (int b = 0; b < batch; ++b) {
+    if (t_in[b].dtype != TT_F64 || t_out[b].dtype != TT_F64) {
+      set_error("tt_round_taped: FP64 trains only");
+      return TT_ERR_ARG;
+    }
+    if (!tape[b].valid) {
+      set_error("tt_round_taped: null valid array (filter %d)", b);
+      return TT_ERR_ARG;
+    }
+    for (int j = 1; j < t_in[b].d; ++j)
+      if (!tape[b].g[j] || !tape[b].f[j]) {
+        set_error("tt_round_taped: null record buffer (filter %d, bond %d)", b, j);
+        return TT_ERR_ARG;
+      }
+  }
+  Arena ar(ws, ws_bytes);
+  RoundShape sh;
+  RoundBufs rb;
+  std::vector<DevTT> vin, vout;
+  std::vector<RoundScratch> vrs;
+  TT_TRY(round_plan(batch, t_in, t_out, ar, sh, rb, vin, vout, vrs));
+  tt_round_tape* dtape = ar.take<tt_round_tape>(batch);
+  if (!ar.fits()) {
+    set_error("tt_round_taped: workspace too small (%zu < %zu)", ws_bytes, ar.used);
+    return TT_ERR_WORKSPACE;
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  TT_TRY(upload(rb.din, vin, st));
+  TT_TRY(upload(rb.dout, vout, st));
+  TT_TRY(upload(rb.drs, vrs, st));
+  std::vector<tt_round_tape> vt(tape, tape + batch);
+  TT_TRY(upload(dtape, vt, st));
+  return round_launch<double, AccDD>(sh, rb, eps, max_rank, st, nullptr, nullptr, 0, dtape);
 }
 
 tt_status tt_round(int32_t batch, const tt_train* t_in, const tt_train* t_out, double eps, int32_t max_rank,
@@ -1254,6 +1329,7 @@ namespace ttg {
 #define RADJ_PLANES 4
 struct RadjCore {  // per filter and core k (0-based)
   double *G, *T, *W, *U, *c, *N, *lfac, *lwork, *gdd, *M, *jw, *sig, *usv, *Ud, *Fm, *Gbar, *D, *YBt, *vs, *js;
+  double* fac;  // F_k used in the products: lfac, or the forward's recorded factor
   int* flag;
   int* piv;
   int* prank;
@@ -1280,6 +1356,7 @@ static void radj_layout(Arena& ar, RadjFilter& F) {
     C.G = ar.take<double>(Rk1 * Rk1);
     C.Gbar = ar.take<double>(Rk1 * Rk1);
     C.lfac = ar.take<double>(Rk1 * Rk1);
+    C.fac = C.lfac;
     C.lwork = ar.take<double>(2 * Rk1 * Rk1);
     C.piv = ar.take<int>(Rk1);
     C.prank = ar.take<int>(1);
@@ -1497,7 +1574,8 @@ size_t tt_round_adjoint_workspace(int32_t batch, const tt_train* a, const tt_tra
 }
 
 tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, const tt_train* y_bar,
-                           const tt_train* a_bar, void* ws, size_t ws_bytes, void* stream) {
+                           const tt_train* a_bar, const tt_round_tape* tape, void* ws, size_t ws_bytes,
+                           void* stream) {
   if (batch < 1 || !a || !y || !y_bar || !a_bar || !ws) {
     set_error("tt_round_adjoint: bad arguments");
     return TT_ERR_ARG;
@@ -1534,7 +1612,19 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
     HIP_TRY(hipMemcpyAsync(&hr[(size_t)(3 * b + 2) * (d + 1)], y_bar[b].ranks, sizeof(int) * (d + 1),
                            hipMemcpyDeviceToHost, st), "ranks");
   }
+  // bonds recorded by the forward (tt_round_taped)
+  std::vector<int> hv(tape ? (size_t)batch * (d + 1) : 0, 0);
+  if (tape)
+    for (int b = 0; b < batch; ++b) {
+      if (!tape[b].valid) {
+        set_error("tt_round_adjoint: tape without a valid array (filter %d)", b);
+        return TT_ERR_ARG;
+      }
+      HIP_TRY(hipMemcpyAsync(&hv[(size_t)b * (d + 1)], tape[b].valid, sizeof(int) * (d + 1), hipMemcpyDeviceToHost,
+                             st), "tape flags");
+    }
   HIP_TRY(hipStreamSynchronize(st), "ranks sync");
+  auto taped = [&](int b, int j) { return tape && j >= 1 && j < d && hv[(size_t)b * (d + 1) + j] == 1; };
   std::vector<RadjFilter> F(batch);
   Arena ar(ws, ws_bytes);
   RadjRun R;
@@ -1581,6 +1671,19 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
   for (int b = 0; b < batch; ++b)
     for (const tt_train* t : {&a[b], &y[b], &y_bar[b], &a_bar[b]})
       R.regions.push_back({reinterpret_cast<const double*>(t->cores), (long long)elems_of(t->d, t->n, t->cap)});
+  for (int b = 0; b < batch; ++b)
+    for (int j = 1; j < d; ++j)
+      if (taped(b, j)) {
+        if (!tape[b].g[j] || !tape[b].f[j]) {
+          set_error("tt_round_adjoint: null record buffer (filter %d, bond %d)", b, j);
+          return TT_ERR_ARG;
+        }
+        const long long c2 = (long long)a[b].cap[j] * a[b].cap[j];
+        R.regions.push_back({tape[b].g[j], c2});
+        R.regions.push_back({tape[b].f[j], c2});
+        F[b].c[j - 1].G = tape[b].g[j];    // G of bond j, leading dimension r_j
+        F[b].c[j - 1].fac = tape[b].f[j];  // its factor
+      }
   auto check_scalar_jobs = [&](int kind) -> tt_status {
     for (const auto& j : R.e) {
       if (kind == 0) {  // radj_scalar_kernel
@@ -1638,7 +1741,8 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
     for (int b = 0; b < batch; ++b) {
       RadjFilter& f = F[b];
       const int R0 = f.Ra[k], R1 = f.Ra[k + 1], n = f.n[k];
-      R.mm(R0 * n, R1, R1, acore(b, k), R1, 1, f.c[k].lfac, R1, 1, f.Tg, R1, 1.0, 0.0);
+      const bool rec = taped(b, k);  // G_{k-1} and F_{k-1} recorded by the forward
+      if (!rec) R.mm(R0 * n, R1, R1, acore(b, k), R1, 1, f.c[k].fac, R1, 1, f.Tg, R1, 1.0, 0.0);
       GramArgs ga;
       memset(&ga, 0, sizeof(ga));
       ga.M = R0;
@@ -1649,6 +1753,7 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
       ga.out = f.c[k].gdd;
       ga.gcap = R0;
       ga.splits = RADJ_PLANES;
+      if (rec) ga.M = 0;
       gj.push_back(ga);
       TT_TRY(R.check(R.inside(f.c[k].gdd, 2LL * RADJ_PLANES * R0 * R0 - 1) &&
                          R.inside(f.Tg, (long long)R0 * n * R1 - 1),
@@ -1665,6 +1770,7 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
       pa.rmax = R0;
       pa.tau2 = RADJ_PCHOL_TAU2;
       if (k == 1 && f.wide0) pa.M = 0;  // F_0 is not needed: M_0's SVD comes from S_0
+      if (rec) pa.M = 0;
       pj.push_back(pa);
       mcap = std::max(mcap, R0);
       tcap = std::max(tcap, (long long)n * R1);
@@ -1677,7 +1783,7 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
     for (int b = 0; b < batch; ++b) {
       RadjFilter& f = F[b];
       const int R0 = f.Ra[k];
-      R.ej(EJ_DDHI, (long long)R0 * R0, f.c[k].gdd, nullptr, f.c[k - 1].G, nullptr, nullptr);
+      if (!taped(b, k)) R.ej(EJ_DDHI, (long long)R0 * R0, f.c[k].gdd, nullptr, f.c[k - 1].G, nullptr, nullptr);
     }
     TT_TRY(R.elem());
   }
@@ -1722,7 +1828,7 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
         R.mm(f.n[0], (int)T, f.Ra[1], acore(b, 0), f.Ra[1], 1, f.Tg, T, 1, f.Mw, T, 1.0, 0.0);
         continue;
       }
-      R.mm(p, R1, R1, f.c[k].N, R1, 1, f.c[k].lfac, R1, 1, f.c[k].M, R1, 1.0, 0.0);
+      R.mm(p, R1, R1, f.c[k].N, R1, 1, f.c[k].fac, R1, 1, f.c[k].M, R1, 1.0, 0.0);
     }
     TT_TRY(R.gemm());
     // The SVD of M_k from a double-double Gram, its pivoted Cholesky factor C
@@ -3171,7 +3277,8 @@ tt_status tt_likelihood_adjoint(int32_t batch, const tt_meas* meas, const tt_tra
   if (nr > 0) {
     hipLaunchKernelGGL(lik_adj_pack_kernel, dim3(batch), dim3(256), 0, st, dj);
     TTG_LAUNCH_CHECK("lik_adj_pack_kernel");
-    TT_TRY(tt_round_adjoint(nr, pl.a.data(), pl.y.data(), pl.ybar.data(), pl.abar.data(), rws, rbytes, stream));
+    TT_TRY(tt_round_adjoint(nr, pl.a.data(), pl.y.data(), pl.ybar.data(), pl.abar.data(), nullptr, rws, rbytes,
+                            stream));
   }
   hipLaunchKernelGGL(lik_adj_unpack_kernel, dim3(batch), dim3(256), 0, st, dj);
   TTG_LAUNCH_CHECK("lik_adj_unpack_kernel");

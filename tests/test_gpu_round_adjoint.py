@@ -44,7 +44,7 @@ CASES_D3 = [([6, 7, 5], [8, 9], 3, 0.6)]
 CASES_R1 = [([40, 6, 5, 4], [9, 1, 1], 8, 0.6)]
 
 
-def run_case(B, cases, seed):
+def run_case(B, cases, seed, taped=False):
     import torch
     rng = np.random.default_rng(seed)
     A, Y, YB, AB, host = [], [], [], [], []
@@ -58,8 +58,9 @@ def run_case(B, cases, seed):
         A.append(ta)
         Y.append(ty)
         host.append((a, n, cap))
+    tape = B.RoundTape(A) if taped else None
     for i, (a, n, cap) in enumerate(host):
-        B.tt_round([A[i]], [Y[i]], 0.0, cap)
+        B.tt_round([A[i]], [Y[i]], 0.0, cap, tape=tape.select([i]) if taped else None)
     torch.cuda.synchronize()
     outs = []
     for i, (a, n, cap) in enumerate(host):
@@ -74,9 +75,37 @@ def run_case(B, cases, seed):
         YB.append(tyb)
         AB.append(B.DeviceTT(n, A[i].cap, B.F64))
         outs.append((a, [1] + [g.shape[2] for g in ycores], t, sbar))
-    B.tt_round_adjoint(A, Y, YB, AB)
+    B.tt_round_adjoint(A, Y, YB, AB, tape=tape.structs if taped else None)
     torch.cuda.synchronize()
+    if taped:
+        outs = [o + (tape.valid[i].cpu().numpy(),) for i, o in enumerate(outs)]
     return outs, AB
+
+
+@pytest.mark.parametrize("cases", [CASES, CASES_D3, CASES_R1], ids=["d4_batch2", "d3", "rank_one_bonds"])
+def test_round_adjoint_with_forward_record(B, cases):
+    """The adjoint fed the forward rounding's recorded right Grams and
+    factors equals the one that recomputes them (same recursion, same
+    thresholds), and the oracle's reverse mode."""
+    print(f"round adjoint with record: {len(cases)} filter(s), d={len(cases[0][0])}", flush=True)
+    outs0, AB0 = run_case(B, cases, 21)
+    outs1, AB1 = run_case(B, cases, 21, taped=True)
+    for (a, ranks, t, sbar, valid), o0, t0, t1 in zip(outs1, outs0, AB0, AB1):
+        d = len(a)
+        # every bond is recorded except bond 1 when the first core is folded in
+        want = [0] + [1] * (d - 1) + [0]
+        if a[0].shape[2] > a[0].shape[1]:
+            want[1] = 0
+        assert list(valid) == want, valid
+        ab0, _, _ = t0.fetch()
+        ab1, ls, st = t1.fetch()
+        assert st == 0 and ls == sbar
+        y_or, tape = oa.round_fwd(a, ranks)
+        ab_or = oa.round_vjp(tape, full_vjp(y_or, t))
+        for k in range(d):
+            sc = np.abs(ab_or[k]).max()
+            assert np.abs(ab1[k] - ab0[k]).max() / sc < 1e-10, k
+            assert np.abs(ab1[k] - ab_or[k]).max() / sc < 1e-8, k
 
 
 @pytest.mark.parametrize("cases", [CASES, CASES_D3, CASES_R1], ids=["d4_batch2", "d3", "rank_one_bonds"])
