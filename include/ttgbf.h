@@ -199,14 +199,18 @@ tt_status tt_round(int32_t batch, const tt_train* t_in, const tt_train* t_out, d
  * needs: for every bond j = 1..d-1 the Gram matrix G of the right part of
  * the input at bond j (r_j x r_j, r_j = the input's rank there, row-major,
  * leading dimension r_j) and its pivoted Cholesky factor F (G ~ F F^T, rows
- * in the original order, r_j x r_j, columns beyond its rank zero).  Bond 1
- * is not recorded when it is wider than n[0] (the sweep folds core 0 into
- * it); valid[j] says which bonds were.  Caller-owned device buffers:
- * g[j], f[j] of in->cap[j]^2 doubles, valid of d+1 int32. */
+ * in the original order, r_j x r_j, columns beyond its rank zero), with
+ * valid[j] = 1 and rank[j] = the factor's rank.  When bond 1 is wider than
+ * n[0] the sweep folds core 0 into it; bond 1 then records the Gram of the
+ * folded n[0] x (n[1] r_2) unfolding (n[0] x n[0], leading dimension n[0])
+ * and its factor, with valid[1] = 2 (not recorded, valid[1] = 0, when n[0]
+ * exceeds 256).  Caller-owned device buffers: g[j], f[j] of in->cap[j]^2
+ * doubles, valid and rank of d+1 int32 each. */
 typedef struct {
   double* g[TT_MAXD];
   double* f[TT_MAXD];
   int32_t* valid;
+  int32_t* rank;
 } tt_round_tape;
 tt_status tt_round_taped(int32_t batch, const tt_train* t_in, const tt_train* t_out, double eps,
                          int32_t max_rank, const tt_round_tape* tape, void* ws, size_t ws_bytes, void* stream);

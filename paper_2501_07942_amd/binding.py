@@ -46,7 +46,8 @@ class FilterSpec(C.Structure):
 
 
 class RoundTapeStruct(C.Structure):
-    _fields_ = [("g", C.c_void_p * MAXD), ("f", C.c_void_p * MAXD), ("valid", C.c_void_p)]
+    _fields_ = [("g", C.c_void_p * MAXD), ("f", C.c_void_p * MAXD), ("valid", C.c_void_p),
+                ("rank", C.c_void_p)]
 
 
 class TTError(RuntimeError):
@@ -360,8 +361,8 @@ def tt_update(grids: Sequence[Grid], meas: Sequence[Meas], z, p_pred: Sequence[D
 class RoundTape:
     """Record of an FP64 rounding's right-to-left sweep, one per filter: for
     each bond j the right-part Gram and its pivoted Cholesky factor
-    (cap[j] x cap[j] doubles each, cap of the rounding's input) and a flag
-    per bond, all in one device allocation."""
+    (cap[j] x cap[j] doubles each, cap of the rounding's input), a flag and
+    the factor's rank per bond, all in device memory."""
 
     def __init__(self, t_in: Sequence[DeviceTT]):
         torch = _torch()
@@ -370,6 +371,7 @@ class RoundTape:
         per = [2 * sum(sz) for sz in self.sizes]
         self.buf = torch.zeros(max(sum(per), 1), dtype=torch.float64, device="cuda")
         self.valid = torch.zeros((len(t_in), self.d + 1), dtype=torch.int32, device="cuda")
+        self.rank = torch.zeros((len(t_in), self.d + 1), dtype=torch.int32, device="cuda")
         self.structs = []
         off = 0
         for b, sz in enumerate(self.sizes):
@@ -380,6 +382,7 @@ class RoundTape:
                 st.f[j] = self.buf.data_ptr() + 8 * off
                 off += sz[j]
             st.valid = self.valid.data_ptr() + 4 * b * (self.d + 1)
+            st.rank = self.rank.data_ptr() + 4 * b * (self.d + 1)
             self.structs.append(st)
 
     def select(self, idx: Sequence[int]):

@@ -1032,11 +1032,13 @@ struct FusedLaunch {
   int mode = 0;  // 0 direct, 1 FFT
 };
 
-// Record of the right-to-left sweep for the rounding adjoint (FP64 path,
-// double-double Gram planes): at step k the Gram of the right part at bond k
-// (plane 0, high words) and its pivoted Cholesky factor, both compacted to
-// leading dimension r_k, the factor's columns beyond its rank zeroed.  A
-// bond 1 folded with core 0 is not recorded.  One workgroup per filter.
+// Record of the right-to-left sweep for the rounding adjoint, written after
+// the pivoted Cholesky of bond k: the Gram (FP64 high words) and the FP64
+// factor, rows in the original order, compacted to leading dimension r_k
+// (n_0 for a bond 1 folded with core 0: the Gram of the folded unfolding),
+// the factor's columns beyond its rank zeroed.  The folded bond is recorded
+// only when its pivoted Cholesky could reach full rank (n_0 <= rqcap[1]), as
+// the adjoint's own does.  One workgroup per filter.
 __global__ void __launch_bounds__(256) round_tape_kernel(const DevTT* __restrict__ din,
                                                          const RoundScratch* __restrict__ drs, int k,
                                                          const tt_round_tape* __restrict__ tapes) {
@@ -1044,17 +1046,21 @@ __global__ void __launch_bounds__(256) round_tape_kernel(const DevTT* __restrict
   const DevTT& X = din[f];
   const RoundScratch& s = drs[f];
   const tt_round_tape& t = tapes[f];
-  if (k == 1 && merge_bond1(X, s)) {
+  const bool mg = k == 1 && merge_bond1(X, s);
+  if (mg && X.n[0] > s.rqcap[1]) {
     if (threadIdx.x == 0) t.valid[1] = 0;
     return;
   }
-  const int R = s.ri[k], rank = s.rq[k], gc = s.gcap;
+  const int R = mg ? X.n[0] : s.ri[k], rank = s.rq[k], gc = s.gcap;
   for (int e = threadIdx.x; e < R * R; e += blockDim.x) {
     const int i = e / R, j = e - (e / R) * R;
     t.g[k][e] = s.gram[2LL * ((long long)i * gc + j)];
     t.f[k][e] = j < rank ? s.lfac[(long long)i * gc + j] : 0.0;
   }
-  if (threadIdx.x == 0) t.valid[k] = 1;
+  if (threadIdx.x == 0) {
+    t.valid[k] = mg ? 2 : 1;
+    t.rank[k] = rank;
+  }
 }
 
 template <typename T, typename Acc>
@@ -1259,8 +1265,8 @@ tt_status tt_round_taped(int32_t batch, const tt_train* t_in, const tt_train* t_
       set_error("tt_round_taped: FP64 trains only");
       return TT_ERR_ARG;
     }
-    if (!tape[b].valid) {
-      set_error("tt_round_taped: null valid array (filter %d)", b);
+    if (!tape[b].valid || !tape[b].rank) {
+      set_error("tt_round_taped: null valid or rank array (filter %d)", b);
       return TT_ERR_ARG;
     }
     for (int j = 1; j < t_in[b].d; ++j)
@@ -1616,8 +1622,8 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
   std::vector<int> hv(tape ? (size_t)batch * (d + 1) : 0, 0);
   if (tape)
     for (int b = 0; b < batch; ++b) {
-      if (!tape[b].valid) {
-        set_error("tt_round_adjoint: tape without a valid array (filter %d)", b);
+      if (!tape[b].valid || !tape[b].rank) {
+        set_error("tt_round_adjoint: tape without a valid or rank array (filter %d)", b);
         return TT_ERR_ARG;
       }
       HIP_TRY(hipMemcpyAsync(&hv[(size_t)b * (d + 1)], tape[b].valid, sizeof(int) * (d + 1), hipMemcpyDeviceToHost,
@@ -1671,6 +1677,17 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
   for (int b = 0; b < batch; ++b)
     for (const tt_train* t : {&a[b], &y[b], &y_bar[b], &a_bar[b]})
       R.regions.push_back({reinterpret_cast<const double*>(t->cores), (long long)elems_of(t->d, t->n, t->cap)});
+  // the folded first bond: the Gram of n0 x (n1 r2) unfolding A_0 Z_1 and its factor
+  auto taped_s0 = [&](int b) { return tape && F[b].wide0 && hv[(size_t)b * (d + 1) + 1] == 2; };
+  for (int b = 0; b < batch; ++b)
+    if (taped_s0(b)) {
+      if (!tape[b].g[1] || !tape[b].f[1]) {
+        set_error("tt_round_adjoint: null record buffer (filter %d, bond 1)", b);
+        return TT_ERR_ARG;
+      }
+      const long long c2 = (long long)a[b].cap[1] * a[b].cap[1];
+      R.regions.push_back({tape[b].f[1], c2});
+    }
   for (int b = 0; b < batch; ++b)
     for (int j = 1; j < d; ++j)
       if (taped(b, j)) {
@@ -1742,7 +1759,10 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
       RadjFilter& f = F[b];
       const int R0 = f.Ra[k], R1 = f.Ra[k + 1], n = f.n[k];
       const bool rec = taped(b, k);  // G_{k-1} and F_{k-1} recorded by the forward
-      if (!rec) R.mm(R0 * n, R1, R1, acore(b, k), R1, 1, f.c[k].fac, R1, 1, f.Tg, R1, 1.0, 0.0);
+      // a folded first bond needs neither G_0 nor F_0 (phase 4 applies G_0
+      // through A_1 and G_1); Z_1 only feeds S_0 when that was not recorded
+      const bool w1 = k == 1 && f.wide0;
+      if (!rec && !(w1 && taped_s0(b))) R.mm(R0 * n, R1, R1, acore(b, k), R1, 1, f.c[k].fac, R1, 1, f.Tg, R1, 1.0, 0.0);
       GramArgs ga;
       memset(&ga, 0, sizeof(ga));
       ga.M = R0;
@@ -1753,7 +1773,7 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
       ga.out = f.c[k].gdd;
       ga.gcap = R0;
       ga.splits = RADJ_PLANES;
-      if (rec) ga.M = 0;
+      if (rec || w1) ga.M = 0;
       gj.push_back(ga);
       TT_TRY(R.check(R.inside(f.c[k].gdd, 2LL * RADJ_PLANES * R0 * R0 - 1) &&
                          R.inside(f.Tg, (long long)R0 * n * R1 - 1),
@@ -1783,7 +1803,8 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
     for (int b = 0; b < batch; ++b) {
       RadjFilter& f = F[b];
       const int R0 = f.Ra[k];
-      if (!taped(b, k)) R.ej(EJ_DDHI, (long long)R0 * R0, f.c[k].gdd, nullptr, f.c[k - 1].G, nullptr, nullptr);
+      if (!taped(b, k) && !(k == 1 && f.wide0))
+        R.ej(EJ_DDHI, (long long)R0 * R0, f.c[k].gdd, nullptr, f.c[k - 1].G, nullptr, nullptr);
     }
     TT_TRY(R.elem());
   }
@@ -1825,7 +1846,7 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
       if (k == 0 && f.wide0) {
         // M'_0 = A_0 Z_1 (Z_1 = A_1 x_3 F_1 is left in Tg by the right sweep)
         const long long T = (long long)f.n[1] * f.Ra[2];
-        R.mm(f.n[0], (int)T, f.Ra[1], acore(b, 0), f.Ra[1], 1, f.Tg, T, 1, f.Mw, T, 1.0, 0.0);
+        if (!taped_s0(b)) R.mm(f.n[0], (int)T, f.Ra[1], acore(b, 0), f.Ra[1], 1, f.Tg, T, 1, f.Mw, T, 1.0, 0.0);
         continue;
       }
       R.mm(p, R1, R1, f.c[k].N, R1, 1, f.c[k].fac, R1, 1, f.c[k].M, R1, 1.0, 0.0);
@@ -1891,6 +1912,12 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
         ja.usv = jv;
         ja.gcap = gm;
         rj[b].ncols = rk;
+        if (wide && taped_s0(b)) {  // S_0's factor and rank from the forward's record
+          ga.M = 0;
+          pa.M = 0;
+          R.ej(EJ_COPY, (long long)gm * gm, tape[b].f[1], nullptr, lf, nullptr, nullptr);
+          rj[b].ncols = tape[b].rank + 1;
+        }
         TT_TRY(R.check((wide ? (f.ry[0] == 1 && R1 > f.n[0]) : p >= 1) &&
                            R.inside(ga.x, wide ? (long long)gm * T - 1 : (long long)p * R1 - 1) &&
                            R.inside(gout, 2LL * RADJ_PLANES * gm * gm - 1) && R.inside(lw, 2LL * gm * gm - 1) &&
@@ -2125,14 +2152,41 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
     for (int b = 0; b < batch; ++b) {  // WG = W_{k+1} G_k, XtN = X^T N
       RadjFilter& f = F[b];
       const int R1 = f.Ra[k + 1], r1 = f.ry[k + 1], p = f.ry[k] * f.n[k];
-      R.mm(r1, R1, R1, f.c[k + 1].W, R1, 1, f.c[k].G, R1, 1, f.WG, R1, 1.0, 0.0);
+      if (!(k == 0 && f.wide0)) R.mm(r1, R1, R1, f.c[k + 1].W, R1, 1, f.c[k].G, R1, 1, f.WG, R1, 1.0, 0.0);
       R.mm(r1, R1, p, f.Ubar, 1, r1, f.c[k].N, R1, 1, f.XtN, R1, 1.0, 0.0);
     }
     TT_TRY(R.gemm());
+    if (k == 0) {
+      // folded first bond: V G_0 = sum_i (V A_1(:,i,:)) G_1 A_1(:,i,:)^T for
+      // V = W_1 and X^T N (G_0 itself is never formed)
+      for (int v = 0; v < 2; ++v) {
+        for (int b = 0; b < batch; ++b) {
+          RadjFilter& f = F[b];
+          if (!f.wide0) continue;
+          const int R1 = f.Ra[1], r1 = f.ry[1], T = f.n[1] * f.Ra[2];
+          R.mm(r1, T, R1, v == 0 ? f.c[1].W : f.XtN, R1, 1, acore(b, 1), T, 1, f.Tg, T, 1.0, 0.0);
+        }
+        TT_TRY(R.gemm());
+        for (int b = 0; b < batch; ++b) {
+          RadjFilter& f = F[b];
+          if (!f.wide0) continue;
+          const int r1 = f.ry[1], R2 = f.Ra[2];
+          R.mm(r1 * f.n[1], R2, R2, f.Tg, R2, 1, f.c[1].G, R2, 1, f.T2, R2, 1.0, 0.0);
+        }
+        TT_TRY(R.gemm());
+        for (int b = 0; b < batch; ++b) {
+          RadjFilter& f = F[b];
+          if (!f.wide0) continue;
+          const int R1 = f.Ra[1], r1 = f.ry[1], T = f.n[1] * f.Ra[2];
+          R.mm(r1, R1, T, f.T2, T, 1, acore(b, 1), 1, T, v == 0 ? f.WG : f.XtNG, R1, 1.0, 0.0);
+        }
+        TT_TRY(R.gemm());
+      }
+    }
     for (int b = 0; b < batch; ++b) {  // XtNG = XtN G, Nbar += X WG, Gbar_k += XtN^T W_{k+1}
       RadjFilter& f = F[b];
       const int R1 = f.Ra[k + 1], r1 = f.ry[k + 1], p = f.ry[k] * f.n[k];
-      R.mm(r1, R1, R1, f.XtN, R1, 1, f.c[k].G, R1, 1, f.XtNG, R1, 1.0, 0.0);
+      if (!(k == 0 && f.wide0)) R.mm(r1, R1, R1, f.XtN, R1, 1, f.c[k].G, R1, 1, f.XtNG, R1, 1.0, 0.0);
       R.mm(p, R1, r1, f.Ubar, r1, 1, f.WG, R1, 1, f.Nbar, R1, 1.0, 1.0);
       R.mm(R1, R1, r1, f.XtN, 1, R1, f.c[k + 1].W, R1, 1, f.c[k].Gbar, R1, 1.0, 1.0);
     }
