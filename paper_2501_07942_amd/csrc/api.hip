@@ -2206,7 +2206,12 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
     TT_TRY(R.gemm());
     cur0 = !cur0;
   }
-  // phase 5: the Gram recursion backwards, from the left
+  // phase 5: the Gram recursion backwards, from the left.  Every Gram is
+  // symmetric, so only the symmetric part of its adjoint reaches the input
+  // (the next step reads Gbar_k through Gbar_k + Gbar_k^T, and sum_i
+  // A_i^T S A_i is antisymmetric for antisymmetric S): Gbar_k takes
+  // (1/2) A_k^T (Gbar_{k-1} + Gbar_{k-1}^T) A_k, which reuses the product
+  // of the A_k adjoint instead of forming Gbar_{k-1} A_k
   for (int k = 1; k < d; ++k) {
     for (int b = 0; b < batch; ++b) {
       RadjFilter& f = F[b];
@@ -2218,15 +2223,13 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
       RadjFilter& f = F[b];
       const int R0 = f.Ra[k], R1 = f.Ra[k + 1], n = f.n[k];
       R.mm(R0, n * R1, R0, f.Gs, R0, 1, acore(b, k), (long long)n * R1, 1, f.Tg, (long long)n * R1, 1.0, 0.0);
-      R.mm(R0, n * R1, R0, f.c[k - 1].Gbar, R0, 1, acore(b, k), (long long)n * R1, 1, f.T2, (long long)n * R1, 1.0,
-           0.0);
     }
     TT_TRY(R.gemm());
     for (int b = 0; b < batch; ++b) {
       RadjFilter& f = F[b];
       const int R0 = f.Ra[k], R1 = f.Ra[k + 1], n = f.n[k];
       R.mm(R0 * n, R1, R1, f.Tg, R1, 1, f.c[k].G, R1, 1, abcore(b, k), R1, 1.0, 1.0);
-      R.mm(R1, R1, R0 * n, acore(b, k), 1, R1, f.T2, R1, 1, f.c[k].Gbar, R1, 1.0, 1.0);
+      if (k < d - 1) R.mm(R1, R1, R0 * n, acore(b, k), 1, R1, f.Tg, R1, 1, f.c[k].Gbar, R1, 0.5, 1.0);
     }
     TT_TRY(R.gemm());
   }
