@@ -4,6 +4,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <type_traits>
 #include <vector>
@@ -183,6 +184,51 @@ static tt_status upload(T* dst, const std::vector<T>& src, hipStream_t s) {
           "descriptor upload");
   // the host vectors die when the call returns: wait for the copy
   HIP_TRY(hipStreamSynchronize(s), "descriptor upload sync");
+  return TT_OK;
+}
+
+// Page-locked staging for the job tables of the calls that synchronise their
+// stream before returning (the rounding adjoint): a table is copied into the
+// staging area and uploaded without waiting; the area rewinds only after a
+// synchronisation of the stream, so no pending copy reads rewritten memory.
+// One call holds it at a time (the guard's lock).
+struct PinnedStage {
+  std::mutex mu;
+  char* buf = nullptr;
+  size_t cap = 0, off = 0;
+};
+static PinnedStage g_stage;
+
+struct StageGuard {
+  std::lock_guard<std::mutex> lock;
+  hipStream_t st;
+  explicit StageGuard(hipStream_t s) : lock(g_stage.mu), st(s) { g_stage.off = 0; }
+  ~StageGuard() {
+    if (g_stage.off) (void)hipStreamSynchronize(st);  // early error return: drain before the next holder
+    g_stage.off = 0;
+  }
+};
+
+template <typename T>
+static tt_status stage_upload(T* dst, const std::vector<T>& src, hipStream_t s) {
+  if (src.empty()) return TT_OK;
+  const size_t bytes = src.size() * sizeof(T), need = (bytes + 255) & ~size_t(255);
+  if (g_stage.off + need > g_stage.cap) {
+    HIP_TRY(hipStreamSynchronize(s), "staging sync");
+    g_stage.off = 0;
+    if (need > g_stage.cap) {
+      if (g_stage.buf) HIP_TRY(hipHostFree(g_stage.buf), "staging free");
+      g_stage.buf = nullptr;
+      g_stage.cap = 0;
+      const size_t c = std::max(need, size_t(8) << 20);
+      HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&g_stage.buf), c, hipHostMallocDefault), "staging alloc");
+      g_stage.cap = c;
+    }
+  }
+  char* p = g_stage.buf + g_stage.off;
+  memcpy(p, src.data(), bytes);
+  g_stage.off += need;
+  HIP_TRY(hipMemcpyAsync(dst, p, bytes, hipMemcpyHostToDevice, s), "descriptor upload");
   return TT_OK;
 }
 
@@ -1349,6 +1395,7 @@ struct RadjFilter {
   // from S_0 = M'_0 M'_0^T, M'_0 = A_0 x_3 Z_1 (n[0] x n[1] Ra[2])
   bool wide0;
   double *Mw, *sdd, *slw, *slf;
+  double* Yw;  // V A_1 and (V A_1) x_3 G_1 for V = W_1, X^T N (four blocks of r_1 n_1 R_2)
   int *spiv, *srank;
 };
 
@@ -1403,6 +1450,7 @@ static void radj_layout(Arena& ar, RadjFilter& F) {
     F.slf = ar.take<double>(n0 * n0);
     F.spiv = ar.take<int>(n0);
     F.srank = ar.take<int>(1);
+    F.Yw = ar.take<double>(4LL * F.ry[1] * F.n[1] * F.Ra[2]);
   }
   const int rl = F.ry[d - 1], nl = F.n[d - 1];
   F.L = ar.take<double>((long long)rl * nl);
@@ -1437,6 +1485,10 @@ struct RadjRun {
   int jcap;
   std::vector<GJob> g;
   std::vector<EJob> e;
+  template <typename T>
+  tt_status up(T* dst, const std::vector<T>& v) const {
+    return stage_upload(dst, v, st);
+  }
   // device regions a job may touch (workspace, the trains' core buffers):
   // every job's extent is checked on the host before anything is launched
   std::vector<std::pair<const double*, long long>> regions;
@@ -1469,7 +1521,7 @@ struct RadjRun {
       j.tile0 = tiles;
       tiles += std::max(1, (j.M + 63) / 64) * j.tn;
     }
-    TT_TRY(upload(dg, g, st));
+    TT_TRY(up(dg, g));
     hipLaunchKernelGGL(gjob_mfma_kernel, dim3(tiles), dim3(256), 0, st, dg, (int)g.size());
     TTG_LAUNCH_CHECK("gjob_mfma_kernel");
     g.clear();
@@ -1493,7 +1545,7 @@ struct RadjRun {
     }
     long long mx = 1;
     for (auto& j : e) mx = std::max(mx, j.cnt);
-    TT_TRY(upload(de, e, st));
+    TT_TRY(up(de, e));
     hipLaunchKernelGGL(ejob_kernel, dim3(std::min(cdiv(mx, 256), 1024), (int)e.size()), dim3(256), 0, st, de);
     TTG_LAUNCH_CHECK("ejob_kernel");
     e.clear();
@@ -1608,6 +1660,7 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
       }
   }
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  StageGuard stage(st);  // job tables go through page-locked staging (the call ends synchronised)
   // the ranks, once, to the host
   std::vector<int> hr((size_t)batch * 3 * (d + 1));
   for (int b = 0; b < batch; ++b) {
@@ -1727,6 +1780,7 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
     return reinterpret_cast<const double*>(y_bar[b].cores) + make_dev(y_bar[b]).off[k];
   };
   auto abcore = [&](int b, int k) { return reinterpret_cast<double*>(a_bar[b].cores) + make_dev(a_bar[b]).off[k]; };
+  auto ywblk = [&](const RadjFilter& f, int v) { return f.Yw + (long long)v * f.ry[1] * f.n[1] * f.Ra[2]; };
   // zero accumulators and factors; G_{d-1} = 1, W_0 = 1
   for (int b = 0; b < batch; ++b) {
     RadjFilter& f = F[b];
@@ -1796,9 +1850,9 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
       tcap = std::max(tcap, (long long)n * R1);
     }
     TT_TRY(R.gemm());
-    TT_TRY(upload(R.dga, gj, st));
+    TT_TRY(R.up(R.dga, gj));
     TT_TRY((launch_gram<double, AccDD>(FAdjGram{R.dga}, batch, mcap, tcap, RADJ_PLANES, st)));
-    TT_TRY(upload(R.dp, pj, st));
+    TT_TRY(R.up(R.dp, pj));
     TT_TRY((launch_pchol<AccDD, FAdjPchol>(FAdjPchol{R.dp}, batch, mcap, st)));
     for (int b = 0; b < batch; ++b) {
       RadjFilter& f = F[b];
@@ -1818,7 +1872,7 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
   }
   if (!R.e.empty()) {
     TT_TRY(check_scalar_jobs(0));
-    TT_TRY(upload(R.de, R.e, st));
+    TT_TRY(R.up(R.de, R.e));
     hipLaunchKernelGGL(radj_scalar_kernel, dim3((int)R.e.size()), dim3(256), 0, st, R.de);
     TTG_LAUNCH_CHECK("radj_scalar_kernel");
     R.e.clear();
@@ -1928,11 +1982,11 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
         tcap = std::max(tcap, T);
       }
       TT_TRY(R.elem());
-      TT_TRY(upload(R.dga, gj, st));
+      TT_TRY(R.up(R.dga, gj));
       TT_TRY((launch_gram<double, AccDD>(FAdjGram{R.dga}, batch, mcap, tcap, RADJ_PLANES, st)));
-      TT_TRY(upload(R.dp, pj, st));
+      TT_TRY(R.up(R.dp, pj));
       TT_TRY((launch_pchol<AccDD, FAdjPchol>(FAdjPchol{R.dp}, batch, mcap, st)));
-      TT_TRY(upload(R.drj, rj, st));
+      TT_TRY(R.up(R.drj, rj));
       TT_TRY(launch_jacobi(FAdjJacobiRk{R.drj}, batch, st));
       for (int b = 0; b < batch; ++b) {  // sigma_c u_c = M_k v_c (tall cores)
         RadjFilter& f = F[b];
@@ -1992,14 +2046,14 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
                        "refinement"));
         dmax = std::max(dmax, (long long)p * R1);
       }
-      TT_TRY(upload(R.drf, rf, st));
+      TT_TRY(R.up(R.drf, rf));
       hipLaunchKernelGGL(radj_refine_flag_kernel, dim3(cdiv(batch, 64)), dim3(64), 0, st, R.drf, batch);
       TTG_LAUNCH_CHECK("radj_refine_flag_kernel");
-      TT_TRY(upload(R.ddj, dj, st));
+      TT_TRY(R.up(R.ddj, dj));
       hipLaunchKernelGGL(radj_ddprod_kernel, dim3((int)std::min<long long>(cdiv(dmax, 256), 4096), batch), dim3(256),
                          0, st, R.ddj);
       TTG_LAUNCH_CHECK("radj_ddprod_kernel");
-      TT_TRY(upload(R.dcj, cj, st));
+      TT_TRY(R.up(R.dcj, cj));
       TT_TRY(launch_jacobi(FAdjJacobiIf{R.dcj}, batch, st));
       hipLaunchKernelGGL(radj_refine_tail_kernel, dim3(batch), dim3(64), 0, st, R.drf, batch);
       TTG_LAUNCH_CHECK("radj_refine_tail_kernel");
@@ -2028,7 +2082,7 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
                      "adopt"));
       aj.push_back(a1);
     }
-    TT_TRY(upload(R.daj, aj, st));
+    TT_TRY(R.up(R.daj, aj));
     hipLaunchKernelGGL(radj_adopt_kernel, dim3(batch), dim3(256), 0, st, R.daj);
     TTG_LAUNCH_CHECK("radj_adopt_kernel");
     for (int b = 0; b < batch; ++b) {
@@ -2057,7 +2111,7 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
     R.ej(1, (long long)f.ry[d - 1] * f.n[d - 1], f.Lbar, f.L, nullptr, f.kappa, nullptr);
   }
   TT_TRY(check_scalar_jobs(0));
-  TT_TRY(upload(R.de, R.e, st));
+  TT_TRY(R.up(R.de, R.e));
   hipLaunchKernelGGL(radj_scalar_kernel, dim3((int)R.e.size()), dim3(256), 0, st, R.de);
   TTG_LAUNCH_CHECK("radj_scalar_kernel");
   R.e.clear();
@@ -2083,7 +2137,7 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
       }
     }
     TT_TRY(check_scalar_jobs(1));
-    TT_TRY(upload(R.de, R.e, st));
+    TT_TRY(R.up(R.de, R.e));
     hipLaunchKernelGGL(radj_eigprep_kernel, dim3((int)R.e.size()), dim3(256), 0, st, R.de);
     TTG_LAUNCH_CHECK("radj_eigprep_kernel");
     R.e.clear();
@@ -2137,7 +2191,7 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
       long long mx = 1;
       for (auto& j : R.e) mx = std::max(mx, (long long)j.p * j.r + (long long)(j.R - j.r) * j.r);
       TT_TRY(check_scalar_jobs(2));
-      TT_TRY(upload(R.de, R.e, st));
+      TT_TRY(R.up(R.de, R.e));
       hipLaunchKernelGGL(radj_eigapply_kernel, dim3(std::min(cdiv(mx, 256), 1024), (int)R.e.size()), dim3(256), 0, st,
                          R.de);
       TTG_LAUNCH_CHECK("radj_eigapply_kernel");
@@ -2158,30 +2212,32 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
     TT_TRY(R.gemm());
     if (k == 0) {
       // folded first bond: V G_0 = sum_i (V A_1(:,i,:)) G_1 A_1(:,i,:)^T for
-      // V = W_1 and X^T N (G_0 itself is never formed)
-      for (int v = 0; v < 2; ++v) {
-        for (int b = 0; b < batch; ++b) {
-          RadjFilter& f = F[b];
-          if (!f.wide0) continue;
-          const int R1 = f.Ra[1], r1 = f.ry[1], T = f.n[1] * f.Ra[2];
-          R.mm(r1, T, R1, v == 0 ? f.c[1].W : f.XtN, R1, 1, acore(b, 1), T, 1, f.Tg, T, 1.0, 0.0);
-        }
-        TT_TRY(R.gemm());
-        for (int b = 0; b < batch; ++b) {
-          RadjFilter& f = F[b];
-          if (!f.wide0) continue;
-          const int r1 = f.ry[1], R2 = f.Ra[2];
-          R.mm(r1 * f.n[1], R2, R2, f.Tg, R2, 1, f.c[1].G, R2, 1, f.T2, R2, 1.0, 0.0);
-        }
-        TT_TRY(R.gemm());
-        for (int b = 0; b < batch; ++b) {
-          RadjFilter& f = F[b];
-          if (!f.wide0) continue;
-          const int R1 = f.Ra[1], r1 = f.ry[1], T = f.n[1] * f.Ra[2];
-          R.mm(r1, R1, T, f.T2, T, 1, acore(b, 1), 1, T, v == 0 ? f.WG : f.XtNG, R1, 1.0, 0.0);
-        }
-        TT_TRY(R.gemm());
+      // V = W_1 and X^T N (G_0 itself is never formed); Y_V = V A_1 and
+      // Y'_V = Y_V x_3 G_1 stay in Yw for the Gram recursion below
+      for (int b = 0; b < batch; ++b) {
+        RadjFilter& f = F[b];
+        if (!f.wide0) continue;
+        const int R1 = f.Ra[1], r1 = f.ry[1], T = f.n[1] * f.Ra[2];
+        for (int v = 0; v < 2; ++v)
+          R.mm(r1, T, R1, v == 0 ? f.c[1].W : f.XtN, R1, 1, acore(b, 1), T, 1, ywblk(f, v), T, 1.0, 0.0);
       }
+      TT_TRY(R.gemm());
+      for (int b = 0; b < batch; ++b) {
+        RadjFilter& f = F[b];
+        if (!f.wide0) continue;
+        const int r1 = f.ry[1], R2 = f.Ra[2];
+        for (int v = 0; v < 2; ++v)
+          R.mm(r1 * f.n[1], R2, R2, ywblk(f, v), R2, 1, f.c[1].G, R2, 1, ywblk(f, 2 + v), R2, 1.0, 0.0);
+      }
+      TT_TRY(R.gemm());
+      for (int b = 0; b < batch; ++b) {
+        RadjFilter& f = F[b];
+        if (!f.wide0) continue;
+        const int R1 = f.Ra[1], r1 = f.ry[1], T = f.n[1] * f.Ra[2];
+        for (int v = 0; v < 2; ++v)
+          R.mm(r1, R1, T, ywblk(f, 2 + v), T, 1, acore(b, 1), 1, T, v == 0 ? f.WG : f.XtNG, R1, 1.0, 0.0);
+      }
+      TT_TRY(R.gemm());
     }
     for (int b = 0; b < batch; ++b) {  // XtNG = XtN G, Nbar += X WG, Gbar_k += XtN^T W_{k+1}
       RadjFilter& f = F[b];
@@ -2221,17 +2277,36 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
     TT_TRY(R.elem());
     for (int b = 0; b < batch; ++b) {
       RadjFilter& f = F[b];
+      if (k == 1 && f.wide0) continue;
       const int R0 = f.Ra[k], R1 = f.Ra[k + 1], n = f.n[k];
       R.mm(R0, n * R1, R0, f.Gs, R0, 1, acore(b, k), (long long)n * R1, 1, f.Tg, (long long)n * R1, 1.0, 0.0);
     }
     TT_TRY(R.gemm());
     for (int b = 0; b < batch; ++b) {
       RadjFilter& f = F[b];
+      if (k == 1 && f.wide0) continue;
       const int R0 = f.Ra[k], R1 = f.Ra[k + 1], n = f.n[k];
       R.mm(R0 * n, R1, R1, f.Tg, R1, 1, f.c[k].G, R1, 1, abcore(b, k), R1, 1.0, 1.0);
       if (k < d - 1) R.mm(R1, R1, R0 * n, acore(b, k), 1, R1, f.Tg, R1, 1, f.c[k].Gbar, R1, 0.5, 1.0);
     }
     TT_TRY(R.gemm());
+    if (k == 1) {
+      // folded first bond: Gbar_0 = (X^T N)^T W_1 comes from the backward
+      // sweep alone, so Gs A_1 = (X^T N)^T Y_W + W_1^T Y_X has rank 2 r_1:
+      //   Abar_1 += (X^T N)^T Y'_W + W_1^T Y'_X,
+      //   Gbar_1 += (Y_X^T Y_W + Y_W^T Y_X) / 2  (summed over the mode index)
+      for (int v = 0; v < 2; ++v) {
+        for (int b = 0; b < batch; ++b) {
+          RadjFilter& f = F[b];
+          if (!f.wide0) continue;
+          const int R1 = f.Ra[1], r1 = f.ry[1], R2 = f.Ra[2], T = f.n[1] * R2;
+          R.mm(R1, T, r1, v == 0 ? f.XtN : f.c[1].W, 1, R1, ywblk(f, 2 + v), T, 1, abcore(b, 1), T, 1.0, 1.0);
+          if (d > 2)
+            R.mm(R2, R2, r1 * f.n[1], ywblk(f, 1 - v), 1, R2, ywblk(f, v), R2, 1, f.c[1].Gbar, R2, 0.5, 1.0);
+        }
+        TT_TRY(R.gemm());
+      }
+    }
   }
   // the adjoint train: ranks of a, log-scale adjoint of y_bar, status 0
   for (int b = 0; b < batch; ++b) {
