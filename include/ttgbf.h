@@ -195,20 +195,29 @@ tt_status tt_round(int32_t batch, const tt_train* t_in, const tt_train* t_out, d
                    int32_t max_rank, void* ws, size_t ws_bytes, void* stream);
 
 /* tt_round_taped -- tt_round (FP64 trains only) that also records, per
- * filter, the products of its right-to-left sweep that tt_round_adjoint
- * needs: for every bond j = 1..d-1 the Gram matrix G of the right part of
- * the input at bond j (r_j x r_j, r_j = the input's rank there, row-major,
- * leading dimension r_j) and its pivoted Cholesky factor F (G ~ F F^T, rows
- * in the original order, r_j x r_j, columns beyond its rank zero), with
- * valid[j] = 1 and rank[j] = the factor's rank.  When bond 1 is wider than
- * n[0] the sweep folds core 0 into it; bond 1 then records the Gram of the
- * folded n[0] x (n[1] r_2) unfolding (n[0] x n[0], leading dimension n[0])
- * and its factor, with valid[1] = 2 (not recorded, valid[1] = 0, when n[0]
- * exceeds 256).  Caller-owned device buffers: g[j], f[j] of in->cap[j]^2
- * doubles, valid and rank of d+1 int32 each. */
+ * filter, the products of its two sweeps that tt_round_adjoint would
+ * otherwise recompute.  valid[j] is a bit set per bond j = 1..d-1:
+ *   1: g[j] = the Gram matrix G of the right part of the input at bond j
+ *      (r_j x r_j, r_j = the input's rank there, row-major, leading
+ *      dimension r_j) and f[j] = its pivoted Cholesky factor F (G ~ F F^T,
+ *      rows in the original order, r_j x r_j, columns beyond its rank zero),
+ *      rank[j] = the factor's rank;
+ *   2: bond 1 wider than n[0], which the sweep folds with core 0: g[1], f[1]
+ *      = the Gram of the folded n[0] x (n[1] r_2) unfolding (n[0] x n[0],
+ *      leading dimension n[0]) and its factor, rank[1] its rank (not
+ *      recorded when n[0] exceeds 256);
+ *   4: v[j], s[j] = the singular vectors and values of the left-to-right
+ *      step that ends at bond j (the unfolding of output core j-1 in the
+ *      coordinates of F at bond j): vector c in column c of v[j] (r_j x r_j,
+ *      column-major, leading dimension r_j), s[j] descending, zeros beyond
+ *      the rank.
+ * Caller-owned device buffers: g[j], f[j], v[j] of in->cap[j]^2 doubles,
+ * s[j] of in->cap[j] doubles, valid and rank of d+1 int32 each. */
 typedef struct {
   double* g[TT_MAXD];
   double* f[TT_MAXD];
+  double* v[TT_MAXD];
+  double* s[TT_MAXD];
   int32_t* valid;
   int32_t* rank;
 } tt_round_tape;
@@ -288,8 +297,9 @@ size_t tt_normalize_moments_workspace(int32_t batch, const tt_train* t);
  * (rounding noise there exceeds their signal) and discarded ones below 1e-9
  * count as null space.  The call reads the ranks to the host once and is
  * synchronous (it returns after the work is done).  tape (nullable): the
- * record tt_round_taped wrote for this rounding; its Grams and factors are
- * used instead of being recomputed.  Workspace:
+ * record tt_round_taped wrote for this rounding, read only; its Grams,
+ * factors and the singular vectors of the tall unfoldings whose right
+ * factor it holds are used instead of being recomputed.  Workspace:
  * tt_round_adjoint_workspace(batch, a, y) bytes (from the capacities).
  * Errors: TT_ERR_ARG (null, non-FP64, a recorded bond whose buffers are
  * null), TT_ERR_SHAPE (modes, capacities or ranks inconsistent, y_bar ranks

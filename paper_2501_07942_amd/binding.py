@@ -46,8 +46,8 @@ class FilterSpec(C.Structure):
 
 
 class RoundTapeStruct(C.Structure):
-    _fields_ = [("g", C.c_void_p * MAXD), ("f", C.c_void_p * MAXD), ("valid", C.c_void_p),
-                ("rank", C.c_void_p)]
+    _fields_ = [("g", C.c_void_p * MAXD), ("f", C.c_void_p * MAXD), ("v", C.c_void_p * MAXD),
+                ("s", C.c_void_p * MAXD), ("valid", C.c_void_p), ("rank", C.c_void_p)]
 
 
 class TTError(RuntimeError):
@@ -359,16 +359,18 @@ def tt_update(grids: Sequence[Grid], meas: Sequence[Meas], z, p_pred: Sequence[D
 
 
 class RoundTape:
-    """Record of an FP64 rounding's right-to-left sweep, one per filter: for
-    each bond j the right-part Gram and its pivoted Cholesky factor
-    (cap[j] x cap[j] doubles each, cap of the rounding's input), a flag and
-    the factor's rank per bond, all in device memory."""
+    """Record of an FP64 rounding's sweeps, one per filter: for each bond j
+    the right-part Gram and its pivoted Cholesky factor, the singular vectors
+    of the left-to-right step ending there (cap[j] x cap[j] doubles each, cap
+    of the rounding's input) and its singular values, a flag set and the
+    factor's rank per bond, all in device memory."""
 
     def __init__(self, t_in: Sequence[DeviceTT]):
         torch = _torch()
         self.d = t_in[0].d
         self.sizes = [[t.cap[j] * t.cap[j] if 1 <= j < self.d else 0 for j in range(self.d)] for t in t_in]
-        per = [2 * sum(sz) for sz in self.sizes]
+        caps = [[t.cap[j] if 1 <= j < self.d else 0 for j in range(self.d)] for t in t_in]
+        per = [3 * sum(sz) + sum(c) for sz, c in zip(self.sizes, caps)]
         self.buf = torch.zeros(max(sum(per), 1), dtype=torch.float64, device="cuda")
         self.valid = torch.zeros((len(t_in), self.d + 1), dtype=torch.int32, device="cuda")
         self.rank = torch.zeros((len(t_in), self.d + 1), dtype=torch.int32, device="cuda")
@@ -381,6 +383,10 @@ class RoundTape:
                 off += sz[j]
                 st.f[j] = self.buf.data_ptr() + 8 * off
                 off += sz[j]
+                st.v[j] = self.buf.data_ptr() + 8 * off
+                off += sz[j]
+                st.s[j] = self.buf.data_ptr() + 8 * off
+                off += caps[b][j]
             st.valid = self.valid.data_ptr() + 4 * b * (self.d + 1)
             st.rank = self.rank.data_ptr() + 4 * b * (self.d + 1)
             self.structs.append(st)

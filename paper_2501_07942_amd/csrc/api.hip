@@ -1109,6 +1109,26 @@ __global__ void __launch_bounds__(256) round_tape_kernel(const DevTT* __restrict
   }
 }
 
+// Record of the left-to-right step k: the Jacobi singular vectors (column c
+// = vector c, rq[k+1] components in the coordinates of the bond-(k+1)
+// factor) and values of B_k, compacted to r_{k+1} x r_{k+1} column-major,
+// zeros beyond the pivoted-Cholesky rank.  One workgroup per filter.
+__global__ void __launch_bounds__(256) round_tape_svd_kernel(const RoundScratch* __restrict__ drs, int k,
+                                                             const tt_round_tape* __restrict__ tapes) {
+  const int f = blockIdx.x;
+  const RoundScratch& s = drs[f];
+  const tt_round_tape& t = tapes[f];
+  const int R = s.ri[k + 1], rq = s.rq[k + 1], nc = s.misc[0], gc = s.gcap;
+  double* v = t.v[k + 1];
+  double* sg = t.s[k + 1];
+  for (int e = threadIdx.x; e < R * R; e += blockDim.x) {
+    const int c = e / R, j = e - (e / R) * R;
+    v[e] = (c < nc && j < rq) ? s.usv[(long long)c * gc + j] : 0.0;
+  }
+  for (int c = threadIdx.x; c < R; c += blockDim.x) sg[c] = c < nc ? s.sigma[c] : 0.0;
+  if (threadIdx.x == 0) t.valid[k + 1] |= 4;
+}
+
 template <typename T, typename Acc>
 static tt_status round_launch(const RoundShape& sh, const RoundBufs& rb, double eps, int max_rank,
                               hipStream_t st, const FusedLaunch* fl = nullptr, const int* forced = nullptr,
@@ -1174,6 +1194,10 @@ static tt_status round_launch(const RoundShape& sh, const RoundBufs& rb, double 
     TT_TRY((launch_gram<T, Acc>(FLrGram<T>{c}, B, sh.rq[k + 1], (long long)sh.rout[k] * sh.n[k], sh.splits, st)));
     TT_TRY((launch_pchol<Acc>(FLrPchol{c}, B, sh.gcap, st)));
     TT_TRY((launch_jacobi(FLrJacobi{c}, B, st)));
+    if (dtape) {
+      hipLaunchKernelGGL(round_tape_svd_kernel, dim3(B), dim3(256), 0, st, rb.drs, k, dtape);
+      TTG_LAUNCH_CHECK("round_tape_svd_kernel");
+    }
     hipLaunchKernelGGL(round_select_kernel, dim3(B), dim3(256), 0, st, rb.dout, rb.drs, k, max_rank, forced, fstride);
     TTG_LAUNCH_CHECK("round_select_kernel");
     TT_TRY((launch_tall<T>(FLrU<T>{c}, B, (long long)sh.rout[k] * sh.n[k], sh.rout[k + 1], st)));
@@ -1316,7 +1340,7 @@ tt_status tt_round_taped(int32_t batch, const tt_train* t_in, const tt_train* t_
       return TT_ERR_ARG;
     }
     for (int j = 1; j < t_in[b].d; ++j)
-      if (!tape[b].g[j] || !tape[b].f[j]) {
+      if (!tape[b].g[j] || !tape[b].f[j] || !tape[b].v[j] || !tape[b].s[j]) {
         set_error("tt_round_taped: null record buffer (filter %d, bond %d)", b, j);
         return TT_ERR_ARG;
       }
@@ -1683,7 +1707,7 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
                              st), "tape flags");
     }
   HIP_TRY(hipStreamSynchronize(st), "ranks sync");
-  auto taped = [&](int b, int j) { return tape && j >= 1 && j < d && hv[(size_t)b * (d + 1) + j] == 1; };
+  auto taped = [&](int b, int j) { return tape && j >= 1 && j < d && (hv[(size_t)b * (d + 1) + j] & 1); };
   std::vector<RadjFilter> F(batch);
   Arena ar(ws, ws_bytes);
   RadjRun R;
@@ -1731,7 +1755,12 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
     for (const tt_train* t : {&a[b], &y[b], &y_bar[b], &a_bar[b]})
       R.regions.push_back({reinterpret_cast<const double*>(t->cores), (long long)elems_of(t->d, t->n, t->cap)});
   // the folded first bond: the Gram of n0 x (n1 r2) unfolding A_0 Z_1 and its factor
-  auto taped_s0 = [&](int b) { return tape && F[b].wide0 && hv[(size_t)b * (d + 1) + 1] == 2; };
+  auto taped_s0 = [&](int b) { return tape && F[b].wide0 && (hv[(size_t)b * (d + 1) + 1] & 2); };
+  // the SVD of a tall unfolding M_k = N_k F_k, recorded by the forward in the
+  // coordinates of F_k (so only where F_k itself is the recorded factor)
+  auto taped_svd = [&](int b, int k) {
+    return k + 1 < d && !(k == 0 && F[b].wide0) && taped(b, k + 1) && (hv[(size_t)b * (d + 1) + k + 1] & 4);
+  };
   for (int b = 0; b < batch; ++b)
     if (taped_s0(b)) {
       if (!tape[b].g[1] || !tape[b].f[1]) {
@@ -1751,6 +1780,14 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
         const long long c2 = (long long)a[b].cap[j] * a[b].cap[j];
         R.regions.push_back({tape[b].g[j], c2});
         R.regions.push_back({tape[b].f[j], c2});
+        if (taped_svd(b, j - 1)) {
+          if (!tape[b].v[j] || !tape[b].s[j]) {
+            set_error("tt_round_adjoint: null singular-vector record (filter %d, bond %d)", b, j);
+            return TT_ERR_ARG;
+          }
+          R.regions.push_back({tape[b].v[j], c2});
+          R.regions.push_back({tape[b].s[j], (long long)a[b].cap[j]});
+        }
         F[b].c[j - 1].G = tape[b].g[j];    // G of bond j, leading dimension r_j
         F[b].c[j - 1].fac = tape[b].f[j];  // its factor
       }
@@ -1934,8 +1971,14 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
         int* rk = wide ? f.srank : f.c[k].prank;
         double* jv = wide ? f.c[0].usv : f.c[k].vs;
         double* jwk = wide ? f.c[0].jw : f.c[k].js;
-        R.ej(EJ_FILL, R1, nullptr, nullptr, f.c[k].sig, nullptr, nullptr);
-        R.ej(EJ_FILL, (long long)gm * gm, nullptr, nullptr, jv, nullptr, nullptr);
+        const bool rsvd = taped_svd(b, k);
+        if (rsvd) {  // V and sigma from the forward's record; no Gram, factor or Jacobi here
+          R.ej(EJ_COPY, R1, tape[b].s[k + 1], nullptr, f.c[k].sig, nullptr, nullptr);
+          R.ej(EJ_COPY, (long long)gm * gm, tape[b].v[k + 1], nullptr, jv, nullptr, nullptr);
+        } else {
+          R.ej(EJ_FILL, R1, nullptr, nullptr, f.c[k].sig, nullptr, nullptr);
+          R.ej(EJ_FILL, (long long)gm * gm, nullptr, nullptr, jv, nullptr, nullptr);
+        }
         GramArgs& ga = gj[b];
         ga.M = gm;
         ga.T = (int)T;
@@ -1966,6 +2009,11 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
         ja.usv = jv;
         ja.gcap = gm;
         rj[b].ncols = rk;
+        if (rsvd) {
+          ga.M = 0;
+          pa.M = 0;
+          rj[b].ja.rows = 0;
+        }
         if (wide && taped_s0(b)) {  // S_0's factor and rank from the forward's record
           ga.M = 0;
           pa.M = 0;

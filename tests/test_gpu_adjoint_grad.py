@@ -38,11 +38,17 @@ def test_adjoint_gradient_binding_cap_batch(mods):
     ll, g, _ = AG.loglik_grad_adjoint(specs, zs)
     ll_fd, g_fd, _ = G.loglik_grad(specs, zs)
     # checkpoint segments of two steps, and a checkpoint per step without
-    # the tape: the same computations, bit for bit
+    # the tape: the same computations, bit for bit; with the tape the
+    # rounding adjoint takes the forward's singular vectors of the same
+    # unfoldings, equal up to rounding (amplified by the small kept singular
+    # values, well below this case's distance to the differences)
     ll2, g2, _ = AG.loglik_grad_adjoint(specs, zs, ckpt_every=2)
-    assert np.array_equal(ll2, ll) and np.array_equal(g2, g)
     ll1, g1, _ = AG.loglik_grad_adjoint(specs, zs, tape=False)
-    assert np.array_equal(ll1, ll) and np.array_equal(g1, g)
+    assert np.array_equal(ll1, ll2) and np.array_equal(g1, g2)
+    assert np.array_equal(ll1, ll)
+    for b in range(2):
+        print(f"  filter {b}: with vs without the tape {rel(g[b], g1[b]):.1e}", flush=True)
+        assert rel(g[b], g1[b]) < 1e-6
     # the parameter tangents by forward instead of central differences
     _, g_f, _ = AG.loglik_grad_adjoint(specs, zs, scheme="forward")
     with pytest.raises(ValueError):

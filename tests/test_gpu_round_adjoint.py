@@ -92,10 +92,11 @@ def test_round_adjoint_with_forward_record(B, cases):
     outs1, AB1 = run_case(B, cases, 21, taped=True)
     for (a, ranks, t, sbar, valid), o0, t0, t1 in zip(outs1, outs0, AB0, AB1):
         d = len(a)
-        # every bond is recorded; bond 1 folded with the first core as such
-        want = [0] + [1] * (d - 1) + [0]
+        # every bond's Gram and factor is recorded (bond 1 folded with the
+        # first core as such), and every left-to-right SVD
+        want = [0] + [1 | 4] * (d - 1) + [0]
         if a[0].shape[2] > a[0].shape[1]:
-            want[1] = 2
+            want[1] = 2 | 4
         assert list(valid) == want, valid
         ab0, _, _ = t0.fetch()
         ab1, ls, st = t1.fetch()
