@@ -301,21 +301,35 @@ __global__ void __launch_bounds__(256) sum_env_kernel(const DevTT* __restrict__ 
   }
   __syncthreads();
   __shared__ double part[256];
-  // left[k+1](b) = sum over rows (a, i) of left[k](a) X_k(a, i, b): groups of
-  // nb threads own the columns, the groups split the rows, an LDS pass sums
-  // the groups (blockDim.x = 256)
+  // left[k+1](b) = sum_a left[k](a) sum_i X_k(a, i, b): groups of nb threads
+  // own the columns, the groups split the mode index i, an LDS pass sums the
+  // groups (blockDim.x = 256); the mode sum of one row a is unrolled so that
+  // several loads are in flight per thread
   for (int k = 0; k < d; ++k) {
     const int r0 = X.ranks[k], r1 = X.ranks[k + 1], n = X.n[k];
     const T* xc = core_ptr<T>(X, k);
     const double* lk = left + (long long)k * rcap;
     const int nb = min(r1, 256), G = 256 / nb;
     const int g = threadIdx.x / nb, tb = threadIdx.x - (threadIdx.x / nb) * nb;
-    const long long rows = (long long)r0 * n;
     for (int b0 = 0; b0 < r1; b0 += nb) {
       const int b = b0 + tb;
       double acc = 0.0;
-      if (g < G && b < r1)
-        for (long long row = g; row < rows; row += G) acc += lk[row / n] * bulk_to_double(xc[row * r1 + b]);
+      if (g < G && b < r1) {
+        const long long rs = (long long)G * r1;  // stride between this thread's i
+        for (int a = 0; a < r0; ++a) {
+          const T* xp = xc + ((long long)a * n + g) * r1 + b;
+          double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+          int i = g;
+          for (; i + 3 * G < n; i += 4 * G, xp += 4 * rs) {
+            s0 += bulk_to_double(xp[0]);
+            s1 += bulk_to_double(xp[rs]);
+            s2 += bulk_to_double(xp[2 * rs]);
+            s3 += bulk_to_double(xp[3 * rs]);
+          }
+          for (; i < n; i += G, xp += rs) s0 += bulk_to_double(xp[0]);
+          acc += lk[a] * ((s0 + s1) + (s2 + s3));
+        }
+      }
       part[threadIdx.x] = acc;
       __syncthreads();
       if (threadIdx.x < nb && b < r1) {
@@ -327,19 +341,60 @@ __global__ void __launch_bounds__(256) sum_env_kernel(const DevTT* __restrict__ 
     }
   }
   // right[k](a) = sum over (i, b) of X_k(a, i, b) right[k+1](b): one
-  // wavefront per row a, lanes over the contiguous (i, b) block
+  // wavefront per row a over the contiguous (i, b) block (the column of a
+  // lane advances by 64 modulo r1), or the whole workgroup per row when the
+  // core has fewer rows than wavefronts
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
   for (int k = d - 1; k >= 0; --k) {
     const int r0 = X.ranks[k], r1 = X.ranks[k + 1], n = X.n[k];
     const T* xc = core_ptr<T>(X, k);
     const double* rk1 = right + (long long)(k + 1) * rcap;
-    const long long len = (long long)n * r1;
-    for (int a = wv; a < r0; a += nw) {
-      const T* row = xc + (long long)a * len;
-      double acc = 0.0;
-      for (long long e = lane; e < len; e += 64) acc += bulk_to_double(row[e]) * rk1[e % r1];
-      for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-      if (lane == 0) right[(long long)k * rcap + a] = acc;
+    const int len = n * r1;
+    if (r0 >= nw) {
+      const int b0 = lane % r1, step = 64 % r1;
+      for (int a = wv; a < r0; a += nw) {
+        const T* row = xc + (long long)a * len;
+        double s0 = 0.0, s1 = 0.0;
+        int e = lane, b = b0;
+        for (; e + 64 < len; e += 128) {
+          const double x0 = bulk_to_double(row[e]), x1 = bulk_to_double(row[e + 64]);
+          int b1 = b + step;
+          if (b1 >= r1) b1 -= r1;
+          s0 += x0 * rk1[b];
+          s1 += x1 * rk1[b1];
+          b = b1 + step;
+          if (b >= r1) b -= r1;
+        }
+        if (e < len) s0 += bulk_to_double(row[e]) * rk1[b];
+        double acc = s0 + s1;
+        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+        if (lane == 0) right[(long long)k * rcap + a] = acc;
+      }
+    } else {
+      const int t = threadIdx.x, b0 = t % r1, step = 256 % r1;
+      for (int a = 0; a < r0; ++a) {
+        const T* row = xc + (long long)a * len;
+        double s0 = 0.0, s1 = 0.0;
+        int e = t, b = b0;
+        for (; e + 256 < len; e += 512) {
+          const double x0 = bulk_to_double(row[e]), x1 = bulk_to_double(row[e + 256]);
+          int b1 = b + step;
+          if (b1 >= r1) b1 -= r1;
+          s0 += x0 * rk1[b];
+          s1 += x1 * rk1[b1];
+          b = b1 + step;
+          if (b >= r1) b -= r1;
+        }
+        if (e < len) s0 += bulk_to_double(row[e]) * rk1[b];
+        part[t] = s0 + s1;
+        __syncthreads();
+        for (int h = 128; h > 0; h >>= 1) {
+          if (t < h) part[t] += part[t + h];
+          __syncthreads();
+        }
+        if (t == 0) right[(long long)k * rcap + a] = part[0];
+        __syncthreads();
+      }
     }
     __syncthreads();
   }

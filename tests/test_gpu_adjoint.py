@@ -121,7 +121,9 @@ def test_hadamard_adjoint_flags_mismatched_ranks(B):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_normalize_adjoint_matches_oracle(B, prec):
+@pytest.mark.parametrize("shape", [([9, 11, 7], [4, 3]), ([6, 13, 5, 4], [300, 70, 2])],
+                         ids=["small", "wide_bonds"])
+def test_normalize_adjoint_matches_oracle(B, prec, shape):
     # downstream g(P) = <full(P), T> + w * log m for P = X / (sum(X) delta):
     # the GPU representation keeps the cores and moves the scale into the
     # log-scale; both must give the same derivative with respect to X's cores
@@ -129,8 +131,9 @@ def test_normalize_adjoint_matches_oracle(B, prec):
     import torch
     pr = B.F64 if prec == "f64" else B.F32
     rng = np.random.default_rng(10)
-    n = [9, 11, 7]
-    x = [np.abs(g) + 0.2 for g in rand_tt(rng, n, [4, 3])]
+    n, r = shape
+    caps = [1] + list(r) + [1]
+    x = [np.abs(g) + 0.2 for g in rand_tt(rng, n, r)]
     delta = 0.37
     t = rng.standard_normal(n)
     w = 0.8
@@ -146,14 +149,14 @@ def test_normalize_adjoint_matches_oracle(B, prec):
     ls_p = -math.log(s * delta)
     pbar_gpu = [g * math.exp(ls_p) for g in full_vjp(x, t)]
     sbar_p = float(np.sum(ttm.full(x) * t)) * math.exp(ls_p)
-    X = dev(B, x, [1, 4, 3, 1], pr)
-    PB = dev(B, pbar_gpu, [1, 4, 3, 1], pr, log_scale=sbar_p)
-    XB = empty_like(B, x, [1, 4, 3, 1], pr)
+    X = dev(B, x, caps, pr)
+    PB = dev(B, pbar_gpu, caps, pr, log_scale=sbar_p)
+    XB = empty_like(B, x, caps, pr)
     lmb = torch.tensor([w], dtype=torch.float64, device="cuda")
     print(f"normalize adjoint {prec}: n={n}", flush=True)
     B.tt_normalize_adjoint([X], [PB], lmb, [XB])
     torch.cuda.synchronize()
     xb, ls, st = XB.fetch()
     assert st == 0 and ls == w
-    for k in range(3):
+    for k in range(len(n)):
         assert rel(xb[k], xbar_or[k]) < (1e-12 if prec == "f64" else 1e-5), k
