@@ -1507,6 +1507,8 @@ struct RadjRun {
   CondJacobi* dcj;
   RefJob* drf;
   int jcap;
+  double* part = nullptr;  // partial products of split-K jobs
+  long long part_cap = 0;
   std::vector<GJob> g;
   std::vector<EJob> e;
   template <typename T>
@@ -1539,15 +1541,45 @@ struct RadjRun {
       TT_TRY(check(j.K == 0 || inside(j.b, (long long)(j.K - 1) * j.sbk + (long long)(j.N - 1) * j.sbn), "gemm b"));
       TT_TRY(check(inside(j.c, (long long)(j.M - 1) * j.scm + (long long)(j.N - 1) * j.scn), "gemm c"));
     }
-    int tiles = 0;
+    // long products with few output tiles split K over the partial-product
+    // area (at most 32 slices of >= 1024, while the area lasts)
+    long long avail = part_cap;
+    double* pp = part;
+    bool split = false;
+    int tiles = 0, mx = 1;
     for (auto& j : g) {
       j.tn = std::max(1, (j.N + 63) / 64);
+      j.ks = 1;
+      j.kc = j.K;
+      j.part = nullptr;
+      const int tm = std::max(1, (j.M + 63) / 64);
+      const long long mn = (long long)j.M * j.N;
+      if (j.K >= 4096 && tm * j.tn <= 16 && mn > 0) {
+        int ks = (int)std::min<long long>(std::min(32, j.K / 1024), avail / mn);
+        if (ks >= 2) {
+          const int kc = ((j.K + ks - 1) / ks + 31) / 32 * 32;
+          ks = (j.K + kc - 1) / kc;
+          j.ks = ks;
+          j.kc = kc;
+          j.part = pp;
+          pp += ks * mn;
+          avail -= ks * mn;
+          split = true;
+          mx = std::max(mx, cdiv(mn, 256));
+        }
+      }
       j.tile0 = tiles;
-      tiles += std::max(1, (j.M + 63) / 64) * j.tn;
+      tiles += tm * j.tn * j.ks;
     }
+    for (const auto& j : g)
+      if (j.ks > 1) TT_TRY(check(inside(j.part, (long long)j.ks * j.M * j.N - 1), "gemm partials"));
     TT_TRY(up(dg, g));
     hipLaunchKernelGGL(gjob_mfma_kernel, dim3(tiles), dim3(256), 0, st, dg, (int)g.size());
     TTG_LAUNCH_CHECK("gjob_mfma_kernel");
+    if (split) {
+      hipLaunchKernelGGL(gjob_reduce_kernel, dim3(std::min(mx, 1024), (int)g.size()), dim3(256), 0, st, dg);
+      TTG_LAUNCH_CHECK("gjob_reduce_kernel");
+    }
     g.clear();
     return TT_OK;
   }
@@ -1634,6 +1666,13 @@ static long long radj_bytes(const RadjFilter& proto) {
 
 extern "C" {
 
+// partial-product area of the split-K products, per filter (from the capacities)
+static long long radj_part_elems(const tt_train& a) {
+  long long rm = 1;
+  for (int k = 0; k <= a.d; ++k) rm = std::max<long long>(rm, a.cap[k]);
+  return std::min(8 * rm * rm, 1LL << 20);
+}
+
 size_t tt_round_adjoint_workspace(int32_t batch, const tt_train* a, const tt_train* y) {
   if (batch < 1 || !a || !y) return 0;
   const int dd = a[0].d;
@@ -1650,7 +1689,7 @@ size_t tt_round_adjoint_workspace(int32_t batch, const tt_train* a, const tt_tra
       F.Ra[k] = a[b].cap[k];
       F.ry[k] = y[b].cap[k];
     }
-    total += (size_t)radj_bytes(F) + 256 * 64;
+    total += (size_t)radj_bytes(F) + 256 * 64 + sizeof(double) * (size_t)radj_part_elems(a[b]);
   }
   return total;
 }
@@ -1746,6 +1785,8 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
     }
     radj_layout(ar, f);
   }
+  for (int b = 0; b < batch; ++b) R.part_cap += radj_part_elems(a[b]);
+  R.part = ar.take<double>(R.part_cap);
   if (!ar.fits()) {
     set_error("tt_round_adjoint: workspace too small (%zu < %zu)", ws_bytes, ar.used);
     return TT_ERR_WORKSPACE;

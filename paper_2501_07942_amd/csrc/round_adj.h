@@ -64,6 +64,11 @@ struct GJob {
   double alpha, beta;
   int tile0;  // first global tile of this job
   int tn;     // tiles along N
+  // split K: ks > 1 slices of kc (a multiple of 32) each write their partial
+  // product to part[s][M][N]; gjob_reduce_kernel then sums the slices in
+  // order and applies alpha and beta
+  int ks, kc;
+  double* part;
 };
 
 // The job table on the FP64 matrix cores: wavefront w of a tile owns rows
@@ -84,9 +89,12 @@ __global__ void __launch_bounds__(256) gjob_mfma_kernel(const GJob* __restrict__
       hi = mid - 1;
   }
   const GJob g = jobs[lo];
-  const int lt = t - g.tile0;
+  const int tmn = ((g.M + 63) / 64) * g.tn;  // tiles of one K slice
+  const int sl = (t - g.tile0) / tmn, lt = t - g.tile0 - sl * tmn;
   const int m0 = (lt / g.tn) * 64, n0 = (lt - (lt / g.tn) * g.tn) * 64;
   if (m0 >= g.M || n0 >= g.N) return;
+  const int kbeg = g.ks > 1 ? sl * g.kc : 0;
+  const int kend = g.ks > 1 ? min(g.K, kbeg + g.kc) : g.K;
   // K blocks of 32; the next block is fetched into registers while the
   // current one is multiplied out of the LDS
   constexpr int KB = 32;
@@ -104,14 +112,14 @@ __global__ void __launch_bounds__(256) gjob_mfma_kernel(const GJob* __restrict__
       const int e = threadIdx.x + 256 * u;
       const int mm = e >> 5, kk = e & 31;  // A: 64 rows x 32 k
       const int m = m0 + mm, k = k0 + kk;
-      ra[u] = (m < g.M && k < g.K) ? g.a[(long long)m * g.sam + (long long)k * g.sak] : 0.0;
+      ra[u] = (m < g.M && k < kend) ? g.a[(long long)m * g.sam + (long long)k * g.sak] : 0.0;
       const int kb = e >> 6, nn = e & 63;  // B: 32 k x 64 columns
       const int n = n0 + nn, k2 = k0 + kb;
-      rb[u] = (n < g.N && k2 < g.K) ? g.b[(long long)k2 * g.sbk + (long long)n * g.sbn] : 0.0;
+      rb[u] = (n < g.N && k2 < kend) ? g.b[(long long)k2 * g.sbk + (long long)n * g.sbn] : 0.0;
     }
   };
-  fetch(0);
-  for (int k0 = 0; k0 < g.K; k0 += KB) {
+  fetch(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += KB) {
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int e = threadIdx.x + 256 * u;
@@ -119,7 +127,7 @@ __global__ void __launch_bounds__(256) gjob_mfma_kernel(const GJob* __restrict__
       Bs[e >> 6][e & 63] = rb[u];
     }
     __syncthreads();
-    if (k0 + KB < g.K) fetch(k0 + KB);
+    if (k0 + KB < kend) fetch(k0 + KB);
 #pragma unroll
     for (int kk = 0; kk < KB; kk += 4) {
       const double av = As[kk + lk][16 * w + li];
@@ -135,10 +143,29 @@ __global__ void __launch_bounds__(256) gjob_mfma_kernel(const GJob* __restrict__
     for (int v = 0; v < 4; ++v) {
       const int m = m0 + 16 * w + 4 * v + lk, n = n0 + 16 * j + li;
       if (m < g.M && n < g.N) {
-        double* cp = g.c + (long long)m * g.scm + (long long)n * g.scn;
-        *cp = g.beta == 0.0 ? g.alpha * acc[j][v] : __fma_rn(g.alpha, acc[j][v], g.beta * *cp);
+        if (g.ks > 1) {
+          g.part[((long long)sl * g.M + m) * g.N + n] = acc[j][v];
+        } else {
+          double* cp = g.c + (long long)m * g.scm + (long long)n * g.scn;
+          *cp = g.beta == 0.0 ? g.alpha * acc[j][v] : __fma_rn(g.alpha, acc[j][v], g.beta * *cp);
+        }
       }
     }
+}
+
+// C = alpha * sum_s part[s] + beta * C for the split jobs of a table, the
+// slices summed in increasing order; blockIdx.y selects the job
+__global__ void __launch_bounds__(256) gjob_reduce_kernel(const GJob* __restrict__ jobs) {
+  const GJob g = jobs[blockIdx.y];
+  if (g.ks <= 1) return;
+  const long long mn = (long long)g.M * g.N;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < mn; e += (long long)gridDim.x * blockDim.x) {
+    double v = 0.0;
+    for (int sl = 0; sl < g.ks; ++sl) v += g.part[sl * mn + e];
+    const int m = (int)(e / g.N), n = (int)(e - (long long)m * g.N);
+    double* cp = g.c + (long long)m * g.scm + (long long)n * g.scn;
+    *cp = g.beta == 0.0 ? g.alpha * v : __fma_rn(g.alpha, v, g.beta * *cp);
+  }
 }
 
 // ---------------------------------------------------------------------------

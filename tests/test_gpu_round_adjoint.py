@@ -42,6 +42,8 @@ CASES = [
 CASES_D3 = [([6, 7, 5], [8, 9], 3, 0.6)]
 # a wide first bond over rank-one bonds (the update rounding of the first step)
 CASES_R1 = [([40, 6, 5, 4], [9, 1, 1], 8, 0.6)]
+# unfoldings with n r = 4096 columns: the long products split their K
+CASES_LONG = [([8, 64, 64, 6], [8, 64, 6], 5, 0.7)]
 
 
 def run_case(B, cases, seed, taped=False):
@@ -82,7 +84,8 @@ def run_case(B, cases, seed, taped=False):
     return outs, AB
 
 
-@pytest.mark.parametrize("cases", [CASES, CASES_D3, CASES_R1], ids=["d4_batch2", "d3", "rank_one_bonds"])
+@pytest.mark.parametrize("cases", [CASES, CASES_D3, CASES_R1, CASES_LONG],
+                         ids=["d4_batch2", "d3", "rank_one_bonds", "long_products"])
 def test_round_adjoint_with_forward_record(B, cases):
     """The adjoint fed the forward rounding's recorded right Grams and
     factors equals the one that recomputes them (same recursion, same
@@ -109,7 +112,8 @@ def test_round_adjoint_with_forward_record(B, cases):
             assert np.abs(ab1[k] - ab_or[k]).max() / sc < 1e-8, k
 
 
-@pytest.mark.parametrize("cases", [CASES, CASES_D3, CASES_R1], ids=["d4_batch2", "d3", "rank_one_bonds"])
+@pytest.mark.parametrize("cases", [CASES, CASES_D3, CASES_R1, CASES_LONG],
+                         ids=["d4_batch2", "d3", "rank_one_bonds", "long_products"])
 def test_round_adjoint_matches_oracle_reverse_mode(B, cases):
     print(f"round adjoint: {len(cases)} filter(s), d={len(cases[0][0])}, binding caps", flush=True)
     outs, AB = run_case(B, cases, 21)
