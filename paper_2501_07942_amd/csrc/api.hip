@@ -1,6 +1,8 @@
 // Host side of the C ABI: argument checks, workspace planning, descriptor
 // upload and the launch sequences of every entry point in ttgbf.h.
+#include <array>
 #include <cmath>
+#include <cstdlib>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -1573,6 +1575,24 @@ struct RadjRun {
     }
     for (const auto& j : g)
       if (j.ks > 1) TT_TRY(check(inside(j.part, (long long)j.ks * j.M * j.N - 1), "gemm partials"));
+    static const bool trace = getenv("TTGBF_TRACE_GEMM") != nullptr;
+    if (trace) {  // one line per launch: its distinct job shapes (M N K slices) and counts
+      std::vector<std::pair<std::array<int, 4>, int>> shapes;
+      for (const auto& j : g) {
+        const std::array<int, 4> key{j.M, j.N, j.K, j.ks};
+        bool found = false;
+        for (auto& sh : shapes)
+          if (sh.first == key) {
+            ++sh.second;
+            found = true;
+          }
+        if (!found) shapes.push_back({key, 1});
+      }
+      fprintf(stderr, "gjob tiles=%d", tiles);
+      for (const auto& sh : shapes)
+        fprintf(stderr, " [%dx%dx%d/%d]x%d", sh.first[0], sh.first[1], sh.first[2], sh.first[3], sh.second);
+      fprintf(stderr, "\n");
+    }
     TT_TRY(up(dg, g));
     hipLaunchKernelGGL(gjob_mfma_kernel, dim3(tiles), dim3(256), 0, st, dg, (int)g.size());
     TTG_LAUNCH_CHECK("gjob_mfma_kernel");
