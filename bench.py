@@ -195,6 +195,60 @@ def grad_bench(G, wl, steps, batch):
                             "ms_base": round(info["ms_base"], 1), "ms_perturbed": round(info["ms_perturbed"], 1)}}
 
 
+def einsum_bench(binding, batch=64, d=4, n=64, rt=64, rp=16, calls=10):
+    """The Einstein-summation prediction (Alg. 1, tt_predict_einsum) on a
+    batch of FP64 filters with random 2d-core transition trains (inner
+    ranks rt) and densities (inner ranks rp): ms per batched call, the HBM
+    rate of its algorithmic bytes (every transition core read once, the
+    first d-1 written once, the density read once, the output's last core
+    written); the CPU baseline leg times the oracle's Alg. 1 beside it."""
+    import torch
+    tc = [1] + [rt] * (2 * d - 1) + [1]
+    pc = [1] + [rp] * (d - 1) + [1]
+    T = binding.DeviceTT.batch([[n] * (2 * d)] * batch, [tc] * batch, binding.F64)
+    P = binding.DeviceTT.batch([[n] * d] * batch, [pc] * batch, binding.F64)
+    O = binding.DeviceTT.batch([[n] * d] * batch, [tc[:d] + [1]] * batch, binding.F64)
+    gen = torch.Generator(device="cuda").manual_seed(20250114)
+    for t, c in [(x, tc) for x in T] + [(x, pc) for x in P]:
+        t.cores.normal_(generator=gen)
+        t.ranks.copy_(torch.tensor(c, dtype=torch.int32))
+    binding.tt_predict_einsum(T, P, O)  # warm
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(calls):
+        binding.tt_predict_einsum(T, P, O)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / calls
+    core = lambda a, b: a * n * b
+    tbytes = sum(core(tc[k], tc[k + 1]) for k in range(2 * d)) + sum(core(tc[k], tc[k + 1]) for k in range(d - 1))
+    byts = 8 * batch * (tbytes + sum(core(pc[k], pc[k + 1]) for k in range(d)) + tc[d - 1] * n)
+    gbs = byts / (ms * 1e-3) / 1e9
+    return {"workload": f"random 2d-core transition trains, d={d} N={n} rank {rt}, densities rank {rp}",
+            "filters": batch, "precision": "fp64", "ms_per_call": round(ms, 4),
+            "filter_calls_per_s": round(batch / (ms * 1e-3), 1),
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(gbs / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_call": byts}}
+
+
+def einsum_cpu_baseline(d=4, n=64, rt=64, rp=16):
+    """The oracle's Alg. 1 on one filter of the einsum_bench shapes (host
+    cores; part of the CPU baseline leg)."""
+    import numpy as np
+    from oracle import tt as ttm
+    tc = [1] + [rt] * (2 * d - 1) + [1]
+    pc = [1] + [rp] * (d - 1) + [1]
+    rng = np.random.default_rng(20250114)
+    tt = [rng.standard_normal((tc[k], n, tc[k + 1])) for k in range(2 * d)]
+    pp = [rng.standard_normal((pc[k], n, pc[k + 1])) for k in range(d)]
+    t0 = time.perf_counter()
+    ttm.einsum_predict(tt, pp)
+    return {"value": round(1.0 / (time.perf_counter() - t0), 2), "unit": "filter-calls/s", "kind": "oracle",
+            "sample": f"1 filter, d={d} N={n} rank {rt}, density rank {rp}, FP64 NumPy"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -206,6 +260,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--profile-steps", type=int, default=2)
     ap.add_argument("--no-grad", action="store_true", help="skip the gradient timing")
+    ap.add_argument("--no-einsum", action="store_true", help="skip the Einstein-summation prediction timing")
     ap.add_argument("--grad-steps", type=int, default=50)
     ap.add_argument("--grad-batch", type=int, default=32)
     ap.add_argument("--grad-only", action="store_true",
@@ -297,6 +352,9 @@ def main():
         "graph_step": main_res["graph"],
         "autotune": main_res["autotune"],
     }
+    if not args.no_einsum:
+        out["einsum_predict"] = einsum_bench(binding)
+        torch.cuda.empty_cache()
     if not args.no_plain:
         plain = run_batch(None, runner, binding, wl, args.workload, 1, args.steps, args.warmup, binding.F64)
         out["fp64_plain"] = {"value": round(args.steps / (plain["ms"] / 1000.0), 3), "unit": "filter-steps/s",
@@ -311,6 +369,8 @@ def main():
         out["grad"] = grad_bench(G, wl, args.grad_steps, args.grad_batch)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl)
+        if "einsum_predict" in out:
+            out["einsum_predict"]["cpu_baseline"] = einsum_cpu_baseline()
     print(json.dumps(out), flush=True)
 
 

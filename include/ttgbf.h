@@ -158,6 +158,30 @@ tt_status tt_predict(int32_t batch, const tt_train* kernels, const tt_train* p_i
                      const tt_train* p_out, void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------
+ * tt_predict_einsum -- Chapman-Kolmogorov prediction with a general
+ * transition tensor by Einstein summation (Sec. 4.2, eqs. ttConvolutionP,
+ * ttConvolutionZ, ttConvolutionM, ttConvolutionZrecursion; Alg. 1):
+ *   P'(i_1..i_d) = sum_{j_1..j_d} T(i_1..i_d, j_1..j_d) P(j_1..j_d)
+ * with T a TT of 2d cores (cores 0..d-1 over the predicted grid, cores
+ * d..2d-1 over the current grid, mode sizes n[k] = n[d+k] = the density's)
+ * and P a d-core TT.  P' keeps T's first d-1 cores; its core d-1 is
+ * T_{d-1} x_3 Z with Z built backwards over T's second half from Z = 1:
+ *   Z'(a, c) = sum_{i, b, e} T_{d+k}(a, i, b) P_k(c, i, e) Z(b, e).
+ * Out ranks are T's ranks 0..d-1 and 1; log_scale(out) = log_scale(tpm) +
+ * log_scale(in); status(out) = status(in).  Sums in FP64 whatever the
+ * storage type; all trains of a call share one dtype and one d (2d <= 16).
+ *   tpm[b], p_in[b], p_out[b]  filter b (tpm entries may describe one TT);
+ *              p_out->cap[k] >= tpm->cap[k] for k < d.
+ * Workspace: tt_predict_einsum_workspace(batch, tpm, p_in) bytes (per
+ * filter max_k cap'_k n_k cap_{d+k+1} + 2 max_k cap_{d+k} cap'_k doubles).
+ * Errors: TT_ERR_ARG (null), TT_ERR_SHAPE (d, modes or capacities
+ * inconsistent), TT_ERR_WORKSPACE, TT_ERR_HIP.
+ * --------------------------------------------------------------------- */
+size_t tt_predict_einsum_workspace(int32_t batch, const tt_train* tpm, const tt_train* p_in);
+tt_status tt_predict_einsum(int32_t batch, const tt_train* tpm, const tt_train* p_in, const tt_train* p_out,
+                            void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------
  * tt_update -- Bayes update (Sec. 2.2 eqs. pmf_filtrace_a/b; Alg. 2 step 2):
  * builds the likelihood TT for measurement z (FP64, max-shifted, its log
  * shift added to the log-scale), forms H = L o P_pred as the Kronecker

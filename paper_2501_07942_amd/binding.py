@@ -57,6 +57,11 @@ class TTError(RuntimeError):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2501_07942_amd.build`")
+    # torch first: the library then binds to the HIP runtime torch already
+    # loaded, so both see the same devices and streams whatever the caller's
+    # import order (loaded the other way round, the library's runtime found
+    # no device)
+    import torch  # noqa: F401
     lib = C.CDLL(LIB_PATH)
     P, S, I, D = C.c_void_p, C.c_size_t, C.c_int32, C.c_double
     sigs = {
@@ -86,6 +91,8 @@ def _load():
         "tt_round_adjoint_workspace": (S, [I, P, P]),
         "tt_round_adjoint": (I, [I, P, P, P, P, P, P, S, P]),
         "tt_round_taped": (I, [I, P, P, D, I, P, P, S, P]),
+        "tt_predict_einsum_workspace": (S, [I, P, P]),
+        "tt_predict_einsum": (I, [I, P, P, P, P, S, P]),
         "tt_prior": (I, [I, P, P, P, P, P, S, P]),
         "tt_likelihood": (I, [I, P, P, P, I, P, I, P, S, P]),
         "tt_kernel_build_batch_workspace": (S, [I, P, P, P]),
@@ -121,7 +128,8 @@ EXPORTED = ("tt_train_elems", "tt_last_error", "tt_version", "tt_kernel_build_wo
             "tt_round_adjoint_workspace", "tt_round_adjoint", "tt_prior", "tt_likelihood", "tt_likelihood_dense",
             "tt_kernel_build_batch_workspace", "tt_kernel_build_batch",
             "tt_likelihood_adjoint_workspace", "tt_likelihood_adjoint", "tt_adjoint_axpy",
-            "tt_adjoint_inner", "tt_align_signs", "tt_round_taped")
+            "tt_adjoint_inner", "tt_align_signs", "tt_round_taped", "tt_predict_einsum_workspace",
+            "tt_predict_einsum")
 
 PREDICT_DIRECT, PREDICT_FFT, PREDICT_UNFUSED, PREDICT_DIRECT_VALU = 0, 1, 2, 3
 
@@ -410,6 +418,18 @@ def tt_round(t_in: Sequence[DeviceTT], t_out: Sequence[DeviceTT], eps: float, ma
         assert len(tape) == B
         _check(LIB.tt_round_taped(B, a, b, float(eps), int(max_rank), _arr(list(tape)), ws.data_ptr(), ws.numel(),
                                   _stream()), "tt_round_taped")
+
+
+def tt_predict_einsum(tpm: Sequence[DeviceTT], p_in: Sequence[DeviceTT], p_out: Sequence[DeviceTT]):
+    """P' = sum_j T(i, j) P(j) with T a 2d-core transition train (Alg. 1)."""
+    B = len(p_in)
+    tt, pp = _arr([t.struct() for t in tpm]), _arr([p.struct() for p in p_in])
+    nbytes = LIB.tt_predict_einsum_workspace(B, tt, pp)
+    if nbytes == 0:
+        _check(ERR_ARG, "tt_predict_einsum_workspace")
+    ws = _ws(nbytes)
+    _check(LIB.tt_predict_einsum(B, tt, pp, _arr([o.struct() for o in p_out]), ws.data_ptr(), ws.numel(),
+                                 _stream()), "tt_predict_einsum")
 
 
 def tt_normalize_moments(grids: Sequence[Grid], tts: Sequence[DeviceTT], log_mass, mean=None, cov=None):

@@ -17,6 +17,7 @@
 #include "fft.h"
 #include "adjoint.h"
 #include "round_adj.h"
+#include "einsum.h"
 #include "pred_mfma.h"
 
 namespace ttg {
@@ -2921,6 +2922,146 @@ tt_status tt_predict(int32_t batch, const tt_train* kernels, const tt_train* p_i
   TT_TRY(upload(dx, vx, st));
   if (dtype == TT_F64) return launch_conv<double>(batch, p_in[0].d, r0cap, smem, dk, dp, dx, st);
   return launch_conv<float>(batch, p_in[0].d, r0cap, smem, dk, dp, dx, st);
+}
+
+// ---------------------------------------------------------------------------
+// prediction by Einstein summation with a 2d-core transition TT
+// ---------------------------------------------------------------------------
+static tt_status einsum_check(int32_t batch, const tt_train* tpm, const tt_train* p_in, const tt_train* p_out) {
+  if (batch < 1 || !tpm || !p_in) {
+    set_error("tt_predict_einsum: bad arguments");
+    return TT_ERR_ARG;
+  }
+  const int dtype = p_in[0].dtype, d = p_in[0].d;
+  if (2 * d > TT_MAXD) {
+    set_error("tt_predict_einsum: 2d = %d cores exceed %d", 2 * d, TT_MAXD);
+    return TT_ERR_SHAPE;
+  }
+  for (int b = 0; b < batch; ++b) {
+    TT_TRY(check_train(&tpm[b], "tpm", dtype));
+    TT_TRY(check_train(&p_in[b], "p_in", dtype));
+    if (p_out) TT_TRY(check_train(&p_out[b], "p_out", dtype));
+    if (p_in[b].d != d || tpm[b].d != 2 * d || (p_out && p_out[b].d != d)) {
+      set_error("tt_predict_einsum: need d-core densities and 2d-core transition trains of one d");
+      return TT_ERR_SHAPE;
+    }
+    for (int k = 0; k < d; ++k) {
+      if (tpm[b].n[k] != p_in[b].n[k] || tpm[b].n[d + k] != p_in[b].n[k] || (p_out && p_out[b].n[k] != p_in[b].n[k])) {
+        set_error("tt_predict_einsum: mode sizes differ (filter %d, axis %d)", b, k);
+        return TT_ERR_SHAPE;
+      }
+      if (p_out && p_out[b].cap[k] < tpm[b].cap[k]) {
+        set_error("tt_predict_einsum: p_out cap[%d] = %d below the transition train's %d", k, p_out[b].cap[k],
+                  tpm[b].cap[k]);
+        return TT_ERR_SHAPE;
+      }
+    }
+  }
+  return TT_OK;
+}
+
+// scratch of one filter, in doubles: Y, then two Z buffers
+static void einsum_sizes(const tt_train& t, const tt_train& p, long long& ysz, long long& zsz) {
+  const int d = p.d;
+  ysz = 1;
+  zsz = 1;
+  for (int k = 0; k < d; ++k) {
+    ysz = std::max(ysz, (long long)p.cap[k] * p.n[k] * t.cap[d + k + 1]);
+    zsz = std::max(zsz, (long long)t.cap[d + k] * p.cap[k]);
+  }
+}
+
+size_t tt_predict_einsum_workspace(int32_t batch, const tt_train* tpm, const tt_train* p_in) {
+  if (einsum_check(batch, tpm, p_in, nullptr) != TT_OK) return 0;
+  size_t total = (size_t)batch * (3 * sizeof(DevTT) + 3 * sizeof(double*)) + 4096;
+  for (int b = 0; b < batch; ++b) {
+    long long ysz, zsz;
+    einsum_sizes(tpm[b], p_in[b], ysz, zsz);
+    total += (size_t)(ysz + 2 * zsz) * sizeof(double) + 3 * 256;
+  }
+  return total;
+}
+
+tt_status tt_predict_einsum(int32_t batch, const tt_train* tpm, const tt_train* p_in, const tt_train* p_out,
+                            void* ws, size_t ws_bytes, void* stream) {
+  if (!p_out || !ws) {
+    set_error("tt_predict_einsum: bad arguments");
+    return TT_ERR_ARG;
+  }
+  TT_TRY(einsum_check(batch, tpm, p_in, p_out));
+  const int d = p_in[0].d;
+  const bool f64 = p_in[0].dtype == TT_F64;
+  Arena ar(ws, ws_bytes);
+  DevTT* dt = ar.take<DevTT>(batch);
+  DevTT* dp = ar.take<DevTT>(batch);
+  DevTT* dout = ar.take<DevTT>(batch);
+  double** dy = ar.take<double*>(batch);
+  double** dz0 = ar.take<double*>(batch);
+  double** dz1 = ar.take<double*>(batch);
+  std::vector<DevTT> vt(batch), vp(batch), vo(batch);
+  std::vector<double*> vy(batch), vz0(batch), vz1(batch);
+  long long ymax = 1, zmax = 1, omax = 1;
+  int rtmax = 1, rpmax = 1;  // row blocks of the Z pass
+  for (int b = 0; b < batch; ++b) {
+    vt[b] = make_dev(tpm[b]);
+    vp[b] = make_dev(p_in[b]);
+    vo[b] = make_dev(p_out[b]);
+    long long ysz, zsz;
+    einsum_sizes(tpm[b], p_in[b], ysz, zsz);
+    vy[b] = ar.take<double>(ysz);
+    vz0[b] = ar.take<double>(zsz);
+    vz1[b] = ar.take<double>(zsz);
+    ymax = std::max(ymax, ysz);
+    zmax = std::max(zmax, zsz);
+    for (int k = 0; k < d; ++k) {
+      omax = std::max(omax, (long long)tpm[b].cap[k] * tpm[b].n[k] * tpm[b].cap[k + 1]);
+      rtmax = std::max(rtmax, tpm[b].cap[d + k]);
+      rpmax = std::max(rpmax, p_in[b].cap[k]);
+    }
+  }
+  if (!ar.fits()) {
+    set_error("tt_predict_einsum: workspace too small (%zu < %zu)", ws_bytes, ar.used);
+    return TT_ERR_WORKSPACE;
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  {
+    // the descriptors and scratch pointers sit contiguously at the start of
+    // the arena: one upload
+    const char* base = reinterpret_cast<const char*>(dt);
+    const size_t span = reinterpret_cast<const char*>(dz1 + batch) - base;
+    std::vector<char> h(span, 0);
+    auto put = [&](const void* dst, const void* src, size_t bytes) {
+      memcpy(h.data() + (reinterpret_cast<const char*>(dst) - base), src, bytes);
+    };
+    put(dt, vt.data(), batch * sizeof(DevTT));
+    put(dp, vp.data(), batch * sizeof(DevTT));
+    put(dout, vo.data(), batch * sizeof(DevTT));
+    put(dy, vy.data(), batch * sizeof(double*));
+    put(dz0, vz0.data(), batch * sizeof(double*));
+    put(dz1, vz1.data(), batch * sizeof(double*));
+    TT_TRY(upload(const_cast<char*>(base), h, st));
+  }
+  const dim3 gy(stride_grid(cdiv(ymax, 256), batch), 1, batch), gz(cdiv(rtmax, EZ_ROWS), cdiv(rpmax, EZ_CB), batch);
+  double** zc = nullptr;  // Z of the cores already summed (none: Z = 1)
+  for (int k = d - 1; k >= 0; --k) {
+    double** zn = (zc == dz0) ? dz1 : dz0;
+    if (f64) {
+      hipLaunchKernelGGL((einsum_y_kernel<double>), gy, dim3(256), 0, st, dt, dp, zc, dy, k);
+      hipLaunchKernelGGL((einsum_z_kernel<double>), gz, dim3(256), 0, st, dt, dp, dy, zn, k);
+    } else {
+      hipLaunchKernelGGL((einsum_y_kernel<float>), gy, dim3(256), 0, st, dt, dp, zc, dy, k);
+      hipLaunchKernelGGL((einsum_z_kernel<float>), gz, dim3(256), 0, st, dt, dp, dy, zn, k);
+    }
+    TTG_LAUNCH_CHECK("einsum_y_kernel / einsum_z_kernel");
+    zc = zn;
+  }
+  const dim3 go(stride_grid(cdiv(omax, 256), batch * d), d, batch);
+  if (f64)
+    hipLaunchKernelGGL((einsum_out_kernel<double>), go, dim3(256), 0, st, dt, dp, dout, zc);
+  else
+    hipLaunchKernelGGL((einsum_out_kernel<float>), go, dim3(256), 0, st, dt, dp, dout, zc);
+  TTG_LAUNCH_CHECK("einsum_out_kernel");
+  return TT_OK;
 }
 
 // ---------------------------------------------------------------------------

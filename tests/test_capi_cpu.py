@@ -90,3 +90,36 @@ def test_filter_run_workspace_query():
     assert B.LIB.tt_filter_run_workspace(2, arr, karr, 1, B.F64) > 0
     assert B.LIB.tt_filter_run_workspace(2, arr, karr, 1, 7) == 0
     assert B.LIB.tt_filter_run_workspace(2, arr, None, 0, B.F64) == 0
+
+
+def test_einsum_prediction_validation():
+    from paper_2501_07942_amd import binding as B
+
+    def train(d, n, caps):
+        t = B.Train()
+        t.d = d
+        for k in range(d):
+            t.n[k] = n[k]
+        for k in range(d + 1):
+            t.cap[k] = caps[k]
+        t.dtype = B.F64
+        t.cores = t.ranks = t.log_scale = t.status = 1024  # never dereferenced on the host
+        return t
+
+    p = train(2, [5, 6], [1, 3, 1])
+    tpm = train(4, [5, 6, 5, 6], [1, 4, 9, 4, 1])
+    P, T = (B.Train * 1)(p), (B.Train * 1)(tpm)
+    need = B.LIB.tt_predict_einsum_workspace(1, T, P)
+    assert need > 0
+    # a transition train of the wrong length or mode sizes is rejected
+    bad = (B.Train * 1)(train(3, [5, 6, 5], [1, 4, 9, 1]))
+    assert B.LIB.tt_predict_einsum_workspace(1, bad, P) == 0
+    bad = (B.Train * 1)(train(4, [5, 6, 5, 7], [1, 4, 9, 4, 1]))
+    assert B.LIB.tt_predict_einsum_workspace(1, bad, P) == 0
+    # an output whose capacities cannot hold the transition train's ranks
+    small = (B.Train * 1)(train(2, [5, 6], [1, 2, 1]))
+    st = B.LIB.tt_predict_einsum(1, T, P, small, C.c_void_p(4096), need, None)
+    assert st == B.ERR_SHAPE
+    ok = (B.Train * 1)(train(2, [5, 6], [1, 4, 1]))
+    st = B.LIB.tt_predict_einsum(1, T, P, ok, C.c_void_p(4096), 16, None)
+    assert st == B.ERR_WORKSPACE
