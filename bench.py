@@ -261,6 +261,8 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=2)
     ap.add_argument("--no-grad", action="store_true", help="skip the gradient timing")
     ap.add_argument("--no-einsum", action="store_true", help="skip the Einstein-summation prediction timing")
+    ap.add_argument("--einsum-only", action="store_true",
+                    help="only time the Einstein-summation prediction (prints {\"einsum_predict\": ...})")
     ap.add_argument("--grad-steps", type=int, default=50)
     ap.add_argument("--grad-batch", type=int, default=32)
     ap.add_argument("--grad-only", action="store_true",
@@ -291,6 +293,9 @@ def main():
         print(json.dumps({"copy_bytes_read": nel * 4, "copy_bytes_written": nel * 4, "copies": 5}), flush=True)
         return
 
+    if args.einsum_only:
+        print(json.dumps({"einsum_predict": einsum_bench(binding)}), flush=True)
+        return
     if args.grad_only:
         from paper_2501_07942_amd import grad as G
         print(json.dumps({"grad": grad_bench(G, wl, args.grad_steps, args.grad_batch)}), flush=True)
