@@ -275,7 +275,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
-              f"(independent filters shard across GPUs without communication; see DESIGN.md)",
+              f"(independent filters shard across GPUs without communication)",
               file=sys.stderr)
         sys.exit(2)
     import torch

@@ -3,7 +3,7 @@ likelihood of the random-walk state-space model.
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
 
-Readings of points the paper leaves open (each listed in the design doc):
+Readings of points the paper leaves open:
   * grid: inclusive linspace per axis, spacing (hi-lo)/(N-1), cell volume
     the product of spacings (Sec. 2, eq. pdf_pm, and the grid bullet of
     Sec. 4 state an equidistant grid with points at cell centres);

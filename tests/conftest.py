@@ -15,7 +15,7 @@ def pytest_configure(config):
 
 def pytest_collection_modifyitems(config, items):
     # GPU tests are skipped (not failed) on hosts without a device so that the
-    # CPU suite stays green; on the GPU machine they run and fail loudly.
+    # CPU suite stays green; with a device present they run and fail loudly.
     try:
         import torch
         has_gpu = torch.cuda.is_available()
