@@ -182,7 +182,7 @@ tt_status tt_predict_einsum(int32_t batch, const tt_train* tpm, const tt_train* 
                             void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------
- * tt_update -- Bayes update (Sec. 2.2 eqs. pmf_filtrace_a/b; Alg. 2 step 2):
+ * tt_update -- Bayes update (Sec. 2.2 eqs. pmf_filtrace_a/b; the update of Alg. 2):
  * builds the likelihood TT for measurement z (FP64, max-shifted, its log
  * shift added to the log-scale), forms H = L o P_pred as the Kronecker
  * product of the core slices (Sec. 4.1 'times'; ranks multiply) and
@@ -250,7 +250,7 @@ tt_status tt_round_taped(int32_t batch, const tt_train* t_in, const tt_train* t_
 
 /* ---------------------------------------------------------------------
  * tt_normalize_moments -- mass, normalisation and moments (Sec. 4.1 'sum',
- * 'mrdivide', 'power', 'dot'; Alg. 2 steps 2-4), for rank capacities <= 64:
+ * 'mrdivide', 'power', 'dot'; the normalisation of Alg. 2), for rank capacities <= 64:
  *   mass = sum_i A(i) * delta,  log_mass_dev[b] = log(mass) (before),
  *   log_scale -= log(mass)  (A now integrates to one),
  *   mean_dev[b*d + l]       = sum_i xi_l(i_l) A(i) delta,

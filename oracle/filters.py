@@ -43,7 +43,7 @@ def _marginal_min(p):
 def run_tt_filter(axes, q, halfwidths, meas, z, m0, p0_diag, cap, eps,
                   kernel_tol=1e-12, lik_tol=1e-12, lik_max_rank=None,
                   kernel=None, record_density=False, replay=None):
-    """TT point-mass filter in FP64 (Alg. 2 loop order, Alg. 3 step 4 FFT
+    """TT point-mass filter in FP64 (Alg. 2 loop order, Alg. 3's FFT
     prediction with F = I).  z has shape [K, b].  Returns a dict of per-step
     records and the final filtering TT.
 

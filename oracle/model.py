@@ -184,7 +184,7 @@ def likelihood_dense(axes, z, meas):
 def moments_tt(p, axes):
     """Mass, mean and covariance of a PMD held as a TT: contractions of the
     cores with the per-axis vectors 1, xi^l and (xi^l)^2 (Sec. 4.1 'power',
-    'dot'; Alg. 2 step 3).  Returns (mass, mean[d], cov[d,d]) where mass is
+    'dot'; the moments of Alg. 2).  Returns (mass, mean[d], cov[d,d]) where mass is
     sum_i P(i) delta and the moments are of the normalised density."""
     d = len(axes)
     delta = cell_volume(axes)

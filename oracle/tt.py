@@ -286,8 +286,8 @@ def einsum_predict(t_cores, p_cores):
     For each second-half core of T a 4-way tensor M_k contracts the shared
     grid index with the matching core of P; Z is built backwards from
     Z^{(2d)} = 1, and the result keeps the first d cores of T with Z
-    absorbed into the d-th.  (The paper's step 5 loops back to the step that
-    builds M; this is read as looping over all d second-half cores.)"""
+    absorbed into the d-th.  (The paper's loop back to the construction of M is read as looping
+    over all d second-half cores.)"""
     d = len(p_cores)
     assert len(t_cores) == 2 * d
     z = np.ones((1, 1))
