@@ -14,5 +14,6 @@ Contents
   filters  TT point-mass filter, dense point-mass filter, Kalman filter
   grad     log-likelihood gradients: replayed-rank differences, complex step
   adjoint  reverse-mode log-likelihood gradient at fixed ranks
+  redesign grid re-design (Alg. 4) and TT interpolation onto a new grid
 """
 from . import tt, model, filters  # noqa: F401
