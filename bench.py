@@ -198,8 +198,9 @@ def grad_bench(G, wl, steps, batch):
 def einsum_bench(binding, batch=64, d=4, n=64, rt=64, rp=16, calls=10):
     """The Einstein-summation prediction (Alg. 1, tt_predict_einsum) on a
     batch of FP64 filters with random 2d-core transition trains (inner
-    ranks rt) and densities (inner ranks rp): ms per batched call, the HBM
-    rate of its algorithmic bytes (every transition core read once, the
+    ranks rt) and densities (inner ranks rp): ms per batched call (host
+    marshalling included) and, from the library's launch events, the kernel
+    time and the HBM rate of its algorithmic bytes (every transition core read once, the
     first d-1 written once, the density read once, the output's last core
     written); the CPU baseline leg times the oracle's Alg. 1 beside it."""
     import torch
@@ -221,16 +222,80 @@ def einsum_bench(binding, batch=64, d=4, n=64, rt=64, rp=16, calls=10):
         binding.tt_predict_einsum(T, P, O)
     e1.record(st)
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / calls
+    ms_call = e0.elapsed_time(e1) / calls
+    # the kernels alone: library events around the launches of each call
+    binding.profile_begin(("einsum",))
+    for _ in range(calls):
+        binding.tt_predict_einsum(T, P, O)
+    torch.cuda.synchronize()
+    kms, kn = binding.profile_end()["einsum"][:2]
+    ms = kms / max(kn, 1)
     core = lambda a, b: a * n * b
     tbytes = sum(core(tc[k], tc[k + 1]) for k in range(2 * d)) + sum(core(tc[k], tc[k + 1]) for k in range(d - 1))
     byts = 8 * batch * (tbytes + sum(core(pc[k], pc[k + 1]) for k in range(d)) + tc[d - 1] * n)
     gbs = byts / (ms * 1e-3) / 1e9
     return {"workload": f"random 2d-core transition trains, d={d} N={n} rank {rt}, densities rank {rp}",
-            "filters": batch, "precision": "fp64", "ms_per_call": round(ms, 4),
-            "filter_calls_per_s": round(batch / (ms * 1e-3), 1),
+            "filters": batch, "precision": "fp64", "ms_per_call": round(ms_call, 4),
+            "filter_calls_per_s": round(batch / (ms_call * 1e-3), 1), "kernel_ms_per_call": round(ms, 4),
             "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(gbs / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_call": byts}}
+
+
+def interp_bench(binding, batch=256, d=6, n=128, r=16, calls=10):
+    """Interpolation of filtering densities onto re-designed grids (Alg. 4,
+    tt_interpolate) at the metric workload's shapes (FP32 cores, rank r):
+    ms per batched call (host marshalling included) and, from the library's
+    launch events, the kernel time and the HBM rate of its algorithmic bytes
+    (the input cores read once, the output cores written once)."""
+    import torch
+    caps = [1] + [r] * (d - 1) + [1]
+    T_in = binding.DeviceTT.batch([[n] * d] * batch, [caps] * batch, binding.F32)
+    T_out = binding.DeviceTT.batch([[n] * d] * batch, [caps] * batch, binding.F32)
+    gen = torch.Generator(device="cuda").manual_seed(20250114)
+    for t in T_in:
+        t.cores.normal_(generator=gen)
+        t.ranks.copy_(torch.tensor(caps, dtype=torch.int32))
+    old = [binding.make_grid(d, [n] * d, [-20.0] * d, [20.0] * d)] * batch
+    new = [binding.make_grid(d, [n] * d, [-17.0 + 0.01 * b] * d, [22.5 - 0.01 * b] * d) for b in range(batch)]
+    binding.tt_interpolate(old, new, T_in, T_out)  # warm
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(calls):
+        binding.tt_interpolate(old, new, T_in, T_out)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms_call = e0.elapsed_time(e1) / calls
+    binding.profile_begin(("interp",))
+    for _ in range(calls):
+        binding.tt_interpolate(old, new, T_in, T_out)
+    torch.cuda.synchronize()
+    kms, kn = binding.profile_end()["interp"][:2]
+    ms = kms / max(kn, 1)
+    elems = sum(caps[k] * n * caps[k + 1] for k in range(d))
+    byts = 4 * batch * 2 * elems
+    gbs = byts / (ms * 1e-3) / 1e9
+    return {"workload": f"filtering densities d={d} N={n} rank {r} onto shifted and rescaled grids",
+            "filters": batch, "precision": "fp32", "ms_per_call": round(ms_call, 4),
+            "filter_calls_per_s": round(batch / (ms_call * 1e-3), 1), "kernel_ms_per_call": round(ms, 4),
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(gbs / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_call": byts}}
+
+
+def interp_cpu_baseline(d=6, n=128, r=16):
+    """The oracle's interpolation on one filter of the interp_bench shapes
+    (part of the CPU baseline leg)."""
+    import numpy as np
+    from oracle import model as mdl
+    from oracle import redesign as rd
+    caps = [1] + [r] * (d - 1) + [1]
+    rng = np.random.default_rng(20250114)
+    cores = [rng.standard_normal((caps[k], n, caps[k + 1])) for k in range(d)]
+    t0 = time.perf_counter()
+    rd.interpolate_tt(cores, mdl.grid_axes(-20.0, 20.0, [n] * d), mdl.grid_axes(-17.0, 22.5, [n] * d))
+    return {"value": round(1.0 / (time.perf_counter() - t0), 2), "unit": "filter-calls/s", "kind": "oracle",
+            "sample": f"1 filter, d={d} N={n} rank {r}, FP64 NumPy"}
 
 
 def einsum_cpu_baseline(d=4, n=64, rt=64, rp=16):
@@ -262,7 +327,7 @@ def main():
     ap.add_argument("--no-grad", action="store_true", help="skip the gradient timing")
     ap.add_argument("--no-einsum", action="store_true", help="skip the Einstein-summation prediction timing")
     ap.add_argument("--einsum-only", action="store_true",
-                    help="only time the Einstein-summation prediction (prints {\"einsum_predict\": ...})")
+                    help="only time the Einstein-summation prediction and the interpolation onto a new grid")
     ap.add_argument("--grad-steps", type=int, default=50)
     ap.add_argument("--grad-batch", type=int, default=32)
     ap.add_argument("--grad-only", action="store_true",
@@ -294,7 +359,8 @@ def main():
         return
 
     if args.einsum_only:
-        print(json.dumps({"einsum_predict": einsum_bench(binding)}), flush=True)
+        print(json.dumps({"einsum_predict": einsum_bench(binding), "interpolate": interp_bench(binding)}),
+              flush=True)
         return
     if args.grad_only:
         from paper_2501_07942_amd import grad as G
@@ -360,6 +426,8 @@ def main():
     if not args.no_einsum:
         out["einsum_predict"] = einsum_bench(binding)
         torch.cuda.empty_cache()
+        out["interpolate"] = interp_bench(binding)
+        torch.cuda.empty_cache()
     if not args.no_plain:
         plain = run_batch(None, runner, binding, wl, args.workload, 1, args.steps, args.warmup, binding.F64)
         out["fp64_plain"] = {"value": round(args.steps / (plain["ms"] / 1000.0), 3), "unit": "filter-steps/s",
@@ -376,6 +444,8 @@ def main():
         out["cpu_baseline"] = cpu_baseline(wl)
         if "einsum_predict" in out:
             out["einsum_predict"]["cpu_baseline"] = einsum_cpu_baseline()
+        if "interpolate" in out:
+            out["interpolate"]["cpu_baseline"] = interp_cpu_baseline()
     print(json.dumps(out), flush=True)
 
 

@@ -182,6 +182,46 @@ tt_status tt_predict_einsum(int32_t batch, const tt_train* tpm, const tt_train* 
                             void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------
+ * tt_grid_redesign -- the grid re-design of Alg. 4 (used twice by Alg. 3):
+ * per filter, the local Kalman prediction of the filtering moments
+ * m' = F m, P' = F P F^T + Q, the predictive box m' +- nsigma sqrt(P'_ll),
+ * and the new filtering grid: the smallest axis-aligned box holding the
+ * box's 2^d corners mapped by F^{-1} (computed as F^{-1} m' +- |F^{-1}| h),
+ * with the old grid's number of points per axis.
+ *   f, q       d x d row-major, host, shared by the batch (F invertible)
+ *   mean_dev   device [batch*d], cov_dev device [batch*d*d] (the outputs of
+ *              tt_normalize_moments)
+ *   old_grids  host [batch]; new_grids host [batch], written (n copied)
+ * Synchronous (returns after the boxes are on the host).  Workspace:
+ * tt_grid_redesign_workspace(batch, d).  Errors: TT_ERR_ARG (null, nsigma
+ * <= 0, F singular, a degenerate or non-finite box), TT_ERR_SHAPE (a grid's
+ * d differs), TT_ERR_WORKSPACE, TT_ERR_HIP.
+ * --------------------------------------------------------------------- */
+size_t tt_grid_redesign_workspace(int32_t batch, int32_t d);
+tt_status tt_grid_redesign(int32_t batch, int32_t d, const double* f, const double* q, double nsigma,
+                           const double* mean_dev, const double* cov_dev, const tt_grid* old_grids,
+                           tt_grid* new_grids, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------
+ * tt_interpolate -- multilinear interpolation of a TT density onto a new
+ * axis-aligned grid (Sec. 4.2, interpolation on the level of the cores;
+ * Alg. 3 and Alg. 4): every core is contracted with its axis' two-tap
+ * linear interpolation operator,
+ *   out_k(a, i', b) = (1 - t) in_k(a, j, b) + t in_k(a, j + 1, b)
+ * where x_j <= x'_{i'} <= x_{j+1} on the old axis, and zero where x'_{i'}
+ * is off the old grid.  Grid points are lo + (hi - lo) i / (n - 1).  Out
+ * ranks, log_scale and status are in's; mass is not renormalised.
+ *   from[b], to[b]  host grids of filter b (from = in's grid, to = out's;
+ *              n >= 2 per axis); in[b], out[b] one dtype, out->cap >= in's.
+ * Workspace: tt_interpolate_workspace(batch).  Errors: TT_ERR_ARG,
+ * TT_ERR_SHAPE (grids, modes or capacities inconsistent),
+ * TT_ERR_WORKSPACE, TT_ERR_HIP.
+ * --------------------------------------------------------------------- */
+size_t tt_interpolate_workspace(int32_t batch);
+tt_status tt_interpolate(int32_t batch, const tt_grid* from, const tt_grid* to, const tt_train* in,
+                         const tt_train* out, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------
  * tt_update -- Bayes update (Sec. 2.2 eqs. pmf_filtrace_a/b; the update of Alg. 2):
  * builds the likelihood TT for measurement z (FP64, max-shifted, its log
  * shift added to the log-scale), forms H = L o P_pred as the Kronecker
@@ -557,7 +597,9 @@ int32_t tt_get_predict_mode(void);
  * (1 << c) set in mask:
  *   0 convolution, 1 Hadamard, 2 Gram, 3 pivoted Cholesky, 4 Jacobi,
  *   5 triangular solve, 6 GEMM, 7 likelihood build, 8 sum/moments,
- *   9 fused prediction (convolution and absorption of the next factor).
+ *   9 fused prediction (convolution and absorption of the next factor),
+ *   10 Einstein-summation prediction (all passes of one call),
+ *   11 interpolation onto a new grid.
  * For classes with a work model (9; direct prediction mode only) a
  * one-workgroup kernel after each launch adds the launch's algorithmic
  * flops and HBM bytes, computed from the device-resident ranks, to a small

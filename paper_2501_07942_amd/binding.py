@@ -93,6 +93,10 @@ def _load():
         "tt_round_taped": (I, [I, P, P, D, I, P, P, S, P]),
         "tt_predict_einsum_workspace": (S, [I, P, P]),
         "tt_predict_einsum": (I, [I, P, P, P, P, S, P]),
+        "tt_grid_redesign_workspace": (S, [I, I]),
+        "tt_grid_redesign": (I, [I, I, P, P, D, P, P, P, P, P, S, P]),
+        "tt_interpolate_workspace": (S, [I]),
+        "tt_interpolate": (I, [I, P, P, P, P, P, S, P]),
         "tt_prior": (I, [I, P, P, P, P, P, S, P]),
         "tt_likelihood": (I, [I, P, P, P, I, P, I, P, S, P]),
         "tt_kernel_build_batch_workspace": (S, [I, P, P, P]),
@@ -129,7 +133,8 @@ EXPORTED = ("tt_train_elems", "tt_last_error", "tt_version", "tt_kernel_build_wo
             "tt_kernel_build_batch_workspace", "tt_kernel_build_batch",
             "tt_likelihood_adjoint_workspace", "tt_likelihood_adjoint", "tt_adjoint_axpy",
             "tt_adjoint_inner", "tt_align_signs", "tt_round_taped", "tt_predict_einsum_workspace",
-            "tt_predict_einsum")
+            "tt_predict_einsum", "tt_grid_redesign_workspace", "tt_grid_redesign", "tt_interpolate_workspace",
+            "tt_interpolate")
 
 PREDICT_DIRECT, PREDICT_FFT, PREDICT_UNFUSED, PREDICT_DIRECT_VALU = 0, 1, 2, 3
 
@@ -137,7 +142,8 @@ PREDICT_DIRECT, PREDICT_FFT, PREDICT_UNFUSED, PREDICT_DIRECT_VALU = 0, 1, 2, 3
 def set_predict_mode(mode: int):
     _check(LIB.tt_set_predict_mode(int(mode)), "tt_set_predict_mode")
 
-PROFILE_CLASSES = ("conv", "hadamard", "gram", "pchol", "jacobi", "trsm", "gemm", "lik", "contract", "pred")
+PROFILE_CLASSES = ("conv", "hadamard", "gram", "pchol", "jacobi", "trsm", "gemm", "lik", "contract", "pred",
+                   "einsum", "interp")
 
 
 def profile_begin(classes=PROFILE_CLASSES):
@@ -430,6 +436,29 @@ def tt_predict_einsum(tpm: Sequence[DeviceTT], p_in: Sequence[DeviceTT], p_out: 
     ws = _ws(nbytes)
     _check(LIB.tt_predict_einsum(B, tt, pp, _arr([o.struct() for o in p_out]), ws.data_ptr(), ws.numel(),
                                  _stream()), "tt_predict_einsum")
+
+
+def tt_grid_redesign(old_grids: Sequence[Grid], f, q, nsigma: float, mean, cov) -> List[Grid]:
+    """New filtering grids by Alg. 4.  f, q: host (d, d) float64 arrays;
+    mean [B, d], cov [B, d, d]: torch float64 device tensors."""
+    B = len(old_grids)
+    d = old_grids[0].d
+    fa = np.ascontiguousarray(f, dtype=np.float64)
+    qa = np.ascontiguousarray(q, dtype=np.float64)
+    out = (Grid * B)()
+    ws = _ws(LIB.tt_grid_redesign_workspace(B, d))
+    _check(LIB.tt_grid_redesign(B, d, fa.ctypes.data, qa.ctypes.data, float(nsigma), mean.data_ptr(), cov.data_ptr(),
+                                _arr(list(old_grids)), out, ws.data_ptr(), ws.numel(), _stream()), "tt_grid_redesign")
+    return list(out)
+
+
+def tt_interpolate(from_grids: Sequence[Grid], to_grids: Sequence[Grid], t_in: Sequence[DeviceTT],
+                   t_out: Sequence[DeviceTT]):
+    B = len(t_in)
+    ws = _ws(LIB.tt_interpolate_workspace(B))
+    _check(LIB.tt_interpolate(B, _arr(list(from_grids)), _arr(list(to_grids)), _arr([t.struct() for t in t_in]),
+                              _arr([t.struct() for t in t_out]), ws.data_ptr(), ws.numel(), _stream()),
+           "tt_interpolate")
 
 
 def tt_normalize_moments(grids: Sequence[Grid], tts: Sequence[DeviceTT], log_mass, mean=None, cov=None):

@@ -18,6 +18,7 @@
 #include "adjoint.h"
 #include "round_adj.h"
 #include "einsum.h"
+#include "interp.h"
 #include "pred_mfma.h"
 
 namespace ttg {
@@ -40,7 +41,8 @@ tt_status check_hip(hipError_t e, const char* what) {
 // optional timing of kernel classes with HIP events on the launch stream
 // ---------------------------------------------------------------------------
 enum ProfClass {
-  PC_CONV = 0, PC_HADAMARD, PC_GRAM, PC_PCHOL, PC_JACOBI, PC_TRSM, PC_GEMM, PC_LIK, PC_CONTRACT, PC_PRED, PC_OTHER,
+  PC_CONV = 0, PC_HADAMARD, PC_GRAM, PC_PCHOL, PC_JACOBI, PC_TRSM, PC_GEMM, PC_LIK, PC_CONTRACT, PC_PRED, PC_EINSUM,
+  PC_INTERP, PC_OTHER,
   PC_N
 };
 struct ProfRec {
@@ -3042,6 +3044,7 @@ tt_status tt_predict_einsum(int32_t batch, const tt_train* tpm, const tt_train* 
     TT_TRY(upload(const_cast<char*>(base), h, st));
   }
   const dim3 gy(stride_grid(cdiv(ymax, 256), batch), 1, batch), gz(cdiv(rtmax, EZ_ROWS), cdiv(rpmax, EZ_CB), batch);
+  ProfScope ps_(PC_EINSUM, st);
   double** zc = nullptr;  // Z of the cores already summed (none: Z = 1)
   for (int k = d - 1; k >= 0; --k) {
     double** zn = (zc == dz0) ? dz1 : dz0;
@@ -3061,6 +3064,165 @@ tt_status tt_predict_einsum(int32_t batch, const tt_train* tpm, const tt_train* 
   else
     hipLaunchKernelGGL((einsum_out_kernel<float>), go, dim3(256), 0, st, dt, dp, dout, zc);
   TTG_LAUNCH_CHECK("einsum_out_kernel");
+  return TT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// grid re-design and interpolation onto the new grid
+// ---------------------------------------------------------------------------
+size_t tt_grid_redesign_workspace(int32_t batch, int32_t d) {
+  if (batch < 1 || d < 1 || d > TT_MAXD) return 0;
+  return (size_t)batch * sizeof(GridBox) + 3 * (size_t)d * d * sizeof(double) + 4 * 256;
+}
+
+tt_status tt_grid_redesign(int32_t batch, int32_t d, const double* f, const double* q, double nsigma,
+                           const double* mean_dev, const double* cov_dev, const tt_grid* old_grids,
+                           tt_grid* new_grids, void* ws, size_t ws_bytes, void* stream) {
+  if (batch < 1 || d < 1 || d > TT_MAXD || !f || !q || !mean_dev || !cov_dev || !old_grids || !new_grids || !ws ||
+      !(nsigma > 0.0)) {
+    set_error("tt_grid_redesign: bad arguments");
+    return TT_ERR_ARG;
+  }
+  for (int b = 0; b < batch; ++b)
+    if (old_grids[b].d != d) {
+      set_error("tt_grid_redesign: grid %d has d = %d, not %d", b, old_grids[b].d, d);
+      return TT_ERR_SHAPE;
+    }
+  // F^{-1} of the model matrix (d x d, once per call): Gauss-Jordan with
+  // partial pivoting on the host
+  std::vector<double> a(f, f + (size_t)d * d), inv((size_t)d * d, 0.0);
+  for (int i = 0; i < d; ++i) inv[(size_t)i * d + i] = 1.0;
+  double fmaxabs = 0.0;
+  for (int i = 0; i < d * d; ++i) fmaxabs = std::max(fmaxabs, std::fabs(a[i]));
+  for (int c = 0; c < d; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < d; ++r)
+      if (std::fabs(a[(size_t)r * d + c]) > std::fabs(a[(size_t)piv * d + c])) piv = r;
+    if (!(std::fabs(a[(size_t)piv * d + c]) > 1e-14 * fmaxabs)) {
+      set_error("tt_grid_redesign: F is singular");
+      return TT_ERR_ARG;
+    }
+    for (int j = 0; j < d; ++j) {
+      std::swap(a[(size_t)c * d + j], a[(size_t)piv * d + j]);
+      std::swap(inv[(size_t)c * d + j], inv[(size_t)piv * d + j]);
+    }
+    const double dinv = 1.0 / a[(size_t)c * d + c];
+    for (int j = 0; j < d; ++j) {
+      a[(size_t)c * d + j] *= dinv;
+      inv[(size_t)c * d + j] *= dinv;
+    }
+    for (int r = 0; r < d; ++r) {
+      if (r == c) continue;
+      const double m = a[(size_t)r * d + c];
+      if (m == 0.0) continue;
+      for (int j = 0; j < d; ++j) {
+        a[(size_t)r * d + j] -= m * a[(size_t)c * d + j];
+        inv[(size_t)r * d + j] -= m * inv[(size_t)c * d + j];
+      }
+    }
+  }
+  Arena ar(ws, ws_bytes);
+  GridBox* dbox = ar.take<GridBox>(batch);
+  double* dmat = ar.take<double>(3 * (size_t)d * d);
+  if (!ar.fits()) {
+    set_error("tt_grid_redesign: workspace too small");
+    return TT_ERR_WORKSPACE;
+  }
+  std::vector<double> mats(3 * (size_t)d * d);
+  std::copy(f, f + (size_t)d * d, mats.begin());
+  std::copy(inv.begin(), inv.end(), mats.begin() + (size_t)d * d);
+  std::copy(q, q + (size_t)d * d, mats.begin() + 2 * (size_t)d * d);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  TT_TRY(upload(dmat, mats, st));
+  hipLaunchKernelGGL(grid_box_kernel, dim3(cdiv(batch, 64)), dim3(64), 0, st, (int)batch, (int)d, dmat,
+                     dmat + (size_t)d * d, dmat + 2 * (size_t)d * d, nsigma, mean_dev, cov_dev, dbox);
+  TTG_LAUNCH_CHECK("grid_box_kernel");
+  std::vector<GridBox> hb(batch);
+  HIP_TRY(hipMemcpyAsync(hb.data(), dbox, batch * sizeof(GridBox), hipMemcpyDeviceToHost, st), "box download");
+  HIP_TRY(hipStreamSynchronize(st), "tt_grid_redesign");
+  for (int b = 0; b < batch; ++b) {
+    tt_grid g = old_grids[b];
+    for (int l = 0; l < d; ++l) {
+      if (!(hb[b].hi[l] > hb[b].lo[l]) || !std::isfinite(hb[b].lo[l]) || !std::isfinite(hb[b].hi[l])) {
+        set_error("tt_grid_redesign: degenerate box for filter %d, axis %d", b, l);
+        return TT_ERR_ARG;
+      }
+      g.lo[l] = hb[b].lo[l];
+      g.hi[l] = hb[b].hi[l];
+    }
+    new_grids[b] = g;
+  }
+  return TT_OK;
+}
+
+size_t tt_interpolate_workspace(int32_t batch) {
+  if (batch < 1) return 0;
+  return (size_t)batch * (2 * sizeof(DevTT) + sizeof(InterpArgs)) + 3 * 256;
+}
+
+tt_status tt_interpolate(int32_t batch, const tt_grid* from, const tt_grid* to, const tt_train* in,
+                         const tt_train* out, void* ws, size_t ws_bytes, void* stream) {
+  if (batch < 1 || !from || !to || !in || !out || !ws) {
+    set_error("tt_interpolate: bad arguments");
+    return TT_ERR_ARG;
+  }
+  const int dtype = in[0].dtype;
+  std::vector<DevTT> vi(batch), vo(batch);
+  std::vector<InterpArgs> va(batch);
+  long long omax = 1;
+  int dmax = 1;
+  for (int b = 0; b < batch; ++b) {
+    TT_TRY(check_train(&in[b], "in", dtype));
+    TT_TRY(check_train(&out[b], "out", dtype));
+    const int d = in[b].d;
+    if (out[b].d != d || from[b].d != d || to[b].d != d) {
+      set_error("tt_interpolate: d differs (filter %d)", b);
+      return TT_ERR_SHAPE;
+    }
+    InterpArgs& g = va[b];
+    memset(&g, 0, sizeof(g));
+    for (int k = 0; k < d; ++k) {
+      if (from[b].n[k] != in[b].n[k] || to[b].n[k] != out[b].n[k] || in[b].n[k] < 2 || out[b].n[k] < 2 ||
+          !(from[b].hi[k] > from[b].lo[k]) || !(to[b].hi[k] > to[b].lo[k])) {
+        set_error("tt_interpolate: grids and trains disagree, or an axis has < 2 points (filter %d, axis %d)", b,
+                  k);
+        return TT_ERR_SHAPE;
+      }
+      if (out[b].cap[k + 1] < in[b].cap[k + 1]) {
+        set_error("tt_interpolate: out cap[%d] below in's", k + 1);
+        return TT_ERR_SHAPE;
+      }
+      g.n_old[k] = in[b].n[k];
+      g.n_new[k] = out[b].n[k];
+      g.lo_old[k] = from[b].lo[k];
+      g.hi_old[k] = from[b].hi[k];
+      g.lo_new[k] = to[b].lo[k];
+      g.hi_new[k] = to[b].hi[k];
+      omax = std::max(omax, (long long)in[b].cap[k] * out[b].n[k] * in[b].cap[k + 1]);
+    }
+    dmax = std::max(dmax, d);
+    vi[b] = make_dev(in[b]);
+    vo[b] = make_dev(out[b]);
+  }
+  Arena ar(ws, ws_bytes);
+  DevTT* di = ar.take<DevTT>(batch);
+  DevTT* dout = ar.take<DevTT>(batch);
+  InterpArgs* da = ar.take<InterpArgs>(batch);
+  if (!ar.fits()) {
+    set_error("tt_interpolate: workspace too small");
+    return TT_ERR_WORKSPACE;
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  TT_TRY(upload(di, vi, st));
+  TT_TRY(upload(dout, vo, st));
+  TT_TRY(upload(da, va, st));
+  const dim3 grid(stride_grid(cdiv(omax, 256), batch * dmax), dmax, batch);
+  ProfScope ps_(PC_INTERP, st);
+  if (dtype == TT_F64)
+    hipLaunchKernelGGL((interp_kernel<double>), grid, dim3(256), 0, st, di, dout, da);
+  else
+    hipLaunchKernelGGL((interp_kernel<float>), grid, dim3(256), 0, st, di, dout, da);
+  TTG_LAUNCH_CHECK("interp_kernel");
   return TT_OK;
 }
 

@@ -123,3 +123,49 @@ def test_einsum_prediction_validation():
     ok = (B.Train * 1)(train(2, [5, 6], [1, 4, 1]))
     st = B.LIB.tt_predict_einsum(1, T, P, ok, C.c_void_p(4096), 16, None)
     assert st == B.ERR_WORKSPACE
+
+
+def test_redesign_and_interpolation_validation():
+    from paper_2501_07942_amd import binding as B
+
+    def train(n, caps):
+        t = B.Train()
+        t.d = len(n)
+        for k in range(t.d):
+            t.n[k] = n[k]
+        for k in range(t.d + 1):
+            t.cap[k] = caps[k]
+        t.dtype = B.F64
+        t.cores = t.ranks = t.log_scale = t.status = 1024  # never dereferenced on the host
+        return t
+
+    g0 = B.make_grid(2, [8, 9], [-1.0, -1.0], [1.0, 1.0])
+    g1 = B.make_grid(2, [8, 9], [-2.0, -1.0], [1.0, 2.0])
+    gi = (B.Grid * 1)(g0)
+    go = (B.Grid * 1)(g1)
+    tin = (B.Train * 1)(train([8, 9], [1, 3, 1]))
+    need = B.LIB.tt_interpolate_workspace(1)
+    assert need > 0
+    ws = C.c_void_p(4096)
+    # grid and train disagree on a mode size
+    bad = (B.Train * 1)(train([8, 10], [1, 3, 1]))
+    assert B.LIB.tt_interpolate(1, gi, go, tin, bad, ws, need, None) == B.ERR_SHAPE
+    # output capacity below the input's
+    small = (B.Train * 1)(train([8, 9], [1, 2, 1]))
+    assert B.LIB.tt_interpolate(1, gi, go, tin, small, ws, need, None) == B.ERR_SHAPE
+    # an axis of one point has no spacing
+    g2 = (B.Grid * 1)(B.make_grid(2, [1, 9], [-1.0, -1.0], [1.0, 1.0]))
+    one = (B.Train * 1)(train([1, 9], [1, 3, 1]))
+    assert B.LIB.tt_interpolate(1, g2, g2, one, one, ws, need, None) == B.ERR_SHAPE
+    # grid re-design: a singular F and a non-positive nsigma are rejected
+    # before anything reaches the device
+    f = (C.c_double * 4)(1.0, 2.0, 2.0, 4.0)
+    q = (C.c_double * 4)(1.0, 0.0, 0.0, 1.0)
+    out = (B.Grid * 1)()
+    rneed = B.LIB.tt_grid_redesign_workspace(1, 2)
+    assert rneed > 0
+    st = B.LIB.tt_grid_redesign(1, 2, f, q, 3.0, C.c_void_p(4096), C.c_void_p(4096), gi, out, ws, rneed, None)
+    assert st == B.ERR_ARG and b"singular" in B.LIB.tt_last_error()
+    f2 = (C.c_double * 4)(1.1, 0.1, -0.2, 1.1)
+    st = B.LIB.tt_grid_redesign(1, 2, f2, q, 0.0, C.c_void_p(4096), C.c_void_p(4096), gi, out, ws, rneed, None)
+    assert st == B.ERR_ARG
