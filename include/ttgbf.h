@@ -333,8 +333,8 @@ size_t tt_normalize_moments_workspace(int32_t batch, const tt_train* t);
  *   b_bar_k(c,i,e) = sum_{a,b} h_bar_k(a rb0 + c, i, b rb1 + e) A_k(a,i,b)
  * (either output may be null) and copies h_bar's log_scale into both.
  *
- * tt_normalize_adjoint: the normalisation of tt_normalize_moments (Alg. 2
- * step 4, the normaliser of eq. pmf_filtrace_b) keeps the cores of X and
+ * tt_normalize_adjoint: the normalisation of tt_normalize_moments (Alg. 2,
+ * the normaliser of eq. pmf_filtrace_b) keeps the cores of X and
  * sets log_scale(P) = -log(S delta), S = sum of the stored entries of X,
  * with log-mass log m = log_scale(X) + log(S delta).  Given p_bar (its
  * log_scale = the derivative with respect to log_scale(P)) and the

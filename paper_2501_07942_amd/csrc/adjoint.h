@@ -1,8 +1,7 @@
 // Adjoints (reverse-mode derivatives) of the linear steps of one filter
 // step: the core-wise convolution of the prediction (Sec. 4.2), the
 // Hadamard product of the update (Sec. 4.1 'times') and the normalisation
-// to unit mass (Sec. 2.2, the normaliser of eq. pmf_filtrace_b; Alg. 2
-// step 4).
+// to unit mass (Sec. 2.2, the normaliser of eq. pmf_filtrace_b; Alg. 2).
 //
 // A TT here is stored cores times exp(log_scale).  An adjoint train has the
 // layout and ranks of its primal: its cores hold the derivative with
