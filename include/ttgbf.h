@@ -274,9 +274,10 @@ tt_status tt_round(int32_t batch, const tt_train* t_in, const tt_train* t_out, d
  *      step that ends at bond j (the unfolding of output core j-1 in the
  *      coordinates of F at bond j): vector c in column c of v[j] (r_j x r_j,
  *      column-major, leading dimension r_j), s[j] descending, zeros beyond
- *      the rank.
- * Caller-owned device buffers: g[j], f[j], v[j] of in->cap[j]^2 doubles,
- * s[j] of in->cap[j] doubles, valid and rank of d+1 int32 each. */
+ *      the rank (not recorded for the folded bond 1).
+ * Caller-owned device buffers: g[j], f[j], v[j] of c_j^2 doubles and s[j]
+ * of c_j doubles with c_j = in->cap[j] (c_1 = min(in->cap[1], n[0]): a
+ * bond 1 of rank above n[0] is folded), valid and rank of d+1 int32 each. */
 typedef struct {
   double* g[TT_MAXD];
   double* f[TT_MAXD];

@@ -82,9 +82,9 @@ class ComposedGradient:
         # with a checkpoint per step the forward also keeps each step's
         # rounded and normalised predictive, likelihood and update product
         # (a few MB per filter and step), so the reverse sweep recomputes only
-        # the prediction product, not the two roundings; the prediction
-        # rounding also records its right-part Grams and factors, which its
-        # adjoint would otherwise recompute
+        # the prediction product, not the two roundings; both roundings also
+        # record the Grams, factors and SVDs their adjoints would otherwise
+        # recompute
         self.tape = bool(tape) and self.C == 1
         self.torch = torch
         self.specs = list(specs)
@@ -132,8 +132,8 @@ class ComposedGradient:
 
     def _step(self, k, p_prev, record=False):
         """Recompute step k from the filtering density p_prev (None at k = 0).
-        record: keep the prediction rounding's right-to-left Grams and factors
-        (st.xtape) for its adjoint."""
+        record: keep the records of the prediction and update roundings
+        (st.xtape, st.htape) for their adjoints."""
         st = _Step()
         st.xtape = None
         if k == 0:
@@ -153,7 +153,8 @@ class ComposedGradient:
         log_c = self.torch.zeros(self.Bn, dtype=self.torch.float64, device="cuda")
         B.tt_update(self.grids, self.meas, self._zk(k), pt, st.h, self.lik_rank_cap, log_c)
         st.log_c = log_c
-        st.hr = self._round(st.h)
+        st.htape = B.RoundTape(st.h) if record else None
+        st.hr = self._round(st.h, st.htape)
         self._normalise(st.hr)         # hr now holds P_k
         return st
 
@@ -219,7 +220,7 @@ class ComposedGradient:
         B.tt_normalize_adjoint(st.hr, pbar, None, hrbar)
         # HR = round(H)
         hbar = _like(st.h)
-        B.tt_round_adjoint(st.h, st.hr, hrbar, hbar)
+        B.tt_round_adjoint(st.h, st.hr, hrbar, hbar, tape=st.htape.structs if st.htape is not None else None)
         # log c_k = log(sum(H) delta): the log-mass adjoint of H with weight one
         cbar = _like(st.h)
         one = self.torch.ones(self.Bn, dtype=self.torch.float64, device="cuda")

@@ -375,15 +375,18 @@ def tt_update(grids: Sequence[Grid], meas: Sequence[Meas], z, p_pred: Sequence[D
 class RoundTape:
     """Record of an FP64 rounding's sweeps, one per filter: for each bond j
     the right-part Gram and its pivoted Cholesky factor, the singular vectors
-    of the left-to-right step ending there (cap[j] x cap[j] doubles each, cap
-    of the rounding's input) and its singular values, a flag set and the
-    factor's rank per bond, all in device memory."""
+    of the left-to-right step ending there (c_j x c_j doubles each, c_j the
+    input's cap[j], min(cap[1], n[0]) for bond 1) and its singular values, a
+    flag set and the factor's rank per bond, all in device memory."""
 
     def __init__(self, t_in: Sequence[DeviceTT]):
         torch = _torch()
         self.d = t_in[0].d
-        self.sizes = [[t.cap[j] * t.cap[j] if 1 <= j < self.d else 0 for j in range(self.d)] for t in t_in]
-        caps = [[t.cap[j] if 1 <= j < self.d else 0 for j in range(self.d)] for t in t_in]
+        # bond 1 of rank above n[0] is folded with the first core: its record
+        # is n[0] x n[0] at most
+        caps = [[(min(t.cap[1], t.n[0]) if j == 1 else t.cap[j]) if 1 <= j < self.d else 0 for j in range(self.d)]
+                for t in t_in]
+        self.sizes = [[c * c for c in cc] for cc in caps]
         per = [3 * sum(sz) + sum(c) for sz, c in zip(self.sizes, caps)]
         self.buf = torch.zeros(max(sum(per), 1), dtype=torch.float64, device="cuda")
         self.valid = torch.zeros((len(t_in), self.d + 1), dtype=torch.int32, device="cuda")

@@ -1117,12 +1117,15 @@ __global__ void __launch_bounds__(256) round_tape_kernel(const DevTT* __restrict
 // Record of the left-to-right step k: the Jacobi singular vectors (column c
 // = vector c, rq[k+1] components in the coordinates of the bond-(k+1)
 // factor) and values of B_k, compacted to r_{k+1} x r_{k+1} column-major,
-// zeros beyond the pivoted-Cholesky rank.  One workgroup per filter.
-__global__ void __launch_bounds__(256) round_tape_svd_kernel(const RoundScratch* __restrict__ drs, int k,
+// zeros beyond the pivoted-Cholesky rank; not for a first core folded into
+// bond 1.  One workgroup per filter.
+__global__ void __launch_bounds__(256) round_tape_svd_kernel(const DevTT* __restrict__ din,
+                                                             const RoundScratch* __restrict__ drs, int k,
                                                              const tt_round_tape* __restrict__ tapes) {
   const int f = blockIdx.x;
   const RoundScratch& s = drs[f];
   const tt_round_tape& t = tapes[f];
+  if (k == 0 && merge_bond1(din[f], s)) return;  // the folded first core: its adjoint works from S_0
   const int R = s.ri[k + 1], rq = s.rq[k + 1], nc = s.misc[0], gc = s.gcap;
   double* v = t.v[k + 1];
   double* sg = t.s[k + 1];
@@ -1200,7 +1203,7 @@ static tt_status round_launch(const RoundShape& sh, const RoundBufs& rb, double 
     TT_TRY((launch_pchol<Acc>(FLrPchol{c}, B, sh.gcap, st)));
     TT_TRY((launch_jacobi(FLrJacobi{c}, B, st)));
     if (dtape) {
-      hipLaunchKernelGGL(round_tape_svd_kernel, dim3(B), dim3(256), 0, st, rb.drs, k, dtape);
+      hipLaunchKernelGGL(round_tape_svd_kernel, dim3(B), dim3(256), 0, st, rb.din, rb.drs, k, dtape);
       TTG_LAUNCH_CHECK("round_tape_svd_kernel");
     }
     hipLaunchKernelGGL(round_select_kernel, dim3(B), dim3(256), 0, st, rb.dout, rb.drs, k, max_rank, forced, fstride);
@@ -1831,8 +1834,8 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
         set_error("tt_round_adjoint: null record buffer (filter %d, bond 1)", b);
         return TT_ERR_ARG;
       }
-      const long long c2 = (long long)a[b].cap[1] * a[b].cap[1];
-      R.regions.push_back({tape[b].f[1], c2});
+      const long long c1 = std::min(a[b].cap[1], a[b].n[0]);
+      R.regions.push_back({tape[b].f[1], c1 * c1});
     }
   for (int b = 0; b < batch; ++b)
     for (int j = 1; j < d; ++j)
@@ -1841,7 +1844,8 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
           set_error("tt_round_adjoint: null record buffer (filter %d, bond %d)", b, j);
           return TT_ERR_ARG;
         }
-        const long long c2 = (long long)a[b].cap[j] * a[b].cap[j];
+        const long long cj = j == 1 ? std::min(a[b].cap[1], a[b].n[0]) : a[b].cap[j];
+        const long long c2 = cj * cj;
         R.regions.push_back({tape[b].g[j], c2});
         R.regions.push_back({tape[b].f[j], c2});
         if (taped_svd(b, j - 1)) {
@@ -1850,7 +1854,7 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
             return TT_ERR_ARG;
           }
           R.regions.push_back({tape[b].v[j], c2});
-          R.regions.push_back({tape[b].s[j], (long long)a[b].cap[j]});
+          R.regions.push_back({tape[b].s[j], cj});
         }
         F[b].c[j - 1].G = tape[b].g[j];    // G of bond j, leading dimension r_j
         F[b].c[j - 1].fac = tape[b].f[j];  // its factor

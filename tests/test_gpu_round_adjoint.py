@@ -96,10 +96,10 @@ def test_round_adjoint_with_forward_record(B, cases):
     for (a, ranks, t, sbar, valid), o0, t0, t1 in zip(outs1, outs0, AB0, AB1):
         d = len(a)
         # every bond's Gram and factor is recorded (bond 1 folded with the
-        # first core as such), and every left-to-right SVD
+        # first core as such), and every left-to-right SVD of a tall unfolding
         want = [0] + [1 | 4] * (d - 1) + [0]
         if a[0].shape[2] > a[0].shape[1]:
-            want[1] = 2 | 4
+            want[1] = 2  # its adjoint works from S_0: no SVD record
         assert list(valid) == want, valid
         ab0, _, _ = t0.fetch()
         ab1, ls, st = t1.fetch()
