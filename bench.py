@@ -283,6 +283,46 @@ def interp_bench(binding, batch=256, d=6, n=128, r=16, calls=10):
                          "frac": round(gbs / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_call": byts}}
 
 
+def conv_bench(binding, runner, wl, batch=32, r=16, calls=5):
+    """The materialised prediction (tt_predict: per-core convolution of the
+    kernel TT with the density TT, ranks multiplied, not rounded) at the
+    metric workload's shapes (d=6, N=128, FP32, density rank r, its kernel
+    TT): kernel time per batched call from the library's launch events and
+    the HBM rate of its algorithmic bytes (the product written once, the
+    kernel and density cores read once)."""
+    import torch
+    specs, _, _ = wl.make_batch("range6d_n128_c16", batch=1, steps=1)
+    kern, _, _ = runner.build_kernels(specs, binding.F32)
+    K = kern[0]
+    d, n = specs[0].d, specs[0].n
+    pc = [1] + [r] * (d - 1) + [1]
+    P = binding.DeviceTT.batch([[n] * d] * batch, [pc] * batch, binding.F32)
+    gen = torch.Generator(device="cuda").manual_seed(20250114)
+    for t in P:
+        t.cores.uniform_(generator=gen)
+        t.ranks.copy_(torch.tensor(pc, dtype=torch.int32))
+    kr = K.ranks.cpu().numpy().tolist()
+    xc = [a * b for a, b in zip(K.cap, pc)]
+    X = binding.DeviceTT.batch([[n] * d] * batch, [xc] * batch, binding.F32)
+    binding.tt_predict([K] * batch, P, X)  # warm
+    torch.cuda.synchronize()
+    binding.profile_begin(("conv",))
+    for _ in range(calls):
+        binding.tt_predict([K] * batch, P, X)
+    torch.cuda.synchronize()
+    kms, kn = binding.profile_end()["conv"][:2]
+    ms = kms / max(kn, 1)
+    xr = [a * b for a, b in zip(kr, pc)]
+    out_elems = sum(xr[k] * n * xr[k + 1] for k in range(d))
+    in_elems = sum(pc[k] * n * pc[k + 1] for k in range(d)) + sum(kr[k] * K.n[k] * kr[k + 1] for k in range(d))
+    byts = 4 * batch * (out_elems + in_elems)
+    gbs = byts / (ms * 1e-3) / 1e9
+    return {"workload": f"range6d_n128_c16 densities (d={d}, N={n}, rank {r}) times its kernel TT, ranks {xr}",
+            "filters": batch, "precision": "fp32", "kernel": "conv_kernel<float>", "kernel_ms_per_call": round(ms, 4),
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(gbs / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_call": byts}}
+
+
 def interp_cpu_baseline(d=6, n=128, r=16):
     """The oracle's interpolation on one filter of the interp_bench shapes
     (part of the CPU baseline leg)."""
@@ -325,9 +365,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--profile-steps", type=int, default=2)
     ap.add_argument("--no-grad", action="store_true", help="skip the gradient timing")
-    ap.add_argument("--no-einsum", action="store_true", help="skip the Einstein-summation prediction timing")
-    ap.add_argument("--einsum-only", action="store_true",
-                    help="only time the Einstein-summation prediction and the interpolation onto a new grid")
+    ap.add_argument("--no-einsum", action="store_true",
+                    help="skip the Einstein-summation, interpolation and materialised-convolution timings")
+    ap.add_argument("--extra-only", action="store_true",
+                    help="only time the Einstein-summation prediction, the interpolation onto a new grid and the "
+                         "materialised convolution")
     ap.add_argument("--grad-steps", type=int, default=50)
     ap.add_argument("--grad-batch", type=int, default=32)
     ap.add_argument("--grad-only", action="store_true",
@@ -358,9 +400,9 @@ def main():
         print(json.dumps({"copy_bytes_read": nel * 4, "copy_bytes_written": nel * 4, "copies": 5}), flush=True)
         return
 
-    if args.einsum_only:
-        print(json.dumps({"einsum_predict": einsum_bench(binding), "interpolate": interp_bench(binding)}),
-              flush=True)
+    if args.extra_only:
+        print(json.dumps({"einsum_predict": einsum_bench(binding), "interpolate": interp_bench(binding),
+                          "conv_hbm": conv_bench(binding, runner, wl)}), flush=True)
         return
     if args.grad_only:
         from paper_2501_07942_amd import grad as G
@@ -427,6 +469,8 @@ def main():
         out["einsum_predict"] = einsum_bench(binding)
         torch.cuda.empty_cache()
         out["interpolate"] = interp_bench(binding)
+        torch.cuda.empty_cache()
+        out["conv_hbm"] = conv_bench(binding, runner, wl)
         torch.cuda.empty_cache()
     if not args.no_plain:
         plain = run_batch(None, runner, binding, wl, args.workload, 1, args.steps, args.warmup, binding.F64)

@@ -76,8 +76,10 @@ __global__ void __launch_bounds__(256) conv_kernel(const DevTT* __restrict__ ker
     T acc[CONV_ROWS];
 #pragma unroll
     for (int r = 0; r < CONV_ROWS; ++r) acc[r] = (T)0;
-    // output i uses Ppad[front + i + 2h - tm] for tap tm (offset m = tm - h)
-    for (int tm0 = 0; tm0 < taps_pad; tm0 += CONV_TB) {
+    // output i uses Ppad[front + i + 2h - tm] for tap tm (offset m = tm - h);
+    // whole blocks of CONV_TB taps, then the remaining taps one by one
+    const int tfull = taps / CONV_TB * CONV_TB;
+    for (int tm0 = 0; tm0 < tfull; tm0 += CONV_TB) {
       T kv[CONV_TB];
 #pragma unroll
       for (int u = 0; u < CONV_TB; ++u) kv[u] = Ks[(tm0 + u) * rk1 + a2];
@@ -91,10 +93,18 @@ __global__ void __launch_bounds__(256) conv_kernel(const DevTT* __restrict__ ker
 #pragma unroll
         for (int r = 0; r < CONV_ROWS; ++r) acc[r] += kv[u] * w[r - u + CONV_TB - 1];
     }
+    for (int tm = tfull; tm < taps; ++tm) {
+      const T kvt = Ks[tm * rk1 + a2];
+      const int base = front + i0 + 2 * h - tm;
+#pragma unroll
+      for (int r = 0; r < CONV_ROWS; ++r) acc[r] += kvt * Ps[(base + r) * rp1 + b2];
+    }
+    // the product is far larger than the caches and is read back by the
+    // rounding's own sweep: stream it past them
 #pragma unroll
     for (int r = 0; r < CONV_ROWS; ++r) {
       const int i = i0 + r;
-      if (i < n) xc[(long long)i * R1 + j] = acc[r];
+      if (i < n) __builtin_nontemporal_store(acc[r], &xc[(long long)i * R1 + j]);
     }
   }
 }
