@@ -3054,10 +3054,10 @@ tt_status tt_predict_einsum(int32_t batch, const tt_train* tpm, const tt_train* 
     double** zn = (zc == dz0) ? dz1 : dz0;
     if (f64) {
       hipLaunchKernelGGL((einsum_y_kernel<double>), gy, dim3(256), 0, st, dt, dp, zc, dy, k);
-      hipLaunchKernelGGL((einsum_z_kernel<double>), gz, dim3(256), 0, st, dt, dp, dy, zn, k);
+      hipLaunchKernelGGL((einsum_z_kernel<double>), gz, dim3(64 * EZ_WAVES), 0, st, dt, dp, dy, zn, k);
     } else {
       hipLaunchKernelGGL((einsum_y_kernel<float>), gy, dim3(256), 0, st, dt, dp, zc, dy, k);
-      hipLaunchKernelGGL((einsum_z_kernel<float>), gz, dim3(256), 0, st, dt, dp, dy, zn, k);
+      hipLaunchKernelGGL((einsum_z_kernel<float>), gz, dim3(64 * EZ_WAVES), 0, st, dt, dp, dy, zn, k);
     }
     TTG_LAUNCH_CHECK("einsum_y_kernel / einsum_z_kernel");
     zc = zn;

@@ -62,17 +62,19 @@ __global__ void __launch_bounds__(256) einsum_y_kernel(const DevTT* __restrict__
 }
 
 // Z'(a, c) = sum over the contiguous (i, b) of T_{d+k}(a, i, b) Y(c, i, b),
-// stored transposed (Zt[c][a]) for the next Y pass.  A workgroup owns EZ_ROWS rows a of T (four per wavefront) and EZ_CB
+// stored transposed (Zt[c][a]) for the next Y pass.  A workgroup of EZ_WAVES
+// wavefronts owns EZ_ROWS rows a of T (four per wavefront) and EZ_CB
 // entries c; chunks of EZ_TC columns (i, b) of those Y rows are staged in
 // LDS and every lane multiplies its four T values per row against them, so
 // T is streamed once, coalesced, and Y once per row block.  Each entry sums
 // its lanes' partial sums by a shuffle tree (the order does not depend on
 // the batch).
-#define EZ_ROWS 16
+#define EZ_WAVES 8
+#define EZ_ROWS (4 * EZ_WAVES)
 #define EZ_CB 16
 #define EZ_TC 256
 template <typename E>
-__global__ void __launch_bounds__(256) einsum_z_kernel(const DevTT* __restrict__ tt, const DevTT* __restrict__ pp,
+__global__ void __launch_bounds__(64 * EZ_WAVES) einsum_z_kernel(const DevTT* __restrict__ tt, const DevTT* __restrict__ pp,
                                                        double* const* __restrict__ yin,
                                                        double* const* __restrict__ zout, int k) {
   const int f = blockIdx.z;
@@ -93,7 +95,7 @@ __global__ void __launch_bounds__(256) einsum_z_kernel(const DevTT* __restrict__
 #pragma unroll
     for (int c = 0; c < EZ_CB; ++c) acc[q][c] = 0.0;
   for (int t0 = 0; t0 < len; t0 += EZ_TC) {
-    for (int e = threadIdx.x; e < EZ_CB * EZ_TC; e += 256) {
+    for (int e = threadIdx.x; e < EZ_CB * EZ_TC; e += blockDim.x) {
       const int c = e / EZ_TC, j = e - (e / EZ_TC) * EZ_TC;
       const int cc = c0 + c, t = t0 + j;
       Ys[c][j] = (cc < rp0 && t < len) ? y[(long long)cc * len + t] : 0.0;
@@ -146,9 +148,17 @@ __global__ void __launch_bounds__(256) einsum_out_kernel(const DevTT* __restrict
   E* oc = core_ptr<E>(O, k);
   if (k < d - 1) {
     const long long tot = (long long)r0 * n * r1;
-    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < tot;
-         e += (long long)gridDim.x * blockDim.x)
-      oc[e] = tc[e];
+    const long long gid = blockIdx.x * (long long)blockDim.x + threadIdx.x, gstride = (long long)gridDim.x * blockDim.x;
+    long long done = 0;
+    if (((reinterpret_cast<unsigned long long>(tc) | reinterpret_cast<unsigned long long>(oc)) & 15) == 0) {
+      constexpr int U = 16 / (int)sizeof(E);  // elements per 16-byte unit
+      const long long nv = tot / U;
+      const uint4* s4 = reinterpret_cast<const uint4*>(tc);
+      uint4* d4 = reinterpret_cast<uint4*>(oc);
+      for (long long v = gid; v < nv; v += gstride) d4[v] = s4[v];
+      done = nv * U;
+    }
+    for (long long e = done + gid; e < tot; e += gstride) oc[e] = tc[e];
   } else {
     // one wavefront per row (a, i), lanes over b, a shuffle tree per row
     const double* z = zin[f];
