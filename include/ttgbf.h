@@ -361,7 +361,10 @@ size_t tt_normalize_moments_workspace(int32_t batch, const tt_train* t);
  * 6e-6 of the largest at a bond are left out of the eigenvector adjoint
  * (rounding noise there exceeds their signal) and discarded ones below 1e-9
  * count as null space.  The call reads the ranks to the host once and is
- * synchronous (it returns after the work is done).  tape (nullable): the
+ * synchronous (it returns after the work is done); its job tables go
+ * through one page-locked host staging area per process (allocated on
+ * first use, at least 8 MB, grown when needed; calls from several threads
+ * take turns on it).  tape (nullable): the
  * record tt_round_taped wrote for this rounding, read only; its Grams,
  * factors and the singular vectors of the tall unfoldings whose right
  * factor it holds are used instead of being recomputed.  Workspace:
