@@ -100,6 +100,15 @@ def run_batch(B, runner, binding, wl, name, batch, steps, warmup, precision, pro
             "status": st, "total": total, "graph": graph, "autotune": tune}
 
 
+def _shape_of(specs):
+    """d, N and rank cap of the filters actually run (lists when they differ
+    per filter, as in a ragged batch)."""
+    def one(vals):
+        vals = sorted(set(int(v) for v in vals))
+        return vals[0] if len(vals) == 1 else vals
+    return {"d": one(s.d for s in specs), "N": one(s.n for s in specs), "rank_cap": one(s.cap for s in specs)}
+
+
 def cpu_baseline(wl, steps=6, warm=3):
     """The FP64 oracle on a bounded sample: one filter of the same workload,
     `warm` untimed full steps after step 0 (ranks reach the cap), then
@@ -455,7 +464,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic (seeded random-walk trajectories and range/linear measurements)",
-        "config": {"workload": args.workload, "d": 6, "N": 128, "rank_cap": 16, "filters": B,
+        "config": {"workload": args.workload, **_shape_of(main_res["specs"]), "filters": B,
                    "precision": "fp32 bulk, fp64 Gram/pivoted-Cholesky/Jacobi, fp64 log-normaliser",
                    "failed_filters": int((main_res["status"] != 0).sum()),
                    "workspace_GB": round(main_res["run"].ws.numel() * main_res["run"].ws.element_size() / 1e9, 2)},

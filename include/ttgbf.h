@@ -106,6 +106,12 @@ size_t tt_train_elems(int32_t d, const int32_t* n, const int32_t* cap);
 /* Message of the last host-side error in this thread (never NULL). */
 const char* tt_last_error(void);
 
+/* Static description of a tt_status return code (never NULL). */
+const char* tt_status_string(int32_t code);
+
+/* Static description of a combination of TT_STATUS_* device bits (never NULL). */
+const char* tt_device_status_string(int32_t bits);
+
 /* Library version string. */
 const char* tt_version(void);
 
@@ -544,6 +550,35 @@ tt_status tt_filter_graph_create(int32_t batch, const tt_filter_spec* specs, con
                                  tt_graph** out);
 tt_status tt_filter_graph_launch(tt_graph* graph, void* stream);
 void tt_filter_graph_destroy(tt_graph* graph);
+
+/* ---------------------------------------------------------------------
+ * tt_filter_state -- save or restore the filtering densities that a
+ * tt_filter_run workspace carries from one call to the next: after steps
+ * 0..k of the recursion (Alg. 2), filter b's state is its filtering density
+ * P_{k|k} as a TT (ranks, FP64 log-scale and cores); nothing else persists
+ * between calls.
+ *   direction TT_STATE_SAVE: ws -> trains[b]; TT_STATE_LOAD: trains[b] -> ws.
+ *   specs, kernels, n_kernels, precision: exactly those of the tt_filter_run
+ *              calls the workspace serves (they fix its layout); ws, ws_bytes
+ *              that workspace (tt_filter_run_workspace bytes).
+ *   trains[b]  caller-owned device TT of dtype `precision`, d and modes of
+ *              filter b's grid, capacities >= 1 (cap[j] >= spec.cap suffices).
+ * A load followed by tt_filter_run with k_begin = k+1 continues the
+ * recursion bitwise as an uninterrupted run would, in the same or in a fresh
+ * workspace (log_c of steps 0..k must then already be in log_c_dev for the
+ * log-likelihood sum).  Save clears the train's status word; a rank that does
+ * not fit the destination's capacity copies nothing and sets
+ * TT_STATUS_CAPACITY on the train's status word (both directions).  The
+ * caller's status_dev of the run is not part of the state.  Asynchronous on
+ * stream after a synchronous descriptor upload.  Errors: TT_ERR_ARG,
+ * TT_ERR_SHAPE (d or modes differ from the grids), TT_ERR_WORKSPACE,
+ * TT_ERR_HIP.
+ * --------------------------------------------------------------------- */
+#define TT_STATE_SAVE 0
+#define TT_STATE_LOAD 1
+tt_status tt_filter_state(int32_t batch, const tt_filter_spec* specs, const tt_train* kernels, int32_t n_kernels,
+                          int32_t precision, int32_t direction, const tt_train* trains, void* ws, size_t ws_bytes,
+                          void* stream);
 
 /* ---------------------------------------------------------------------
  * tt_autotune_prediction -- time the launch shapes of the matrix-core

@@ -202,6 +202,62 @@ def tt_dot(a, b):
     return float(acc[0, 0])
 
 
+def marginal(tt, keep):
+    """Sum of a TT over every index whose axis is not in ``keep``: a dense
+    array over the kept axes, in ascending axis order (the 'sum' of Sec. 4.1
+    taken over some axes only).  Cores of summed axes are reduced to their
+    slice sums; cores of kept axes keep their grid index."""
+    keep = sorted(set(int(k) for k in keep))
+    acc = np.ones((1, 1))                  # (kept multi-index, rank)
+    shape = []
+    for k, g in enumerate(tt):
+        if k in keep:
+            acc = np.einsum("ma,aib->mib", acc, g).reshape(-1, g.shape[2])
+            shape.append(g.shape[1])
+        else:
+            acc = acc @ g.sum(axis=1)
+    return acc.reshape(shape) if shape else float(acc[0, 0])
+
+
+def values(tt, idx):
+    """A(i) at the grid multi-indices in the rows of ``idx`` (count x d), as
+    products of core slices (Sec. 3.1, eq. ttd_exact) taken for all rows at
+    once."""
+    idx = np.asarray(idx, dtype=np.int64)
+    v = np.ones((idx.shape[0], 1))
+    for k, g in enumerate(tt):
+        v = np.einsum("sa,asb->sb", v, g[:, idx[:, k], :])
+    return v[:, 0]
+
+
+def sample(tt, count, rng):
+    """Draw ``count`` grid multi-indices from the distribution proportional
+    to A (negative conditional weights, which truncation can leave in a
+    density, count as zero), one axis after the other from its conditional
+    given the axes already drawn.  Returns (idx [count, d], q [count]) with q
+    the probability with which each drawn index was chosen; for a
+    non-negative A, q = A(i) / sum(A)."""
+    d = len(tt)
+    right = [None] * (d + 1)
+    right[d] = np.ones((1,))
+    for k in range(d - 1, -1, -1):
+        right[k] = tt[k].sum(axis=1) @ right[k + 1]
+    left = np.ones((count, 1))
+    idx = np.zeros((count, d), dtype=np.int64)
+    q = np.ones(count)
+    for k, g in enumerate(tt):
+        w = np.einsum("sa,aib,b->si", left, g, right[k + 1])
+        w = np.maximum(w, 0.0)
+        w = w / w.sum(axis=1, keepdims=True)
+        cdf = np.cumsum(w, axis=1)
+        u = rng.random(count)[:, None]
+        pick = np.minimum((u > cdf).sum(axis=1), g.shape[1] - 1)
+        idx[:, k] = pick
+        q *= w[np.arange(count), pick]
+        left = np.einsum("sa,asb->sb", left, g[:, pick, :])
+    return idx, q
+
+
 def scale(tt, c):
     """Multiply a TT by a scalar (Sec. 4.1 'mrdivide' divides)."""
     out = [g.copy() for g in tt]

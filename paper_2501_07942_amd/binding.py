@@ -20,6 +20,7 @@ MAXD = 16
 F64, F32 = 0, 1
 OK, ERR_ARG, ERR_SHAPE, ERR_WORKSPACE, ERR_HIP = 0, 1, 2, 3, 4
 STATUS_NONPOSITIVE, STATUS_NONFINITE, STATUS_CAPACITY = 1, 2, 4
+STATE_SAVE, STATE_LOAD = 0, 1
 
 
 class Grid(C.Structure):
@@ -113,6 +114,9 @@ def _load():
         "tt_autotune_prediction": (I, [I, P, P, I, P, I, I, I, P, P, P, P, P, S, P, I, I, C.POINTER(C.c_int32),
                                        C.POINTER(C.c_float)]),
         "tt_filter_graph_destroy": (None, [P]),
+        "tt_filter_state": (I, [I, P, P, I, I, I, P, P, S, P]),
+        "tt_status_string": (C.c_char_p, [I]),
+        "tt_device_status_string": (C.c_char_p, [I]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -134,7 +138,7 @@ EXPORTED = ("tt_train_elems", "tt_last_error", "tt_version", "tt_kernel_build_wo
             "tt_likelihood_adjoint_workspace", "tt_likelihood_adjoint", "tt_adjoint_axpy",
             "tt_adjoint_inner", "tt_align_signs", "tt_round_taped", "tt_predict_einsum_workspace",
             "tt_predict_einsum", "tt_grid_redesign_workspace", "tt_grid_redesign", "tt_interpolate_workspace",
-            "tt_interpolate")
+            "tt_interpolate", "tt_filter_state", "tt_status_string", "tt_device_status_string")
 
 PREDICT_DIRECT, PREDICT_FFT, PREDICT_UNFUSED, PREDICT_DIRECT_VALU = 0, 1, 2, 3
 
@@ -168,7 +172,15 @@ def profile_end():
 
 def _check(st: int, what: str):
     if st != OK:
-        raise TTError(f"{what} failed ({st}): {LIB.tt_last_error().decode()}")
+        raise TTError(f"{what} failed ({LIB.tt_status_string(st).decode()}): {LIB.tt_last_error().decode()}")
+
+
+def status_string(code: int) -> str:
+    return LIB.tt_status_string(int(code)).decode()
+
+
+def device_status_string(bits: int) -> str:
+    return LIB.tt_device_status_string(int(bits)).decode()
 
 
 def _torch():
@@ -659,6 +671,31 @@ class FilterRun:
                                rf.data_ptr() if rf is not None else None, self.ws.data_ptr(),
                                self.ws.numel(), _stream())
         _check(st, "tt_filter_run")
+
+    def _state(self, trains: Sequence[DeviceTT], direction: int):
+        if len(trains) != self.B:
+            raise TTError("one train per filter")
+        _check(LIB.tt_filter_state(self.B, self.specs, self.karr, len(self.kernels), self.precision, direction,
+                                   _arr([t.struct() for t in trains]), self.ws.data_ptr(), self.ws.numel(),
+                                   _stream()), "tt_filter_state")
+
+    def state_trains(self) -> List[DeviceTT]:
+        """Trains that can hold every filter's state (the run's rank caps)."""
+        specs = list(self.specs)
+        return DeviceTT.batch([[s.grid.n[k] for k in range(self.d)] for s in specs],
+                              [[1] + [int(s.cap)] * (self.d - 1) + [1] for s in specs], self.precision)
+
+    def save_state(self, trains: Optional[Sequence[DeviceTT]] = None) -> List[DeviceTT]:
+        """tt_filter_state(SAVE): the filtering densities after the last step
+        run, one train per filter."""
+        trains = list(trains) if trains is not None else self.state_trains()
+        self._state(trains, STATE_SAVE)
+        return trains
+
+    def load_state(self, trains: Sequence[DeviceTT]):
+        """tt_filter_state(LOAD): make this workspace continue from the given
+        filtering densities (then call with k_begin = the next step)."""
+        self._state(list(trains), STATE_LOAD)
 
     def autotune(self, z, warmup_steps: int = 3, rounds: int = 2) -> dict:
         """tt_autotune_prediction on this batch: times each prediction launch

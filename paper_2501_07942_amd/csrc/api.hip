@@ -4386,6 +4386,7 @@ struct RunPlan {
   bool any_range = false;
   int n0max = 1, n1max = 1, gcap = 1, splits = 1;
   int d = 0;
+  DevTT* dS = nullptr;               // source and destination tables of tt_filter_state
 };
 
 static tt_status run_plan(int32_t batch, const tt_filter_spec* specs, const tt_train* kernels, int32_t n_kernels,
@@ -4641,6 +4642,7 @@ static tt_status run_plan(int32_t batch, const tt_filter_spec* specs, const tt_t
   p.mspf = (long long)moments_scratch_per_filter(d, p.mrcap);
   p.mscr = ar.take<double>((size_t)batch * p.mspf);
   p.lmass = ar.take<double>((size_t)batch);
+  p.dS = ar.take<DevTT>((size_t)2 * batch);
   return TT_OK;
 }
 
@@ -4909,6 +4911,94 @@ void tt_filter_graph_destroy(tt_graph* g) {
   hipGraphExecDestroy(g->exec);
   hipGraphDestroy(g->graph);
   delete g;
+}
+
+
+tt_status tt_filter_state(int32_t batch, const tt_filter_spec* specs, const tt_train* kernels, int32_t n_kernels,
+                          int32_t precision, int32_t direction, const tt_train* trains, void* ws, size_t ws_bytes,
+                          void* stream) {
+  using namespace ttg;
+  if (!kernels || n_kernels < 1 || !trains || !ws || (direction != TT_STATE_SAVE && direction != TT_STATE_LOAD)) {
+    set_error("tt_filter_state: null pointer or bad direction");
+    return TT_ERR_ARG;
+  }
+  Arena ar(ws, ws_bytes);
+  RunPlan p;
+  TT_TRY(run_plan(batch, specs, kernels, n_kernels, precision, nullptr, ar, p));
+  if (!ar.fits()) {
+    set_error("tt_filter_state: workspace too small (%zu < %zu)", ws_bytes, ar.used);
+    return TT_ERR_WORKSPACE;
+  }
+  std::vector<DevTT> tab(2 * (size_t)batch);
+  for (int b = 0; b < batch; ++b) {
+    TT_TRY(check_train(&trains[b], "tt_filter_state train", precision));
+    const tt_train& t = trains[b];
+    if (t.d != p.d) {
+      set_error("tt_filter_state: train %d has d=%d, the run d=%d", b, t.d, p.d);
+      return TT_ERR_SHAPE;
+    }
+    for (int k = 0; k < t.d; ++k)
+      if (t.n[k] != specs[b].grid.n[k]) {
+        set_error("tt_filter_state: train %d mode %d is %d, the grid's %d", b, k, t.n[k], specs[b].grid.n[k]);
+        return TT_ERR_SHAPE;
+      }
+    const DevTT w = p.vP[b], c = make_dev(t);
+    tab[b] = direction == TT_STATE_SAVE ? w : c;
+    tab[batch + b] = direction == TT_STATE_SAVE ? c : w;
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  TT_TRY(upload(p.dS, tab, st));
+  long long most = 1;
+  for (int b = 0; b < batch; ++b) most = std::max(most, (long long)elems_of(p.d, p.vP[b].n, p.vP[b].cap));
+  const dim3 grid(std::max(1, std::min(64, cdiv(most, 256 * 8))), batch);
+  if (precision == TT_F64)
+    hipLaunchKernelGGL((copy_tt_kernel<double>), grid, dim3(256), 0, st, p.dS, p.dS + batch,
+                       direction == TT_STATE_LOAD ? 1 : 0);
+  else
+    hipLaunchKernelGGL((copy_tt_kernel<float>), grid, dim3(256), 0, st, p.dS, p.dS + batch,
+                       direction == TT_STATE_LOAD ? 1 : 0);
+  TTG_LAUNCH_CHECK("copy_tt_kernel");
+  return TT_OK;
+}
+
+const char* tt_status_string(int32_t code) {
+  switch (code) {
+    case TT_OK:
+      return "TT_OK: success";
+    case TT_ERR_ARG:
+      return "TT_ERR_ARG: null pointer, non-positive size or bad enumeration value";
+    case TT_ERR_SHAPE:
+      return "TT_ERR_SHAPE: inconsistent dimension, modes, ranks or capacities";
+    case TT_ERR_WORKSPACE:
+      return "TT_ERR_WORKSPACE: workspace smaller than its query returns";
+    case TT_ERR_HIP:
+      return "TT_ERR_HIP: a HIP call failed (tt_last_error holds the message)";
+    default:
+      return "unknown tt_status code";
+  }
+}
+
+const char* tt_device_status_string(int32_t bits) {
+  switch (bits) {
+    case 0:
+      return "ok";
+    case TT_STATUS_NONPOSITIVE:
+      return "TT_STATUS_NONPOSITIVE: a mass or normaliser c_k was not positive";
+    case TT_STATUS_NONFINITE:
+      return "TT_STATUS_NONFINITE: a NaN or infinity was met";
+    case TT_STATUS_CAPACITY:
+      return "TT_STATUS_CAPACITY: a rank needed more room than its capacity";
+    case TT_STATUS_NONPOSITIVE | TT_STATUS_NONFINITE:
+      return "TT_STATUS_NONPOSITIVE | TT_STATUS_NONFINITE";
+    case TT_STATUS_NONPOSITIVE | TT_STATUS_CAPACITY:
+      return "TT_STATUS_NONPOSITIVE | TT_STATUS_CAPACITY";
+    case TT_STATUS_NONFINITE | TT_STATUS_CAPACITY:
+      return "TT_STATUS_NONFINITE | TT_STATUS_CAPACITY";
+    case TT_STATUS_NONPOSITIVE | TT_STATUS_NONFINITE | TT_STATUS_CAPACITY:
+      return "TT_STATUS_NONPOSITIVE | TT_STATUS_NONFINITE | TT_STATUS_CAPACITY";
+    default:
+      return "unknown device status bits";
+  }
 }
 
 }  // extern "C"

@@ -649,6 +649,39 @@ __global__ void __launch_bounds__(256) convert_tt_kernel(const DevTT* __restrict
   }
 }
 
+// copy a TT into a TT of the same type and modes whose capacities may differ:
+// ranks, log-scale and the stored cores, repacked at the destination's
+// offsets.  A rank above the destination's capacity copies nothing and sets
+// TT_STATUS_CAPACITY on the status word of the caller's side (the source when
+// report_src, else the destination); otherwise the destination's status word,
+// when it has one, is cleared.
+template <typename T>
+__global__ void __launch_bounds__(256) copy_tt_kernel(const DevTT* __restrict__ src, const DevTT* __restrict__ dst,
+                                                      int report_src) {
+  const int f = blockIdx.y;
+  const DevTT &S = src[f], &D = dst[f];
+  bool fits = S.d == D.d;
+  for (int j = 0; fits && j <= S.d; ++j) fits = S.ranks[j] >= 1 && S.ranks[j] <= D.cap[j];
+  for (int k = 0; fits && k < S.d; ++k) fits = S.n[k] == D.n[k];
+  if (!fits) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) set_status(report_src ? S.status : D.status, TT_STATUS_CAPACITY);
+    return;
+  }
+  for (int k = 0; k < S.d; ++k) {
+    const long long tot = (long long)S.ranks[k] * S.n[k] * S.ranks[k + 1];
+    const T* s = core_ptr<T>(S, k);
+    T* o = core_ptr<T>(D, k);
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < tot;
+         e += (long long)gridDim.x * blockDim.x)
+      o[e] = s[e];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    for (int j = 0; j <= S.d; ++j) D.ranks[j] = S.ranks[j];
+    *D.log_scale = *S.log_scale;
+    if (D.status) *D.status = 0;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Normaliser c_k = <L, P> * delta (Sec. 2.2 eq. pmf_filtrace_b; Sec. 4.1
 // 'dot') computed from the two factors, never from their Hadamard product:

@@ -169,3 +169,20 @@ def test_redesign_and_interpolation_validation():
     f2 = (C.c_double * 4)(1.1, 0.1, -0.2, 1.1)
     st = B.LIB.tt_grid_redesign(1, 2, f2, q, 0.0, C.c_void_p(4096), C.c_void_p(4096), gi, out, ws, rneed, None)
     assert st == B.ERR_ARG
+
+
+def test_status_strings():
+    from paper_2501_07942_amd import binding as B
+    assert B.status_string(B.OK).startswith("TT_OK")
+    assert B.status_string(B.ERR_WORKSPACE).startswith("TT_ERR_WORKSPACE")
+    assert B.status_string(99) == "unknown tt_status code"
+    assert B.device_status_string(0) == "ok"
+    both = B.device_status_string(B.STATUS_NONFINITE | B.STATUS_CAPACITY)
+    assert "NONFINITE" in both and "CAPACITY" in both
+
+
+def test_filter_state_rejects_bad_direction_before_launch():
+    from paper_2501_07942_amd import binding as B
+    st = B.LIB.tt_filter_state(1, None, None, 0, B.F64, 7, None, None, 0, None)
+    assert st == B.ERR_ARG
+    assert b"tt_filter_state" in B.LIB.tt_last_error()

@@ -83,3 +83,25 @@ def test_einsum_ragged_batch_matches_oracle(B, prec):
             want = ttm.full(ref)
             got = ttm.full(cores)
             assert np.abs(got - want).max() <= tol * np.abs(want).max()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_einsum_at_the_measured_shape_matches_oracle(B, prec):
+    # the shape the throughput measurement times (d = 4, N = 64, transition
+    # rank 64, density rank 16) and densities of rank 20..40 with transition
+    # ranks that are not multiples of 32 (density-rank blocks beyond the
+    # first 16 columns of the Z pass); compared core by core with the
+    # oracle's Alg. 1, every core relative to its largest entry
+    rng = np.random.default_rng(41)
+    pr = B.F64 if prec == "f64" else B.F32
+    tol = 1e-12 if prec == "f64" else 2e-5
+    cases = (([64] * 4, [64] * 7, [16] * 3), ([24] * 3, [45, 50, 37, 61, 29], [20, 40]))
+    for n, tr, prr in cases:
+        t = rand_tt(rng, n + n, tr)
+        p = rand_tt(rng, n, prr)
+        (cores, ls, st), = run(B, [t], [p], pr)
+        assert st == 0
+        ref = ttm.einsum_predict(t, p)
+        for k in range(len(n)):
+            assert cores[k].shape == ref[k].shape
+            assert np.abs(cores[k] - ref[k]).max() <= tol * np.abs(ref[k]).max(), (n, k)

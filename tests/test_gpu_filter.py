@@ -8,6 +8,7 @@ import pytest
 
 from oracle import filters as flt
 from oracle import model as mdl
+from oracle import tt as ttm
 
 pytestmark = pytest.mark.gpu
 
@@ -164,3 +165,23 @@ def test_fp32_batch_of_64_equals_single_runs(mods):
         one, _ = runner.run_filters([specs[b]], [zs[b]], B.F32)
         assert np.array_equal(one.log_c.cpu().numpy()[0], run.log_c.cpu().numpy()[b])
         assert np.array_equal(one.mean.cpu().numpy()[0], run.mean.cpu().numpy()[b])
+
+
+@pytest.mark.parametrize("predict_mode", [0, 3], indirect=True)
+@pytest.mark.parametrize("d,n,cap,steps", [(3, 40, 8, 6), (4, 32, 8, 5)])
+def test_fp32_density_l1_against_dense_oracle(mods, d, n, cap, steps, predict_mode):
+    # the reduced-precision bar on the density itself: L1 = sum |dP| delta of
+    # the final filtering densities, reconstructed densely (N^d <= 1.1e6)
+    B, runner, wl = mods
+    specs, xs, zs = wl.make_batch("range4d", batch=1, steps=steps, d=d, n=n, cap=cap)
+    s, z = specs[0], zs[0]
+    axes = mdl.grid_axes(s.lo, s.hi, [s.n] * s.d)
+    ref = flt.run_tt_filter(axes, s.q, s.halfwidths(), s.meas(), z, s.m0, s.p0_diag, s.cap, s.eps)
+    run, _ = runner.run_filters(specs, zs, B.F32)
+    assert int(run.status.cpu()[0]) == 0
+    cores, st = run.save_state()[0].fetch_scaled()
+    assert st == 0
+    delta = mdl.cell_volume(axes)
+    l1 = float(np.abs(ttm.full(cores) - ttm.full(ref["final"])).sum()) * delta
+    print(f"fp32 d={d} N={n} cap={cap}: dense L1 of the final density {l1:.2e}")
+    assert l1 <= 1e-4

@@ -71,3 +71,16 @@ def test_tt_filter_unit_mass_and_records():
     # a nonnegative PMD cannot gain more mass than the kernel carries
     ksum = mdl.kernel_dense(s.q, axes, s.halfwidths()).sum()
     assert np.all(out["log_mpred"] <= math.log(ksum) + 1e-12)
+
+
+def test_marginal_min_is_the_smallest_dense_marginal_value():
+    # the negativity monitor of the oracle filter against the dense marginals
+    # of a TT with negative entries
+    from oracle.filters import _marginal_min
+    rng = np.random.default_rng(21)
+    rk = [1, 2, 3, 1]
+    a = [rng.standard_normal((rk[k], n, rk[k + 1])) for k, n in enumerate((4, 5, 3))]
+    f = ttm.full(a)
+    want = min(float(f.sum(axis=tuple(j for j in range(3) if j != l)).min()) for l in range(3))
+    assert abs(_marginal_min(a) - want) < 1e-12 * np.abs(f).sum()
+    assert want < 0.0

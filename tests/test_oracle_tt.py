@@ -188,3 +188,51 @@ def test_add_and_rel_diff():
     assert np.allclose(ttm.full(ttm.add(a, b)), ttm.full(a) + ttm.full(b))
     expect = np.linalg.norm(ttm.full(a) - ttm.full(b)) / np.linalg.norm(ttm.full(b))
     assert abs(ttm.rel_diff(a, b) - expect) < 1e-12 * expect
+
+
+@pytest.mark.parametrize("keep", [(), (2,), (0, 3), (1, 2), (0, 1, 2, 3)])
+def test_marginal_is_the_dense_sum_over_the_other_axes(keep):
+    rng = np.random.default_rng(11)
+    a = rand_tt(rng, [3, 4, 2, 5], [2, 3, 2])
+    f = ttm.full(a)
+    other = tuple(ax for ax in range(4) if ax not in keep)
+    want = f.sum(axis=other) if other else f
+    got = ttm.marginal(a, keep)
+    assert np.allclose(got, want, rtol=0, atol=1e-12 * np.abs(f).sum())
+
+
+def test_values_are_elements():
+    rng = np.random.default_rng(12)
+    a = rand_tt(rng, [3, 4, 2, 5], [2, 3, 2])
+    f = ttm.full(a)
+    idx = np.stack([rng.integers(0, s, 50) for s in f.shape], axis=1)
+    assert np.allclose(ttm.values(a, idx), f[tuple(idx.T)], rtol=1e-13, atol=0)
+
+
+def test_sample_probabilities_of_a_nonnegative_tt():
+    # for A >= 0 the sequential conditionals multiply to A(i) / sum(A)
+    rng = np.random.default_rng(13)
+    a = rand_tt(rng, [3, 4, 2, 5], [2, 3, 2], positive=True)
+    f = ttm.full(a)
+    idx, q = ttm.sample(a, 400, np.random.default_rng(5))
+    assert np.allclose(q, f[tuple(idx.T)] / f.sum(), rtol=1e-12, atol=0)
+
+
+def test_sample_frequencies_and_negative_weights():
+    # a 1-D train with a negative entry is never drawn there; the empirical
+    # frequencies of a small 2-D tensor approach its probabilities
+    a = [np.array([1.0, -0.5, 2.0]).reshape(1, 3, 1)]
+    idx, q = ttm.sample(a, 2000, np.random.default_rng(1))
+    assert not np.any(idx[:, 0] == 1)
+    assert np.allclose(q[idx[:, 0] == 0], 1 / 3) and np.allclose(q[idx[:, 0] == 2], 2 / 3)
+    rng = np.random.default_rng(14)
+    b = rand_tt(rng, [3, 4], [2], positive=True)
+    f = ttm.full(b)
+    p = f / f.sum()
+    idx, _ = ttm.sample(b, 200000, np.random.default_rng(2))
+    freq = np.zeros_like(p)
+    np.add.at(freq, (idx[:, 0], idx[:, 1]), 1.0)
+    freq /= idx.shape[0]
+    # binomial standard errors: every cell within 5 of them
+    se = np.sqrt(p * (1 - p) / idx.shape[0])
+    assert np.all(np.abs(freq - p) < 5 * se)
