@@ -464,8 +464,9 @@ tt_status tt_normalize_adjoint(int32_t batch, const tt_train* x, const tt_train*
  * tt_filter_run -- the whole recursion for a batch of independent filters
  * (Alg. 2 loop order with the convolution prediction; step 0 is an update
  * only; steps k >= 1 predict, round, normalise, update, round, normalise).
- * All filters share d; N, rank cap and model may differ per filter (ragged
- * batch).  Outputs (device, FP64):
+ * All filters share d and the rounding tolerance eps; N, rank cap and model
+ * may differ per filter (ragged batch: each filter's rank rule is capped at
+ * its own spec.cap).  Outputs (device, FP64):
  *   loglik_dev[b]          = sum_k log c_k
  *   log_c_dev[b*K + k]     = log c_k
  *   log_mpred_dev[b*K + k] = log predictive mass before normalisation

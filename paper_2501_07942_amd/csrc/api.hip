@@ -691,7 +691,7 @@ __global__ void round_select_kernel(const DevTT* __restrict__ O, const RoundScra
       }
     }
     r = max(r, 1);
-    r = min(r, max_rank);
+    r = min(r, s.max_rank > 0 ? min(s.max_rank, max_rank) : max_rank);
     r = min(r, max(nc, 1));
     if (r > o.cap[k + 1]) {
       r = o.cap[k + 1];
@@ -4435,6 +4435,10 @@ static tt_status run_plan(int32_t batch, const tt_filter_spec* specs, const tt_t
       set_error("tt_filter_run: filter %d: cap, kernel_cap, lik_rank_cap >= 1 and eps >= 0 required", b);
       return TT_ERR_ARG;
     }
+    if (s.eps != specs[0].eps) {
+      set_error("tt_filter_run: filter %d: every filter of a batch must share the rounding tolerance eps", b);
+      return TT_ERR_ARG;
+    }
     if (s.meas.kind != 0 && s.meas.kind != 1) {
       set_error("tt_filter_run: meas kind must be 0 or 1");
       return TT_ERR_ARG;
@@ -4538,7 +4542,10 @@ static tt_status run_plan(int32_t batch, const tt_filter_spec* specs, const tt_t
     return TT_ERR_SHAPE;
   }
   p.splits = shU.splits;
-  for (int b = 0; b < batch; ++b) plan_round_scratch(ar, vU[b], p.vP[b], f64, p.gcap, p.splits, p.vrs[b]);
+  for (int b = 0; b < batch; ++b) {
+    plan_round_scratch(ar, vU[b], p.vP[b], f64, p.gcap, p.splits, p.vrs[b]);
+    p.vrs[b].max_rank = specs[b].cap;  // ragged batches: each filter's own cap
+  }
   round_shape(batch, p.vX, p.vP, f64, p.shX);
   round_shape(batch, p.vH, p.vP, f64, p.shH);
   // fused FFT prediction (interior cores exist for d >= 3)
@@ -4652,8 +4659,8 @@ static tt_status run_steps(RunPlan& p, int B, const double* z, int zdim, int K, 
                            int* ranks_out, int* ranks_pred_out, const int* replay_pred, const int* replay_filt,
                            const tt_filter_spec* specs, hipStream_t st) {
   const int d = p.d;
-  // all filters of a batch share one (eps, max_rank) pair per launch; group
-  // filters by rounding settings when they differ
+  // all filters of a batch share eps (checked by run_plan); the rank rule
+  // takes each filter's own cap from its rounding scratch, bounded by maxcap
   const double eps = specs[0].eps;
   int maxcap = 1;
   for (int b = 0; b < B; ++b) maxcap = std::max(maxcap, specs[b].cap);

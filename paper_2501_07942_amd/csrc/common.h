@@ -35,6 +35,7 @@ struct RoundScratch {
   long long qoff[TT_MAXD];  // element offsets of the orthogonal cores in qbuf
   int gcap;                 // leading dimension of every square scratch matrix
   int splits;               // split-K partial Gram matrices
+  int max_rank;             // this filter's rank cap for the rank rule (0: the launch's)
   void* qbuf;               // orthogonal cores Q_k (bulk type)
   void* zbuf;               // Z_k = X_k x_3 T_{k+1} (bulk type)
   void* bbuf;               // B_k = W_k x_1 Q_k (bulk type)

@@ -42,6 +42,10 @@ def test_split_run_with_saved_state_is_bitwise_the_whole_run(mods, precision):
     second.load_state(saved)
     second(z, k_begin=split, k_count=K - split)
     torch.cuda.synchronize()
+    # the caps 4 and 6 bind below the batch's largest cap 8: each filter's
+    # rank rule stops at its own cap without a capacity flag
+    assert np.all(whole.status.cpu().numpy() == 0)
+    assert whole.ranks.cpu().numpy()[0].max() == 4 and whole.ranks.cpu().numpy()[2].max() == 6
     assert np.all(second.status.cpu().numpy() == 0)
     for name in ("log_c", "log_mpred", "mean", "cov", "ranks"):
         a = getattr(whole, name).cpu().numpy()[:, split:]
