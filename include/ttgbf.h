@@ -310,6 +310,28 @@ tt_status tt_normalize_moments(int32_t batch, const tt_grid* grids, const tt_tra
 size_t tt_normalize_moments_workspace(int32_t batch, const tt_train* t);
 
 /* ---------------------------------------------------------------------
+ * tt_normalize_moments_noalloc -- tt_normalize_moments for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the same kernels and
+ * results, bitwise, with the workspace replaced by a static device array of
+ * TT_NOALLOC_SCRATCH_BYTES that the library holds on every device it runs
+ * on until the process ends.  The caller still owns t and the outputs.
+ * The call allocates nothing (no hipMalloc/hipFree, no allocating library
+ * routine); its first call on a device looks the array's address up with
+ * that device current.  Every call on a device shares that device's array
+ * and leaves its contents behind: calls that overlap on one device (several
+ * streams or host threads) race and must be serialised by the caller.  The
+ * descriptor upload synchronises `stream` as tt_normalize_moments does.
+ * Errors: as tt_normalize_moments; TT_ERR_WORKSPACE when batch, d and the
+ * rank capacities need more than TT_NOALLOC_SCRATCH_BYTES (the message
+ * gives both sizes), TT_ERR_HIP when the device or the array's address
+ * cannot be queried.
+ * --------------------------------------------------------------------- */
+#define TT_NOALLOC_SCRATCH_BYTES ((size_t)16 << 20)
+tt_status tt_normalize_moments_noalloc(int32_t batch, const tt_grid* grids, const tt_train* t,
+                                       double* log_mass_dev, double* mean_dev, double* cov_dev, void* stream);
+
+/* ---------------------------------------------------------------------
  * Adjoints (reverse-mode derivatives) of the linear steps.
  *
  * Convention: a TT is its stored cores times exp(log_scale).  An adjoint

@@ -115,6 +115,7 @@ def _load():
                                        C.POINTER(C.c_float)]),
         "tt_filter_graph_destroy": (None, [P]),
         "tt_filter_state": (I, [I, P, P, I, I, I, P, P, S, P]),
+        "tt_normalize_moments_noalloc": (I, [I, P, P, P, P, P, P]),
         "tt_status_string": (C.c_char_p, [I]),
         "tt_device_status_string": (C.c_char_p, [I]),
     }
@@ -138,7 +139,8 @@ EXPORTED = ("tt_train_elems", "tt_last_error", "tt_version", "tt_kernel_build_wo
             "tt_likelihood_adjoint_workspace", "tt_likelihood_adjoint", "tt_adjoint_axpy",
             "tt_adjoint_inner", "tt_align_signs", "tt_round_taped", "tt_predict_einsum_workspace",
             "tt_predict_einsum", "tt_grid_redesign_workspace", "tt_grid_redesign", "tt_interpolate_workspace",
-            "tt_interpolate", "tt_filter_state", "tt_status_string", "tt_device_status_string")
+            "tt_interpolate", "tt_filter_state", "tt_status_string", "tt_device_status_string",
+            "tt_normalize_moments_noalloc")
 
 PREDICT_DIRECT, PREDICT_FFT, PREDICT_UNFUSED, PREDICT_DIRECT_VALU = 0, 1, 2, 3
 
@@ -483,6 +485,16 @@ def tt_normalize_moments(grids: Sequence[Grid], tts: Sequence[DeviceTT], log_mas
     _check(LIB.tt_normalize_moments(B, g, a, log_mass.data_ptr(), mean.data_ptr() if mean is not None else None,
                                     cov.data_ptr() if cov is not None else None, ws.data_ptr(), ws.numel(),
                                     _stream()), "tt_normalize_moments")
+
+
+def tt_normalize_moments_noalloc(grids: Sequence[Grid], tts: Sequence[DeviceTT], log_mass, mean=None, cov=None):
+    """tt_normalize_moments on the library's static scratch (allocates nothing)."""
+    B = len(tts)
+    g, a = _arr(list(grids)), _arr([t.struct() for t in tts])
+    _check(LIB.tt_normalize_moments_noalloc(B, g, a, log_mass.data_ptr(),
+                                            mean.data_ptr() if mean is not None else None,
+                                            cov.data_ptr() if cov is not None else None, _stream()),
+           "tt_normalize_moments_noalloc")
 
 
 def _adj_ws(tts):

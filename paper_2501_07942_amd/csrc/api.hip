@@ -4035,14 +4035,21 @@ size_t tt_normalize_moments_workspace(int32_t batch, const tt_train* t) {
   return ar.used + 256;
 }
 
-tt_status tt_normalize_moments(int32_t batch, const tt_grid* grids, const tt_train* t, double* log_mass_dev,
-                               double* mean_dev, double* cov_dev, void* ws, size_t ws_bytes, void* stream) {
+}  // extern "C"
+
+namespace ttg {
+
+// tt_normalize_moments on an explicit scratch area (the caller's workspace,
+// or the library's static array for tt_normalize_moments_noalloc).
+static tt_status normalize_moments_impl(const char* who, int32_t batch, const tt_grid* grids, const tt_train* t,
+                                        double* log_mass_dev, double* mean_dev, double* cov_dev, void* ws,
+                                        size_t ws_bytes, void* stream) {
   if (batch < 1 || !grids || !t || !ws) {
-    set_error("tt_normalize_moments: bad arguments");
+    set_error("%s: bad arguments", who);
     return TT_ERR_ARG;
   }
   if (cov_dev && !mean_dev) {
-    set_error("tt_normalize_moments: cov needs mean");
+    set_error("%s: cov needs mean", who);
     return TT_ERR_ARG;
   }
   const int dtype = t[0].dtype, d = t[0].d;
@@ -4053,7 +4060,7 @@ tt_status tt_normalize_moments(int32_t batch, const tt_grid* grids, const tt_tra
     TT_TRY(check_grid(&grids[b]));
     TT_TRY(check_train(&t[b], "t", dtype));
     if (t[b].d != d || grids[b].d != d) {
-      set_error("tt_normalize_moments: d differs");
+      set_error("%s: d differs", who);
       return TT_ERR_SHAPE;
     }
     for (int j = 0; j <= d; ++j) rcap = std::max(rcap, t[b].cap[j]);
@@ -4061,7 +4068,7 @@ tt_status tt_normalize_moments(int32_t batch, const tt_grid* grids, const tt_tra
     vfc[b] = make_const(grids[b], nullptr);
   }
   if (rcap > 64) {
-    set_error("tt_normalize_moments: rank capacity %d > 64", rcap);
+    set_error("%s: rank capacity %d > 64", who, rcap);
     return TT_ERR_SHAPE;
   }
   Arena ar(ws, ws_bytes);
@@ -4070,7 +4077,7 @@ tt_status tt_normalize_moments(int32_t batch, const tt_grid* grids, const tt_tra
   const long long spf = (long long)moments_scratch_per_filter(d, rcap);
   double* scratch = ar.take<double>((size_t)batch * spf);
   if (!ar.fits()) {
-    set_error("tt_normalize_moments: workspace too small");
+    set_error("%s: %zu bytes of scratch needed, %zu available", who, ar.used, ws_bytes);
     return TT_ERR_WORKSPACE;
   }
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
@@ -4081,6 +4088,61 @@ tt_status tt_normalize_moments(int32_t batch, const tt_grid* grids, const tt_tra
                                   spf, rcap, st);
   return launch_moments<float>(batch, dt, dfc, log_mass_dev, 1, mean_dev, d, cov_dev, (long long)d * d, scratch, spf,
                                rcap, st);
+}
+
+// Scratch of tt_normalize_moments_noalloc: one static array per device (the
+// descriptor tables and the per-filter contraction chains), reached from the
+// host only through the device address hipGetSymbolAddress returns for the
+// current device, looked up once per device on the first call there.
+namespace noalloc {
+static __device__ __align__(256) char scratch[TT_NOALLOC_SCRATCH_BYTES];
+}
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[64];
+
+static tt_status scratch_address(void** out) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+  if (dev < 0 || dev >= 64) {
+    set_error("tt_normalize_moments_noalloc: device %d out of range", dev);
+    return TT_ERR_ARG;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(noalloc::scratch)), "hipGetSymbolAddress(scratch)");
+    if (!ptr) {
+      set_error("tt_normalize_moments_noalloc: no device address for the scratch array");
+      return TT_ERR_HIP;
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return TT_OK;
+}
+
+}  // namespace ttg
+
+extern "C" {
+
+tt_status tt_normalize_moments(int32_t batch, const tt_grid* grids, const tt_train* t, double* log_mass_dev,
+                               double* mean_dev, double* cov_dev, void* ws, size_t ws_bytes, void* stream) {
+  return ttg::normalize_moments_impl("tt_normalize_moments", batch, grids, t, log_mass_dev, mean_dev, cov_dev, ws,
+                                     ws_bytes, stream);
+}
+
+tt_status tt_normalize_moments_noalloc(int32_t batch, const tt_grid* grids, const tt_train* t, double* log_mass_dev,
+                                       double* mean_dev, double* cov_dev, void* stream) {
+  using namespace ttg;
+  if (batch < 1 || !grids || !t) {
+    set_error("tt_normalize_moments_noalloc: bad arguments");
+    return TT_ERR_ARG;
+  }
+  void* ptr = nullptr;
+  TT_TRY(scratch_address(&ptr));
+  return normalize_moments_impl("tt_normalize_moments_noalloc", batch, grids, t, log_mass_dev, mean_dev, cov_dev, ptr,
+                                TT_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 // ---------------------------------------------------------------------------
