@@ -15,5 +15,6 @@ Contents
   grad     log-likelihood gradients: replayed-rank differences, complex step
   adjoint  reverse-mode log-likelihood gradient at fixed ranks
   redesign grid re-design (Alg. 4) and TT interpolation onto a new grid
+  cross    deterministic TT-cross (maxvol pivots) of point-wise functions
 """
 from . import tt, model, filters  # noqa: F401
