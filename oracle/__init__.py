@@ -16,5 +16,6 @@ Contents
   adjoint  reverse-mode log-likelihood gradient at fixed ranks
   redesign grid re-design (Alg. 4) and TT interpolation onto a new grid
   cross    deterministic TT-cross (maxvol pivots) of point-wise functions
+  linear   the filter for linear dynamics on re-designed grids (Alg. 3, 4)
 """
 from . import tt, model, filters  # noqa: F401
