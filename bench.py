@@ -158,8 +158,9 @@ def grad_bench(G, wl, steps, batch):
     """grad ms/step: the FP64 gradient of sum_k log c_k with respect to the
     noise and sensor parameters on the differentiated workload (d=4, N=128,
     cap 16, range + linear, 8 parameters), by the reverse sweep
-    (adjoint_grad: forward with a checkpoint per step, the adjoint of every
-    step, parameter tangents of the kernel and likelihood builds) and, beside
+    (tt_filter_run_taped / tt_filter_run_adjoint: forward with a tape per
+    step, the adjoint of every step, parameter tangents of the kernel and
+    likelihood builds) and, beside
     it, by batched rank-replay central differences.  One untimed call of each
     over two steps first (kernel builds, first launches), then one timed call
     each over `steps` steps (50 by default: the differentiated workload's
@@ -191,9 +192,10 @@ def grad_bench(G, wl, steps, batch):
             "filter_steps_per_s": round(batch * steps / (ms_adj / 1000.0), 1),
             "workload": "range4d_grad", "d": 4, "N": 128, "rank_cap": 16, "filters": batch, "steps": steps,
             "n_theta": int(g.shape[1]), "precision": "fp64",
-            "method": "reverse sweep: forward with a checkpoint per step, adjoints of prediction, rounding "
-                      "(fixed ranks), Hadamard update, normalisation and likelihood build; parameter tangents "
-                      "of the kernel and likelihood builds by central differences",
+            "method": "tt_filter_run_taped + tt_filter_run_adjoint: forward with a tape per step, adjoints of "
+                      "prediction, rounding (fixed ranks), Hadamard update, normalisation and likelihood build; "
+                      "measurement parameters by the analytic derivative of the dense likelihood, process-noise "
+                      "parameters by central differences of the kernel TT-SVD builds",
             "checkpoint_every": 1, "peak_hbm_GB": round(peak_gb, 2),
             "max_rel_diff_vs_differences": agree, "max_abs_dll": float(np.abs(ll_a - ll).max()),
             "differences": {"value": round(ms_fd_wall / steps, 2), "unit": "ms per batched step (forward + gradient)",
@@ -332,6 +334,84 @@ def conv_bench(binding, runner, wl, batch=32, r=16, calls=5):
                          "frac": round(gbs / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_call": byts}}
 
 
+def cross_bench(binding, wl, runner, batch=4):
+    """The transition kernel of the d=10, N=256 workload (41 taps per axis,
+    1.3e16 entries, no dense tensor) by the device TT-cross
+    (tt_kernel_build_cross): ms per batched build of `batch` kernels and the
+    ranks; the oracle's cross on the host for one kernel beside it."""
+    import numpy as np
+    import torch
+    specs, _, _ = wl.make_batch("range10d_n256_c32", batch=batch, steps=2)
+    s = specs[0]
+    hw = s.halfwidths()
+    taps = [2 * h + 1 for h in hw]
+    outs = [binding.DeviceTT(taps, [1] + [32] * (s.d - 1) + [1], binding.F64) for _ in specs]
+    grids = [runner.grid_of(x) for x in specs]
+    qs = [x.q for x in specs]
+    binding.tt_kernel_build_cross(grids, qs, hw, s.kernel_tol, outs)  # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    binding.tt_kernel_build_cross(grids, qs, hw, s.kernel_tol, outs)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    ranks = outs[0].ranks.cpu().numpy().tolist()
+    from oracle import cross as ocr
+    from oracle import model as mdl
+    axes = mdl.grid_axes([s.lo] * s.d, [s.hi] * s.d, [s.n] * s.d)
+    t0 = time.perf_counter()
+    ocr.kernel_tt_cross(s.q, axes, hw, s.kernel_tol)
+    cpu_s = time.perf_counter() - t0
+    return {"workload": f"kernel TT d={s.d}, {taps[0]} taps per axis (N={s.n} on [{s.lo},{s.hi}]), tol {s.kernel_tol}",
+            "kernels": batch, "ms_per_batched_build": round(ms, 1), "ranks": ranks,
+            "cpu_baseline": {"value": round(cpu_s * 1e3, 1), "unit": "ms per kernel", "kind": "oracle",
+                             "sample": "1 kernel, the oracle's deterministic TT-cross, FP64 NumPy"}}
+
+
+def linear_bench(binding, runner, batch=64, n=64, steps=10):
+    """The filter for linear dynamics on re-designed grids (Alg. 3 with
+    Alg. 4, tt_filter_run_linear) on the paper's 2-D dynamics
+    F = [[1.1, 0.1], [-0.2, 1.1]], Q = I, range + linear measurement, N = 64,
+    cap 16, FP64: ms per batched step; the oracle's run of one filter beside
+    it."""
+    import numpy as np
+    import torch
+    from paper_2501_07942_amd import workload as wl
+    f = np.array([[1.1, 0.1], [-0.2, 1.1]])
+    q = np.eye(2)
+    rng = np.random.default_rng(20250114)
+    specs, zs = [], []
+    for b in range(batch):
+        spec = wl.FilterSpec(d=2, n=n, lo=-10.0, hi=10.0, q=q, truncate_kernel=True, meas_kind="range",
+                             m0=np.zeros(2), p0_diag=np.full(2, 4.0), cap=16)
+        x = np.zeros((steps, 2))
+        x[0] = rng.normal(0.0, 2.0, 2)
+        for k in range(1, steps):
+            x[k] = f @ x[k - 1] + rng.standard_normal(2)
+        rho = np.hypot(x[:, 0] - spec.sensor[0], x[:, 1] - spec.sensor[1])
+        zs.append(np.stack([rho + spec.sigma_r * rng.standard_normal(steps), x[:, 1] + rng.standard_normal(steps)],
+                           axis=1))
+        specs.append(spec)
+    fs = runner.filter_specs(specs, [0] * batch, 16, 64)
+    z = torch.tensor(np.stack(zs), dtype=torch.float64, device="cuda")
+    binding.filter_run_linear(fs[:1], f, q, z[:1].contiguous())  # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = binding.filter_run_linear(fs, f, q, z)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    from oracle import linear as lin
+    t0 = time.perf_counter()
+    lin.run_tt_filter_linear(f, q, specs[0].meas(), zs[0], specs[0].m0, specs[0].p0_diag, [-10.0] * 2, [10.0] * 2, n,
+                             16, 1e-10)
+    cpu_s = time.perf_counter() - t0
+    return {"workload": f"Alg. 3 (re-designed grids) on the paper's 2-D dynamics, range + linear, N={n}, cap 16",
+            "filters": batch, "steps": steps, "precision": "fp64", "ms_per_batched_step": round(ms / steps, 2),
+            "filter_steps_per_s": round(batch * steps / (ms * 1e-3), 1),
+            "failed_filters": int((out["status"].cpu().numpy() != 0).sum()),
+            "cpu_baseline": {"value": round(steps / cpu_s, 2), "unit": "filter-steps/s", "kind": "oracle",
+                             "sample": f"1 filter x {steps} steps, FP64 NumPy (dense second interpolation)"}}
+
+
 def interp_cpu_baseline(d=6, n=128, r=16):
     """The oracle's interpolation on one filter of the interp_bench shapes
     (part of the CPU baseline leg)."""
@@ -379,6 +459,7 @@ def main():
     ap.add_argument("--extra-only", action="store_true",
                     help="only time the Einstein-summation prediction, the interpolation onto a new grid and the "
                          "materialised convolution")
+    ap.add_argument("--no-ragged", action="store_true", help="skip the ragged batch (N and cap drawn per filter)")
     ap.add_argument("--grad-steps", type=int, default=50)
     ap.add_argument("--grad-batch", type=int, default=32)
     ap.add_argument("--grad-only", action="store_true",
@@ -474,6 +555,24 @@ def main():
         "graph_step": main_res["graph"],
         "autotune": main_res["autotune"],
     }
+    if not args.no_einsum:
+        out["kernel_cross"] = cross_bench(binding, wl, runner)
+        out["linear_dynamics"] = linear_bench(binding, runner)
+        torch.cuda.empty_cache()
+    if not args.no_ragged:
+        # the ragged batch: N and rank cap drawn per filter, same model
+        rg = run_batch(None, runner, binding, wl, "range6d_ragged", B, args.steps, args.warmup, binding.F32)
+        mix = {}
+        for s in rg["specs"]:
+            key = f"N{s.n}_c{s.cap}"
+            mix[key] = mix.get(key, 0) + 1
+        out["ragged"] = {"workload": "range6d_ragged", "value": round(B * args.steps / (rg["ms"] / 1000.0), 2),
+                         "unit": "filter-steps/s", "ms_per_step": round(rg["ms"] / args.steps, 3), "filters": B,
+                         "mix": dict(sorted(mix.items())), "failed_filters": int((rg["status"] != 0).sum()),
+                         "workspace_GB": round(rg["run"].ws.numel() * rg["run"].ws.element_size() / 1e9, 2),
+                         "precision": "fp32 bulk, fp64 Gram/pivoted-Cholesky/Jacobi, fp64 log-normaliser"}
+        rg.clear()
+        torch.cuda.empty_cache()
     if not args.no_einsum:
         out["einsum_predict"] = einsum_bench(binding)
         torch.cuda.empty_cache()

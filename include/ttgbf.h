@@ -148,6 +148,63 @@ tt_status tt_kernel_build_batch(int32_t batch, const tt_grid* grids, const doubl
                                 double svd_tol, const tt_train* out, void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------
+ * tt_kernel_build_cross -- the transition kernel of tt_kernel_build without
+ * the dense tensor, for any d (the d = 10, 41-tap kernel has 1.3e16
+ * entries): K(m) is evaluated point by point and approximated by a
+ * deterministic TT-cross (Sec. 3.3 cross approximation; maxvol pivots in
+ * place of the paper's randomised greedy cross): alternating sweeps over
+ * the cores, each fibre matrix f(I_{<k}, i_k, J_{>k}) reduced to an
+ * orthonormal basis of its range (the library's rounding of a two-core
+ * train; only exactly dependent columns are dropped), maxvol rows of that
+ * basis as the next index set, the cores in interpolation form; two sweeps
+ * per rank level, the rank starting at 8 and doubling up to max_rank (and
+ * to at most 4096 / the largest mode size) while the rounded result's rank
+ * at some bond is within 2 of the rank used there.  The result is rounded
+ * (Sec. 4.1 'round') at svd_tol into out.  Synchronous (reads ranks after
+ * each level).
+ *   grids, q, halfwidths, out  as tt_kernel_build_batch (d <= TT_MAXD,
+ *              2 h_l + 1 <= 4096 taps); max_rank in [1, 64]; out FP64 or
+ *              FP32.
+ * Workspace: tt_kernel_build_cross_workspace(batch, grids, halfwidths, out).
+ * Errors: TT_ERR_ARG (null, svd_tol <= 0, max_rank out of range, Q not
+ * positive definite), TT_ERR_SHAPE, TT_ERR_WORKSPACE, TT_ERR_HIP.
+ * --------------------------------------------------------------------- */
+size_t tt_kernel_build_cross_workspace(int32_t batch, const tt_grid* grids, const int32_t* halfwidths,
+                                       const tt_train* out);
+tt_status tt_kernel_build_cross(int32_t batch, const tt_grid* grids, const double* q, const int32_t* halfwidths,
+                                double svd_tol, int32_t max_rank, const tt_train* out, void* ws, size_t ws_bytes,
+                                void* stream);
+
+/* ---------------------------------------------------------------------
+ * tt_interpolate_lattice -- the second interpolation of Alg. 3: for linear
+ * dynamics the temporary predictive lives on the lattice x(j) = F xi(j) of
+ * an axis-aligned grid `lattice` (the time update's convolution grid); it
+ * is interpolated onto the axis-aligned grid `to` (the smallest box holding
+ * the lattice's corners, Alg. 3 and Alg. 4):
+ *   out(i) = sum over the 2^d lattice neighbours j of u of
+ *            prod_l (1 - |u_l - j_l|) in(j),   u = (F diag dx)^{-1} (x(i) - F lo)
+ * with dx, lo the lattice grid's spacing and lower corner, x(i) the point i
+ * of `to`, and zero for a neighbour off the lattice.  The result couples
+ * the axes, so it is built by the TT-cross of tt_kernel_build_cross from
+ * point values of the interpolant (each a sum of 2^d point values of `in`)
+ * and rounded at tol with out's capacities; out's log_scale is in's plus
+ * the rounding's.
+ *   f          d x d row-major, host, shared by the batch (invertible)
+ *   lattice[b], to[b]  host grids of filter b (2 <= d <= 6; every `to`
+ *              grid has the same point counts)
+ *   in[b]      FP64 on lattice's modes, rank capacities <= 32
+ *   out[b]     FP64 or FP32 on to's modes; max_rank in [1, 64] bounds the
+ *              cross (and 4096 / the largest point count)
+ * Synchronous.  Workspace: tt_interpolate_lattice_workspace(batch, to, out,
+ * max_rank).  Errors: TT_ERR_ARG (null, tol <= 0, F singular),
+ * TT_ERR_SHAPE, TT_ERR_WORKSPACE, TT_ERR_HIP.
+ * --------------------------------------------------------------------- */
+size_t tt_interpolate_lattice_workspace(int32_t batch, const tt_grid* to, const tt_train* out, int32_t max_rank);
+tt_status tt_interpolate_lattice(int32_t batch, const double* f, const tt_grid* lattice, const tt_grid* to,
+                                 const tt_train* in, double tol, int32_t max_rank, const tt_train* out, void* ws,
+                                 size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------
  * tt_predict -- Chapman-Kolmogorov prediction for x_{k+1} = x_k + w_k as
  * the linear convolution of the PMD with the kernel, cropped to the grid
  * (Sec. 2.1 eq. tpmconvFFT; Sec. 4.2: the cores of a TT convolution are the
@@ -541,6 +598,102 @@ tt_status tt_filter_run(int32_t batch, const tt_filter_spec* specs, const tt_tra
                         void* stream);
 
 /* ---------------------------------------------------------------------
+ * The differentiated recursion: LL = sum_k log c_k (Sec. 2.2, eq.
+ * pmf_filtrace_b) of every filter of a batch and its gradient with respect
+ * to theta = (sigma_w[0..d-1], sigma_r, sigma_lin, s_1, s_2) for the range
+ * model (n_theta = d + 4) or (sigma_w[0..d-1], sigma_lin) for the all-linear
+ * one (n_theta = d + 1), where Q = D C D with D = diag(sigma_w) and C the
+ * correlation of spec.q.  FP64 throughout.
+ *
+ * tt_grad_spec: a filter (grid, measurement model with sigma_r, sigma_lin and
+ * sensor, prior, rank cap, eps, lik_rank_cap; kernel_cap = the largest kernel
+ * TT rank reserved for; kernel_index unused), its process-noise covariance q
+ * (d x d row-major, sigma_w = sqrt(diag q)), the kernel offset box and the
+ * kernel's TT-SVD tolerance.  All filters of a batch share d, the
+ * measurement kind, eps, cap, kernel_cap, lik_rank_cap and the box.
+ *
+ * tt_filter_run_taped runs the recursion of tt_filter_run (Alg. 2 order,
+ * materialised prediction) from the prior: it builds each filter's kernel
+ * TT (tt_kernel_build_batch), writes loglik_dev[b] and keeps in ws what the
+ * reverse sweep needs: with ckpt_every = 1 every step's rounded predictive,
+ * likelihood TT, update product, filtering density and the records of both
+ * roundings (tt_round_taped); with ckpt_every = C > 1 only the filtering
+ * density that starts each segment of C steps.
+ * tt_filter_run_adjoint then runs the reverse sweep on the same ws (same
+ * batch, specs, z_dev, K and ckpt_every, nothing else written to ws in
+ * between): segments from the last, each recomputed from its checkpoint,
+ * steps backwards through tt_normalize_adjoint, tt_round_adjoint (ranks of
+ * the forward held fixed), tt_hadamard_adjoint, tt_likelihood_adjoint and
+ * tt_predict_adjoint, the adjoint of every log c_k seeded with
+ * loglik_bar_dev[b].  It writes
+ *   theta_bar_dev[b * n_theta + j] = loglik_bar[b] * dLL_b / dtheta_j.
+ * The measurement parameters enter through the dense likelihood, whose
+ * theta-derivative is analytic (the log-derivatives of the range and linear
+ * Gaussian factors, evaluated on the device); sigma_w enters through the
+ * kernel TT, whose tangent is the central difference of two device TT-SVD
+ * builds at sigma_w[j] +- h_j (h_j = 1e-5 max(1, sigma_w[j])) put into the
+ * base build's bond bases (tt_align_signs), the quotient taken on the device.
+ * status_dev[b] (both calls) receives the OR of the filter's TT_STATUS_*
+ * bits (TT_STATUS_CAPACITY also when a perturbed kernel build changes a
+ * rank); the caller clears it before the taped run.  Both calls synchronise
+ * the stream before they return.  Workspace: tt_filter_grad_workspace bytes
+ * (device memory for the kernels, the tape or checkpoints, one step's
+ * temporaries and the sub-calls' workspaces).  Errors: TT_ERR_ARG (null,
+ * ckpt_every < 1, K < 1, a parameter <= 0 where positive is required),
+ * TT_ERR_SHAPE (the shared fields differ, d < 2), TT_ERR_WORKSPACE,
+ * TT_ERR_HIP, and those of the sub-calls.
+ * --------------------------------------------------------------------- */
+typedef struct {
+  tt_filter_spec f;
+  double q[TT_MAXD * TT_MAXD];
+  int32_t halfwidths[TT_MAXD];
+  double kernel_tol;
+} tt_grad_spec;
+
+size_t tt_filter_grad_workspace(int32_t batch, const tt_grad_spec* specs, int32_t K, int32_t ckpt_every);
+tt_status tt_filter_run_taped(int32_t batch, const tt_grad_spec* specs, const double* z_dev, int32_t zdim,
+                              int32_t K, int32_t ckpt_every, double* loglik_dev, int32_t* status_dev, void* ws,
+                              size_t ws_bytes, void* stream);
+tt_status tt_filter_run_adjoint(int32_t batch, const tt_grad_spec* specs, const double* z_dev, int32_t zdim,
+                                int32_t K, int32_t ckpt_every, const double* loglik_bar_dev, double* theta_bar_dev,
+                                int32_t* status_dev, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------
+ * tt_filter_run_linear -- the point-mass filter for linear dynamics
+ * x_{k+1} = F x_k + w_k (w ~ N(0, Q)) on grids that follow the density
+ * (Alg. 3 with the grid re-design of Alg. 4), FP64.  Step 0 updates the
+ * prior on spec.grid; every later step
+ *   re-designs the grid (tt_normalize_moments, tt_grid_redesign with
+ *     nsigma: the predictive moments' sigma box mapped back by F^{-1}) and
+ *     interpolates the density onto it (tt_interpolate);
+ *   predicts on the lattice F xi of that grid: the convolution (tt_predict)
+ *     with the kernel N(F (dx o m); 0, Q) dx^d = N(dx o m; 0, F^{-1} Q F^{-T})
+ *     dx^d / |det F| on the box |m_l| <= floor(kernel_nsigma
+ *     sqrt((F^{-1} Q F^{-T})_ll) / dx_l) (the smallest spacing over the
+ *     batch, capped at N - 1), built by tt_kernel_build_cross at kernel_tol,
+ *     then rounds (eps, cap);
+ *   re-designs again: the smallest box holding the lattice's corners, onto
+ *     which the prediction is interpolated (tt_interpolate_lattice at
+ *     kernel_tol), rounded and normalised (log_mpred);
+ * then updates as tt_filter_run does (likelihood, c_k, rounding,
+ * normalisation, moments).  Outputs as tt_filter_run (log_c_dev,
+ * log_mpred_dev [B*K], mean_dev [B*K*d], cov_dev [B*K*d*d], nullable
+ * moments) plus grids_out (host, nullable) [B*K*2d]: lo then hi of each
+ * step's filtering grid.  specs: grid (N points on every axis), meas,
+ * prior, cap and kernel_cap in [1, 32], eps, lik_rank_cap, all but the
+ * grid box, prior and measurement values shared by the batch; f, q: d x d
+ * host (shared), 2 <= d <= 6.  Synchronous.  Workspace:
+ * tt_filter_run_linear_workspace(batch, specs, K).  Errors: TT_ERR_ARG,
+ * TT_ERR_SHAPE, TT_ERR_WORKSPACE, TT_ERR_HIP and those of the sub-calls.
+ * --------------------------------------------------------------------- */
+size_t tt_filter_run_linear_workspace(int32_t batch, const tt_filter_spec* specs, int32_t K);
+tt_status tt_filter_run_linear(int32_t batch, const tt_filter_spec* specs, const double* f, const double* q,
+                               double nsigma, double kernel_nsigma, double kernel_tol, const double* z_dev,
+                               int32_t zdim, int32_t K, double* loglik_dev, double* log_c_dev, double* log_mpred_dev,
+                               double* mean_dev, double* cov_dev, double* grids_out, int32_t* status_dev, void* ws,
+                               size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------
  * tt_filter_graph_* -- the steps of tt_filter_run recorded once as a HIP
  * graph and replayed (one graph per time step when k_count = 1; the
  * recursion of Alg. 2 repeated without host launch work).
@@ -632,6 +785,22 @@ tt_status tt_autotune_prediction(int32_t batch, const tt_filter_spec* specs, con
                                  int32_t* status_dev, void* ws, size_t ws_bytes, void* stream,
                                  int32_t warmup_steps, int32_t rounds, int32_t* best_bb, float* ms_per_candidate);
 
+/* tt_autotune_save / tt_autotune_load -- persist the tuned launch shapes.
+ * save writes every shape tt_autotune_prediction has decided in this
+ * process to `path` as a JSON array, one object per shape:
+ *   {"arch": "gfx950", "knob": "prediction_fibres_per_workgroup",
+ *    "dtype": "f32", "batch": 256, "halfwidth": 12, "n": 128,
+ *    "rank_cap": 16, "kernel_rank_cap": 16, "value": 16}
+ * (arch = the current device's architecture name).  load reads such a
+ * file (the format save writes, objects in any order) and adopts the
+ * entries whose arch is the current device's, replacing decisions for the
+ * same shape; *n_loaded (nullable) receives their number.  Host-only file
+ * I/O, no device work.  Errors: TT_ERR_ARG (null path, unreadable or
+ * unwritable file, an entry that does not parse), TT_ERR_HIP (device
+ * properties unavailable). */
+tt_status tt_autotune_save(const char* path);
+tt_status tt_autotune_load(const char* path, int32_t* n_loaded);
+
 /* ---------------------------------------------------------------------
  * How tt_filter_run evaluates the prediction for d >= 3 (process-wide
  * setting; all modes compute the same Z_k = conv(K_k, P_k) x_3 L_{k+1} that
@@ -647,6 +816,8 @@ tt_status tt_autotune_prediction(int32_t batch, const tt_filter_spec* specs, con
  *     with a tall GEMM;
  *   3 direct fused on the vector ALUs for both precisions (mode 0 without
  *     the matrix cores).
+ * A batch whose fused prediction would need more than the 160 KB of LDS of
+ * a compute unit (FP64 at rank cap 24 and N = 128, say) runs mode 2.
  * tt_predict always materialises the product.
  * --------------------------------------------------------------------- */
 tt_status tt_set_predict_mode(int32_t mode);

@@ -46,6 +46,11 @@ class FilterSpec(C.Structure):
                 ("lik_rank_cap", C.c_int32)]
 
 
+class GradSpec(C.Structure):
+    _fields_ = [("f", FilterSpec), ("q", C.c_double * (MAXD * MAXD)), ("halfwidths", C.c_int32 * MAXD),
+                ("kernel_tol", C.c_double)]
+
+
 class RoundTapeStruct(C.Structure):
     _fields_ = [("g", C.c_void_p * MAXD), ("f", C.c_void_p * MAXD), ("v", C.c_void_p * MAXD),
                 ("s", C.c_void_p * MAXD), ("valid", C.c_void_p), ("rank", C.c_void_p)]
@@ -116,6 +121,17 @@ def _load():
         "tt_filter_graph_destroy": (None, [P]),
         "tt_filter_state": (I, [I, P, P, I, I, I, P, P, S, P]),
         "tt_normalize_moments_noalloc": (I, [I, P, P, P, P, P, P]),
+        "tt_kernel_build_cross_workspace": (S, [I, P, P, P]),
+        "tt_kernel_build_cross": (I, [I, P, P, P, D, I, P, P, S, P]),
+        "tt_interpolate_lattice_workspace": (S, [I, P, P, I]),
+        "tt_interpolate_lattice": (I, [I, P, P, P, P, D, I, P, P, S, P]),
+        "tt_filter_run_linear_workspace": (S, [I, P, I]),
+        "tt_filter_run_linear": (I, [I, P, P, P, D, D, D, P, I, I, P, P, P, P, P, P, P, P, S, P]),
+        "tt_filter_grad_workspace": (S, [I, P, I, I]),
+        "tt_filter_run_taped": (I, [I, P, P, I, I, I, P, P, P, S, P]),
+        "tt_filter_run_adjoint": (I, [I, P, P, I, I, I, P, P, P, P, S, P]),
+        "tt_autotune_save": (I, [C.c_char_p]),
+        "tt_autotune_load": (I, [C.c_char_p, C.POINTER(C.c_int32)]),
         "tt_status_string": (C.c_char_p, [I]),
         "tt_device_status_string": (C.c_char_p, [I]),
     }
@@ -140,9 +156,94 @@ EXPORTED = ("tt_train_elems", "tt_last_error", "tt_version", "tt_kernel_build_wo
             "tt_adjoint_inner", "tt_align_signs", "tt_round_taped", "tt_predict_einsum_workspace",
             "tt_predict_einsum", "tt_grid_redesign_workspace", "tt_grid_redesign", "tt_interpolate_workspace",
             "tt_interpolate", "tt_filter_state", "tt_status_string", "tt_device_status_string",
-            "tt_normalize_moments_noalloc")
+            "tt_normalize_moments_noalloc", "tt_autotune_save", "tt_autotune_load", "tt_filter_grad_workspace",
+            "tt_filter_run_taped", "tt_filter_run_adjoint", "tt_kernel_build_cross_workspace",
+            "tt_kernel_build_cross", "tt_interpolate_lattice_workspace", "tt_interpolate_lattice",
+            "tt_filter_run_linear_workspace", "tt_filter_run_linear")
 
 PREDICT_DIRECT, PREDICT_FFT, PREDICT_UNFUSED, PREDICT_DIRECT_VALU = 0, 1, 2, 3
+
+
+def filter_run_linear(fspecs: Sequence[FilterSpec], f: np.ndarray, q: np.ndarray, z, nsigma: float = 4.0,
+                      kernel_nsigma: float = 4.0, kernel_tol: float = 1e-12) -> dict:
+    """tt_filter_run_linear over a batch (z: float64 device [B, K, zdim]);
+    returns device tensors loglik, log_c, log_mpred, mean, cov, status and
+    the host array grids [B, K, 2d] (lo, hi of each step's grid)."""
+    torch = _torch()
+    B = len(fspecs)
+    K, zdim = int(z.shape[1]), int(z.shape[2])
+    d = fspecs[0].grid.d
+    arr = (FilterSpec * B)(*fspecs)
+    nbytes = LIB.tt_filter_run_linear_workspace(B, arr, K)
+    if nbytes == 0:
+        _check(ERR_ARG, "tt_filter_run_linear_workspace")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dev = lambda *shape: torch.zeros(*shape, dtype=torch.float64, device="cuda")  # noqa: E731
+    out = {"loglik": dev(B), "log_c": dev(B, K), "log_mpred": dev(B, K), "mean": dev(B, K, d), "cov": dev(B, K, d, d),
+           "status": torch.zeros(B, dtype=torch.int32, device="cuda")}
+    grids = np.zeros((B, K, 2 * d))
+    ff = np.ascontiguousarray(np.asarray(f, dtype=np.float64))
+    qq = np.ascontiguousarray(np.asarray(q, dtype=np.float64))
+    _check(LIB.tt_filter_run_linear(B, arr, ff.ctypes.data_as(C.c_void_p), qq.ctypes.data_as(C.c_void_p),
+                                    float(nsigma), float(kernel_nsigma), float(kernel_tol), z.data_ptr(), zdim, K,
+                                    out["loglik"].data_ptr(), out["log_c"].data_ptr(), out["log_mpred"].data_ptr(),
+                                    out["mean"].data_ptr(), out["cov"].data_ptr(), grids.ctypes.data_as(C.c_void_p),
+                                    out["status"].data_ptr(), ws.data_ptr(), ws.numel(), _stream()),
+           "tt_filter_run_linear")
+    out["grids"] = grids
+    return out
+
+
+class FilterGrad:
+    """tt_filter_run_taped / tt_filter_run_adjoint for a batch of GradSpec:
+    the workspace (kernels, tape or checkpoints, temporaries) lives as long
+    as this object.  z: float64 device tensor [B, K, zdim]."""
+
+    def __init__(self, gspecs: Sequence[GradSpec], z, ckpt_every: int = 1):
+        torch = _torch()
+        self.B = len(gspecs)
+        self.specs = (GradSpec * self.B)(*gspecs)
+        self.z = z
+        self.K, self.zdim = int(z.shape[1]), int(z.shape[2])
+        self.C = int(ckpt_every)
+        d = gspecs[0].f.grid.d
+        self.n_theta = d + 4 if gspecs[0].f.meas.kind == 1 else d + 1
+        nbytes = LIB.tt_filter_grad_workspace(self.B, self.specs, self.K, self.C)
+        if nbytes == 0:
+            _check(ERR_ARG, "tt_filter_grad_workspace")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        self.loglik = torch.zeros(self.B, dtype=torch.float64, device="cuda")
+        self.theta_bar = torch.zeros(self.B, self.n_theta, dtype=torch.float64, device="cuda")
+        self.status = torch.zeros(self.B, dtype=torch.int32, device="cuda")
+
+    def forward(self):
+        """LL [B] (device); keeps what the reverse sweep needs."""
+        self.status.zero_()
+        _check(LIB.tt_filter_run_taped(self.B, self.specs, self.z.data_ptr(), self.zdim, self.K, self.C,
+                                       self.loglik.data_ptr(), self.status.data_ptr(), self.ws.data_ptr(),
+                                       self.ws.numel(), _stream()), "tt_filter_run_taped")
+        return self.loglik
+
+    def backward(self, loglik_bar):
+        """theta_bar [B, n_theta] = loglik_bar[b] * dLL_b/dtheta (device)."""
+        lb = loglik_bar.to(dtype=_torch().float64).contiguous()
+        _check(LIB.tt_filter_run_adjoint(self.B, self.specs, self.z.data_ptr(), self.zdim, self.K, self.C,
+                                         lb.data_ptr(), self.theta_bar.data_ptr(), self.status.data_ptr(),
+                                         self.ws.data_ptr(), self.ws.numel(), _stream()), "tt_filter_run_adjoint")
+        return self.theta_bar
+
+
+def autotune_save(path: str):
+    """tt_autotune_save: the tuned launch shapes of this process as JSON."""
+    _check(LIB.tt_autotune_save(os.fsencode(path)), "tt_autotune_save")
+
+
+def autotune_load(path: str) -> int:
+    """tt_autotune_load: adopt the shapes a previous run saved for this
+    device's architecture; returns how many were adopted."""
+    n = C.c_int32(0)
+    _check(LIB.tt_autotune_load(os.fsencode(path), C.byref(n)), "tt_autotune_load")
+    return int(n.value)
 
 
 def set_predict_mode(mode: int):
@@ -370,6 +471,37 @@ def tt_predict(kernels: Sequence[DeviceTT], p_in: Sequence[DeviceTT], p_out: Seq
     ks, ps, xs = _arr([k.struct() for k in kernels]), _arr([p.struct() for p in p_in]), _arr([x.struct() for x in p_out])
     ws = _ws(LIB.tt_predict_workspace(B))
     _check(LIB.tt_predict(B, ks, ps, xs, ws.data_ptr(), ws.numel(), _stream()), "tt_predict")
+
+
+def tt_kernel_build_cross(grids: Sequence[Grid], qs: Sequence[np.ndarray], halfwidths: Sequence[int],
+                          svd_tol: float, outs: Sequence[DeviceTT], max_rank: int = 64):
+    """The kernel TT by deterministic TT-cross from point values (any d)."""
+    B = len(outs)
+    d = grids[0].d
+    hw = (C.c_int32 * d)(*[int(h) for h in halfwidths])
+    qq = np.ascontiguousarray(np.stack([np.asarray(q, dtype=np.float64).reshape(d, d) for q in qs]))
+    g, o = _arr(list(grids)), _arr([t.struct() for t in outs])
+    nbytes = LIB.tt_kernel_build_cross_workspace(B, g, hw, o)
+    if nbytes == 0:
+        _check(ERR_ARG, "tt_kernel_build_cross_workspace")
+    ws = _ws(nbytes)
+    _check(LIB.tt_kernel_build_cross(B, g, qq.ctypes.data_as(C.c_void_p), hw, float(svd_tol), int(max_rank), o,
+                                     ws.data_ptr(), ws.numel(), _stream()), "tt_kernel_build_cross")
+
+
+def tt_interpolate_lattice(f: np.ndarray, lattice: Sequence[Grid], to: Sequence[Grid], t_in: Sequence[DeviceTT],
+                           t_out: Sequence[DeviceTT], tol: float = 1e-12, max_rank: int = 64):
+    """Weights on the lattice F xi(lattice) interpolated onto the grids `to`."""
+    B = len(t_in)
+    ff = np.ascontiguousarray(np.asarray(f, dtype=np.float64))
+    tg, o = _arr(list(to)), _arr([t.struct() for t in t_out])
+    nbytes = LIB.tt_interpolate_lattice_workspace(B, tg, o, int(max_rank))
+    if nbytes == 0:
+        _check(ERR_ARG, "tt_interpolate_lattice_workspace")
+    ws = _ws(nbytes)
+    _check(LIB.tt_interpolate_lattice(B, ff.ctypes.data_as(C.c_void_p), _arr(list(lattice)), tg,
+                                      _arr([t.struct() for t in t_in]), float(tol), int(max_rank), o, ws.data_ptr(),
+                                      ws.numel(), _stream()), "tt_interpolate_lattice")
 
 
 def tt_update(grids: Sequence[Grid], meas: Sequence[Meas], z, p_pred: Sequence[DeviceTT],

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <string>
 #include <type_traits>
 #include <vector>
 
@@ -4663,10 +4664,9 @@ static tt_status run_plan(int32_t batch, const tt_filter_spec* specs, const tt_t
                                      : (use_mfma_pred<float>(hmax, nmax, p.pcap, p.kcap)
                                             ? mfma_pred_smem<float>(hmax, nmax, p.pcap, p.kcap)
                                             : direct_smem<float>(hmax, nmax, p.pcap, p.kcap)));
-      if (need > 160 * 1024) {
-        set_error("tt_filter_run: the fused prediction needs %zu bytes of LDS", need);
-        return TT_ERR_SHAPE;
-      }
+      // a fused prediction that does not fit the LDS of a CU gives way to
+      // the materialised convolution and the plain rounding (mode 2)
+      if (need > 160 * 1024) p.fused = false;
     }
     for (int ki = 0; ki < nk; ++ki) {
       if (p.kL[ki] == 0) continue;
@@ -5030,6 +5030,140 @@ tt_status tt_filter_state(int32_t batch, const tt_filter_spec* specs, const tt_t
   return TT_OK;
 }
 
+}  // extern "C"
+
+namespace ttg {
+
+static tt_status device_arch(char* out, size_t len) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
+  size_t i = 0;
+  for (; i + 1 < len && prop.gcnArchName[i] && prop.gcnArchName[i] != ':'; ++i) out[i] = prop.gcnArchName[i];
+  out[i] = 0;
+  return TT_OK;
+}
+
+// value of "key": <int> or "key": "<word>" inside one JSON object's text
+static bool json_int(const char* obj, const char* key, int* v) {
+  char pat[64];
+  snprintf(pat, sizeof(pat), "\"%s\"", key);
+  const char* p = strstr(obj, pat);
+  if (!p) return false;
+  p = strchr(p + strlen(pat), ':');
+  return p && sscanf(p + 1, " %d", v) == 1;
+}
+
+static bool json_word(const char* obj, const char* key, char* out, size_t len) {
+  char pat[64];
+  snprintf(pat, sizeof(pat), "\"%s\"", key);
+  const char* p = strstr(obj, pat);
+  if (!p) return false;
+  p = strchr(p + strlen(pat), ':');
+  if (!p) return false;
+  p = strchr(p, '"');
+  if (!p) return false;
+  const char* e = strchr(p + 1, '"');
+  if (!e || (size_t)(e - p - 1) >= len) return false;
+  memcpy(out, p + 1, e - p - 1);
+  out[e - p - 1] = 0;
+  return true;
+}
+
+}  // namespace ttg
+
+extern "C" {
+
+tt_status tt_autotune_save(const char* path) {
+  using namespace ttg;
+  if (!path) {
+    set_error("tt_autotune_save: null path");
+    return TT_ERR_ARG;
+  }
+  char arch[64];
+  TT_TRY(device_arch(arch, sizeof(arch)));
+  FILE* f = fopen(path, "w");
+  if (!f) {
+    set_error("tt_autotune_save: cannot write %s", path);
+    return TT_ERR_ARG;
+  }
+  fprintf(f, "[\n");
+  for (size_t i = 0; i < g_tuned_bb.size(); ++i) {
+    const TuneKey& k = g_tuned_bb[i].first;
+    fprintf(f,
+            "  {\"arch\": \"%s\", \"knob\": \"prediction_fibres_per_workgroup\", \"dtype\": \"%s\", "
+            "\"batch\": %d, \"halfwidth\": %d, \"n\": %d, \"rank_cap\": %d, \"kernel_rank_cap\": %d, "
+            "\"value\": %d}%s\n",
+            arch, k.f64 ? "f64" : "f32", k.B, k.hmax, k.nmax, k.pcap, k.kcap, g_tuned_bb[i].second,
+            i + 1 < g_tuned_bb.size() ? "," : "");
+  }
+  fprintf(f, "]\n");
+  const bool ok = fclose(f) == 0;
+  if (!ok) {
+    set_error("tt_autotune_save: writing %s failed", path);
+    return TT_ERR_ARG;
+  }
+  return TT_OK;
+}
+
+tt_status tt_autotune_load(const char* path, int32_t* n_loaded) {
+  using namespace ttg;
+  if (!path) {
+    set_error("tt_autotune_load: null path");
+    return TT_ERR_ARG;
+  }
+  char arch[64];
+  TT_TRY(device_arch(arch, sizeof(arch)));
+  FILE* f = fopen(path, "r");
+  if (!f) {
+    set_error("tt_autotune_load: cannot read %s", path);
+    return TT_ERR_ARG;
+  }
+  std::vector<char> text;
+  char buf[4096];
+  size_t got;
+  while ((got = fread(buf, 1, sizeof(buf), f)) > 0) text.insert(text.end(), buf, buf + got);
+  fclose(f);
+  text.push_back(0);
+  std::vector<std::pair<TuneKey, int>> found;
+  const char* p = text.data();
+  while ((p = strchr(p, '{')) != nullptr) {
+    const char* e = strchr(p, '}');
+    if (!e) {
+      set_error("tt_autotune_load: unterminated entry in %s", path);
+      return TT_ERR_ARG;
+    }
+    std::string obj(p, e - p + 1);
+    char a[64], knob[64], dt[16];
+    TuneKey k{};
+    int v = 0;
+    if (!json_word(obj.c_str(), "arch", a, sizeof(a)) || !json_word(obj.c_str(), "knob", knob, sizeof(knob)) ||
+        !json_word(obj.c_str(), "dtype", dt, sizeof(dt)) || !json_int(obj.c_str(), "batch", &k.B) ||
+        !json_int(obj.c_str(), "halfwidth", &k.hmax) || !json_int(obj.c_str(), "n", &k.nmax) ||
+        !json_int(obj.c_str(), "rank_cap", &k.pcap) || !json_int(obj.c_str(), "kernel_rank_cap", &k.kcap) ||
+        !json_int(obj.c_str(), "value", &v) || strcmp(knob, "prediction_fibres_per_workgroup") != 0 ||
+        (strcmp(dt, "f32") != 0 && strcmp(dt, "f64") != 0) || (v != 2 && v != 4 && v != 8 && v != 16)) {
+      set_error("tt_autotune_load: entry does not parse: %.200s", obj.c_str());
+      return TT_ERR_ARG;
+    }
+    k.f64 = strcmp(dt, "f64") == 0;
+    if (strcmp(a, arch) == 0) found.push_back({k, v});
+    p = e + 1;
+  }
+  for (const auto& fe : found) {
+    bool rep = false;
+    for (auto& e : g_tuned_bb)
+      if (e.first == fe.first) {
+        e.second = fe.second;
+        rep = true;
+      }
+    if (!rep) g_tuned_bb.push_back(fe);
+  }
+  if (n_loaded) *n_loaded = (int32_t)found.size();
+  return TT_OK;
+}
+
 const char* tt_status_string(int32_t code) {
   switch (code) {
     case TT_OK:
@@ -5207,3 +5341,7 @@ tt_status tt_autotune_prediction(int32_t batch, const tt_filter_spec* specs, con
 }
 
 }  // extern "C"
+
+#include "grad_run.h"
+#include "cross.h"
+#include "linear_run.h"

@@ -127,13 +127,14 @@ class TTFilterLogLik:
     """torch.autograd.Function-style wrapper: apply(theta, specs, zs) returns
     LL[B] as a float64 tensor whose backward gives dLL/dtheta.  theta is
     [n_theta] (shared by the batch) or [B, n_theta].  method "adjoint" (the
-    default) takes the gradient from the reverse sweep of
-    adjoint_grad.loglik_grad_adjoint (forward with checkpoints, adjoints of
-    every step); "differences" from the batched rank-replay central
-    differences of loglik_grad (step h_rel)."""
+    default): the forward runs tt_filter_run_taped (recursion with its tape)
+    and the backward tt_filter_run_adjoint (the reverse sweep, seeded with
+    the incoming gradient of LL); "differences": the forward takes the
+    gradient from the batched rank-replay central differences of loglik_grad
+    (step h_rel) and the backward scales it."""
 
     @staticmethod
-    def apply(theta, specs, zs, h_rel: float = 1e-5, method: str = "adjoint"):
+    def apply(theta, specs, zs, h_rel: float = 1e-5, method: str = "adjoint", ckpt_every: int = 1):
         import torch
         if method not in ("adjoint", "differences"):
             raise ValueError(f"unknown gradient method {method!r}")
@@ -144,19 +145,28 @@ class TTFilterLogLik:
                 tcpu = th.detach().cpu().numpy().astype(np.float64)
                 shared = tcpu.ndim == 1
                 thetas = np.tile(tcpu, (len(specs), 1)) if shared else tcpu
+                ctx.shared = shared
                 if method == "adjoint":
                     from . import adjoint_grad
-                    ll, g, _ = adjoint_grad.loglik_grad_adjoint(specs, zs, thetas)
-                else:
-                    ll, g, _ = loglik_grad(specs, zs, thetas, h_rel)
-                ctx.shared = shared
+                    ctx.fg = adjoint_grad.filter_grad(specs, zs, thetas, ckpt_every=ckpt_every)
+                    ll = ctx.fg.forward().clone()
+                    return ll.to(dtype=th.dtype, device=th.device)
+                ll, g, _ = loglik_grad(specs, zs, thetas, h_rel)
+                ctx.fg = None
                 ctx.save_for_backward(torch.as_tensor(g, dtype=th.dtype, device=th.device))
                 return torch.as_tensor(ll, dtype=th.dtype, device=th.device)
 
             @staticmethod
             def backward(ctx, gout):
-                (g,) = ctx.saved_tensors
-                gt = gout[:, None] * g
+                if ctx.fg is not None:
+                    gt = ctx.fg.backward(gout.to(device="cuda", dtype=torch.float64))
+                    st = ctx.fg.status.cpu().numpy()
+                    if np.any(st != 0):
+                        raise B.TTError(f"gradient run status bits {np.unique(st)}")
+                    gt = gt.to(dtype=gout.dtype, device=gout.device)
+                else:
+                    (g,) = ctx.saved_tensors
+                    gt = gout[:, None] * g
                 return gt.sum(0) if ctx.shared else gt
 
         return _Fn.apply(theta)

@@ -27,8 +27,9 @@ def kernel_key(spec: WSpec) -> Tuple:
 
 def build_kernels(specs: Sequence[WSpec], precision: int, kernel_cap: int = 32):
     """One device kernel TT per distinct (grid, Q, box), re-packed with
-    capacities equal to its ranks.  Returns (kernels, index per filter,
-    largest interior kernel rank)."""
+    capacities equal to its ranks: the dense TT-SVD build up to d = 8 and
+    2^28 taps, the TT-cross build beyond.  Returns (kernels, index per
+    filter, largest interior kernel rank)."""
     kernels: List[B.DeviceTT] = []
     index: Dict[Tuple, int] = {}
     idx = []
@@ -42,7 +43,13 @@ def build_kernels(specs: Sequence[WSpec], precision: int, kernel_cap: int = 32):
             cap = [1] + [min(kernel_cap, 1024 // taps[j], 1024 // taps[j - 1], int(np.prod(taps[:j])),
                              int(np.prod(taps[j:]))) for j in range(1, s.d)] + [1]
             kt = B.DeviceTT(taps, cap, precision)
-            B.tt_kernel_build(grid_of(s), s.q, hw, s.kernel_tol, kt)
+            if s.d > 8 or float(np.prod([float(t) for t in taps])) > 2.0 ** 28:
+                # no dense tensor: the kernel by TT-cross from point values
+                kt = B.DeviceTT(taps, [1] + [min(kernel_cap, 64, int(min(np.prod(taps[:j]), np.prod(taps[j:]))))
+                                             for j in range(1, s.d)] + [1], precision)
+                B.tt_kernel_build_cross([grid_of(s)], [s.q], hw, s.kernel_tol, [kt], max_rank=64)
+            else:
+                B.tt_kernel_build(grid_of(s), s.q, hw, s.kernel_tol, kt)
             cores, ls, st = kt.fetch()
             if st != 0:
                 raise B.TTError(f"kernel build status {st}")

@@ -147,6 +147,7 @@ WORKLOADS = {
     "range6d_n128_c16": ("d=6 N=128 cap16 range+linear, uniform batch", 256, 100),
     "range6d_ragged": ("d=6 N in {64,96,128} cap in {8,16,24}, ragged batch", 256, 100),
     "range4d_grad": ("d=4 N=128 cap16 differentiated batch", 32, 50),
+    "range10d_n256_c32": ("d=10 N=256 on [-25,25] cap32 range+linear, large batch", 64, 200),
 }
 
 
@@ -181,6 +182,8 @@ def make_batch(name: str, batch: Optional[int] = None, steps: Optional[int] = No
             spec = spec_range(d or 4, n or 128, cap or 16)
         elif name == "range6d_n128_c16":
             spec = spec_range(d or 6, n or 128, cap or 16)
+        elif name == "range10d_n256_c32":
+            spec = spec_range(d or 10, n or 256, cap or 32, lo=-25.0, hi=25.0)
         elif name == "range6d_ragged":
             nn, cc = ragged_choice(choice_seq)
             spec = spec_range(d or 6, n or nn, cap or cc)

@@ -34,28 +34,21 @@ def rel(a, b):
 def test_adjoint_gradient_binding_cap_batch(mods):
     AG, G, wl = mods
     specs, xs, zs = wl.make_batch("range4d", batch=2, steps=5, d=3, n=32, cap=6)
-    print("composed adjoint: 2 filters, d=3, N=32, cap 6, 5 steps", flush=True)
+    print("reverse sweep (tt_filter_run_adjoint): 2 filters, d=3, N=32, cap 6, 5 steps", flush=True)
     ll, g, _ = AG.loglik_grad_adjoint(specs, zs)
     ll_fd, g_fd, _ = G.loglik_grad(specs, zs)
-    # checkpoint segments of two steps, and a checkpoint per step without
-    # the tape: the same computations, bit for bit; with the tape the
-    # rounding adjoint takes the forward's singular vectors of the same
-    # unfoldings, equal up to rounding (amplified by the small kept singular
-    # values, well below this case's distance to the differences)
+    # checkpoint segments of two and of three steps recompute the same
+    # steps: bit for bit the same; the tape (a checkpoint per step) hands the
+    # rounding adjoint the forward's singular vectors of the same unfoldings,
+    # equal up to rounding (amplified by the small kept singular values, well
+    # below this case's distance to the differences)
     ll2, g2, _ = AG.loglik_grad_adjoint(specs, zs, ckpt_every=2)
-    ll1, g1, _ = AG.loglik_grad_adjoint(specs, zs, tape=False)
-    assert np.array_equal(ll1, ll2) and np.array_equal(g1, g2)
-    assert np.array_equal(ll1, ll)
+    ll3, g3, _ = AG.loglik_grad_adjoint(specs, zs, ckpt_every=3)
+    assert np.array_equal(ll2, ll3) and np.array_equal(g2, g3)
+    assert np.array_equal(ll2, ll)
     for b in range(2):
-        print(f"  filter {b}: with vs without the tape {rel(g[b], g1[b]):.1e}", flush=True)
-        assert rel(g[b], g1[b]) < 1e-6
-    # the parameter tangents by forward instead of central differences
-    _, g_f, _ = AG.loglik_grad_adjoint(specs, zs, scheme="forward")
-    with pytest.raises(ValueError):
-        AG.loglik_grad_adjoint(specs, zs, scheme="backward")
-    for b in range(2):
-        print(f"  filter {b}: forward vs central tangents {rel(g_f[b], g[b]):.1e}", flush=True)
-        assert rel(g_f[b], g[b]) < 1e-5
+        print(f"  filter {b}: tape vs checkpoints {rel(g[b], g2[b]):.1e}", flush=True)
+        assert rel(g[b], g2[b]) < 1e-6
         ctx = ctx_of(specs[b], zs[b])
         base = og.loglik_tt(G.theta_of(specs[b]), ctx)
         # same log-likelihood as the oracle and the fused forward
@@ -70,21 +63,37 @@ def test_adjoint_gradient_binding_cap_batch(mods):
         assert rel(g[b], g_or) < 1e-4
 
 
+def test_autograd_wrapper_runs_the_reverse_sweep_in_backward(mods):
+    # forward = the taped recursion only; backward = tt_filter_run_adjoint
+    # seeded with the incoming gradient of LL
+    import torch
+    AG, G, wl = mods
+    specs, xs, zs = wl.make_batch("range4d", batch=2, steps=4, d=3, n=24, cap=5)
+    ll_ref, g_ref, _ = AG.loglik_grad_adjoint(specs, zs)
+    # seeds that are powers of two scale every step exactly; others up to
+    # the rounding noise of the reverse sweep
+    for seed, tol in (([0.5, -2.0], 0.0), ([0.7, -1.3], 1e-6)):
+        th = torch.tensor(np.stack([G.theta_of(s) for s in specs]), dtype=torch.float64, requires_grad=True)
+        ll = G.TTFilterLogLik.apply(th, specs, zs)
+        w = torch.tensor(seed, dtype=torch.float64)
+        (ll * w).sum().backward()
+        assert np.array_equal(ll.detach().numpy(), ll_ref)
+        want = w.numpy()[:, None] * g_ref
+        err = float(np.abs(th.grad.numpy() - want).max() / np.abs(want).max())
+        print(f"  autograd seed {seed}: {err:.1e}", flush=True)
+        assert err <= tol
+
+
 def test_adjoint_gradient_linear_gaussian(mods):
     AG, G, wl = mods
     s = wl.spec_kf2d()
     x, z = wl.simulate(s, 12, np.random.SeedSequence(11))
-    # tangents by central differences (O(h^2), h = 1e-5, the default)
     ll, g, _ = AG.loglik_grad_adjoint([s], [z])
     ctx, th = ctx_of(s, z), G.theta_of(s)
     g_dense = og.grad_complex_step(og.loglik_dense_cs, th, ctx)
     print(f"  linear Gaussian: vs dense {rel(g[0], g_dense):.1e}", flush=True)
     assert rel(g[0], g_dense) < 1e-8
     assert rel(g[0], og.grad_complex_step(og.loglik_kalman_cs, th, ctx)) < 1e-7
-    # forward differences (O(h), h = 1e-7)
-    _, g_f, _ = AG.loglik_grad_adjoint([s], [z], scheme="forward")
-    print(f"  linear Gaussian, forward tangents: vs dense {rel(g_f[0], g_dense):.1e}", flush=True)
-    assert rel(g_f[0], g_dense) < 1e-6
 
 
 def test_adjoint_gradient_loose_cap_matches_dense_complex_step(mods):

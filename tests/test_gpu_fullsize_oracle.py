@@ -15,15 +15,18 @@ norm of the difference TT (normed by an orthogonalisation sweep, no
 cancellation), for FP32 as the exact L1 error of every 1-D and 2-D marginal
 and an importance-sampled estimate of the full L1 error (the dense 128^6
 tensor cannot be formed)."""
-import itertools
-import math
-
 import numpy as np
 import pytest
+
+import os
+import sys
 
 from oracle import filters as flt
 from oracle import model as mdl
 from oracle import tt as ttm
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+from gpu_helpers import l1_marginals, l1_sampled, run_saving_states  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -47,37 +50,11 @@ def refs():
     return specs, zs, axes, out
 
 
-def run_saving_states(specs, zs, precision, keep):
-    """tt_filter_run one step per call; after each step the states of the
-    filters in ``keep`` are saved (tt_filter_state) and fetched."""
-    import torch
-    from paper_2501_07942_amd import binding as B, runner
-    kernels, kidx, kr = runner.build_kernels(specs, precision)
-    fspecs = runner.filter_specs(specs, kidx, kr, 64)
-    z, zdim = runner.z_tensor(zs)
-    run = B.FilterRun(fspecs, kernels, STEPS, zdim, precision)
-    trains = run.state_trains()
-    dens = {b: [] for b in keep}
-    for k in range(STEPS):
-        run(z, k_begin=k, k_count=1)
-        run.save_state(trains)
-        for b in keep:
-            cores, st = trains[b].fetch_scaled()
-            assert st == 0
-            dens[b].append(cores)
-    torch.cuda.synchronize()
-    out = {k: getattr(run, k).cpu().numpy() for k in ("log_c", "log_mpred", "mean", "cov", "ranks", "ranks_pred",
-                                                      "status", "loglik")}
-    del run, trains
-    torch.cuda.empty_cache()
-    return out, dens
-
-
 def test_fp64_path_matches_oracle_at_full_size(refs):
     from paper_2501_07942_amd import binding as B
     specs, zs, axes, ref = refs
     sub = [specs[b] for b in SAMPLED]
-    out, dens = run_saving_states(sub, [zs[b] for b in SAMPLED], B.F64, range(len(SAMPLED)))
+    out, dens = run_saving_states(sub, [zs[b] for b in SAMPLED], B.F64, range(len(SAMPLED)), STEPS)
     for i, b in enumerate(SAMPLED):
         r, s = ref[b], specs[b]
         assert out["status"][i] == 0
@@ -96,38 +73,18 @@ def test_fp64_path_matches_oracle_at_full_size(refs):
         assert err_p <= 1e-10
 
 
-def _l1_marginals(p_gpu, p_ora, delta):
-    """Exact L1 error sum |dm| * (cell volume of the marginal) of every 1-D
-    and 2-D marginal of two densities on the same grid (delta = the spacing
-    per axis); returns the largest."""
-    d = len(p_ora)
-    worst = 0.0
-    for keep in itertools.chain(((l,) for l in range(d)), itertools.combinations(range(d), 2)):
-        dm = ttm.marginal(p_gpu, keep) - ttm.marginal(p_ora, keep)
-        worst = max(worst, float(np.abs(dm).sum()) * delta ** d)
-    return worst
-
-
-def _l1_sampled(p_gpu, p_ora, delta, seed):
-    """Importance-sampled full L1 error sum_i |dP(i)| delta with indices
-    drawn from the oracle's density: mean and standard error."""
-    idx, q = ttm.sample(p_ora, L1_SAMPLES, np.random.default_rng(seed))
-    w = np.abs(ttm.values(p_gpu, idx) - ttm.values(p_ora, idx)) * delta / q
-    return float(w.mean()), float(w.std() / math.sqrt(len(w)))
-
-
 def test_fp32_batch_matches_oracle_at_full_size(refs):
     from paper_2501_07942_amd import binding as B
     specs, zs, axes, ref = refs
-    out, dens = run_saving_states(specs, zs, B.F32, SAMPLED)
+    out, dens = run_saving_states(specs, zs, B.F32, SAMPLED, STEPS)
     assert np.all(out["status"] == 0)
     dx = specs[0].spacing()
     for b in SAMPLED:
         r = ref[b]
         err_c = float(np.abs(out["log_c"][b] - r["log_c"]).max())
         err_m = float(np.abs(out["mean"][b] - r["mean"]).max())
-        l1m = max(_l1_marginals(g, o, dx) for g, o in zip(dens[b], r["densities"]))
-        est = [_l1_sampled(g, o, dx ** len(o), 100 + k) for k, (g, o) in enumerate(zip(dens[b], r["densities"]))]
+        l1m = max(l1_marginals(g, o, dx) for g, o in zip(dens[b], r["densities"]))
+        est = [l1_sampled(g, o, dx ** len(o), 100 + k, L1_SAMPLES) for k, (g, o) in enumerate(zip(dens[b], r["densities"]))]
         l1s, se = max(est)
         print(f"fp32 filter {b}: |dlog c| {err_c:.2e} |dmean|/dx {err_m / dx:.2e} marginal L1 {l1m:.2e}"
               f" sampled L1 {l1s:.2e} +- {se:.1e}")

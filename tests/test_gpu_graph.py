@@ -77,3 +77,21 @@ def test_autotuned_prediction_shape_changes_no_result_bit(mods):
     torch.cuda.synchronize()
     assert np.array_equal(run.log_c.cpu().numpy(), before.log_c.cpu().numpy())
     assert np.array_equal(run.mean.cpu().numpy(), before.mean.cpu().numpy())
+    # the decision persists: saved as JSON keyed by architecture and shape,
+    # adopted again by a load; entries of another architecture are ignored
+    import json
+    import tempfile
+    with tempfile.TemporaryDirectory() as tmp:
+        path = tmp + "/tune.json"
+        B.autotune_save(path)
+        entries = json.load(open(path))
+        mine = [e for e in entries if e["batch"] == 4 and e["n"] == 48 and e["dtype"] == "f32"]
+        assert len(mine) == 1 and mine[0]["value"] == res["best_bb"]
+        assert mine[0]["arch"].startswith("gfx") and mine[0]["rank_cap"] == 8
+        assert B.autotune_load(path) == len(entries)
+        other = [dict(e, arch="gfx000") for e in entries]
+        json.dump(other, open(tmp + "/other.json", "w"))
+        assert B.autotune_load(tmp + "/other.json") == 0
+        open(tmp + "/bad.json", "w").write('[{"arch": "gfx950", "value": 3}]')
+        with pytest.raises(B.TTError):
+            B.autotune_load(tmp + "/bad.json")
