@@ -41,14 +41,14 @@ def log(msg):
 
 
 def run_batch(B, runner, binding, wl, name, batch, steps, warmup, precision, profile_steps=0, seed=None,
-              graph_replays=0, autotune=False):
+              graph_replays=0, autotune=False, lik_rank_cap=64):
     import torch
     total = 1 + warmup + steps + profile_steps
     kw = {} if seed is None else {"seed": seed}
     specs, xs, zs = wl.make_batch(name, batch=batch, steps=total, **kw)
     t0 = time.time()
     kernels, kidx, kr = runner.build_kernels(specs, precision)
-    fspecs = runner.filter_specs(specs, kidx, kr, 64)
+    fspecs = runner.filter_specs(specs, kidx, kr, lik_rank_cap)
     z, zdim = runner.z_tensor(zs)
     run = binding.FilterRun(fspecs, kernels, total, zdim, precision)
     torch.cuda.synchronize()
@@ -460,6 +460,7 @@ def main():
                     help="only time the Einstein-summation prediction, the interpolation onto a new grid and the "
                          "materialised convolution")
     ap.add_argument("--no-ragged", action="store_true", help="skip the ragged batch (N and cap drawn per filter)")
+    ap.add_argument("--no-large", action="store_true", help="skip the d=10, N=256, cap-32 batch of 64 filters")
     ap.add_argument("--grad-steps", type=int, default=50)
     ap.add_argument("--grad-batch", type=int, default=32)
     ap.add_argument("--grad-only", action="store_true",
@@ -592,6 +593,25 @@ def main():
         main_res.clear()  # release the batch's workspace before the gradient runs
         torch.cuda.empty_cache()
         out["grad"] = grad_bench(G, wl, args.grad_steps, args.grad_batch)
+    if not args.no_large:
+        # the large workload: d=10, N=256 on [-25,25]^10, cap 32, 64 filters,
+        # all 200 steps (10 untimed after the first update, 189 timed); the
+        # kernel TT by TT-cross, likelihood blocks up to rank 96
+        main_res.clear()
+        torch.cuda.empty_cache()
+        torch.cuda.reset_peak_memory_stats()
+        lg = run_batch(None, runner, binding, wl, "range10d_n256_c32", 64, 189, 10, binding.F32, lik_rank_cap=96)
+        st = lg["status"]
+        out["large_d10"] = {"workload": "range10d_n256_c32",
+                            "value": round(64 * 189 / (lg["ms"] / 1000.0), 2), "unit": "filter-steps/s",
+                            "ms_per_step": round(lg["ms"] / 189, 3), "filters": 64, "timed_steps": 189,
+                            "failed_filters": int((st != 0).sum()),
+                            "max_rank_last_step": int(lg["run"].ranks[:, -1].max().item()),
+                            "workspace_GB": round(lg["run"].ws.numel() * lg["run"].ws.element_size() / 1e9, 2),
+                            "peak_hbm_GB": round(torch.cuda.max_memory_allocated() / 1e9, 2),
+                            "precision": "fp32 bulk, fp64 Gram/pivoted-Cholesky/Jacobi, fp64 log-normaliser"}
+        lg.clear()
+        torch.cuda.empty_cache()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl)
         if "einsum_predict" in out:

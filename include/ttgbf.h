@@ -156,10 +156,12 @@ tt_status tt_kernel_build_batch(int32_t batch, const tt_grid* grids, const doubl
  * the cores, each fibre matrix f(I_{<k}, i_k, J_{>k}) reduced to an
  * orthonormal basis of its range (the library's rounding of a two-core
  * train; only exactly dependent columns are dropped), maxvol rows of that
- * basis as the next index set, the cores in interpolation form; two sweeps
- * per rank level, the rank starting at 8 and doubling up to max_rank (and
- * to at most 4096 / the largest mode size) while the rounded result's rank
- * at some bond is within 2 of the rank used there.  The result is rounded
+ * basis as the next index set, the cores in interpolation form; at each
+ * rank level sweeps until the rounded result's ranks stop moving (two to
+ * six), the rank starting at 8 and doubling up to max_rank (and to at most
+ * 4096 / the largest mode size) until the rounded ranks have room (2 below
+ * the rank used, or the bond's full rank) and equal those of the previous
+ * level.  The result is rounded
  * (Sec. 4.1 'round') at svd_tol into out.  Synchronous (reads ranks after
  * each level).
  *   grids, q, halfwidths, out  as tt_kernel_build_batch (d <= TT_MAXD,

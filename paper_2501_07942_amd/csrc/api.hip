@@ -294,6 +294,16 @@ struct RoundShape {  // host-side maxima over the batch, for grid sizing
 static const int RQ_MAX_F64 = 256;
 static const int RQ_MAX_F32 = 128;
 
+// Capacity of the ranks kept by the pre-truncation of the right-to-left
+// pass: 256 for FP64; for FP32 128, raised to 8x the output's largest rank
+// capacity (at most 256) so that a wide cap is not starved by it.
+static int rq_limit(bool f64, const int* out_cap, int d) {
+  if (f64) return RQ_MAX_F64;
+  int oc = 1;
+  for (int j = 0; j <= d; ++j) oc = std::max(oc, out_cap[j]);
+  return std::max(RQ_MAX_F32, std::min(2 * RQ_MAX_F32, 8 * oc));
+}
+
 struct RoundBufs {
   DevTT* din = nullptr;
   DevTT* dout = nullptr;
@@ -306,7 +316,7 @@ static void plan_round_scratch(Arena& ar, const DevTT& in, const DevTT& out, boo
                                int splits, RoundScratch& rs) {
   memset(&rs, 0, sizeof(rs));
   const int d = in.d;
-  const int rqmax = f64 ? RQ_MAX_F64 : RQ_MAX_F32;
+  const int rqmax = rq_limit(f64, out.cap, out.d);
   rs.rqcap[0] = 1;
   rs.rqcap[d] = 1;
   for (int j = 1; j < d; ++j) rs.rqcap[j] = std::min(in.cap[j], rqmax);
@@ -1038,17 +1048,18 @@ template <typename TZ, typename TQ, typename F>
 static tt_status launch_trsm(F f, int B, long long mcap, int rcap, hipStream_t st) {
   ProfScope ps_(PC_TRSM, st);
   if constexpr (sizeof(TQ) == 4) {
-    // FP32 bulk: explicit inverse of the pivot block, then one thread per column
-    const size_t lb = (size_t)rcap * rcap * sizeof(double);  // pivot block in LDS
+    // FP32 bulk: explicit inverse of the pivot block (in LDS when it fits),
+    // then one thread per column
+    const size_t lb = (size_t)rcap * rcap * sizeof(double);
     if (lb > 160 * 1024) {
-      set_error("triangular inverse: pivot block of rank %d does not fit in LDS", rcap);
-      return TT_ERR_SHAPE;
+      hipLaunchKernelGGL((tri_inverse_kernel<F, false>), dim3(1, 1, B), dim3(256), 0, st, f);
+    } else {
+      if (lb > 48 * 1024)
+        HIP_TRY(hipFuncSetAttribute((const void*)tri_inverse_kernel<F, true>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lb),
+                "tri inverse smem");
+      hipLaunchKernelGGL((tri_inverse_kernel<F, true>), dim3(1, 1, B), dim3(256), lb, st, f);
     }
-    if (lb > 48 * 1024)
-      HIP_TRY(hipFuncSetAttribute((const void*)tri_inverse_kernel<F>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)lb),
-              "tri inverse smem");
-    hipLaunchKernelGGL((tri_inverse_kernel<F>), dim3(1, 1, B), dim3(256), lb, st, f);
     TTG_LAUNCH_CHECK("tri_inverse_kernel");
     hipLaunchKernelGGL((tri_apply_kernel<TZ, TQ, F>), dim3(stride_grid(cdiv(mcap, 256), B), 1, B), dim3(256), 0,
                        st, f);
@@ -1224,9 +1235,9 @@ static void round_shape(int B, const std::vector<DevTT>& in, const std::vector<D
   sh.B = B;
   sh.d = in[0].d;
   sh.f64 = f64;
-  const int rqmax = f64 ? RQ_MAX_F64 : RQ_MAX_F32;
   int gcap = 1;
   for (int b = 0; b < B; ++b) {
+    const int rqmax = rq_limit(f64, out[b].cap, out[b].d);
     for (int j = 0; j <= sh.d; ++j) {
       sh.rin[j] = std::max(sh.rin[j], in[b].cap[j]);
       sh.rout[j] = std::max(sh.rout[j], out[b].cap[j]);

@@ -681,6 +681,7 @@ static tt_status cross_run(CrossPlan& p, const std::vector<Fn>& fns, double tol,
   const double eps_rank = 1e-16;  // a basis of the fibre matrix's range (exact rank deficiency only)
   const int rtop = std::min(max_rank, p.rmax);
   int r = std::min(8, rtop);
+  std::vector<int> prev_level;
   for (int level = 0;; ++level) {
     std::vector<int> target(TT_MAXD + 1, 1);
     for (int k = 1; k < d; ++k) target[k] = (int)std::min<long long>(r, p.bound[k]);
@@ -763,7 +764,10 @@ static tt_status cross_run(CrossPlan& p, const std::vector<Fn>& fns, double tol,
       prev_got = got;
       if (stable || !slack) break;
     }
-    if (slack || r >= rtop) break;
+    // done when the ranks have room at this level and did not move from the
+    // previous level's (a doubled rank found nothing more)
+    if ((slack && prev_got == prev_level) || r >= rtop) break;
+    prev_level = prev_got;
     r = std::min(2 * r, rtop);
   }
   if (f32) {

@@ -813,25 +813,28 @@ __global__ void __launch_bounds__(256) trsm_f64_kernel(F f) {
 // one thread, which accumulates 32 rows at a time in FP64 registers while W
 // is read with wave-uniform loads.
 // ---------------------------------------------------------------------------
-template <typename F>
+template <typename F, bool InLds>
 __global__ void __launch_bounds__(256) tri_inverse_kernel(F f) {
   const int b = blockIdx.z;
   TrsmArgs a;
   if (!f(b, a)) return;
   // the pivot block L_pp (lower triangle, row j = lfac row piv[j]) in LDS
+  // when it fits, else read in place (only t <= j is ever touched)
   extern __shared__ double lpp[];  // [r][r]
   const int r = a.r;
-  for (int e = threadIdx.x; e < r * r; e += blockDim.x) {
-    const int j = e / r, t = e - (e / r) * r;
-    lpp[e] = (t <= j) ? a.lfac[(long long)a.piv[j] * a.gcap + t] : 0.0;
+  if (InLds) {
+    for (int e = threadIdx.x; e < r * r; e += blockDim.x) {
+      const int j = e / r, t = e - (e / r) * r;
+      lpp[e] = (t <= j) ? a.lfac[(long long)a.piv[j] * a.gcap + t] : 0.0;
+    }
+    __syncthreads();
   }
-  __syncthreads();
   double* wt = a.wbuf;
   for (int c = threadIdx.x; c < r; c += blockDim.x) {
     double* w = wt + (long long)c * a.gcap;
     for (int j = 0; j < c; ++j) w[j] = 0.0;
     for (int j = c; j < r; ++j) {
-      const double* lrow = lpp + (long long)j * r;
+      const double* lrow = InLds ? lpp + (long long)j * r : a.lfac + (long long)a.piv[j] * a.gcap;
       double s = (j == c) ? 1.0 : 0.0;
 #pragma unroll 4
       for (int t = c; t < j; ++t) s = __fma_rn(-lrow[t], w[t], s);
@@ -841,27 +844,32 @@ __global__ void __launch_bounds__(256) tri_inverse_kernel(F f) {
 }
 
 #define TA_ROWS 32
-#define TA_TMAX 128  // largest pivot block (the FP32 pre-truncated rank capacity)
+#define TA_TMAX 128  // rows of W staged in LDS at a time
 template <typename TZ, typename TQ, typename F>
 __global__ void __launch_bounds__(256) tri_apply_kernel(F f) {
   const int b = blockIdx.z;
   TrsmArgs a;
   if (!f(b, a)) return;
   if (blockIdx.x * 256 >= a.m) return;
-  __shared__ double ws[TA_TMAX * TA_ROWS];  // W(j0 + u, t) at ws[t * 32 + u], zero past row r
+  __shared__ double ws[TA_TMAX * TA_ROWS];  // W(j0 + u, t0 + t) at ws[t * 32 + u], zero past row r
   const TZ* z = reinterpret_cast<const TZ*>(a.z);
   TQ* q = reinterpret_cast<TQ*>(a.q);
   const double* wt = a.wbuf;
-  const int r = min(a.r, TA_TMAX);
+  const int r = a.r;
   for (int j0 = 0; j0 < r; j0 += TA_ROWS) {
     const int tend = min(r, j0 + TA_ROWS);  // W(j, t) = 0 for t > j
     const int jn = min(TA_ROWS, r - j0);
-    __syncthreads();  // previous chunk consumed
-    for (int e = threadIdx.x; e < tend * TA_ROWS; e += blockDim.x) {
-      const int t = e / TA_ROWS, u = e - t * TA_ROWS;
-      ws[e] = u < jn ? wt[(long long)t * a.gcap + j0 + u] : 0.0;
-    }
-    __syncthreads();
+    // stage W(j0.., t0..t1) (workgroup-uniform calls)
+    auto stage = [&](int t0, int t1) {
+      __syncthreads();  // previous chunk consumed
+      for (int e = threadIdx.x; e < (t1 - t0) * TA_ROWS; e += blockDim.x) {
+        const int t = e / TA_ROWS, u = e - t * TA_ROWS;
+        ws[e] = u < jn ? wt[(long long)(t0 + t) * a.gcap + j0 + u] : 0.0;
+      }
+      __syncthreads();
+    };
+    const bool once = tend <= TA_TMAX;  // every t of this chunk fits at once
+    if (once) stage(0, tend);
     // grid-stride over 256-column blocks: the grid is sized for the usual
     // width, not the capacity, so few workgroups start with nothing to do
     for (int cb = blockIdx.x; cb * 256 < a.m; cb += gridDim.x) {
@@ -875,12 +883,16 @@ __global__ void __launch_bounds__(256) tri_apply_kernel(F f) {
       double acc[TA_ROWS];
 #pragma unroll
       for (int u = 0; u < TA_ROWS; ++u) acc[u] = 0.0;
+      for (int t0 = 0; t0 < tend; t0 += TA_TMAX) {
+        const int t1 = min(tend, t0 + TA_TMAX);
+        if (!once) stage(t0, t1);
 #pragma unroll 2
-      for (int t = 0; t < tend; ++t) {
-        const double zv = bulk_to_double(z[(long long)a.piv[t] * a.ldz + zc]);
-        const double* wrow = ws + t * TA_ROWS;
+        for (int t = t0; t < t1; ++t) {
+          const double zv = bulk_to_double(z[(long long)a.piv[t] * a.ldz + zc]);
+          const double* wrow = ws + (t - t0) * TA_ROWS;
 #pragma unroll
-        for (int u = 0; u < TA_ROWS; ++u) acc[u] = __fma_rn(wrow[u], zv, acc[u]);
+          for (int u = 0; u < TA_ROWS; ++u) acc[u] = __fma_rn(wrow[u], zv, acc[u]);
+        }
       }
       if (live) {
 #pragma unroll

@@ -1,0 +1,82 @@
+"""Oracle parity of the whole recursion on the large workload: d=10, N=256
+points per axis on [-25,25]^10, rank cap 32, 64 filters in one FP32-bulk
+batch (the launch configuration the throughput measurement times), the
+41-tap kernel TT built by TT-cross on both sides (no dense tensor exists at
+this size).  Steps 0..2 (update; then prediction, rounding, normalisation,
+update, rounding, normalisation in the loop order of Alg. 2) of sampled
+filters are compared with the oracle's FP64 run of the same filter: log c_k
+(eq. pmf_filtrace_b), the posterior means in grid steps, the exact L1 error
+of every 1-D and 2-D marginal and an importance-sampled estimate of the full
+L1 error (the 256^10 tensor cannot be formed)."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import cross as ocr
+from oracle import filters as flt
+from oracle import model as mdl
+from oracle import tt as ttm
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+from gpu_helpers import l1_marginals, l1_sampled, run_saving_states  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+STEPS = 3
+SAMPLED = (0, 41)
+L1_SAMPLES = 20000
+
+
+@pytest.fixture(scope="module")
+def refs():
+    from paper_2501_07942_amd import workload as wl
+    specs, xs, zs = wl.make_batch("range10d_n256_c32", steps=STEPS)
+    s = specs[0]
+    axes = mdl.grid_axes([s.lo] * s.d, [s.hi] * s.d, [s.n] * s.d)
+    print(f"oracle: kernel TT by cross (d={s.d}, taps {2 * s.halfwidths()[0] + 1})", flush=True)
+    kern = ocr.kernel_tt_cross(s.q, axes, s.halfwidths(), s.kernel_tol)
+    out = {}
+    for b in SAMPLED:
+        sb = specs[b]
+        print(f"oracle: filter {b}, {STEPS} steps", flush=True)
+        out[b] = flt.run_tt_filter(axes, sb.q, sb.halfwidths(), sb.meas(), zs[b], sb.m0, sb.p0_diag, sb.cap,
+                                   sb.eps, kernel=kern, record_density=True)
+    return specs, zs, kern, out
+
+
+def test_fp32_batch_of_64_matches_oracle(refs):
+    from paper_2501_07942_amd import binding as B
+    specs, zs, kern, ref = refs
+    assert len(specs) == 64
+    out, dens = run_saving_states(specs, zs, B.F32, SAMPLED, STEPS)
+    assert np.all(out["status"] == 0)
+    dx = specs[0].spacing()
+    for b in SAMPLED:
+        r = ref[b]
+        err_c = float(np.abs(out["log_c"][b] - r["log_c"]).max())
+        err_m = float(np.abs(out["mean"][b] - r["mean"]).max())
+        l1m = max(l1_marginals(g, o, dx) for g, o in zip(dens[b], r["densities"]))
+        est = [l1_sampled(g, o, dx ** len(o), 300 + k, L1_SAMPLES)
+               for k, (g, o) in enumerate(zip(dens[b], r["densities"]))]
+        l1s, se = max(est)
+        print(f"fp32 filter {b}: ranks {out['ranks'][b][-1].tolist()} (oracle {r['ranks_filt'][-1]}) "
+              f"|dlog c| {err_c:.2e} |dmean|/dx {err_m / dx:.2e} marginal L1 {l1m:.2e} sampled L1 {l1s:.2e} +- {se:.1e}",
+              flush=True)
+        assert err_m <= 1e-3 * dx
+        assert err_c <= 1e-4
+        assert l1m <= 1e-4
+        assert l1s + 3.0 * se <= 1e-4
+
+
+def test_device_cross_kernel_matches_oracle_cross(refs):
+    from paper_2501_07942_amd import binding as B, runner
+    specs, zs, kern, ref = refs
+    kernels, kidx, kr = runner.build_kernels(specs[:1], B.F64)
+    cores, st = kernels[0].fetch_scaled()
+    assert st == 0
+    rel = ttm.rel_diff(cores, kern)
+    print(f"kernel: ranks {ttm.ranks(cores)} (oracle {ttm.ranks(kern)}), rel {rel:.1e}", flush=True)
+    assert ttm.ranks(cores) == ttm.ranks(kern)
+    assert rel <= 1e-10
