@@ -206,6 +206,34 @@ def grad_bench(G, wl, steps, batch):
                             "ms_base": round(info["ms_base"], 1), "ms_perturbed": round(info["ms_perturbed"], 1)}}
 
 
+def grad_large_bench(wl, steps=20, batch=16, ckpt=10):
+    """The FP64 gradient on the large workload (d=10, N=256 on [-25,25]^10,
+    cap 32; 14 parameters: ten process-noise deviations, range and linear
+    deviations, sensor position) by the reverse sweep with a checkpoint every
+    `ckpt` steps, the kernel TT and its tangents by TT-cross: one untimed call
+    over two steps, then one timed call over `steps` steps for `batch`
+    filters (the FP64 workspace of one filter is about 13 GB)."""
+    import torch
+    from paper_2501_07942_amd import adjoint_grad as AG
+    specs, xs, zs = wl.make_batch("range10d_n256_c32", batch=batch, steps=steps)
+    AG.loglik_grad_adjoint(specs, [z[:2] for z in zs], ckpt_every=ckpt)
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    torch.cuda.reset_peak_memory_stats()
+    base_mem = torch.cuda.memory_allocated()
+    t0 = time.perf_counter()
+    ll, g, _ = AG.loglik_grad_adjoint(specs, zs, ckpt_every=ckpt)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    peak_gb = (torch.cuda.max_memory_allocated() - base_mem) / 1e9
+    return {"value": round(ms / steps, 2), "unit": "ms per batched step (forward + gradient)",
+            "filter_steps_per_s": round(batch * steps / (ms / 1000.0), 2), "workload": "range10d_n256_c32",
+            "d": 10, "N": 256, "rank_cap": 32, "filters": batch, "steps": steps, "n_theta": int(g.shape[1]),
+            "precision": "fp64", "checkpoint_every": ckpt, "peak_hbm_GB": round(peak_gb, 2),
+            "method": "tt_filter_run_taped + tt_filter_run_adjoint with checkpoints (segments recomputed), "
+                      "kernel TT and its 2d perturbed builds by TT-cross in one batched call"}
+
+
 def einsum_bench(binding, batch=64, d=4, n=64, rt=64, rp=16, calls=10):
     """The Einstein-summation prediction (Alg. 1, tt_predict_einsum) on a
     batch of FP64 filters with random 2d-core transition trains (inner
@@ -612,6 +640,9 @@ def main():
                             "precision": "fp32 bulk, fp64 Gram/pivoted-Cholesky/Jacobi, fp64 log-normaliser"}
         lg.clear()
         torch.cuda.empty_cache()
+        if not args.no_grad:
+            out["large_d10"]["grad"] = grad_large_bench(wl)
+            torch.cuda.empty_cache()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl)
         if "einsum_predict" in out:

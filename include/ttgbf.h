@@ -165,8 +165,12 @@ tt_status tt_kernel_build_batch(int32_t batch, const tt_grid* grids, const doubl
  * (Sec. 4.1 'round') at svd_tol into out.  Synchronous (reads ranks after
  * each level).
  *   grids, q, halfwidths, out  as tt_kernel_build_batch (d <= TT_MAXD,
- *              2 h_l + 1 <= 4096 taps); max_rank in [1, 64]; out FP64 or
- *              FP32.
+ *              2 h_l + 1 <= 4096 taps); out FP64 or FP32, its capacities
+ *              bound the result's ranks (TT_STATUS_CAPACITY when a rank
+ *              needs more).
+ *   max_rank   in [1, 64]: the working rank of the cross, not the result's
+ *              cap; a search stopped by it before the ranks have room is
+ *              not converged, so it should exceed the expected ranks by 2.
  * Workspace: tt_kernel_build_cross_workspace(batch, grids, halfwidths, out).
  * Errors: TT_ERR_ARG (null, svd_tol <= 0, max_rank out of range, Q not
  * positive definite), TT_ERR_SHAPE, TT_ERR_WORKSPACE, TT_ERR_HIP.
@@ -506,9 +510,11 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
  * log_scale fields: the derivative <a_bar, db> of the scalar that a_bar is
  * the adjoint of, for a tangent db of the train b.
  *
- * tt_align_signs: flips the sign of each bond index of t (in both adjacent
- * cores, so the tensor is unchanged) to correlate positively with ref,
- * bond by bond from the left: puts a truncated-SVD build at perturbed
+ * tt_align_signs: rotates each bond basis of t (in both adjacent cores, so
+ * the tensor is unchanged) by the orthogonal polar factor of its cosine
+ * matrix with ref's, bond by bond from the left (sign flips, and rotations
+ * among nearly equal singular values; a bond with a cosine singular value
+ * below 1e-6 is left as is): puts a truncated-SVD build at perturbed
  * parameters into the basis of the build at the base parameters.
  * Workspace for the last three: tt_adjoint_workspace.
  * --------------------------------------------------------------------- */
@@ -632,9 +638,15 @@ tt_status tt_filter_run(int32_t batch, const tt_filter_spec* specs, const tt_tra
  * The measurement parameters enter through the dense likelihood, whose
  * theta-derivative is analytic (the log-derivatives of the range and linear
  * Gaussian factors, evaluated on the device); sigma_w enters through the
- * kernel TT, whose tangent is the central difference of two device TT-SVD
- * builds at sigma_w[j] +- h_j (h_j = 1e-5 max(1, sigma_w[j])) put into the
- * base build's bond bases (tt_align_signs), the quotient taken on the device.
+ * kernel TT, whose tangent is the central difference of two device builds at
+ * sigma_w[j] +- h_j (h_j = 1e-5 max(1, sigma_w[j])) put into the base
+ * build's bond bases (tt_align_signs), the quotient taken on the device.
+ * The builds are the dense TT-SVD up to d = 8 and 2^28 taps; beyond, the
+ * base kernel is a TT-cross (as tt_kernel_build_cross, working rank 64)
+ * whose index sets, row choices and ranks are kept, and the 2d perturbed
+ * kernels (built in one batched call) are the same cross replayed on those
+ * index sets and rounded to the base ranks, so that they change smoothly
+ * with sigma_w.
  * status_dev[b] (both calls) receives the OR of the filter's TT_STATUS_*
  * bits (TT_STATUS_CAPACITY also when a perturbed kernel build changes a
  * rank); the caller clears it before the taped run.  Both calls synchronise

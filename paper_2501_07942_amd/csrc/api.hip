@@ -383,6 +383,7 @@ struct RCtx {
   const FusedPred* FP = nullptr;  //                   FFT descriptors
   int fused = 0;                  // interior Z_k come from the fused path
   int zt = 0;                     // ... in (j, i) column order (FFT variant)
+  double tau2_flag = 0.0;         // pre-truncation losses below this x ||X||^2 are not a capacity failure
 };
 
 template <typename T>
@@ -534,6 +535,7 @@ struct FRlPchol {
     p.gcap = s.gcap;
     p.rmax = s.rqcap[k];
     p.tau2 = c.tau2;
+    p.tau2_flag = c.tau2_flag;
     return true;
   }
 };
@@ -1187,6 +1189,10 @@ static tt_status round_launch(const RoundShape& sh, const RoundBufs& rb, double 
     const bool mg = sh.merge && k == 1;  // some filter may fold core 0 into this step
     if (mg) TT_TRY((launch_gemm<T, T, T, T>(FRlMerge<T>{c}, B, sh.n[0], (long long)sh.n[1] * sh.rq[2], st)));
     c.tau2 = tau2_rl;
+    // the pre-truncation to rqcap ranks fails only when it drops more than
+    // (1% of the rounding's tolerance)^2 of ||X||^2 (the result then still
+    // meets eps); at eps = 0 any drop above the precision's level fails
+    c.tau2_flag = (0.01 * eps) * (0.01 * eps);
     const int mcap = (k == 1) ? std::min(sh.rin[1], std::max(sh.n[0], 1)) : sh.rin[k];
     TT_TRY((launch_gram<T, Acc>(FRlGram<T>{c}, B, mcap, (long long)sh.n[k] * sh.rq[k + 1], sh.splits, st)));
     TT_TRY((launch_pchol<Acc>(FRlPchol{c}, B, sh.gcap, st)));
@@ -1414,6 +1420,32 @@ tt_status tt_round(int32_t batch, const tt_train* t_in, const tt_train* t_out, d
 }
 
 }  // extern "C"
+
+namespace ttg {
+
+// tt_round with the rank of every bond j forced to forced[b * fstride + j]
+// (device; rank replay, clamped to the numerical rank and the capacity like
+// the rule)
+static tt_status round_forced(int32_t batch, const tt_train* t_in, const tt_train* t_out, const int* forced,
+                              long long fstride, void* ws, size_t ws_bytes, hipStream_t st) {
+  Arena ar(ws, ws_bytes);
+  RoundShape sh;
+  RoundBufs rb;
+  std::vector<DevTT> vin, vout;
+  std::vector<RoundScratch> vrs;
+  TT_TRY(round_plan(batch, t_in, t_out, ar, sh, rb, vin, vout, vrs));
+  if (!ar.fits()) {
+    set_error("tt_round (forced ranks): workspace too small (%zu < %zu)", ws_bytes, ar.used);
+    return TT_ERR_WORKSPACE;
+  }
+  TT_TRY(upload(rb.din, vin, st));
+  TT_TRY(upload(rb.dout, vout, st));
+  TT_TRY(upload(rb.drs, vrs, st));
+  if (sh.f64) return round_launch<double, AccDD>(sh, rb, 0.0, 1 << 30, st, nullptr, forced, fstride);
+  return round_launch<float, AccD>(sh, rb, 0.0, 1 << 30, st, nullptr, forced, fstride);
+}
+
+}  // namespace ttg
 
 // ===========================================================================
 // adjoint of the rounding (FP64): host orchestration of the phases described
@@ -1963,7 +1995,7 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
       if (k == 1 && f.wide0) pa.M = 0;  // F_0 is not needed: M_0's SVD comes from S_0
       if (rec) pa.M = 0;
       pj.push_back(pa);
-      mcap = std::max(mcap, R0);
+      if (!w1) mcap = std::max(mcap, R0);  // (a folded first bond has no Gram here)
       tcap = std::max(tcap, (long long)n * R1);
     }
     TT_TRY(R.gemm());
@@ -1997,9 +2029,9 @@ tt_status tt_round_adjoint(int32_t batch, const tt_train* a, const tt_train* y, 
   // phase 2/3, core by core: N_k = W_k x_1 A_k, M_k = N_k F_k and its
   // Jacobi SVD; the kept vectors of that SVD (signs matched to the forward's
   // output) become U_k, and W_{k+1} = U_k^T N_k
-  int gmax = 1;
+  int gmax = 1;  // the largest Gram of these phases (n[0] for a folded first bond)
   for (int b = 0; b < batch; ++b)
-    for (int k = 0; k < d; ++k) gmax = std::max(gmax, F[b].Ra[k + 1]);
+    for (int k = 0; k < d; ++k) gmax = std::max(gmax, (k == 0 && F[b].wide0) ? F[b].n[0] : F[b].Ra[k + 1]);
   if (gmax > 1024) {
     set_error("tt_round_adjoint: rank above 1024");
     return TT_ERR_SHAPE;
@@ -5353,6 +5385,6 @@ tt_status tt_autotune_prediction(int32_t batch, const tt_filter_spec* specs, con
 
 }  // extern "C"
 
-#include "grad_run.h"
 #include "cross.h"
+#include "grad_run.h"
 #include "linear_run.h"

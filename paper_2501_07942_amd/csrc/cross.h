@@ -97,13 +97,26 @@ struct CrossInterpFn {
 //   iset + (k * CROSS_RMAX + a) * TT_MAXD: tuple a of I_k (axes 0..k-1)
 //   jset + (k * CROSS_RMAX + a) * TT_MAXD: tuple a of J_k (axes k..d-1)
 //   cnt[0..d]: counts of I_k, cnt[TT_MAXD+1 + k]: counts of J_k
+//   rowsk + k * CROSS_RMAX: the maxvol rows that made J_k and core k (the
+//   last right-to-left pass), ruk[k] the rank of that fibre matrix's basis
+//   and seedk + k * CROSS_RMAX the rows that completed it; tgt[0..d]: the
+//   rank targets of the last level
+// iset, jset, cnt, rowsk, ruk, seedk and tgt are one block of
+// CROSS_STATE_INTS ints, so that a finished cross can be saved and replayed.
 struct CrossState {
   int* iset;
   int* jset;
   int* cnt;
+  int* rowsk;
+  int* ruk;
+  int* seedk;
+  int* tgt;
   double* work;  // maxvol scratch: m x r working copy, B, r x 2r inverse
   int* rows;     // maxvol pivots
 };
+static const long long CROSS_SET_INTS = (long long)(TT_MAXD + 1) * CROSS_RMAX * TT_MAXD;
+static const long long CROSS_STATE_INTS =
+    2 * CROSS_SET_INTS + 2 * (TT_MAXD + 1) + 2LL * (TT_MAXD + 1) * CROSS_RMAX + 2 * (TT_MAXD + 1);
 
 // Fibre matrix of core k as core 0 of the two-core train T (rows_cap rows,
 // R columns), core 1 of T the R x R identity.
@@ -191,14 +204,17 @@ __global__ void cross_first_core_kernel(const Fn* __restrict__ fn, const CrossSt
 //   dir 1: rows i * bcap + b -> J_k[j] = (i, J_{k+1}[b]), cnt J_k = r, and
 //          core k of Y (r, n_k, |J_{k+1}|) = B^T
 // One workgroup per filter.
+// frozen (dir 1 only): the rows are the saved rowsk of bond k and the rank
+// the saved count of J_k (a cross replayed on the index sets of another).
 __global__ void __launch_bounds__(256) cross_maxvol_kernel(const DevTT* __restrict__ U, const CrossState* __restrict__ cs,
                                                            const DevTT* __restrict__ Y, int k, int nk, int dir, int m,
-                                                           int bcap, int want) {
+                                                           int bcap, int want, int frozen = 0) {
   const int f = blockIdx.x;
   const DevTT& u = U[f];
   const CrossState& S = cs[f];
-  const int r0 = u.ranks[1];                 // the rounding's basis of M's range
-  const int r = max(r0, min(want, m));       // its width after completion
+  const int ru = u.ranks[1];                                              // the rounding's basis of M's range
+  const int r = frozen ? S.cnt[TT_MAXD + 1 + k] : max(ru, min(want, m));  // its width after completion
+  const int r0 = min(ru, r);                                              // basis columns kept
   const double* u0 = core_ptr<double>(u, 0);
   double* Uc = S.work;                                  // m x r, the (completed) basis
   double* W = Uc + (long long)m * CROSS_RMAX;           // m x r, elimination copy
@@ -218,7 +234,7 @@ __global__ void __launch_bounds__(256) cross_maxvol_kernel(const DevTT* __restri
   for (long long e = tid; e < (long long)m * r; e += blockDim.x) {
     const long long i = e / r;
     const int c = (int)(e % r);
-    Uc[e] = c < r0 ? u0[i * r0 + c] : 0.0;
+    Uc[e] = c < r0 ? u0[i * ru + c] : 0.0;
   }
   __syncthreads();
   // A rank-deficient fibre matrix leaves fewer basis vectors than rows to
@@ -226,32 +242,37 @@ __global__ void __launch_bounds__(256) cross_maxvol_kernel(const DevTT* __restri
   // least leverage, orthogonalised twice (the pivots then still explore
   // the whole target rank)
   for (int c = r0; c < r; ++c) {
-    double best = 1e300;
-    int bi = m;
-    for (int p = tid; p < m; p += blockDim.x) {
-      const bool ok = dir == 0 ? (p / nk) < cvalid : (p % bcap) < cvalid;
-      bool seeded = false;
-      for (int q = 0; q < c - r0; ++q) seeded = seeded || s_seed[q] == p;
-      if (!ok || seeded) continue;
-      double lev = 0.0;
-      for (int q = 0; q < c; ++q) lev += Uc[(long long)p * r + q] * Uc[(long long)p * r + q];
-      if (lev < best) {
-        best = lev;
-        bi = p;
+    int p;
+    if (frozen) {
+      p = S.seedk[k * CROSS_RMAX + (c - r0)];  // the completion of the replayed cross
+    } else {
+      double best = 1e300;
+      int bi = m;
+      for (int q = tid; q < m; q += blockDim.x) {
+        const bool ok = dir == 0 ? (q / nk) < cvalid : (q % bcap) < cvalid;
+        bool seeded = false;
+        for (int u2 = 0; u2 < c - r0; ++u2) seeded = seeded || s_seed[u2] == q;
+        if (!ok || seeded) continue;
+        double lev = 0.0;
+        for (int u2 = 0; u2 < c; ++u2) lev += Uc[(long long)q * r + u2] * Uc[(long long)q * r + u2];
+        if (lev < best) {
+          best = lev;
+          bi = q;
+        }
       }
-    }
-    sv[tid] = best;
-    si[tid] = bi;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-      if (tid < o && (sv[tid + o] < sv[tid] || (sv[tid + o] == sv[tid] && si[tid + o] < si[tid]))) {
-        sv[tid] = sv[tid + o];
-        si[tid] = si[tid + o];
+      sv[tid] = best;
+      si[tid] = bi;
+      __syncthreads();
+      for (int o = 128; o > 0; o >>= 1) {
+        if (tid < o && (sv[tid + o] < sv[tid] || (sv[tid + o] == sv[tid] && si[tid + o] < si[tid]))) {
+          sv[tid] = sv[tid + o];
+          si[tid] = si[tid + o];
+        }
+        __syncthreads();
       }
+      p = si[0];
       __syncthreads();
     }
-    const int p = si[0];
-    __syncthreads();
     if (tid == 0) s_seed[c - r0] = p;
     if (p >= m) break;  // no valid row left (cannot happen when the target fits the valid rows)
     for (int i = tid; i < m; i += blockDim.x) {
@@ -280,9 +301,11 @@ __global__ void __launch_bounds__(256) cross_maxvol_kernel(const DevTT* __restri
   }
   const double* uc = Uc;
   for (long long e = tid; e < (long long)m * r; e += blockDim.x) W[e] = uc[e];
+  if (frozen)
+    for (int j = tid; j < r; j += blockDim.x) s_used[j] = S.rowsk[k * CROSS_RMAX + j];
   __syncthreads();
   // Gaussian elimination with partial pivoting for the initial rows
-  for (int j = 0; j < r; ++j) {
+  for (int j = 0; j < (frozen ? 0 : r); ++j) {
     double best = -1.0;
     int bi = 0;
     for (int i = tid; i < m; i += blockDim.x) {
@@ -372,7 +395,7 @@ __global__ void __launch_bounds__(256) cross_maxvol_kernel(const DevTT* __restri
   for (int j = tid; j < r; j += blockDim.x) rows[j] = s_used[j];
   __syncthreads();
   // swaps while some |B_ij| > 1.05 (each multiplies the volume by |B_ij|)
-  for (int it = 0; it < 8 * CROSS_RMAX; ++it) {
+  for (int it = 0; it < (frozen ? 0 : 8 * CROSS_RMAX); ++it) {
     double best = -1.0;
     int bi = 0;
     for (long long e = tid; e < (long long)m * r; e += blockDim.x) {
@@ -445,6 +468,9 @@ __global__ void __launch_bounds__(256) cross_maxvol_kernel(const DevTT* __restri
       const int i = rem / cj, b = rem % cj;
       yc[e] = Bm[(long long)(i * bcap + b) * r + j];
     }
+    for (int j = tid; j < r; j += blockDim.x) S.rowsk[k * CROSS_RMAX + j] = rows[j];
+    for (int c = tid; c < r - r0; c += blockDim.x) S.seedk[k * CROSS_RMAX + c] = s_seed[c];
+    if (tid == 0) S.ruk[k] = r0;
     if (tid == 0) {
       S.cnt[TT_MAXD + 1 + k] = r;
       y.ranks[k] = r;
@@ -466,9 +492,11 @@ __device__ inline unsigned long long cross_mix(unsigned long long x) {
 }
 
 __global__ void cross_extend_kernel(const CrossState* __restrict__ cs, const int* __restrict__ n, int d,
-                                    const int* __restrict__ target, unsigned long long seed) {
+                                    const int* __restrict__ target, unsigned long long seed,
+                                    const int* __restrict__ ids) {
   const int f = blockIdx.x;
   const CrossState& S = cs[f];
+  const unsigned long long id = (unsigned long long)ids[f];  // the generator's stream of this function
   for (int k = threadIdx.x + 1; k < d; k += blockDim.x) {
     const int have = S.cnt[TT_MAXD + 1 + k];
     const int want = target[k];
@@ -490,7 +518,7 @@ __global__ void cross_extend_kernel(const CrossState* __restrict__ cs, const int
         for (int attempt = 0; attempt < 64; ++attempt) {
           for (int l = k; l < d; ++l) {
             const unsigned long long h = cross_mix(
-                seed ^ cross_mix(((unsigned long long)f << 44) ^ ((unsigned long long)k << 36) ^
+                seed ^ cross_mix((id << 44) ^ ((unsigned long long)k << 36) ^
                                  ((unsigned long long)a << 24) ^ ((unsigned long long)attempt << 8) ^
                                  (unsigned long long)l));
             t[l - k] = (a == 0 && attempt == 0) ? n[l] / 2 : (int)(h % (unsigned long long)n[l]);
@@ -517,6 +545,15 @@ __global__ void cross_extend_kernel(const CrossState* __restrict__ cs, const int
 }  // namespace ttg
 
 namespace ttg {
+
+// ranks [1, ruk[k], 1] of the two-core fibre train of bond k (replay)
+__global__ void cross_ru_kernel(const CrossState* __restrict__ cs, int nf, int k, int* __restrict__ out) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nf) return;
+  out[f * 3] = 1;
+  out[f * 3 + 1] = max(1, cs[f].ruk[k]);
+  out[f * 3 + 2] = 1;
+}
 
 // the cross TT's log-scale and status before its rounding
 __global__ void cross_y_init_kernel(const DevTT* __restrict__ Y, int nf) {
@@ -552,6 +589,8 @@ struct CrossPlan {
   int* dn = nullptr;
   int* dtarget = nullptr;
   int* dranks = nullptr;  // batch x (d+1) ranks read back after a level
+  int* dids = nullptr;    // generator stream per function
+  int* dru = nullptr;     // batch x 3 forced ranks of a fibre matrix's rounding (replay)
   DevTT* tab = nullptr;   // 2 * batch descriptors
   std::vector<tt_train> T2, T2r, Y, Z;
   void* rws = nullptr;
@@ -617,6 +656,8 @@ static tt_status cross_plan(int batch, int d, const int* n, int max_rank, size_t
   p.dn = ar.take<int>(TT_MAXD);
   p.dtarget = ar.take<int>(TT_MAXD + 1);
   p.dranks = ar.take<int>((size_t)batch * (TT_MAXD + 1));
+  p.dids = ar.take<int>(batch);
+  p.dru = ar.take<int>((size_t)batch * 3);
   p.tab = ar.take<DevTT>((size_t)2 * batch);
   const int n2[2] = {p.mmax, p.rmax};
   const int c2[3] = {1, p.rmax, 1};
@@ -629,9 +670,14 @@ static tt_status cross_plan(int batch, int d, const int* n, int max_rank, size_t
   const bool f32 = out[0].dtype == TT_F32;
   for (int b = 0; b < batch; ++b) {
     CrossState& s = p.cs[b];
-    s.iset = ar.take<int>((size_t)(d + 1) * CROSS_RMAX * TT_MAXD);
-    s.jset = ar.take<int>((size_t)(d + 1) * CROSS_RMAX * TT_MAXD);
-    s.cnt = ar.take<int>(2 * (TT_MAXD + 1));
+    int* blob = ar.take<int>((size_t)CROSS_STATE_INTS);
+    s.iset = blob;
+    s.jset = blob + CROSS_SET_INTS;
+    s.cnt = blob + 2 * CROSS_SET_INTS;
+    s.rowsk = s.cnt + 2 * (TT_MAXD + 1);
+    s.ruk = s.rowsk + (TT_MAXD + 1) * CROSS_RMAX;
+    s.seedk = s.ruk + (TT_MAXD + 1);
+    s.tgt = s.seedk + (TT_MAXD + 1) * CROSS_RMAX;
     s.work = ar.take<double>((size_t)3 * p.mmax * CROSS_RMAX + 2 * CROSS_RMAX * CROSS_RMAX);
     s.rows = ar.take<int>(CROSS_RMAX);
     p.T2[b] = cross_train(ar, 2, n2, c2);
@@ -662,13 +708,24 @@ static tt_status cross_upload_pair(CrossPlan& p, const std::vector<tt_train>& a,
 
 // The cross of the functions fns[b] (one per output), rounded at tol into
 // out (capacities cap bound the ranks).  Synchronises after each rank level.
+// ids (empty: 0, 1, ...) name each function's stream of random tuples;
+// forced (device, nullable) replaces the final rounding's rank rule by the
+// ranks forced[b * fstride + j] (rank replay).
+// state_save (device, nullable): each function's final index sets, row
+// choices and targets (CROSS_STATE_INTS ints per function) for cross_frozen.
 template <typename Fn>
 static tt_status cross_run(CrossPlan& p, const std::vector<Fn>& fns, double tol, int max_rank, const tt_train* out,
-                           hipStream_t st) {
+                           hipStream_t st, const std::vector<int>& ids = {}, const int* forced = nullptr,
+                           long long fstride = 0, int* state_save = nullptr) {
   const int batch = p.B, d = p.d;
   Fn* dfn = reinterpret_cast<Fn*>(p.dfn);
   TT_TRY(upload(dfn, fns, st));
   TT_TRY(upload(p.dcs, p.cs, st));
+  {
+    std::vector<int> iv(batch);
+    for (int b = 0; b < batch; ++b) iv[b] = ids.empty() ? b : ids[b];
+    TT_TRY(upload(p.dids, iv, st));
+  }
   {
     std::vector<int> nv(p.n, p.n + TT_MAXD);
     TT_TRY(upload(p.dn, nv, st));
@@ -681,13 +738,14 @@ static tt_status cross_run(CrossPlan& p, const std::vector<Fn>& fns, double tol,
   const double eps_rank = 1e-16;  // a basis of the fibre matrix's range (exact rank deficiency only)
   const int rtop = std::min(max_rank, p.rmax);
   int r = std::min(8, rtop);
-  std::vector<int> prev_level;
+  std::vector<int> prev_level, last_target;
   for (int level = 0;; ++level) {
     std::vector<int> target(TT_MAXD + 1, 1);
     for (int k = 1; k < d; ++k) target[k] = (int)std::min<long long>(r, p.bound[k]);
+    last_target = target;
     TT_TRY(upload(p.dtarget, target, st));
     hipLaunchKernelGGL(cross_extend_kernel, dim3(batch), dim3(64), 0, st, p.dcs, p.dn, d, p.dtarget,
-                       0x5eedULL + 977ULL * (unsigned long long)level);
+                       0x5eedULL + 977ULL * (unsigned long long)level, p.dids);
     TTG_LAUNCH_CHECK("cross_extend_kernel");
     std::vector<int> prev_got;
     bool slack = false;
@@ -770,6 +828,20 @@ static tt_status cross_run(CrossPlan& p, const std::vector<Fn>& fns, double tol,
     prev_level = prev_got;
     r = std::min(2 * r, rtop);
   }
+  if (state_save)
+    for (int b = 0; b < batch; ++b) {
+      TT_TRY(upload(p.cs[b].tgt, last_target, st));
+      HIP_TRY(hipMemcpyAsync(state_save + (long long)b * CROSS_STATE_INTS, p.cs[b].iset,
+                             (size_t)CROSS_STATE_INTS * sizeof(int), hipMemcpyDeviceToDevice, st),
+              "cross state save");
+    }
+  if (forced) {  // the last interpolant again, at the given ranks
+    const std::vector<tt_train> dst = f32 ? p.Z : std::vector<tt_train>(out, out + batch);
+    TT_TRY(cross_upload_pair(p, dst, dst, st));
+    hipLaunchKernelGGL(cross_clear_status_kernel, dim3(cdiv(batch, 64)), dim3(64), 0, st, p.tab, batch);
+    TTG_LAUNCH_CHECK("cross_clear_status_kernel");
+    TT_TRY(round_forced(batch, p.Y.data(), dst.data(), forced, fstride, p.rws, p.rws_bytes, st));
+  }
   if (f32) {
     std::vector<DevTT> vz(batch), vo(batch);
     for (int b = 0; b < batch; ++b) {
@@ -781,6 +853,82 @@ static tt_status cross_run(CrossPlan& p, const std::vector<Fn>& fns, double tol,
     hipLaunchKernelGGL((convert_tt_kernel<float>), dim3(64, batch), dim3(256), 0, st, p.tab, p.tab + batch);
     TTG_LAUNCH_CHECK("convert_tt_kernel");
   }
+  return TT_OK;
+}
+
+// The cross of fns[b] replayed on the index sets and row choices of a
+// finished cross (saved by cross_run at state_in + src[b] *
+// CROSS_STATE_INTS): one right-to-left pass, each core in interpolation form
+// B = U U_rows^{-1} with the saved rows, then the rounding into out (FP64) at
+// the ranks forced (device, stride fstride) or, when null, at tol.  A small
+// change of the function changes the interpolant smoothly: the index sets
+// do not move.  Synchronous.
+template <typename Fn>
+static tt_status cross_frozen(CrossPlan& p, const std::vector<Fn>& fns, const int* state_in,
+                              const std::vector<int>& src, double tol, const int* forced, long long fstride,
+                              const tt_train* out, hipStream_t st) {
+  const int batch = p.B, d = p.d;
+  if (out[0].dtype != TT_F64) {
+    set_error("TT-cross replay: FP64 output only");
+    return TT_ERR_ARG;
+  }
+  Fn* dfn = reinterpret_cast<Fn*>(p.dfn);
+  TT_TRY(upload(dfn, fns, st));
+  TT_TRY(upload(p.dcs, p.cs, st));
+  for (int b = 0; b < batch; ++b)
+    HIP_TRY(hipMemcpyAsync(p.cs[b].iset, state_in + (long long)src[b] * CROSS_STATE_INTS,
+                           (size_t)CROSS_STATE_INTS * sizeof(int), hipMemcpyDeviceToDevice, st),
+            "cross state load");
+  std::vector<int> target(TT_MAXD + 1);
+  HIP_TRY(hipMemcpyAsync(target.data(), p.cs[0].tgt, (TT_MAXD + 1) * sizeof(int), hipMemcpyDeviceToHost, st),
+          "cross targets");
+  HIP_TRY(hipStreamSynchronize(st), "cross targets sync");
+  for (int k = 1; k < d; ++k)
+    if (target[k] < 1 || target[k] > p.rmax) {
+      set_error("TT-cross replay: saved rank target %d out of range", target[k]);
+      return TT_ERR_SHAPE;
+    }
+  for (int k = d - 1; k >= 1; --k) {
+    const int acap = target[k], bcap = k == d - 1 ? 1 : target[k + 1], m = p.n[k] * bcap;
+    std::vector<tt_train> t2(batch), t2r(batch);
+    for (int b = 0; b < batch; ++b) {
+      t2[b] = cross_t2_view(p.T2[b], m, acap);
+      t2r[b] = cross_t2_view(p.T2r[b], m, acap);
+    }
+    TT_TRY(cross_upload_pair(p, t2, t2r, st));
+    hipLaunchKernelGGL((cross_fibre_kernel<Fn>), dim3(std::max(1, std::min(1024, cdiv((long long)m * acap, 256))),
+                                                      batch),
+                       dim3(256), 0, st, dfn, p.dcs, p.tab, d, k, p.n[k], 1, m, acap, bcap);
+    TTG_LAUNCH_CHECK("cross_fibre_kernel");
+    // the basis at the replayed cross's rank (not at the rank rule, whose
+    // decision at the round-off level may differ for a nearby function)
+    hipLaunchKernelGGL(cross_ru_kernel, dim3(cdiv(batch, 64)), dim3(64), 0, st, p.dcs, batch, k, p.dru);
+    TTG_LAUNCH_CHECK("cross_ru_kernel");
+    TT_TRY(round_forced(batch, t2.data(), t2r.data(), p.dru, 3, p.rws, p.rws_bytes, st));
+    TT_TRY(cross_upload_pair(p, t2r, p.Y, st));
+    hipLaunchKernelGGL(cross_maxvol_kernel, dim3(batch), dim3(256), 0, st, p.tab, p.dcs, p.tab + batch, k, p.n[k], 1,
+                       m, bcap, acap, 1);
+    TTG_LAUNCH_CHECK("cross_maxvol_kernel");
+  }
+  TT_TRY(cross_upload_pair(p, p.Y, p.Y, st));
+  hipLaunchKernelGGL((cross_first_core_kernel<Fn>), dim3(std::max(1, cdiv(p.n[0] * target[1], 256)), batch),
+                     dim3(256), 0, st, dfn, p.dcs, p.tab, d, p.n[0]);
+  TTG_LAUNCH_CHECK("cross_first_core_kernel");
+  hipLaunchKernelGGL(cross_y_init_kernel, dim3(cdiv(batch, 64)), dim3(64), 0, st, p.tab, batch);
+  TTG_LAUNCH_CHECK("cross_y_init_kernel");
+  const std::vector<tt_train> dst(out, out + batch);
+  TT_TRY(cross_upload_pair(p, dst, dst, st));
+  hipLaunchKernelGGL(cross_clear_status_kernel, dim3(cdiv(batch, 64)), dim3(64), 0, st, p.tab, batch);
+  TTG_LAUNCH_CHECK("cross_clear_status_kernel");
+  if (forced) {
+    TT_TRY(round_forced(batch, p.Y.data(), dst.data(), forced, fstride, p.rws, p.rws_bytes, st));
+  } else {
+    int outcap = 1;
+    for (int b = 0; b < batch; ++b)
+      for (int j = 0; j <= d; ++j) outcap = std::max(outcap, out[b].cap[j]);
+    TT_TRY(tt_round(batch, p.Y.data(), dst.data(), tol, outcap, p.rws, p.rws_bytes, st));
+  }
+  HIP_TRY(hipStreamSynchronize(st), "cross replay sync");
   return TT_OK;
 }
 
@@ -820,23 +968,16 @@ static tt_status kernel_cross_args(int32_t batch, const tt_grid* grids, const in
 
 }  // namespace ttg
 
-extern "C" {
+namespace ttg {
 
-size_t tt_kernel_build_cross_workspace(int32_t batch, const tt_grid* grids, const int32_t* halfwidths,
-                                       const tt_train* out) {
-  using namespace ttg;
-  int n[TT_MAXD];
-  if (kernel_cross_args(batch, grids, halfwidths, out, n) != TT_OK) return 0;
-  Arena ar(nullptr, 0);
-  CrossPlan p;
-  if (cross_plan(batch, grids[0].d, n, CROSS_RMAX, sizeof(CrossKernelFn), out, ar, p) != TT_OK) return 0;
-  return ar.used + 256;
-}
-
-tt_status tt_kernel_build_cross(int32_t batch, const tt_grid* grids, const double* q, const int32_t* halfwidths,
-                                double svd_tol, int32_t max_rank, const tt_train* out, void* ws, size_t ws_bytes,
-                                void* stream) {
-  using namespace ttg;
+// tt_kernel_build_cross, with the random-tuple streams ids, optional forced
+// final ranks and the index sets saved (state_save) or replayed (state_load,
+// function b on the saved state ids[b]; see cross_run and cross_frozen)
+static tt_status kernel_cross_impl(int32_t batch, const tt_grid* grids, const double* q, const int32_t* halfwidths,
+                                   double svd_tol, int32_t max_rank, const tt_train* out, void* ws, size_t ws_bytes,
+                                   hipStream_t st, const std::vector<int>& ids = {},
+                                   const int* forced = nullptr, long long fstride = 0, int* state_save = nullptr,
+                                   const int* state_load = nullptr) {
   int n[TT_MAXD];
   TT_TRY(kernel_cross_args(batch, grids, halfwidths, out, n));
   if (!q || !ws || !(svd_tol > 0.0) || max_rank < 1 || max_rank > CROSS_RMAX) {
@@ -868,7 +1009,34 @@ tt_status tt_kernel_build_cross(int32_t batch, const tt_grid* grids, const doubl
     }
     F.c = std::exp(-0.5 * d * std::log(2.0 * M_PI) - 0.5 * std::log(det) + logdelta);
   }
-  return cross_run(p, fns, svd_tol, max_rank, out, reinterpret_cast<hipStream_t>(stream));
+  if (state_load) {  // replay on saved index sets: function b on the state ids[b]
+    std::vector<int> src(batch);
+    for (int b = 0; b < batch; ++b) src[b] = ids.empty() ? b : ids[b];
+    return cross_frozen(p, fns, state_load, src, svd_tol, forced, fstride, out, st);
+  }
+  return cross_run(p, fns, svd_tol, max_rank, out, st, ids, forced, fstride, state_save);
+}
+
+}  // namespace ttg
+
+extern "C" {
+
+size_t tt_kernel_build_cross_workspace(int32_t batch, const tt_grid* grids, const int32_t* halfwidths,
+                                       const tt_train* out) {
+  using namespace ttg;
+  int n[TT_MAXD];
+  if (kernel_cross_args(batch, grids, halfwidths, out, n) != TT_OK) return 0;
+  Arena ar(nullptr, 0);
+  CrossPlan p;
+  if (cross_plan(batch, grids[0].d, n, CROSS_RMAX, sizeof(CrossKernelFn), out, ar, p) != TT_OK) return 0;
+  return ar.used + 256;
+}
+
+tt_status tt_kernel_build_cross(int32_t batch, const tt_grid* grids, const double* q, const int32_t* halfwidths,
+                                double svd_tol, int32_t max_rank, const tt_train* out, void* ws, size_t ws_bytes,
+                                void* stream) {
+  return ttg::kernel_cross_impl(batch, grids, q, halfwidths, svd_tol, max_rank, out, ws, ws_bytes,
+                                reinterpret_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

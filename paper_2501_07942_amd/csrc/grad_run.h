@@ -212,6 +212,10 @@ struct GradRun {
   std::vector<double> qs, m0, p0;
   std::vector<int32_t> hw;
   double ktol = 0.0;
+  bool cross = false;  // kernel TTs by TT-cross (the dense tensor is out of reach)
+  int npert = 1;       // perturbed kernel builds per call (all 2d at once for TT-cross)
+  int* kranks = nullptr;  // [npert * B][TT_MAXD + 1] the base kernels' ranks (device)
+  int* kstate = nullptr;  // [B][CROSS_STATE_INTS] the base crosses' index sets (device)
   // persistent trains
   Batch kern, kbar, kp;
   double* logc = nullptr;   // [K][B]
@@ -323,6 +327,12 @@ static tt_status grad_plan(int32_t batch, const tt_grad_spec* specs, int32_t K, 
   g.m0.assign((size_t)batch * d, 0.0);
   g.p0.assign((size_t)batch * d, 0.0);
   g.hw.assign(specs[0].halfwidths, specs[0].halfwidths + d);
+  {  // the dense kernel build up to d = 8 and 2^28 taps, TT-cross beyond
+    double taps = 1.0;
+    for (int l = 0; l < d; ++l) taps *= 2.0 * g.hw[l] + 1.0;
+    g.cross = d > 8 || taps > 268435456.0;
+    g.npert = g.cross ? 2 * d : 1;
+  }
   for (int b = 0; b < batch; ++b) {
     const tt_grad_spec& s = specs[b];
     TT_TRY(check_grid(&s.f.grid));
@@ -389,8 +399,13 @@ static tt_status grad_plan(int32_t batch, const tt_grad_spec* specs, int32_t K, 
   // persistent part
   g.kern = gr_batch(ar, g, kc, ntap);
   g.kbar = gr_batch(ar, g, kc, ntap);
-  g.kp = gr_batch(ar, g, kc, ntap);
+  for (int pi = 0; pi < g.npert; ++pi) {
+    const Batch kp = gr_batch(ar, g, kc, ntap);
+    g.kp.insert(g.kp.end(), kp.begin(), kp.end());
+  }
   g.logc = ar.take<double>((size_t)K * batch);
+  g.kranks = ar.take<int>((size_t)g.npert * batch * (TT_MAXD + 1));
+  if (g.cross) g.kstate = ar.take<int>((size_t)batch * CROSS_STATE_INTS);
   g.vals = ar.take<double>((size_t)2 * d * batch);
   g.hstep = ar.take<double>((size_t)d * batch);
   g.lmass = ar.take<double>(batch);
@@ -446,7 +461,7 @@ static tt_status grad_plan(int32_t batch, const tt_grad_spec* specs, int32_t K, 
     for (int c = 0; c < g.C; ++c) g.seg[c] = gr_batch(ar, g, pc, ngrid);
   }
   g.stab = ar.take<int32_t*>(g.statuses.size());
-  g.tab_n = 4 * batch;
+  g.tab_n = std::max(4, g.npert) * batch;
   g.tab = ar.take<DevTT>((size_t)g.tab_n);
   g.dfc = ar.take<FilterConst>(batch);
   // the sub-calls' workspace: the largest query
@@ -457,7 +472,12 @@ static tt_status grad_plan(int32_t batch, const tt_grad_spec* specs, int32_t K, 
     std::vector<int32_t> caps((size_t)batch * (d + 1));
     for (int b = 0; b < batch; ++b)
       for (int j = 0; j <= d; ++j) caps[(size_t)b * (d + 1) + j] = kc[b][j];
-    const size_t kw = tt_kernel_build_batch_workspace(batch, g.grids.data(), g.hw.data(), caps.data());
+    std::vector<tt_grid> grep_;  // the grids once per perturbed build
+    for (int pi = 0; pi < g.npert; ++pi) grep_.insert(grep_.end(), g.grids.begin(), g.grids.end());
+    const size_t kw =
+        g.cross ? std::max(tt_kernel_build_cross_workspace(batch, g.grids.data(), g.hw.data(), g.kern.data()),
+                           tt_kernel_build_cross_workspace(g.npert * batch, grep_.data(), g.hw.data(), g.kp.data()))
+                : tt_kernel_build_batch_workspace(batch, g.grids.data(), g.hw.data(), caps.data());
     if (kw == 0) {
       set_error("tt_filter_grad: the kernel box or capacities are not supported by the kernel build");
       return TT_ERR_SHAPE;
@@ -478,6 +498,7 @@ static tt_status grad_plan(int32_t batch, const tt_grad_spec* specs, int32_t K, 
   for (int b = 0; b < batch; ++b)
     for (int j = 0; j <= d; ++j) rmax = std::max({rmax, xc[b][j], hc[b][j], dc[b][j]});
   upd(tt_adjoint_workspace(batch, d, rmax));
+  upd(tt_adjoint_workspace(g.npert * batch, d, rmax));
   upd((size_t)2 * batch * 4096 + 4096);  // tt_prior
   g.sub_bytes = need + 4096;
   g.sub = ar.take<char>(g.sub_bytes);
@@ -554,9 +575,25 @@ static tt_status gr_step(GradRun& g, int k, const Batch* pprev, const Batch& pt,
 }
 
 // the kernel TTs at the specs' parameters
-static tt_status gr_kernels(GradRun& g, const std::vector<double>& qs, const Batch& out, hipStream_t st) {
-  return tt_kernel_build_batch(g.B, g.grids.data(), qs.data(), g.hw.data(), g.ktol, out.data(), g.sub, g.sub_bytes,
-                               st);
+// (out.size() / B builds of the batch's kernels, q per build and filter).
+// TT-cross: working rank 64 (the trains' capacities cap the result).  The
+// base builds (forced null) save their index sets in kstate; a perturbed
+// build i (forced: the base builds' ranks, stride TT_MAXD + 1) replays the
+// index sets of filter i mod B and rounds to its ranks, so the perturbed
+// kernels are the base's interpolant of the perturbed function, smooth in
+// the parameters.
+static tt_status gr_kernels(GradRun& g, const std::vector<double>& qs, const Batch& out, hipStream_t st,
+                            const int* forced = nullptr) {
+  const int n = (int)out.size();
+  std::vector<tt_grid> grids;
+  for (int i = 0; i < n / g.B; ++i) grids.insert(grids.end(), g.grids.begin(), g.grids.end());
+  if (g.cross) {
+    std::vector<int> ids(n);
+    for (int i = 0; i < n; ++i) ids[i] = i % g.B;
+    return kernel_cross_impl(n, grids.data(), qs.data(), g.hw.data(), g.ktol, 64, out.data(), g.sub, g.sub_bytes,
+                             st, ids, forced, TT_MAXD + 1, forced ? nullptr : g.kstate, forced ? g.kstate : nullptr);
+  }
+  return tt_kernel_build_batch(n, grids.data(), qs.data(), g.hw.data(), g.ktol, out.data(), g.sub, g.sub_bytes, st);
 }
 
 }  // namespace ttg
@@ -710,11 +747,16 @@ tt_status tt_filter_run_adjoint(int32_t batch, const tt_grad_spec* specs, const 
     }
   }
   // sigma_w: central differences of the kernel builds, put into the base
-  // build's bond bases, against the kernel adjoint
+  // build's bond bases, against the kernel adjoint; perturbation p = 2 j + s
+  // (s = 0: +h, 1: -h), npert of them built per call
   std::vector<double> hs((size_t)d * B);
-  for (int j = 0; j < d; ++j) {
-    for (int sg = 0; sg < 2; ++sg) {
-      std::vector<double> qp(g.qs);
+  const int P = 2 * d;
+  for (int p0 = 0; p0 < P; p0 += g.npert) {
+    const int pn = std::min(g.npert, P - p0);
+    std::vector<double> qp((size_t)pn * B * d * d);
+    Batch ref((size_t)pn * B), kbr((size_t)pn * B), kp(g.kp.begin(), g.kp.begin() + (size_t)pn * B);
+    for (int pi = 0; pi < pn; ++pi) {
+      const int j = (p0 + pi) / 2, sg = (p0 + pi) % 2;
       for (int b = 0; b < B; ++b) {
         const double* q = &g.qs[(size_t)b * d * d];
         std::vector<double> sw(d);
@@ -723,26 +765,41 @@ tt_status tt_filter_run_adjoint(int32_t batch, const tt_grad_spec* specs, const 
         hs[(size_t)j * B + b] = hj;
         std::vector<double> swp(sw);
         swp[j] += sg == 0 ? hj : -hj;
+        double* o = &qp[((size_t)pi * B + b) * d * d];
         for (int l = 0; l < d; ++l)
-          for (int m = 0; m < d; ++m)
-            qp[(size_t)b * d * d + l * d + m] = q[l * d + m] / (sw[l] * sw[m]) * swp[l] * swp[m];
+          for (int m = 0; m < d; ++m) o[l * d + m] = q[l * d + m] / (sw[l] * sw[m]) * swp[l] * swp[m];
+        ref[(size_t)pi * B + b] = g.kern[b];
+        kbr[(size_t)pi * B + b] = g.kbar[b];
       }
-      TT_TRY(gr_kernels(g, qp, g.kp, st));
-      TT_TRY(tt_align_signs(B, g.kern.data(), g.kp.data(), g.sub, g.sub_bytes, st));
-      {
-        std::vector<DevTT> v(2 * B);
-        for (int b = 0; b < B; ++b) {
-          v[b] = make_dev(g.kern[b]);
-          v[B + b] = make_dev(g.kp[b]);
-        }
-        TT_TRY(upload(g.tab, v, st));
-        hipLaunchKernelGGL(rank_match_kernel, dim3(cdiv(B, 64)), dim3(64), 0, st, g.tab, g.tab + B, B, status_dev);
-        TTG_LAUNCH_CHECK("rank_match_kernel");
-      }
-      TT_TRY(tt_adjoint_inner(B, g.kbar.data(), g.kp.data(), g.vals + (size_t)(2 * j + sg) * B, g.sub, g.sub_bytes,
-                              st));
-      TT_TRY(gr_or_status(g, {&g.kp}, status_dev, st));
     }
+    const int* forced = nullptr;
+    if (g.cross) {  // the base ranks, once per perturbed build
+      std::vector<DevTT> v((size_t)pn * B);
+      for (size_t i = 0; i < v.size(); ++i) v[i] = make_dev(ref[i]);
+      TT_TRY(upload(g.tab, v, st));
+      hipLaunchKernelGGL(record_ranks_kernel, dim3(cdiv(pn * B, 64)), dim3(64), 0, st, g.tab, pn * B, g.kranks,
+                         (long long)(TT_MAXD + 1));
+      TTG_LAUNCH_CHECK("record_ranks_kernel");
+      forced = g.kranks;
+    }
+    TT_TRY(gr_kernels(g, qp, kp, st, forced));
+    TT_TRY(tt_align_signs(pn * B, ref.data(), kp.data(), g.sub, g.sub_bytes, st));
+    std::vector<Batch> parts(pn);
+    std::vector<const Batch*> pp(pn);
+    for (int pi = 0; pi < pn; ++pi) {
+      parts[pi].assign(kp.begin() + (size_t)pi * B, kp.begin() + (size_t)(pi + 1) * B);
+      pp[pi] = &parts[pi];
+      std::vector<DevTT> v(2 * B);
+      for (int b = 0; b < B; ++b) {
+        v[b] = make_dev(g.kern[b]);
+        v[B + b] = make_dev(parts[pi][b]);
+      }
+      TT_TRY(upload(g.tab, v, st));
+      hipLaunchKernelGGL(rank_match_kernel, dim3(cdiv(B, 64)), dim3(64), 0, st, g.tab, g.tab + B, B, status_dev);
+      TTG_LAUNCH_CHECK("rank_match_kernel");
+    }
+    TT_TRY(tt_adjoint_inner(pn * B, kbr.data(), kp.data(), g.vals + (size_t)p0 * B, g.sub, g.sub_bytes, st));
+    TT_TRY(gr_or_status(g, pp, status_dev, st));
   }
   TT_TRY(upload(g.hstep, hs, st));
   hipLaunchKernelGGL(kernel_theta_kernel, dim3(cdiv(B, 64)), dim3(64), 0, st, g.vals, g.hstep, d, B, g.nth,

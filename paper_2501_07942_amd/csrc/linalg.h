@@ -273,12 +273,15 @@ struct PcholArgs {
   int gcap;
   int rmax;             // rank capacity
   double tau2;          // relative threshold on the Schur diagonal
+  double tau2_flag;     // a full-capacity stop flags TT_STATUS_CAPACITY only when the
+                        // residual trace exceeds max(tau2, tau2_flag) x the trace
 };
 
 template <typename Acc, typename F>
 __global__ void __launch_bounds__(256) pchol_kernel(F f, int ncl) {
   const int b = blockIdx.x;
   PcholArgs p;
+  p.tau2_flag = 0.0;
   if (!f(b, p)) return;
   using V = typename Acc::V;
   extern __shared__ double smem[];
@@ -408,7 +411,8 @@ __global__ void __launch_bounds__(256) pchol_kernel(F f, int ncl) {
   if (tid == 0) {
     *p.rank_out = rank;
     if (p.resid_out) *p.resid_out = resid;
-    if (rank == jmax && jmax < p.M && resid > thr && p.status) atomicOr(p.status, TT_STATUS_CAPACITY);
+    if (rank == jmax && jmax < p.M && resid > fmax(p.tau2, p.tau2_flag) * s_trace && p.status)
+      atomicOr(p.status, TT_STATUS_CAPACITY);
     if (bad && p.status) atomicOr(p.status, TT_STATUS_NONFINITE);
   }
   // FP64 row-major copy, zero beyond the rank

@@ -377,7 +377,8 @@ tt_status tt_filter_run_linear(int32_t batch, const tt_filter_spec* specs, const
       std::vector<double> qes((size_t)B * d * d);
       for (int b = 0; b < B; ++b)
         for (int e = 0; e < d * d; ++e) qes[(size_t)b * d * d + e] = qe[e];
-      TT_TRY(tt_kernel_build_cross(B, hat.data(), qes.data(), hw.data(), kernel_tol, g.kcap, kt.data(), g.sub,
+      // (working rank 64; the kernel trains' capacities kernel_cap cap the result)
+      TT_TRY(tt_kernel_build_cross(B, hat.data(), qes.data(), hw.data(), kernel_tol, 64, kt.data(), g.sub,
                                    g.sub_bytes, st));
       {
         std::vector<DevTT> v(B);

@@ -80,3 +80,46 @@ def test_device_cross_kernel_matches_oracle_cross(refs):
     print(f"kernel: ranks {ttm.ranks(cores)} (oracle {ttm.ranks(kern)}), rel {rel:.1e}", flush=True)
     assert ttm.ranks(cores) == ttm.ranks(kern)
     assert rel <= 1e-10
+
+
+def test_fp64_gradient_matches_oracle_replay_differences():
+    # the reverse sweep (tt_filter_run_taped / tt_filter_run_adjoint) at
+    # d=10, N=256: one filter, an update then a full step, the kernel TT and
+    # its process-noise tangents by TT-cross; against central differences of
+    # the oracle's run with every rounding's rank replayed (its kernel built by
+    # the oracle's own cross at each perturbed Q) on sampled parameters
+    from oracle import grad as og
+    from paper_2501_07942_amd import adjoint_grad as AG, grad as G, workload as wl
+    specs, xs, zs = wl.make_batch("range10d_n256_c32", batch=1, steps=2)
+    s = specs[0]
+    d = s.d
+    print("d=10 gradient: 1 filter, 2 steps (reverse sweep on the device)", flush=True)
+    ll, g, _ = AG.loglik_grad_adjoint(specs, zs)
+    axes = mdl.grid_axes([s.lo] * d, [s.hi] * d, [s.n] * d)
+    sw0 = np.sqrt(np.diag(s.q))
+    corr = s.q / np.outer(sw0, sw0)
+
+    def run(theta, replay=None):
+        sw, meas = og.unpack(theta, d, "range")
+        q = og.q_of(sw, corr)
+        kern = ocr.kernel_tt_cross(q, axes, s.halfwidths(), s.kernel_tol)
+        return flt.run_tt_filter(axes, q, s.halfwidths(), meas, zs[0], s.m0, s.p0_diag, s.cap, s.eps, kernel=kern,
+                                 replay=replay)
+
+    th = np.asarray(G.theta_of(s), dtype=np.float64)
+    base = run(th)
+    replay = {"ranks_pred": base["ranks_pred"], "ranks_filt": base["ranks_filt"]}
+    hs = og.fd_steps(th, 1e-5)
+    sampled = (0, 4, 9, 10, 11, 12, 13)
+    g_o = {}
+    for j in sampled:
+        tp, tm = th.copy(), th.copy()
+        tp[j] += hs[j]
+        tm[j] -= hs[j]
+        g_o[j] = (run(tp, replay)["loglik"] - run(tm, replay)["loglik"]) / (2.0 * hs[j])
+    scale = max(abs(v) for v in g_o.values())
+    err = max(abs(g[0][j] - g_o[j]) for j in sampled) / scale
+    print(f"  |dLL|/|LL| {abs(ll[0] - base['loglik']) / abs(base['loglik']):.1e}, gradient vs oracle differences "
+          f"{err:.1e} on theta {list(sampled)}", flush=True)
+    assert abs(ll[0] - base["loglik"]) < 1e-10 * abs(base["loglik"])
+    assert err < 1e-4
