@@ -606,6 +606,44 @@ tt_status tt_filter_run(int32_t batch, const tt_filter_spec* specs, const tt_tra
                         void* stream);
 
 /* ---------------------------------------------------------------------
+ * tt_filter_run_monitored -- tt_filter_run with per-step records of two
+ * quantities the paper's filter leaves unchecked: the negativity of the TT
+ * density (Sec. 5.1 and Sec. 6 report negative PMD values for d >= 3) and
+ * the error of each rounding (Sec. 3.2: the TT-SVD truncation error is at
+ * most the square root of the sum of the squared discarded tails).  Every
+ * argument but monitor is that of tt_filter_run (same workspace query);
+ * monitor (host struct, nullable) holds device pointers, each nullable:
+ *   marg_min_dev[b * K + k]      smallest value over every 1-D marginal of
+ *                                the filtering density P_{k|k} (the sums of
+ *                                its point values over all axes but one)
+ *   tail_dev[(b * K + k) * 2]    sqrt(sum over the bonds of the discarded
+ *                                tail^2) / ||A|| of the prediction's
+ *                                rounding at step k (0 at k = 0), and at
+ *                                + 1 the same for the update's rounding
+ * Records of steps outside [k_begin, k_begin + k_count) are not written.
+ *
+ * tt_marginal_min: out_dev[b] = the smallest 1-D marginal value of the TT
+ * t[b] as above (log_scale included), any dtype, ragged ranks.  Workspace:
+ * tt_marginal_min_workspace(batch, t) bytes.  Asynchronous.  Errors:
+ * TT_ERR_ARG, TT_ERR_SHAPE, TT_ERR_WORKSPACE.
+ * --------------------------------------------------------------------- */
+typedef struct {
+  double* marg_min_dev;
+  double* tail_dev;
+} tt_monitor;
+
+tt_status tt_filter_run_monitored(int32_t batch, const tt_filter_spec* specs, const tt_train* kernels,
+                                  int32_t n_kernels, const double* z_dev, int32_t zdim, int32_t K, int32_t k_begin,
+                                  int32_t k_count, int32_t precision, double* loglik_dev, double* log_c_dev,
+                                  double* log_mpred_dev, double* mean_dev, double* cov_dev, int32_t* ranks_dev,
+                                  int32_t* status_dev, int32_t* ranks_pred_dev, const int32_t* replay_pred_dev,
+                                  const int32_t* replay_filt_dev, const tt_monitor* monitor, void* ws,
+                                  size_t ws_bytes, void* stream);
+size_t tt_marginal_min_workspace(int32_t batch, const tt_train* t);
+tt_status tt_marginal_min(int32_t batch, const tt_train* t, double* out_dev, void* ws, size_t ws_bytes,
+                          void* stream);
+
+/* ---------------------------------------------------------------------
  * The differentiated recursion: LL = sum_k log c_k (Sec. 2.2, eq.
  * pmf_filtrace_b) of every filter of a batch and its gradient with respect
  * to theta = (sigma_w[0..d-1], sigma_r, sigma_lin, s_1, s_2) for the range

@@ -235,6 +235,67 @@ def sum_vjp(tt, sbar):
     return [sbar * np.einsum("a,i,b->aib", left[k], np.ones(tt[k].shape[1]), right[k]) for k in range(d)]
 
 
+def weighted_sum_vjp(tt, weights, sbar):
+    """Adjoint of s = sum_i w(i) X(i) for a rank-one weight
+    w = w_0 (x) ... (x) w_{d-1} (a TT contraction with vectors, Sec. 4.1
+    'dot'): core k receives sbar * left_k (x) w_k (x) right_k, with left and
+    right the weighted prefix and suffix chains."""
+    d = len(tt)
+    mats = [np.einsum("i,aib->ab", w, g) for w, g in zip(weights, tt)]
+    left = [np.ones((1,))]
+    for k in range(d - 1):
+        left.append(left[-1] @ mats[k])
+    right = [None] * d
+    acc = np.ones((1,))
+    for k in range(d - 1, -1, -1):
+        right[k] = acc
+        acc = mats[k] @ acc
+    return [sbar * np.einsum("a,i,b->aib", left[k], weights[k], right[k]) for k in range(d)]
+
+
+def moments_vjp(tt, axes, mean_bar, cov_bar):
+    """Adjoint with respect to the cores of the moments of a TT density
+    (model.moments_tt: mean_l = M1_l / M0, cov_lj = M2_lj / M0 - mean_l
+    mean_j, M_w = sum_i w(i) X(i); the cell volume cancels), given the
+    adjoints of mean [d] and cov [d, d] (both entries of a symmetric pair
+    count)."""
+    d = len(tt)
+    ones = [np.ones(len(ax)) for ax in axes]
+    mean_bar = np.zeros(d) if mean_bar is None else np.asarray(mean_bar, dtype=np.float64)
+    cov_bar = np.zeros((d, d)) if cov_bar is None else np.asarray(cov_bar, dtype=np.float64)
+
+    def wvec(powers):
+        return [np.asarray(axes[l], dtype=np.float64) ** powers.get(l, 0) if l in powers else ones[l]
+                for l in range(d)]
+
+    m0 = ttm.contract_vectors(tt, ones)
+    m1 = np.array([ttm.contract_vectors(tt, wvec({l: 1})) for l in range(d)])
+    mean = m1 / m0
+    terms = []  # (weights, coefficient)
+    mbar = mean_bar.copy()
+    c0 = 0.0
+    for l in range(d):
+        for j in range(l, d):
+            w = wvec({l: 2}) if l == j else wvec({l: 1, j: 1})
+            m2 = ttm.contract_vectors(tt, w)
+            cb = cov_bar[l, l] if l == j else cov_bar[l, j] + cov_bar[j, l]
+            terms.append((w, cb / m0))
+            c0 -= cb * m2 / m0 ** 2
+            if l == j:
+                mbar[l] -= 2.0 * cb * mean[l]
+            else:
+                mbar[l] -= cb * mean[j]
+                mbar[j] -= cb * mean[l]
+    for l in range(d):
+        terms.append((wvec({l: 1}), mbar[l] / m0))
+        c0 -= mbar[l] * mean[l] / m0
+    terms.append((ones, c0))
+    out = [np.zeros_like(g) for g in tt]
+    for w, c in terms:
+        tt_axpy(out, weighted_sum_vjp(tt, w, c))
+    return out
+
+
 def hadamard_vjp(a, b, hbar):
     """Adjoint of H_k((a,c), i, (b,d)) = A_k(a,i,b) B_k(c,i,d) (Sec. 4.1 'times')."""
     abar, bbar = [], []

@@ -40,6 +40,13 @@ def _marginal_min(p):
     return min(mins)
 
 
+def _tail_rel(info):
+    """The rounding's error bound relative to the input's norm: the square
+    root of the sum over the bonds of the squared discarded tails, over
+    ||A|| (the TT-SVD truncation bound, Sec. 3.2)."""
+    return math.sqrt(sum(t * t for t in info["tails"])) / info["norm"] if info["norm"] > 0 else 0.0
+
+
 def run_tt_filter(axes, q, halfwidths, meas, z, m0, p0_diag, cap, eps,
                   kernel_tol=1e-12, lik_tol=1e-12, lik_max_rank=None,
                   kernel=None, record_density=False, replay=None):
@@ -56,7 +63,8 @@ def run_tt_filter(axes, q, halfwidths, meas, z, m0, p0_diag, cap, eps,
     p = mdl.prior_tt(axes, m0, p0_diag)
     nsteps = z.shape[0]
     rec = {"log_c": [], "log_mpred": [], "mean": [], "cov": [], "ranks_pred": [],
-           "ranks_filt": [], "ranks_unrounded": [], "marg_min": [], "tails": [],
+           "ranks_filt": [], "ranks_unrounded": [], "marg_min": [], "tails": [], "tail_rel_pred": [],
+           "tail_rel_filt": [],
            "densities": []}
     for k in range(nsteps):
         if k > 0:
@@ -64,6 +72,7 @@ def run_tt_filter(axes, q, halfwidths, meas, z, m0, p0_diag, cap, eps,
             rec["ranks_unrounded"].append(ttm.ranks(c))
             fr = None if replay is None else replay["ranks_pred"][k - 1]
             pt, info = ttm.tt_round(c, eps, cap, return_info=True, forced_ranks=fr)
+            rec["tail_rel_pred"].append(_tail_rel(info))
             mpred = ttm.tt_sum(pt) * delta
             rec["log_mpred"].append(math.log(mpred))
             p = ttm.scale(pt, 1.0 / mpred)
@@ -77,6 +86,7 @@ def run_tt_filter(axes, q, halfwidths, meas, z, m0, p0_diag, cap, eps,
         fr = None if replay is None else replay["ranks_filt"][k]
         hr, info = ttm.tt_round(h, eps, cap, return_info=True, forced_ranks=fr)
         rec["tails"].append(info["tails"])
+        rec["tail_rel_filt"].append(_tail_rel(info))
         mass = ttm.tt_sum(hr) * delta
         p = ttm.scale(hr, 1.0 / mass)
         rec["ranks_filt"].append(ttm.ranks(p))
@@ -86,7 +96,8 @@ def run_tt_filter(axes, q, halfwidths, meas, z, m0, p0_diag, cap, eps,
         rec["marg_min"].append(_marginal_min(p))
         if record_density:
             rec["densities"].append(p)
-    out = {key: (np.array(v) if key in ("log_c", "log_mpred", "mean", "cov", "marg_min") else v)
+    out = {key: (np.array(v) if key in ("log_c", "log_mpred", "mean", "cov", "marg_min", "tail_rel_pred",
+                                        "tail_rel_filt") else v)
            for key, v in rec.items()}
     out["loglik"] = float(np.sum(out["log_c"]))
     out["final"] = p

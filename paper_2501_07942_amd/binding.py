@@ -46,6 +46,10 @@ class FilterSpec(C.Structure):
                 ("lik_rank_cap", C.c_int32)]
 
 
+class Monitor(C.Structure):
+    _fields_ = [("marg_min_dev", C.c_void_p), ("tail_dev", C.c_void_p)]
+
+
 class GradSpec(C.Structure):
     _fields_ = [("f", FilterSpec), ("q", C.c_double * (MAXD * MAXD)), ("halfwidths", C.c_int32 * MAXD),
                 ("kernel_tol", C.c_double)]
@@ -90,6 +94,9 @@ def _load():
         "tt_get_predict_mode": (I, []),
         "tt_profile_end": (I, [P, P, P, P, I]),
         "tt_filter_run": (I, [I, P, P, I, P, I, I, I, I, I, P, P, P, P, P, P, P, P, P, P, P, S, P]),
+        "tt_filter_run_monitored": (I, [I, P, P, I, P, I, I, I, I, I, P, P, P, P, P, P, P, P, P, P, P, P, S, P]),
+        "tt_marginal_min_workspace": (S, [I, P]),
+        "tt_marginal_min": (I, [I, P, P, P, S, P]),
         "tt_filter_graph_create": (I, [I, P, P, I, P, I, I, I, I, I, P, P, P, P, P, P, P, P, P, P, P, S, P,
                                        C.POINTER(C.c_void_p)]),
         "tt_filter_graph_launch": (I, [P, P]),
@@ -159,7 +166,8 @@ EXPORTED = ("tt_train_elems", "tt_last_error", "tt_version", "tt_kernel_build_wo
             "tt_normalize_moments_noalloc", "tt_autotune_save", "tt_autotune_load", "tt_filter_grad_workspace",
             "tt_filter_run_taped", "tt_filter_run_adjoint", "tt_kernel_build_cross_workspace",
             "tt_kernel_build_cross", "tt_interpolate_lattice_workspace", "tt_interpolate_lattice",
-            "tt_filter_run_linear_workspace", "tt_filter_run_linear")
+            "tt_filter_run_linear_workspace", "tt_filter_run_linear", "tt_filter_run_monitored",
+            "tt_marginal_min_workspace", "tt_marginal_min")
 
 PREDICT_DIRECT, PREDICT_FFT, PREDICT_UNFUSED, PREDICT_DIRECT_VALU = 0, 1, 2, 3
 
@@ -704,6 +712,14 @@ def tt_likelihood(grids: Sequence[Grid], meas: Sequence[Meas], z, l_out: Sequenc
                              ws.numel(), _stream()), "tt_likelihood")
 
 
+def tt_marginal_min(tts: Sequence[DeviceTT], out):
+    """out: float64 device tensor [B] <- the smallest 1-D marginal value of each TT."""
+    B = len(tts)
+    a = _arr([t.struct() for t in tts])
+    ws = _ws(LIB.tt_marginal_min_workspace(B, a))
+    _check(LIB.tt_marginal_min(B, a, out.data_ptr(), ws.data_ptr(), ws.numel(), _stream()), "tt_marginal_min")
+
+
 def tt_likelihood_dense(grids: Sequence[Grid], meas: Sequence[Meas], z, p_out: Sequence[DeviceTT]):
     """The likelihood before the range block's SVD (bond 1 of full rank n[1]
     for the range model).  z: float64 device tensor [B, zdim]."""
@@ -764,7 +780,10 @@ class FilterRun:
     """Device buffers and workspace of one batched tt_filter_run call."""
 
     def __init__(self, specs: Sequence[FilterSpec], kernels: Sequence[DeviceTT], K: int, zdim: int,
-                 precision: int):
+                 precision: int, monitor: bool = False):
+        """monitor: also record per step the smallest 1-D marginal value of
+        the filtering density (marg_min [B, K]) and the relative error bounds
+        of both roundings (tails [B, K, 2]) by tt_filter_run_monitored."""
         torch = _torch()
         self.B = len(specs)
         self.K = K
@@ -784,6 +803,11 @@ class FilterRun:
         self.ranks = torch.zeros(self.B, K, d + 1, dtype=torch.int32, device=dev)
         self.ranks_pred = torch.zeros(self.B, K, d + 1, dtype=torch.int32, device=dev)
         self.status = torch.zeros(self.B, dtype=torch.int32, device=dev)
+        self.monitor = None
+        if monitor:
+            self.marg_min = torch.zeros(self.B, K, dtype=torch.float64, device=dev)
+            self.tails = torch.zeros(self.B, K, 2, dtype=torch.float64, device=dev)
+            self.monitor = Monitor(self.marg_min.data_ptr(), self.tails.data_ptr())
         nbytes = LIB.tt_filter_run_workspace(self.B, self.specs, self.karr, len(kernels), precision)
         if nbytes == 0:
             _check(ERR_ARG, "tt_filter_run_workspace")
@@ -804,16 +828,17 @@ class FilterRun:
             for t in (rp, rf):
                 if tuple(t.shape) != (self.B, self.K, self.d + 1) or t.dtype != _torch().int32 or not t.is_contiguous():
                     raise TTError("replay ranks must be contiguous int32 [B, K, d+1]")
-        st = LIB.tt_filter_run(self.B, self.specs, self.karr, len(self.kernels), z.data_ptr(), self.zdim,
-                               self.K, int(k_begin), int(k_count), self.precision, self.loglik.data_ptr(),
-                               self.log_c.data_ptr(),
-                               self.log_mpred.data_ptr(),
-                               self.mean.data_ptr() if moments else None,
-                               self.cov.data_ptr() if moments else None,
-                               self.ranks.data_ptr(), self.status.data_ptr(), self.ranks_pred.data_ptr(),
-                               rp.data_ptr() if rp is not None else None,
-                               rf.data_ptr() if rf is not None else None, self.ws.data_ptr(),
-                               self.ws.numel(), _stream())
+        args = (self.B, self.specs, self.karr, len(self.kernels), z.data_ptr(), self.zdim,
+                self.K, int(k_begin), int(k_count), self.precision, self.loglik.data_ptr(),
+                self.log_c.data_ptr(), self.log_mpred.data_ptr(),
+                self.mean.data_ptr() if moments else None, self.cov.data_ptr() if moments else None,
+                self.ranks.data_ptr(), self.status.data_ptr(), self.ranks_pred.data_ptr(),
+                rp.data_ptr() if rp is not None else None, rf.data_ptr() if rf is not None else None)
+        if self.monitor is not None:
+            st = LIB.tt_filter_run_monitored(*args, C.byref(self.monitor), self.ws.data_ptr(), self.ws.numel(),
+                                             _stream())
+        else:
+            st = LIB.tt_filter_run(*args, self.ws.data_ptr(), self.ws.numel(), _stream())
         _check(st, "tt_filter_run")
 
     def _state(self, trains: Sequence[DeviceTT], direction: int):

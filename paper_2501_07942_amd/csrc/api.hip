@@ -713,6 +713,11 @@ __global__ void round_select_kernel(const DevTT* __restrict__ O, const RoundScra
     o.ranks[k + 1] = r;
     s_r = r;
   }
+  if (threadIdx.x == 0) {  // the discarded part of this bond (the rounding's error bound, squared)
+    double t2 = fmax(s.scal[2], 0.0);
+    for (int j = s_r; j < nc; ++j) t2 += s.sigma[j] * s.sigma[j];
+    s.scal[3] += t2;
+  }
   __syncthreads();
   const int r = s_r;
   for (int e = threadIdx.x; e < r * rq; e += blockDim.x) {
@@ -770,7 +775,18 @@ __global__ void round_norm_kernel(const DevTT* __restrict__ X, const RoundScratc
   if (threadIdx.x == 0) {
     s.scal[0] = sqrt(a);
     s.scal[1] = eps * sqrt(a) / sqrt((double)max(x.d - 1, 1));
+    s.scal[3] = 0.0;  // discarded tail^2, summed over the bonds by round_select_kernel
   }
+}
+
+// tails[f * stride] = sqrt(sum of the bonds' discarded tail^2) / ||A|| of the
+// last rounding (its relative error bound)
+__global__ void tail_record_kernel(const RoundScratch* __restrict__ S, int nf, double* __restrict__ tails,
+                                   long long stride) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nf) return;
+  const RoundScratch& s = S[f];
+  tails[f * stride] = s.scal[0] > 0.0 ? sqrt(fmax(s.scal[3], 0.0)) / s.scal[0] : 0.0;
 }
 
 // Workgroups per filter for a grid-stride kernel: enough to fill the chip
@@ -4762,8 +4778,10 @@ template <typename T, typename Acc>
 static tt_status run_steps(RunPlan& p, int B, const double* z, int zdim, int K, int k_begin, int k_count,
                            double* loglik, double* log_c, double* log_mpred, double* mean, double* cov,
                            int* ranks_out, int* ranks_pred_out, const int* replay_pred, const int* replay_filt,
-                           const tt_filter_spec* specs, hipStream_t st) {
+                           const tt_filter_spec* specs, hipStream_t st, const tt_monitor* mon) {
   const int d = p.d;
+  double* tails = mon ? mon->tail_dev : nullptr;
+  double* mmin = mon ? mon->marg_min_dev : nullptr;
   // all filters of a batch share eps (checked by run_plan); the rank rule
   // takes each filter's own cap from its rounding scratch, bounded by maxcap
   const double eps = specs[0].eps;
@@ -4814,7 +4832,15 @@ static tt_status run_steps(RunPlan& p, int B, const double* z, int zdim, int K, 
       TT_TRY(launch_conv<T>(B, d, p.r0capX, p.csmem, p.dK, p.dP, p.dX, st, p.fused ? 0 : 1));
       TT_TRY((round_launch<T, Acc>(p.shX, rx, eps, maxcap, st, p.fused ? &fl : nullptr,
                                    replay_pred ? replay_pred + (long long)k * (d + 1) : nullptr, rstride)));
+      if (tails) {
+        hipLaunchKernelGGL(tail_record_kernel, dim3(cdiv(B, 64)), dim3(64), 0, st, p.drs, B, tails + (long long)k * 2,
+                           (long long)K * 2);
+        TTG_LAUNCH_CHECK("tail_record_kernel");
+      }
       TT_TRY(launch_moments<T>(B, p.dP, p.dfc, log_mpred + k, K, nullptr, 0, nullptr, 0, p.mscr, p.mspf, p.mrcap, st));
+    } else if (tails) {  // no prediction at step 0
+      hipLaunchKernelGGL(fill_kernel, dim3(cdiv(B, 256)), dim3(256), 0, st, tails, (long long)B, (long long)K * 2, 0.0);
+      TTG_LAUNCH_CHECK("fill_kernel");
     }
     if (ranks_pred_out) {  // ranks of the predictive (the prior's at k = 0)
       hipLaunchKernelGGL(record_ranks_kernel, dim3(cdiv(B, 64)), dim3(64), 0, st, p.dP, B,
@@ -4827,9 +4853,19 @@ static tt_status run_steps(RunPlan& p, int B, const double* z, int zdim, int K, 
     TT_TRY(launch_hadamard<T>(B, d, p.r0capH, p.dL, p.dP, p.dH, st));
     TT_TRY((round_launch<T, Acc>(p.shH, rh, eps, maxcap, st, nullptr,
                                  replay_filt ? replay_filt + (long long)k * (d + 1) : nullptr, rstride)));
+    if (tails) {
+      hipLaunchKernelGGL(tail_record_kernel, dim3(cdiv(B, 64)), dim3(64), 0, st, p.drs, B,
+                         tails + (long long)k * 2 + 1, (long long)K * 2);
+      TTG_LAUNCH_CHECK("tail_record_kernel");
+    }
     TT_TRY(launch_moments<T>(B, p.dP, p.dfc, p.lmass, 1, mean ? mean + (long long)k * d : nullptr, (long long)K * d,
                              cov ? cov + (long long)k * d * d : nullptr, (long long)K * d * d, p.mscr, p.mspf,
                              p.mrcap, st));
+    if (mmin) {  // after the moments: the scratch is free again
+      hipLaunchKernelGGL((marginal_min_kernel<T>), dim3(B), dim3(256), 0, st, p.dP, mmin + k, (long long)K, p.mscr,
+                         p.mspf, p.mrcap);
+      TTG_LAUNCH_CHECK("marginal_min_kernel");
+    }
     if (ranks_out) {
       hipLaunchKernelGGL(record_ranks_kernel, dim3(cdiv(B, 64)), dim3(64), 0, st, p.dP, B,
                          ranks_out + (long long)k * (d + 1), rstride);
@@ -4866,7 +4902,7 @@ static tt_status filter_run_impl(int32_t batch, const tt_filter_spec* specs, con
                                  double* log_mpred_dev, double* mean_dev, double* cov_dev, int32_t* ranks_dev,
                                  int32_t* status_dev, int32_t* ranks_pred_dev, const int32_t* replay_pred_dev,
                                  const int32_t* replay_filt_dev, void* ws, size_t ws_bytes, hipStream_t st,
-                                 hipGraph_t* graph) {
+                                 hipGraph_t* graph, const tt_monitor* mon = nullptr) {
   if (!kernels || n_kernels < 1 || !z_dev || K < 1 || zdim < 1 || !loglik_dev || !log_c_dev || !log_mpred_dev ||
       !status_dev || !ws) {
     set_error("tt_filter_run: null pointer or bad size");
@@ -4924,10 +4960,10 @@ static tt_status filter_run_impl(int32_t batch, const tt_filter_spec* specs, con
   tt_status rs = precision == TT_F64
                      ? run_steps<double, AccDD>(p, batch, z_dev, zdim, K, k_begin, k_count, loglik_dev, log_c_dev,
                                                 log_mpred_dev, mean_dev, cov_dev, ranks_dev, ranks_pred_dev,
-                                                replay_pred_dev, replay_filt_dev, specs, run_st)
+                                                replay_pred_dev, replay_filt_dev, specs, run_st, mon)
                      : run_steps<float, AccD>(p, batch, z_dev, zdim, K, k_begin, k_count, loglik_dev, log_c_dev,
                                               log_mpred_dev, mean_dev, cov_dev, ranks_dev, ranks_pred_dev,
-                                              replay_pred_dev, replay_filt_dev, specs, run_st);
+                                              replay_pred_dev, replay_filt_dev, specs, run_st, mon);
   if (graph) {
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(run_st, &g);
@@ -4965,6 +5001,63 @@ tt_status tt_filter_run(int32_t batch, const tt_filter_spec* specs, const tt_tra
                          log_c_dev, log_mpred_dev, mean_dev, cov_dev, ranks_dev, status_dev, ranks_pred_dev,
                          replay_pred_dev, replay_filt_dev, ws, ws_bytes, reinterpret_cast<hipStream_t>(stream),
                          nullptr);
+}
+
+tt_status tt_filter_run_monitored(int32_t batch, const tt_filter_spec* specs, const tt_train* kernels,
+                                  int32_t n_kernels, const double* z_dev, int32_t zdim, int32_t K, int32_t k_begin,
+                                  int32_t k_count, int32_t precision, double* loglik_dev, double* log_c_dev,
+                                  double* log_mpred_dev, double* mean_dev, double* cov_dev, int32_t* ranks_dev,
+                                  int32_t* status_dev, int32_t* ranks_pred_dev, const int32_t* replay_pred_dev,
+                                  const int32_t* replay_filt_dev, const tt_monitor* monitor, void* ws,
+                                  size_t ws_bytes, void* stream) {
+  return filter_run_impl(batch, specs, kernels, n_kernels, z_dev, zdim, K, k_begin, k_count, precision, loglik_dev,
+                         log_c_dev, log_mpred_dev, mean_dev, cov_dev, ranks_dev, status_dev, ranks_pred_dev,
+                         replay_pred_dev, replay_filt_dev, ws, ws_bytes, reinterpret_cast<hipStream_t>(stream),
+                         nullptr, monitor);
+}
+
+size_t tt_marginal_min_workspace(int32_t batch, const tt_train* tts) {
+  if (batch < 1 || !tts) return 0;
+  int rcap = 1, dmax = 1;
+  for (int b = 0; b < batch; ++b) {
+    dmax = std::max(dmax, tts[b].d);
+    for (int j = 0; j <= tts[b].d && j <= TT_MAXD; ++j) rcap = std::max(rcap, tts[b].cap[j]);
+  }
+  const size_t spf = (size_t)dmax * rcap * rcap + 2 * (size_t)(dmax + 1) * rcap;
+  return (size_t)batch * (spf * sizeof(double) + sizeof(DevTT)) + 4096;
+}
+
+tt_status tt_marginal_min(int32_t batch, const tt_train* tts, double* out_dev, void* ws, size_t ws_bytes,
+                          void* stream) {
+  if (batch < 1 || !tts || !out_dev || !ws) {
+    set_error("tt_marginal_min: null pointer or batch < 1");
+    return TT_ERR_ARG;
+  }
+  const int dtype = tts[0].dtype;
+  int rcap = 1, dmax = 1;
+  std::vector<DevTT> v(batch);
+  for (int b = 0; b < batch; ++b) {
+    TT_TRY(check_train(&tts[b], "tt_marginal_min", dtype));
+    dmax = std::max(dmax, tts[b].d);
+    for (int j = 0; j <= tts[b].d; ++j) rcap = std::max(rcap, tts[b].cap[j]);
+    v[b] = make_dev(tts[b]);
+  }
+  const long long spf = (long long)dmax * rcap * rcap + 2LL * (dmax + 1) * rcap;
+  Arena ar(ws, ws_bytes);
+  DevTT* dt = ar.take<DevTT>(batch);
+  double* scr = ar.take<double>((size_t)batch * spf);
+  if (!ar.fits()) {
+    set_error("tt_marginal_min: workspace too small (%zu < %zu)", ws_bytes, ar.used);
+    return TT_ERR_WORKSPACE;
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  TT_TRY(upload(dt, v, st));
+  if (dtype == TT_F64)
+    hipLaunchKernelGGL((marginal_min_kernel<double>), dim3(batch), dim3(256), 0, st, dt, out_dev, 1LL, scr, spf, rcap);
+  else
+    hipLaunchKernelGGL((marginal_min_kernel<float>), dim3(batch), dim3(256), 0, st, dt, out_dev, 1LL, scr, spf, rcap);
+  TTG_LAUNCH_CHECK("marginal_min_kernel");
+  return TT_OK;
 }
 
 tt_status tt_filter_graph_create(int32_t batch, const tt_filter_spec* specs, const tt_train* kernels,

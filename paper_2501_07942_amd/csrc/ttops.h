@@ -444,6 +444,82 @@ __global__ void __launch_bounds__(256) moments_kernel(const DevTT* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
+// Smallest value over every 1-D marginal of a TT: the sums of its point
+// values over all axes but one, times exp(log_scale) (the negativity monitor:
+// the paper reports negative PMD values, Sec. 5.1 and Sec. 6).  Per core the
+// sums over the grid index S_k = sum_i A_k(:, i, :), prefix and suffix
+// chains of them, then per axis l and grid point i
+// left_l A_l(:, i, :) right_{l+1}.  One workgroup per filter;
+// scratch per filter: d rcap^2 + 2 (d + 1) rcap doubles.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) marginal_min_kernel(const DevTT* __restrict__ tt, double* __restrict__ out,
+                                                           long long stride, double* __restrict__ scratch,
+                                                           long long spf, int rcap) {
+  const int f = blockIdx.x;
+  const DevTT& A = tt[f];
+  const int d = A.d, tid = threadIdx.x;
+  const long long mat = (long long)rcap * rcap;
+  double* S = scratch + f * spf;          // [d][rcap * rcap]
+  double* left = S + d * mat;             // [d + 1][rcap]
+  double* right = left + (d + 1) * rcap;  // [d + 1][rcap]
+  __shared__ double smin[256];
+  for (int k = 0; k < d; ++k) {
+    const int r0 = A.ranks[k], r1 = A.ranks[k + 1], n = A.n[k];
+    const T* c = core_ptr<T>(A, k);
+    for (int q = tid; q < r0 * r1; q += blockDim.x) {
+      const int a = q / r1, bq = q - (q / r1) * r1;
+      double s0 = 0.0;
+      for (int i = 0; i < n; ++i) s0 += bulk_to_double(c[((long long)a * n + i) * r1 + bq]);
+      S[k * mat + a * r1 + bq] = s0;
+    }
+  }
+  if (tid == 0) {
+    left[0] = 1.0;
+    right[d * rcap] = 1.0;
+  }
+  __syncthreads();
+  for (int k = 0; k < d; ++k) {
+    const int r0 = A.ranks[k], r1 = A.ranks[k + 1];
+    for (int bq = tid; bq < r1; bq += blockDim.x) {
+      double s = 0.0;
+      for (int a = 0; a < r0; ++a) s += left[k * rcap + a] * S[k * mat + a * r1 + bq];
+      left[(k + 1) * rcap + bq] = s;
+    }
+    const int kk = d - 1 - k;
+    const int q0 = A.ranks[kk], q1 = A.ranks[kk + 1];
+    for (int a = tid; a < q0; a += blockDim.x) {
+      double s = 0.0;
+      for (int bq = 0; bq < q1; ++bq) s += S[kk * mat + a * q1 + bq] * right[(kk + 1) * rcap + bq];
+      right[kk * rcap + a] = s;
+    }
+    __syncthreads();
+  }
+  double mn = 1.7e308;
+  for (int l = 0; l < d; ++l) {
+    const int r0 = A.ranks[l], r1 = A.ranks[l + 1], n = A.n[l];
+    const T* c = core_ptr<T>(A, l);
+    for (int i = tid; i < n; i += blockDim.x) {
+      double v = 0.0;
+      for (int a = 0; a < r0; ++a) {
+        const T* row = c + ((long long)a * n + i) * r1;
+        double w = 0.0;
+        for (int bq = 0; bq < r1; ++bq) w += bulk_to_double(row[bq]) * right[(l + 1) * rcap + bq];
+        v += left[l * rcap + a] * w;
+      }
+      mn = fmin(mn, v);
+    }
+  }
+  smin[tid] = mn;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if (tid < o) smin[tid] = fmin(smin[tid], smin[tid + o]);
+    __syncthreads();
+  }
+  if (tid == 0) out[f * stride] = smin[0] * exp(*A.log_scale);
+}
+
+// ---------------------------------------------------------------------------
 // balance: scale the last core to unit Frobenius norm, log_scale += log(norm)
 // ---------------------------------------------------------------------------
 template <typename T>

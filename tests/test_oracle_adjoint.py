@@ -52,6 +52,35 @@ def test_sum_vjp_is_the_derivative_of_the_sum():
         assert abs(inner(g, dk) - exact) < 1e-12 * max(1.0, abs(exact))
 
 
+def test_moments_vjp_matches_directional_differences():
+    # the moments of model.moments_tt (means and covariance of the density
+    # the TT holds, on its grid) differentiated along a random core direction,
+    # against central differences of the moments themselves; the cell volume
+    # cancels, so it is the derivative with respect to the cores
+    rng = np.random.default_rng(4)
+    n = [6, 7, 5]
+    a = [np.abs(g) + 0.1 for g in rand_tt(rng, n, [3, 2])]
+    da = rand_tt(rng, n, [3, 2])
+    axes = mdl.grid_axes([-2.0, -1.0, 0.5], [3.0, 2.5, 4.0], n)
+    mb = rng.standard_normal(3)
+    cb = rng.standard_normal((3, 3))  # not symmetric: both entries of a pair count
+
+    def f(cores):
+        _, mean, cov = mdl.moments_tt(cores, axes)
+        return float(mb @ mean + np.sum(cb * cov))
+
+    g = oa.moments_vjp(a, axes, mb, cb)
+    h = 1e-6
+    fd = (f(perturbed(a, da, h)) - f(perturbed(a, da, -h))) / (2 * h)
+    assert abs(inner(g, da) - fd) < 1e-7 * max(1.0, abs(fd))
+    # only the means, only the covariance
+    g1 = oa.moments_vjp(a, axes, mb, None)
+    g2 = oa.moments_vjp(a, axes, None, cb)
+    assert abs(inner(g1, da) + inner(g2, da) - inner(g, da)) < 1e-12 * max(1.0, abs(fd))
+    # a scaled density has the same moments: the adjoint is orthogonal to it
+    assert abs(inner(g, a)) < 1e-10 * max(1.0, float(np.sqrt(inner(g, g) * inner(a, a))))
+
+
 def test_hadamard_and_conv_adjoint_identities():
     # <Cbar, dC> = <Abar, dA> + <Bbar, dB> for the bilinear maps, with the
     # forward maps taken from oracle.tt

@@ -84,3 +84,23 @@ def test_marginal_min_is_the_smallest_dense_marginal_value():
     want = min(float(f.sum(axis=tuple(j for j in range(3) if j != l)).min()) for l in range(3))
     assert abs(_marginal_min(a) - want) < 1e-12 * np.abs(f).sum()
     assert want < 0.0
+
+
+def test_rounding_tail_record_is_the_truncation_error_bound():
+    # the per-rounding record of the oracle filter: sqrt(sum of the squared
+    # discarded tails) / ||A||; for one bond it is the truncation error itself
+    # (Eckart-Young), for several an upper bound of it (the TT-SVD bound)
+    from oracle import tt as ttm
+    from oracle.filters import _tail_rel
+    rng = np.random.default_rng(11)
+    m = rng.standard_normal((20, 7)) @ rng.standard_normal((7, 18)) + 1e-3 * rng.standard_normal((20, 18))
+    a2 = [m.reshape(1, 20, 18), np.eye(18).reshape(18, 18, 1)]
+    r2, info = ttm.tt_round(a2, 1e-12, 4, return_info=True)
+    err = np.linalg.norm(ttm.full(r2) - m) / np.linalg.norm(m)
+    assert abs(_tail_rel(info) - err) <= 1e-10 * err
+    cores = [rng.standard_normal((1, 6, 5)), rng.standard_normal((5, 7, 6)), rng.standard_normal((6, 5, 4)),
+             rng.standard_normal((4, 6, 1))]
+    r4, info = ttm.tt_round(cores, 1e-12, 3, return_info=True)
+    full = ttm.full(cores)
+    err = np.linalg.norm(ttm.full(r4) - full) / np.linalg.norm(full)
+    assert 0.0 < err <= _tail_rel(info) * (1 + 1e-10)
