@@ -435,6 +435,59 @@ tt_status tt_normalize_moments_noalloc(int32_t batch, const tt_grid* grids, cons
  *   x_bar.log_scale = mbar.
  * --------------------------------------------------------------------- */
 /* ---------------------------------------------------------------------
+ * tt_update_adjoint: the adjoint of tt_update (Sec. 2.2 eqs.
+ * pmf_filtrace_a/b: the likelihood TT L built from z, H = L o P_pred,
+ * log c_k = log(sum(H) delta) + log-scales), FP64.  Given the forward's
+ * p_pred and its output h (same grids, meas, z, lik_rank_cap as that
+ * tt_update call), the adjoint h_bar of H (cores and log-scale, H's ranks;
+ * nullable: 0) and log_c_bar_dev[b] (nullable: 0), it rebuilds L and the
+ * dense likelihood input, and writes
+ *   p_pred_bar   the adjoint of P_pred (cores; log_scale = that of H's
+ *                total adjoint), TT_STATUS_CAPACITY on its status word when a
+ *                rank or capacity does not match;
+ *   theta_bar_dev[b * n_theta + d + j] += the derivative with respect to the
+ *                measurement parameters (sigma_r, sigma_lin, s_1, s_2 for the
+ *                range model, n_theta = d + 4; sigma_lin for the linear one,
+ *                n_theta = d + 1), analytic in the dense likelihood through
+ *                the adjoint of its truncated SVD (tt_likelihood_adjoint);
+ *                entries 0..d-1 are not touched (the caller zeroes or
+ *                accumulates).
+ * z_dev[b * z_stride + j] as for tt_update.  Workspace:
+ * tt_update_adjoint_workspace(...) bytes.  Asynchronous after its descriptor
+ * uploads.  Errors: TT_ERR_ARG, TT_ERR_SHAPE, TT_ERR_WORKSPACE and those of
+ * the composed calls.
+ * --------------------------------------------------------------------- */
+size_t tt_update_adjoint_workspace(int32_t batch, const tt_grid* grids, const tt_meas* meas, const tt_train* p_pred,
+                                   const tt_train* h, int32_t lik_rank_cap);
+tt_status tt_update_adjoint(int32_t batch, const tt_grid* grids, const tt_meas* meas, const double* z_dev,
+                            int32_t z_stride, const tt_train* p_pred, const tt_train* h, const tt_train* h_bar,
+                            const double* log_c_bar_dev, int32_t lik_rank_cap, const tt_train* p_pred_bar,
+                            double* theta_bar_dev, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------
+ * tt_normalize_moments_adjoint: the adjoint of tt_normalize_moments with
+ * its moments (the moments of Alg. 2; Sec. 4.1 'dot', 'power'): given p_bar
+ * and log_mass_bar_dev as for tt_normalize_adjoint, and the adjoints of the
+ * moments of the normalised density, mean_bar_dev[b * d + l] and
+ * cov_bar_dev[b * d * d + l * d + j] (each nullable: 0; both entries of a
+ * symmetric pair count), writes x_bar = tt_normalize_adjoint's result plus
+ * the moments' term: with M_w = sum_i w(i) X(i) for the rank-one weights
+ * 1, x_l, x_l^2 and x_l x_j on the grid points of grids[b] (the cell volume
+ * and the log-scale cancel), mean_l = M_{x_l} / M_1 and cov_lj =
+ * M_{x_l x_j} / M_1 - mean_l mean_j, the term is sum_w c_w dM_w / dX with
+ * the coefficients of the quotient and product rules.  x, p_bar, x_bar as
+ * for tt_normalize_adjoint (FP64 or FP32, x_bar with x's layout); grids[b]
+ * has x[b]'s modes.  Workspace: tt_normalize_moments_adjoint_workspace(
+ * batch, x) bytes.  Asynchronous after its descriptor uploads.  Errors:
+ * TT_ERR_ARG, TT_ERR_SHAPE, TT_ERR_WORKSPACE.
+ * --------------------------------------------------------------------- */
+size_t tt_normalize_moments_adjoint_workspace(int32_t batch, const tt_train* x);
+tt_status tt_normalize_moments_adjoint(int32_t batch, const tt_grid* grids, const tt_train* x,
+                                       const tt_train* p_bar, const double* log_mass_bar_dev,
+                                       const double* mean_bar_dev, const double* cov_bar_dev,
+                                       const tt_train* x_bar, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------
  * tt_round_adjoint: adjoint of the rounding of Sec. 4.1 'round' (the
  * right-to-left orthogonalisation and the left-to-right truncated SVDs of
  * tt_round) at the ranks it produced, FP64.

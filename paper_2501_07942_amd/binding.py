@@ -96,6 +96,10 @@ def _load():
         "tt_filter_run": (I, [I, P, P, I, P, I, I, I, I, I, P, P, P, P, P, P, P, P, P, P, P, S, P]),
         "tt_filter_run_monitored": (I, [I, P, P, I, P, I, I, I, I, I, P, P, P, P, P, P, P, P, P, P, P, P, S, P]),
         "tt_marginal_min_workspace": (S, [I, P]),
+        "tt_normalize_moments_adjoint_workspace": (S, [I, P]),
+        "tt_update_adjoint_workspace": (S, [I, P, P, P, P, I]),
+        "tt_update_adjoint": (I, [I, P, P, P, I, P, P, P, P, I, P, P, P, S, P]),
+        "tt_normalize_moments_adjoint": (I, [I, P, P, P, P, P, P, P, P, S, P]),
         "tt_marginal_min": (I, [I, P, P, P, S, P]),
         "tt_filter_graph_create": (I, [I, P, P, I, P, I, I, I, I, I, P, P, P, P, P, P, P, P, P, P, P, S, P,
                                        C.POINTER(C.c_void_p)]),
@@ -167,7 +171,8 @@ EXPORTED = ("tt_train_elems", "tt_last_error", "tt_version", "tt_kernel_build_wo
             "tt_filter_run_taped", "tt_filter_run_adjoint", "tt_kernel_build_cross_workspace",
             "tt_kernel_build_cross", "tt_interpolate_lattice_workspace", "tt_interpolate_lattice",
             "tt_filter_run_linear_workspace", "tt_filter_run_linear", "tt_filter_run_monitored",
-            "tt_marginal_min_workspace", "tt_marginal_min")
+            "tt_marginal_min_workspace", "tt_marginal_min", "tt_normalize_moments_adjoint_workspace",
+            "tt_normalize_moments_adjoint", "tt_update_adjoint_workspace", "tt_update_adjoint")
 
 PREDICT_DIRECT, PREDICT_FFT, PREDICT_UNFUSED, PREDICT_DIRECT_VALU = 0, 1, 2, 3
 
@@ -710,6 +715,40 @@ def tt_likelihood(grids: Sequence[Grid], meas: Sequence[Meas], z, l_out: Sequenc
     ws = _ws(nbytes)
     _check(LIB.tt_likelihood(B, g, m, z.data_ptr(), int(z.shape[1]), ls, int(lik_rank_cap), ws.data_ptr(),
                              ws.numel(), _stream()), "tt_likelihood")
+
+
+def tt_normalize_moments_adjoint(grids: Sequence[Grid], x: Sequence[DeviceTT], p_bar: Sequence[DeviceTT],
+                                 log_mass_bar, x_bar: Sequence[DeviceTT], mean_bar=None, cov_bar=None):
+    """log_mass_bar [B], mean_bar [B, d], cov_bar [B, d, d]: float64 device tensors (the last two nullable)."""
+    B = len(x)
+    xs = _arr([t.struct() for t in x])
+    ws = _ws(LIB.tt_normalize_moments_adjoint_workspace(B, xs))
+    _check(LIB.tt_normalize_moments_adjoint(B, _arr(list(grids)), xs, _arr([t.struct() for t in p_bar]),
+                                            log_mass_bar.data_ptr() if log_mass_bar is not None else None,
+                                            mean_bar.data_ptr() if mean_bar is not None else None,
+                                            cov_bar.data_ptr() if cov_bar is not None else None,
+                                            _arr([t.struct() for t in x_bar]), ws.data_ptr(), ws.numel(),
+                                            _stream()), "tt_normalize_moments_adjoint")
+
+
+def tt_update_adjoint(grids: Sequence[Grid], meas: Sequence[Meas], z, p_pred: Sequence[DeviceTT],
+                      h: Sequence[DeviceTT], h_bar, log_c_bar, lik_rank_cap: int, p_pred_bar: Sequence[DeviceTT],
+                      theta_bar):
+    """z: float64 device tensor [B, zdim]; h_bar: list of DeviceTT or None;
+    log_c_bar [B] (or None) and theta_bar [B, n_theta] float64 device tensors
+    (theta_bar is accumulated into)."""
+    B = len(p_pred)
+    g, m = _arr(list(grids)), _arr(list(meas))
+    ps, hs = _arr([t.struct() for t in p_pred]), _arr([t.struct() for t in h])
+    nbytes = LIB.tt_update_adjoint_workspace(B, g, m, ps, hs, int(lik_rank_cap))
+    if nbytes == 0:
+        _check(ERR_ARG, "tt_update_adjoint_workspace")
+    ws = _ws(nbytes)
+    _check(LIB.tt_update_adjoint(B, g, m, z.data_ptr(), int(z.shape[1]), ps, hs,
+                                 _arr([t.struct() for t in h_bar]) if h_bar is not None else None,
+                                 log_c_bar.data_ptr() if log_c_bar is not None else None, int(lik_rank_cap),
+                                 _arr([t.struct() for t in p_pred_bar]), theta_bar.data_ptr(), ws.data_ptr(),
+                                 ws.numel(), _stream()), "tt_update_adjoint")
 
 
 def tt_marginal_min(tts: Sequence[DeviceTT], out):

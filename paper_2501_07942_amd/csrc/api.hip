@@ -5481,3 +5481,5 @@ tt_status tt_autotune_prediction(int32_t batch, const tt_filter_spec* specs, con
 #include "cross.h"
 #include "grad_run.h"
 #include "linear_run.h"
+#include "moments_adj.h"
+#include "update_adj.h"

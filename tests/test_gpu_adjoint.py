@@ -160,3 +160,57 @@ def test_normalize_adjoint_matches_oracle(B, prec, shape):
     assert st == 0 and ls == w
     for k in range(len(n)):
         assert rel(xb[k], xbar_or[k]) < (1e-12 if prec == "f64" else 1e-5), k
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_normalize_moments_adjoint_matches_oracle(B, prec):
+    # the normalisation's adjoint plus that of the moments: downstream
+    # g = <full(P), T> + w log m + <mb, mean> + <cb, cov>, a batch of two
+    # filters with different grids and ranks; the oracle adds moments_vjp
+    import math
+    import torch
+    from oracle import model as mdl
+    pr = B.F64 if prec == "f64" else B.F32
+    rng = np.random.default_rng(12)
+    shapes = [([9, 11, 7], [4, 3], [-2.0, -1.0, 0.5], [3.0, 2.5, 4.0]),
+              ([6, 13, 5], [2, 5], [0.0, -4.0, -1.0], [1.5, 4.0, 2.0])]
+    X, PB, XB, grids, refs = [], [], [], [], []
+    mbs, cbs, lms = [], [], []
+    for n, r, lo, hi in shapes:
+        caps = [1] + list(r) + [1]
+        x = [np.abs(g) + 0.2 for g in rand_tt(rng, n, r)]
+        axes = mdl.grid_axes(lo, hi, n)
+        delta = mdl.cell_volume(axes)
+        t = rng.standard_normal(n)
+        w = float(rng.standard_normal())
+        mb = rng.standard_normal(3)
+        cb = rng.standard_normal((3, 3))
+        s = ttm.tt_sum(x)
+        m = s * delta
+        p_or = ttm.scale(x, 1.0 / m)
+        pbar_or = full_vjp(p_or, t)
+        xbar_or, cbs_ = oa.scale_vjp(x, 1.0 / m, pbar_or)
+        oa.tt_axpy(xbar_or, oa.sum_vjp(x, (-cbs_ / m ** 2 + w / m) * delta))
+        oa.tt_axpy(xbar_or, oa.moments_vjp(x, axes, mb, cb))
+        refs.append(xbar_or)
+        ls_p = -math.log(s * delta)
+        pbar_gpu = [g * math.exp(ls_p) for g in full_vjp(x, t)]
+        sbar_p = float(np.sum(ttm.full(x) * t)) * math.exp(ls_p)
+        X.append(dev(B, x, caps, pr))
+        PB.append(dev(B, pbar_gpu, caps, pr, log_scale=sbar_p))
+        XB.append(empty_like(B, x, caps, pr))
+        grids.append(B.make_grid(3, n, lo, hi))
+        mbs.append(mb)
+        cbs.append(cb)
+        lms.append(w)
+    lmb = torch.tensor(lms, dtype=torch.float64, device="cuda")
+    mbt = torch.tensor(np.stack(mbs), dtype=torch.float64, device="cuda")
+    cbt = torch.tensor(np.stack(cbs), dtype=torch.float64, device="cuda")
+    print(f"normalize + moments adjoint {prec}: 2 filters", flush=True)
+    B.tt_normalize_moments_adjoint(grids, X, PB, lmb, XB, mbt, cbt)
+    torch.cuda.synchronize()
+    for f, ref in enumerate(refs):
+        xb, ls, st = XB[f].fetch()
+        assert st == 0 and ls == lms[f]
+        for k in range(3):
+            assert rel(xb[k], ref[k]) < (1e-11 if prec == "f64" else 1e-4), (f, k, rel(xb[k], ref[k]))
