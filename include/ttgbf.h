@@ -23,6 +23,12 @@
  *   - `stream` is a hipStream_t passed as void* (NULL = default stream).
  *     Work is enqueued asynchronously; results are valid after the stream
  *     is synchronised.  Calls are reentrant given distinct workspaces.
+ *     Descriptor tables reach the device through a page-locked ring the
+ *     library keeps per process (64 MB, allocated on the first call that
+ *     uploads; its regions are reused only after their copies completed),
+ *     so the uploads do not wait on the stream; the calls marked
+ *     synchronous below wait for their own reasons (host reads of ranks or
+ *     boxes).
  *   - Return value: TT_OK, or an argument/shape/workspace/HIP error detected
  *     on the host BEFORE anything is enqueued (TT_ERR_HIP is returned when a
  *     launch fails; tt_last_error() then holds the message).
@@ -384,7 +390,8 @@ size_t tt_normalize_moments_workspace(int32_t batch, const tt_train* t);
  * that device current.  Every call on a device shares that device's array
  * and leaves its contents behind: calls that overlap on one device (several
  * streams or host threads) race and must be serialised by the caller.  The
- * descriptor upload synchronises `stream` as tt_normalize_moments does.
+ * descriptor upload does not use the library's upload ring: it copies from
+ * the call's own host memory and synchronises `stream`.
  * Errors: as tt_normalize_moments; TT_ERR_WORKSPACE when batch, d and the
  * rank capacities need more than TT_NOALLOC_SCRATCH_BYTES (the message
  * gives both sizes), TT_ERR_HIP when the device or the array's address
@@ -407,8 +414,7 @@ tt_status tt_normalize_moments_noalloc(int32_t batch, const tt_grid* grids, cons
  * else 0.  All sums are FP64 in a fixed order.  Workspace:
  * tt_adjoint_workspace(batch, d, largest rank capacity) bytes, used for the
  * uploaded descriptors (and the sum environments of tt_normalize_adjoint);
- * the calls are asynchronous on stream after a synchronous descriptor
- * upload, like the forward calls.
+ * the calls are asynchronous on stream, like the forward calls.
  *
  * tt_predict_adjoint: for the prediction C = K (*) P of tt_predict (Sec.
  * 4.2: C_k(a rp0 + c, i, b rp1 + e) = sum_m K_k(a, m+h, b) P_k(c, i-m, e),
@@ -804,8 +810,8 @@ tt_status tt_filter_run_linear(int32_t batch, const tt_filter_spec* specs, const
  * recursion of Alg. 2 repeated without host launch work).
  *
  * tt_filter_graph_create takes exactly the arguments of tt_filter_run.  It
- * validates them, uploads the batch descriptors into ws (synchronously, on
- * stream), records the launches of steps k_begin .. k_begin+k_count-1 on a
+ * validates them, uploads the batch descriptors into ws (on stream, then
+ * waits for them), records the launches of steps k_begin .. k_begin+k_count-1 on a
  * capture stream of its own and instantiates the graph; nothing runs.
  * k_begin must be >= 1: step 0 starts from the prior and is run once with
  * tt_filter_run.  Every tt_filter_graph_launch then executes those steps on
@@ -851,7 +857,7 @@ void tt_filter_graph_destroy(tt_graph* graph);
  * not fit the destination's capacity copies nothing and sets
  * TT_STATUS_CAPACITY on the train's status word (both directions).  The
  * caller's status_dev of the run is not part of the state.  Asynchronous on
- * stream after a synchronous descriptor upload.  Errors: TT_ERR_ARG,
+ * stream.  Errors: TT_ERR_ARG,
  * TT_ERR_SHAPE (d or modes differ from the grids), TT_ERR_WORKSPACE,
  * TT_ERR_HIP.
  * --------------------------------------------------------------------- */

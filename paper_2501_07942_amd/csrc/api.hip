@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <mutex>
 #include <new>
 #include <string>
@@ -183,13 +184,98 @@ static tt_status check_train(const tt_train* t, const char* name, int want_dtype
   return TT_OK;
 }
 
+// Descriptor uploads without a stream wait: the host data is copied into a
+// page-locked ring (64 MB, allocated on first use) and uploaded from there
+// with an event recorded behind the copy; a ring region is reused only after
+// the event of every upload that occupied it has completed (the oldest
+// uploads are waited for when the ring is full).  Regions are taken in
+// order, so the in-flight uploads form one circular interval of the ring.
+// An upload larger than the ring falls back to a copy and a stream wait.
+// the upload with a stream wait and no library memory (the allocation-free
+// entry point)
 template <typename T>
-static tt_status upload(T* dst, const std::vector<T>& src, hipStream_t s) {
+static tt_status upload_wait(T* dst, const std::vector<T>& src, hipStream_t s) {
   if (src.empty()) return TT_OK;
   HIP_TRY(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s),
           "descriptor upload");
-  // the host vectors die when the call returns: wait for the copy
-  HIP_TRY(hipStreamSynchronize(s), "descriptor upload sync");
+  HIP_TRY(hipStreamSynchronize(s), "descriptor upload sync");  // the host vectors die when the call returns
+  return TT_OK;
+}
+
+struct UploadRing {
+  struct Slot {
+    hipEvent_t ev;
+    size_t start, end;
+  };
+  std::mutex mu;
+  char* buf = nullptr;
+  size_t cap = 0;
+  std::deque<Slot> inflight;
+  std::vector<hipEvent_t> spare;
+};
+static UploadRing g_ring;
+
+template <typename T>
+static tt_status upload(T* dst, const std::vector<T>& src, hipStream_t s) {
+  if (src.empty()) return TT_OK;
+  const size_t bytes = src.size() * sizeof(T), need = (bytes + 255) & ~size_t(255);
+  std::lock_guard<std::mutex> lk(g_ring.mu);
+  if (!g_ring.buf) {
+    const size_t c = size_t(64) << 20;
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&g_ring.buf), c, hipHostMallocPortable), "upload ring alloc");
+    g_ring.cap = c;
+  }
+  if (need >= g_ring.cap / 2) {
+    HIP_TRY(hipMemcpyAsync(dst, src.data(), bytes, hipMemcpyHostToDevice, s), "descriptor upload");
+    HIP_TRY(hipStreamSynchronize(s), "descriptor upload sync");
+    return TT_OK;
+  }
+  auto& q = g_ring.inflight;
+  while (!q.empty() && hipEventQuery(q.front().ev) == hipSuccess) {  // completed uploads free their regions
+    g_ring.spare.push_back(q.front().ev);
+    q.pop_front();
+  }
+  size_t start = 0;
+  for (;;) {
+    if (q.empty()) {
+      start = 0;
+      break;
+    }
+    const size_t fs = q.front().start, be = q.back().end;
+    if (be > fs) {  // occupied [fs, be): free [be, cap) and [0, fs)
+      if (be + need <= g_ring.cap) {
+        start = be;
+        break;
+      }
+      if (need < fs) {
+        start = 0;
+        break;
+      }
+    } else if (be + need < fs) {  // wrapped, occupied [fs, cap) and [0, be): free [be, fs)
+      start = be;
+      break;
+    }
+    HIP_TRY(hipEventSynchronize(q.front().ev), "upload ring wait");
+    g_ring.spare.push_back(q.front().ev);
+    q.pop_front();
+  }
+  hipEvent_t ev;
+  if (g_ring.spare.empty()) {
+    HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "upload event");
+  } else {
+    ev = g_ring.spare.back();
+    g_ring.spare.pop_back();
+  }
+  memcpy(g_ring.buf + start, src.data(), bytes);
+  const hipError_t e1 = hipMemcpyAsync(dst, g_ring.buf + start, bytes, hipMemcpyHostToDevice, s);
+  const hipError_t e2 = e1 == hipSuccess ? hipEventRecord(ev, s) : e1;
+  if (e2 != hipSuccess) {
+    // the region may still be read: drain the stream before it can be reused
+    (void)hipStreamSynchronize(s);
+    g_ring.spare.push_back(ev);
+    return check_hip(e2, "descriptor upload");
+  }
+  q.push_back({ev, start, start + need});
   return TT_OK;
 }
 
@@ -4103,7 +4189,7 @@ namespace ttg {
 // or the library's static array for tt_normalize_moments_noalloc).
 static tt_status normalize_moments_impl(const char* who, int32_t batch, const tt_grid* grids, const tt_train* t,
                                         double* log_mass_dev, double* mean_dev, double* cov_dev, void* ws,
-                                        size_t ws_bytes, void* stream) {
+                                        size_t ws_bytes, void* stream, bool no_ring = false) {
   if (batch < 1 || !grids || !t || !ws) {
     set_error("%s: bad arguments", who);
     return TT_ERR_ARG;
@@ -4141,8 +4227,13 @@ static tt_status normalize_moments_impl(const char* who, int32_t batch, const tt
     return TT_ERR_WORKSPACE;
   }
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  TT_TRY(upload(dt, vt, st));
-  TT_TRY(upload(dfc, vfc, st));
+  if (no_ring) {
+    TT_TRY(upload_wait(dt, vt, st));
+    TT_TRY(upload_wait(dfc, vfc, st));
+  } else {
+    TT_TRY(upload(dt, vt, st));
+    TT_TRY(upload(dfc, vfc, st));
+  }
   if (dtype == TT_F64)
     return launch_moments<double>(batch, dt, dfc, log_mass_dev, 1, mean_dev, d, cov_dev, (long long)d * d, scratch,
                                   spf, rcap, st);
@@ -4202,7 +4293,7 @@ tt_status tt_normalize_moments_noalloc(int32_t batch, const tt_grid* grids, cons
   void* ptr = nullptr;
   TT_TRY(scratch_address(&ptr));
   return normalize_moments_impl("tt_normalize_moments_noalloc", batch, grids, t, log_mass_dev, mean_dev, cov_dev, ptr,
-                                TT_NOALLOC_SCRATCH_BYTES, stream);
+                                TT_NOALLOC_SCRATCH_BYTES, stream, true);
 }
 
 // ---------------------------------------------------------------------------
@@ -4948,8 +5039,10 @@ static tt_status filter_run_impl(int32_t batch, const tt_filter_spec* specs, con
   hipStream_t run_st = st;
   if (graph) {
     // capture on a stream of our own (the caller's may be the null stream);
-    // the descriptors are already on the device, so nothing in the recorded
-    // steps reads host memory
+    // the descriptors are on the device once the uploads on st are done (the
+    // replays may run on any stream), so nothing in the recorded steps reads
+    // host memory
+    HIP_TRY(hipStreamSynchronize(st), "descriptor uploads before capture");
     HIP_TRY(hipStreamCreateWithFlags(&run_st, hipStreamNonBlocking), "capture stream");
     const hipError_t e = hipStreamBeginCapture(run_st, hipStreamCaptureModeRelaxed);
     if (e != hipSuccess) {
