@@ -916,7 +916,7 @@ static tt_status launch_gram(F f, int B, int Mcap, long long Tcap, int smax, hip
   // 32 x 32 or 64 x 64 tiles (both sum every element in the same order).
   const int t = (Mcap + 63) / 64;
   if constexpr (std::is_same<Acc, AccD>::value) {
-    hipLaunchKernelGGL((gram_mfma_kernel<T, F>), dim3(t * (t + 1) / 2, smax, B), dim3(256), 0, st, f);
+    hipLaunchKernelGGL((gram_mfma_kernel<T, F>), dim3(t * (t + 1) / 2, std::min(smax, GM_YMAX), B), dim3(256), 0, st, f);
   } else {
     if (Mcap > 32)
       hipLaunchKernelGGL((gram_partial_kernel<T, Acc, 64, F>), dim3(t * (t + 1) / 2, smax, B), dim3(256), 0, st, f);

@@ -8,6 +8,32 @@
 
 #define TTG_HOST_DEVICE __host__ __device__
 
+// Global-memory view of a device pointer.  Pointers that a kernel reads out
+// of a descriptor are generic, and loads and stores through them compile to
+// flat instructions, which count against the LDS wait counter as well: every
+// LDS wait in such a kernel then also waits for its HBM traffic in flight.
+// Accesses through this view are global instructions instead.  The
+// qualifier exists only in the device pass; host code never dereferences it.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define TTG_GLOBAL __attribute__((address_space(1)))
+#else
+#define TTG_GLOBAL
+#endif
+template <typename T>
+__device__ __forceinline__ TTG_GLOBAL T* gmem(T* p) {
+  return (TTG_GLOBAL T*)p;
+}
+
+// Workgroup barrier that orders LDS accesses only.  __syncthreads() also
+// waits for every global store of the wavefront to complete; the kernels
+// that use this never read back their own global writes, so their output
+// stores stay in flight across the barrier.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // ---------------------------------------------------------------------------
 // device copy of a tt_train, with core offsets resolved
 // ---------------------------------------------------------------------------

@@ -108,21 +108,53 @@ __global__ void __launch_bounds__(256) gram_partial_kernel(F f) {
 
 // ---------------------------------------------------------------------------
 // The same Gram partials with FP64 accumulation on the matrix cores
-// (v_mfma_f64_16x16x4f64): one 64 x 64 upper-triangular tile pair and one
-// split per workgroup, each wavefront a 32 x 32 quadrant (2 x 2 MFMA tiles).
-// A chunk of 32 summation indices of both row blocks is staged in LDS as
-// FP64; within a chunk the k-lane lk of an MFMA step s takes index
-// lk * 8 + s, so a lane reads its eight operands as one contiguous run.
-// Products of FP32 inputs are exact in FP64.  Lane layout of the MFMA:
+// (v_mfma_f64_16x16x4f64): one 64 x 64 upper-triangular tile pair per
+// workgroup, each wavefront a 32 x 32 quadrant (2 x 2 MFMA tiles).  Chunks
+// of 32 summation indices of both row blocks are staged in LDS in the input
+// type, double-buffered (one barrier per chunk: the next chunk is fetched
+// into registers and stored to the other buffer while this one is
+// multiplied) and widened to FP64 as they are read; within a chunk the
+// k-lane lk of an MFMA step s takes index lk * 8 + s, so a lane reads its
+// eight operands as one contiguous run.  Products of FP32 inputs are exact
+// in FP64.  A workgroup takes the splits blockIdx.y, blockIdx.y + gridDim.y,
+// ... of its tile pair, so a launch sized for the largest split count does
+// not leave most of its workgroups without work.  Lane layout of the MFMA:
 // A(i, k) in lane i + 16 k, B(k, j) in lane j + 16 k, D(i, j) in lane
 // j + 16 (i % 4), register i / 4.
 // ---------------------------------------------------------------------------
 typedef double md4 __attribute__((ext_vector_type(4)));
 #define GM_KC 32
-#define GM_PITCH (GM_KC + 2)
+#define GM_YMAX 4  // split planes per launch row (workgroups loop over the rest)
+
+template <typename TB>
+struct GmLds {
+  static constexpr int pitch = GM_KC + 16 / (int)sizeof(TB);  // 16-byte aligned rows
+  // four consecutive elements widened to FP64
+  __device__ static inline void read4(const TB* p, double* v) {
+    if constexpr (sizeof(TB) == 4) {
+      const float4 t = *reinterpret_cast<const float4*>(p);
+      v[0] = t.x;
+      v[1] = t.y;
+      v[2] = t.z;
+      v[3] = t.w;
+    } else {
+      const double2 t0 = *reinterpret_cast<const double2*>(p);
+      const double2 t1 = *reinterpret_cast<const double2*>(p + 2);
+      v[0] = t0.x;
+      v[1] = t0.y;
+      v[2] = t1.x;
+      v[3] = t1.y;
+    }
+  }
+  // element u of a thread's share of a chunk: row r of the block, index c
+  __device__ static inline int2 rc(int tid, int u, bool t_fast) {
+    const int e = tid + u * 256;
+    return t_fast ? int2{e / GM_KC, e % GM_KC} : int2{e % 64, e / 64};
+  }
+};
 
 template <typename TB, typename F>
-__global__ void __launch_bounds__(256) gram_mfma_kernel(F f) {
+__global__ void __launch_bounds__(256, 2) gram_mfma_kernel(F f) {
   const int b = blockIdx.z;
   GramArgs g;
   if (!f(b, g)) return;
@@ -135,100 +167,98 @@ __global__ void __launch_bounds__(256) gram_mfma_kernel(F f) {
   }
   if (ti >= ntile) return;
   const int tj = ti + tp;
-  const int s = blockIdx.y;
-  if (s >= g.splits) return;
-  const int chunk = (g.T + g.splits - 1) / g.splits;
-  const int t_begin = s * chunk, t_end = min(g.T, t_begin + chunk);
-  __shared__ double As[64 * GM_PITCH];
-  __shared__ double Bs[64 * GM_PITCH];
+  constexpr int PITCH = GmLds<TB>::pitch;
+  constexpr int BUF = 64 * PITCH;  // one row block of one chunk
+  __shared__ __align__(16) TB Ls[2 * 2 * BUF];  // [buffer][A or B][64][PITCH]
   const bool diag_tile = ti == tj;
-  const double* Bsrc = diag_tile ? As : Bs;
-  const TB* x = reinterpret_cast<const TB*>(g.x);
+  const TTG_GLOBAL TB* x = gmem(reinterpret_cast<const TB*>(g.x));
   const bool t_fast = g.st == 1;
   const int a0 = ti * 64, b0 = tj * 64;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int qa = wv >> 1, qb = wv & 1;
   const int lr = lane & 15, lk = lane >> 4;
-  md4 acc[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = md4{0.0, 0.0, 0.0, 0.0};
-  // each thread stages GM_PER elements of both row blocks per chunk; the
-  // next chunk is loaded into registers while the current one is multiplied
+  const int chunk = (g.T + g.splits - 1) / g.splits;
   constexpr int GM_PER = 64 * GM_KC / 256;
-  TB pa_[GM_PER], pb_[GM_PER];
-  auto fetch = [&](int t0) {
+  for (int s = blockIdx.y; s < g.splits; s += gridDim.y) {
+    const int t_begin = s * chunk, t_end = min(g.T, t_begin + chunk);
+    md4 acc[2][2];
 #pragma unroll
-    for (int u = 0; u < GM_PER; ++u) {
-      const int e = tid + u * 256;
-      int r, c;
-      if (t_fast) {
-        r = e / GM_KC;
-        c = e - r * GM_KC;
-      } else {
-        c = e / 64;
-        r = e - c * 64;
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = md4{0.0, 0.0, 0.0, 0.0};
+    // each thread stages GM_PER elements of both row blocks per chunk
+    TB pa_[GM_PER], pb_[GM_PER];
+    // element u sits at a wave-uniform base plus this lane's 32-bit offset
+    // (loff), so the loads need no 64-bit address per element
+    const unsigned loff = t_fast ? (unsigned)((tid >> 5) * g.sa + (tid & 31))
+                                 : (unsigned)((tid & 63) * g.sa + (tid >> 6) * g.st);
+    const long long ustep = t_fast ? 8 * g.sa : 4 * g.st;
+    auto fetch = [&](int t0) {
+      const TTG_GLOBAL TB* xa = x + (long long)a0 * g.sa + (long long)t0 * g.st;
+      const TTG_GLOBAL TB* xb = x + (long long)b0 * g.sa + (long long)t0 * g.st;
+#pragma unroll
+      for (int u = 0; u < GM_PER; ++u) {
+        const int2 q = GmLds<TB>::rc(tid, u, t_fast);
+        const bool tv = t0 + q.y < t_end;
+        pa_[u] = (tv && a0 + q.x < g.M) ? (xa + u * ustep)[loff] : (TB)0;
+        pb_[u] = (!diag_tile && tv && b0 + q.x < g.M) ? (xb + u * ustep)[loff] : (TB)0;
       }
-      const int t = t0 + c;
-      const bool tv = t < t_end;
-      pa_[u] = (tv && a0 + r < g.M) ? x[(long long)(a0 + r) * g.sa + (long long)t * g.st] : (TB)0;
-      pb_[u] = (!diag_tile && tv && b0 + r < g.M) ? x[(long long)(b0 + r) * g.sa + (long long)t * g.st] : (TB)0;
-    }
-  };
-  if (t_begin < t_end) fetch(t_begin);
-  for (int t0 = t_begin; t0 < t_end; t0 += GM_KC) {
-    __syncthreads();  // previous chunk consumed
+    };
+    auto stage = [&](int buf) {
+      TB* As = Ls + buf * 2 * BUF;
 #pragma unroll
-    for (int u = 0; u < GM_PER; ++u) {
-      const int e = tid + u * 256;
-      int r, c;
-      if (t_fast) {
-        r = e / GM_KC;
-        c = e - r * GM_KC;
-      } else {
-        c = e / 64;
-        r = e - c * 64;
+      for (int u = 0; u < GM_PER; ++u) {
+        const int2 q = GmLds<TB>::rc(tid, u, t_fast);
+        As[q.x * PITCH + q.y] = pa_[u];
+        if (!diag_tile) As[BUF + q.x * PITCH + q.y] = pb_[u];
       }
-      As[r * GM_PITCH + c] = bulk_to_double(pa_[u]);
-      if (!diag_tile) Bs[r * GM_PITCH + c] = bulk_to_double(pb_[u]);
+    };
+    lds_barrier();  // the previous split's last chunk is consumed
+    if (t_begin < t_end) {
+      fetch(t_begin);
+      stage(0);
     }
-    __syncthreads();
-    if (t0 + GM_KC < t_end) fetch(t0 + GM_KC);
-    double av[2][8], bv[2][8];
+    lds_barrier();
+    int buf = 0;
+    for (int t0 = t_begin; t0 < t_end; t0 += GM_KC) {
+      const bool more = t0 + GM_KC < t_end;
+      if (more) fetch(t0 + GM_KC);
+      const TB* As = Ls + buf * 2 * BUF;
+      const TB* Bsrc = diag_tile ? As : As + BUF;
+      // steps 0..3, then 4..7 (operands of one half at a time)
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const double* pa = As + (qa * 32 + i * 16 + lr) * GM_PITCH + lk * 8;
-      const double* pb = Bsrc + (qb * 32 + i * 16 + lr) * GM_PITCH + lk * 8;
+      for (int hf = 0; hf < 2; ++hf) {
+        double av[2][4], bv[2][4];
 #pragma unroll
-      for (int u = 0; u < 8; u += 2) {
-        const double2 ta = *reinterpret_cast<const double2*>(pa + u);
-        const double2 tb = *reinterpret_cast<const double2*>(pb + u);
-        av[i][u] = ta.x;
-        av[i][u + 1] = ta.y;
-        bv[i][u] = tb.x;
-        bv[i][u + 1] = tb.y;
+        for (int i = 0; i < 2; ++i) {
+          GmLds<TB>::read4(As + (qa * 32 + i * 16 + lr) * PITCH + lk * 8 + 4 * hf, av[i]);
+          GmLds<TB>::read4(Bsrc + (qb * 32 + i * 16 + lr) * PITCH + lk * 8 + 4 * hf, bv[i]);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][u], bv[j][u], acc[i][j], 0, 0, 0);
       }
+      if (more) stage(buf ^ 1);
+      lds_barrier();  // the other buffer is stored; this one is consumed
+      buf ^= 1;
     }
+    TTG_GLOBAL double* out = gmem(g.out) + (long long)s * g.gcap * g.gcap;
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][u], bv[j][u], acc[i][j], 0, 0, 0);
+        for (int v = 0; v < 4; ++v) {
+          const int a = a0 + qa * 32 + i * 16 + lk + 4 * v;
+          const int c = b0 + qb * 32 + j * 16 + lr;
+          if (a < g.M && c < g.M) out[(long long)a * g.gcap + c] = acc[i][j][v];
+        }
   }
-  double* out = g.out + (long long)s * g.gcap * g.gcap;
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int a = a0 + qa * 32 + i * 16 + lk + 4 * v;
-        const int c = b0 + qb * 32 + j * 16 + lr;
-        if (a < g.M && c < g.M) out[(long long)a * g.gcap + c] = acc[i][j][v];
-      }
 }
 
 template <typename Acc, typename F>
@@ -849,6 +879,7 @@ __global__ void __launch_bounds__(256) tri_inverse_kernel(F f) {
 
 #define TA_ROWS 32
 #define TA_TMAX 128  // rows of W staged in LDS at a time
+#define TA_ZB 8      // rows of Z loaded ahead per batch
 template <typename TZ, typename TQ, typename F>
 __global__ void __launch_bounds__(256) tri_apply_kernel(F f) {
   const int b = blockIdx.z;
@@ -856,21 +887,24 @@ __global__ void __launch_bounds__(256) tri_apply_kernel(F f) {
   if (!f(b, a)) return;
   if (blockIdx.x * 256 >= a.m) return;
   __shared__ double ws[TA_TMAX * TA_ROWS];  // W(j0 + u, t0 + t) at ws[t * 32 + u], zero past row r
-  const TZ* z = reinterpret_cast<const TZ*>(a.z);
-  TQ* q = reinterpret_cast<TQ*>(a.q);
-  const double* wt = a.wbuf;
+  __shared__ int pvs[TA_TMAX];              // piv[t0 + t]
+  const TTG_GLOBAL TZ* z = gmem(reinterpret_cast<const TZ*>(a.z));
+  TTG_GLOBAL TQ* q = gmem(reinterpret_cast<TQ*>(a.q));
+  const TTG_GLOBAL double* wt = gmem(static_cast<const double*>(a.wbuf));
+  const TTG_GLOBAL int* piv = gmem(static_cast<const int*>(a.piv));
   const int r = a.r;
   for (int j0 = 0; j0 < r; j0 += TA_ROWS) {
     const int tend = min(r, j0 + TA_ROWS);  // W(j, t) = 0 for t > j
     const int jn = min(TA_ROWS, r - j0);
-    // stage W(j0.., t0..t1) (workgroup-uniform calls)
+    // stage W(j0.., t0..t1) and the pivots of t0..t1 (workgroup-uniform calls)
     auto stage = [&](int t0, int t1) {
-      __syncthreads();  // previous chunk consumed
+      lds_barrier();  // previous chunk consumed
       for (int e = threadIdx.x; e < (t1 - t0) * TA_ROWS; e += blockDim.x) {
         const int t = e / TA_ROWS, u = e - t * TA_ROWS;
         ws[e] = u < jn ? wt[(long long)(t0 + t) * a.gcap + j0 + u] : 0.0;
       }
-      __syncthreads();
+      for (int t = threadIdx.x; t < t1 - t0; t += blockDim.x) pvs[t] = piv[t0 + t];
+      lds_barrier();
     };
     const bool once = tend <= TA_TMAX;  // every t of this chunk fits at once
     if (once) stage(0, tend);
@@ -890,12 +924,22 @@ __global__ void __launch_bounds__(256) tri_apply_kernel(F f) {
       for (int t0 = 0; t0 < tend; t0 += TA_TMAX) {
         const int t1 = min(tend, t0 + TA_TMAX);
         if (!once) stage(t0, t1);
-#pragma unroll 2
-        for (int t = t0; t < t1; ++t) {
-          const double zv = bulk_to_double(z[(long long)a.piv[t] * a.ldz + zc]);
-          const double* wrow = ws + (t - t0) * TA_ROWS;
+        // TA_ZB rows of Z in flight at once; t ascends, as in the plain loop
+        for (int tb = t0; tb < t1; tb += TA_ZB) {
+          double zv[TA_ZB];
 #pragma unroll
-          for (int u = 0; u < TA_ROWS; ++u) acc[u] = __fma_rn(wrow[u], zv, acc[u]);
+          for (int x = 0; x < TA_ZB; ++x) {
+            const int t = min(tb + x, t1 - 1);
+            zv[x] = bulk_to_double(z[(long long)pvs[t - t0] * a.ldz + zc]);
+          }
+#pragma unroll
+          for (int x = 0; x < TA_ZB; ++x) {
+            if (tb + x < t1) {
+              const double* wrow = ws + (tb + x - t0) * TA_ROWS;
+#pragma unroll
+              for (int u = 0; u < TA_ROWS; ++u) acc[u] = __fma_rn(wrow[u], zv[x], acc[u]);
+            }
+          }
         }
       }
       if (live) {
@@ -1010,9 +1054,9 @@ __global__ void __launch_bounds__(256) gemm_mfma_kernel(F f) {
   if (!f(bz, g)) return;
   __shared__ float As[TM * GF_PITCH];
   __shared__ float Bs[TN * GF_PITCH];
-  const TA* A = reinterpret_cast<const TA*>(g.a);
-  const TB* Bm = reinterpret_cast<const TB*>(g.b);
-  float* C = reinterpret_cast<float*>(g.c);
+  const TTG_GLOBAL TA* A = gmem(reinterpret_cast<const TA*>(g.a));
+  const TTG_GLOBAL TB* Bm = gmem(reinterpret_cast<const TB*>(g.b));
+  TTG_GLOBAL float* C = gmem(reinterpret_cast<float*>(g.c));
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int qa = wv / QN, qb = wv - (wv / QN) * QN;
@@ -1062,7 +1106,7 @@ __global__ void __launch_bounds__(256) gemm_mfma_kernel(F f) {
     };
     fetch(0);
     for (int k0 = 0; k0 < g.K; k0 += GF_KC) {
-      __syncthreads();  // previous chunk consumed
+      lds_barrier();  // previous chunk consumed
 #pragma unroll
       for (int u = 0; u < PA; ++u) {
         const int e = tid + u * 256;
@@ -1089,7 +1133,7 @@ __global__ void __launch_bounds__(256) gemm_mfma_kernel(F f) {
         }
         Bs[n * GF_PITCH + kk] = rb[u];
       }
-      __syncthreads();
+      lds_barrier();
       if (k0 + GF_KC < g.K) fetch(k0 + GF_KC);
       constexpr int KS = GF_KC / 4;  // MFMA steps per chunk; lane lk takes k = KS lk + s
       float av[2][KS], bv[2][KS];

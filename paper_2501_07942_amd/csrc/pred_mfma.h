@@ -33,6 +33,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "common.h"
+
 typedef float mf4 __attribute__((ext_vector_type(4)));
 typedef double md4p __attribute__((ext_vector_type(4)));
 
@@ -108,28 +110,19 @@ __device__ inline int mp_vswz(int jl, int q) {
   return jl * QP + u * S + (q % S);
 }
 
-// One pair of 16-row tiles times NJ 16-column tiles over all taps.
+// Operands of one tap for one pair of 16-row tiles and NJ 16-column tiles.
 template <typename E, int S, int NJ>
-__device__ inline void mp_tiles(const E* pa, const E* vb, int taps, int pp, int vstride,
-                                typename MpT<E>::acc* acc) {
-  constexpr int QP = 4 * S;
-  const int o1 = 16 * pp;  // second i-tile
+struct MpTap {
   MpVec<E, S> a0, a1, b0, b1;
-  a0.load(pa);
-  a1.load(pa + o1);
-  b0.load(vb);
-  if constexpr (NJ == 2) b1.load(vb + vstride);
-  for (int m = 0; m < taps; ++m) {
-    MpVec<E, S> na0, na1, nb0, nb1;
-    const bool more = m + 1 < taps;
-    if (more) {
-      const E* pan = pa - (m + 1) * pp;
-      const E* vbn = vb + (m + 1) * 16 * QP;
-      na0.load(pan);
-      na1.load(pan + o1);
-      nb0.load(vbn);
-      if constexpr (NJ == 2) nb1.load(vbn + vstride);
-    }
+  __device__ inline void load(const E* pa, const E* vb, int m, int pp, int vstride) {
+    const E* p = pa - m * pp;
+    const E* v = vb + m * 16 * (4 * S);
+    a0.load(p);
+    a1.load(p + 16 * pp);  // second i-tile
+    b0.load(v);
+    if constexpr (NJ == 2) b1.load(v + vstride);
+  }
+  __device__ inline void mma(typename MpT<E>::acc* acc) const {
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       acc[0] = MpT<E>::mfma(a0.v[s], b0.v[s], acc[0]);
@@ -139,12 +132,31 @@ __device__ inline void mp_tiles(const E* pa, const E* vb, int taps, int pp, int 
         acc[3] = MpT<E>::mfma(a1.v[s], b1.v[s], acc[3]);
       }
     }
-    if (!more) break;
-    a0 = na0;
-    a1 = na1;
-    b0 = nb0;
-    if constexpr (NJ == 2) b1 = nb1;
   }
+};
+
+// One pair of 16-row tiles times NJ 16-column tiles over all taps.  Two
+// operand sets alternate (taps m and m + 1): the LDS reads of one tap are
+// issued before the MFMAs of the other, and scheduling barriers keep the
+// compiler from sinking them below those MFMAs, so each wait covers only
+// reads that have had a whole tap of matrix work to land.
+template <typename E, int S, int NJ>
+__device__ inline void mp_tiles(const E* pa, const E* vb, int taps, int pp, int vstride,
+                                typename MpT<E>::acc* acc) {
+  MpTap<E, S, NJ> x, y;
+  x.load(pa, vb, 0, pp, vstride);
+  int m = 0;
+  for (; m + 1 < taps; m += 2) {
+    y.load(pa, vb, m + 1, pp, vstride);
+    __builtin_amdgcn_sched_barrier(0);
+    x.mma(acc);
+    __builtin_amdgcn_sched_barrier(0);
+    x.load(pa, vb, min(m + 2, taps - 1), pp, vstride);  // a valid tap; unused past the end
+    __builtin_amdgcn_sched_barrier(0);
+    y.mma(acc);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  if (m < taps) x.mma(acc);
 }
 
 template <typename E, int S, typename F>
@@ -165,7 +177,9 @@ __device__ inline void mp_body(const typename F::Args& g, int al, int bb, int BB
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lr = lane & 15, lk = lane >> 4;
-  const E* kc = g.kcore + (long long)al * taps * rk1;
+  const TTG_GLOBAL E* gp = gmem(g.p);
+  TTG_GLOBAL E* gz = gmem(g.z);
+  const TTG_GLOBAL E* kc = gmem(g.kcore) + (long long)al * taps * rk1;
   for (int e = tid; e < taps * 32; e += blockDim.x) {
     const int m = e >> 5, a2 = e & 31;
     Ks[e] = a2 < rk1 ? kc[m * rk1 + a2] : (E)0;
@@ -176,7 +190,7 @@ __device__ inline void mp_body(const typename F::Args& g, int al, int bb, int BB
   const bool vec = rp1 == QP;      // P rows are whole 16-byte units
   for (int jc0 = 0; jc0 < N; jc0 += JC) {
     const int njt = (N - jc0 > MP_JT && JC > MP_JT) ? 2 : 1;
-    __syncthreads();  // Ks ready; the previous pass's V and P are consumed
+    lds_barrier();  // Ks ready; the previous pass's V and P are consumed
     // V for this pass: a thread owns one (b', j) fibre.  Its 32 values of L
     // are loaded from clamped (always valid) addresses; rows past rk1 meet
     // the zero padding of Ks, and fibres outside the bond or the columns
@@ -185,7 +199,7 @@ __device__ inline void mp_body(const typename F::Args& g, int al, int bb, int BB
       const int q = e / JC, jj = e - q * JC;
       const int j = jc0 + jj;
       const bool live = q < rp1 && j < N;
-      const double* lc = g.lfac + (long long)min(q, rp1 - 1) * g.gcap + min(j, N - 1);
+      const TTG_GLOBAL double* lc = gmem(g.lfac) + (long long)min(q, rp1 - 1) * g.gcap + min(j, N - 1);
       E lv[32];
 #pragma unroll
       for (int a2 = 0; a2 < 32; ++a2) lv[a2] = (E)lc[(long long)min(a2, rk1 - 1) * rp1 * g.gcap];
@@ -202,9 +216,9 @@ __device__ inline void mp_body(const typename F::Args& g, int al, int bb, int BB
     for (int e = tid; e < plen * QP; e += blockDim.x) {
       const int pr = e / QP, q = e - pr * QP;
       const int row = pr - h;
-      Ps[pr * pp + q] = (q < rp1 && row >= 0 && row < n) ? g.p[((long long)bfirst * n + row) * rp1 + q] : (E)0;
+      Ps[pr * pp + q] = (q < rp1 && row >= 0 && row < n) ? gp[((long long)bfirst * n + row) * rp1 + q] : (E)0;
     }
-    __syncthreads();
+    lds_barrier();
     for (int bo = 0; bo < nfib; ++bo) {
       const int be = bfirst + bo;
       E* Pc = Ps + (bo & 1) * plen * pp;
@@ -213,7 +227,7 @@ __device__ inline void mp_body(const typename F::Args& g, int al, int bb, int BB
       // the next fibre goes to registers while this one is multiplied
       float4 pf[MP_PF];
       if (next) {
-        const E* pc = g.p + (long long)(be + 1) * n * rp1;
+        const TTG_GLOBAL E* pc = gp + (long long)(be + 1) * n * rp1;
 #pragma unroll
         for (int u = 0; u < MP_PF; ++u) {
           const int eu = tid + u * 256;
@@ -222,10 +236,10 @@ __device__ inline void mp_body(const typename F::Args& g, int al, int bb, int BB
           float4 t = {0.f, 0.f, 0.f, 0.f};
           if (eu < pelu && row >= 0 && row < n) {
             if (vec) {
-              t = *reinterpret_cast<const float4*>(pc + (long long)row * QP + U * cu);
+              t = *reinterpret_cast<const TTG_GLOBAL float4*>(pc + (long long)row * QP + U * cu);
             } else {
               E tmp[U];
-              const E* src = pc + (long long)row * rp1;
+              const TTG_GLOBAL E* src = pc + (long long)row * rp1;
 #pragma unroll
               for (int x = 0; x < U; ++x) tmp[x] = (U * cu + x < rp1) ? src[U * cu + x] : (E)0;
               __builtin_memcpy(&t, tmp, 16);
@@ -253,12 +267,12 @@ __device__ inline void mp_body(const typename F::Args& g, int al, int bb, int BB
           const int i0 = it0 * 16 + MpT<E>::drow(lk, v), i1 = i0 + 16;
           const int j0 = jc0 + lr, j1 = j0 + MP_JT;
           if (i0 < n) {
-            if (j0 < N) g.z[zrow + (long long)i0 * N + j0] = acc[0][v];
-            if (njt == 2 && j1 < N) g.z[zrow + (long long)i0 * N + j1] = acc[2][v];
+            if (j0 < N) gz[zrow + (long long)i0 * N + j0] = acc[0][v];
+            if (njt == 2 && j1 < N) gz[zrow + (long long)i0 * N + j1] = acc[2][v];
           }
           if (i1 < n) {
-            if (j0 < N) g.z[zrow + (long long)i1 * N + j0] = acc[1][v];
-            if (njt == 2 && j1 < N) g.z[zrow + (long long)i1 * N + j1] = acc[3][v];
+            if (j0 < N) gz[zrow + (long long)i1 * N + j0] = acc[1][v];
+            if (njt == 2 && j1 < N) gz[zrow + (long long)i1 * N + j1] = acc[3][v];
           }
         }
       }
@@ -272,13 +286,13 @@ __device__ inline void mp_body(const typename F::Args& g, int al, int bb, int BB
           }
         }
       }
-      __syncthreads();  // next fibre stored; current one consumed
+      lds_barrier();  // next fibre stored; current one consumed
     }
   }
 }
 
 template <typename E, typename F>
-__global__ void __launch_bounds__(256) mfma_pred_kernel(F fn, int BB) {
+__global__ void __launch_bounds__(256, sizeof(E) == 4 ? 2 : 1) mfma_pred_kernel(F fn, int BB) {
   typename F::Args g;
   if (!fn(blockIdx.z, g)) return;
   const int nbb = (g.rp0 + BB - 1) / BB;
