@@ -24,7 +24,7 @@ struct GramArgs {
 
 // split count used for a summation of length T with `planes` planes
 __device__ inline int gram_split_count(int T, int planes) {
-  const int s = (T + 255) / 256;
+  const int s = (T + 511) / 512;
   return max(1, min(s, planes));
 }
 
