@@ -84,9 +84,9 @@ __global__ void __launch_bounds__(64 * EZ_WAVES) einsum_z_kernel(const DevTT* __
   const int a0 = blockIdx.x * EZ_ROWS, c0 = blockIdx.y * EZ_CB;
   if (a0 >= R0 || c0 >= rp0) return;  // uniform over the workgroup
   const int len = n * R1;
-  const E* tc = core_ptr<E>(T, d + k);
-  const double* y = yin[f];
-  double* z = zout[f];
+  const TTG_GLOBAL E* tc = gmem(core_ptr<E>(T, d + k));
+  const TTG_GLOBAL double* y = gmem(static_cast<const double*>(yin[f]));
+  TTG_GLOBAL double* z = gmem(zout[f]);
   __shared__ double Ys[EZ_CB][EZ_TC];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   double acc[4][EZ_CB];
@@ -94,13 +94,11 @@ __global__ void __launch_bounds__(64 * EZ_WAVES) einsum_z_kernel(const DevTT* __
   for (int q = 0; q < 4; ++q)
 #pragma unroll
     for (int c = 0; c < EZ_CB; ++c) acc[q][c] = 0.0;
-  for (int t0 = 0; t0 < len; t0 += EZ_TC) {
-    for (int e = threadIdx.x; e < EZ_CB * EZ_TC; e += blockDim.x) {
-      const int c = e / EZ_TC, j = e - (e / EZ_TC) * EZ_TC;
-      const int cc = c0 + c, t = t0 + j;
-      Ys[c][j] = (cc < rp0 && t < len) ? y[(long long)cc * len + t] : 0.0;
-    }
-    double tv[4][4];
+  // the next chunk's T values and Y entries are loaded into registers while
+  // the current chunk is multiplied (the LDS-only barriers leave them in flight)
+  constexpr int YPT = EZ_CB * EZ_TC / (64 * EZ_WAVES);  // Y entries staged per thread
+  double tv[4][4], yv[YPT];
+  auto load = [&](int t0) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int a = a0 + 4 * w + q;
@@ -110,16 +108,37 @@ __global__ void __launch_bounds__(64 * EZ_WAVES) einsum_z_kernel(const DevTT* __
         tv[q][u] = (a < R0 && t < len) ? (double)tc[(long long)a * len + t] : 0.0;
       }
     }
-    __syncthreads();
+#pragma unroll
+    for (int x = 0; x < YPT; ++x) {
+      const int e = threadIdx.x + x * 64 * EZ_WAVES;
+      const int c = e / EZ_TC, j = e - (e / EZ_TC) * EZ_TC;
+      const int cc = c0 + c, t = t0 + j;
+      yv[x] = (cc < rp0 && t < len) ? y[(long long)cc * len + t] : 0.0;
+    }
+  };
+  load(0);
+  for (int t0 = 0; t0 < len; t0 += EZ_TC) {
+#pragma unroll
+    for (int x = 0; x < YPT; ++x) {
+      const int e = threadIdx.x + x * 64 * EZ_WAVES;
+      Ys[e / EZ_TC][e - (e / EZ_TC) * EZ_TC] = yv[x];
+    }
+    double tcur[4][4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) tcur[q][u] = tv[q][u];
+    lds_barrier();
+    if (t0 + EZ_TC < len) load(t0 + EZ_TC);
 #pragma unroll
     for (int c = 0; c < EZ_CB; ++c)
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const double yv = Ys[c][lane + 64 * u];
+        const double yvv = Ys[c][lane + 64 * u];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[q][c] += tv[q][u] * yv;
+        for (int q = 0; q < 4; ++q) acc[q][c] += tcur[q][u] * yvv;
       }
-    __syncthreads();
+    lds_barrier();
   }
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
