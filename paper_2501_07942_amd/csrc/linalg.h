@@ -111,9 +111,9 @@ __global__ void __launch_bounds__(256) gram_partial_kernel(F f) {
 // (v_mfma_f64_16x16x4f64): one 64 x 64 upper-triangular tile pair per
 // workgroup, each wavefront a 32 x 32 quadrant (2 x 2 MFMA tiles).  Chunks
 // of 32 summation indices of both row blocks are staged in LDS in the input
-// type, double-buffered (one barrier per chunk: the next chunk is fetched
-// into registers and stored to the other buffer while this one is
-// multiplied) and widened to FP64 as they are read; within a chunk the
+// type, double-buffered (one barrier per chunk: while a chunk is multiplied
+// the chunk two ahead is fetched into registers and the next one is stored
+// to the other buffer) and widened to FP64 as they are read; within a chunk the
 // k-lane lk of an MFMA step s takes index lk * 8 + s, so a lane reads its
 // eight operands as one contiguous run.  Products of FP32 inputs are exact
 // in FP64.  A workgroup takes the splits blockIdx.y, blockIdx.y + gridDim.y,
@@ -187,14 +187,16 @@ __global__ void __launch_bounds__(256, 2) gram_mfma_kernel(F f) {
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j) acc[i][j] = md4{0.0, 0.0, 0.0, 0.0};
-    // each thread stages GM_PER elements of both row blocks per chunk
-    TB pa_[GM_PER], pb_[GM_PER];
+    // each thread stages GM_PER elements of both row blocks per chunk; two
+    // register sets take chunks c and c + 1, so a chunk's loads are in
+    // flight for two chunks of MFMAs before they are stored to LDS
+    TB pa0[GM_PER], pb0[GM_PER], pa1[GM_PER], pb1[GM_PER];
     // element u sits at a wave-uniform base plus this lane's 32-bit offset
     // (loff), so the loads need no 64-bit address per element
     const unsigned loff = t_fast ? (unsigned)((tid >> 5) * g.sa + (tid & 31))
                                  : (unsigned)((tid & 63) * g.sa + (tid >> 6) * g.st);
     const long long ustep = t_fast ? 8 * g.sa : 4 * g.st;
-    auto fetch = [&](int t0) {
+    auto fetch = [&](TB (&pa_)[GM_PER], TB (&pb_)[GM_PER], int t0) {
       const TTG_GLOBAL TB* xa = x + (long long)a0 * g.sa + (long long)t0 * g.st;
       const TTG_GLOBAL TB* xb = x + (long long)b0 * g.sa + (long long)t0 * g.st;
 #pragma unroll
@@ -205,7 +207,7 @@ __global__ void __launch_bounds__(256, 2) gram_mfma_kernel(F f) {
         pb_[u] = (!diag_tile && tv && b0 + q.x < g.M) ? (xb + u * ustep)[loff] : (TB)0;
       }
     };
-    auto stage = [&](int buf) {
+    auto stage = [&](const TB (&pa_)[GM_PER], const TB (&pb_)[GM_PER], int buf) {
       TB* As = Ls + buf * 2 * BUF;
 #pragma unroll
       for (int u = 0; u < GM_PER; ++u) {
@@ -214,19 +216,10 @@ __global__ void __launch_bounds__(256, 2) gram_mfma_kernel(F f) {
         if (!diag_tile) As[BUF + q.x * PITCH + q.y] = pb_[u];
       }
     };
-    lds_barrier();  // the previous split's last chunk is consumed
-    if (t_begin < t_end) {
-      fetch(t_begin);
-      stage(0);
-    }
-    lds_barrier();
-    int buf = 0;
-    for (int t0 = t_begin; t0 < t_end; t0 += GM_KC) {
-      const bool more = t0 + GM_KC < t_end;
-      if (more) fetch(t0 + GM_KC);
+    // steps 0..3, then 4..7 of the chunk in LDS buffer buf
+    auto multiply = [&](int buf) {
       const TB* As = Ls + buf * 2 * BUF;
       const TB* Bsrc = diag_tile ? As : As + BUF;
-      // steps 0..3, then 4..7 (operands of one half at a time)
 #pragma unroll
       for (int hf = 0; hf < 2; ++hf) {
         double av[2][4], bv[2][4];
@@ -243,9 +236,26 @@ __global__ void __launch_bounds__(256, 2) gram_mfma_kernel(F f) {
             for (int j = 0; j < 2; ++j)
               acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][u], bv[j][u], acc[i][j], 0, 0, 0);
       }
-      if (more) stage(buf ^ 1);
-      lds_barrier();  // the other buffer is stored; this one is consumed
-      buf ^= 1;
+    };
+    const int nch = t_begin < t_end ? (t_end - t_begin + GM_KC - 1) / GM_KC : 0;
+    lds_barrier();  // the previous split's last chunk is consumed
+    if (nch > 0) {
+      fetch(pa0, pb0, t_begin);
+      if (nch > 1) fetch(pa1, pb1, t_begin + GM_KC);
+      stage(pa0, pb0, 0);
+    }
+    lds_barrier();
+    // chunk c sits in LDS buffer c % 2; register set c % 2 takes chunk c + 2
+    for (int c = 0; c < nch; c += 2) {
+      if (c + 2 < nch) fetch(pa0, pb0, t_begin + (c + 2) * GM_KC);
+      multiply(0);
+      if (c + 1 < nch) stage(pa1, pb1, 1);
+      lds_barrier();  // buffer 1 is stored; buffer 0 is consumed
+      if (c + 1 >= nch) break;
+      if (c + 3 < nch) fetch(pa1, pb1, t_begin + (c + 3) * GM_KC);
+      multiply(1);
+      if (c + 2 < nch) stage(pa0, pb0, 0);
+      lds_barrier();  // buffer 0 is stored; buffer 1 is consumed
     }
     TTG_GLOBAL double* out = gmem(g.out) + (long long)s * g.gcap * g.gcap;
 #pragma unroll
