@@ -723,7 +723,7 @@ struct FLrJacobi {
     J.sigma = s.sigma;
     J.usv = s.usv;
     J.ncols_out = nullptr;
-    J.tol2 = c.esz == 4 ? 1e-24 : 1e-30;  // FP32 bulk: 1e-12 relative orthogonality
+    J.tol2 = c.esz == 4 ? 1e-16 : 1e-30;  // FP32 bulk: 1e-8 relative orthogonality
     J.gcap = s.gcap;
     return true;
   }
