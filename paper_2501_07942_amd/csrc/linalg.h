@@ -415,12 +415,17 @@ __global__ void __launch_bounds__(256) pchol_kernel(F f, int ncl) {
         l = Acc::zero();
       } else {
         V s = Acc::load(p.g, (long long)i * p.gcap + pv);
+        // unrolled so that several terms' loads are in flight (the sum still
+        // runs over t in order)
         if constexpr (lds_cols) {
           const int tl = min(j, ncl);
+#pragma unroll 4
           for (int t = 0; t < tl; ++t) s = Acc::sub(s, Acc::mul(lc[(long long)t * p.M + i], lp[t]));
+#pragma unroll 4
           for (int t = tl; t < j; ++t)
             s = Acc::sub(s, Acc::mul(Acc::load(p.lwork, (long long)t * p.gcap + i), lp[t]));
         } else {
+#pragma unroll 4
           for (int t = 0; t < j; ++t)
             s = Acc::sub(s, Acc::mul(Acc::load(p.lwork, (long long)t * p.gcap + i), lp[t]));
         }
