@@ -461,8 +461,8 @@ __global__ void __launch_bounds__(256) pchol_kernel(F f, int ncl) {
     if (bad && p.status) atomicOr(p.status, TT_STATUS_NONFINITE);
   }
   // FP64 row-major copy, zero beyond the rank
-  for (long long e = tid; e < (long long)p.M * rank; e += nt) {
-    const int i = (int)(e / rank), t = (int)(e % rank);
+  for (int e = tid; e < p.M * rank; e += nt) {  // 32-bit index arithmetic
+    const int i = e / rank, t = e - (e / rank) * rank;
     p.lfac[(long long)i * p.gcap + t] = Acc::hi(Acc::load(p.lwork, (long long)t * p.gcap + i));
   }
 }
@@ -636,8 +636,8 @@ __device__ __forceinline__ void jacobi_body(double* W, long long ldw, const Jaco
                                             int& s_rot) {
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, nw = blockDim.x >> 6;
   const int rows = J.rows, nc = J.ncols;
-  for (long long e = tid; e < (long long)rows * nc; e += blockDim.x) {
-    const int i = (int)(e / nc), c = (int)(e % nc);
+  for (int e = tid; e < rows * nc; e += blockDim.x) {  // 32-bit index arithmetic
+    const int i = e / nc, c = e - (e / nc) * nc;
     W[(long long)c * ldw + i] = J.x[(long long)i * J.ldx + c];
   }
   __syncthreads();
