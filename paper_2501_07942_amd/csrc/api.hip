@@ -1051,8 +1051,8 @@ __global__ void __launch_bounds__(256) pred_work_kernel(FFused<T> fn, int B, dou
 // vector-ALU kernel or the MFMA kernel's LDS would not fit.  The choice
 // depends on the launch's capacities only, never on the batch size.
 template <typename T>
-static bool use_mfma_pred(int hmax, int nmax, int pcap, int kcap) {
-  return g_predict_mode != 3 && mfma_pred_fits<T>(hmax, nmax, pcap, kcap);
+static int use_mfma_pred(int hmax, int nmax, int pcap, int kcap) {
+  return g_predict_mode != 3 ? mfma_pred_variant<T>(hmax, nmax, pcap, kcap) : 0;
 }
 
 template <typename T>
@@ -1060,16 +1060,22 @@ static tt_status launch_direct(const RCtx& c, int B, int hmax, int kcap, int nma
                                hipStream_t st) {
   ProfScope ps_(PC_PRED, st);
   FFused<T> f{c};
-  if (use_mfma_pred<T>(hmax, nmax, pcap, kcap)) {
-    const size_t ms = mfma_pred_smem<T>(hmax, nmax, pcap, kcap);
+  if (const int var = use_mfma_pred<T>(hmax, nmax, pcap, kcap)) {
+    const bool big = var == 2;
+    const size_t ms = mfma_pred_smem<T>(hmax, nmax, pcap, kcap, big);
+    const void* kfn = big ? (const void*)mfma_pred_kernel<T, FFused<T>, true>
+                          : (const void*)mfma_pred_kernel<T, FFused<T>, false>;
     if (ms > 48 * 1024)
-      HIP_TRY(hipFuncSetAttribute((const void*)mfma_pred_kernel<T, FFused<T>>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)ms),
+      HIP_TRY(hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)ms),
               "mfma prediction smem");
     const int BB = pred_bb(TuneKey{sizeof(T) == 8 ? 1 : 0, B, hmax, nmax, pcap, kcap}, B);
     const int grid = kcap * ((pcap + BB - 1) / BB);
-    hipLaunchKernelGGL((mfma_pred_kernel<T, FFused<T>>), dim3(std::max(1, grid), 1, B), dim3(256), ms, st, f,
-                       BB);
+    if (big)
+      hipLaunchKernelGGL((mfma_pred_kernel<T, FFused<T>, true>), dim3(std::max(1, grid), 1, B), dim3(MP_NT_BIG), ms,
+                         st, f, BB);
+    else
+      hipLaunchKernelGGL((mfma_pred_kernel<T, FFused<T>, false>), dim3(std::max(1, grid), 1, B), dim3(256), ms, st,
+                         f, BB);
     TTG_LAUNCH_CHECK("mfma_pred_kernel");
     if (g_work && (g_prof_mask & (1 << PC_PRED))) {
       hipLaunchKernelGGL((pred_work_kernel<T>), dim3(1), dim3(256), 0, st, f, B, g_work);
@@ -4809,10 +4815,12 @@ static tt_status run_plan(int32_t batch, const tt_filter_spec* specs, const tt_t
                               ? (f64 ? fused_smem<double>(p.Lmax, p.kcap, nmax, p.pcap)
                                      : fused_smem<float>(p.Lmax, p.kcap, nmax, p.pcap))
                               : (f64 ? (use_mfma_pred<double>(hmax, nmax, p.pcap, p.kcap)
-                                            ? mfma_pred_smem<double>(hmax, nmax, p.pcap, p.kcap)
+                                            ? mfma_pred_smem<double>(hmax, nmax, p.pcap, p.kcap,
+                                                                     use_mfma_pred<double>(hmax, nmax, p.pcap, p.kcap) == 2)
                                             : direct_smem<double>(hmax, nmax, p.pcap, p.kcap))
                                      : (use_mfma_pred<float>(hmax, nmax, p.pcap, p.kcap)
-                                            ? mfma_pred_smem<float>(hmax, nmax, p.pcap, p.kcap)
+                                            ? mfma_pred_smem<float>(hmax, nmax, p.pcap, p.kcap,
+                                                                    use_mfma_pred<float>(hmax, nmax, p.pcap, p.kcap) == 2)
                                             : direct_smem<float>(hmax, nmax, p.pcap, p.kcap)));
       // a fused prediction that does not fit the LDS of a CU gives way to
       // the materialised convolution and the plain rounding (mode 2)

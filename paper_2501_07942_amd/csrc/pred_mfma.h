@@ -40,6 +40,8 @@ typedef double md4p __attribute__((ext_vector_type(4)));
 
 #define MP_JT 16  // columns of one MFMA tile
 #define MP_PF 6   // 16-byte prefetch registers per thread (fibres of up to 24 KB)
+#define MP_PF_BIG 5   // the same for the single-buffer variant, 512 threads (fibres of up to 40 KB)
+#define MP_NT_BIG 512 // threads of the single-buffer variant's workgroup
 
 template <typename E>
 struct MpT;
@@ -159,11 +161,18 @@ __device__ inline void mp_tiles(const E* pa, const E* vb, int taps, int pp, int 
   if (m < taps) x.mma(acc);
 }
 
-template <typename E, int S, typename F>
+// Big: the variant for long fibres and many taps (one 16-column tile per
+// pass and one fibre buffer, the next fibre held in registers across two
+// barriers), at one workgroup of eight wavefronts per CU (two per SIMD).
+template <typename E, int S, bool Big, typename F>
 __device__ inline void mp_body(const typename F::Args& g, int al, int bb, int BB, E* smem) {
   using Acc = typename MpT<E>::acc;
   constexpr int QP = 4 * S;
-  constexpr int JC = MpT<E>::JC;
+  constexpr int JC = Big ? MP_JT : MpT<E>::JC;
+  constexpr int NB = Big ? 1 : 2;  // fibre buffers
+  constexpr int PF = Big ? MP_PF_BIG : MP_PF;
+  constexpr int NT = Big ? MP_NT_BIG : 256;  // threads of the workgroup
+  constexpr int NW = NT / 64;                // its wavefronts
   constexpr int U = 16 / (int)sizeof(E);  // elements per 16-byte unit
   const int N = g.N, rp0 = g.rp0, rp1 = g.rp1, rk1 = g.rk1, n = g.n;
   const int h = g.hk, taps = 2 * g.hk + 1;
@@ -172,8 +181,8 @@ __device__ inline void mp_body(const typename F::Args& g, int al, int bb, int BB
   const int pp = QP + 4;           // fibre row pitch (keeps 16-byte alignment)
   const int vstride = taps * 16 * QP;
   E* Vs = smem;                    // [JC/16][taps][16][QP]: j-tile, tap, column, bond
-  E* Ps = Vs + (JC / 16) * vstride;  // [2][plen][pp]: double buffer
-  E* Ks = Ps + 2 * plen * pp;      // [taps][32] of row a, zero beyond rk1
+  E* Ps = Vs + (JC / 16) * vstride;  // [NB][plen][pp]: fibre buffers
+  E* Ks = Ps + NB * plen * pp;     // [taps][32] of row a, zero beyond rk1
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lr = lane & 15, lk = lane >> 4;
@@ -221,16 +230,16 @@ __device__ inline void mp_body(const typename F::Args& g, int al, int bb, int BB
     lds_barrier();
     for (int bo = 0; bo < nfib; ++bo) {
       const int be = bfirst + bo;
-      E* Pc = Ps + (bo & 1) * plen * pp;
-      E* Pn = Ps + ((bo + 1) & 1) * plen * pp;
+      E* Pc = Ps + (NB == 2 ? (bo & 1) : 0) * plen * pp;
+      E* Pn = Ps + (NB == 2 ? ((bo + 1) & 1) : 0) * plen * pp;
       const bool next = bo + 1 < nfib;
       // the next fibre goes to registers while this one is multiplied
-      float4 pf[MP_PF];
+      float4 pf[PF];
       if (next) {
         const TTG_GLOBAL E* pc = gp + (long long)(be + 1) * n * rp1;
 #pragma unroll
-        for (int u = 0; u < MP_PF; ++u) {
-          const int eu = tid + u * 256;
+        for (int u = 0; u < PF; ++u) {
+          const int eu = tid + u * NT;
           const int pr = eu / (QP / U), cu = eu - pr * (QP / U);
           const int row = pr - h;
           float4 t = {0.f, 0.f, 0.f, 0.f};
@@ -249,7 +258,7 @@ __device__ inline void mp_body(const typename F::Args& g, int al, int bb, int BB
         }
       }
       const long long zrow = (long long)(al * rp0 + be) * n * N;
-      for (int it0 = 2 * wv; it0 < nit; it0 += 8) {
+      for (int it0 = 2 * wv; it0 < nit; it0 += 2 * NW) {
         Acc acc[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[c] = Acc{0, 0, 0, 0};
@@ -276,10 +285,11 @@ __device__ inline void mp_body(const typename F::Args& g, int al, int bb, int BB
           }
         }
       }
+      if constexpr (Big) lds_barrier();  // the one fibre buffer is consumed
       if (next) {
 #pragma unroll
-        for (int u = 0; u < MP_PF; ++u) {
-          const int eu = tid + u * 256;
+        for (int u = 0; u < PF; ++u) {
+          const int eu = tid + u * NT;
           if (eu < pelu) {
             const int pr = eu / (QP / U), cu = eu - pr * (QP / U);
             *reinterpret_cast<float4*>(Pn + pr * pp + U * cu) = pf[u];
@@ -291,8 +301,8 @@ __device__ inline void mp_body(const typename F::Args& g, int al, int bb, int BB
   }
 }
 
-template <typename E, typename F>
-__global__ void __launch_bounds__(256, sizeof(E) == 4 ? 2 : 1) mfma_pred_kernel(F fn, int BB) {
+template <typename E, typename F, bool Big>
+__global__ void __launch_bounds__(Big ? MP_NT_BIG : 256, (sizeof(E) == 4 && !Big) ? 2 : 1) mfma_pred_kernel(F fn, int BB) {
   typename F::Args g;
   if (!fn(blockIdx.z, g)) return;
   const int nbb = (g.rp0 + BB - 1) / BB;
@@ -301,27 +311,37 @@ __global__ void __launch_bounds__(256, sizeof(E) == 4 ? 2 : 1) mfma_pred_kernel(
   extern __shared__ unsigned char msm_raw[];
   E* msm = reinterpret_cast<E*>(msm_raw);
   switch (mp_s(g.rp1)) {
-    case 1: mp_body<E, 1, F>(g, al, bb, BB, msm); break;
-    case 2: mp_body<E, 2, F>(g, al, bb, BB, msm); break;
-    case 4: mp_body<E, 4, F>(g, al, bb, BB, msm); break;
-    default: mp_body<E, 8, F>(g, al, bb, BB, msm); break;
+    case 1: mp_body<E, 1, Big, F>(g, al, bb, BB, msm); break;
+    case 2: mp_body<E, 2, Big, F>(g, al, bb, BB, msm); break;
+    case 4: mp_body<E, 4, Big, F>(g, al, bb, BB, msm); break;
+    default: mp_body<E, 8, Big, F>(g, al, bb, BB, msm); break;
   }
 }
 
-// LDS bytes of mfma_pred_kernel<E> for the largest shapes of a launch
+// LDS bytes of mfma_pred_kernel<E, F, big> for the largest shapes of a launch
 template <typename E>
-inline size_t mfma_pred_smem(int hmax, int nmax, int pcap, int kcap) {
+inline size_t mfma_pred_smem(int hmax, int nmax, int pcap, int kcap, bool big = false) {
   (void)kcap;
   const int taps = 2 * hmax + 1;
   const int qp = 4 * mp_s(pcap);
-  const int jc = sizeof(E) == 4 ? 32 : 16;
-  return ((size_t)(jc / 16) * taps * 16 * qp + (size_t)2 * mp_plen(nmax, hmax) * (qp + 4) + (size_t)taps * 32) *
+  const int jc = big ? 16 : (sizeof(E) == 4 ? 32 : 16);
+  const int nb = big ? 1 : 2;
+  return ((size_t)(jc / 16) * taps * 16 * qp + (size_t)nb * mp_plen(nmax, hmax) * (qp + 4) + (size_t)taps * 32) *
          sizeof(E);
 }
 
-// bond <= 32 (S <= 8); the next fibre fits the prefetch registers; LDS fits
+// Which variant of mfma_pred_kernel<E> a launch takes: 1 (two fibre
+// buffers, two workgroups per CU), 2 (the single-buffer variant for long
+// fibres or many taps) or 0 (neither fits: bond or kernel rank above 32,
+// the next fibre beyond the prefetch registers, or the LDS).
 template <typename E>
-inline bool mfma_pred_fits(int hmax, int nmax, int pcap, int kcap) {
+inline int mfma_pred_variant(int hmax, int nmax, int pcap, int kcap) {
+  if (pcap > 32 || kcap > 32) return 0;
   const long long bytes = (long long)mp_plen(nmax, hmax) * 4 * mp_s(pcap) * sizeof(E);
-  return pcap <= 32 && kcap <= 32 && bytes <= 256LL * MP_PF * 16 && mfma_pred_smem<E>(hmax, nmax, pcap, kcap) <= 160 * 1024;
+  if (bytes <= 256LL * MP_PF * 16 && mfma_pred_smem<E>(hmax, nmax, pcap, kcap) <= 160 * 1024) return 1;
+  // (FP32 only: the FP64 variant would not fit its registers)
+  if (sizeof(E) == 4 && bytes <= (long long)MP_NT_BIG * MP_PF_BIG * 16 &&
+      mfma_pred_smem<E>(hmax, nmax, pcap, kcap, true) <= 160 * 1024)
+    return 2;
+  return 0;
 }
