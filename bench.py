@@ -623,16 +623,29 @@ def main():
         out["grad"] = grad_bench(G, wl, args.grad_steps, args.grad_batch)
     if not args.no_large:
         # the large workload: d=10, N=256 on [-25,25]^10, cap 32, 64 filters,
-        # all 200 steps (10 untimed after the first update, 189 timed); the
-        # kernel TT by TT-cross, likelihood blocks up to rank 96
+        # all 200 steps (10 untimed after the first update, 187 timed, the
+        # last 2 profiled for the prediction's roofline); the kernel TT by
+        # TT-cross, likelihood blocks up to rank 96
         main_res.clear()
         torch.cuda.empty_cache()
         torch.cuda.reset_peak_memory_stats()
-        lg = run_batch(None, runner, binding, wl, "range10d_n256_c32", 64, 189, 10, binding.F32, lik_rank_cap=96)
+        lg = run_batch(None, runner, binding, wl, "range10d_n256_c32", 64, 187, 10, binding.F32, lik_rank_cap=96,
+                       profile_steps=2)
         st = lg["status"]
+        lroof = None
+        lprof = lg["prof"] or {}
+        if lprof and lprof["pred"][1] > 0 and lprof["pred"][2] > 0:
+            ms_p, n_p, fl_p, by_p = lprof["pred"]
+            achieved = fl_p / n_p / (ms_p / n_p / 1000.0) / 1e12
+            lroof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": FP32_MFMA_PEAK_TFS, "unit": "TFLOP/s",
+                     "frac": round(achieved / FP32_MFMA_PEAK_TFS, 4),
+                     "kernel": "mfma_pred_kernel<float, FFused<float>, true> (single-buffer variant)",
+                     "avg_launch_ms": round(ms_p / n_p, 4), "launches": n_p,
+                     "algorithmic_flops_per_launch": round(fl_p / n_p)}
         out["large_d10"] = {"workload": "range10d_n256_c32",
-                            "value": round(64 * 189 / (lg["ms"] / 1000.0), 2), "unit": "filter-steps/s",
-                            "ms_per_step": round(lg["ms"] / 189, 3), "filters": 64, "timed_steps": 189,
+                            "value": round(64 * 187 / (lg["ms"] / 1000.0), 2), "unit": "filter-steps/s",
+                            "ms_per_step": round(lg["ms"] / 187, 3), "filters": 64, "timed_steps": 187,
+                            "roofline": lroof,
                             "failed_filters": int((st != 0).sum()),
                             "max_rank_last_step": int(lg["run"].ranks[:, -1].max().item()),
                             "workspace_GB": round(lg["run"].ws.numel() * lg["run"].ws.element_size() / 1e9, 2),
