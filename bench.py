@@ -33,7 +33,7 @@ FP32_MFMA_PEAK_TFS = 157.3
 # rocprofv3 FETCH_SIZE (x2.0) and WRITE_SIZE (x1.0), the factors measured on a
 # plain 256 MiB device copy (profiles/mfma_pred_kernel_traffic_*.txt); reset to
 # None whenever the kernel changes
-TRAFFIC = 903309787
+TRAFFIC = 903468715
 
 
 def log(msg):
