@@ -112,8 +112,8 @@ __global__ void __launch_bounds__(256) pred_adj_p_reg_kernel(const DevTT* __rest
   const T* kc = core_ptr<T>(K, k);
   for (int e = threadIdx.x; e < rk0 * taps * rk1; e += blockDim.x) Ks[e] = kc[e];
   __syncthreads();
-  const T* cc = core_ptr<T>(C, k);
-  T* qc = core_ptr<T>(Q, k);
+  const TTG_GLOBAL T* cc = gmem(core_ptr<T>(C, k));
+  TTG_GLOBAL T* qc = gmem(core_ptr<T>(Q, k));
   for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < items;
        t += (long long)gridDim.x * blockDim.x) {
     const int e = (int)(t % rp1);
@@ -124,7 +124,7 @@ __global__ void __launch_bounds__(256) pred_adj_p_reg_kernel(const DevTT* __rest
     for (int r = 0; r < PADJ_JROWS; ++r) acc[r] = 0.0;
     for (int a = 0; a < rk0; ++a)
       for (int b = 0; b < rk1; ++b) {
-        const T* crow = cc + ((long long)(a * rp0 + c) * n) * R1 + (long long)b * rp1 + e;
+        const TTG_GLOBAL T* crow = cc + ((long long)(a * rp0 + c) * n) * R1 + (long long)b * rp1 + e;
         const T* kr = Ks + (long long)a * taps * rk1 + b;
         for (int m0 = 0; m0 < taps; m0 += TC) {
           // output j = j0 + r and tap tm = m0 + u (offset m = tm - h) read

@@ -102,6 +102,8 @@ __global__ void __launch_bounds__(256) gjob_mfma_kernel(const GJob* __restrict__
   __shared__ double Bs[KB][64 + 1];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
+  const TTG_GLOBAL double* ga = gmem(g.a);
+  const TTG_GLOBAL double* gb = gmem(g.b);
   gj_d4 acc[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) acc[j] = gj_d4{0.0, 0.0, 0.0, 0.0};
@@ -112,10 +114,10 @@ __global__ void __launch_bounds__(256) gjob_mfma_kernel(const GJob* __restrict__
       const int e = threadIdx.x + 256 * u;
       const int mm = e >> 5, kk = e & 31;  // A: 64 rows x 32 k
       const int m = m0 + mm, k = k0 + kk;
-      ra[u] = (m < g.M && k < kend) ? g.a[(long long)m * g.sam + (long long)k * g.sak] : 0.0;
+      ra[u] = (m < g.M && k < kend) ? ga[(long long)m * g.sam + (long long)k * g.sak] : 0.0;
       const int kb = e >> 6, nn = e & 63;  // B: 32 k x 64 columns
       const int n = n0 + nn, k2 = k0 + kb;
-      rb[u] = (n < g.N && k2 < kend) ? g.b[(long long)k2 * g.sbk + (long long)n * g.sbn] : 0.0;
+      rb[u] = (n < g.N && k2 < kend) ? gb[(long long)k2 * g.sbk + (long long)n * g.sbn] : 0.0;
     }
   };
   fetch(kbeg);
@@ -126,7 +128,7 @@ __global__ void __launch_bounds__(256) gjob_mfma_kernel(const GJob* __restrict__
       As[e & 31][e >> 5] = ra[u];
       Bs[e >> 6][e & 63] = rb[u];
     }
-    __syncthreads();
+    lds_barrier();
     if (k0 + KB < kend) fetch(k0 + KB);
 #pragma unroll
     for (int kk = 0; kk < KB; kk += 4) {
@@ -135,7 +137,7 @@ __global__ void __launch_bounds__(256) gjob_mfma_kernel(const GJob* __restrict__
       for (int j = 0; j < 4; ++j)
         acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Bs[kk + lk][16 * j + li], acc[j], 0, 0, 0);
     }
-    __syncthreads();
+    lds_barrier();
   }
 #pragma unroll
   for (int j = 0; j < 4; ++j)
@@ -144,9 +146,9 @@ __global__ void __launch_bounds__(256) gjob_mfma_kernel(const GJob* __restrict__
       const int m = m0 + 16 * w + 4 * v + lk, n = n0 + 16 * j + li;
       if (m < g.M && n < g.N) {
         if (g.ks > 1) {
-          g.part[((long long)sl * g.M + m) * g.N + n] = acc[j][v];
+          gmem(g.part)[((long long)sl * g.M + m) * g.N + n] = acc[j][v];
         } else {
-          double* cp = g.c + (long long)m * g.scm + (long long)n * g.scn;
+          TTG_GLOBAL double* cp = gmem(g.c) + (long long)m * g.scm + (long long)n * g.scn;
           *cp = g.beta == 0.0 ? g.alpha * acc[j][v] : __fma_rn(g.alpha, acc[j][v], g.beta * *cp);
         }
       }
