@@ -630,7 +630,7 @@ def main():
         torch.cuda.empty_cache()
         torch.cuda.reset_peak_memory_stats()
         lg = run_batch(None, runner, binding, wl, "range10d_n256_c32", 64, 187, 10, binding.F32, lik_rank_cap=96,
-                       profile_steps=2)
+                       profile_steps=2, autotune=not args.no_autotune)
         st = lg["status"]
         lroof = None
         lprof = lg["prof"] or {}
