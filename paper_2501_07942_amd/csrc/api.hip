@@ -2653,6 +2653,7 @@ struct LikCtx {
   const double* mbuf;
   long long mstride;
   double tau2;  // relative pre-truncation of the pivoted Cholesky
+  double jtol2;  // Jacobi stop: squared relative orthogonality (1e-8 for FP32 bulk)
 };
 
 struct FLikGram {  // Gram of the columns of M (n0 x n1)
@@ -2703,7 +2704,7 @@ struct FLikJacobi {
     J.sigma = s.sigma;
     J.usv = s.usv;
     J.ncols_out = nullptr;
-    J.tol2 = 1e-30;
+    J.tol2 = c.jtol2;
     J.gcap = s.gcap;
     return true;
   }
@@ -2744,7 +2745,7 @@ static tt_status lik_launch(int B, const DevTT* dL, const RoundScratch* drs, con
   hipLaunchKernelGGL(lik_dense_kernel, dim3(B), dim3(256), 0, st, dL, dfc, z, zstride, mbuf, mstride);
   TTG_LAUNCH_CHECK("lik_dense_kernel");
   if (!any_range) return TT_OK;
-  LikCtx c{dL, drs, dfc, mbuf, mstride, f32 ? 1e-14 : 1e-31};
+  LikCtx c{dL, drs, dfc, mbuf, mstride, f32 ? 1e-14 : 1e-31, f32 ? 1e-16 : 1e-30};
   if (f32) {
     TT_TRY((launch_gram<double, AccD>(FLikGram{c}, B, n1max, n0max, splits, st)));
     TT_TRY((launch_pchol<AccD>(FLikPchol{c}, B, gcap, st)));
