@@ -277,11 +277,10 @@ __global__ void __launch_bounds__(256) gram_reduce_kernel(F f) {
   GramArgs g;
   if (!f(b, g)) return;
   g.splits = gram_split_count(g.T, g.splits);
-  const long long mm = (long long)g.M * g.M;
+  const int mm = g.M * g.M;  // 32-bit index arithmetic (M <= a few thousand)
   const long long plane = (long long)g.gcap * g.gcap;
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < mm;
-       e += (long long)gridDim.x * blockDim.x) {
-    const int a = (int)(e / g.M), c = (int)(e % g.M);
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < mm; e += gridDim.x * blockDim.x) {
+    const int a = e / g.M, c = e - (e / g.M) * g.M;
     if (a > c) continue;
     typename Acc::V s = Acc::load(g.out, (long long)a * g.gcap + c);
     for (int sp = 1; sp < g.splits; ++sp)
