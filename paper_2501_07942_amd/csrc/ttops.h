@@ -782,11 +782,12 @@ __global__ void __launch_bounds__(256) dot_kernel(const DevTT* __restrict__ lik,
     const int l0 = L.ranks[k], l1 = L.ranks[k + 1], p0 = P.ranks[k], p1 = P.ranks[k + 1], n = P.n[k];
     const double* lc = core_ptr<double>(L, k);
     const T* pc = core_ptr<T>(P, k);
-    const long long nt = (long long)l1 * p0 * n;
-    for (long long e = tid; e < nt; e += blockDim.x) {
-      const int a2 = (int)(e / ((long long)p0 * n));
-      const int rem = (int)(e % ((long long)p0 * n));
-      const int b = rem / n, i = rem % n;
+    const int nt = l1 * p0 * n;  // 32-bit index arithmetic
+    const int pn = p0 * n;
+    for (int e = tid; e < nt; e += blockDim.x) {
+      const int a2 = e / pn;
+      const int rem = e - a2 * pn;
+      const int b = rem / n, i = rem - (rem / n) * n;
       double s = 0.0;
       for (int a = 0; a < l0; ++a) s += v[a * p0 + b] * lc[((long long)a * n + i) * l1 + a2];
       t[e] = s;
