@@ -231,10 +231,10 @@ __global__ void __launch_bounds__(256) cross_maxvol_kernel(const DevTT* __restri
   const int tid = threadIdx.x;
   // rows of existing index tuples (the others are zero padding)
   const int cvalid = dir == 0 ? S.cnt[k] : S.cnt[TT_MAXD + 1 + k + 1];
-  for (long long e = tid; e < (long long)m * r; e += blockDim.x) {
-    const long long i = e / r;
-    const int c = (int)(e % r);
-    Uc[e] = c < r0 ? u0[i * ru + c] : 0.0;
+  // (32-bit index arithmetic: m r stays far below 2^31)
+  for (int e = tid; e < m * r; e += blockDim.x) {
+    const int i = e / r, c = e - (e / r) * r;
+    Uc[e] = c < r0 ? u0[(long long)i * ru + c] : 0.0;
   }
   __syncthreads();
   // A rank-deficient fibre matrix leaves fewer basis vectors than rows to
@@ -300,7 +300,7 @@ __global__ void __launch_bounds__(256) cross_maxvol_kernel(const DevTT* __restri
     __syncthreads();
   }
   const double* uc = Uc;
-  for (long long e = tid; e < (long long)m * r; e += blockDim.x) W[e] = uc[e];
+  for (int e = tid; e < m * r; e += blockDim.x) W[e] = uc[e];
   if (frozen)
     for (int j = tid; j < r; j += blockDim.x) s_used[j] = S.rowsk[k * CROSS_RMAX + j];
   __syncthreads();
@@ -385,11 +385,10 @@ __global__ void __launch_bounds__(256) cross_maxvol_kernel(const DevTT* __restri
     __syncthreads();
   }
   // B = U inv(U_rows)
-  for (long long e = tid; e < (long long)m * r; e += blockDim.x) {
-    const long long i = e / r;
-    const int c = (int)(e % r);
+  for (int e = tid; e < m * r; e += blockDim.x) {
+    const int i = e / r, c = e - (e / r) * r;
     double s = 0.0;
-    for (int q = 0; q < r; ++q) s += uc[i * r + q] * G[q * 2 * r + r + c];
+    for (int q = 0; q < r; ++q) s += uc[(long long)i * r + q] * G[q * 2 * r + r + c];
     Bm[e] = s;
   }
   for (int j = tid; j < r; j += blockDim.x) rows[j] = s_used[j];
@@ -398,11 +397,11 @@ __global__ void __launch_bounds__(256) cross_maxvol_kernel(const DevTT* __restri
   for (int it = 0; it < (frozen ? 0 : 8 * CROSS_RMAX); ++it) {
     double best = -1.0;
     int bi = 0;
-    for (long long e = tid; e < (long long)m * r; e += blockDim.x) {
+    for (int e = tid; e < m * r; e += blockDim.x) {
       const double v = fabs(Bm[e]);
       if (v > best) {
         best = v;
-        bi = (int)e;
+        bi = e;
       }
     }
     sv[tid] = best;
@@ -426,9 +425,8 @@ __global__ void __launch_bounds__(256) cross_maxvol_kernel(const DevTT* __restri
     for (int c = tid; c < r; c += blockDim.x) W[c] = Bm[(long long)i * r + c] - (c == j ? 1.0 : 0.0);
     for (int q = tid; q < m; q += blockDim.x) W[r + q] = Bm[(long long)q * r + j];
     __syncthreads();
-    for (long long e = tid; e < (long long)m * r; e += blockDim.x) {
-      const long long q = e / r;
-      const int c = (int)(e % r);
+    for (int e = tid; e < m * r; e += blockDim.x) {
+      const int q = e / r, c = e - (e / r) * r;
       Bm[e] -= W[r + q] * W[c] / bij;
     }
     if (tid == 0) rows[j] = i;
@@ -462,10 +460,11 @@ __global__ void __launch_bounds__(256) cross_maxvol_kernel(const DevTT* __restri
     // core k of Y: (r, n_k, cj), entry (j, i, b) = B[(i * R + b), j]
     const DevTT& y = Y[f];
     double* yc = core_ptr<double>(y, k);
-    for (long long e = tid; e < (long long)r * nk * cj; e += blockDim.x) {
-      const int j = (int)(e / ((long long)nk * cj));
-      const int rem = (int)(e % ((long long)nk * cj));
-      const int i = rem / cj, b = rem % cj;
+    const int nkcj = nk * cj;
+    for (int e = tid; e < r * nkcj; e += blockDim.x) {
+      const int j = e / nkcj;
+      const int rem = e - j * nkcj;
+      const int i = rem / cj, b = rem - (rem / cj) * cj;
       yc[e] = Bm[(long long)(i * bcap + b) * r + j];
     }
     for (int j = tid; j < r; j += blockDim.x) S.rowsk[k * CROSS_RMAX + j] = rows[j];
