@@ -281,11 +281,16 @@ __global__ void __launch_bounds__(256) cross_maxvol_kernel(const DevTT* __restri
       Uc[(long long)i * r + c] = v;
     }
     __syncthreads();
-    for (int q = 0; q < c; ++q) {
-      double part = 0.0;
-      for (int i = tid; i < m; i += blockDim.x) part += Uc[(long long)i * r + q] * Uc[(long long)i * r + c];
-      const double w = block_sum(part, red);
-      if (tid == 0) s_w[q] = w;
+    // the c projections at once: a wavefront per basis column q, each summed
+    // over the rows by its own lanes (no workgroup reduction per column)
+    {
+      const int lane = tid & 63, nw = blockDim.x >> 6;
+      for (int q = tid >> 6; q < c; q += nw) {
+        double part = 0.0;
+        for (int i = lane; i < m; i += 64) part += Uc[(long long)i * r + q] * Uc[(long long)i * r + c];
+        part = wave_sum(part);
+        if (lane == 0) s_w[q] = part;
+      }
     }
     __syncthreads();
     double nn = 0.0;
