@@ -398,10 +398,12 @@ __global__ void __launch_bounds__(256) cross_maxvol_kernel(const DevTT* __restri
   }
   for (int j = tid; j < r; j += blockDim.x) rows[j] = s_used[j];
   __syncthreads();
-  // swaps while some |B_ij| > 1.05 (each multiplies the volume by |B_ij|)
-  for (int it = 0; it < (frozen ? 0 : 8 * CROSS_RMAX); ++it) {
-    double best = -1.0;
-    int bi = 0;
+  // swaps while some |B_ij| > 1.05 (each multiplies the volume by |B_ij|);
+  // each update pass also finds the next candidate (same order of visits as
+  // a separate search)
+  double best = -1.0;
+  int bi = 0;
+  if (!frozen)
     for (int e = tid; e < m * r; e += blockDim.x) {
       const double v = fabs(Bm[e]);
       if (v > best) {
@@ -409,6 +411,7 @@ __global__ void __launch_bounds__(256) cross_maxvol_kernel(const DevTT* __restri
         bi = e;
       }
     }
+  for (int it = 0; it < (frozen ? 0 : 8 * CROSS_RMAX); ++it) {
     sv[tid] = best;
     si[tid] = bi;
     __syncthreads();
@@ -430,9 +433,16 @@ __global__ void __launch_bounds__(256) cross_maxvol_kernel(const DevTT* __restri
     for (int c = tid; c < r; c += blockDim.x) W[c] = Bm[(long long)i * r + c] - (c == j ? 1.0 : 0.0);
     for (int q = tid; q < m; q += blockDim.x) W[r + q] = Bm[(long long)q * r + j];
     __syncthreads();
+    best = -1.0;
+    bi = 0;
     for (int e = tid; e < m * r; e += blockDim.x) {
       const int q = e / r, c = e - (e / r) * r;
       Bm[e] -= W[r + q] * W[c] / bij;
+      const double v = fabs(Bm[e]);
+      if (v > best) {
+        best = v;
+        bi = e;
+      }
     }
     if (tid == 0) rows[j] = i;
     __syncthreads();
