@@ -228,7 +228,14 @@ __global__ void __launch_bounds__(256) cross_maxvol_kernel(const DevTT* __restri
   __shared__ int s_seed[CROSS_RMAX];
   __shared__ double s_w[CROSS_RMAX];
   __shared__ double red[8];
+  // rows already taken (a completion seed, or a pivot of the elimination),
+  // flagged when the fibre matrix fits: a constant-time test per row
+  constexpr int FLAG_MAX = 16384;
+  __shared__ unsigned char s_flag[FLAG_MAX];
   const int tid = threadIdx.x;
+  const bool use_flag = m <= FLAG_MAX;
+  if (use_flag)
+    for (int q = tid; q < m; q += blockDim.x) s_flag[q] = 0;
   // rows of existing index tuples (the others are zero padding)
   const int cvalid = dir == 0 ? S.cnt[k] : S.cnt[TT_MAXD + 1 + k + 1];
   // (32-bit index arithmetic: m r stays far below 2^31)
@@ -251,7 +258,10 @@ __global__ void __launch_bounds__(256) cross_maxvol_kernel(const DevTT* __restri
       for (int q = tid; q < m; q += blockDim.x) {
         const bool ok = dir == 0 ? (q / nk) < cvalid : (q % bcap) < cvalid;
         bool seeded = false;
-        for (int u2 = 0; u2 < c - r0; ++u2) seeded = seeded || s_seed[u2] == q;
+        if (use_flag)
+          seeded = s_flag[q] != 0;
+        else
+          for (int u2 = 0; u2 < c - r0; ++u2) seeded = seeded || s_seed[u2] == q;
         if (!ok || seeded) continue;
         double lev = 0.0;
         for (int u2 = 0; u2 < c; ++u2) lev += Uc[(long long)q * r + u2] * Uc[(long long)q * r + u2];
@@ -275,6 +285,7 @@ __global__ void __launch_bounds__(256) cross_maxvol_kernel(const DevTT* __restri
     }
     if (tid == 0) s_seed[c - r0] = p;
     if (p >= m) break;  // no valid row left (cannot happen when the target fits the valid rows)
+    if (use_flag && tid == 0) s_flag[p] = 1;
     for (int i = tid; i < m; i += blockDim.x) {
       double v = (i == p) ? 1.0 : 0.0;
       for (int q = 0; q < c; ++q) v -= Uc[(long long)i * r + q] * Uc[(long long)p * r + q];
@@ -308,6 +319,8 @@ __global__ void __launch_bounds__(256) cross_maxvol_kernel(const DevTT* __restri
   for (int e = tid; e < m * r; e += blockDim.x) W[e] = uc[e];
   if (frozen)
     for (int j = tid; j < r; j += blockDim.x) s_used[j] = S.rowsk[k * CROSS_RMAX + j];
+  if (use_flag)
+    for (int q = tid; q < m; q += blockDim.x) s_flag[q] = 0;  // from now on: pivot rows
   __syncthreads();
   // Gaussian elimination with partial pivoting for the initial rows
   for (int j = 0; j < (frozen ? 0 : r); ++j) {
@@ -315,7 +328,10 @@ __global__ void __launch_bounds__(256) cross_maxvol_kernel(const DevTT* __restri
     int bi = 0;
     for (int i = tid; i < m; i += blockDim.x) {
       bool used = false;
-      for (int q = 0; q < j; ++q) used = used || (s_used[q] == i);
+      if (use_flag)
+        used = s_flag[i] != 0;
+      else
+        for (int q = 0; q < j; ++q) used = used || (s_used[q] == i);
       const double v = used ? -1.0 : fabs(W[(long long)i * r + j]);
       if (v > best) {
         best = v;
@@ -335,6 +351,7 @@ __global__ void __launch_bounds__(256) cross_maxvol_kernel(const DevTT* __restri
     if (tid == 0) {
       s_piv = si[0];
       s_used[j] = si[0];
+      if (use_flag) s_flag[si[0]] = 1;
     }
     __syncthreads();
     const int p = s_piv;
@@ -342,7 +359,10 @@ __global__ void __launch_bounds__(256) cross_maxvol_kernel(const DevTT* __restri
     if (pv != 0.0) {
       for (int i = tid; i < m; i += blockDim.x) {
         bool used = false;
-        for (int q = 0; q <= j; ++q) used = used || (s_used[q] == i);
+        if (use_flag)
+          used = s_flag[i] != 0;
+        else
+          for (int q = 0; q <= j; ++q) used = used || (s_used[q] == i);
         if (used) continue;
         const double fct = W[(long long)i * r + j] / pv;
         for (int c = j; c < r; ++c) W[(long long)i * r + c] -= fct * W[(long long)p * r + c];
