@@ -247,7 +247,17 @@ __global__ void __launch_bounds__(256) cross_maxvol_kernel(const DevTT* __restri
   // A rank-deficient fibre matrix leaves fewer basis vectors than rows to
   // pick: complete the basis with the unit vectors of the valid rows of
   // least leverage, orthogonalised twice (the pivots then still explore
-  // the whole target rank)
+  // the whole target rank).  Each row's leverage over the columns so far is
+  // kept as a running sum (W is free until the elimination), added in the
+  // columns' order.
+  if (!frozen && r0 < r) {
+    for (int q = tid; q < m; q += blockDim.x) {
+      double lev = 0.0;
+      for (int u2 = 0; u2 < r0; ++u2) lev += Uc[(long long)q * r + u2] * Uc[(long long)q * r + u2];
+      W[q] = lev;
+    }
+    __syncthreads();
+  }
   for (int c = r0; c < r; ++c) {
     int p;
     if (frozen) {
@@ -263,8 +273,7 @@ __global__ void __launch_bounds__(256) cross_maxvol_kernel(const DevTT* __restri
         else
           for (int u2 = 0; u2 < c - r0; ++u2) seeded = seeded || s_seed[u2] == q;
         if (!ok || seeded) continue;
-        double lev = 0.0;
-        for (int u2 = 0; u2 < c; ++u2) lev += Uc[(long long)q * r + u2] * Uc[(long long)q * r + u2];
+        const double lev = W[q];
         if (lev < best) {
           best = lev;
           bi = q;
@@ -312,7 +321,10 @@ __global__ void __launch_bounds__(256) cross_maxvol_kernel(const DevTT* __restri
       nn += v * v;
     }
     const double nrm = sqrt(block_sum(nn, red));
-    for (int i = tid; i < m; i += blockDim.x) Uc[(long long)i * r + c] /= nrm;
+    for (int i = tid; i < m; i += blockDim.x) {
+      Uc[(long long)i * r + c] /= nrm;
+      if (!frozen) W[i] += Uc[(long long)i * r + c] * Uc[(long long)i * r + c];
+    }
     __syncthreads();
   }
   const double* uc = Uc;
