@@ -421,12 +421,20 @@ __global__ void __launch_bounds__(256) cross_maxvol_kernel(const DevTT* __restri
       if (i != j) G[i * 2 * r + j] = 0.0;
     __syncthreads();
   }
-  // B = U inv(U_rows)
-  for (int e = tid; e < m * r; e += blockDim.x) {
-    const int i = e / r, c = e - (e / r) * r;
-    double s = 0.0;
-    for (int q = 0; q < r; ++q) s += uc[(long long)i * r + q] * G[q * 2 * r + r + c];
-    Bm[e] = s;
+  // B = U inv(U_rows), the inverse staged in LDS
+  {
+    __shared__ double s_ginv[CROSS_RMAX * CROSS_RMAX];
+    for (int e = tid; e < r * r; e += blockDim.x) {
+      const int q = e / r, c = e - (e / r) * r;
+      s_ginv[e] = G[q * 2 * r + r + c];
+    }
+    __syncthreads();
+    for (int e = tid; e < m * r; e += blockDim.x) {
+      const int i = e / r, c = e - (e / r) * r;
+      double s = 0.0;
+      for (int q = 0; q < r; ++q) s += uc[(long long)i * r + q] * s_ginv[q * r + c];
+      Bm[e] = s;
+    }
   }
   for (int j = tid; j < r; j += blockDim.x) rows[j] = s_used[j];
   __syncthreads();
