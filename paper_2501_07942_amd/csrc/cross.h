@@ -389,15 +389,27 @@ __global__ void __launch_bounds__(256) cross_maxvol_kernel(const DevTT* __restri
   }
   __syncthreads();
   for (int j = 0; j < r; ++j) {
-    if (tid == 0) {
-      int p = j;
-      double bv = fabs(G[j * 2 * r + j]);
-      for (int i = j + 1; i < r; ++i)
-        if (fabs(G[i * 2 * r + j]) > bv) {
-          bv = fabs(G[i * 2 * r + j]);
+    // partial pivot: the first row of largest |G(i, j)|, i >= j, found by
+    // the first wavefront's lanes and a shuffle reduction
+    if (tid < 64) {
+      double bv = -1.0;
+      int p = r;
+      for (int i = j + tid; i < r; i += 64) {
+        const double v = fabs(G[i * 2 * r + j]);
+        if (v > bv) {
+          bv = v;
           p = i;
         }
-      s_piv = p;
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(bv, o, 64);
+        const int oi = __shfl_xor(p, o, 64);
+        if (ov > bv || (ov == bv && oi < p)) {
+          bv = ov;
+          p = oi;
+        }
+      }
+      if (tid == 0) s_piv = p < r ? p : j;  // (no comparable entry: keep row j, as a serial scan would)
     }
     __syncthreads();
     const int p = s_piv;
