@@ -368,13 +368,21 @@ __global__ void __launch_bounds__(256) cross_maxvol_kernel(const DevTT* __restri
     __syncthreads();
     const int p = s_piv;
     const double pv = W[(long long)p * r + j];
-    if (pv != 0.0) {
+    if (pv != 0.0 && use_flag) {
+      // the rows' multipliers first (Bm is free until B is formed), then the
+      // update with consecutive threads on consecutive columns of a row
+      for (int i = tid; i < m; i += blockDim.x) Bm[i] = s_flag[i] ? 0.0 : W[(long long)i * r + j] / pv;
+      __syncthreads();
+      const int w = r - j;
+      for (int e = tid; e < m * w; e += blockDim.x) {
+        const int i = e / w, c = j + (e - (e / w) * w);
+        if (s_flag[i]) continue;
+        W[(long long)i * r + c] -= Bm[i] * W[(long long)p * r + c];
+      }
+    } else if (pv != 0.0) {
       for (int i = tid; i < m; i += blockDim.x) {
         bool used = false;
-        if (use_flag)
-          used = s_flag[i] != 0;
-        else
-          for (int q = 0; q <= j; ++q) used = used || (s_used[q] == i);
+        for (int q = 0; q <= j; ++q) used = used || (s_used[q] == i);
         if (used) continue;
         const double fct = W[(long long)i * r + j] / pv;
         for (int c = j; c < r; ++c) W[(long long)i * r + c] -= fct * W[(long long)p * r + c];
