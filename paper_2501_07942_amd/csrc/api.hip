@@ -905,6 +905,26 @@ static tt_status launch_pchol(F f, int B, int gcap, hipStream_t st) {
   return TT_OK;
 }
 
+// compute units of the current device, read once per device
+static tt_status device_cus(int* out) {
+  static std::mutex mu;
+  static int cached[64] = {0};
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+  std::lock_guard<std::mutex> lk(mu);
+  if (dev < 0 || dev >= 64) {
+    set_error("device_cus: device index %d out of range", dev);
+    return TT_ERR_ARG;
+  }
+  if (!cached[dev]) {
+    int n = 0;
+    HIP_TRY(hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev), "compute unit count");
+    cached[dev] = std::max(1, n);
+  }
+  *out = cached[dev];
+  return TT_OK;
+}
+
 template <typename T, typename Acc, typename F>
 static tt_status launch_gram(F f, int B, int Mcap, long long Tcap, int smax, hipStream_t st) {
   ProfScope ps_(PC_GRAM, st);
@@ -916,7 +936,15 @@ static tt_status launch_gram(F f, int B, int Mcap, long long Tcap, int smax, hip
   // 32 x 32 or 64 x 64 tiles (both sum every element in the same order).
   const int t = (Mcap + 63) / 64;
   if constexpr (std::is_same<Acc, AccD>::value) {
-    hipLaunchKernelGGL((gram_mfma_kernel<T, F>), dim3(t * (t + 1) / 2, std::min(smax, GM_YMAX), B), dim3(256), 0, st, f);
+    // split planes per launch row: about one full wave of workgroups (two
+    // fit per CU at this kernel's register use) counting one tile pair per
+    // filter (the tile pairs are sized for the rank capacity, and those
+    // beyond a filter's own rank exit at once), within [GM_YMIN, GM_YMAX];
+    // every result bit is the same whatever the row holds
+    int cus = 0;
+    TT_TRY(device_cus(&cus));
+    const int rows = std::min(GM_YMAX, std::max(GM_YMIN, (2 * cus + B - 1) / B));
+    hipLaunchKernelGGL((gram_mfma_kernel<T, F>), dim3(t * (t + 1) / 2, std::min(smax, rows), B), dim3(256), 0, st, f);
   } else {
     if (Mcap > 32)
       hipLaunchKernelGGL((gram_partial_kernel<T, Acc, 64, F>), dim3(t * (t + 1) / 2, smax, B), dim3(256), 0, st, f);

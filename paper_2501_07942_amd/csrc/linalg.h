@@ -124,7 +124,8 @@ __global__ void __launch_bounds__(256) gram_partial_kernel(F f) {
 // ---------------------------------------------------------------------------
 typedef double md4 __attribute__((ext_vector_type(4)));
 #define GM_KC 32
-#define GM_YMAX 4  // split planes per launch row (workgroups loop over the rest)
+#define GM_YMIN 2  // split planes per launch row: at least this many,
+#define GM_YMAX 4  // at most this many (workgroups loop over the rest)
 
 template <typename TB>
 struct GmLds {
