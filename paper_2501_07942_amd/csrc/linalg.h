@@ -531,70 +531,6 @@ __device__ inline bool jac_rotation(double al, double be, double ga, double& cs,
   return true;
 }
 
-// sum over aligned groups of lp lanes (lp a power of two)
-__device__ inline double jw_group_sum(double v, int lp) {
-  for (int o = lp >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-// One column pair (x_p, x_q) of a Jacobi round, its rows split over lp
-// lanes (lane lip takes rows lip, lip + lp, ...): the three dot products,
-// reduced over the lp lanes, then the rotation if one is due.  Up to JR_MAX
-// rows per lane stay in registers between the dot products and the
-// rotation; the stores of the rotation would otherwise force every later
-// row to be read again (the compiler cannot tell that the two columns do
-// not overlap).  Both forms sum and rotate in the same order.
-#define JR_MAX 8
-__device__ __forceinline__ bool jac_pair(double* xp, double* xq, int rows, int lip, int lp, bool live,
-                                         double tol2, double& cs, double& sn) {
-  double al = 0.0, be = 0.0, ga = 0.0;
-  const bool regs = rows <= JR_MAX * lp;
-  double ur[JR_MAX], vr[JR_MAX];
-  if (live && regs) {
-#pragma unroll
-    for (int j = 0; j < JR_MAX; ++j) {
-      const int k = lip + j * lp;
-      ur[j] = k < rows ? xp[k] : 0.0;
-      vr[j] = k < rows ? xq[k] : 0.0;
-    }
-#pragma unroll
-    for (int j = 0; j < JR_MAX; ++j)
-      if (lip + j * lp < rows) {
-        al = __fma_rn(ur[j], ur[j], al);
-        be = __fma_rn(vr[j], vr[j], be);
-        ga = __fma_rn(ur[j], vr[j], ga);
-      }
-  } else if (live) {
-    for (int k = lip; k < rows; k += lp) {
-      const double u = xp[k], v = xq[k];
-      al = __fma_rn(u, u, al);
-      be = __fma_rn(v, v, be);
-      ga = __fma_rn(u, v, ga);
-    }
-  }
-  al = jw_group_sum(al, lp);
-  be = jw_group_sum(be, lp);
-  ga = jw_group_sum(ga, lp);
-  if (!(live && jac_rotation(al, be, ga, cs, sn, tol2))) return false;
-  if (regs) {
-#pragma unroll
-    for (int j = 0; j < JR_MAX; ++j) {
-      const int k = lip + j * lp;
-      if (k < rows) {
-        xp[k] = cs * ur[j] - sn * vr[j];
-        xq[k] = sn * ur[j] + cs * vr[j];
-      }
-    }
-  } else {
-    for (int k = lip; k < rows; k += lp) {
-      const double u = xp[k], v = xq[k];
-      xp[k] = cs * u - sn * v;
-      xq[k] = sn * u + cs * v;
-    }
-  }
-  return true;
-}
-
 // One-sided Jacobi for at most JW_NMAX columns and few rows per lane, run by
 // a single wavefront:
 // the n/2 column pairs of a round each get LP = 64 / (n/2) lanes (rounded
@@ -603,6 +539,11 @@ __device__ __forceinline__ bool jac_pair(double* xp, double* xq, int rows, int l
 // and stopping rule as the workgroup version below.  Writes sigma (descending)
 // and the scaled left vectors like it.
 #define JW_NMAX 64
+__device__ inline double jw_group_sum(double v, int lp) {
+  for (int o = lp >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
 __device__ __forceinline__ void jacobi_wave(double* W, long long ldw, int rows, int nc, double* s_sig,
                                             const JacobiArgs& J) {
   const int lane = threadIdx.x & 63;
@@ -630,8 +571,26 @@ __device__ __forceinline__ void jacobi_wave(double* W, long long ldw, int rows, 
         const bool live = i < npair && pc < nc && qc < nc;
         double* xp = W + (long long)(live ? pc : 0) * ldw;
         double* xq = W + (long long)(live ? qc : 0) * ldw;
+        double al = 0.0, be = 0.0, ga = 0.0;
+        if (live)
+          for (int k = lip; k < rows; k += lp) {
+            const double u = xp[k], v = xq[k];
+            al = __fma_rn(u, u, al);
+            be = __fma_rn(v, v, be);
+            ga = __fma_rn(u, v, ga);
+          }
+        al = jw_group_sum(al, lp);
+        be = jw_group_sum(be, lp);
+        ga = jw_group_sum(ga, lp);
         double cs, sn;
-        if (jac_pair(xp, xq, rows, lip, lp, live, J.tol2, cs, sn)) rot = 1;
+        if (live && jac_rotation(al, be, ga, cs, sn, J.tol2)) {
+          for (int k = lip; k < rows; k += lp) {
+            const double u = xp[k], v = xq[k];
+            xp[k] = cs * u - sn * v;
+            xq[k] = sn * u + cs * v;
+          }
+          rot = 1;
+        }
         // the next round reads columns other lanes just rotated
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_wave_barrier();
@@ -719,8 +678,26 @@ __device__ __forceinline__ void jacobi_body(double* W, long long ldw, const Jaco
         const bool live = i < npair && pc < nc && qc < nc;
         double* xp = W + (long long)(live ? pc : 0) * ldw;
         double* xq = W + (long long)(live ? qc : 0) * ldw;
+        double al = 0.0, be = 0.0, ga = 0.0;
+        if (live)
+          for (int k = lip; k < rows; k += lp) {
+            const double u = xp[k], v = xq[k];
+            al = __fma_rn(u, u, al);
+            be = __fma_rn(v, v, be);
+            ga = __fma_rn(u, v, ga);
+          }
+        al = jw_group_sum(al, lp);
+        be = jw_group_sum(be, lp);
+        ga = jw_group_sum(ga, lp);
         double cs, sn;
-        if (jac_pair(xp, xq, rows, lip, lp, live, J.tol2, cs, sn) && lip == 0) s_rot = 1;
+        if (live && jac_rotation(al, be, ga, cs, sn, J.tol2)) {
+          for (int k = lip; k < rows; k += lp) {
+            const double u = xp[k], v = xq[k];
+            xp[k] = cs * u - sn * v;
+            xq[k] = sn * u + cs * v;
+          }
+          if (lip == 0) s_rot = 1;
+        }
       }
       __syncthreads();
     }
