@@ -283,9 +283,22 @@ __global__ void __launch_bounds__(256) gram_reduce_kernel(F f) {
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < mm; e += gridDim.x * blockDim.x) {
     const int a = e / g.M, c = e - (e / g.M) * g.M;
     if (a > c) continue;
-    typename Acc::V s = Acc::load(g.out, (long long)a * g.gcap + c);
-    for (int sp = 1; sp < g.splits; ++sp)
-      s = Acc::add(s, Acc::load(g.out + sp * plane * Acc::words, (long long)a * g.gcap + c));
+    const long long ix = (long long)a * g.gcap + c;
+    typename Acc::V s = Acc::load(g.out, ix);
+    // the planes' loads are issued four at a time (all in flight together);
+    // the sum still runs over the planes in order
+    int sp = 1;
+    for (; sp + 4 <= g.splits; sp += 4) {
+      const typename Acc::V v0 = Acc::load(g.out + (sp + 0) * plane * Acc::words, ix);
+      const typename Acc::V v1 = Acc::load(g.out + (sp + 1) * plane * Acc::words, ix);
+      const typename Acc::V v2 = Acc::load(g.out + (sp + 2) * plane * Acc::words, ix);
+      const typename Acc::V v3 = Acc::load(g.out + (sp + 3) * plane * Acc::words, ix);
+      s = Acc::add(s, v0);
+      s = Acc::add(s, v1);
+      s = Acc::add(s, v2);
+      s = Acc::add(s, v3);
+    }
+    for (; sp < g.splits; ++sp) s = Acc::add(s, Acc::load(g.out + sp * plane * Acc::words, ix));
     Acc::store(g.out, (long long)a * g.gcap + c, s);
     Acc::store(g.out, (long long)c * g.gcap + a, s);
   }
